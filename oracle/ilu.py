@@ -1,0 +1,148 @@
+"""Incomplete LU factorisations -- test infrastructure (oracle).
+
+Paper, section "Iterative Solvers": the preconditioner M ~ L~ is an
+incomplete LU factorisation of the (permuted) modified Liouvillian, and its
+quality is judged by the condition estimate ||(LU)^{-1} e||_inf, e = (1,...,1).
+
+ilu0  -- ILU with zero fill: L unit lower and U upper keep exactly the
+         pattern of A, and (LU)_ij = a_ij on that pattern.  Computed in the
+         row-wise (IKJ) elimination order, one row at a time.
+ilut  -- dual-threshold ILU: during the elimination of row i, multipliers and
+         fill entries smaller than drop_tol * ||a_i||_inf are dropped, and at
+         most ceil(fill * nnz(a_i)) entries are kept in each of the strict lower
+         and the strict upper part (largest magnitude first, ties to the lower
+         column index); the diagonal is always kept.  No pivoting.
+
+Both return a single CSR matrix holding the strict lower part of L (the unit
+diagonal is implicit) and U (diagonal included), with sorted column indices.
+A pivot whose magnitude falls below guard * ||a_i||_inf is replaced by that
+value times the pivot's phase (or by the bare value when it is exactly zero)
+and counted.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _guard(piv: complex, bound: float) -> tuple[complex, bool]:
+    if abs(piv) >= bound:
+        return piv, False
+    if piv == 0:
+        return complex(bound), True
+    return piv / abs(piv) * bound, True
+
+
+def ilu0(A, guard: float = 0.0):
+    """ILU(0) of a square CSR matrix with a non-zero diagonal pattern.
+    Returns (LU as csr_matrix, number of guarded pivots)."""
+    A = sp.csr_matrix(A, dtype=np.complex128)
+    A.sort_indices()
+    n = A.shape[0]
+    indptr, indices = A.indptr, A.indices
+    vals = A.data.copy()
+    # column -> position map per row, and the diagonal position
+    pos = [dict(zip(indices[indptr[i]:indptr[i + 1]].tolist(),
+                    range(indptr[i], indptr[i + 1]))) for i in range(n)]
+    diag = np.array([pos[i].get(i, -1) for i in range(n)])
+    if np.any(diag < 0):
+        raise ValueError("ilu0: structurally zero diagonal")
+    guarded = 0
+    for i in range(n):
+        rownorm = float(np.max(np.abs(A.data[indptr[i]:indptr[i + 1]]))) if indptr[i + 1] > indptr[i] else 0.0
+        row_pos = pos[i]
+        for e in range(indptr[i], diag[i]):          # k < i, ascending
+            k = indices[e]
+            vals[e] = vals[e] / vals[diag[k]]
+            lik = vals[e]
+            for f in range(diag[k] + 1, indptr[k + 1]):  # u_kj, j > k
+                j = indices[f]
+                p = row_pos.get(j)
+                if p is not None:
+                    vals[p] -= lik * vals[f]
+        if guard > 0:
+            v, g = _guard(complex(vals[diag[i]]), guard * rownorm)
+            vals[diag[i]] = v
+            guarded += int(g)
+    return sp.csr_matrix((vals, indices.copy(), indptr.copy()), shape=A.shape), guarded
+
+
+def ilut(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0):
+    """Dual-threshold ILUT without pivoting.  Returns (LU csr, guarded pivots)."""
+    A = sp.csr_matrix(A, dtype=np.complex128)
+    A.sort_indices()
+    n = A.shape[0]
+    U_rows: list[dict] = [None] * n   # j -> u_ij for j >= i
+    out_rows = []
+    guarded = 0
+    for i in range(n):
+        cols = A.indices[A.indptr[i]:A.indptr[i + 1]]
+        vals = A.data[A.indptr[i]:A.indptr[i + 1]]
+        nz = len(cols)
+        rownorm = float(np.max(np.abs(vals))) if nz else 0.0
+        tau = drop_tol * rownorm
+        keep = int(math.ceil(fill * nz))
+        w = dict(zip(cols.tolist(), vals.tolist()))
+        L_part = {}
+        while True:
+            lower = [c for c in w if c < i and c not in L_part]
+            if not lower:
+                break
+            k = min(lower)
+            wk = w[k] / U_rows[k][k]
+            if abs(wk) < tau:
+                del w[k]
+                continue
+            L_part[k] = wk
+            w[k] = wk
+            for j, ukj in U_rows[k].items():
+                if j > k:
+                    w[j] = w.get(j, 0.0) - wk * ukj
+        # second dropping rule on the remaining entries
+        lo = [(c, v) for c, v in w.items() if c < i and abs(v) >= tau]
+        up = [(c, v) for c, v in w.items() if c > i and abs(v) >= tau]
+        lo.sort(key=lambda cv: (-abs(cv[1]), cv[0]))
+        up.sort(key=lambda cv: (-abs(cv[1]), cv[0]))
+        lo = lo[:keep]
+        up = up[:keep]
+        piv = w.get(i, 0.0)
+        if guard > 0:
+            piv, g = _guard(complex(piv), guard * rownorm)
+            guarded += int(g)
+        elif piv == 0:
+            raise ZeroDivisionError(f"ilut: zero pivot in row {i}")
+        U_rows[i] = dict(up)
+        U_rows[i][i] = piv
+        row = sorted(lo + up + [(i, piv)])
+        out_rows.append(row)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    for i, row in enumerate(out_rows):
+        indptr[i + 1] = indptr[i] + len(row)
+    indices = np.array([c for row in out_rows for c, _ in row], dtype=np.int32)
+    data = np.array([v for row in out_rows for _, v in row], dtype=np.complex128)
+    return sp.csr_matrix((data, indices, indptr), shape=A.shape), guarded
+
+
+def split(LU):
+    """(unit lower L, upper U) as separate CSR matrices."""
+    LU = sp.csr_matrix(LU)
+    n = LU.shape[0]
+    L = sp.tril(LU, k=-1, format="csr") + sp.identity(n, dtype=LU.dtype, format="csr")
+    U = sp.triu(LU, k=0, format="csr")
+    return L.tocsr(), U.tocsr()
+
+
+def apply_inverse(LU, b):
+    """(LU)^{-1} b by forward then backward substitution."""
+    from scipy.sparse.linalg import spsolve_triangular
+    L, U = split(LU)
+    y = spsolve_triangular(L, b, lower=True, unit_diagonal=True)
+    return spsolve_triangular(U, y, lower=False)
+
+
+def condition_estimate(LU) -> float:
+    """||(LU)^{-1} e||_inf with e the all-ones vector."""
+    n = LU.shape[0]
+    return float(np.max(np.abs(apply_inverse(LU, np.ones(n, dtype=np.complex128)))))

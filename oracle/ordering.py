@@ -1,0 +1,123 @@
+"""Bandwidth, profile and (reverse) Cuthill-McKee ordering -- test
+infrastructure (oracle).
+
+Paper, section "Direct factorization":
+  * upper/lower bandwidth ub = max_{a_ij != 0} (j - i), lb = max_{a_ij != 0} (i - j),
+    total bandwidth B = ub + lb + 1;
+  * upper profile up = sum over rows i of max_{a_ij != 0} (j - i), lower profile
+    lp = sum over columns j of max_{a_ij != 0} (i - j), P = up + lp (each
+    per-row / per-column maximum is taken as 0 when negative or absent);
+  * RCM is computed on the structure of A + A^T and the same permutation is
+    applied to rows and columns.
+
+The Cuthill-McKee search itself is plain C (oracle/c/cm_order.c), compiled
+with gcc on first use so large graphs stay fast.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "c", "cm_order.c")
+_LIB = os.path.join(_HERE, "c", "liboracle_cm.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build_c() -> str:
+    """Compile the C part of the oracle with gcc (called by the build step and
+    lazily on first use)."""
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", _LIB, _SRC])
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build_c()
+            lib = ctypes.CDLL(_LIB)
+            lib.oracle_cuthill_mckee.restype = ctypes.c_int
+            lib.oracle_cuthill_mckee.argtypes = [ctypes.c_int64, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+            _lib = lib
+    return _lib
+
+
+def pattern(A) -> sp.csr_matrix:
+    """Boolean structure of the non-zero entries of A (explicit zeros excluded)."""
+    A = sp.csr_matrix(A)
+    P = sp.csr_matrix((A.data != 0, A.indices, A.indptr), shape=A.shape)
+    P.eliminate_zeros()
+    P = P.astype(np.int8)
+    P.sort_indices()
+    return P
+
+
+def symmetrized_pattern(A) -> sp.csr_matrix:
+    """Structure of A + A^T (the union of both patterns)."""
+    P = pattern(A)
+    S = ((P + P.T) != 0).astype(np.int8).tocsr()
+    S.sort_indices()
+    return S
+
+
+def bandwidth(A) -> tuple[int, int, int]:
+    """(ub, lb, B) of the non-zero structure."""
+    C = pattern(A).tocoo()
+    if C.nnz == 0:
+        return 0, 0, 1
+    diff = C.col.astype(np.int64) - C.row.astype(np.int64)
+    ub = max(int(diff.max()), 0)
+    lb = max(int((-diff).max()), 0)
+    return ub, lb, ub + lb + 1
+
+
+def profile(A) -> tuple[int, int, int]:
+    """(up, lp, P) of the non-zero structure."""
+    C = pattern(A).tocoo()
+    n = A.shape[0]
+    r = C.row.astype(np.int64)
+    c = C.col.astype(np.int64)
+    row_max = np.zeros(n, dtype=np.int64)
+    np.maximum.at(row_max, r, c - r)
+    col_max = np.zeros(A.shape[1], dtype=np.int64)
+    np.maximum.at(col_max, c, r - c)
+    up = int(row_max.sum())
+    lp = int(col_max.sum())
+    return up, lp, up + lp
+
+
+def cuthill_mckee(S) -> np.ndarray:
+    """Cuthill-McKee visit order of a symmetric pattern S (CSR)."""
+    S = sp.csr_matrix(S)
+    S.sort_indices()
+    n = S.shape[0]
+    indptr = np.ascontiguousarray(S.indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(S.indices, dtype=np.int32)
+    order = np.empty(n, dtype=np.int32)
+    rc = _load().oracle_cuthill_mckee(n, indptr.ctypes.data, indices.ctypes.data, order.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle Cuthill-McKee: allocation failed")
+    return order
+
+
+def rcm(A) -> np.ndarray:
+    """Reverse Cuthill-McKee permutation of A: perm[new] = old, computed on the
+    structure of A + A^T."""
+    return cuthill_mckee(symmetrized_pattern(A))[::-1].copy()
+
+
+def permute(A, perm) -> sp.csr_matrix:
+    """P A P^T with P the row permutation perm[new] = old."""
+    A = sp.csr_matrix(A)
+    B = A[perm, :][:, perm].tocsr()
+    B.sort_indices()
+    return B
