@@ -1,0 +1,242 @@
+/*
+ * ss.h -- C ABI of the MI355X steady-state solver for Lindblad master equations.
+ *
+ * Method: P. D. Nation, "Steady-state solution methods for open quantum
+ * optical systems".  Given a Hamiltonian H and collapse operators C_k (d x d
+ * sparse matrices), find the density matrix rho with L vec(rho) = 0 and
+ * Tr rho = 1, where L is the Lindblad Liouvillian (section "Steady-state
+ * density matrix", eqs. lindblad and eigval) in column-stacking order,
+ * vec(rho)[i + d*j] = rho[i, j].
+ *
+ * Every step of the solve runs in HIP kernels on the current GPU: Liouvillian
+ * assembly, the trace-row or shift transform, reverse Cuthill-McKee ordering,
+ * incomplete LU factorisation, sparse triangular solves, sparse
+ * matrix-vector products and the preconditioned Krylov iterations.
+ *
+ * Conventions for every entry point:
+ *   - return value: SS_OK (0) on success, a negative SS_E_* code on error,
+ *     SS_PENDING (1) from ss_poll while a request is still running;
+ *   - on error, ss_last_error() returns a message for the calling thread;
+ *   - complex numbers are stored as interleaved (re, im) doubles;
+ *   - pointers marked "host or device" may point to host memory or to memory
+ *     allocated on the current HIP device; the library inspects the pointer;
+ *   - input buffers are borrowed for the duration of the call only.
+ */
+#ifndef SS_H
+#define SS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define SS_OK               0
+#define SS_PENDING          1
+#define SS_E_INVALID_ARG   -1  /* bad shape, index, NaN/Inf, unknown enum   */
+#define SS_E_OOM           -2  /* device or host allocation failed          */
+#define SS_E_NOT_CONVERGED -3  /* iteration limit reached (section "Iterative
+                                  Solvers": maximum number of iterations);
+                                  the best iterate and its residual are still
+                                  returned                                  */
+#define SS_E_BREAKDOWN     -4  /* BiCGSTAB breakdown (residual orthogonal to
+                                  the shadow residual, section "Numerical
+                                  Simulations") and no fallback allowed     */
+#define SS_E_ZERO_PIVOT    -5  /* structurally zero diagonal in the ILU      */
+#define SS_E_HIP           -6  /* HIP runtime error                          */
+#define SS_E_STATE         -7  /* call not valid for the handle's state      */
+#define SS_E_TIMEOUT       -8  /* a bounded device-side wait gave up         */
+
+/* --------------------------------------------------------------- inputs */
+/* d x d complex sparse matrix in CSR form.  indptr has n+1 entries, column
+ * indices are strictly increasing within a row and lie in [0, n); data holds
+ * 2*nnz doubles (re, im).  All three arrays may be host or device memory
+ * (all three on the same side). */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *indptr;
+    const int32_t *indices;
+    const double *data;
+} ss_csr_z;
+
+/* opaque handles; each owns device memory until freed */
+typedef struct ss_liouv_s *ss_liouv;
+typedef struct ss_server_s *ss_server;
+
+/* ------------------------------------------------------------ methods */
+/* SS_TRACE_*  : the unit-trace linear system L~ x = w e_0 with
+ *               L~ = L + w T (section "Direct factorization", eq. linear),
+ *               w = mean of the diagonal of L (Fig. 4 caption), solved by
+ *               ILU-preconditioned BiCGSTAB or restarted GMRES(m) (section
+ *               "Iterative Solvers", eq. modified).
+ * SS_INVPOW_* : the doubly-iterative inverse-power method (section
+ *               "Iterative Solvers", last paragraph): shifted inverse power
+ *               on L - sigma I (eqs. inverse, inverseiter) whose linear
+ *               solves are ILU-preconditioned Krylov iterations with a
+ *               tolerance one decade below the outer one. */
+#define SS_TRACE_BICGSTAB   0
+#define SS_TRACE_GMRES      1
+#define SS_INVPOW_BICGSTAB  2
+#define SS_INVPOW_GMRES     3
+
+/* precision: SS_FP64 runs everything in complex128.  SS_MIXED runs the
+ * inner Krylov iterations, ILU factors and SpMV in complex64 and keeps the
+ * outer residual, correction accumulation and trace normalisation in fp64
+ * (iterative refinement). */
+#define SS_FP64   0
+#define SS_MIXED  1
+
+#define SS_ILU0   0  /* zero-fill ILU on the pattern of the permuted matrix */
+#define SS_ILUT   1  /* dual-threshold ILU (drop_tol, fill), section
+                        "Iterative Solvers" (iLUTP without pivoting)        */
+
+#define SS_ORDER_RCM      0  /* reverse Cuthill-McKee on L~ + L~^T      */
+#define SS_ORDER_NATURAL  1
+
+typedef struct {
+    int32_t prec;       /* SS_FP64 | SS_MIXED                       (SS_FP64)  */
+    int32_t ilu;        /* SS_ILU0 | SS_ILUT                        (SS_ILU0)  */
+    int32_t ordering;   /* SS_ORDER_RCM | SS_ORDER_NATURAL          (RCM)      */
+    int32_t gmres_m;    /* GMRES restart length                     (20)       */
+    int32_t maxiter;    /* inner Krylov iteration limit per solve   (1000)     */
+    int32_t max_outer;  /* outer refinement / inverse-power steps   (20)       */
+    int32_t flags;      /* SS_FLAG_* bits                           (0)        */
+    int32_t reserved;
+    double drop_tol;    /* ILUT drop tolerance relative to ||row||_inf (1e-4)  */
+    double fill;        /* ILUT entries kept per part, x nnz(row)     (10)     */
+    double sigma;       /* inverse-power shift                        (1e-15)  */
+    double inner_tol;   /* relative inner Krylov tolerance; 0 = default:
+                           tol/10 relative to the outer residual in FP64,
+                           1e-4 in SS_MIXED                                     */
+    double weight;      /* trace-row weight w; 0 = mean diagonal of L          */
+} ss_options;
+
+#define SS_FLAG_HERMITIZE   1  /* return (rho + rho^+)/2                      */
+#define SS_FLAG_NO_FALLBACK 2  /* no GMRES fallback after BiCGSTAB breakdown  */
+
+typedef struct {
+    int32_t status;          /* the call's return code                        */
+    int32_t outer_its;       /* refinement or inverse-power steps             */
+    int32_t inner_its;       /* total Krylov iterations                       */
+    int32_t breakdowns;      /* BiCGSTAB restarts after breakdown             */
+    int32_t pivots_guarded;  /* ILU pivots replaced by the guard value        */
+    int32_t fell_back;       /* 1 if BiCGSTAB fell back to GMRES              */
+    int32_t bandwidth;       /* B of the matrix that was factorised           */
+    int32_t reserved;
+    int64_t profile;         /* P of the matrix that was factorised           */
+    int64_t nnz_matrix;      /* nnz of L~ or L - sigma I                      */
+    int64_t nnz_factors;     /* nnz(L) + nnz(U) of the ILU                    */
+    double resid_l2;         /* ||L vec(rho)||_2 in fp64 with Tr rho = 1      */
+    double herm_err;         /* max |rho - rho^+|                             */
+    double trace_err;        /* |Tr rho - 1| before normalisation's rounding  */
+    double cond_est;         /* ||(LU)^-1 e||_inf, e = ones                   */
+    double fill_factor;      /* nnz_factors / nnz_matrix                      */
+    double weight;           /* w used by the trace row                       */
+    double t_setup_ms;       /* transform + ordering + factorisation          */
+    double t_solve_ms;       /* Krylov iterations + finish                    */
+} ss_info;
+
+/* fills *opt with the defaults listed above */
+int ss_options_default(ss_options *opt);
+
+/* ----------------------------------------------------- core entry points */
+/* Assemble the Liouvillian of eq. (lindblad) on the device:
+ *   L = -i (I (x) H - H^T (x) I)
+ *       + sum_k [ conj(C_k) (x) C_k - 1/2 I (x) C_k^+ C_k - 1/2 (C_k^+ C_k)^T (x) I ]
+ * as an n x n CSR matrix, n = N^2, with entries that sum to exactly zero
+ * dropped.  H and c_ops[k] are N x N (host or device).  n_cops may be 0.
+ * Limits: N <= 46340 and nnz(L) < 2^31.  *out receives a new handle. */
+int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cops,
+                         int64_t N, ss_liouv *out);
+
+/* Solve for the steady state.  method: SS_TRACE_* or SS_INVPOW_*; tol: the
+ * target for ||L vec(rho)||_2 with Tr rho = 1; opt: NULL for defaults.
+ * rho_out: N*N complex (2*N*N doubles), column-major (= vec order), host or
+ * device, caller-owned.  info may be NULL.  rho is always trace-normalised;
+ * on SS_E_NOT_CONVERGED it holds the best iterate. */
+int ss_solve(ss_liouv L, int32_t method, double tol, const ss_options *opt,
+             double *rho_out, ss_info *info);
+
+void ss_liouv_free(ss_liouv L);
+
+/* N, n = N^2 and nnz of the assembled Liouvillian */
+int ss_liouv_shape(ss_liouv L, int64_t *N, int64_t *n, int64_t *nnz);
+
+/* ------------------------------------------------ stage-wise inspection */
+/* Run the problem transform, ordering and factorisation of a method (the
+ * set-up half of ss_solve) and keep the results on the handle. */
+int ss_prepare(ss_liouv L, int32_t method, const ss_options *opt);
+
+#define SS_MAT_L         0  /* assembled Liouvillian, natural order            */
+#define SS_MAT_A         1  /* transformed matrix (L~ or L - sigma I), natural  */
+#define SS_MAT_A_PERM    2  /* transformed matrix after the ordering: P A P^T  */
+#define SS_MAT_LU        3  /* ILU factors in one CSR: strict lower part of the
+                               unit-lower L, then U with its diagonal          */
+#define SS_MAT_SYM       4  /* symmetrised pattern of A used by RCM (data = 1)  */
+
+/* Copy a matrix to host arrays.  Call first with indptr = indices = data =
+ * NULL to get *nnz; then with arrays of n+1, nnz and 2*nnz entries. */
+int ss_export_csr(ss_liouv L, int32_t which, int64_t *nnz, int64_t *indptr,
+                  int32_t *indices, double *data);
+
+/* Copy the ordering perm[new] = old (n entries) to a host array. */
+int ss_export_perm(ss_liouv L, int32_t *perm);
+
+#define SS_OP_SPMV_L      0  /* y = L x          (natural order, fp64)         */
+#define SS_OP_SPMV_APERM  1  /* y = (P A P^T) x  (prec selects c128 / c64)     */
+#define SS_OP_PRECOND     2  /* y = (LU)^-1 x    (prec selects c128 / c64)     */
+#define SS_OP_LSOLVE      3  /* y = L_f^-1 x     unit lower factor             */
+#define SS_OP_USOLVE      4  /* y = U_f^-1 x     upper factor                  */
+
+/* Apply one operator of the prepared handle to x (n complex, host or
+ * device) giving y (n complex, host or device).  prec = SS_FP64 or SS_MIXED:
+ * in SS_MIXED x is rounded to complex64, the operator runs in complex64 and
+ * y is widened back to complex128. */
+int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
+
+/* Bandwidth B and profile P of a stage matrix (definitions of the section
+ * "Direct factorization"), computed on the device. */
+int ss_bandwidth_profile(ss_liouv L, int32_t which, int64_t *B, int64_t *P);
+
+/* ------------------------------------------------------------- serving */
+/* A server keeps many small solves resident on the device and advances them
+ * together (continuous batching): requests are admitted while their
+ * predicted footprint fits in hbm_budget_bytes and fewer than max_slots run;
+ * requests that arrive later wait and are admitted as slots and memory free
+ * up, between batched iteration rounds. */
+int ss_server_create(size_t hbm_budget_bytes, int32_t max_slots, ss_server *out);
+
+/* Queue a steady-state request (inputs are copied before return).  method
+ * and opt as in ss_solve.  *ticket identifies the request. */
+int ss_submit(ss_server S, const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cops,
+              int64_t N, int32_t method, double tol, const ss_options *opt,
+              uint64_t *ticket);
+
+/* Non-blocking.  Returns SS_PENDING while the request runs; otherwise the
+ * request's status, with rho_out (N*N complex, host) and info filled, and
+ * the ticket retired. */
+int ss_poll(ss_server S, uint64_t ticket, double *rho_out, ss_info *info);
+
+/* Block until every queued request has finished. */
+int ss_server_drain(ss_server S);
+
+void ss_server_destroy(ss_server S);
+
+/* ---------------------------------------------------------------- misc */
+/* thread-local message describing the last error */
+const char *ss_last_error(void);
+
+/* Make subsequent calls of this thread enqueue their work on a HIP stream
+ * (a hipStream_t cast to void*; NULL = the library's own stream per handle). */
+int ss_set_stream(void *hip_stream);
+
+/* library version string */
+const char *ss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SS_H */

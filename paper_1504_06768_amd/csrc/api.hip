@@ -1,0 +1,240 @@
+// extern "C" entry points of include/ss.h: argument checks, error
+// translation and handle lifetime.  The work itself is in the other files.
+#include <mutex>
+
+#include "assemble.hpp"
+#include "csr_tools.hpp"
+#include "handle.hpp"
+#include "rcm.hpp"
+
+namespace ss {
+void set_thread_stream(hipStream_t s);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const ss::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(SS_E_OOM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SS_E_HIP, e.what());
+    }
+}
+
+ss_options resolve(const ss_options *opt) {
+    ss_options o;
+    ss_options_default(&o);
+    if (opt) o = *opt;
+    if (o.gmres_m <= 0) o.gmres_m = 20;
+    if (o.maxiter <= 0) o.maxiter = 1000;
+    if (o.max_outer <= 0) o.max_outer = 20;
+    if (o.fill <= 0) o.fill = 10.0;
+    if (o.drop_tol < 0) o.drop_tol = 1e-4;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ss_last_error(void) { return g_err.c_str(); }
+
+const char *ss_version(void) { return "ssolve-0.1 (gfx950)"; }
+
+int ss_options_default(ss_options *opt) {
+    if (!opt) return fail(SS_E_INVALID_ARG, "opt is NULL");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->prec = SS_FP64;
+    opt->ilu = SS_ILU0;
+    opt->ordering = SS_ORDER_RCM;
+    opt->gmres_m = 20;
+    opt->maxiter = 1000;
+    opt->max_outer = 20;
+    opt->flags = 0;
+    opt->drop_tol = 1e-4;
+    opt->fill = 10.0;
+    opt->sigma = 1e-15;
+    opt->inner_tol = 0.0;
+    opt->weight = 0.0;
+    return SS_OK;
+}
+
+int ss_set_stream(void *hip_stream) {
+    ss::set_thread_stream(reinterpret_cast<hipStream_t>(hip_stream));
+    return SS_OK;
+}
+
+int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cops, int64_t N, ss_liouv *out) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(out != nullptr, SS_E_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<ss_liouv_s> h(new ss_liouv_s());
+        SS_HIP(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+        h->N = N;
+        h->d = (int)N;
+        h->n = (int)(N * N);
+        try {
+            ss::assemble_liouvillian(H, c_ops, n_cops, N, ss::stream_of(h.get()), h->L);
+        } catch (...) {
+            (void)hipStreamDestroy(h->own_stream);
+            h->own_stream = nullptr;
+            throw;
+        }
+        *out = h.release();
+        return SS_OK;
+    });
+}
+
+void ss_liouv_free(ss_liouv L) {
+    if (!L) return;
+    if (L->own_stream) {
+        (void)hipStreamSynchronize(L->own_stream);
+    }
+    hipStream_t s = L->own_stream;
+    delete L;
+    if (s) (void)hipStreamDestroy(s);
+}
+
+int ss_liouv_shape(ss_liouv L, int64_t *N, int64_t *n, int64_t *nnz) {
+    if (!L) return fail(SS_E_INVALID_ARG, "null handle");
+    if (N) *N = L->N;
+    if (n) *n = L->n;
+    if (nnz) *nnz = L->L.nnz;
+    return SS_OK;
+}
+
+int ss_prepare(ss_liouv L, int32_t method, const ss_options *opt) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr, SS_E_INVALID_ARG, "null handle");
+        ss::prepare(L, method, resolve(opt));
+        return SS_OK;
+    });
+}
+
+int ss_solve(ss_liouv L, int32_t method, double tol, const ss_options *opt, double *rho_out, ss_info *info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    const int rc = guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr, SS_E_INVALID_ARG, "null handle");
+        SS_REQUIRE(rho_out != nullptr, SS_E_INVALID_ARG, "rho_out is NULL");
+        const int st = ss::solve(L, method, tol, resolve(opt), rho_out, info);
+        if (st == SS_E_NOT_CONVERGED) g_err = "iteration limit reached before ||L rho|| <= tol";
+        if (st == SS_E_BREAKDOWN) g_err = "BiCGSTAB breakdown (no fallback allowed)";
+        return st;
+    });
+    if (info) info->status = rc;
+    return rc;
+}
+
+static const ss::CsrBuf<double2> *pick(ss_liouv L, int which) {
+    switch (which) {
+        case SS_MAT_L: return &L->L;
+        case SS_MAT_A: return L->prepared ? &L->A : nullptr;
+        case SS_MAT_A_PERM: return L->prepared ? &L->Ap : nullptr;
+        case SS_MAT_LU: return L->prepared ? &L->LU : nullptr;
+        case SS_MAT_SYM: return L->prepared ? &L->S : nullptr;
+        default: return nullptr;
+    }
+}
+
+int ss_export_csr(ss_liouv L, int32_t which, int64_t *nnz, int64_t *indptr, int32_t *indices, double *data) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr, SS_E_INVALID_ARG, "null handle");
+        const ss::CsrBuf<double2> *m = pick(L, which);
+        SS_REQUIRE(m != nullptr, which >= 0 && which <= 4 ? SS_E_STATE : SS_E_INVALID_ARG,
+                   "matrix not available (unknown id, or ss_prepare not called)");
+        if (nnz) *nnz = m->nnz;
+        hipStream_t s = ss::stream_of(L);
+        if (indptr) {
+            std::vector<int> rp((size_t)m->n + 1);
+            ss::d2h(rp.data(), m->rowptr.get(), rp.size(), s);
+            for (size_t i = 0; i < rp.size(); ++i) indptr[i] = rp[i];
+        }
+        if (indices && m->nnz) ss::d2h(indices, m->col.get(), (size_t)m->nnz, s);
+        if (data && m->nnz) ss::d2h(reinterpret_cast<double2 *>(data), m->val.get(), (size_t)m->nnz, s);
+        return SS_OK;
+    });
+}
+
+int ss_export_perm(ss_liouv L, int32_t *perm) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr && perm != nullptr, SS_E_INVALID_ARG, "null argument");
+        SS_REQUIRE(L->prepared, SS_E_STATE, "ss_prepare not called");
+        ss::d2h(perm, L->perm.get(), (size_t)L->n, ss::stream_of(L));
+        return SS_OK;
+    });
+}
+
+int ss_bandwidth_profile(ss_liouv L, int32_t which, int64_t *B, int64_t *P) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr && B != nullptr && P != nullptr, SS_E_INVALID_ARG, "null argument");
+        const ss::CsrBuf<double2> *m = pick(L, which);
+        SS_REQUIRE(m != nullptr, SS_E_STATE, "matrix not available");
+        ss::bandwidth_profile(m->n, m->rowptr.get(), m->col.get(), B, P, ss::stream_of(L));
+        return SS_OK;
+    });
+}
+
+int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr && x != nullptr && y != nullptr, SS_E_INVALID_ARG, "null argument");
+        SS_REQUIRE(prec == SS_FP64 || prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
+        SS_REQUIRE(op >= 0 && op <= 4, SS_E_INVALID_ARG, "unknown operator");
+        SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
+        SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
+                   "complex64 operators exist only after a mixed-precision ss_prepare");
+        hipStream_t s = ss::stream_of(L);
+        const int n = L->n;
+        ss::DevBuf<double2> xd((size_t)n), yd((size_t)n);
+        SS_HIP(hipMemcpyAsync(xd.get(), x, sizeof(double2) * n,
+                              ss::is_device_ptr(x) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        if (op == SS_OP_SPMV_L) {
+            const ss::Csr<double2> A = L->L.view();
+            ss::spmv<double2>(A, xd.get(), yd.get(), ss::spmv_group(A.n, A.nnz), s);
+        } else if (prec == SS_FP64) {
+            if (op == SS_OP_SPMV_APERM) {
+                const ss::Csr<double2> A = L->Ap.view();
+                ss::spmv<double2>(A, xd.get(), yd.get(), ss::spmv_group(A.n, A.nnz), s);
+            } else {
+                ss::Precond<double2> M;
+                M.setup(&L->LU, L->lu_diag.get(), n, s);
+                if (op == SS_OP_PRECOND) M.apply(xd.get(), yd.get(), s);
+                else if (op == SS_OP_LSOLVE) M.lower(xd.get(), yd.get(), s);
+                else M.upper(xd.get(), yd.get(), s);
+                SS_REQUIRE(!(M.read_status(s) & ss::STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve timed out");
+            }
+        } else {
+            ss::DevBuf<float2> xf((size_t)n), yf((size_t)n);
+            ss::convert<float2, double2>(n, xd.get(), xf.get(), nullptr, s);
+            if (op == SS_OP_SPMV_APERM) {
+                const ss::Csr<float2> A = L->Ap32.view();
+                ss::spmv<float2>(A, xf.get(), yf.get(), ss::spmv_group(A.n, A.nnz), s);
+            } else {
+                ss::Precond<float2> M;
+                M.setup(&L->LU32, L->lu_diag.get(), n, s);
+                if (op == SS_OP_PRECOND) M.apply(xf.get(), yf.get(), s);
+                else if (op == SS_OP_LSOLVE) M.lower(xf.get(), yf.get(), s);
+                else M.upper(xf.get(), yf.get(), s);
+                SS_REQUIRE(!(M.read_status(s) & ss::STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve timed out");
+            }
+            ss::convert<double2, float2>(n, yf.get(), yd.get(), nullptr, s);
+        }
+        SS_HIP(hipMemcpyAsync(y, yd.get(), sizeof(double2) * n,
+                              ss::is_device_ptr(y) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        SS_HIP(hipStreamSynchronize(s));
+        return SS_OK;
+    });
+}
+
+}  // extern "C"

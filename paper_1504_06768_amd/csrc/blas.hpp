@@ -1,0 +1,58 @@
+// Sparse matrix-vector products, vector kernels and deterministic reductions
+// (blas.hip).
+#pragma once
+#include "ss_internal.hpp"
+
+namespace ss {
+
+constexpr int VEC_BS = 256;
+constexpr int VEC_MAX_BLOCKS = 1024;
+
+inline int vec_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(div_up(n, VEC_BS), VEC_MAX_BLOCKS)); }
+
+// lanes per row for the CSR SpMV, from the mean row length
+int spmv_group(int n, int nnz);
+
+// y = A x
+template <typename T>
+void spmv(const Csr<T> &A, const T *x, T *y, int group, hipStream_t s, const int *skip = nullptr);
+
+// y = A x and block partials of conj(u1).y and (if u2 != null) conj(u2).y;
+// u2 == y requests y^H y.  partials: 2 * vec_blocks(A.n) entries.
+template <typename T>
+void spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, double2 *partials, int group,
+               hipStream_t s, const int *skip);
+
+// r = b - A x in fp64 plus block partials of ||r||^2 (partials[0 .. nb))
+void spmv_residual(const Csr<double2> &A, const double2 *b, const double2 *x, double2 *r, double2 *partials,
+                   int group, hipStream_t s);
+
+// sum of the first nb partials of each of k groups (group stride nb) into
+// out[0..k) on the device, in a fixed order
+void sum_partials(const double2 *partials, int nb, int k, double2 *out, hipStream_t s);
+
+// ||x||^2 of a complex vector (fp64 accumulation) into *out (device)
+template <typename T>
+void norm2(int64_t n, const T *x, double2 *partials, double2 *out, hipStream_t s);
+
+// max_i |x_i| into *out (device, .x)
+template <typename T>
+void norm_inf(int64_t n, const T *x, double2 *partials, double2 *out, hipStream_t s);
+
+// sum_k x[idx[k]] for k < m (fp64), into *out (device)
+void gather_sum(int m, const int *idx, const double2 *x, double2 *out, hipStream_t s);
+
+// dst = src (widening / rounding between precisions), with an optional
+// device-side scale factor 1 / *scale_den (.x) when scale_den != null
+template <typename TD, typename TS>
+void convert(int64_t n, const TS *src, TD *dst, const double2 *scale_den, hipStream_t s);
+
+// x += alpha * d with alpha = *alpha_src (device, real part .x), x fp64
+template <typename T>
+void axpy_widen(int64_t n, const double2 *alpha_src, const T *d, double2 *x, hipStream_t s);
+
+// x[i] = 0
+template <typename T>
+void zero(int64_t n, T *x, hipStream_t s);
+
+}  // namespace ss

@@ -1,0 +1,326 @@
+// Incomplete LU factorisation with zero fill, ILU(0) (section "Iterative
+// Solvers": iLU preconditioner of the permuted modified Liouvillian), and the
+// sync-free sparse triangular solves that apply it.
+//
+// Factorisation: row-wise (IKJ) elimination, one wavefront per row, rows in
+// increasing order.  For every k < i with a_ik != 0 (increasing k): wait for
+// row k's published U part, l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the
+// j > k present in both row i and row k.  This is the serial ILU(0) order,
+// so the factors equal a serial ILU(0) up to rounding of each fused
+// multiply-add.  Done in fp64 for both precisions; the mixed path rounds the
+// finished factors to complex64.
+//
+// Pivot guard: |u_ii| < guard * ||a_i||_inf is replaced by guard * ||a_i||_inf
+// times the pivot's phase (or by that value when the pivot is 0), counted.
+#include "csr_tools.hpp"
+#include "ilu.hpp"
+#include "syncfree.hpp"
+
+namespace ss {
+
+constexpr int ILU_WPB = 4;  // wavefronts (rows) per workgroup
+
+__global__ void __launch_bounds__(ILU_WPB * 64) k_ilu0(int n, const int *rowptr, const int *col, const int *diag,
+                                                       const double2 *a, double2 *w, double2 *out, unsigned *ctr,
+                                                       unsigned base, double guard, unsigned *status,
+                                                       int *nguard) {
+    const unsigned bid = ordered_block(ctr, base);
+    const int lane = threadIdx.x & 63;
+    const int row = (int)bid * ILU_WPB + (int)(threadIdx.x >> 6);
+    if (row >= n) return;
+    const int rs = rowptr[row], re = rowptr[row + 1], dg = diag[row];
+    double rn = 0.0;
+    for (int e = rs + lane; e < re; e += 64) {
+        const double2 v = a[e];
+        w[e] = v;
+        rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
+    }
+    for (int off = 32; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, 64));
+
+    for (int ek = rs; ek < dg; ++ek) {
+        const int k = col[ek];
+        const int dk = diag[k];
+        const int ke = rowptr[k + 1];
+        double2 ukk = mk(0.0, 0.0);
+        if (lane == 0) ukk = wait_load(out + dk, status);
+        ukk.x = __shfl(ukk.x, 0, 64);
+        ukk.y = __shfl(ukk.y, 0, 64);
+        const int owner = (ek - rs) & 63;
+        double2 l = mk(0.0, 0.0);
+        if (lane == owner) {
+            l = cdiv(w[ek], ukk);
+            w[ek] = l;
+        }
+        l.x = __shfl(l.x, owner, 64);
+        l.y = __shfl(l.y, owner, 64);
+        for (int e = rs + lane; e < re; e += 64) {
+            if (e <= ek) continue;
+            const int j = col[e];
+            int lo = dk + 1, hi = ke - 1, f = -1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int c = col[mid];
+                if (c == j) { f = mid; break; }
+                if (c < j) lo = mid + 1; else hi = mid - 1;
+            }
+            if (f >= 0) {
+                const double2 u = wait_load(out + f, status);
+                w[e] = csub(w[e], cmul(l, u));
+            }
+        }
+    }
+    if (lane == ((dg - rs) & 63)) {
+        const double2 p = w[dg];
+        const double mag = sqrt(p.x * p.x + p.y * p.y);
+        const double bound = guard * rn;
+        if (!(mag >= bound)) {
+            w[dg] = (mag > 0.0) ? cscale(p, bound / mag) : mk(bound > 0.0 ? bound : 1.0, 0.0);
+            atomicAdd(nguard, 1);
+        }
+    }
+    for (int e = rs + lane; e < re; e += 64) publish(out + e, w[e]);
+}
+
+template <typename T>
+__global__ void k_fill_sentinel(int64_t n, T *p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) set_sentinel(p + i);
+}
+
+template <typename T>
+void fill_sentinel(int64_t n, T *p, hipStream_t s) {
+    if (n > 0) {
+        k_fill_sentinel<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, p);
+        SS_HIP(hipGetLastError());
+    }
+}
+template void fill_sentinel<double2>(int64_t, double2 *, hipStream_t);
+template void fill_sentinel<float2>(int64_t, float2 *, hipStream_t);
+
+__global__ void k_round_c64(int64_t n, const double2 *a, float2 *b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = to_c64(a[i]);
+}
+
+void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s) {
+    if (n > 0) {
+        k_round_c64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, b);
+        SS_HIP(hipGetLastError());
+    }
+}
+
+IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double guard, CsrBuf<double2> &LU,
+                      hipStream_t s) {
+    const int n = A.n, nnz = A.nnz;
+    LU.alloc(n, nnz);
+    SS_HIP(hipMemcpyAsync(LU.rowptr.get(), A.rowptr.get(), sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) SS_HIP(hipMemcpyAsync(LU.col.get(), A.col.get(), sizeof(int) * nnz, hipMemcpyDeviceToDevice, s));
+    DevBuf<double2> work((size_t)nnz);
+    fill_sentinel<double2>(nnz, LU.val.get(), s);
+    DevBuf<unsigned> status(1);
+    DevBuf<int> nguard(1);
+    SS_HIP(hipMemsetAsync(status.get(), 0, sizeof(unsigned), s));
+    SS_HIP(hipMemsetAsync(nguard.get(), 0, sizeof(int), s));
+    BlockCounter bc;
+    bc.init(s);
+    const unsigned grid = (unsigned)div_up(n, ILU_WPB);
+    if (n) {
+        k_ilu0<<<grid, ILU_WPB * 64, 0, s>>>(n, A.rowptr.get(), A.col.get(), diag, A.val.get(), work.get(),
+                                              LU.val.get(), bc.ctr.get(), bc.take(grid), guard, status.get(),
+                                              nguard.get());
+        SS_HIP(hipGetLastError());
+    }
+    IluResult r;
+    unsigned st = 0;
+    d2h(&st, status.get(), 1, s);
+    d2h(&r.guarded, nguard.get(), 1, s);
+    SS_REQUIRE(!(st & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "ILU(0): dependency wait timed out");
+    return r;
+}
+
+// ------------------------------------------------ triangular solves
+// One thread per row.  Each pass a lane loads the next batch of dependency
+// values (independent loads, issued together) and consumes them in column
+// order while they are published, so the accumulation order is fixed.
+constexpr int TRSV_BS = 256;
+constexpr int TRSV_BATCH = 8;
+
+// y = L^-1 b with L unit lower (strict lower part of LU); resets `reset`
+// (the output of the following upper solve) to the sentinel.
+template <typename T>
+__global__ void __launch_bounds__(TRSV_BS) k_trsv_lower(int n, const int *rowptr, const int *col, const T *val,
+                                                        const int *diag, const T *b, T *y, T *reset,
+                                                        unsigned *ctr, unsigned base, unsigned *status,
+                                                        const int *skip) {
+    const unsigned bid = ordered_block(ctr, base);
+    if (skip && *skip) return;
+    const int row = (int)bid * TRSV_BS + threadIdx.x;
+    const bool active = row < n;
+    int e = 0, ee = 0;
+    T acc = czero<T>();
+    if (active) {
+        e = rowptr[row];
+        ee = diag[row];
+        acc = b[row];
+        if (reset) set_sentinel(reset + row);
+    }
+    bool done = !active;
+    unsigned spins = 0;
+    while (true) {
+        if (!done) {
+            T v[TRSV_BATCH];
+            bool ok[TRSV_BATCH];
+#pragma unroll
+            for (int q = 0; q < TRSV_BATCH; ++q) {
+                ok[q] = false;
+                if (e + q < ee) ok[q] = try_load(y + col[e + q], v[q]);
+            }
+            bool run = true;
+            int used = 0;
+#pragma unroll
+            for (int q = 0; q < TRSV_BATCH; ++q) {
+                if (run && e + q < ee && ok[q]) {
+                    acc = csub(acc, cmul(val[e + q], v[q]));
+                    ++used;
+                } else {
+                    run = false;
+                }
+            }
+            e += used;
+            if (used) {
+                spins = 0;
+            } else if (e < ee) {
+                ++spins;
+                if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(status))) {
+                    atomicOr(status, STATUS_SPIN_TIMEOUT);
+                    e = ee;
+                }
+            }
+            if (e >= ee) {
+                publish(y + row, acc);
+                done = true;
+            }
+        }
+        if (__all(done)) break;
+    }
+}
+
+// z = U^-1 y (U = diagonal and upper part of LU), rows from the last one
+// up; resets y to the sentinel for the next lower solve.
+template <typename T>
+__global__ void __launch_bounds__(TRSV_BS) k_trsv_upper(int n, const int *rowptr, const int *col, const T *val,
+                                                        const int *diag, T *y, T *z, unsigned *ctr, unsigned base,
+                                                        unsigned *status, const int *skip) {
+    const unsigned bid = ordered_block(ctr, base);
+    if (skip && *skip) return;
+    const int lin = (int)bid * TRSV_BS + threadIdx.x;
+    const bool active = lin < n;
+    const int row = n - 1 - lin;
+    int e = 0, ee = 0, dg = 0;
+    T acc = czero<T>();
+    if (active) {
+        dg = diag[row];
+        e = dg + 1;
+        ee = rowptr[row + 1];
+        acc = y[row];
+        set_sentinel(y + row);
+    }
+    bool done = !active;
+    unsigned spins = 0;
+    while (true) {
+        if (!done) {
+            T v[TRSV_BATCH];
+            bool ok[TRSV_BATCH];
+#pragma unroll
+            for (int q = 0; q < TRSV_BATCH; ++q) {
+                ok[q] = false;
+                if (e + q < ee) ok[q] = try_load(z + col[e + q], v[q]);
+            }
+            bool run = true;
+            int used = 0;
+#pragma unroll
+            for (int q = 0; q < TRSV_BATCH; ++q) {
+                if (run && e + q < ee && ok[q]) {
+                    acc = csub(acc, cmul(val[e + q], v[q]));
+                    ++used;
+                } else {
+                    run = false;
+                }
+            }
+            e += used;
+            if (used) {
+                spins = 0;
+            } else if (e < ee) {
+                ++spins;
+                if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(status))) {
+                    atomicOr(status, STATUS_SPIN_TIMEOUT);
+                    e = ee;
+                }
+            }
+            if (e >= ee) {
+                publish(z + row, cdiv(acc, val[dg]));
+                done = true;
+            }
+        }
+        if (__all(done)) break;
+    }
+}
+
+template <typename T>
+void Precond<T>::setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s) {
+    LU = lu;
+    diag = dg;
+    n = n_;
+    y.resize((size_t)n);
+    fill_sentinel<T>(n, y.get(), s);
+    status.resize(1);
+    SS_HIP(hipMemsetAsync(status.get(), 0, sizeof(unsigned), s));
+    counter.init(s);
+}
+
+template <typename T>
+void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
+    if (n == 0) return;
+    const unsigned grid = (unsigned)div_up(n, TRSV_BS);
+    k_trsv_lower<T><<<grid, TRSV_BS, 0, s>>>(n, LU->rowptr.get(), LU->col.get(), LU->val.get(), diag, b, y.get(),
+                                              out, counter.ctr.get(), counter.take(grid), status.get(), skip);
+    k_trsv_upper<T><<<grid, TRSV_BS, 0, s>>>(n, LU->rowptr.get(), LU->col.get(), LU->val.get(), diag, y.get(), out,
+                                              counter.ctr.get(), counter.take(grid), status.get(), skip);
+    SS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void Precond<T>::lower(const T *b, T *out, hipStream_t s) {
+    // out = L^-1 b: run the lower solve into y, then copy (out must not alias y)
+    if (n == 0) return;
+    const unsigned grid = (unsigned)div_up(n, TRSV_BS);
+    k_trsv_lower<T><<<grid, TRSV_BS, 0, s>>>(n, LU->rowptr.get(), LU->col.get(), LU->val.get(), diag, b, y.get(),
+                                              nullptr, counter.ctr.get(), counter.take(grid), status.get(),
+                                              nullptr);
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipMemcpyAsync(out, y.get(), sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    fill_sentinel<T>(n, y.get(), s);
+}
+
+template <typename T>
+void Precond<T>::upper(const T *b, T *out, hipStream_t s) {
+    if (n == 0) return;
+    SS_HIP(hipMemcpyAsync(y.get(), b, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    fill_sentinel<T>(n, out, s);
+    const unsigned grid = (unsigned)div_up(n, TRSV_BS);
+    k_trsv_upper<T><<<grid, TRSV_BS, 0, s>>>(n, LU->rowptr.get(), LU->col.get(), LU->val.get(), diag, y.get(), out,
+                                              counter.ctr.get(), counter.take(grid), status.get(), nullptr);
+    SS_HIP(hipGetLastError());
+}
+
+template <typename T>
+unsigned Precond<T>::read_status(hipStream_t s) {
+    unsigned st = 0;
+    d2h(&st, status.get(), 1, s);
+    return st;
+}
+
+template struct Precond<double2>;
+template struct Precond<float2>;
+
+}  // namespace ss

@@ -1,0 +1,43 @@
+// ILU factorisation and its application (ilu.hip).
+#pragma once
+#include "ss_internal.hpp"
+#include "syncfree.hpp"
+
+namespace ss {
+
+struct IluResult {
+    int guarded = 0;
+};
+
+// ILU(0) of A (rows sorted, diagonal positions in diag) in fp64.
+IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double guard, CsrBuf<double2> &LU, hipStream_t s);
+
+// Dual-threshold ILUT (drop_tol relative to ||row||_inf, at most
+// ceil(fill * nnz(row)) entries kept in each of L and U per row).
+IluResult ilut_factor(const CsrBuf<double2> &A, const int *diag, double drop_tol, double fill, double guard,
+                      CsrBuf<double2> &LU, DevBuf<int> &lu_diag, hipStream_t s);
+
+template <typename T>
+void fill_sentinel(int64_t n, T *p, hipStream_t s);
+
+void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s);
+
+// M^-1 = (L U)^-1 applied with the sync-free triangular solves.
+template <typename T>
+struct Precond {
+    const CsrBuf<T> *LU = nullptr;
+    const int *diag = nullptr;
+    int n = 0;
+    DevBuf<T> y;           // lower-solve result, kept at the sentinel between applies
+    DevBuf<unsigned> status;
+    BlockCounter counter;
+    void setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s);
+    // out = (LU)^-1 b; out must not alias b or y.  When *skip != 0 on the
+    // device, both solves return at once (used after convergence).
+    void apply(const T *b, T *out, hipStream_t s, const int *skip = nullptr);
+    void lower(const T *b, T *out, hipStream_t s);
+    void upper(const T *b, T *out, hipStream_t s);
+    unsigned read_status(hipStream_t s);
+};
+
+}  // namespace ss

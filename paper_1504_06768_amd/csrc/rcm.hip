@@ -1,0 +1,303 @@
+// Reverse Cuthill-McKee ordering on the device (section "Direct
+// factorization": BFS from a node of lowest degree, neighbours visited in
+// increasing degree, per connected component, order reversed; computed on the
+// structure of A + A^T and applied to rows and columns alike).
+//
+// The sequential queue search is reformulated level by level, which gives
+// the same order: a node first reached from level k is queued by the
+// frontier node that was dequeued first, i.e. the one at the lowest position
+// in the order, and the children of one frontier node are queued by
+// (degree, index).  So level k+1 is sorted by (parent position, degree,
+// index) -- each frontier node claims its unvisited neighbours with an
+// atomicMin on the position, counts and ranks the ones it owns, and an
+// exclusive scan over the frontier gives every node its slot.
+//
+// Tie-breaks where the paper is silent: degree = graph degree in the
+// symmetric pattern (stored row entries, a diagonal entry counted twice); a
+// component starts at the unvisited node of lowest degree and highest index;
+// equal-degree neighbours are queued in increasing index.
+#include "csr_tools.hpp"
+#include "rcm.hpp"
+
+namespace ss {
+
+// --------------------------------------------------- symmetrised pattern
+__global__ void k_union_count(int n, const int *ar, const int *ac, const int *br, const int *bc, int *cnt) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int a = ar[r], ae = ar[r + 1], b = br[r], be = br[r + 1], c = 0;
+    while (a < ae || b < be) {
+        const int x = (a < ae) ? ac[a] : 0x7fffffff;
+        const int y = (b < be) ? bc[b] : 0x7fffffff;
+        if (x <= y) ++a;
+        if (y <= x) ++b;
+        ++c;
+    }
+    cnt[r] = c;
+}
+
+__global__ void k_union_fill(int n, const int *ar, const int *ac, const int *br, const int *bc, const int *orow,
+                             int *ocol, double2 *oval) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int a = ar[r], ae = ar[r + 1], b = br[r], be = br[r + 1], o = orow[r];
+    while (a < ae || b < be) {
+        const int x = (a < ae) ? ac[a] : 0x7fffffff;
+        const int y = (b < be) ? bc[b] : 0x7fffffff;
+        const int m = min(x, y);
+        if (x <= y) ++a;
+        if (y <= x) ++b;
+        ocol[o] = m;
+        if (oval) oval[o] = mk(1.0, 0.0);
+        ++o;
+    }
+}
+
+void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_t s) {
+    CsrBuf<double2> At;
+    transpose(A, At, s, false);
+    const int n = A.n;
+    DevBuf<int> cnt((size_t)n + 1);
+    k_union_count<<<div_up(n, 256), 256, 0, s>>>(n, A.rowptr.get(), A.col.get(), At.rowptr.get(), At.col.get(),
+                                                 cnt.get());
+    SS_HIP(hipGetLastError());
+    S.rowptr.resize((size_t)n + 1);
+    const int64_t nnz = scan_exclusive(cnt.get(), S.rowptr.get(), n, s, true);
+    SS_REQUIRE(nnz < (int64_t(1) << 31), SS_E_INVALID_ARG, "symmetrised pattern too large");
+    S.n = n;
+    S.nnz = (int)nnz;
+    S.col.resize((size_t)nnz);
+    S.val.resize((size_t)nnz);
+    k_union_fill<<<div_up(n, 256), 256, 0, s>>>(n, A.rowptr.get(), A.col.get(), At.rowptr.get(), At.col.get(),
+                                                S.rowptr.get(), S.col.get(), S.val.get());
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ degree
+__global__ void k_degree(int n, const int *rowptr, const int *col, int *deg) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int dg = rowptr[r + 1] - rowptr[r];
+    int lo = rowptr[r], hi = rowptr[r + 1] - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = col[mid];
+        if (c == r) { ++dg; break; }
+        if (c < r) lo = mid + 1; else hi = mid - 1;
+    }
+    deg[r] = dg;
+}
+
+// start node: minimum of (degree, -index) over unvisited nodes
+__global__ void k_pick_start(int n, const int *deg, const int *pos_of, unsigned long long *best) {
+    unsigned long long b = ~0ull;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        if (pos_of[r] < 0) {
+            const unsigned long long key = ((unsigned long long)(unsigned)deg[r] << 32) |
+                                           (unsigned long long)(0xffffffffu - (unsigned)r);
+            b = key < b ? key : b;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_down(b, off, 64);
+        b = o < b ? o : b;
+    }
+    if ((threadIdx.x & 63) == 0 && b != ~0ull) atomicMin(best, b);
+}
+
+__global__ void k_place_start(unsigned long long *best, int *order, int *pos_of, int at) {
+    const unsigned long long b = *best;
+    const int r = (int)(0xffffffffu - (unsigned)(b & 0xffffffffull));
+    order[at] = r;
+    pos_of[r] = at;
+    *best = ~0ull;
+}
+
+// one wavefront per frontier node
+__global__ void __launch_bounds__(256) k_claim(int lo, int hi, const int *order, const int *rowptr, const int *col,
+                                               const int *pos_of, int *owner) {
+    const int lane = threadIdx.x & 63;
+    const int p = lo + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= hi) return;
+    const int u = order[p];
+    for (int e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) {
+        const int v = col[e];
+        if (pos_of[v] < 0) atomicMin(&owner[v], p);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_count_owned(int lo, int hi, const int *order, const int *rowptr,
+                                                     const int *col, const int *pos_of, const int *owner, int *cnt) {
+    const int lane = threadIdx.x & 63;
+    const int p = lo + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= hi) return;
+    const int u = order[p];
+    int c = 0;
+    for (int e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) {
+        const int v = col[e];
+        c += (pos_of[v] < 0 && owner[v] == p);
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if (lane == 0) cnt[p - lo] = c;
+}
+
+__global__ void __launch_bounds__(256) k_place_children(int lo, int hi, int next, const int *order_in,
+                                                        const int *rowptr, const int *col, const int *pos_of,
+                                                        const int *owner, const int *deg, const int *offs,
+                                                        int *order_out) {
+    const int lane = threadIdx.x & 63;
+    const int p = lo + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= hi) return;
+    const int u = order_in[p];
+    const int rs = rowptr[u], re = rowptr[u + 1];
+    const int base = next + offs[p - lo];
+    for (int e = rs + lane; e < re; e += 64) {
+        const int v = col[e];
+        if (!(pos_of[v] < 0 && owner[v] == p)) continue;
+        const int dv = deg[v];
+        int rank = 0;
+        for (int f = rs; f < re; ++f) {
+            const int w = col[f];
+            if (pos_of[w] < 0 && owner[w] == p) {
+                const int dw = deg[w];
+                rank += (dw < dv) || (dw == dv && w < v);
+            }
+        }
+        order_out[base + rank] = v;
+    }
+}
+
+__global__ void k_mark_level(int from, int to, const int *order, int *pos_of) {
+    const int q = from + blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < to) pos_of[order[q]] = q;
+}
+
+__global__ void k_reverse(int n, const int *order, int *perm, int *iperm) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int v = order[n - 1 - q];
+    perm[q] = v;
+    iperm[v] = q;
+}
+
+__global__ void k_identity(int n, int *perm, int *iperm) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) { perm[q] = q; iperm[q] = q; }
+}
+
+__global__ void k_fill_int(int n, int *p, int v) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) p[q] = v;
+}
+
+void rcm_order(const CsrBuf<double2> &S, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s) {
+    const int n = S.n;
+    perm.resize((size_t)n);
+    iperm.resize((size_t)n);
+    if (n == 0) return;
+    DevBuf<int> deg((size_t)n), pos_of((size_t)n), owner((size_t)n), order((size_t)n);
+    DevBuf<int> cnt((size_t)n + 1), offs((size_t)n + 1);
+    DevBuf<unsigned long long> best(1);
+    k_degree<<<div_up(n, 256), 256, 0, s>>>(n, S.rowptr.get(), S.col.get(), deg.get());
+    k_fill_int<<<div_up(n, 256), 256, 0, s>>>(n, pos_of.get(), -1);
+    k_fill_int<<<div_up(n, 256), 256, 0, s>>>(n, owner.get(), 0x7fffffff);
+    SS_HIP(hipMemsetAsync(best.get(), 0xff, sizeof(unsigned long long), s));
+    SS_HIP(hipGetLastError());
+    int visited = 0;
+    while (visited < n) {
+        k_pick_start<<<std::min(div_up(n, 256), 1024), 256, 0, s>>>(n, deg.get(), pos_of.get(), best.get());
+        k_place_start<<<1, 1, 0, s>>>(best.get(), order.get(), pos_of.get(), visited);
+        SS_HIP(hipGetLastError());
+        int lo = visited, hi = visited + 1;
+        visited += 1;
+        while (lo < hi) {
+            const int width = hi - lo;
+            const int nb = div_up(width, 4);
+            k_claim<<<nb, 256, 0, s>>>(lo, hi, order.get(), S.rowptr.get(), S.col.get(), pos_of.get(),
+                                       owner.get());
+            k_count_owned<<<nb, 256, 0, s>>>(lo, hi, order.get(), S.rowptr.get(), S.col.get(), pos_of.get(),
+                                             owner.get(), cnt.get());
+            SS_HIP(hipGetLastError());
+            const int total = (int)scan_exclusive(cnt.get(), offs.get(), width, s, true);
+            if (total > 0) {
+                k_place_children<<<nb, 256, 0, s>>>(lo, hi, hi, order.get(), S.rowptr.get(), S.col.get(),
+                                                    pos_of.get(), owner.get(), deg.get(), offs.get(), order.get());
+                k_mark_level<<<div_up(total, 256), 256, 0, s>>>(hi, hi + total, order.get(), pos_of.get());
+                SS_HIP(hipGetLastError());
+            }
+            lo = hi;
+            hi += total;
+            visited += total;
+        }
+    }
+    k_reverse<<<div_up(n, 256), 256, 0, s>>>(n, order.get(), perm.get(), iperm.get());
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+void identity_order(int n, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s) {
+    perm.resize((size_t)n);
+    iperm.resize((size_t)n);
+    if (n) {
+        k_identity<<<div_up(n, 256), 256, 0, s>>>(n, perm.get(), iperm.get());
+        SS_HIP(hipGetLastError());
+    }
+}
+
+// ----------------------------------------------------------- P A P^T
+__global__ void k_perm_count(int n, const int *perm, const int *rowptr, int *cnt) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) cnt[q] = rowptr[perm[q] + 1] - rowptr[perm[q]];
+}
+
+// one wavefront per output row: map columns through iperm, rank-sort
+__global__ void __launch_bounds__(256) k_perm_fill(int n, const int *perm, const int *iperm, const int *rowptr,
+                                                   const int *col, const double2 *val, const int *orow, int *ocol,
+                                                   double2 *oval) {
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= n) return;
+    const int r = perm[q];
+    const int rs = rowptr[r], re = rowptr[r + 1];
+    const int o = orow[q];
+    for (int e = rs + lane; e < re; e += 64) {
+        const int c = iperm[col[e]];
+        int rank = 0;
+        for (int f = rs; f < re; ++f) rank += (iperm[col[f]] < c);
+        ocol[o + rank] = c;
+        oval[o + rank] = val[e];
+    }
+}
+
+void permute_matrix(const CsrBuf<double2> &A, const int *perm, const int *iperm, CsrBuf<double2> &B, hipStream_t s) {
+    const int n = A.n;
+    DevBuf<int> cnt((size_t)n + 1);
+    B.alloc(n, A.nnz);
+    if (n) {
+        k_perm_count<<<div_up(n, 256), 256, 0, s>>>(n, perm, A.rowptr.get(), cnt.get());
+        SS_HIP(hipGetLastError());
+    }
+    scan_exclusive(cnt.get(), B.rowptr.get(), n, s, false);
+    if (n) {
+        k_perm_fill<<<div_up(n, 4), 256, 0, s>>>(n, perm, iperm, A.rowptr.get(), A.col.get(), A.val.get(),
+                                                 B.rowptr.get(), B.col.get(), B.val.get());
+        SS_HIP(hipGetLastError());
+    }
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------ vector permutes
+__global__ void k_gather_c128(int n, const int *idx, const double2 *x, double2 *y) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = x[idx[q]];
+}
+
+void gather(int n, const int *idx, const double2 *x, double2 *y, hipStream_t s) {
+    if (n) {
+        k_gather_c128<<<div_up(n, 256), 256, 0, s>>>(n, idx, x, y);
+        SS_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace ss

@@ -1,0 +1,21 @@
+// Ordering (rcm.hip).
+#pragma once
+#include "ss_internal.hpp"
+
+namespace ss {
+
+// pattern of A + A^T (values set to 1)
+void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_t s);
+
+// reverse Cuthill-McKee of a symmetric pattern: perm[new] = old, iperm[old] = new
+void rcm_order(const CsrBuf<double2> &S, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s);
+
+void identity_order(int n, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s);
+
+// B = P A P^T (rows and columns permuted, rows sorted)
+void permute_matrix(const CsrBuf<double2> &A, const int *perm, const int *iperm, CsrBuf<double2> &B, hipStream_t s);
+
+// y[q] = x[idx[q]]
+void gather(int n, const int *idx, const double2 *x, double2 *y, hipStream_t s);
+
+}  // namespace ss

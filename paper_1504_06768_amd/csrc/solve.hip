@@ -1,0 +1,360 @@
+// Set-up and solve drivers.
+//
+// Set-up (ss_prepare): problem transform (trace row or shift), symmetrised
+// pattern, reverse Cuthill-McKee, P A P^T, ILU factors -- all on the device.
+//
+// Trace-row driver (section "Direct factorization", eq. linear, solved
+// iteratively as in section "Iterative Solvers", eq. modified): fp64
+// iterative refinement around the inner Krylov solve,
+//     r = b - L~ x   (fp64),  solve L~ d = r / ||r||  (inner precision),
+//     x += ||r|| d   (fp64),
+// until ||L vec(rho)||_2 <= tol with rho = unvec(x) / Tr x.  With fp64 inner
+// solves this is plain preconditioned Krylov plus a residual check.
+//
+// Inverse-power driver (the doubly-iterative inverse-power method, section
+// "Iterative Solvers", eqs. inverse and inverseiter): the normalised step
+// x <- (L - sigma I)^-1 x / || . || is taken in the equivalent correction
+// form  (L - sigma I)^-1 x = -(x - d) / sigma  with  (L - sigma I) d = L x,
+// i.e. x <- x - d, then x <- x / Tr x.  The direction is the same; the inner
+// right-hand side is the (trace-free) residual, which stays meaningful when
+// the inner solve runs in complex64, where sigma = 1e-15 cannot be
+// represented next to O(1) diagonal entries.  Inner tolerance one decade
+// below the outer one (relative to the current residual).
+#include <chrono>
+
+#include "assemble.hpp"
+#include "csr_tools.hpp"
+#include "handle.hpp"
+#include "rcm.hpp"
+#include "transform.hpp"
+
+namespace ss {
+
+static thread_local hipStream_t tls_stream = nullptr;
+
+void set_thread_stream(hipStream_t s) { tls_stream = s; }
+hipStream_t stream_of(ss_liouv h) { return tls_stream ? tls_stream : h->own_stream; }
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+__global__ void k_trace_positions(int d, const int *iperm, int *tpos) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < d) tpos[k] = iperm[(int64_t)k * (d + 1)];
+}
+
+__global__ void k_copy_d2(const double2 *src, double2 *dst) { *dst = *src; }
+
+template <typename TD>
+__global__ void k_round_vals(int64_t n, const double2 *a, TD *b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = from_c128<TD>(a[i]);
+}
+
+static void copy_pattern_c64(const CsrBuf<double2> &a, CsrBuf<float2> &b, hipStream_t s) {
+    b.alloc(a.n, a.nnz);
+    SS_HIP(hipMemcpyAsync(b.rowptr.get(), a.rowptr.get(), sizeof(int) * (a.n + 1), hipMemcpyDeviceToDevice, s));
+    if (a.nnz) {
+        SS_HIP(hipMemcpyAsync(b.col.get(), a.col.get(), sizeof(int) * a.nnz, hipMemcpyDeviceToDevice, s));
+        round_to_c64(a.nnz, a.val.get(), b.val.get(), s);
+    }
+}
+
+static bool is_trace(int method) { return method == SS_TRACE_BICGSTAB || method == SS_TRACE_GMRES; }
+static bool is_gmres(int method) { return method == SS_TRACE_GMRES || method == SS_INVPOW_GMRES; }
+
+void prepare(ss_liouv h, int method, const ss_options &o) {
+    SS_REQUIRE(method >= 0 && method <= 3, SS_E_INVALID_ARG, "unknown method");
+    SS_REQUIRE(o.prec == SS_FP64 || o.prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
+    SS_REQUIRE(o.ilu == SS_ILU0 || o.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
+    SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG, "unknown ordering");
+    hipStream_t s = stream_of(h);
+    const double t0 = now_ms();
+    h->prepared = false;
+    const int n = h->n, d = h->d;
+    h->d_w.resize(1);
+    if (is_trace(method)) {
+        if (o.weight != 0.0) {
+            const double2 w = mk(o.weight, 0.0);
+            h2d(h->d_w.get(), &w, 1, s);
+        } else {
+            mean_diagonal(h->L, h->d_w.get(), s);
+        }
+        d2h(&h->w, h->d_w.get(), 1, s);
+        SS_REQUIRE(h->w.x != 0.0 || h->w.y != 0.0, SS_E_INVALID_ARG, "trace-row weight is zero");
+        make_modified(h->L, d, h->d_w.get(), h->A, s);
+    } else {
+        h->w = mk(0.0, 0.0);
+        make_shifted(h->L, o.sigma, h->A, s);
+    }
+    symmetrize_pattern(h->A, h->S, s);
+    if (o.ordering == SS_ORDER_RCM) rcm_order(h->S, h->perm, h->iperm, s);
+    else identity_order(n, h->perm, h->iperm, s);
+    permute_matrix(h->A, h->perm.get(), h->iperm.get(), h->Ap, s);
+    h->diag.resize((size_t)n);
+    const int missing = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
+    SS_REQUIRE(missing == 0, SS_E_ZERO_PIVOT,
+               std::to_string(missing) + " rows of the transformed matrix have a structurally zero diagonal");
+    const double guard = (o.prec == SS_MIXED) ? 1e-6 : 1e-12;
+    if (o.ilu == SS_ILU0) {
+        h->guarded = ilu0_factor(h->Ap, h->diag.get(), guard, h->LU, s).guarded;
+        h->lu_diag.resize((size_t)n);
+        if (n) SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+        h->guarded = ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, guard, h->LU, h->lu_diag, s).guarded;
+    }
+    if (o.prec == SS_MIXED) {
+        copy_pattern_c64(h->Ap, h->Ap32, s);
+        copy_pattern_c64(h->LU, h->LU32, s);
+    } else {
+        h->Ap32 = CsrBuf<float2>();
+        h->LU32 = CsrBuf<float2>();
+    }
+    h->tpos.resize((size_t)d);
+    k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
+    SS_HIP(hipGetLastError());
+    d2h(&h->q0, h->iperm.get(), 1, s);
+    h->p_method = method;
+    h->p_opt = o;
+    h->prepared = true;
+    h->t_setup_ms = now_ms() - t0;
+}
+
+// ------------------------------------------------------------ helpers
+__global__ void k_set_scalar(double2 *dst, double2 v) { *dst = v; }
+
+// x[idx[k]] = v for k < m
+__global__ void k_set_at(int m, const int *idx, double2 *x, double2 v) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) x[idx[k]] = v;
+}
+
+// x *= 1 / t (complex)
+__global__ void k_scale_inv(int n, double2 *x, const double2 *t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 inv = cdiv(mk(1.0, 0.0), *t);
+    x[i] = cmul(x[i], inv);
+}
+
+// y[perm[q]] = x[q] / t   (undo the ordering, normalise the trace)
+__global__ void k_unpermute_scale(int n, const int *perm, const double2 *x, const double2 *t, double2 *y) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double2 inv = cdiv(mk(1.0, 0.0), *t);
+    y[perm[q]] = cmul(x[q], inv);
+}
+
+// max |rho_ij - conj(rho_ji)| over the d x d matrix stored column-major
+__global__ void k_herm_err(int d, const double2 *rho, double2 *partials) {
+    __shared__ double sh[256];
+    double m = 0;
+    const int64_t nn = (int64_t)d * d;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nn; q += (int64_t)gridDim.x * 256) {
+        const int i = (int)(q % d), j = (int)(q / d);
+        const double2 a = rho[q], b = rho[(int64_t)i * d + j];
+        const double dx = a.x - b.x, dy = a.y + b.y;
+        m = fmax(m, sqrt(dx * dx + dy * dy));
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = mk(sh[0], 0.0);
+}
+
+__global__ void k_hermitize(int d, const double2 *rho, double2 *out) {
+    const int64_t nn = (int64_t)d * d;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nn) return;
+    const int i = (int)(q % d), j = (int)(q / d);
+    const double2 a = rho[q], b = rho[(int64_t)i * d + j];
+    out[q] = mk(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+}
+
+__global__ void k_max_part(const double2 *p, int nb, double2 *out) {
+    if (threadIdx.x) return;
+    double m = 0;
+    for (int b = 0; b < nb; ++b) m = fmax(m, p[b].x);
+    *out = mk(m, 0.0);
+}
+
+// ------------------------------------------------------------- driver
+template <typename T>
+static int run(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
+               double *rho_out, ss_info *info) {
+    hipStream_t s = stream_of(h);
+    const int n = h->n, d = h->d;
+    const double t0 = now_ms();
+    Precond<T> M;
+    M.setup(&LUin, h->lu_diag.get(), n, s);
+    Krylov<T> K;
+    K.init(Ain.view(), &M, s);
+    const Csr<double2> A64 = h->Ap.view();
+    const int gA = spmv_group(A64.n, A64.nnz);
+
+    DevBuf<double2> x((size_t)n), r((size_t)n), part(4 * (size_t)VEC_MAX_BLOCKS), scal(16);
+    DevBuf<T> bT((size_t)n), dT((size_t)n);
+    double2 *sc = scal.get();
+    const bool trace = is_trace(method);
+    const bool mixed = (o.prec == SS_MIXED);
+    bool use_gmres = is_gmres(method);
+    DevBuf<double2> bvec;
+    if (trace) {
+        bvec.resize((size_t)n);
+        zero<double2>(n, bvec.get(), s);
+        k_set_at<<<1, 1, 0, s>>>(1, h->iperm.get(), bvec.get(), h->w);  // b = w e_0, permuted
+        zero<double2>(n, x.get(), s);
+    } else {
+        zero<double2>(n, x.get(), s);
+        k_set_at<<<div_up(d, 256), 256, 0, s>>>(d, h->tpos.get(), x.get(), mk(1.0 / d, 0.0));  // vec(I / d)
+    }
+    SS_HIP(hipGetLastError());
+
+    int status = SS_E_NOT_CONVERGED;
+    int outer = 0, inner_total = 0, breakdowns = 0, fell_back = 0;
+    double resid = INFINITY;
+    const int maxouter = o.max_outer > 0 ? o.max_outer : 20;
+    for (outer = 0; outer <= maxouter; ++outer) {
+        // fp64 residual and trace
+        double2 hs[3];
+        if (trace) {
+            spmv_residual(A64, bvec.get(), x.get(), r.get(), part.get(), gA, s);
+            sum_partials(part.get(), vec_blocks(n), 1, sc, s);
+            gather_sum(d, h->tpos.get(), x.get(), sc + 1, s);
+            k_copy_d2<<<1, 1, 0, s>>>(r.get() + h->q0, sc + 2);
+            SS_HIP(hipGetLastError());
+            d2h(hs, sc, 3, s);
+            const double r2 = hs[0].x;
+            const double2 tr = hs[1], rq = hs[2];
+            // L x = -r + w (1 - Tr x) e_q0  (row q0 carries the trace row)
+            const double2 one_m_tr = mk(1.0 - tr.x, -tr.y);
+            const double2 e0 = csub(cmul(h->w, one_m_tr), rq);
+            const double lx2 = fmax(r2 - (rq.x * rq.x + rq.y * rq.y), 0.0) + e0.x * e0.x + e0.y * e0.y;
+            const double trm = sqrt(tr.x * tr.x + tr.y * tr.y);
+            resid = (trm > 0) ? sqrt(lx2) / trm : INFINITY;
+            if (outer > 0 && resid <= tol) { status = SS_OK; break; }
+            if (outer == maxouter) break;
+            const double rn = sqrt(r2);
+            if (rn == 0.0) { status = SS_OK; break; }
+            double2 den = mk(rn, 0.0);
+            h2d(sc + 4, &den, 1, s);
+        } else {
+            // r = L x = (L - sigma I) x + sigma x
+            spmv_residual(A64, nullptr, x.get(), r.get(), part.get(), gA, s);
+            double2 sg = mk(o.sigma, 0.0);
+            h2d(sc + 5, &sg, 1, s);
+            axpy_widen<double2>(n, sc + 5, x.get(), r.get(), s);
+            norm2<double2>(n, r.get(), part.get(), sc, s);
+            gather_sum(d, h->tpos.get(), x.get(), sc + 1, s);
+            d2h(hs, sc, 2, s);
+            const double trm = sqrt(hs[1].x * hs[1].x + hs[1].y * hs[1].y);
+            resid = (trm > 0) ? sqrt(hs[0].x) / trm : INFINITY;
+            if (resid <= tol) { status = SS_OK; break; }
+            if (outer == maxouter) break;
+            double2 den = mk(sqrt(hs[0].x), 0.0);
+            h2d(sc + 4, &den, 1, s);
+        }
+        // inner solve of A d = r / ||r||
+        double2 hden;
+        d2h(&hden, sc + 4, 1, s);
+        double rtol_in = o.inner_tol;
+        if (rtol_in <= 0) rtol_in = mixed ? 1e-4 : std::max(0.1 * tol / hden.x, 1e-13);
+        rtol_in = std::min(rtol_in, 0.5);
+        convert<T, double2>(n, r.get(), bT.get(), sc + 4, s);
+        KrylovResult kr;
+        if (!use_gmres) {
+            kr = K.bicgstab(bT.get(), dT.get(), rtol_in, o.maxiter);
+            breakdowns += kr.breakdown;
+            if (!kr.converged && kr.breakdown) {
+                if (o.flags & SS_FLAG_NO_FALLBACK) {
+                    inner_total += kr.iters;
+                    status = SS_E_BREAKDOWN;
+                    break;
+                }
+                // fall back to GMRES for this and the remaining steps
+                inner_total += kr.iters;
+                use_gmres = true;
+                fell_back = 1;
+                kr = K.gmres(bT.get(), dT.get(), rtol_in, o.maxiter, o.gmres_m);
+            }
+        } else {
+            kr = K.gmres(bT.get(), dT.get(), rtol_in, o.maxiter, o.gmres_m);
+        }
+        inner_total += kr.iters;
+        const unsigned pst = M.read_status(s);
+        SS_REQUIRE(!(pst & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve: dependency wait timed out");
+        if (trace) {
+            axpy_widen<T>(n, sc + 4, dT.get(), x.get(), s);  // x += ||r|| d
+        } else {
+            double2 neg = mk(-hden.x, 0.0);
+            h2d(sc + 6, &neg, 1, s);
+            axpy_widen<T>(n, sc + 6, dT.get(), x.get(), s);  // x -= ||r|| d
+            gather_sum(d, h->tpos.get(), x.get(), sc + 7, s);
+            k_scale_inv<<<div_up(n, 256), 256, 0, s>>>(n, x.get(), sc + 7);  // x /= Tr x
+            SS_HIP(hipGetLastError());
+        }
+    }
+    const double t1 = now_ms();
+
+    // finish: unpermute, normalise the trace, certificate with L itself
+    gather_sum(d, h->tpos.get(), x.get(), sc + 8, s);
+    double2 trx;
+    d2h(&trx, sc + 8, 1, s);
+    DevBuf<double2> rho((size_t)n), Lr((size_t)n);
+    k_unpermute_scale<<<div_up(n, 256), 256, 0, s>>>(n, h->perm.get(), x.get(), sc + 8, rho.get());
+    SS_HIP(hipGetLastError());
+    if (o.flags & SS_FLAG_HERMITIZE) {
+        k_hermitize<<<div_up(n, 256), 256, 0, s>>>(d, rho.get(), Lr.get());
+        SS_HIP(hipMemcpyAsync(rho.get(), Lr.get(), sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+    }
+    const Csr<double2> Lv = h->L.view();
+    spmv<double2>(Lv, rho.get(), Lr.get(), spmv_group(Lv.n, Lv.nnz), s);
+    norm2<double2>(n, Lr.get(), part.get(), sc + 9, s);
+    const int nbh = vec_blocks(n);
+    k_herm_err<<<nbh, 256, 0, s>>>(d, rho.get(), part.get());
+    k_max_part<<<1, 64, 0, s>>>(part.get(), nbh, sc + 10);
+    SS_HIP(hipGetLastError());
+    double2 fin[2];
+    d2h(fin, sc + 9, 2, s);
+    if (rho_out) {
+        const hipMemcpyKind k = is_device_ptr(rho_out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        SS_HIP(hipMemcpyAsync(rho_out, rho.get(), sizeof(double2) * n, k, s));
+        SS_HIP(hipStreamSynchronize(s));
+    }
+    const double final_res = sqrt(fin[0].x);
+    if (status == SS_E_NOT_CONVERGED && final_res <= tol) status = SS_OK;
+    if (info) {
+        info->status = status;
+        info->outer_its = outer;
+        info->inner_its = inner_total;
+        info->breakdowns = breakdowns;
+        info->pivots_guarded = h->guarded;
+        info->fell_back = fell_back;
+        info->nnz_matrix = h->Ap.nnz;
+        info->nnz_factors = h->LU.nnz;
+        info->fill_factor = h->Ap.nnz ? (double)h->LU.nnz / h->Ap.nnz : 0.0;
+        info->resid_l2 = final_res;
+        info->herm_err = fin[1].x;
+        info->trace_err = sqrt((trx.x - 1.0) * (trx.x - 1.0) + trx.y * trx.y);
+        info->weight = h->w.x;
+        info->t_setup_ms = h->t_setup_ms;
+        info->t_solve_ms = t1 - t0;
+    }
+    return status;
+}
+
+int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {
+    SS_REQUIRE(tol > 0 && std::isfinite(tol), SS_E_INVALID_ARG, "tol must be positive");
+    prepare(h, method, o);
+    int st;
+    if (o.prec == SS_MIXED) st = run<float2>(h, method, tol, o, h->Ap32, h->LU32, rho_out, info);
+    else st = run<double2>(h, method, tol, o, h->Ap, h->LU, rho_out, info);
+    return st;
+}
+
+}  // namespace ss

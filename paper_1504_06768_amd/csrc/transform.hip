@@ -1,0 +1,179 @@
+// Problem transforms of the Liouvillian (a2):
+//   modified  L~ = L + w T  (section "Direct factorization", eq. linear), T
+//             with ones in row 0 at the columns k (d + 1) of the diagonal of
+//             rho, w = mean of the diagonal of L unless given;
+//   shifted   L - sigma I   (section "Eigenvalue Methods", eq. inverse).
+#include "csr_tools.hpp"
+#include "transform.hpp"
+
+namespace ss {
+
+// Sum of the diagonal of a CSR matrix (binary search per row), reduced in a
+// fixed order: per-block partial sums, then one block adds them in order.
+__global__ void __launch_bounds__(256) k_diag_partial(int n, const int *rowptr, const int *col, const double2 *val,
+                                                      double2 *partial) {
+    __shared__ double sx[256], sy[256];
+    double ax = 0, ay = 0;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+        int lo = rowptr[r], hi = rowptr[r + 1] - 1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int c = col[mid];
+            if (c == r) { ax += val[mid].x; ay += val[mid].y; break; }
+            if (c < r) lo = mid + 1; else hi = mid - 1;
+        }
+    }
+    sx[threadIdx.x] = ax;
+    sy[threadIdx.x] = ay;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            sx[threadIdx.x] += sx[threadIdx.x + off];
+            sy[threadIdx.x] += sy[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = mk(sx[0], sy[0]);
+}
+
+__global__ void k_mean_finish(int nparts, const double2 *partial, int n, double2 *out) {
+    if (threadIdx.x != 0) return;
+    double ax = 0, ay = 0;
+    for (int b = 0; b < nparts; ++b) { ax += partial[b].x; ay += partial[b].y; }
+    *out = mk(ax / n, ay / n);
+}
+
+void mean_diagonal(const CsrBuf<double2> &L, double2 *d_out, hipStream_t s) {
+    constexpr int NB = 256;
+    DevBuf<double2> part(NB);
+    k_diag_partial<<<NB, 256, 0, s>>>(L.n, L.rowptr.get(), L.col.get(), L.val.get(), part.get());
+    SS_HIP(hipGetLastError());
+    k_mean_finish<<<1, 64, 0, s>>>(NB, part.get(), L.n, d_out);
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- modified
+// Row 0 of L~ is the merge of row 0 of L with w at the trace columns; all
+// other rows are copied.  Entries that cancel to exactly zero are dropped.
+template <bool FILL>
+__device__ int trace_row0(int d, const int *rowptr, const int *col, const double2 *val, double2 w, int *ocol,
+                          double2 *oval) {
+    int e = rowptr[0];
+    const int ee = rowptr[1];
+    int k = 0;
+    int cnt = 0;
+    while (e < ee || k < d) {
+        const int ce = (e < ee) ? col[e] : 0x7fffffff;
+        const int ct = (k < d) ? k * (d + 1) : 0x7fffffff;
+        const int c = min(ce, ct);
+        double2 v = mk(0.0, 0.0);
+        if (ce == c) { v = val[e]; ++e; }
+        if (ct == c) { v = cadd(v, w); ++k; }
+        if (v.x != 0.0 || v.y != 0.0) {
+            if (FILL) { ocol[cnt] = c; oval[cnt] = v; }
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__global__ void k_mod_count(int n, int d, const int *rowptr, const int *col, const double2 *val, const double2 *w,
+                            int *cnt) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (r == 0) cnt[0] = trace_row0<false>(d, rowptr, col, val, *w, nullptr, nullptr);
+    else cnt[r] = rowptr[r + 1] - rowptr[r];
+}
+
+__global__ void k_mod_fill(int n, int d, const int *rowptr, const int *col, const double2 *val, const double2 *w,
+                           const int *orow, int *ocol, double2 *oval) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (r == 0) {
+        trace_row0<true>(d, rowptr, col, val, *w, ocol + orow[0], oval + orow[0]);
+    } else {
+        const int o = orow[r];
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            ocol[o + e - rowptr[r]] = col[e];
+            oval[o + e - rowptr[r]] = val[e];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- shifted
+template <bool FILL>
+__device__ int shift_row(int r, const int *rowptr, const int *col, const double2 *val, double sigma, int *ocol,
+                         double2 *oval) {
+    int cnt = 0;
+    bool placed = false;
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        const int c = col[e];
+        if (!placed && c > r) {
+            if (FILL) { ocol[cnt] = r; oval[cnt] = mk(-sigma, 0.0); }
+            ++cnt;
+            placed = true;
+        }
+        double2 v = val[e];
+        if (c == r) {
+            v.x -= sigma;
+            placed = true;
+        }
+        if (v.x != 0.0 || v.y != 0.0) {
+            if (FILL) { ocol[cnt] = c; oval[cnt] = v; }
+            ++cnt;
+        }
+    }
+    if (!placed) {
+        if (FILL) { ocol[cnt] = r; oval[cnt] = mk(-sigma, 0.0); }
+        ++cnt;
+    }
+    return cnt;
+}
+
+__global__ void k_shift_count(int n, const int *rowptr, const int *col, const double2 *val, double sigma, int *cnt) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) cnt[r] = shift_row<false>(r, rowptr, col, val, sigma, nullptr, nullptr);
+}
+
+__global__ void k_shift_fill(int n, const int *rowptr, const int *col, const double2 *val, double sigma,
+                             const int *orow, int *ocol, double2 *oval) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) shift_row<true>(r, rowptr, col, val, sigma, ocol + orow[r], oval + orow[r]);
+}
+
+static void finish_rows(CsrBuf<double2> &A, int n, DevBuf<int> &cnt, hipStream_t s) {
+    A.rowptr.resize((size_t)n + 1);
+    const int64_t nnz = scan_exclusive(cnt.get(), A.rowptr.get(), n, s, true);
+    SS_REQUIRE(nnz < (int64_t(1) << 31), SS_E_INVALID_ARG, "transformed matrix too large");
+    A.n = n;
+    A.nnz = (int)nnz;
+    A.col.resize((size_t)nnz);
+    A.val.resize((size_t)nnz);
+}
+
+void make_modified(const CsrBuf<double2> &L, int d, const double2 *d_w, CsrBuf<double2> &A, hipStream_t s) {
+    const int n = L.n;
+    DevBuf<int> cnt((size_t)n + 1);
+    k_mod_count<<<div_up(n, 256), 256, 0, s>>>(n, d, L.rowptr.get(), L.col.get(), L.val.get(), d_w, cnt.get());
+    SS_HIP(hipGetLastError());
+    finish_rows(A, n, cnt, s);
+    k_mod_fill<<<div_up(n, 256), 256, 0, s>>>(n, d, L.rowptr.get(), L.col.get(), L.val.get(), d_w,
+                                              A.rowptr.get(), A.col.get(), A.val.get());
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+void make_shifted(const CsrBuf<double2> &L, double sigma, CsrBuf<double2> &A, hipStream_t s) {
+    const int n = L.n;
+    DevBuf<int> cnt((size_t)n + 1);
+    k_shift_count<<<div_up(n, 256), 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma, cnt.get());
+    SS_HIP(hipGetLastError());
+    finish_rows(A, n, cnt, s);
+    k_shift_fill<<<div_up(n, 256), 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma,
+                                                A.rowptr.get(), A.col.get(), A.val.get());
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace ss

@@ -1,0 +1,330 @@
+"""ctypes binding of libss.so (include/ss.h), same entry-point names.
+
+Inputs are scipy sparse matrices, numpy arrays or torch tensors; host
+inputs are converted to CSR with int64 row pointers, int32 column indices and
+interleaved complex128 values and handed to the library, which validates and
+copies them to the device.  Torch tensors on the GPU are passed as device
+pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libss.so")
+
+SS_OK, SS_PENDING = 0, 1
+SS_E_INVALID_ARG, SS_E_OOM, SS_E_NOT_CONVERGED, SS_E_BREAKDOWN = -1, -2, -3, -4
+SS_E_ZERO_PIVOT, SS_E_HIP, SS_E_STATE, SS_E_TIMEOUT = -5, -6, -7, -8
+SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES = 0, 1, 2, 3
+SS_FP64, SS_MIXED = 0, 1
+SS_ILU0, SS_ILUT = 0, 1
+SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
+SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK = 1, 2
+SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
+SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
+
+METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3}
+PRECS = {"fp64": 0, "mixed": 1}
+
+
+class SolverError(RuntimeError):
+    def __init__(self, code: int, msg: str, info: Optional[dict] = None):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+        self.info = info
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p), ("data", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("ilu", ctypes.c_int32), ("ordering", ctypes.c_int32),
+                ("gmres_m", ctypes.c_int32), ("maxiter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("drop_tol", ctypes.c_double), ("fill", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("weight", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_its", ctypes.c_int32), ("inner_its", ctypes.c_int32),
+                ("breakdowns", ctypes.c_int32), ("pivots_guarded", ctypes.c_int32), ("fell_back", ctypes.c_int32),
+                ("bandwidth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("profile", ctypes.c_int64), ("nnz_matrix", ctypes.c_int64), ("nnz_factors", ctypes.c_int64),
+                ("resid_l2", ctypes.c_double), ("herm_err", ctypes.c_double), ("trace_err", ctypes.c_double),
+                ("cond_est", ctypes.c_double), ("fill_factor", ctypes.c_double), ("weight", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1504_06768_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ss_options_default": (ctypes.c_int, [P]),
+        "ss_build_liouvillian": (ctypes.c_int, [P, P, I32, I64, P]),
+        "ss_solve": (ctypes.c_int, [P, I32, D, P, P, P]),
+        "ss_liouv_free": (None, [P]),
+        "ss_liouv_shape": (ctypes.c_int, [P, P, P, P]),
+        "ss_prepare": (ctypes.c_int, [P, I32, P]),
+        "ss_export_csr": (ctypes.c_int, [P, I32, P, P, P, P]),
+        "ss_export_perm": (ctypes.c_int, [P, P]),
+        "ss_apply": (ctypes.c_int, [P, I32, I32, P, P]),
+        "ss_bandwidth_profile": (ctypes.c_int, [P, I32, P, P]),
+        "ss_server_create": (ctypes.c_int, [ctypes.c_size_t, I32, P]),
+        "ss_submit": (ctypes.c_int, [P, P, P, I32, I64, I32, D, P, P]),
+        "ss_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, P]),
+        "ss_server_drain": (ctypes.c_int, [P]),
+        "ss_server_destroy": (None, [P]),
+        "ss_last_error": (ctypes.c_char_p, []),
+        "ss_set_stream": (ctypes.c_int, [P]),
+        "ss_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_solve", "ss_liouv_free", "ss_liouv_shape",
+            "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile",
+            "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_destroy",
+            "ss_last_error", "ss_set_stream", "ss_version")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def version() -> str:
+    return _lib.ss_version().decode()
+
+
+def _err() -> str:
+    m = _lib.ss_last_error()
+    return m.decode() if m else ""
+
+
+def _check(rc: int, what: str, info=None):
+    if rc != SS_OK:
+        raise SolverError(rc, f"{what}: {_err()}", info)
+
+
+# ------------------------------------------------------------ marshalling
+class _HostCsr:
+    """Keeps the converted arrays alive while the library reads them."""
+
+    def __init__(self, m):
+        if _is_torch(m):
+            raise TypeError("pass device CSR matrices as a tuple of torch tensors (indptr, indices, data, n)")
+        if isinstance(m, tuple):
+            indptr, indices, data, n = m
+            self.keep = (indptr, indices, data)
+            self.s = _Csr(int(n), int(indices.numel()), _ptr(indptr), _ptr(indices), _ptr(data))
+            return
+        A = sp.csr_matrix(m, dtype=np.complex128)
+        A.sum_duplicates()
+        A.sort_indices()
+        self.indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        self.indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+        self.data = np.ascontiguousarray(A.data, dtype=np.complex128)
+        self.s = _Csr(A.shape[0], A.nnz, self.indptr.ctypes.data, self.indices.ctypes.data,
+                      self.data.ctypes.data)
+        if A.shape[0] != A.shape[1]:
+            raise ValueError("operators must be square")
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x) -> int:
+    if _is_torch(x):
+        return int(x.data_ptr())
+    return int(x.ctypes.data)
+
+
+def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
+            drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
+            no_fallback=False) -> _Options:
+    o = _Options()
+    _lib.ss_options_default(ctypes.byref(o))
+    o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
+    o.ilu = {"ilu0": 0, "ilut": 1}[ilu] if isinstance(ilu, str) else int(ilu)
+    o.ordering = {"rcm": 0, "natural": 1}[ordering] if isinstance(ordering, str) else int(ordering)
+    o.gmres_m, o.maxiter, o.max_outer = gmres_m, maxiter, max_outer
+    o.drop_tol, o.fill, o.sigma, o.inner_tol, o.weight = drop_tol, fill, sigma, inner_tol, weight
+    o.flags = (SS_FLAG_HERMITIZE if hermitize else 0) | (SS_FLAG_NO_FALLBACK if no_fallback else 0)
+    return o
+
+
+def _method(m) -> int:
+    return METHODS[m] if isinstance(m, str) else int(m)
+
+
+# ----------------------------------------------------------- entry points
+class Liouvillian:
+    """Owning wrapper of an ss_liouv handle."""
+
+    def __init__(self, handle: int, N: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.N = N
+        self.n = N * N
+
+    def shape(self):
+        N, n, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.ss_liouv_shape(self.handle, ctypes.byref(N), ctypes.byref(n), ctypes.byref(nnz)),
+               "ss_liouv_shape")
+        return N.value, n.value, nnz.value
+
+    @property
+    def nnz(self) -> int:
+        return self.shape()[2]
+
+    def free(self):
+        if self.handle:
+            _lib.ss_liouv_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_liouvillian(H, c_ops: Iterable = ()) -> Liouvillian:
+    """ss_build_liouvillian: assemble L on the device from H and c_ops."""
+    Hc = _HostCsr(H)
+    cs = [_HostCsr(c) for c in c_ops]
+    arr = (_Csr * max(len(cs), 1))(*[c.s for c in cs])
+    N = Hc.s.n
+    h = ctypes.c_void_p()
+    _check(_lib.ss_build_liouvillian(ctypes.byref(Hc.s), arr if cs else None, len(cs), N, ctypes.byref(h)),
+           "ss_build_liouvillian")
+    return Liouvillian(h.value, N)
+
+
+def solve(L: Liouvillian, method="trace_bicgstab", tol: float = 1e-10, out=None, raise_on_error=True,
+          **opts):
+    """ss_solve: returns (rho as an N x N complex128 array, info dict).  `out`
+    may be a torch complex128 tensor on the GPU (N*N elements) to receive rho
+    in column-major order; rho is then returned as that tensor."""
+    o = options(**opts)
+    info = _Info()
+    if out is not None:
+        ptr = _ptr(out)
+        rho = out
+    else:
+        buf = np.empty(L.n, dtype=np.complex128)
+        ptr = buf.ctypes.data
+        rho = buf
+    rc = _lib.ss_solve(L.handle, _method(method), float(tol), ctypes.byref(o), ctypes.c_void_p(ptr),
+                       ctypes.byref(info))
+    d = info.as_dict()
+    if rc != SS_OK and raise_on_error:
+        raise SolverError(rc, f"ss_solve: {_err()}", d)
+    if out is None:
+        rho = rho.reshape(L.N, L.N, order="F")
+    return rho, d
+
+
+def prepare(L: Liouvillian, method="trace_bicgstab", **opts):
+    """ss_prepare: the set-up half of ss_solve (transform, ordering, ILU)."""
+    o = options(**opts)
+    _check(_lib.ss_prepare(L.handle, _method(method), ctypes.byref(o)), "ss_prepare")
+
+
+def export_csr(L: Liouvillian, which=SS_MAT_L) -> sp.csr_matrix:
+    nnz = ctypes.c_int64()
+    _check(_lib.ss_export_csr(L.handle, which, ctypes.byref(nnz), None, None, None), "ss_export_csr")
+    indptr = np.empty(L.n + 1, dtype=np.int64)
+    indices = np.empty(nnz.value, dtype=np.int32)
+    data = np.empty(nnz.value, dtype=np.complex128)
+    _check(_lib.ss_export_csr(L.handle, which, None, indptr.ctypes.data, indices.ctypes.data,
+                              data.ctypes.data), "ss_export_csr")
+    return sp.csr_matrix((data, indices, indptr), shape=(L.n, L.n))
+
+
+def export_perm(L: Liouvillian) -> np.ndarray:
+    perm = np.empty(L.n, dtype=np.int32)
+    _check(_lib.ss_export_perm(L.handle, perm.ctypes.data), "ss_export_perm")
+    return perm
+
+
+def apply(L: Liouvillian, op: int, x, prec="fp64"):
+    """ss_apply: y = op(x) for a vector of n complex values."""
+    xh = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty(L.n, dtype=np.complex128)
+    _check(_lib.ss_apply(L.handle, op, PRECS[prec] if isinstance(prec, str) else prec, xh.ctypes.data,
+                         y.ctypes.data), "ss_apply")
+    return y
+
+
+def bandwidth_profile(L: Liouvillian, which=SS_MAT_A_PERM):
+    B, P = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.ss_bandwidth_profile(L.handle, which, ctypes.byref(B), ctypes.byref(P)), "ss_bandwidth_profile")
+    return B.value, P.value
+
+
+class Server:
+    """ss_server_*: continuous-batching request server."""
+
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_slots: int = 256):
+        h = ctypes.c_void_p()
+        _check(_lib.ss_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)), "ss_server_create")
+        self.handle = h
+        self._N = {}
+
+    def submit(self, H, c_ops=(), method="trace_bicgstab", tol=1e-10, **opts) -> int:
+        Hc = _HostCsr(H)
+        cs = [_HostCsr(c) for c in c_ops]
+        arr = (_Csr * max(len(cs), 1))(*[c.s for c in cs])
+        o = options(**opts)
+        t = ctypes.c_uint64()
+        _check(_lib.ss_submit(self.handle, ctypes.byref(Hc.s), arr if cs else None, len(cs), Hc.s.n,
+                              _method(method), float(tol), ctypes.byref(o), ctypes.byref(t)), "ss_submit")
+        self._N[t.value] = Hc.s.n
+        return t.value
+
+    def poll(self, ticket: int):
+        """Returns None while pending, else (rho, info); raises on failure."""
+        N = self._N[ticket]
+        rho = np.empty(N * N, dtype=np.complex128)
+        info = _Info()
+        rc = _lib.ss_poll(self.handle, ctypes.c_uint64(ticket), rho.ctypes.data, ctypes.byref(info))
+        if rc == SS_PENDING:
+            return None
+        del self._N[ticket]
+        d = info.as_dict()
+        if rc != SS_OK:
+            raise SolverError(rc, f"ss_poll: {_err()}", d)
+        return rho.reshape(N, N, order="F"), d
+
+    def drain(self):
+        _check(_lib.ss_server_drain(self.handle), "ss_server_drain")
+
+    def close(self):
+        if self.handle:
+            _lib.ss_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

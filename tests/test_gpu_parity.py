@@ -1,0 +1,279 @@
+"""Parity of every stage of the HIP path with the CPU oracle (GPU required).
+
+Stages are exported through the C ABI (ss_export_csr / ss_export_perm /
+ss_apply) and compared element by element with the oracle on the same seeded
+inputs; the end-to-end solves are compared with the dense fp64 oracle.
+Tolerances: integer and index results exact; assembled values to 1e-14
+relative (sums of at most a few fp64 products in a different order); ILU
+factors to 1e-11 relative; steady states to 1e-8 max-abs in fp64 mode and
+1e-6 in mixed mode, with ||L rho||_2 <= 1e-10.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.linalg import spsolve_triangular
+
+import qsystems as qs
+from oracle import ilu as oilu
+from oracle import ordering as oord
+from oracle import transforms as otr
+from oracle.liouvillian import liouvillian_sparse
+from oracle.steady import steady_state_dense
+
+pytestmark = pytest.mark.gpu
+
+ssl = pytest.importorskip("paper_1504_06768_amd")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+SMALL = {
+    "kerr20": lambda: qs.config(1),
+    "jc8": lambda: qs.jaynes_cummings(8, seed=0),
+    "random7": lambda: qs.random_lindblad(7, 3, seed=4),
+    "spin3": lambda: qs.spin_chain(3),
+    "opto3x5": lambda: qs.optomechanics(3, 5, nth=1.0),
+    "two_level": lambda: qs.two_level_atom(),
+}
+
+
+def _max_rel(a, b):
+    a = sp.csr_matrix(a)
+    b = sp.csr_matrix(b)
+    scale = max(abs(b).max(), 1e-300)
+    return abs(a - b).max() / scale
+
+
+# ------------------------------------------------------------ assembly
+@pytest.mark.parametrize("name", list(SMALL))
+def test_assembly_matches_oracle(name):
+    s = SMALL[name]()
+    _say("assembly", name, s.dim)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    Lg = ssl.export_csr(L, ssl.SS_MAT_L)
+    Lo = liouvillian_sparse(s.H, s.c_ops)
+    assert Lg.shape == Lo.shape
+    assert _max_rel(Lg, Lo) <= 1e-14
+    # the structure equals the oracle's non-zero structure
+    big = abs(Lo) > 1e-12 * abs(Lo).max()
+    assert ((abs(Lg) > 0) != (abs(Lo) > 0)).multiply(big).nnz == 0
+    # rows sorted, unique columns
+    for i in range(Lg.shape[0]):
+        c = Lg.indices[Lg.indptr[i]:Lg.indptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+
+
+def test_assembly_full_size_sampled_rows():
+    """Optomechanics 10 x 60 (n = 360000): sampled rows of L against the
+    oracle's sparse Kronecker assembly."""
+    s = qs.config(3)
+    _say("assembly optomech 10x60")
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    Lg = ssl.export_csr(L, ssl.SS_MAT_L)
+    Lo = liouvillian_sparse(s.H, s.c_ops)
+    assert Lg.nnz == Lo.nnz
+    rows = np.random.default_rng(0).choice(Lg.shape[0], 2000, replace=False)
+    assert _max_rel(Lg[rows], Lo[rows]) <= 1e-14
+
+
+# ------------------------------------------------------------ transforms
+@pytest.mark.parametrize("name", ["kerr20", "jc8", "spin3"])
+def test_transforms_match_oracle(name):
+    s = SMALL[name]()
+    Lo = liouvillian_sparse(s.H, s.c_ops)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab")
+    A = ssl.export_csr(L, ssl.SS_MAT_A)
+    Ao, _, w = otr.modified(Lo)
+    assert _max_rel(A, Ao) <= 1e-14
+    ssl.prepare(L, "invpow_bicgstab")
+    S = ssl.export_csr(L, ssl.SS_MAT_A)
+    So = otr.shifted(Lo, 1e-15)
+    assert _max_rel(S, So) <= 1e-14
+    assert S.nnz == So.nnz
+
+
+# ------------------------------------------------------------ ordering
+def _paper(name):
+    return {"jc": lambda: qs.jaynes_cummings_paper(16), "spin": lambda: qs.spin_chain(5),
+            "opto": lambda: qs.optomechanics(4, 8, nth=1.0)}[name]()
+
+
+@pytest.mark.parametrize("system", ["jc", "spin", "opto"])
+@pytest.mark.parametrize("method", ["trace_bicgstab", "invpow_bicgstab"])
+def test_rcm_permutation_bit_exact(system, method):
+    """GPU RCM = oracle RCM exactly, on the paper's Fig. 1/3 systems."""
+    s = _paper(system)
+    _say("rcm", system, method)
+    Lo = liouvillian_sparse(s.H, s.c_ops)
+    Ao = otr.modified(Lo)[0] if method.startswith("trace") else otr.shifted(Lo)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, method)
+    perm = ssl.export_perm(L)
+    assert np.array_equal(perm, oord.rcm(Ao))
+    Sg = ssl.export_csr(L, ssl.SS_MAT_SYM)
+    So = oord.symmetrized_pattern(Ao)
+    assert (Sg != 0).astype(np.int8).nnz == So.nnz
+    assert ((Sg != 0).astype(np.int8) - So).nnz == 0
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    assert _max_rel(Ap, oord.permute(Ao, perm)) == 0.0
+    B, P = ssl.bandwidth_profile(L, ssl.SS_MAT_A_PERM)
+    assert (B, P) == (oord.bandwidth(Ap)[2], oord.profile(Ap)[2])
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_rcm_on_workloads(k):
+    s = qs.config(k)
+    _say("rcm workload", k)
+    Ao = otr.modified(liouvillian_sparse(s.H, s.c_ops))[0]
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab")
+    assert np.array_equal(ssl.export_perm(L), oord.rcm(Ao))
+
+
+# ------------------------------------------------------------ ILU(0)
+@pytest.mark.parametrize("name", ["kerr20", "jc8", "random7", "opto3x5"])
+def test_ilu0_matches_oracle(name):
+    s = SMALL[name]()
+    _say("ilu0", name)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab")
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    LUg = ssl.export_csr(L, ssl.SS_MAT_LU)
+    LUo, g = oilu.ilu0(Ap, guard=1e-12)
+    assert np.array_equal(LUg.indptr, LUo.indptr) and np.array_equal(LUg.indices, LUo.indices)
+    rel = np.abs(LUg.data - LUo.data) / np.maximum(np.abs(LUo.data), 1e-300)
+    big = np.abs(LUo.data) > 1e-10 * np.abs(LUo.data).max()
+    assert np.max(rel[big]) <= 1e-11
+
+
+def test_ilu0_property_on_jc40():
+    """(LU)_ij = a_ij on the pattern of A, on the Jaynes-Cummings workload."""
+    s = qs.config(2)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab")
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
+    P = (Lf @ Uf).tocsr()
+    C = Ap.tocoo()
+    prod = np.asarray(P[C.row, C.col]).ravel()
+    assert np.max(np.abs(prod - C.data)) <= 1e-11 * np.abs(C.data).max()
+
+
+# ------------------------------------------------------------ SpMV / trsv
+@pytest.mark.parametrize("name", ["kerr20", "jc8", "spin3"])
+def test_spmv_and_triangular_solves(name):
+    s = SMALL[name]()
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab")
+    Lo = liouvillian_sparse(s.H, s.c_ops)
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=Lo.shape[0]) + 1j * rng.normal(size=Lo.shape[0])
+    y = ssl.apply(L, ssl.SS_OP_SPMV_L, x)
+    ref = Lo @ x
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    y = ssl.apply(L, ssl.SS_OP_SPMV_APERM, x)
+    assert np.max(np.abs(y - Ap @ x)) <= 1e-13 * np.max(np.abs(Ap @ x))
+    Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
+    yl = ssl.apply(L, ssl.SS_OP_LSOLVE, x)
+    refl = spsolve_triangular(Lf, x, lower=True, unit_diagonal=True)
+    assert np.max(np.abs(yl - refl)) <= 1e-11 * np.max(np.abs(refl))
+    yu = ssl.apply(L, ssl.SS_OP_USOLVE, x)
+    refu = spsolve_triangular(Uf, x, lower=False)
+    assert np.max(np.abs(yu - refu)) <= 1e-11 * np.max(np.abs(refu))
+    yp = ssl.apply(L, ssl.SS_OP_PRECOND, x)
+    refp = spsolve_triangular(Uf, refl, lower=False)
+    assert np.max(np.abs(yp - refp)) <= 1e-11 * np.max(np.abs(refp))
+
+
+def test_mixed_precision_operators():
+    s = SMALL["kerr20"]()
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab", prec="mixed")
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    x = np.random.default_rng(2).normal(size=Ap.shape[0]).astype(np.complex128)
+    y = ssl.apply(L, ssl.SS_OP_SPMV_APERM, x, prec="mixed")
+    ref = Ap @ x
+    assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
+    Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
+    yp = ssl.apply(L, ssl.SS_OP_PRECOND, x, prec="mixed")
+    refp = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
+    assert np.max(np.abs(yp - refp)) <= 1e-4 * np.max(np.abs(refp))
+
+
+# ------------------------------------------------------------ end to end
+METHODS = ["trace_bicgstab", "trace_gmres", "invpow_bicgstab", "invpow_gmres"]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("name", ["kerr20", "jc8", "random7", "spin3", "opto3x5"])
+def test_steady_state_matches_dense_oracle(name, method, prec, tol):
+    s = SMALL[name]()
+    _say("solve", name, method, prec)
+    ref = steady_state_dense(s.H, s.c_ops)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec)
+    err = np.max(np.abs(rho - ref))
+    _say("   err", err, "resid", info["resid_l2"], "its", info["outer_its"], info["inner_its"])
+    assert err <= tol
+    assert info["resid_l2"] <= 1e-10
+    assert abs(np.trace(rho) - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_jaynes_cummings_workload(prec, tol):
+    """Driven Jaynes-Cummings, cavity 40 x qubit (n = 6400)."""
+    s = qs.config(2)
+    _say("solve jc40", prec)
+    ref = steady_state_dense(s.H, s.c_ops)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, prec=prec)
+    _say("   err", np.max(np.abs(rho - ref)), info)
+    assert np.max(np.abs(rho - ref)) <= tol
+    assert info["resid_l2"] <= 1e-10
+
+
+def test_closed_forms_on_gpu():
+    s = qs.coherent_drive(40, 0.5, 1.0, 1.0)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, _ = ssl.solve(L, "trace_bicgstab", tol=1e-10)
+    alpha = -1j / (0.5 + 0.5j)
+    c = np.empty(40, dtype=complex)
+    c[0] = np.exp(-abs(alpha) ** 2 / 2)
+    for k in range(1, 40):
+        c[k] = c[k - 1] * alpha / np.sqrt(k)
+    assert np.max(np.abs(rho - np.outer(c, c.conj()))) <= 1e-8
+    s = qs.thermal_oscillator(20, 2.0, 0.7, 1.3)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, _ = ssl.solve(L, "invpow_bicgstab", tol=1e-10)
+    r = 2.0 / 3.0
+    p = (1 - r) * r ** np.arange(20) / (1 - r ** 20)
+    assert np.max(np.abs(rho - np.diag(p))) <= 1e-8
+
+
+# ------------------------------------------------------------ error paths
+def test_invalid_inputs_are_rejected():
+    s = SMALL["kerr20"]()
+    H = s.H.toarray()
+    H[0, 0] = np.nan
+    with pytest.raises(ssl.SolverError) as e:
+        ssl.build_liouvillian(H, s.c_ops)
+    assert e.value.code == -1
+    with pytest.raises(ssl.SolverError) as e:
+        ssl.build_liouvillian(s.H, [sp.identity(3, dtype=complex, format="csr")])
+    assert e.value.code == -1
+
+
+def test_iteration_limit_reports_not_converged():
+    s = qs.config(2)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    with pytest.raises(ssl.SolverError) as e:
+        ssl.solve(L, "trace_bicgstab", tol=1e-12, maxiter=1, max_outer=1)
+    assert e.value.code == -3
+    assert e.value.info["inner_its"] >= 1
