@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Steady-state solver benchmark on one MI355X.
+
+Workload (default): the driven Jaynes-Cummings system, cavity N = 40 x qubit
+(Hilbert dimension 80, Liouvillian 6400 x 6400), parameters (g, E, Delta_c,
+omega_a, kappa, gamma) drawn from a seeded uniform [0.1, 2]; synthetic, no
+data files.  One step = one whole solve through the C ABI: Liouvillian
+assembly from H and the collapse operators already resident in HBM, trace-row
+transform, RCM, ILU(0), preconditioned BiCGSTAB with fp64 refinement, finish
+(unpermute, normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
+
+Prints one JSON line: solves/s of the mixed-precision path (value) next to
+the fp64 path, the roofline position of the dominant kernel (timed live with
+HIP events), the SpMV bandwidth on the large Kerr-chain matrix (n = 10^6) and
+the CPU oracle (dense LU) timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _device_csr(m, torch):
+    import numpy as np
+    import scipy.sparse as sp
+    A = sp.csr_matrix(m, dtype=np.complex128)
+    A.sort_indices()
+    ip = torch.from_numpy(np.ascontiguousarray(A.indptr, dtype=np.int64)).cuda()
+    ix = torch.from_numpy(np.ascontiguousarray(A.indices, dtype=np.int32)).cuda()
+    dv = torch.from_numpy(np.ascontiguousarray(A.data)).cuda()
+    return (ip, ix, dv, A.shape[0])
+
+
+def spmv_bytes(n, nnz, s):
+    """Algorithmic bytes of one CSR SpMV: values + column indices, row
+    pointers, x read once, y written once (s = bytes per complex value)."""
+    return nnz * (s + 4) + 4 * (n + 1) + 2 * n * s
+
+
+def trsv_pair_bytes(n, nnz_lu, s):
+    """Algorithmic bytes of one L-solve + U-solve pair: factor values and
+    indices once, row pointers and diagonal positions for both sweeps, and
+    right-hand side, intermediate and result vectors."""
+    return nnz_lu * (s + 4) + 8 * (n + 1) + 8 * n + 4 * n * s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--method", default="trace_bicgstab")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 SpMV measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (each solve fits one MI355X; "
+              "independent requests would be routed to separate GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1504_06768_amd as ssl
+    import qsystems as qs
+
+    torch.cuda.set_device(0)
+    s = qs.config(2)
+    N = s.dim
+    _log(f"workload jc_N40xqubit: N = {N}, n = {N * N}")
+    Hd = _device_csr(s.H, torch)
+    Cd = [_device_csr(c, torch) for c in s.c_ops]
+    out = torch.empty(N * N, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(prec):
+        L = ssl.build_liouvillian(Hd, Cd)
+        _, info = ssl.solve(L, args.method, tol=1e-10, out=out, prec=prec)
+        L.free()
+        return info
+
+    results = {}
+    for prec in ("mixed", "fp64"):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [step(prec) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rho = out.cpu().numpy().reshape(N, N, order="F")
+        results[prec] = dict(ms=1e3 * dt / args.steps, solves_per_s=args.steps / dt, info=infos[-1], rho=rho)
+        _log(f"{prec}: {1e3 * dt / args.steps:.2f} ms/solve, resid {infos[-1]['resid_l2']:.2e}, "
+             f"outer {infos[-1]['outer_its']}, inner {infos[-1]['inner_its']}")
+
+    # accuracy against the fp64 dense oracle, and the oracle's own time
+    from oracle.steady import steady_state_dense
+    cpu = None
+    t0 = time.perf_counter()
+    ref = steady_state_dense(s.H, s.c_ops)
+    t_oracle = time.perf_counter() - t0
+    if not args.no_cpu_baseline:
+        reps = max(1, min(3, int(20.0 / max(t_oracle, 1e-3))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            steady_state_dense(s.H, s.c_ops)
+        t_cpu = (time.perf_counter() - t0) / reps
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": cores, "kind": "oracle",
+               "sample": f"{reps} dense fp64 LU solve(s) of the trace-replaced 6400 x 6400 Liouvillian "
+                         f"of the same workload (numpy/LAPACK)"}
+    err = {p: float(np.max(np.abs(results[p]["rho"] - ref))) for p in results}
+
+    # dominant kernel of the solve, timed live with HIP events on the solver's stream
+    L = ssl.build_liouvillian(Hd, Cd)
+    ssl.prepare(L, args.method, prec="mixed")
+    n = N * N
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    LU = ssl.export_csr(L, ssl.SS_MAT_LU)
+    t_spmv = ssl.time_operator(L, ssl.SS_OP_SPMV_APERM, "mixed", 200)
+    t_pre = ssl.time_operator(L, ssl.SS_OP_PRECOND, "mixed", 100)
+    L.free()
+    its = results["mixed"]["info"]["inner_its"]
+    # per BiCGSTAB iteration: 2 SpMV and 2 preconditioner applications
+    share_spmv, share_pre = 2 * its * t_spmv, 2 * its * t_pre
+    if share_pre >= share_spmv:
+        kern = "sync-free ILU(0) triangular solve pair (complex64)"
+        alg = trsv_pair_bytes(n, LU.nnz, 8)
+        t_k = t_pre
+    else:
+        kern = "CSR SpMV (complex64)"
+        alg = spmv_bytes(n, Ap.nnz, 8)
+        t_k = t_spmv
+    achieved = alg / (t_k * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": kern,
+                "bytes_per_launch": alg, "avg_launch_ms": t_k,
+                "spmv_ms": t_spmv, "precond_ms": t_pre}
+
+    large = None
+    if not args.no_large:
+        ch = qs.config(4)
+        Lc = ssl.build_liouvillian(ch.H, ch.c_ops)
+        ssl.prepare(Lc, "invpow_bicgstab", prec="mixed")
+        _, nc, nnzc = Lc.shape()
+        Apc = ssl.export_csr(Lc, ssl.SS_MAT_A_PERM)
+        t64 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "mixed", 50)
+        t128 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "fp64", 50)
+        b64, b128 = spmv_bytes(nc, Apc.nnz, 8), spmv_bytes(nc, Apc.nnz, 16)
+        large = {"workload": "kerr_chain_3x10 (n = 1e6)", "nnz": int(Apc.nnz),
+                 "c64": {"ms": t64, "GB/s": b64 / (t64 * 1e-3) / 1e9, "bytes": b64},
+                 "c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128}}
+        Lc.free()
+
+    m, f = results["mixed"], results["fp64"]
+    line = {
+        "metric": "steady-state solves/sec + SpMV HBM GB/s at ||L.rho||<=1e-10, mixed vs FP64",
+        "value": m["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 inner / c128 refinement",
+        "data": "synthetic",
+        "config": {"workload": "jc_N40xqubit: driven Jaynes-Cummings, cavity 40 x qubit, n = 6400",
+                   "method": args.method, "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0"},
+        "fp64": {"solves_per_s": f["solves_per_s"], "ms_per_step": f["ms"], "max_abs_err_vs_oracle": err["fp64"],
+                 "resid_l2": f["info"]["resid_l2"], "outer_its": f["info"]["outer_its"],
+                 "inner_its": f["info"]["inner_its"]},
+        "mixed": {"max_abs_err_vs_oracle": err["mixed"], "resid_l2": m["info"]["resid_l2"],
+                  "outer_its": m["info"]["outer_its"], "inner_its": m["info"]["inner_its"],
+                  "t_setup_ms": m["info"]["t_setup_ms"], "t_solve_ms": m["info"]["t_solve_ms"]},
+        "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"],
+        "roofline": roofline,
+        "spmv_large": large,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

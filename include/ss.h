@@ -104,7 +104,10 @@ typedef struct {
     int32_t maxiter;    /* inner Krylov iteration limit per solve   (1000)     */
     int32_t max_outer;  /* outer refinement / inverse-power steps   (20)       */
     int32_t flags;      /* SS_FLAG_* bits                           (0)        */
-    int32_t reserved;
+    int32_t trace_row;  /* population k whose row k (N + 1) carries the trace
+                           row T; -1 = the population row with the smallest
+                           |L_rr| (ties: lowest k).  The paper notes the row
+                           is arbitrary and uses row 0.                (-1)    */
     double drop_tol;    /* ILUT drop tolerance relative to ||row||_inf (1e-4)  */
     double fill;        /* ILUT entries kept per part, x nnz(row)     (10)     */
     double sigma;       /* inverse-power shift                        (1e-15)  */
@@ -196,6 +199,13 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
  * in SS_MIXED x is rounded to complex64, the operator runs in complex64 and
  * y is widened back to complex128. */
 int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
+
+/* Time `reps` back-to-back applications of an operator of the prepared
+ * handle (SS_OP_SPMV_L, SS_OP_SPMV_APERM or SS_OP_PRECOND; prec as in
+ * ss_apply) on the handle's stream, bracketed by HIP events; *avg_ms
+ * receives the mean time per application.  Input and output vectors are
+ * library-owned device scratch.  Used to measure achieved bandwidth. */
+int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double *avg_ms);
 
 /* Bandwidth B and profile P of a stage matrix (definitions of the section
  * "Direct factorization"), computed on the device. */

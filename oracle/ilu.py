@@ -15,9 +15,10 @@ ilut  -- dual-threshold ILU: during the elimination of row i, multipliers and
 
 Both return a single CSR matrix holding the strict lower part of L (the unit
 diagonal is implicit) and U (diagonal included), with sorted column indices.
-A pivot whose magnitude falls below guard * ||a_i||_inf is replaced by that
-value times the pivot's phase (or by the bare value when it is exactly zero)
-and counted.
+A pivot whose magnitude falls below guard * ||a_i||_inf is replaced by
+boost * ||a_i||_inf times the pivot's phase (or by that value when it is
+exactly zero) and counted; boost defaults to guard.  The solver uses
+guard = 1e-8 and boost = 0.1.
 """
 from __future__ import annotations
 
@@ -27,17 +28,20 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def _guard(piv: complex, bound: float) -> tuple[complex, bool]:
+def _guard(piv: complex, bound: float, value: float) -> tuple[complex, bool]:
     if abs(piv) >= bound:
         return piv, False
+    if value <= 0:
+        value = 1.0
     if piv == 0:
-        return complex(bound), True
-    return piv / abs(piv) * bound, True
+        return complex(value), True
+    return piv / abs(piv) * value, True
 
 
-def ilu0(A, guard: float = 0.0):
+def ilu0(A, guard: float = 0.0, boost: float | None = None):
     """ILU(0) of a square CSR matrix with a non-zero diagonal pattern.
     Returns (LU as csr_matrix, number of guarded pivots)."""
+    boost = guard if boost is None else boost
     A = sp.csr_matrix(A, dtype=np.complex128)
     A.sort_indices()
     n = A.shape[0]
@@ -63,14 +67,15 @@ def ilu0(A, guard: float = 0.0):
                 if p is not None:
                     vals[p] -= lik * vals[f]
         if guard > 0:
-            v, g = _guard(complex(vals[diag[i]]), guard * rownorm)
+            v, g = _guard(complex(vals[diag[i]]), guard * rownorm, boost * rownorm)
             vals[diag[i]] = v
             guarded += int(g)
     return sp.csr_matrix((vals, indices.copy(), indptr.copy()), shape=A.shape), guarded
 
 
-def ilut(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0):
+def ilut(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0, boost: float | None = None):
     """Dual-threshold ILUT without pivoting.  Returns (LU csr, guarded pivots)."""
+    boost = guard if boost is None else boost
     A = sp.csr_matrix(A, dtype=np.complex128)
     A.sort_indices()
     n = A.shape[0]
@@ -109,7 +114,7 @@ def ilut(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0):
         up = up[:keep]
         piv = w.get(i, 0.0)
         if guard > 0:
-            piv, g = _guard(complex(piv), guard * rownorm)
+            piv, g = _guard(complex(piv), guard * rownorm, boost * rownorm)
             guarded += int(g)
         elif piv == 0:
             raise ZeroDivisionError(f"ilut: zero pivot in row {i}")

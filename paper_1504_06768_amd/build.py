@@ -1,8 +1,9 @@
 """Build libss.so (the solver's C-ABI library) for gfx950 with hipcc.
 
 Every HIP source under csrc/ is compiled to an object in parallel, then
-linked into paper_1504_06768_amd/libss.so.  Usage: python -m
-paper_1504_06768_amd.build  (or call build()).
+linked into paper_1504_06768_amd/libss.so.  Usage: python
+paper_1504_06768_amd/build.py (run by path, so the package -- which loads the
+library -- is not imported), or build() from __graft_entry__.
 """
 from __future__ import annotations
 

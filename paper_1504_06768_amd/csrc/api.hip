@@ -1,6 +1,7 @@
 // extern "C" entry points of include/ss.h: argument checks, error
 // translation and handle lifetime.  The work itself is in the other files.
 #include <mutex>
+#include <type_traits>
 
 #include "assemble.hpp"
 #include "csr_tools.hpp"
@@ -63,6 +64,7 @@ int ss_options_default(ss_options *opt) {
     opt->maxiter = 1000;
     opt->max_outer = 20;
     opt->flags = 0;
+    opt->trace_row = -1;
     opt->drop_tol = 1e-4;
     opt->fill = 10.0;
     opt->sigma = 1e-15;
@@ -233,6 +235,66 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
         SS_HIP(hipMemcpyAsync(y, yd.get(), sizeof(double2) * n,
                               ss::is_device_ptr(y) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
         SS_HIP(hipStreamSynchronize(s));
+        return SS_OK;
+    });
+}
+
+int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double *avg_ms) {
+    return guarded([&]() -> int {
+        SS_REQUIRE(L != nullptr && avg_ms != nullptr && reps > 0, SS_E_INVALID_ARG, "bad argument");
+        SS_REQUIRE(op == SS_OP_SPMV_L || op == SS_OP_SPMV_APERM || op == SS_OP_PRECOND, SS_E_INVALID_ARG,
+                   "operator cannot be timed");
+        SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
+        SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
+                   "complex64 operators exist only after a mixed-precision ss_prepare");
+        hipStream_t s = ss::stream_of(L);
+        const int n = L->n;
+        hipEvent_t e0, e1;
+        SS_HIP(hipEventCreate(&e0));
+        SS_HIP(hipEventCreate(&e1));
+        float ms = 0.f;
+        auto run = [&](auto zero_val) {
+            using T = decltype(zero_val);
+            ss::DevBuf<T> x((size_t)n), y((size_t)n);
+            ss::zero<T>(n, y.get(), s);
+            ss::DevBuf<double2> ones((size_t)n);
+            ss::zero<double2>(n, ones.get(), s);
+            ss::convert<T, double2>(n, ones.get(), x.get(), nullptr, s);
+            const ss::CsrBuf<T> *A = nullptr;
+            const ss::CsrBuf<T> *LU = nullptr;
+            if constexpr (std::is_same<T, double2>::value) {
+                A = (op == SS_OP_SPMV_L) ? &L->L : &L->Ap;
+                LU = &L->LU;
+            } else {
+                A = &L->Ap32;
+                LU = &L->LU32;
+            }
+            ss::Precond<T> M;
+            if (op == SS_OP_PRECOND) M.setup(LU, L->lu_diag.get(), n, s);
+            const ss::Csr<T> Av = A->view();
+            const int g = ss::spmv_group(Av.n, Av.nnz);
+            auto once = [&]() {
+                if (op == SS_OP_PRECOND) M.apply(x.get(), y.get(), s);
+                else ss::spmv<T>(Av, x.get(), y.get(), g, s);
+            };
+            once();  // warm-up
+            SS_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) once();
+            SS_HIP(hipEventRecord(e1, s));
+            SS_HIP(hipEventSynchronize(e1));
+            SS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        };
+        try {
+            if (prec == SS_FP64 || op == SS_OP_SPMV_L) run(double2{0, 0});
+            else run(float2{0, 0});
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_ms = (double)ms / reps;
         return SS_OK;
     });
 }

@@ -27,8 +27,10 @@ struct ss_liouv_s {
     ss::DevBuf<int> tpos;      // permuted positions of the diagonal of rho
     ss::DevBuf<double2> d_w;   // trace-row weight (device)
     double2 w = {0, 0};
-    int q0 = 0;                // permuted position of vec index 0
+    int trow = 0;              // row of L~ carrying the trace row T
+    int q0 = 0;                // its position after the ordering
     int guarded = 0;
+    int diag_added = 0;        // explicit zero diagonals added to Ap
     double t_setup_ms = 0;
 };
 

@@ -10,8 +10,13 @@
 // multiply-add.  Done in fp64 for both precisions; the mixed path rounds the
 // finished factors to complex64.
 //
-// Pivot guard: |u_ii| < guard * ||a_i||_inf is replaced by guard * ||a_i||_inf
-// times the pivot's phase (or by that value when the pivot is 0), counted.
+// Pivot boost: a pivot with |u_ii| < detect * ||a_i||_inf is replaced by
+// boost * ||a_i||_inf times the pivot's phase (or by that value when the pivot
+// is 0) and counted.  Tiny pivots come from states no channel leaves (a
+// structurally zero diagonal of L) and from the shift sigma of L - sigma I;
+// without pivoting, a pivot boosted to a fraction of the row norm keeps the
+// preconditioner bounded, and the Krylov iteration on the exact matrix
+// absorbs the rank-one difference.
 #include "csr_tools.hpp"
 #include "ilu.hpp"
 #include "syncfree.hpp"
@@ -22,8 +27,8 @@ constexpr int ILU_WPB = 4;  // wavefronts (rows) per workgroup
 
 __global__ void __launch_bounds__(ILU_WPB * 64) k_ilu0(int n, const int *rowptr, const int *col, const int *diag,
                                                        const double2 *a, double2 *w, double2 *out, unsigned *ctr,
-                                                       unsigned base, double guard, unsigned *status,
-                                                       int *nguard) {
+                                                       unsigned base, double detect, double boost,
+                                                       unsigned *status, int *nguard) {
     const unsigned bid = ordered_block(ctr, base);
     const int lane = threadIdx.x & 63;
     const int row = (int)bid * ILU_WPB + (int)(threadIdx.x >> 6);
@@ -72,9 +77,10 @@ __global__ void __launch_bounds__(ILU_WPB * 64) k_ilu0(int n, const int *rowptr,
     if (lane == ((dg - rs) & 63)) {
         const double2 p = w[dg];
         const double mag = sqrt(p.x * p.x + p.y * p.y);
-        const double bound = guard * rn;
+        const double bound = detect * rn;
         if (!(mag >= bound)) {
-            w[dg] = (mag > 0.0) ? cscale(p, bound / mag) : mk(bound > 0.0 ? bound : 1.0, 0.0);
+            const double b = (rn > 0.0) ? boost * rn : 1.0;
+            w[dg] = (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0);
             atomicAdd(nguard, 1);
         }
     }
@@ -109,7 +115,7 @@ void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s) {
     }
 }
 
-IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double guard, CsrBuf<double2> &LU,
+IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double detect, double boost, CsrBuf<double2> &LU,
                       hipStream_t s) {
     const int n = A.n, nnz = A.nnz;
     LU.alloc(n, nnz);
@@ -126,8 +132,8 @@ IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double guard, C
     const unsigned grid = (unsigned)div_up(n, ILU_WPB);
     if (n) {
         k_ilu0<<<grid, ILU_WPB * 64, 0, s>>>(n, A.rowptr.get(), A.col.get(), diag, A.val.get(), work.get(),
-                                              LU.val.get(), bc.ctr.get(), bc.take(grid), guard, status.get(),
-                                              nguard.get());
+                                              LU.val.get(), bc.ctr.get(), bc.take(grid), detect, boost,
+                                              status.get(), nguard.get());
         SS_HIP(hipGetLastError());
     }
     IluResult r;

@@ -9,13 +9,18 @@ struct IluResult {
     int guarded = 0;
 };
 
-// ILU(0) of A (rows sorted, diagonal positions in diag) in fp64.
-IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double guard, CsrBuf<double2> &LU, hipStream_t s);
+// ILU(0) of A (rows sorted, diagonal positions in diag) in fp64; pivots below
+// detect * ||a_i||_inf become boost * ||a_i||_inf (phase kept).
+IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double detect, double boost, CsrBuf<double2> &LU,
+                      hipStream_t s);
 
 // Dual-threshold ILUT (drop_tol relative to ||row||_inf, at most
 // ceil(fill * nnz(row)) entries kept in each of L and U per row).
-IluResult ilut_factor(const CsrBuf<double2> &A, const int *diag, double drop_tol, double fill, double guard,
-                      CsrBuf<double2> &LU, DevBuf<int> &lu_diag, hipStream_t s);
+IluResult ilut_factor(const CsrBuf<double2> &A, const int *diag, double drop_tol, double fill, double detect,
+                      double boost, CsrBuf<double2> &LU, DevBuf<int> &lu_diag, hipStream_t s);
+
+constexpr double PIVOT_DETECT = 1e-8;  // relative to ||a_i||_inf
+constexpr double PIVOT_BOOST = 1e-1;
 
 template <typename T>
 void fill_sentinel(int64_t n, T *p, hipStream_t s);

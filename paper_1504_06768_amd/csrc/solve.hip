@@ -84,9 +84,12 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
         }
         d2h(&h->w, h->d_w.get(), 1, s);
         SS_REQUIRE(h->w.x != 0.0 || h->w.y != 0.0, SS_E_INVALID_ARG, "trace-row weight is zero");
-        make_modified(h->L, d, h->d_w.get(), h->A, s);
+        SS_REQUIRE(o.trace_row < d, SS_E_INVALID_ARG, "trace_row must be < N");
+        h->trow = pick_trace_row(h->L, d, o.trace_row, s);
+        make_modified(h->L, d, h->trow, h->d_w.get(), h->A, s);
     } else {
         h->w = mk(0.0, 0.0);
+        h->trow = 0;
         make_shifted(h->L, o.sigma, h->A, s);
     }
     symmetrize_pattern(h->A, h->S, s);
@@ -94,16 +97,26 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     else identity_order(n, h->perm, h->iperm, s);
     permute_matrix(h->A, h->perm.get(), h->iperm.get(), h->Ap, s);
     h->diag.resize((size_t)n);
-    const int missing = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
-    SS_REQUIRE(missing == 0, SS_E_ZERO_PIVOT,
-               std::to_string(missing) + " rows of the transformed matrix have a structurally zero diagonal");
-    const double guard = (o.prec == SS_MIXED) ? 1e-6 : 1e-12;
+    h->diag_added = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
+    if (h->diag_added > 0) {
+        // Rows whose diagonal is structurally zero (e.g. the ground-state
+        // population of a Jaynes-Cummings system, which the trace row in row 0
+        // does not touch) get an explicit zero diagonal entry, so the
+        // zero-fill ILU has a pivot position; the matrix itself is unchanged.
+        CsrBuf<double2> aug;
+        make_shifted(h->Ap, 0.0, aug, s);
+        h->Ap = std::move(aug);
+        const int still = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
+        SS_REQUIRE(still == 0, SS_E_ZERO_PIVOT, "could not give every row a diagonal entry");
+    }
     if (o.ilu == SS_ILU0) {
-        h->guarded = ilu0_factor(h->Ap, h->diag.get(), guard, h->LU, s).guarded;
+        h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
         h->lu_diag.resize((size_t)n);
         if (n) SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
     } else {
-        h->guarded = ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, guard, h->LU, h->lu_diag, s).guarded;
+        h->guarded =
+            ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU, h->lu_diag, s)
+                .guarded;
     }
     if (o.prec == SS_MIXED) {
         copy_pattern_c64(h->Ap, h->Ap32, s);
@@ -115,7 +128,7 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     h->tpos.resize((size_t)d);
     k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
     SS_HIP(hipGetLastError());
-    d2h(&h->q0, h->iperm.get(), 1, s);
+    d2h(&h->q0, h->iperm.get() + h->trow, 1, s);
     h->p_method = method;
     h->p_opt = o;
     h->prepared = true;
@@ -207,7 +220,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
     if (trace) {
         bvec.resize((size_t)n);
         zero<double2>(n, bvec.get(), s);
-        k_set_at<<<1, 1, 0, s>>>(1, h->iperm.get(), bvec.get(), h->w);  // b = w e_0, permuted
+        k_set_at<<<1, 1, 0, s>>>(1, h->iperm.get() + h->trow, bvec.get(), h->w);  // b = w e_rt, permuted
         zero<double2>(n, x.get(), s);
     } else {
         zero<double2>(n, x.get(), s);
@@ -231,7 +244,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
             d2h(hs, sc, 3, s);
             const double r2 = hs[0].x;
             const double2 tr = hs[1], rq = hs[2];
-            // L x = -r + w (1 - Tr x) e_q0  (row q0 carries the trace row)
+            // L x = -r + w (1 - Tr x) e_q0  (permuted row q0 carries T)
             const double2 one_m_tr = mk(1.0 - tr.x, -tr.y);
             const double2 e0 = csub(cmul(h->w, one_m_tr), rq);
             const double lx2 = fmax(r2 - (rq.x * rq.x + rq.y * rq.y), 0.0) + e0.x * e0.x + e0.y * e0.y;

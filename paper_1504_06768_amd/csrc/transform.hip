@@ -54,13 +54,61 @@ void mean_diagonal(const CsrBuf<double2> &L, double2 *d_out, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- modified
-// Row 0 of L~ is the merge of row 0 of L with w at the trace columns; all
+// The row carrying T: any population row k (d + 1) may take it, because the
+// population rows of L sum to zero (trace preservation); the one with the
+// smallest |L_rr| is taken so that a structurally zero diagonal (a state no
+// channel leaves, e.g. a ground state) gets the trace entry as its pivot.
+__global__ void k_pick_trace_row(int d, const int *rowptr, const int *col, const double2 *val, int forced,
+                                 int *row_out) {
+    __shared__ double sm[256];
+    __shared__ int sk[256];
+    double best = INFINITY;
+    int bk = 0x7fffffff;
+    for (int k = threadIdx.x; k < d; k += 256) {
+        const int r = k * (d + 1);
+        double mag = 0.0;
+        int lo = rowptr[r], hi = rowptr[r + 1] - 1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int c = col[mid];
+            if (c == r) { mag = sqrt(val[mid].x * val[mid].x + val[mid].y * val[mid].y); break; }
+            if (c < r) lo = mid + 1; else hi = mid - 1;
+        }
+        if (mag < best || (mag == best && k < bk)) { best = mag; bk = k; }
+    }
+    sm[threadIdx.x] = best;
+    sk[threadIdx.x] = bk;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            const double m2 = sm[threadIdx.x + off];
+            const int k2 = sk[threadIdx.x + off];
+            if (m2 < sm[threadIdx.x] || (m2 == sm[threadIdx.x] && k2 < sk[threadIdx.x])) {
+                sm[threadIdx.x] = m2;
+                sk[threadIdx.x] = k2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *row_out = (forced >= 0 ? forced : sk[0]) * (d + 1);
+}
+
+int pick_trace_row(const CsrBuf<double2> &L, int d, int forced, hipStream_t s) {
+    DevBuf<int> r(1);
+    k_pick_trace_row<<<1, 256, 0, s>>>(d, L.rowptr.get(), L.col.get(), L.val.get(), forced, r.get());
+    SS_HIP(hipGetLastError());
+    int h = 0;
+    d2h(&h, r.get(), 1, s);
+    return h;
+}
+
+// Row rt of L~ is the merge of row rt of L with w at the trace columns; all
 // other rows are copied.  Entries that cancel to exactly zero are dropped.
 template <bool FILL>
-__device__ int trace_row0(int d, const int *rowptr, const int *col, const double2 *val, double2 w, int *ocol,
+__device__ int trace_row0(int d, int rt, const int *rowptr, const int *col, const double2 *val, double2 w, int *ocol,
                           double2 *oval) {
-    int e = rowptr[0];
-    const int ee = rowptr[1];
+    int e = rowptr[rt];
+    const int ee = rowptr[rt + 1];
     int k = 0;
     int cnt = 0;
     while (e < ee || k < d) {
@@ -78,20 +126,20 @@ __device__ int trace_row0(int d, const int *rowptr, const int *col, const double
     return cnt;
 }
 
-__global__ void k_mod_count(int n, int d, const int *rowptr, const int *col, const double2 *val, const double2 *w,
-                            int *cnt) {
+__global__ void k_mod_count(int n, int d, int rt, const int *rowptr, const int *col, const double2 *val,
+                            const double2 *w, int *cnt) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    if (r == 0) cnt[0] = trace_row0<false>(d, rowptr, col, val, *w, nullptr, nullptr);
+    if (r == rt) cnt[r] = trace_row0<false>(d, rt, rowptr, col, val, *w, nullptr, nullptr);
     else cnt[r] = rowptr[r + 1] - rowptr[r];
 }
 
-__global__ void k_mod_fill(int n, int d, const int *rowptr, const int *col, const double2 *val, const double2 *w,
-                           const int *orow, int *ocol, double2 *oval) {
+__global__ void k_mod_fill(int n, int d, int rt, const int *rowptr, const int *col, const double2 *val,
+                           const double2 *w, const int *orow, int *ocol, double2 *oval) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    if (r == 0) {
-        trace_row0<true>(d, rowptr, col, val, *w, ocol + orow[0], oval + orow[0]);
+    if (r == rt) {
+        trace_row0<true>(d, rt, rowptr, col, val, *w, ocol + orow[r], oval + orow[r]);
     } else {
         const int o = orow[r];
         for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
@@ -152,13 +200,13 @@ static void finish_rows(CsrBuf<double2> &A, int n, DevBuf<int> &cnt, hipStream_t
     A.val.resize((size_t)nnz);
 }
 
-void make_modified(const CsrBuf<double2> &L, int d, const double2 *d_w, CsrBuf<double2> &A, hipStream_t s) {
+void make_modified(const CsrBuf<double2> &L, int d, int rt, const double2 *d_w, CsrBuf<double2> &A, hipStream_t s) {
     const int n = L.n;
     DevBuf<int> cnt((size_t)n + 1);
-    k_mod_count<<<div_up(n, 256), 256, 0, s>>>(n, d, L.rowptr.get(), L.col.get(), L.val.get(), d_w, cnt.get());
+    k_mod_count<<<div_up(n, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(), d_w, cnt.get());
     SS_HIP(hipGetLastError());
     finish_rows(A, n, cnt, s);
-    k_mod_fill<<<div_up(n, 256), 256, 0, s>>>(n, d, L.rowptr.get(), L.col.get(), L.val.get(), d_w,
+    k_mod_fill<<<div_up(n, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(), d_w,
                                               A.rowptr.get(), A.col.get(), A.val.get());
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s));

@@ -48,7 +48,7 @@ class _Csr(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("ilu", ctypes.c_int32), ("ordering", ctypes.c_int32),
                 ("gmres_m", ctypes.c_int32), ("maxiter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("trace_row", ctypes.c_int32),
                 ("drop_tol", ctypes.c_double), ("fill", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("weight", ctypes.c_double)]
 
@@ -68,7 +68,7 @@ class _Info(ctypes.Structure):
 
 def _load():
     if not os.path.exists(_LIB_PATH):
-        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1504_06768_amd.build` "
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python paper_1504_06768_amd/build.py` "
                           "(there is no fallback implementation)")
     lib = ctypes.CDLL(_LIB_PATH)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -83,6 +83,7 @@ def _load():
         "ss_export_perm": (ctypes.c_int, [P, P]),
         "ss_apply": (ctypes.c_int, [P, I32, I32, P, P]),
         "ss_bandwidth_profile": (ctypes.c_int, [P, I32, P, P]),
+        "ss_time_operator": (ctypes.c_int, [P, I32, I32, I32, P]),
         "ss_server_create": (ctypes.c_int, [ctypes.c_size_t, I32, P]),
         "ss_submit": (ctypes.c_int, [P, P, P, I32, I64, I32, D, P, P]),
         "ss_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, P]),
@@ -101,7 +102,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_solve", "ss_liouv_free", "ss_liouv_shape",
-            "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile",
+            "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile", "ss_time_operator",
             "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_destroy",
             "ss_last_error", "ss_set_stream", "ss_version")
 
@@ -160,7 +161,7 @@ def _ptr(x) -> int:
 
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
-            no_fallback=False) -> _Options:
+            no_fallback=False, trace_row=-1) -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -168,6 +169,7 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     o.ordering = {"rcm": 0, "natural": 1}[ordering] if isinstance(ordering, str) else int(ordering)
     o.gmres_m, o.maxiter, o.max_outer = gmres_m, maxiter, max_outer
     o.drop_tol, o.fill, o.sigma, o.inner_tol, o.weight = drop_tol, fill, sigma, inner_tol, weight
+    o.trace_row = int(trace_row)
     o.flags = (SS_FLAG_HERMITIZE if hermitize else 0) | (SS_FLAG_NO_FALLBACK if no_fallback else 0)
     return o
 
@@ -273,6 +275,14 @@ def apply(L: Liouvillian, op: int, x, prec="fp64"):
     _check(_lib.ss_apply(L.handle, op, PRECS[prec] if isinstance(prec, str) else prec, xh.ctypes.data,
                          y.ctypes.data), "ss_apply")
     return y
+
+
+def time_operator(L: Liouvillian, op: int, prec="fp64", reps: int = 50) -> float:
+    """ss_time_operator: mean milliseconds per application (HIP events)."""
+    ms = ctypes.c_double()
+    _check(_lib.ss_time_operator(L.handle, op, PRECS[prec] if isinstance(prec, str) else prec, int(reps),
+                                 ctypes.byref(ms)), "ss_time_operator")
+    return ms.value
 
 
 def bandwidth_profile(L: Liouvillian, which=SS_MAT_A_PERM):

@@ -150,6 +150,24 @@ def test_weighted_trace_row_equals_trace_replacement():
     assert np.max(np.abs(r0 - r2)) <= 1e-12
 
 
+def test_trace_row_in_any_population_row():
+    """The population rows of L sum to zero, so T may sit in any of them: the
+    solution of L~ x = w e_row is the steady state for every choice, and the
+    default choice for the Jaynes-Cummings workload is its ground state, whose
+    diagonal entry in L is exactly zero."""
+    s = qs.jaynes_cummings(6, seed=0)
+    L = liouvillian_sparse(s.H, s.c_ops)
+    ref = steady_state_dense(s.H, s.c_ops)
+    d = s.dim
+    for pop in (0, 1, 5, d - 1):
+        A, b, _ = otr.modified(L, pop=pop)
+        x = np.linalg.solve(A.toarray(), b)
+        assert np.max(np.abs(unvec(x, d) - ref)) <= 1e-11
+    k = otr.trace_population(L)
+    assert k == 1 and L[k * (d + 1), k * (d + 1)] == 0  # |0, g> in cavity x qubit order
+    assert otr.trace_population(liouvillian_sparse(qs.kerr(5).H, qs.kerr(5).c_ops)) == 0
+
+
 @pytest.mark.parametrize("sysf", [lambda: qs.config(1), lambda: qs.jaynes_cummings(10, seed=0),
                                   lambda: qs.random_lindblad(8, 3, seed=11),
                                   lambda: qs.spin_chain(3)])
