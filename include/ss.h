@@ -119,6 +119,10 @@ typedef struct {
 
 #define SS_FLAG_HERMITIZE   1  /* return (rho + rho^+)/2                      */
 #define SS_FLAG_NO_FALLBACK 2  /* no GMRES fallback after BiCGSTAB breakdown  */
+#define SS_FLAG_DEVICE_WIDE 4  /* force the device-wide kernels (one kernel
+                                  per step, all CUs) even for small systems   */
+#define SS_FLAG_WORKGROUP   8  /* force the workgroup-resident solve (whole
+                                  BiCGSTAB solve in one workgroup)            */
 
 typedef struct {
     int32_t status;          /* the call's return code                        */
@@ -128,7 +132,9 @@ typedef struct {
     int32_t pivots_guarded;  /* ILU pivots replaced by the guard value        */
     int32_t fell_back;       /* 1 if BiCGSTAB fell back to GMRES              */
     int32_t bandwidth;       /* B of the matrix that was factorised           */
-    int32_t reserved;
+    int32_t path;            /* 0 device-wide kernels, 1 workgroup-resident
+                                with the solve vector in global memory, 2
+                                workgroup-resident with it in LDS             */
     int64_t profile;         /* P of the matrix that was factorised           */
     int64_t nnz_matrix;      /* nnz of L~ or L - sigma I                      */
     int64_t nnz_factors;     /* nnz(L) + nnz(U) of the ILU                    */
@@ -140,6 +146,10 @@ typedef struct {
     double weight;           /* w used by the trace row                       */
     double t_setup_ms;       /* transform + ordering + factorisation          */
     double t_solve_ms;       /* Krylov iterations + finish                    */
+    double t_kernel_ms;      /* device time of the iteration kernels (HIP
+                                events), workgroup-resident path only         */
+    double bytes_alg;        /* algorithmic HBM bytes of the iterations:
+                                matrix, factors and vectors once per use      */
 } ss_info;
 
 /* fills *opt with the defaults listed above */

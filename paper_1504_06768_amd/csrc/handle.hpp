@@ -34,10 +34,42 @@ struct ss_liouv_s {
     double t_setup_ms = 0;
 };
 
+#include "wgsolve.hpp"
+
 namespace ss {
 
 hipStream_t stream_of(ss_liouv h);
 void prepare(ss_liouv h, int method, const ss_options &o);
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info);
+bool use_workgroup(ss_liouv h, int method, const ss_options &o);
+
+// Counters of one solve, handed to finish().
+struct SolveStats {
+    int status = SS_E_NOT_CONVERGED;
+    int outer = 0, inner = 0, breakdowns = 0, fell_back = 0, path = 0;
+    double t_solve_ms = 0.0, t_kernel_ms = 0.0, elem_bytes = 16.0;
+};
+
+// Device state of one workgroup-resident solve.
+template <typename T>
+struct WgBundle {
+    LevelSched lo, up;
+    PackedSide<T> pl, pu;
+    DevBuf<T> work, ysc;
+    DevBuf<double2> x, r, b;
+    DevBuf<WgResult> res;
+    WgProblem<T> P;
+    int levels = 0;
+};
+
+// Build the workgroup problem of a prepared handle (level schedules, packed
+// factors, start vector, scratch).
+template <typename T>
+void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
+             WgBundle<T> &B, hipStream_t s);
+
+// Unpermute, normalise, certify and copy out the solution x (permuted, fp64).
+int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const SolveStats &st, double *rho_out,
+           ss_info *info, hipStream_t s);
 
 }  // namespace ss

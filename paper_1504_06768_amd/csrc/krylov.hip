@@ -143,12 +143,12 @@ __global__ void k_fin_s(BicgState *st, const double2 *scal) {
     }
 }
 
-// omega = (t, s) / (t, t)
+// omega = (t, s) / (t, t) = conj(s^H t) / |t|^2  (scal[0] holds s^H t)
 __global__ void k_fin_omega(BicgState *st, const double2 *scal) {
     if (st->skip) return;
-    st->dot_ts = scal[0];
+    st->dot_ts = cconj(scal[0]);
     st->dot_tt = scal[1].x;
-    st->omega = (scal[1].x > 0.0) ? cscale(scal[0], 1.0 / scal[1].x) : mk(0.0, 0.0);
+    st->omega = (scal[1].x > 0.0) ? cscale(cconj(scal[0]), 1.0 / scal[1].x) : mk(0.0, 0.0);
 }
 
 // x += alpha p^ + omega s^, r = s - omega t, partials (r^, r) and ||r||^2

@@ -21,12 +21,15 @@
 // represented next to O(1) diagonal entries.  Inner tolerance one decade
 // below the outer one (relative to the current residual).
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 
 #include "assemble.hpp"
 #include "csr_tools.hpp"
 #include "handle.hpp"
 #include "rcm.hpp"
 #include "transform.hpp"
+#include "wgsolve.hpp"
 
 namespace ss {
 
@@ -197,129 +200,97 @@ __global__ void k_max_part(const double2 *p, int nb, double2 *out) {
 }
 
 // ------------------------------------------------------------- driver
-template <typename T>
-static int run(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
-               double *rho_out, ss_info *info) {
-    hipStream_t s = stream_of(h);
-    const int n = h->n, d = h->d;
-    const double t0 = now_ms();
-    Precond<T> M;
-    M.setup(&LUin, h->lu_diag.get(), n, s);
-    Krylov<T> K;
-    K.init(Ain.view(), &M, s);
-    const Csr<double2> A64 = h->Ap.view();
-    const int gA = spmv_group(A64.n, A64.nnz);
+// Largest system solved by the workgroup-resident kernel unless forced.
+constexpr int WG_AUTO_MAX_N = 65536;
 
-    DevBuf<double2> x((size_t)n), r((size_t)n), part(4 * (size_t)VEC_MAX_BLOCKS), scal(16);
-    DevBuf<T> bT((size_t)n), dT((size_t)n);
-    double2 *sc = scal.get();
-    const bool trace = is_trace(method);
-    const bool mixed = (o.prec == SS_MIXED);
-    bool use_gmres = is_gmres(method);
-    DevBuf<double2> bvec;
+bool use_workgroup(ss_liouv h, int method, const ss_options &o) {
+    if (is_gmres(method)) return false;
+    if (o.flags & SS_FLAG_DEVICE_WIDE) return false;
+    if (o.flags & SS_FLAG_WORKGROUP) return true;
+    return h->n <= WG_AUTO_MAX_N;
+}
+
+// Start vector and right-hand side in the permuted order: trace row
+// b = w e_rt, x = 0; inverse power x = vec(I / d).
+static void init_vectors(ss_liouv h, bool trace, double2 *x, double2 *b, hipStream_t s) {
+    const int n = h->n, d = h->d;
+    zero<double2>(n, x, s);
     if (trace) {
-        bvec.resize((size_t)n);
-        zero<double2>(n, bvec.get(), s);
-        k_set_at<<<1, 1, 0, s>>>(1, h->iperm.get() + h->trow, bvec.get(), h->w);  // b = w e_rt, permuted
-        zero<double2>(n, x.get(), s);
+        zero<double2>(n, b, s);
+        k_set_at<<<1, 1, 0, s>>>(1, h->iperm.get() + h->trow, b, h->w);
     } else {
-        zero<double2>(n, x.get(), s);
-        k_set_at<<<div_up(d, 256), 256, 0, s>>>(d, h->tpos.get(), x.get(), mk(1.0 / d, 0.0));  // vec(I / d)
+        k_set_at<<<div_up(d, 256), 256, 0, s>>>(d, h->tpos.get(), x, mk(1.0 / d, 0.0));
     }
     SS_HIP(hipGetLastError());
+}
 
-    int status = SS_E_NOT_CONVERGED;
-    int outer = 0, inner_total = 0, breakdowns = 0, fell_back = 0;
-    double resid = INFINITY;
-    const int maxouter = o.max_outer > 0 ? o.max_outer : 20;
-    for (outer = 0; outer <= maxouter; ++outer) {
-        // fp64 residual and trace
-        double2 hs[3];
-        if (trace) {
-            spmv_residual(A64, bvec.get(), x.get(), r.get(), part.get(), gA, s);
-            sum_partials(part.get(), vec_blocks(n), 1, sc, s);
-            gather_sum(d, h->tpos.get(), x.get(), sc + 1, s);
-            k_copy_d2<<<1, 1, 0, s>>>(r.get() + h->q0, sc + 2);
-            SS_HIP(hipGetLastError());
-            d2h(hs, sc, 3, s);
-            const double r2 = hs[0].x;
-            const double2 tr = hs[1], rq = hs[2];
-            // L x = -r + w (1 - Tr x) e_q0  (permuted row q0 carries T)
-            const double2 one_m_tr = mk(1.0 - tr.x, -tr.y);
-            const double2 e0 = csub(cmul(h->w, one_m_tr), rq);
-            const double lx2 = fmax(r2 - (rq.x * rq.x + rq.y * rq.y), 0.0) + e0.x * e0.x + e0.y * e0.y;
-            const double trm = sqrt(tr.x * tr.x + tr.y * tr.y);
-            resid = (trm > 0) ? sqrt(lx2) / trm : INFINITY;
-            if (outer > 0 && resid <= tol) { status = SS_OK; break; }
-            if (outer == maxouter) break;
-            const double rn = sqrt(r2);
-            if (rn == 0.0) { status = SS_OK; break; }
-            double2 den = mk(rn, 0.0);
-            h2d(sc + 4, &den, 1, s);
-        } else {
-            // r = L x = (L - sigma I) x + sigma x
-            spmv_residual(A64, nullptr, x.get(), r.get(), part.get(), gA, s);
-            double2 sg = mk(o.sigma, 0.0);
-            h2d(sc + 5, &sg, 1, s);
-            axpy_widen<double2>(n, sc + 5, x.get(), r.get(), s);
-            norm2<double2>(n, r.get(), part.get(), sc, s);
-            gather_sum(d, h->tpos.get(), x.get(), sc + 1, s);
-            d2h(hs, sc, 2, s);
-            const double trm = sqrt(hs[1].x * hs[1].x + hs[1].y * hs[1].y);
-            resid = (trm > 0) ? sqrt(hs[0].x) / trm : INFINITY;
-            if (resid <= tol) { status = SS_OK; break; }
-            if (outer == maxouter) break;
-            double2 den = mk(sqrt(hs[0].x), 0.0);
-            h2d(sc + 4, &den, 1, s);
-        }
-        // inner solve of A d = r / ||r||
-        double2 hden;
-        d2h(&hden, sc + 4, 1, s);
-        double rtol_in = o.inner_tol;
-        if (rtol_in <= 0) rtol_in = mixed ? 1e-4 : std::max(0.1 * tol / hden.x, 1e-13);
-        rtol_in = std::min(rtol_in, 0.5);
-        convert<T, double2>(n, r.get(), bT.get(), sc + 4, s);
-        KrylovResult kr;
-        if (!use_gmres) {
-            kr = K.bicgstab(bT.get(), dT.get(), rtol_in, o.maxiter);
-            breakdowns += kr.breakdown;
-            if (!kr.converged && kr.breakdown) {
-                if (o.flags & SS_FLAG_NO_FALLBACK) {
-                    inner_total += kr.iters;
-                    status = SS_E_BREAKDOWN;
-                    break;
-                }
-                // fall back to GMRES for this and the remaining steps
-                inner_total += kr.iters;
-                use_gmres = true;
-                fell_back = 1;
-                kr = K.gmres(bT.get(), dT.get(), rtol_in, o.maxiter, o.gmres_m);
-            }
-        } else {
-            kr = K.gmres(bT.get(), dT.get(), rtol_in, o.maxiter, o.gmres_m);
-        }
-        inner_total += kr.iters;
-        const unsigned pst = M.read_status(s);
-        SS_REQUIRE(!(pst & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve: dependency wait timed out");
-        if (trace) {
-            axpy_widen<T>(n, sc + 4, dT.get(), x.get(), s);  // x += ||r|| d
-        } else {
-            double2 neg = mk(-hden.x, 0.0);
-            h2d(sc + 6, &neg, 1, s);
-            axpy_widen<T>(n, sc + 6, dT.get(), x.get(), s);  // x -= ||r|| d
-            gather_sum(d, h->tpos.get(), x.get(), sc + 7, s);
-            k_scale_inv<<<div_up(n, 256), 256, 0, s>>>(n, x.get(), sc + 7);  // x /= Tr x
-            SS_HIP(hipGetLastError());
-        }
-    }
-    const double t1 = now_ms();
+template <typename T>
+void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
+             WgBundle<T> &B, hipStream_t s) {
+    const int n = h->n;
+    const bool trace = is_trace(method);
+    B.x.resize((size_t)n);
+    B.r.resize((size_t)n);
+    B.b.resize((size_t)n);
+    init_vectors(h, trace, B.x.get(), B.b.get(), s);
+    build_levels(h->LU.view(), h->lu_diag.get(), B.lo, B.up, s);
+    pack_side<T>(B.lo, LUin.view(), false, B.pl, s);
+    pack_side<T>(B.up, LUin.view(), true, B.pu, s);
+    B.work.resize((size_t)11 * n);
+    B.ysc.resize((size_t)n);
+    B.res.resize(1);
+    B.levels = B.lo.nlev + B.up.nlev;
+    WgProblem<T> &P = B.P;
+    std::memset(&P, 0, sizeof(P));
+    P.n = n;
+    P.d = h->d;
+    P.q0 = h->q0;
+    P.trace = trace ? 1 : 0;
+    P.nlev_l = B.lo.nlev;
+    P.nlev_u = B.up.nlev;
+    P.maxiter = o.maxiter;
+    P.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    P.tol = tol;
+    P.rtol_in = (o.inner_tol > 0) ? o.inner_tol : (o.prec == SS_MIXED ? 1e-4 : 0.0);
+    P.sigma = o.sigma;
+    P.w = h->w;
+    P.A = Ain.view();
+    P.A64 = h->Ap.view();
+    P.LU = LUin.view();
+    P.diag = h->lu_diag.get();
+    P.lptr = B.lo.ptr.get();
+    P.lslot = B.pl.slot.get();
+    P.lcol = B.pl.col.get();
+    P.lval = B.pl.val.get();
+    P.uptr = B.up.ptr.get();
+    P.uslot = B.pu.slot.get();
+    P.ucol = B.pu.col.get();
+    P.uval = B.pu.val.get();
+    P.uaux = B.pu.aux.get();
+    P.tpos = h->tpos.get();
+    P.b64 = trace ? B.b.get() : nullptr;
+    P.x64 = B.x.get();
+    P.r64 = B.r.get();
+    P.work = B.work.get();
+    P.ysc = B.ysc.get();
+    P.res = B.res.get();
+}
+template void make_wg<double2>(ss_liouv, int, double, const ss_options &, const CsrBuf<double2> &,
+                               const CsrBuf<double2> &, WgBundle<double2> &, hipStream_t);
+template void make_wg<float2>(ss_liouv, int, double, const ss_options &, const CsrBuf<float2> &,
+                              const CsrBuf<float2> &, WgBundle<float2> &, hipStream_t);
 
-    // finish: unpermute, normalise the trace, certificate with L itself
-    gather_sum(d, h->tpos.get(), x.get(), sc + 8, s);
+// Finish a solve: unpermute, normalise the trace, certify with L itself,
+// Hermiticity error, copy rho out (host or device), fill info.
+int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const SolveStats &st, double *rho_out,
+           ss_info *info, hipStream_t s) {
+    const int n = h->n, d = h->d;
+    DevBuf<double2> scal(4), part((size_t)VEC_MAX_BLOCKS), rho((size_t)n), Lr((size_t)n);
+    double2 *sc = scal.get();
+    gather_sum(d, h->tpos.get(), x, sc, s);
     double2 trx;
-    d2h(&trx, sc + 8, 1, s);
-    DevBuf<double2> rho((size_t)n), Lr((size_t)n);
-    k_unpermute_scale<<<div_up(n, 256), 256, 0, s>>>(n, h->perm.get(), x.get(), sc + 8, rho.get());
+    d2h(&trx, sc, 1, s);
+    k_unpermute_scale<<<div_up(n, 256), 256, 0, s>>>(n, h->perm.get(), x, sc, rho.get());
     SS_HIP(hipGetLastError());
     if (o.flags & SS_FLAG_HERMITIZE) {
         k_hermitize<<<div_up(n, 256), 256, 0, s>>>(d, rho.get(), Lr.get());
@@ -327,27 +298,28 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
     }
     const Csr<double2> Lv = h->L.view();
     spmv<double2>(Lv, rho.get(), Lr.get(), spmv_group(Lv.n, Lv.nnz), s);
-    norm2<double2>(n, Lr.get(), part.get(), sc + 9, s);
+    norm2<double2>(n, Lr.get(), part.get(), sc + 1, s);
     const int nbh = vec_blocks(n);
     k_herm_err<<<nbh, 256, 0, s>>>(d, rho.get(), part.get());
-    k_max_part<<<1, 64, 0, s>>>(part.get(), nbh, sc + 10);
+    k_max_part<<<1, 64, 0, s>>>(part.get(), nbh, sc + 2);
     SS_HIP(hipGetLastError());
     double2 fin[2];
-    d2h(fin, sc + 9, 2, s);
+    d2h(fin, sc + 1, 2, s);
     if (rho_out) {
         const hipMemcpyKind k = is_device_ptr(rho_out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         SS_HIP(hipMemcpyAsync(rho_out, rho.get(), sizeof(double2) * n, k, s));
         SS_HIP(hipStreamSynchronize(s));
     }
     const double final_res = sqrt(fin[0].x);
+    int status = st.status;
     if (status == SS_E_NOT_CONVERGED && final_res <= tol) status = SS_OK;
     if (info) {
         info->status = status;
-        info->outer_its = outer;
-        info->inner_its = inner_total;
-        info->breakdowns = breakdowns;
+        info->outer_its = st.outer;
+        info->inner_its = st.inner;
+        info->breakdowns = st.breakdowns;
         info->pivots_guarded = h->guarded;
-        info->fell_back = fell_back;
+        info->fell_back = st.fell_back;
         info->nnz_matrix = h->Ap.nnz;
         info->nnz_factors = h->LU.nnz;
         info->fill_factor = h->Ap.nnz ? (double)h->LU.nnz / h->Ap.nnz : 0.0;
@@ -356,9 +328,183 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         info->trace_err = sqrt((trx.x - 1.0) * (trx.x - 1.0) + trx.y * trx.y);
         info->weight = h->w.x;
         info->t_setup_ms = h->t_setup_ms;
-        info->t_solve_ms = t1 - t0;
+        info->t_solve_ms = st.t_solve_ms;
+        info->t_kernel_ms = st.t_kernel_ms;
+        info->path = st.path;
+        // algorithmic bytes: per BiCGSTAB iteration two SpMV and two triangular
+        // solve pairs plus about 24 vector passes; per outer step one fp64
+        // SpMV and about 6 vector passes (values, indices, row pointers and
+        // vectors each counted once per use)
+        const double sT = st.elem_bytes;
+        const double spmvT = (double)h->Ap.nnz * (sT + 4) + 4.0 * (n + 1) + 2.0 * n * sT;
+        const double trsvT = (double)h->LU.nnz * (sT + 4) + 8.0 * (n + 1) + 8.0 * n + 4.0 * n * sT;
+        const double spmv64 = (double)h->Ap.nnz * 20.0 + 4.0 * (n + 1) + 32.0 * n;
+        info->bytes_alg = st.inner * (2 * spmvT + 2 * trsvT + 24.0 * n * sT) + (st.outer + 1) * (spmv64 + 96.0 * n);
     }
     return status;
+}
+
+template <typename T>
+static int run(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
+               double *rho_out, ss_info *info) {
+    hipStream_t s = stream_of(h);
+    const int n = h->n, d = h->d;
+    const double t0 = now_ms();
+    const bool trace = is_trace(method);
+    const bool mixed = (o.prec == SS_MIXED);
+    const int maxouter = o.max_outer > 0 ? o.max_outer : 20;
+    SolveStats st;
+    st.elem_bytes = (double)sizeof(T);
+    bool use_gmres = is_gmres(method);
+    int gm_m = o.gmres_m;
+    DevBuf<double2> xbuf, bbuf;
+    double2 *x = nullptr, *bvec = nullptr;
+    WgBundle<T> B;
+    bool done_wg = false;
+    if (use_workgroup(h, method, o)) {
+        // whole solve in one workgroup: level schedules, then one launch
+        make_wg<T>(h, method, tol, o, Ain, LUin, B, s);
+        x = B.x.get();
+        bvec = B.b.get();
+        DevBuf<WgProblem<T>> dP(1);
+        h2d(dP.get(), &B.P, 1, s);
+        hipEvent_t e0, e1;
+        SS_HIP(hipEventCreate(&e0));
+        SS_HIP(hipEventCreate(&e1));
+        SS_HIP(hipEventRecord(e0, s));
+        st.path = wg_fits_lds((size_t)n, sizeof(T), B.levels) ? 2 : 1;
+        wg_solve<T>(dP.get(), 1, n, B.levels, s);
+        SS_HIP(hipEventRecord(e1, s));
+        WgResult hr;
+        d2h(&hr, B.res.get(), 1, s);
+        float kms = 0.f;
+        SS_HIP(hipEventElapsedTime(&kms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        st.t_kernel_ms = kms;
+        if (std::getenv("SS_DEBUG")) {
+            std::fprintf(stderr,
+                         "[ss] workgroup solve: n=%d levels L/U=%d/%d inner=%d outer=%d kernel=%.3f ms "
+                         "precond=%.3f ms spmv=%.3f ms total=%.3f ms (device clock)\n",
+                         n, B.lo.nlev, B.up.nlev, hr.inner, hr.outer, kms, hr.ticks_precond * 1e-5,
+                         hr.ticks_spmv * 1e-5, hr.ticks_total * 1e-5);
+        }
+        st.status = hr.status;
+        st.outer = hr.outer;
+        st.inner = hr.inner;
+        st.breakdowns = hr.breakdowns;
+        done_wg = true;
+        if (st.status == SS_E_BREAKDOWN && !(o.flags & SS_FLAG_NO_FALLBACK)) {
+            // continue from the current iterate with the device-wide GMRES
+            done_wg = false;
+            use_gmres = true;
+            st.fell_back = 1;
+            st.status = SS_E_NOT_CONVERGED;
+        }
+    } else {
+        xbuf.resize((size_t)n);
+        bbuf.resize((size_t)n);
+        x = xbuf.get();
+        bvec = bbuf.get();
+        init_vectors(h, trace, x, bvec, s);
+    }
+    if (!done_wg) {
+        Precond<T> M;
+        M.setup(&LUin, h->lu_diag.get(), n, s);
+        Krylov<T> K;
+        K.init(Ain.view(), &M, s);
+        const Csr<double2> A64 = h->Ap.view();
+        const int gA = spmv_group(A64.n, A64.nnz);
+        DevBuf<double2> r((size_t)n), part(4 * (size_t)VEC_MAX_BLOCKS), scal(16);
+        DevBuf<T> bT((size_t)n), dT((size_t)n);
+        double2 *sc = scal.get();
+        int outer;
+        for (outer = 0; outer <= maxouter; ++outer) {
+            // fp64 residual and trace
+            double2 hs[3];
+            double resid;
+            if (trace) {
+                spmv_residual(A64, bvec, x, r.get(), part.get(), gA, s);
+                sum_partials(part.get(), vec_blocks(n), 1, sc, s);
+                gather_sum(d, h->tpos.get(), x, sc + 1, s);
+                k_copy_d2<<<1, 1, 0, s>>>(r.get() + h->q0, sc + 2);
+                SS_HIP(hipGetLastError());
+                d2h(hs, sc, 3, s);
+                const double r2 = hs[0].x;
+                const double2 tr = hs[1], rq = hs[2];
+                // L x = -r + w (1 - Tr x) e_q0  (permuted row q0 carries T)
+                const double2 one_m_tr = mk(1.0 - tr.x, -tr.y);
+                const double2 e0 = csub(cmul(h->w, one_m_tr), rq);
+                const double lx2 = fmax(r2 - (rq.x * rq.x + rq.y * rq.y), 0.0) + e0.x * e0.x + e0.y * e0.y;
+                const double trm = sqrt(tr.x * tr.x + tr.y * tr.y);
+                resid = (trm > 0) ? sqrt(lx2) / trm : INFINITY;
+                if (outer > 0 && resid <= tol) { st.status = SS_OK; break; }
+                if (outer == maxouter) break;
+                const double rn = sqrt(r2);
+                if (rn == 0.0) { st.status = SS_OK; break; }
+                double2 den = mk(rn, 0.0);
+                h2d(sc + 4, &den, 1, s);
+            } else {
+                // r = L x = (L - sigma I) x + sigma x
+                spmv_residual(A64, nullptr, x, r.get(), part.get(), gA, s);
+                double2 sg = mk(o.sigma, 0.0);
+                h2d(sc + 5, &sg, 1, s);
+                axpy_widen<double2>(n, sc + 5, x, r.get(), s);
+                norm2<double2>(n, r.get(), part.get(), sc, s);
+                gather_sum(d, h->tpos.get(), x, sc + 1, s);
+                d2h(hs, sc, 2, s);
+                const double trm = sqrt(hs[1].x * hs[1].x + hs[1].y * hs[1].y);
+                resid = (trm > 0) ? sqrt(hs[0].x) / trm : INFINITY;
+                if (resid <= tol) { st.status = SS_OK; break; }
+                if (outer == maxouter) break;
+                double2 den = mk(sqrt(hs[0].x), 0.0);
+                h2d(sc + 4, &den, 1, s);
+            }
+            // inner solve of A d = r / ||r||
+            double2 hden;
+            d2h(&hden, sc + 4, 1, s);
+            double rtol_in = o.inner_tol;
+            if (rtol_in <= 0) rtol_in = mixed ? 1e-4 : std::max(0.1 * tol / hden.x, 1e-13);
+            rtol_in = std::min(rtol_in, 0.5);
+            convert<T, double2>(n, r.get(), bT.get(), sc + 4, s);
+            KrylovResult kr;
+            if (!use_gmres) {
+                kr = K.bicgstab(bT.get(), dT.get(), rtol_in, o.maxiter);
+                st.breakdowns += kr.breakdown;
+                if (!kr.converged && kr.breakdown) {
+                    st.inner += kr.iters;
+                    if (o.flags & SS_FLAG_NO_FALLBACK) {
+                        st.status = SS_E_BREAKDOWN;
+                        break;
+                    }
+                    // fall back to GMRES for this and the remaining steps
+                    use_gmres = true;
+                    st.fell_back = 1;
+                    kr = K.gmres(bT.get(), dT.get(), rtol_in, o.maxiter, gm_m);
+                }
+            } else {
+                kr = K.gmres(bT.get(), dT.get(), rtol_in, o.maxiter, gm_m);
+            }
+            // restarted GMRES that stagnates gets a longer Krylov basis next time
+            if (use_gmres && !kr.converged) gm_m = std::min(2 * gm_m, 128);
+            st.inner += kr.iters;
+            const unsigned pst = M.read_status(s);
+            SS_REQUIRE(!(pst & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve: dependency wait timed out");
+            if (trace) {
+                axpy_widen<T>(n, sc + 4, dT.get(), x, s);  // x += ||r|| d
+            } else {
+                double2 neg = mk(-hden.x, 0.0);
+                h2d(sc + 6, &neg, 1, s);
+                axpy_widen<T>(n, sc + 6, dT.get(), x, s);  // x -= ||r|| d
+                gather_sum(d, h->tpos.get(), x, sc + 7, s);
+                k_scale_inv<<<div_up(n, 256), 256, 0, s>>>(n, x, sc + 7);  // x /= Tr x
+                SS_HIP(hipGetLastError());
+            }
+        }
+        st.outer += outer;
+    }
+    st.t_solve_ms = now_ms() - t0;
+    return finish(h, x, o, tol, st, rho_out, info, s);
 }
 
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {

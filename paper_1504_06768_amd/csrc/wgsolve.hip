@@ -1,0 +1,650 @@
+// Workgroup-resident steady-state solve for small systems.
+//
+// One workgroup owns one system for the whole solve: the fp64 refinement or
+// inverse-power outer loop, right-preconditioned BiCGSTAB, the CSR SpMV and
+// the ILU(0) triangular solves all run between workgroup barriers, with no
+// kernel launch or host round trip per iteration.  The triangular solves are
+// level scheduled (section "Iterative Solvers": forward and backward
+// substitution with the iLU factors): rows of one level are independent, a
+// barrier separates levels, and the solution vector lives in LDS so that
+// every dependency read is an LDS access.  Many systems launch together, one
+// workgroup each, which is how the request server batches small solves.
+#include "syncfree.hpp"
+#include "wgsolve.hpp"
+
+namespace ss {
+
+// ================================================= level-set analysis
+__device__ __forceinline__ int ld_int(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ void st_int(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Sync-free level computation (thread per row, ordered workgroups):
+// forward  lvl[i] = 1 + max lvl[k], k in [rowptr[i], diag[i])
+// backward lvl[i] = 1 + max lvl[j], j in (diag[i], rowptr[i+1])
+template <bool UPPER>
+__global__ void __launch_bounds__(256) k_levels(int n, const int *rowptr, const int *col, const int *diag, int *lvl,
+                                                unsigned *ctr, unsigned base, unsigned *status, int *maxlvl) {
+    const unsigned bid = ordered_block(ctr, base);
+    const int lin = (int)bid * 256 + threadIdx.x;
+    const bool active = lin < n;
+    const int row = UPPER ? n - 1 - lin : lin;
+    int e = 0, ee = 0, m = -1;
+    if (active) {
+        e = UPPER ? diag[row] + 1 : rowptr[row];
+        ee = UPPER ? rowptr[row + 1] : diag[row];
+    }
+    bool done = !active;
+    unsigned spins = 0;
+    while (true) {
+        if (!done) {
+            int v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = (e + q < ee) ? ld_int(lvl + col[e + q]) : -1;
+            int used = 0;
+            bool run = true;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (run && e + q < ee && v[q] >= 0) {
+                    m = max(m, v[q]);
+                    ++used;
+                } else {
+                    run = false;
+                }
+            }
+            e += used;
+            if (used) {
+                spins = 0;
+            } else if (e < ee) {
+                ++spins;
+                if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(status))) {
+                    atomicOr(status, STATUS_SPIN_TIMEOUT);
+                    e = ee;
+                }
+            }
+            if (e >= ee) {
+                st_int(lvl + row, m + 1);
+                atomicMax(maxlvl, m + 1);
+                done = true;
+            }
+        }
+        if (__all(done)) break;
+    }
+}
+
+__global__ void k_level_count(int n, const int *lvl, int *cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[lvl[i]], 1);
+}
+
+template <bool UPPER>
+__global__ void k_level_scatter(int n, const int *rowptr, const int *diag, const int *lvl, int *cursor, int4 *slot) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int pos = atomicAdd(&cursor[lvl[i]], 1);
+    slot[pos] = UPPER ? make_int4(i, diag[i] + 1, rowptr[i + 1], 0) : make_int4(i, rowptr[i], diag[i], 0);
+}
+
+__global__ void k_fill_i32(int n, int *p, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <bool UPPER>
+static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s) {
+    const int n = LU.n;
+    DevBuf<int> lvl((size_t)std::max(n, 1)), misc(2);
+    DevBuf<unsigned> status(1);
+    SS_HIP(hipMemsetAsync(misc.get(), 0, 2 * sizeof(int), s));
+    SS_HIP(hipMemsetAsync(status.get(), 0, sizeof(unsigned), s));
+    if (n) {
+        k_fill_i32<<<div_up(n, 256), 256, 0, s>>>(n, lvl.get(), -1);
+        BlockCounter bc;
+        bc.init(s);
+        const unsigned grid = (unsigned)div_up(n, 256);
+        k_levels<UPPER><<<grid, 256, 0, s>>>(n, LU.rowptr, LU.col, diag, lvl.get(), bc.ctr.get(), bc.take(grid),
+                                             status.get(), misc.get());
+        SS_HIP(hipGetLastError());
+    }
+    int maxl = 0;
+    unsigned st = 0;
+    d2h(&maxl, misc.get(), 1, s);
+    d2h(&st, status.get(), 1, s);
+    SS_REQUIRE(!(st & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "level analysis: dependency wait timed out");
+    ls.nlev = n ? maxl + 1 : 0;
+    DevBuf<int> cnt((size_t)ls.nlev + 1);
+    SS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (ls.nlev + 1), s));
+    ls.ptr.resize((size_t)ls.nlev + 1);
+    ls.slot.resize((size_t)std::max(n, 1));
+    if (n) {
+        k_level_count<<<div_up(n, 256), 256, 0, s>>>(n, lvl.get(), cnt.get());
+        SS_HIP(hipGetLastError());
+    }
+    scan_exclusive(cnt.get(), ls.ptr.get(), ls.nlev, s, false);
+    SS_HIP(hipMemcpyAsync(cnt.get(), ls.ptr.get(), sizeof(int) * (ls.nlev + 1), hipMemcpyDeviceToDevice, s));
+    if (n) {
+        k_level_scatter<UPPER><<<div_up(n, 256), 256, 0, s>>>(n, LU.rowptr, diag, lvl.get(), cnt.get(), ls.slot.get());
+        SS_HIP(hipGetLastError());
+    }
+    SS_HIP(hipStreamSynchronize(s));
+}
+
+void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s) {
+    one_side<false>(LU, diag, lo, s);
+    one_side<true>(LU, diag, up, s);
+}
+
+template <typename T>
+__global__ void k_pack_side(int n, const int4 *in, const int *col, const T *val, bool upper, int4 *slot, int *pcol,
+                            T *pval, T *aux) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int4 sl = in[idx];
+    const int len = sl.z - sl.y;
+    slot[idx] = make_int4(sl.x, sl.y, len, 0);
+    constexpr int WG_K = WgK<T>::value;
+#pragma unroll
+    for (int k = 0; k < WG_K; ++k) {
+        pcol[(size_t)k * n + idx] = (k < len) ? col[sl.y + k] : 0;
+        pval[(size_t)k * n + idx] = (k < len) ? val[sl.y + k] : czero<T>();
+    }
+    aux[idx] = upper ? val[sl.y - 1] : czero<T>();
+}
+
+template <typename T>
+void pack_side(const LevelSched &ls, const Csr<T> &LU, bool upper, PackedSide<T> &out, hipStream_t s) {
+    const int n = LU.n;
+    const size_t nn = (size_t)std::max(n, 1);
+    out.slot.resize(nn);
+    out.col.resize(nn * WgK<T>::value);
+    out.val.resize(nn * WgK<T>::value);
+    out.aux.resize(nn);
+    if (n) {
+        k_pack_side<T><<<div_up(n, 256), 256, 0, s>>>(n, ls.slot.get(), LU.col, LU.val, upper, out.slot.get(),
+                                                       out.col.get(), out.val.get(), out.aux.get());
+        SS_HIP(hipGetLastError());
+    }
+}
+template void pack_side<double2>(const LevelSched &, const Csr<double2> &, bool, PackedSide<double2> &, hipStream_t);
+template void pack_side<float2>(const LevelSched &, const Csr<float2> &, bool, PackedSide<float2> &, hipStream_t);
+
+// ============================================== block-level primitives
+// Barrier that orders only LDS traffic: unlike __syncthreads() it does not
+// wait for outstanding global loads, so loads issued for the next level stay
+// in flight across it.  Used where threads communicate through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int BS, int K>
+__device__ __forceinline__ void blk_sum(double2 (&v)[K], double2 (*sh)[BS / 64 + 1]) {
+    constexpr int NW = BS / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k].x, y = v[k].y;
+        for (int off = 32; off > 0; off >>= 1) {
+            x += __shfl_down(x, off, 64);
+            y += __shfl_down(y, off, 64);
+        }
+        if (lane == 0) sh[k][wave] = mk(x, y);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double2 acc = sh[k][0];
+            for (int w = 1; w < NW; ++w) acc = cadd(acc, sh[k][w]);
+            sh[k][NW] = acc;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = sh[k][NW];
+    __syncthreads();
+}
+
+constexpr int WG_G = 4;  // lanes per row in the workgroup SpMV
+
+// y = A x (accumulated in V); returns conj(u1).y and, if u2 != null,
+// conj(u2).y (or |y|^2 when u2 == y) in d0, d1 (fp64, per thread; the
+// caller reduces them).  Each lane group works on WG_U rows at once so that
+// the row-pointer, index/value and gather loads of several rows are in
+// flight together.
+constexpr int WG_U = 8;
+
+template <typename V, int BS>
+__device__ __forceinline__ void blk_spmv(const Csr<V> &A, const V *x, V *y, const V *u1, const V *u2, double2 &d0,
+                                double2 &d1) {
+    const int l = threadIdx.x & (WG_G - 1);
+    const bool u2y = (u2 == y);
+    constexpr int R = BS / WG_G;  // rows per pass
+    for (int base = threadIdx.x / WG_G; base < A.n; base += R * WG_U) {
+        int rs[WG_U], re[WG_U];
+#pragma unroll
+        for (int u = 0; u < WG_U; ++u) {
+            const int row = base + u * R;
+            rs[u] = (row < A.n) ? A.rowptr[row] : 0;
+            re[u] = (row < A.n) ? A.rowptr[row + 1] : 0;
+        }
+        V acc[WG_U];
+#pragma unroll
+        for (int u = 0; u < WG_U; ++u) acc[u] = czero<V>();
+        int mx = 0;
+#pragma unroll
+        for (int u = 0; u < WG_U; ++u) mx = max(mx, re[u] - rs[u]);
+        for (int k = l; k < mx; k += WG_G) {
+#pragma unroll
+            for (int u = 0; u < WG_U; ++u) {
+                const int e = rs[u] + k;
+                if (e < re[u]) acc[u] = cadd(acc[u], cmul(A.val[e], x[A.col[e]]));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WG_U; ++u) {
+#pragma unroll
+            for (int off = WG_G / 2; off > 0; off >>= 1) {
+                acc[u].x += __shfl_xor(acc[u].x, off, WG_G);
+                acc[u].y += __shfl_xor(acc[u].y, off, WG_G);
+            }
+            const int row = base + u * R;
+            if (l == 0 && row < A.n) {
+                y[row] = acc[u];
+                const double2 yy = widen(acc[u]);
+                if (u1) d0 = cadd(d0, cmulc(widen(u1[row]), yy));
+                if (u2y) d1.x += yy.x * yy.x + yy.y * yy.y;
+                else if (u2) d1 = cadd(d1, cmulc(widen(u2[row]), yy));
+            }
+        }
+    }
+}
+
+// One slot of a level held in registers: its packed entries are fetched a
+// few levels before they are used.
+template <typename T>
+struct SlotRegs {
+    static constexpr int WG_K = WgK<T>::value;
+    int4 sl;  // {row, first CSR entry, length, 0}; row < 0: no slot
+    int c[WG_K];
+    T v[WG_K];
+    T aux;    // lower: right-hand side (level order); upper: pivot
+};
+
+// Issue the loads of slot idx (all addressed by idx: none waits on another).
+// Branch-free: an index past the level end is clamped to a valid slot and
+// marked invalid, so the loads stay unconditional and in flight.
+template <typename T, bool UPPER>
+__device__ __forceinline__ void fetch_slot(SlotRegs<T> &q, int idx, int end, int n, const int4 *slot,
+                                           const int *pcol, const T *pval, const T *aux) {
+    constexpr int WG_K = WgK<T>::value;
+    const int j = min(idx, n - 1);
+    q.sl = slot[j];
+#pragma unroll
+    for (int k = 0; k < WG_K; ++k) {
+        q.c[k] = pcol[(size_t)k * n + j];
+        q.v[k] = pval[(size_t)k * n + j];
+    }
+    q.aux = aux[j];
+    q.sl.w = idx < end;  // validity flag
+}
+
+template <typename T, bool UPPER>
+__device__ __forceinline__ void solve_regs(const SlotRegs<T> &q, const int *col, const T *val, T *Y) {
+    constexpr int WG_K = WgK<T>::value;
+    const int len = q.sl.z;
+    T acc = UPPER ? Y[q.sl.x] : q.aux;
+#pragma unroll
+    for (int k = 0; k < WG_K; ++k) {
+        const T y = Y[q.c[k]];
+        const T t = csub(acc, cmul(q.v[k], y));
+        acc = (k < len) ? t : acc;
+    }
+    if (len > WG_K && q.sl.w) {
+        for (int e = q.sl.y + WG_K; e < q.sl.y + len; ++e) acc = csub(acc, cmul(val[e], Y[col[e]]));
+    }
+    const T res = UPPER ? cdiv(acc, q.aux) : acc;
+    if (q.sl.w) Y[q.sl.x] = res;
+}
+
+// Slots of a level beyond the first 64: fetched and solved directly.
+template <typename T, bool UPPER>
+__device__ __forceinline__ void solve_rest(int p0, int p1, int n, const int4 *slot, const int *pcol, const T *pval,
+                                           const T *aux, const int *col, const T *val, T *Y) {
+    for (int idx = p0 + 64 + (int)(threadIdx.x & 63); idx < p1; idx += 64) {
+        SlotRegs<T> q;
+        fetch_slot<T, UPPER>(q, idx, p1, n, slot, pcol, pval, aux);
+        solve_regs<T, UPPER>(q, col, val, Y);
+    }
+}
+
+// One triangular sweep over the level schedule, run by a single wavefront.
+// The instructions of one wavefront reach LDS in program order, so a level
+// reads the values the previous level wrote without any barrier; with Y in
+// global memory a wavefront-scope fence orders the accesses instead.  A
+// three-deep register ring keeps the packed slots of the next levels in
+// flight while a level is solved.
+template <typename T, bool UPPER, bool LDSY>
+__device__ __forceinline__ void wave_sweep(int nlev, int n, const int *ptr, const int4 *slot, const int *pcol,
+                                           const T *pval, const T *aux, const int *col, const T *val, T *Y) {
+    // ptr holds nlev + 5 entries: the last ones repeat ptr[nlev] (empty levels)
+    if (nlev <= 0) return;
+    const int lane = threadIdx.x & 63;
+    SlotRegs<T> r0, r1, r2;
+    fetch_slot<T, UPPER>(r0, ptr[0] + lane, ptr[1], n, slot, pcol, pval, aux);
+    fetch_slot<T, UPPER>(r1, ptr[1] + lane, ptr[2], n, slot, pcol, pval, aux);
+    fetch_slot<T, UPPER>(r2, ptr[2] + lane, ptr[3], n, slot, pcol, pval, aux);
+    for (int lev = 0; lev < nlev; lev += 3) {
+#define SS_SWEEP_STEP(R, L)                                                                             \
+        {                                                                                               \
+            const int a0 = ptr[(L)], a1 = ptr[(L) + 1], a3 = ptr[(L) + 3], a4 = ptr[(L) + 4];           \
+            solve_regs<T, UPPER>(R, col, val, Y);                                                       \
+            if (a1 - a0 > 64) solve_rest<T, UPPER>(a0, a1, n, slot, pcol, pval, aux, col, val, Y);      \
+            fetch_slot<T, UPPER>(R, a3 + lane, a4, n, slot, pcol, pval, aux);                           \
+            if (!LDSY) {                                                                                \
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");                                  \
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");                                  \
+            }                                                                                           \
+        }
+        SS_SWEEP_STEP(r0, lev)
+        SS_SWEEP_STEP(r1, lev + 1)
+        SS_SWEEP_STEP(r2, lev + 2)
+#undef SS_SWEEP_STEP
+    }
+}
+
+template <typename T, int BS, bool LDSY>
+__device__ __forceinline__ void blk_precond(const WgProblem<T> &P, const int *lptr, const int *uptr, const T *b,
+                                            T *out, T *Y) {
+    const int n = P.n;
+    // right-hand side in the forward sweep's level order, so the sweep reads
+    // it by slot index
+    T *bl = P.work + 10 * (size_t)n;
+    for (int idx = threadIdx.x; idx < n; idx += BS) bl[idx] = b[P.lslot[idx].x];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        wave_sweep<T, false, LDSY>(P.nlev_l, n, lptr, P.lslot, P.lcol, P.lval, bl, P.LU.col, P.LU.val, Y);
+        wave_sweep<T, true, LDSY>(P.nlev_u, n, uptr, P.uslot, P.ucol, P.uval, P.uaux, P.LU.col, P.LU.val, Y);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BS) out[i] = Y[i];
+    __syncthreads();
+}
+
+struct InnerStats {
+    int its;
+    int converged;
+    int breakdowns;
+    long long t_pre;
+    long long t_spmv;
+};
+
+// Right-preconditioned BiCGSTAB (van der Vorst) on A d = b from d = 0, to
+// ||r|| <= rtol ||b||; breakdown (r^ orthogonal to r, or omega = 0) restarts
+// with r^ = r up to three times.
+template <typename T, int BS, bool LDSY>
+__device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const int *lptr, const int *uptr,
+                                                   const T *b, T *x, double rtol, T *Y,
+                                                   double2 (*red)[BS / 64 + 1]) {
+    const int n = P.n;
+    T *r = P.work, *rh = r + n, *p = rh + n, *v = p + n, *sv = v + n, *t = sv + n, *ph = t + n, *sh = ph + n;
+    const double bd_eps = sizeof(typename RealOf<T>::type) == 8 ? 1e-30 : 1e-14;
+    InnerStats st = {0, 0, 0, 0, 0};
+    double2 q1[1] = {mk(0.0, 0.0)};
+    for (int i = threadIdx.x; i < n; i += BS) {
+        const T bi = b[i];
+        r[i] = bi;
+        rh[i] = bi;
+        p[i] = czero<T>();
+        v[i] = czero<T>();
+        x[i] = czero<T>();
+        const double2 w = widen(bi);
+        q1[0].x += w.x * w.x + w.y * w.y;
+    }
+    blk_sum<BS, 1>(q1, red);
+    const double b2 = q1[0].x;
+    if (b2 == 0.0) {
+        st.converged = 1;
+        return st;
+    }
+    const double tol2 = rtol * rtol * b2;
+    double rhat2 = b2;
+    double2 rho = mk(b2, 0.0), rho_old = mk(1.0, 0.0), alpha = mk(1.0, 0.0), omega = mk(1.0, 0.0);
+    while (st.its < P.maxiter) {
+        const double2 beta = cmul(cdiv(rho, rho_old), cdiv(alpha, omega));
+        for (int i = threadIdx.x; i < n; i += BS) {
+            const double2 q = csub(widen(p[i]), cmul(omega, widen(v[i])));
+            p[i] = from_c128<T>(cadd(widen(r[i]), cmul(beta, q)));
+        }
+        __syncthreads();
+        long long c0 = wall_clock64();
+        blk_precond<T, BS, LDSY>(P, lptr, uptr, p, ph, Y);
+        long long c1 = wall_clock64();
+        double2 q2[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+        blk_spmv<T, BS>(P.A, LDSY ? Y : ph, v, rh, v, q2[0], q2[1]);
+        blk_sum<BS, 2>(q2, red);
+        long long c2 = wall_clock64();
+        st.t_pre += c1 - c0;
+        st.t_spmv += c2 - c1;
+        const double2 rv = q2[0];
+        bool breakdown = !((rv.x * rv.x + rv.y * rv.y) > bd_eps * bd_eps * rhat2 * q2[1].x);
+        if (!breakdown) {
+            alpha = cdiv(rho, rv);
+            double2 q3[1] = {mk(0.0, 0.0)};
+            for (int i = threadIdx.x; i < n; i += BS) {
+                const T si = from_c128<T>(csub(widen(r[i]), cmul(alpha, widen(v[i]))));
+                sv[i] = si;
+                const double2 w = widen(si);
+                q3[0].x += w.x * w.x + w.y * w.y;
+            }
+            blk_sum<BS, 1>(q3, red);
+            if (q3[0].x <= tol2) {
+                for (int i = threadIdx.x; i < n; i += BS) x[i] = from_c128<T>(cadd(widen(x[i]), cmul(alpha, widen(ph[i]))));
+                __syncthreads();
+                st.its += 1;
+                st.converged = 1;
+                return st;
+            }
+            c0 = wall_clock64();
+            blk_precond<T, BS, LDSY>(P, lptr, uptr, sv, sh, Y);
+            c1 = wall_clock64();
+            double2 q4[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+            blk_spmv<T, BS>(P.A, LDSY ? Y : sh, t, sv, t, q4[0], q4[1]);
+            blk_sum<BS, 2>(q4, red);
+            c2 = wall_clock64();
+            st.t_pre += c1 - c0;
+            st.t_spmv += c2 - c1;
+            // omega = (t, s) / (t, t) = conj(s^H t) / |t|^2
+            omega = (q4[1].x > 0.0) ? cscale(cconj(q4[0]), 1.0 / q4[1].x) : mk(0.0, 0.0);
+            double2 q5[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+            for (int i = threadIdx.x; i < n; i += BS) {
+                const double2 xi =
+                    cadd(cadd(widen(x[i]), cmul(alpha, widen(ph[i]))), cmul(omega, widen(sh[i])));
+                x[i] = from_c128<T>(xi);
+                const T ri = from_c128<T>(csub(widen(sv[i]), cmul(omega, widen(t[i]))));
+                r[i] = ri;
+                const double2 rw = widen(ri);
+                q5[0] = cadd(q5[0], cmulc(widen(rh[i]), rw));
+                q5[1].x += rw.x * rw.x + rw.y * rw.y;
+            }
+            blk_sum<BS, 2>(q5, red);
+            st.its += 1;
+            rho_old = rho;
+            rho = q5[0];
+            const double r2 = q5[1].x;
+            if (r2 <= tol2) {
+                st.converged = 1;
+                return st;
+            }
+            breakdown = !(omega.x != 0.0 || omega.y != 0.0) ||
+                        !((rho.x * rho.x + rho.y * rho.y) > bd_eps * bd_eps * rhat2 * r2);
+        }
+        if (breakdown) {
+            if (st.breakdowns >= 3) return st;
+            st.breakdowns += 1;
+            double2 q6[1] = {mk(0.0, 0.0)};
+            for (int i = threadIdx.x; i < n; i += BS) {
+                const T ri = r[i];
+                rh[i] = ri;
+                p[i] = czero<T>();
+                v[i] = czero<T>();
+                const double2 w = widen(ri);
+                q6[0].x += w.x * w.x + w.y * w.y;
+            }
+            blk_sum<BS, 1>(q6, red);
+            rhat2 = q6[0].x;
+            rho = mk(rhat2, 0.0);
+            rho_old = mk(1.0, 0.0);
+            alpha = mk(1.0, 0.0);
+            omega = mk(1.0, 0.0);
+        }
+    }
+    return st;
+}
+
+// ================================================== the solve kernel
+template <typename T, int BS, bool LDSY>
+__global__ void __launch_bounds__(BS) k_wg_solve(const WgProblem<T> *probs) {
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    __shared__ double2 red[3][BS / 64 + 1];
+    const WgProblem<T> &P = probs[blockIdx.x];
+    T *Y = LDSY ? reinterpret_cast<T *>(dyn_lds) : P.ysc;
+    const int n = P.n;
+    // level pointers in LDS next to Y: reading them is then an LDS access,
+    // ordered with the other LDS traffic of the sweeps
+    const int *lptr = P.lptr, *uptr = P.uptr;
+    {
+        // level pointers in LDS (padded with five repeats of the end so the
+        // sweeps can read ahead without bounds checks)
+        int *lp = reinterpret_cast<int *>(dyn_lds + (LDSY ? (size_t)n * sizeof(T) : 0));
+        int *up = lp + P.nlev_l + 6;
+        for (int k = threadIdx.x; k <= P.nlev_l + 5; k += BS) lp[k] = P.lptr[min(k, P.nlev_l)];
+        for (int k = threadIdx.x; k <= P.nlev_u + 5; k += BS) up[k] = P.uptr[min(k, P.nlev_u)];
+        __syncthreads();
+        lptr = lp;
+        uptr = up;
+    }
+    T *bT = P.work + 8 * (size_t)n, *dT = bT + n;
+    int status = SS_E_NOT_CONVERGED, inner = 0, breakdowns = 0, outer = 0;
+    double resid = INFINITY;
+    const long long t_start = wall_clock64();
+    long long t_pre = 0, t_spmv = 0;
+    for (outer = 0; outer <= P.max_outer; ++outer) {
+        // fp64 residual: trace row  r = b - A x;  inverse power  r = A x + sigma x = L x
+        double2 q[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+        double2 dummy = mk(0.0, 0.0), dummy2 = mk(0.0, 0.0);
+        blk_spmv<double2, BS>(P.A64, P.x64, P.r64, nullptr, nullptr, dummy, dummy2);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += BS) {
+            const double2 ax = P.r64[i];
+            const double2 ri = P.trace ? csub(P.b64[i], ax) : cadd(ax, cscale(P.x64[i], P.sigma));
+            P.r64[i] = ri;
+            q[0].x += ri.x * ri.x + ri.y * ri.y;
+        }
+        for (int k = threadIdx.x; k < P.d; k += BS) q[1] = cadd(q[1], P.x64[P.tpos[k]]);
+        __syncthreads();
+        if (threadIdx.x == 0 && P.trace) q[2] = P.r64[P.q0];
+        blk_sum<BS, 3>(q, red);
+        const double r2 = q[0].x;
+        const double2 tr = q[1];
+        const double trm = sqrt(tr.x * tr.x + tr.y * tr.y);
+        double lx2 = r2;
+        if (P.trace) {
+            // L x = -r + w (1 - Tr x) e_q0 (the permuted row q0 carries T)
+            const double2 rq = q[2];
+            const double2 e0 = csub(cmul(P.w, mk(1.0 - tr.x, -tr.y)), rq);
+            lx2 = fmax(r2 - (rq.x * rq.x + rq.y * rq.y), 0.0) + e0.x * e0.x + e0.y * e0.y;
+        }
+        resid = (trm > 0.0) ? sqrt(lx2) / trm : INFINITY;
+        if ((P.trace == 0 || outer > 0) && resid <= P.tol) { status = SS_OK; break; }
+        if (outer == P.max_outer) break;
+        const double rn = sqrt(r2);
+        if (rn == 0.0) { status = SS_OK; break; }
+        const double rtol = (P.rtol_in > 0.0) ? P.rtol_in : fmax(0.1 * P.tol / rn, 1e-13);
+        const double inv = 1.0 / rn;
+        for (int i = threadIdx.x; i < n; i += BS) bT[i] = from_c128<T>(cscale(P.r64[i], inv));
+        __syncthreads();
+        const InnerStats is = blk_bicgstab<T, BS, LDSY>(P, lptr, uptr, bT, dT, fmin(rtol, 0.5), Y, red);
+        inner += is.its;
+        breakdowns += is.breakdowns;
+        t_pre += is.t_pre;
+        t_spmv += is.t_spmv;
+        if (!is.converged && is.breakdowns >= 3) {
+            status = SS_E_BREAKDOWN;
+            break;
+        }
+        const double sc = P.trace ? rn : -rn;
+        for (int i = threadIdx.x; i < n; i += BS) P.x64[i] = cadd(P.x64[i], cscale(widen(dT[i]), sc));
+        __syncthreads();
+        if (!P.trace) {
+            double2 qt[1] = {mk(0.0, 0.0)};
+            for (int k = threadIdx.x; k < P.d; k += BS) qt[0] = cadd(qt[0], P.x64[P.tpos[k]]);
+            blk_sum<BS, 1>(qt, red);
+            const double2 invt = cdiv(mk(1.0, 0.0), qt[0]);
+            for (int i = threadIdx.x; i < n; i += BS) P.x64[i] = cmul(P.x64[i], invt);
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        P.res->status = status;
+        P.res->outer = outer;
+        P.res->inner = inner;
+        P.res->breakdowns = breakdowns;
+        P.res->resid = resid;
+        P.res->ticks_precond = t_pre;
+        P.res->ticks_spmv = t_spmv;
+        P.res->ticks_total = wall_clock64() - t_start;
+    }
+}
+
+static size_t lds_budget() {
+    static size_t cached = 0;
+    if (!cached) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            size_t b = prop.sharedMemPerBlock;
+            // static LDS of the kernel (reduction scratch) stays below 1 KB
+            cached = b > 2048 ? b - 2048 : 0;
+        } else {
+            (void)hipGetLastError();
+            cached = 64 * 1024 - 2048;
+        }
+    }
+    return cached;
+}
+
+template <typename T>
+int wg_lds_capacity() {
+    return (int)(lds_budget() / sizeof(T));
+}
+template int wg_lds_capacity<double2>();
+template int wg_lds_capacity<float2>();
+
+bool wg_fits_lds(size_t n, size_t elem, int levels) {
+    return n * elem + sizeof(int) * ((size_t)levels + 12) <= lds_budget();
+}
+
+template <typename T>
+void wg_solve(const WgProblem<T> *probs, int count, int max_n, int max_levels, hipStream_t s) {
+    if (count <= 0) return;
+    const size_t ptr_bytes = sizeof(int) * ((size_t)max_levels + 12);
+    const size_t bytes = (size_t)max_n * sizeof(T) + ptr_bytes;
+    if (bytes <= lds_budget()) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        (void)hipGetLastError();
+        k_wg_solve<T, WG_BS, true><<<count, WG_BS, bytes, s>>>(probs);
+    } else {
+        SS_REQUIRE(ptr_bytes <= lds_budget(), SS_E_INVALID_ARG, "too many levels for the workgroup solver");
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ptr_bytes);
+        (void)hipGetLastError();
+        k_wg_solve<T, WG_BS, false><<<count, WG_BS, ptr_bytes, s>>>(probs);
+    }
+    SS_HIP(hipGetLastError());
+}
+template void wg_solve<double2>(const WgProblem<double2> *, int, int, int, hipStream_t);
+template void wg_solve<float2>(const WgProblem<float2> *, int, int, int, hipStream_t);
+
+}  // namespace ss

@@ -25,7 +25,7 @@ SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES = 0, 1, 2
 SS_FP64, SS_MIXED = 0, 1
 SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
-SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK = 1, 2
+SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
 
@@ -56,11 +56,12 @@ class _Options(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("outer_its", ctypes.c_int32), ("inner_its", ctypes.c_int32),
                 ("breakdowns", ctypes.c_int32), ("pivots_guarded", ctypes.c_int32), ("fell_back", ctypes.c_int32),
-                ("bandwidth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bandwidth", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("profile", ctypes.c_int64), ("nnz_matrix", ctypes.c_int64), ("nnz_factors", ctypes.c_int64),
                 ("resid_l2", ctypes.c_double), ("herm_err", ctypes.c_double), ("trace_err", ctypes.c_double),
                 ("cond_est", ctypes.c_double), ("fill_factor", ctypes.c_double), ("weight", ctypes.c_double),
-                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("t_kernel_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -161,7 +162,7 @@ def _ptr(x) -> int:
 
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
-            no_fallback=False, trace_row=-1) -> _Options:
+            no_fallback=False, trace_row=-1, path="auto") -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -171,6 +172,7 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     o.drop_tol, o.fill, o.sigma, o.inner_tol, o.weight = drop_tol, fill, sigma, inner_tol, weight
     o.trace_row = int(trace_row)
     o.flags = (SS_FLAG_HERMITIZE if hermitize else 0) | (SS_FLAG_NO_FALLBACK if no_fallback else 0)
+    o.flags |= {"auto": 0, "device": SS_FLAG_DEVICE_WIDE, "workgroup": SS_FLAG_WORKGROUP}[path]
     return o
 
 

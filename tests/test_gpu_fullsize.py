@@ -1,0 +1,75 @@
+"""Full-size workloads (GPU): optomechanics 10 x 60 (n = 360000) and the
+chain of three Kerr cavities (n = 10^6).  The dense oracle cannot hold these,
+so parity is checked through properties that hold at any size and exact
+product-form special cases:
+  * uncoupled chain (J = 0): rho = rho_1 (x) rho_2 (x) rho_3, each factor from
+    the dense oracle of one 10-state cavity;
+  * optomechanics with g0 = 0: rho = rho_cavity (x) rho_mechanics, the
+    mechanical factor a truncated Bose-Einstein state;
+  * at the workloads' own parameters: ||L rho||_2 <= 1e-10, unit trace and
+    Hermiticity (parity unpinned beyond the residual certificate).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import qsystems as qs
+from oracle.steady import steady_state_dense
+
+pytestmark = pytest.mark.gpu
+ssl = pytest.importorskip("paper_1504_06768_amd")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_kerr_chain_uncoupled_product_form():
+    s = qs.kerr_chain(3, 10, J=0.0)
+    k = qs.kerr(10)
+    r1 = steady_state_dense(k.H, k.c_ops)
+    ref = np.kron(np.kron(r1, r1), r1)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, "invpow_bicgstab", tol=1e-10, prec="mixed", raise_on_error=False)
+    _say("chain J=0 invpow mixed", info)
+    assert info["status"] == 0
+    assert np.max(np.abs(rho - ref)) <= 1e-6
+    assert info["resid_l2"] <= 1e-10
+
+
+def test_optomechanics_decoupled_product_form():
+    s = qs.optomechanics(10, 60, g0=0.0, nth=2.0)
+    cav = qs.kerr(10, delta=0.0, chi=0.0, E=0.1, kappa=0.3)
+    rc = steady_state_dense(cav.H, cav.c_ops)
+    r = 2.0 / 3.0
+    pm = (1 - r) * r ** np.arange(60) / (1 - r ** 60)
+    ref = np.kron(rc, np.diag(pm))
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, prec="fp64", raise_on_error=False)
+    _say("opto g0=0 trace fp64", info)
+    assert info["status"] == 0
+    assert np.max(np.abs(rho - ref)) <= 1e-8
+
+
+@pytest.mark.parametrize("method,prec", [("invpow_bicgstab", "mixed"), ("trace_bicgstab", "mixed")])
+def test_kerr_chain_workload(method, prec):
+    s = qs.config(4)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False)
+    _say("chain", method, prec, info)
+    assert info["status"] == 0
+    assert info["resid_l2"] <= 1e-10
+    assert abs(np.trace(rho) - 1) <= 1e-12
+    assert info["herm_err"] <= 1e-8
+
+
+@pytest.mark.parametrize("method,prec", [("trace_bicgstab", "mixed"), ("trace_gmres", "mixed")])
+def test_optomechanics_workload(method, prec):
+    s = qs.config(3)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False)
+    _say("opto", method, prec, info)
+    assert info["status"] == 0
+    assert info["resid_l2"] <= 1e-10
+    assert abs(np.trace(rho) - 1) <= 1e-12

@@ -226,14 +226,19 @@ CASES = [(name, m) for name in ["kerr20", "jc8", "random7", "opto3x5"] for m in 
 CASES += [("spin3", "invpow_bicgstab"), ("spin3", "invpow_gmres")]
 
 
+CASES = [(n, m, p) for (n, m) in CASES for p in (["device", "workgroup"] if "bicgstab" in m else ["device"])]
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
-@pytest.mark.parametrize("name,method", CASES)
-def test_steady_state_matches_dense_oracle(name, method, prec, tol):
+@pytest.mark.parametrize("name,method,path", CASES)
+def test_steady_state_matches_dense_oracle(name, method, path, prec, tol):
+    """Both execution paths: device-wide kernels, and the whole solve inside
+    one workgroup (level-scheduled triangular solves in LDS)."""
     s = SMALL[name]()
-    _say("solve", name, method, prec)
+    _say("solve", name, method, path, prec)
     ref = steady_state_dense(s.H, s.c_ops)
     L = ssl.build_liouvillian(s.H, s.c_ops)
-    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False)
+    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False, path=path)
     _say("   info", info)
     assert info["status"] == 0
     err = np.max(np.abs(rho - ref))
@@ -243,14 +248,15 @@ def test_steady_state_matches_dense_oracle(name, method, prec, tol):
     assert abs(np.trace(rho) - 1) <= 1e-12
 
 
+@pytest.mark.parametrize("path", ["device", "workgroup"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
-def test_jaynes_cummings_workload(prec, tol):
+def test_jaynes_cummings_workload(prec, tol, path):
     """Driven Jaynes-Cummings, cavity 40 x qubit (n = 6400)."""
     s = qs.config(2)
-    _say("solve jc40", prec)
+    _say("solve jc40", prec, path)
     ref = steady_state_dense(s.H, s.c_ops)
     L = ssl.build_liouvillian(s.H, s.c_ops)
-    rho, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, prec=prec)
+    rho, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, prec=prec, path=path)
     _say("   err", np.max(np.abs(rho - ref)), info)
     assert np.max(np.abs(rho - ref)) <= tol
     assert info["resid_l2"] <= 1e-10
