@@ -130,6 +130,34 @@ def ilut(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0, boos
     return sp.csr_matrix((data, indices, indptr), shape=A.shape), guarded
 
 
+def ilut_c(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0, boost: float | None = None):
+    """The same ILUT as ilut(), computed by the oracle's C routine
+    (oracle/c/ilut.c) with identical arithmetic, for full-size systems.
+    Returns (LU csr, guarded pivots)."""
+    from . import _clib
+    boost = guard if boost is None else boost
+    A = sp.csr_matrix(A, dtype=np.complex128)
+    A.sort_indices()
+    n = A.shape[0]
+    indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+    data = np.ascontiguousarray(A.data, dtype=np.complex128)
+    nz = np.diff(indptr).astype(np.float64)
+    cap = int(n + 2 * np.sum(np.ceil(fill * nz)))
+    lp = np.zeros(n + 1, dtype=np.int64)
+    li = np.zeros(max(cap, 1), dtype=np.int32)
+    lv = np.zeros(max(cap, 1), dtype=np.complex128)
+    rc = _clib.load().oracle_ilut(n, indptr.ctypes.data, indices.ctypes.data, data.ctypes.data, float(drop_tol),
+                                  float(fill), float(guard), float(boost), cap, lp.ctypes.data, li.ctypes.data,
+                                  lv.ctypes.data)
+    if rc == -3:
+        raise ZeroDivisionError("ilut: zero pivot")
+    if rc < 0:
+        raise MemoryError(f"oracle_ilut failed ({rc})")
+    m = int(lp[n])
+    return sp.csr_matrix((lv[:m].copy(), li[:m].copy(), lp), shape=A.shape), rc
+
+
 def split(LU):
     """(unit lower L, upper U) as separate CSR matrices."""
     LU = sp.csr_matrix(LU)

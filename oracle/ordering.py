@@ -15,40 +15,19 @@ with gcc on first use so large graphs stay fast.
 """
 from __future__ import annotations
 
-import ctypes
-import os
-import subprocess
-import threading
-
 import numpy as np
 import scipy.sparse as sp
 
-_HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "c", "cm_order.c")
-_LIB = os.path.join(_HERE, "c", "liboracle_cm.so")
-_lock = threading.Lock()
-_lib = None
+from . import _clib
 
 
 def build_c() -> str:
-    """Compile the C part of the oracle with gcc (called by the build step and
-    lazily on first use)."""
-    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", _LIB, _SRC])
-    return _LIB
+    """Compile the C part of the oracle (kept for the build step)."""
+    return _clib.build_c()
 
 
 def _load():
-    global _lib
-    with _lock:
-        if _lib is None:
-            if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-                build_c()
-            lib = ctypes.CDLL(_LIB)
-            lib.oracle_cuthill_mckee.restype = ctypes.c_int
-            lib.oracle_cuthill_mckee.argtypes = [ctypes.c_int64, ctypes.c_void_p,
-                                                 ctypes.c_void_p, ctypes.c_void_p]
-            _lib = lib
-    return _lib
+    return _clib.load()
 
 
 def pattern(A) -> sp.csr_matrix:

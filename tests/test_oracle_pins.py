@@ -373,3 +373,63 @@ def test_condition_estimate_of_exact_factors():
     LU, _ = oilu.ilut(sp.csr_matrix(M), drop_tol=0.0, fill=100.0)
     ref = np.max(np.abs(np.linalg.solve(M, np.ones(n))))
     assert abs(oilu.condition_estimate(LU) - ref) <= 1e-12 * ref
+
+
+def test_ilut_hand_example():
+    """A 3 x 3 case worked by hand: A = [[4,0,1],[1,4,0],[0,1,4]].
+    drop 0.1 (tau = 0.4): l_10 = l_21 = 1/4 are dropped, so L is empty and
+    U = triu(A); drop 0.01 (tau = 0.04): l_10 = 1/4 is kept, fill u_12 = -1/4, then
+    l_21 = 1/4 and u_22 = 4 + 1/16."""
+    A = sp.csr_matrix(np.array([[4, 0, 1], [1, 4, 0], [0, 1, 4]], dtype=np.complex128))
+    want_coarse = np.array([[4, 0, 1], [0, 4, 0], [0, 0, 4]])
+    want_fine = np.array([[4, 0, 1], [0.25, 4, -0.25], [0, 0.25, 4.0625]])
+    for f in (oilu.ilut, oilu.ilut_c):
+        LU, _ = f(A, drop_tol=0.1, fill=10.0)
+        assert np.array_equal(LU.toarray(), want_coarse)
+        LU, _ = f(A, drop_tol=0.01, fill=10.0)
+        assert np.array_equal(LU.toarray(), want_fine)
+
+
+def _ilut_cases():
+    rng = np.random.default_rng(11)
+    n = 40
+    M = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * (rng.random((n, n)) < 0.12)
+    M += np.diag(rng.normal(size=n) + 3j)
+    yield "random40", sp.csr_matrix(M)
+    s = qs.kerr(10)
+    A = otr.modified(liouvillian_sparse(s.H, s.c_ops))[0]
+    yield "kerr10_rcm", oord.permute(A, oord.rcm(A))
+    s = qs.jaynes_cummings(N=6)
+    L = liouvillian_sparse(s.H, s.c_ops)
+    A = otr.modified(L, pop=otr.trace_population(L))[0]
+    yield "jc6_rcm", oord.permute(A, oord.rcm(A))
+
+
+@pytest.mark.parametrize("drop,fill,guard", [(1e-4, 10.0, 1e-8), (1e-2, 2.0, 1e-8), (0.0, 100.0, 0.0),
+                                             (1e-3, 1.0, 1e-8)])
+def test_ilut_c_equals_python_ilut(drop, fill, guard):
+    """The C ILUT and the Python ILUT are written independently from the same
+    steps with the same complex arithmetic: they must agree bit for bit."""
+    for name, A in _ilut_cases():
+        LUp, gp = oilu.ilut(A, drop_tol=drop, fill=fill, guard=guard, boost=0.1 if guard else None)
+        LUc, gc = oilu.ilut_c(A, drop_tol=drop, fill=fill, guard=guard, boost=0.1 if guard else None)
+        assert gp == gc, name
+        assert np.array_equal(LUp.indptr, LUc.indptr), name
+        assert np.array_equal(LUp.indices, LUc.indices), name
+        assert np.array_equal(LUp.data, LUc.data), name
+
+
+def test_ilut_c_limits():
+    """Complete LU at drop 0 / unlimited fill; ILU(0) where the exact LU has
+    no fill (a tridiagonal matrix)."""
+    rng = np.random.default_rng(12)
+    n = 30
+    M = rng.normal(size=(n, n)) * (rng.random((n, n)) < 0.3) + np.diag(4 * n * np.ones(n))
+    LU, _ = oilu.ilut_c(sp.csr_matrix(M.astype(np.complex128)), drop_tol=0.0, fill=1000.0)
+    L, U = oilu.split(LU)
+    assert np.max(np.abs((L @ U).toarray() - M)) <= 1e-12 * np.max(np.abs(M))
+    T = sp.diags([rng.normal(size=n - 1), 4 + rng.normal(size=n), rng.normal(size=n - 1)], [-1, 0, 1],
+                 format="csr").astype(np.complex128)
+    LUt, _ = oilu.ilut_c(T, drop_tol=0.0, fill=1.0)
+    LU0, _ = oilu.ilu0(T)
+    assert np.max(np.abs((LUt - LU0).toarray())) <= 1e-14
