@@ -2,14 +2,14 @@
 
 Python binding of the C ABI in include/ss.h (argument marshalling only: every
 step of the solve runs in the HIP library libss.so).  The library must have
-been built (python -m paper_1504_06768_amd.build); importing this package
+been built (python paper_1504_06768_amd/build.py); importing this package
 fails loudly otherwise.
 """
 from .ss import (  # noqa: F401
     SS_FP64, SS_MIXED, SS_ILU0, SS_ILUT, SS_ORDER_RCM, SS_ORDER_NATURAL,
     SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES,
     SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM,
-    SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE,
+    SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE, SS_OP_PRECOND_SYNCFREE,
     SolverError, Liouvillian, Server, apply, bandwidth_profile, build_liouvillian,
     export_csr, export_perm, library_path, options, prepare, solve, time_operator, version,
 )

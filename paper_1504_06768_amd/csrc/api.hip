@@ -192,7 +192,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && x != nullptr && y != nullptr, SS_E_INVALID_ARG, "null argument");
         SS_REQUIRE(prec == SS_FP64 || prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
-        SS_REQUIRE(op >= 0 && op <= 4, SS_E_INVALID_ARG, "unknown operator");
+        SS_REQUIRE(op >= 0 && op <= 5, SS_E_INVALID_ARG, "unknown operator");
         SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
         SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
                    "complex64 operators exist only after a mixed-precision ss_prepare");
@@ -211,7 +211,8 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<double2> M;
                 M.setup(&L->LU, L->lu_diag.get(), n, s);
-                if (op == SS_OP_PRECOND) M.apply(xd.get(), yd.get(), s);
+                if (op == SS_OP_PRECOND) M.use_levels(L->LU.view(), s);
+                if (op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE) M.apply(xd.get(), yd.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xd.get(), yd.get(), s);
                 else M.upper(xd.get(), yd.get(), s);
                 SS_REQUIRE(!(M.read_status(s) & ss::STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve timed out");
@@ -225,7 +226,8 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<float2> M;
                 M.setup(&L->LU32, L->lu_diag.get(), n, s);
-                if (op == SS_OP_PRECOND) M.apply(xf.get(), yf.get(), s);
+                if (op == SS_OP_PRECOND) M.use_levels(L->LU.view(), s);
+                if (op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE) M.apply(xf.get(), yf.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xf.get(), yf.get(), s);
                 else M.upper(xf.get(), yf.get(), s);
                 SS_REQUIRE(!(M.read_status(s) & ss::STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve timed out");
@@ -242,7 +244,8 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
 int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double *avg_ms) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && avg_ms != nullptr && reps > 0, SS_E_INVALID_ARG, "bad argument");
-        SS_REQUIRE(op == SS_OP_SPMV_L || op == SS_OP_SPMV_APERM || op == SS_OP_PRECOND, SS_E_INVALID_ARG,
+        const bool pre = op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE;
+        SS_REQUIRE(op == SS_OP_SPMV_L || op == SS_OP_SPMV_APERM || pre, SS_E_INVALID_ARG,
                    "operator cannot be timed");
         SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
         SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
@@ -270,11 +273,12 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
                 LU = &L->LU32;
             }
             ss::Precond<T> M;
-            if (op == SS_OP_PRECOND) M.setup(LU, L->lu_diag.get(), n, s);
+            if (pre) M.setup(LU, L->lu_diag.get(), n, s);
+            if (op == SS_OP_PRECOND) M.use_levels(L->LU.view(), s);
             const ss::Csr<T> Av = A->view();
             const int g = ss::spmv_group(Av.n, Av.nnz);
             auto once = [&]() {
-                if (op == SS_OP_PRECOND) M.apply(x.get(), y.get(), s);
+                if (pre) M.apply(x.get(), y.get(), s);
                 else ss::spmv<T>(Av, x.get(), y.get(), g, s);
             };
             once();  // warm-up

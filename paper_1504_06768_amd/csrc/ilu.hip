@@ -285,8 +285,26 @@ void Precond<T>::setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s
 }
 
 template <typename T>
+void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s) {
+    build_levels(lu64, diag, lo, up, s);
+    pack_side<T>(lo, LU->view(), false, pl, s);
+    pack_side<T>(up, LU->view(), true, pu, s);
+    bl.resize((size_t)std::max(n, 1));
+    block = true;
+}
+
+template <typename T>
 void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
     if (n == 0) return;
+    if (block) {
+        BlockPrecond<T> B;
+        B.lo = &lo;
+        B.up = &up;
+        B.pl = &pl;
+        B.pu = &pu;
+        precond_block<T>(B, LU->view(), b, out, bl.get(), s, skip);
+        return;
+    }
     const unsigned grid = (unsigned)div_up(n, TRSV_BS);
     k_trsv_lower<T><<<grid, TRSV_BS, 0, s>>>(n, LU->rowptr.get(), LU->col.get(), LU->val.get(), diag, b, y.get(),
                                               out, counter.ctr.get(), counter.take(grid), status.get(), skip);

@@ -2,6 +2,7 @@
 #pragma once
 #include "ss_internal.hpp"
 #include "syncfree.hpp"
+#include "levels.hpp"
 
 namespace ss {
 
@@ -36,7 +37,16 @@ struct Precond {
     DevBuf<T> y;           // lower-solve result, kept at the sentinel between applies
     DevBuf<unsigned> status;
     BlockCounter counter;
+    // level-scheduled single-workgroup mode (apply() uses it once built)
+    bool block = false;
+    LevelSched lo, up;
+    PackedSide<T> pl, pu;
+    DevBuf<T> bl;
     void setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s);
+    // Build the level schedules (from the fp64 factors' pattern, which the
+    // rounded copy shares) and packed factors, and switch apply() to the
+    // single-workgroup level-scheduled solve.
+    void use_levels(const Csr<double2> &lu64, hipStream_t s);
     // out = (LU)^-1 b; out must not alias b or y.  When *skip != 0 on the
     // device, both solves return at once (used after convergence).
     void apply(const T *b, T *out, hipStream_t s, const int *skip = nullptr);

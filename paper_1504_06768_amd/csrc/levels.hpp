@@ -1,0 +1,58 @@
+// Level schedules of the ILU triangular factors and their packed level-order
+// copies (wgsolve.hip), shared by the workgroup-resident solver and the
+// single-workgroup triangular solves of the device-wide path.
+#pragma once
+#include "ss_internal.hpp"
+
+namespace ss {
+
+// Level schedule of one triangular factor: slots in level order, each slot
+// {row, first entry, end entry, 0}; levels delimited by ptr.
+struct LevelSched {
+    int nlev = 0;
+    DevBuf<int> ptr;    // nlev + 1
+    DevBuf<int4> slot;  // n
+};
+
+// Level sets of the strict lower part (forward) and of the strict upper part
+// (backward) of the ILU factors; a row's level is one more than the largest
+// level among the rows it depends on.
+void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s);
+
+// factor entries per row kept in the packed level layout (fewer for
+// complex128 so that three levels of them fit in registers)
+template <typename T> struct WgK;
+template <> struct WgK<float2> { static constexpr int value = 8; };
+template <> struct WgK<double2> { static constexpr int value = 4; };
+
+// Level-ordered packed copy of one triangular factor in precision T: for
+// slot idx (level order), slot[idx] = {row, first CSR entry, length, 0}, and
+// the first WgK<T> column indices and values of the row at
+// col[k * n + idx], val[k * n + idx] (zero padded); aux[idx] is the pivot
+// u_ii for the upper factor.  Every load of a slot is addressed by idx alone.
+template <typename T>
+struct PackedSide {
+    DevBuf<int4> slot;
+    DevBuf<int> col;
+    DevBuf<T> val;
+    DevBuf<T> aux;
+};
+
+template <typename T>
+void pack_side(const LevelSched &ls, const Csr<T> &LU, bool upper, PackedSide<T> &out, hipStream_t s);
+
+// Level schedules and packed factors for the single-workgroup triangular
+// solve pair of the device-wide path.
+template <typename T>
+struct BlockPrecond {
+    const LevelSched *lo = nullptr, *up = nullptr;
+    const PackedSide<T> *pl = nullptr, *pu = nullptr;
+};
+
+// out = (L U)^-1 b in one workgroup (bl: n scratch); returns at once when
+// *skip != 0 on the device.
+template <typename T>
+void precond_block(const BlockPrecond<T> &B, const Csr<T> &LU, const T *b, T *out, T *bl, hipStream_t s,
+                   const int *skip);
+
+}  // namespace ss

@@ -411,6 +411,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
     if (!done_wg) {
         Precond<T> M;
         M.setup(&LUin, h->lu_diag.get(), n, s);
+        if (!(o.flags & SS_FLAG_SYNCFREE)) M.use_levels(h->LU.view(), s);
         Krylov<T> K;
         K.init(Ain.view(), &M, s);
         const Csr<double2> A64 = h->Ap.view();

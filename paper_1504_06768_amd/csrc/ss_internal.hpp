@@ -166,7 +166,7 @@ bool is_device_ptr(const void *p);
 
 // ----------------------------------------------- device-wide bounded waits
 // Device status word bits, set by kernels, read by the host after a solve.
-enum : unsigned { STATUS_SPIN_TIMEOUT = 1u, STATUS_ZERO_PIVOT = 2u };
+enum : unsigned { STATUS_SPIN_TIMEOUT = 1u, STATUS_ZERO_PIVOT = 2u, STATUS_OVERFLOW = 4u };
 
 // Large enough that a healthy dependency wait never reaches it, small enough
 // that a broken one ends in seconds.

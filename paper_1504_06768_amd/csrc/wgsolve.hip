@@ -502,6 +502,55 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
     return st;
 }
 
+// ============================================ single-workgroup (L U)^-1
+// Triangular solve pair of a large system in one workgroup: levels are
+// separated by workgroup barriers and the solution vector stays in global
+// memory (cache resident), so a level costs a barrier plus an L2 round trip
+// instead of the cross-device handshakes of the sync-free kernels.
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_precond_block(int n, int nlev_l, const int *lptr, const int4 *lslot,
+                                                      const int *lcol, const T *lval, int nlev_u, const int *uptr,
+                                                      const int4 *uslot, const int *ucol, const T *uval,
+                                                      const T *uaux, const int *col, const T *val, const T *b,
+                                                      T *bl, T *out, const int *skip) {
+    if (skip && *skip) return;
+    for (int idx = threadIdx.x; idx < n; idx += BS) bl[idx] = b[lslot[idx].x];
+    __syncthreads();
+    for (int lev = 0; lev < nlev_l; ++lev) {
+        const int p0 = lptr[lev], p1 = lptr[lev + 1];
+        for (int idx = p0 + threadIdx.x; idx < p1; idx += BS) {
+            SlotRegs<T> q;
+            fetch_slot<T, false>(q, idx, p1, n, lslot, lcol, lval, bl);
+            solve_regs<T, false>(q, col, val, out);
+        }
+        __syncthreads();
+    }
+    for (int lev = 0; lev < nlev_u; ++lev) {
+        const int p0 = uptr[lev], p1 = uptr[lev + 1];
+        for (int idx = p0 + threadIdx.x; idx < p1; idx += BS) {
+            SlotRegs<T> q;
+            fetch_slot<T, true>(q, idx, p1, n, uslot, ucol, uval, uaux);
+            solve_regs<T, true>(q, col, val, out);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+void precond_block(const BlockPrecond<T> &B, const Csr<T> &LU, const T *b, T *out, T *bl, hipStream_t s,
+                   const int *skip) {
+    if (LU.n == 0) return;
+    k_precond_block<T, 1024><<<1, 1024, 0, s>>>(LU.n, B.lo->nlev, B.lo->ptr.get(), B.pl->slot.get(),
+                                                  B.pl->col.get(), B.pl->val.get(), B.up->nlev, B.up->ptr.get(),
+                                                  B.pu->slot.get(), B.pu->col.get(), B.pu->val.get(),
+                                                  B.pu->aux.get(), LU.col, LU.val, b, bl, out, skip);
+    SS_HIP(hipGetLastError());
+}
+template void precond_block<double2>(const BlockPrecond<double2> &, const Csr<double2> &, const double2 *,
+                                     double2 *, double2 *, hipStream_t, const int *);
+template void precond_block<float2>(const BlockPrecond<float2> &, const Csr<float2> &, const float2 *, float2 *,
+                                    float2 *, hipStream_t, const int *);
+
 // ================================================== the solve kernel
 template <typename T, int BS, bool LDSY>
 __global__ void __launch_bounds__(BS) k_wg_solve(const WgProblem<T> *probs) {

@@ -3,22 +3,9 @@
 // system run inside one workgroup, with the triangular-solve vector in LDS.
 #pragma once
 #include "blas.hpp"
-#include "ilu.hpp"
+#include "levels.hpp"
 
 namespace ss {
-
-// Level schedule of one triangular factor: slots in level order, each slot
-// {row, first entry, end entry, 0}; levels delimited by ptr.
-struct LevelSched {
-    int nlev = 0;
-    DevBuf<int> ptr;    // nlev + 1
-    DevBuf<int4> slot;  // n
-};
-
-// Level sets of the strict lower part (forward) and of the strict upper part
-// (backward) of the ILU factors; a row's level is one more than the largest
-// level among the rows it depends on.
-void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s);
 
 // Outcome of a workgroup solve (device struct, one per system).
 struct WgResult {
@@ -31,28 +18,6 @@ struct WgResult {
     long long ticks_spmv;     // the triangular solves, the SpMVs and the
     long long ticks_total;    // whole kernel, measured by thread 0
 };
-
-// factor entries per row kept in the packed level layout (fewer for
-// complex128 so that three levels of them fit in registers)
-template <typename T> struct WgK;
-template <> struct WgK<float2> { static constexpr int value = 8; };
-template <> struct WgK<double2> { static constexpr int value = 4; };
-
-// Level-ordered packed copy of one triangular factor in precision T: for
-// slot idx (level order), slot[idx] = {row, first CSR entry, length, 0}, and
-// the first WgK<T> column indices and values of the row at
-// col[k * n + idx], val[k * n + idx] (zero padded); aux[idx] is the pivot
-// u_ii for the upper factor.  Every load of a slot is addressed by idx alone.
-template <typename T>
-struct PackedSide {
-    DevBuf<int4> slot;
-    DevBuf<int> col;
-    DevBuf<T> val;
-    DevBuf<T> aux;
-};
-
-template <typename T>
-void pack_side(const LevelSched &ls, const Csr<T> &LU, bool upper, PackedSide<T> &out, hipStream_t s);
 
 template <typename T>
 struct WgProblem {

@@ -26,8 +26,10 @@ SS_FP64, SS_MIXED = 0, 1
 SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
+SS_FLAG_SYNCFREE = 16
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
+SS_OP_PRECOND_SYNCFREE = 5
 
 METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3}
 PRECS = {"fp64": 0, "mixed": 1}
@@ -162,7 +164,7 @@ def _ptr(x) -> int:
 
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
-            no_fallback=False, trace_row=-1, path="auto") -> _Options:
+            no_fallback=False, trace_row=-1, path="auto", trsv="auto") -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -173,6 +175,7 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     o.trace_row = int(trace_row)
     o.flags = (SS_FLAG_HERMITIZE if hermitize else 0) | (SS_FLAG_NO_FALLBACK if no_fallback else 0)
     o.flags |= {"auto": 0, "device": SS_FLAG_DEVICE_WIDE, "workgroup": SS_FLAG_WORKGROUP}[path]
+    o.flags |= {"auto": 0, "level": 0, "syncfree": SS_FLAG_SYNCFREE}[trsv]
     return o
 
 

@@ -24,7 +24,9 @@ from oracle.steady import steady_state_dense
 
 pytestmark = pytest.mark.gpu
 
-ssl = pytest.importorskip("paper_1504_06768_amd")
+from conftest import load_product
+
+ssl = load_product()
 
 
 def _say(*a):
@@ -195,9 +197,10 @@ def test_spmv_and_triangular_solves(name):
     yu = ssl.apply(L, ssl.SS_OP_USOLVE, x)
     refu = spsolve_triangular(Uf, x, lower=False)
     assert np.max(np.abs(yu - refu)) <= 1e-11 * np.max(np.abs(refu))
-    yp = ssl.apply(L, ssl.SS_OP_PRECOND, x)
     refp = spsolve_triangular(Uf, refl, lower=False)
-    assert np.max(np.abs(yp - refp)) <= 1e-11 * np.max(np.abs(refp))
+    for op in (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE):
+        yp = ssl.apply(L, op, x)
+        assert np.max(np.abs(yp - refp)) <= 1e-11 * np.max(np.abs(refp))
 
 
 def test_mixed_precision_operators():
@@ -210,9 +213,27 @@ def test_mixed_precision_operators():
     ref = Ap @ x
     assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
     Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
-    yp = ssl.apply(L, ssl.SS_OP_PRECOND, x, prec="mixed")
     refp = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
-    assert np.max(np.abs(yp - refp)) <= 1e-4 * np.max(np.abs(refp))
+    for op in (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE):
+        yp = ssl.apply(L, op, x, prec="mixed")
+        assert np.max(np.abs(yp - refp)) <= 1e-4 * np.max(np.abs(refp))
+
+
+@pytest.mark.parametrize("k,prec,tol", [(2, "fp64", 1e-11), (2, "mixed", 1e-4), (4, "fp64", 1e-11),
+                                        (4, "mixed", 1e-4)])
+def test_level_scheduled_precond_on_workloads(k, prec, tol):
+    """The single-workgroup level-scheduled (LU)^-1 on the workload matrices:
+    factor rows longer than the packed width, levels wider than the
+    workgroup (Kerr chain, n = 10^6)."""
+    s = qs.config(k)
+    _say("precond", k, prec)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "invpow_bicgstab" if k == 4 else "trace_bicgstab", prec=prec)
+    Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
+    x = np.random.default_rng(3).normal(size=Lf.shape[0]) + 0j
+    refp = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
+    yp = ssl.apply(L, ssl.SS_OP_PRECOND, x, prec=prec)
+    assert np.max(np.abs(yp - refp)) <= tol * np.max(np.abs(refp))
 
 
 # ------------------------------------------------------------ end to end
@@ -226,7 +247,8 @@ CASES = [(name, m) for name in ["kerr20", "jc8", "random7", "opto3x5"] for m in 
 CASES += [("spin3", "invpow_bicgstab"), ("spin3", "invpow_gmres")]
 
 
-CASES = [(n, m, p) for (n, m) in CASES for p in (["device", "workgroup"] if "bicgstab" in m else ["device"])]
+CASES = [(n, m, p) for (n, m) in CASES
+         for p in (["device", "device_syncfree", "workgroup"] if "bicgstab" in m else ["device", "device_syncfree"])]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
@@ -238,7 +260,9 @@ def test_steady_state_matches_dense_oracle(name, method, path, prec, tol):
     _say("solve", name, method, path, prec)
     ref = steady_state_dense(s.H, s.c_ops)
     L = ssl.build_liouvillian(s.H, s.c_ops)
-    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False, path=path)
+    trsv = "syncfree" if path == "device_syncfree" else "level"
+    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False, path=path.split("_")[0],
+                          trsv=trsv)
     _say("   info", info)
     assert info["status"] == 0
     err = np.max(np.abs(rho - ref))

@@ -11,7 +11,9 @@ import qsystems as qs
 from oracle.steady import steady_state_dense
 
 pytestmark = pytest.mark.gpu
-ssl = pytest.importorskip("paper_1504_06768_amd")
+from conftest import load_product
+
+ssl = load_product()
 
 
 def _say(*a):
