@@ -123,9 +123,14 @@ typedef struct {
                                   per step, all CUs) even for small systems   */
 #define SS_FLAG_WORKGROUP   8  /* force the workgroup-resident solve (whole
                                   BiCGSTAB solve in one workgroup)            */
-#define SS_FLAG_SYNCFREE   16  /* device-wide path: sync-free triangular
-                                  solves over all CUs instead of the level-
-                                  scheduled single-workgroup solve            */
+#define SS_FLAG_SYNCFREE   16  /* device-wide path: triangular solves
+                                  sync-free over all CUs in row order         */
+#define SS_FLAG_TRSV_BLOCK 32  /* device-wide path: triangular solves in one
+                                  workgroup, level by level                   */
+#define SS_FLAG_TRSV_LEVELS 64 /* device-wide path: triangular solves
+                                  sync-free over all CUs in level order
+                                  (default: BLOCK up to n = 65536, else
+                                  LEVELS)                                     */
 
 typedef struct {
     int32_t status;          /* the call's return code                        */
@@ -204,11 +209,16 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
 #define SS_OP_SPMV_L      0  /* y = L x          (natural order, fp64)         */
 #define SS_OP_SPMV_APERM  1  /* y = (P A P^T) x  (prec selects c128 / c64)     */
 #define SS_OP_PRECOND     2  /* y = (LU)^-1 x    (prec selects c128 / c64),
-                                level-scheduled single-workgroup solves    */
+                                the solver's own choice of the ways below:
+                                BLOCK up to n = 65536, LEVELS above        */
 #define SS_OP_LSOLVE      3  /* y = L_f^-1 x     unit lower factor             */
 #define SS_OP_USOLVE      4  /* y = U_f^-1 x     upper factor                  */
-#define SS_OP_PRECOND_SYNCFREE 5 /* y = (LU)^-1 x by the sync-free solves over
-                                    all CUs (same result up to rounding)   */
+#define SS_OP_PRECOND_SYNCFREE 5 /* y = (LU)^-1 x, sync-free solves over all
+                                    CUs in row order                       */
+#define SS_OP_PRECOND_BLOCK    6 /* y = (LU)^-1 x, one workgroup stepping
+                                    through the level schedule             */
+#define SS_OP_PRECOND_LEVELS   7 /* y = (LU)^-1 x, sync-free solves over all
+                                    CUs in level order                     */
 
 /* Apply one operator of the prepared handle to x (n complex, host or
  * device) giving y (n complex, host or device).  prec = SS_FP64 or SS_MIXED:
@@ -217,8 +227,8 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
 int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
 
 /* Time `reps` back-to-back applications of an operator of the prepared
- * handle (SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND or
- * SS_OP_PRECOND_SYNCFREE; prec as in
+ * handle (SS_OP_SPMV_L, SS_OP_SPMV_APERM or one of the SS_OP_PRECOND*
+ * operators; prec as in
  * ss_apply) on the handle's stream, bracketed by HIP events; *avg_ms
  * receives the mean time per application.  Input and output vectors are
  * library-owned device scratch.  Used to measure achieved bandwidth. */

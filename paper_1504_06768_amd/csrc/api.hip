@@ -188,11 +188,21 @@ int ss_bandwidth_profile(ss_liouv L, int32_t which, int64_t *B, int64_t *P) {
     });
 }
 
+static bool is_precond_op(int op) {
+    return op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE || op == SS_OP_PRECOND_BLOCK ||
+           op == SS_OP_PRECOND_LEVELS;
+}
+
+static int precond_mode(int op) {
+    return op == SS_OP_PRECOND_BLOCK ? ss::PRE_BLOCK : op == SS_OP_PRECOND_LEVELS ? ss::PRE_LEVELS : ss::PRE_AUTO;
+}
+
 int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && x != nullptr && y != nullptr, SS_E_INVALID_ARG, "null argument");
         SS_REQUIRE(prec == SS_FP64 || prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
-        SS_REQUIRE(op >= 0 && op <= 5, SS_E_INVALID_ARG, "unknown operator");
+        SS_REQUIRE(op >= 0 && op <= 7, SS_E_INVALID_ARG, "unknown operator");
+        const bool pre = is_precond_op(op);
         SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
         SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
                    "complex64 operators exist only after a mixed-precision ss_prepare");
@@ -211,8 +221,8 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<double2> M;
                 M.setup(&L->LU, L->lu_diag.get(), n, s);
-                if (op == SS_OP_PRECOND) M.use_levels(L->LU.view(), s);
-                if (op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE) M.apply(xd.get(), yd.get(), s);
+                if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op));
+                if (pre) M.apply(xd.get(), yd.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xd.get(), yd.get(), s);
                 else M.upper(xd.get(), yd.get(), s);
                 SS_REQUIRE(!(M.read_status(s) & ss::STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve timed out");
@@ -226,8 +236,8 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<float2> M;
                 M.setup(&L->LU32, L->lu_diag.get(), n, s);
-                if (op == SS_OP_PRECOND) M.use_levels(L->LU.view(), s);
-                if (op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE) M.apply(xf.get(), yf.get(), s);
+                if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op));
+                if (pre) M.apply(xf.get(), yf.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xf.get(), yf.get(), s);
                 else M.upper(xf.get(), yf.get(), s);
                 SS_REQUIRE(!(M.read_status(s) & ss::STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "triangular solve timed out");
@@ -244,7 +254,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
 int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double *avg_ms) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && avg_ms != nullptr && reps > 0, SS_E_INVALID_ARG, "bad argument");
-        const bool pre = op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE;
+        const bool pre = is_precond_op(op);
         SS_REQUIRE(op == SS_OP_SPMV_L || op == SS_OP_SPMV_APERM || pre, SS_E_INVALID_ARG,
                    "operator cannot be timed");
         SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
@@ -274,7 +284,7 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             }
             ss::Precond<T> M;
             if (pre) M.setup(LU, L->lu_diag.get(), n, s);
-            if (op == SS_OP_PRECOND) M.use_levels(L->LU.view(), s);
+            if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op));
             const ss::Csr<T> Av = A->view();
             const int g = ss::spmv_group(Av.n, Av.nnz);
             auto once = [&]() {

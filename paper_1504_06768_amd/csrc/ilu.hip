@@ -284,25 +284,178 @@ void Precond<T>::setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s
     counter.init(s);
 }
 
+// Sync-free triangular solve in level order over the packed level layout
+// (rows sorted by level): a persistent set of wavefronts takes chunks of 64
+// consecutive slots in increasing order from an atomic counter, so the rows
+// of a chunk belong to one or two adjacent levels and every row a chunk
+// waits on lies in an earlier chunk already taken by a running wavefront.
+// Keeping only ~1k wavefronts in flight (instead of one thread per row)
+// keeps the polling traffic from crowding out the loads that make progress.
+// The first WgK<T> entries of a row come coalesced from the packed copy, the
+// rest from the CSR factor; entries are consumed in CSR order
+// (deterministic rounding), each pass issuing the loads of every pending
+// packed entry at once.
+constexpr int LEV_WAVES_PER_BLOCK = 4;
+constexpr int LEV_MAX_WAVES = 1024;
+
+template <typename T, bool UPPER>
+__global__ void __launch_bounds__(LEV_WAVES_PER_BLOCK * 64)
+    k_trsv_slots(int n, const int4 *slot, const int *pcol, const T *pval, const T *aux, const int *col,
+                 const T *val, T *in, T *out, T *reset, unsigned *ctr, unsigned nwaves, unsigned *status,
+                 const int *skip) {
+    constexpr int K = WgK<T>::value;
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned chunk = 0;
+        if (lane == 0) chunk = atomicAdd(ctr, 1u);
+        chunk = __shfl(chunk, 0, 64);
+        if ((long long)chunk * 64 >= n) {
+            // the last wavefront out resets both counters for the next launch
+            if (lane == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (atomicAdd(ctr + 1, 1u) == nwaves - 1) {
+                    __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            break;
+        }
+        const int idx = (int)chunk * 64 + lane;
+        const bool active = idx < n;
+        int row = 0, start = 0, len = 0;
+        int c[K];
+        T v[K];
+        T acc = czero<T>(), piv = czero<T>();
+        if (active) {
+            const int4 sl = slot[idx];
+            row = sl.x;
+            start = sl.y;
+            len = sl.z;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                c[k] = pcol[(size_t)k * n + idx];
+                v[k] = pval[(size_t)k * n + idx];
+            }
+            acc = in[row];
+            if (UPPER) {
+                piv = aux[idx];
+                set_sentinel(in + row);  // the lower result goes back to the sentinel
+            }
+            if (reset) set_sentinel(reset + row);
+        }
+        int q = 0;  // entries consumed
+        bool done = !active;
+        unsigned spins = 0;
+        while (true) {
+            if (!done) {
+                int used = 0;
+                if (q < K) {
+                    T y[K];
+                    bool ok[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        ok[k] = false;
+                        if (k >= q && k < len) ok[k] = try_load(out + c[k], y[k]);
+                    }
+                    bool run = true;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        if (k >= q && k < len) {
+                            if (run && ok[k]) {
+                                acc = csub(acc, cmul(v[k], y[k]));
+                                ++used;
+                            } else {
+                                run = false;
+                            }
+                        }
+                    }
+                } else {
+                    T y[TRSV_BATCH];
+                    bool ok[TRSV_BATCH];
+#pragma unroll
+                    for (int b = 0; b < TRSV_BATCH; ++b) {
+                        ok[b] = false;
+                        if (q + b < len) ok[b] = try_load(out + col[start + q + b], y[b]);
+                    }
+                    bool run = true;
+#pragma unroll
+                    for (int b = 0; b < TRSV_BATCH; ++b) {
+                        if (run && q + b < len && ok[b]) {
+                            acc = csub(acc, cmul(val[start + q + b], y[b]));
+                            ++used;
+                        } else {
+                            run = false;
+                        }
+                    }
+                }
+                q += used;
+                if (used) {
+                    spins = 0;
+                } else if (q < len) {
+                    ++spins;
+                    if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(status))) {
+                        atomicOr(status, STATUS_SPIN_TIMEOUT);
+                        q = len;
+                    }
+                }
+                if (q >= len) {
+                    publish(out + row, UPPER ? cdiv(acc, piv) : acc);
+                    done = true;
+                }
+            }
+            if (__all(done)) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+// workgroups of one level-order solve
+inline unsigned slots_blocks(int n) {
+    const long long chunks = (n + 63) / 64;
+    const long long waves = std::min<long long>(chunks, LEV_MAX_WAVES);
+    return (unsigned)((waves + LEV_WAVES_PER_BLOCK - 1) / LEV_WAVES_PER_BLOCK);
+}
+
 template <typename T>
-void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s) {
+void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s, int m) {
     build_levels(lu64, diag, lo, up, s);
     pack_side<T>(lo, LU->view(), false, pl, s);
     pack_side<T>(up, LU->view(), true, pu, s);
-    bl.resize((size_t)std::max(n, 1));
-    block = true;
+    if (m == PRE_AUTO) m = (n <= PRE_BLOCK_MAX_N) ? PRE_BLOCK : PRE_LEVELS;
+    if (m == PRE_BLOCK) bl.resize((size_t)std::max(n, 1));
+    if (m == PRE_LEVELS) {
+        lev_ctr.resize(2);
+        SS_HIP(hipMemsetAsync(lev_ctr.get(), 0, 2 * sizeof(unsigned), s));
+    }
+    mode = m;
 }
 
 template <typename T>
 void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
     if (n == 0) return;
-    if (block) {
+    if (mode == PRE_BLOCK) {
         BlockPrecond<T> B;
         B.lo = &lo;
         B.up = &up;
         B.pl = &pl;
         B.pu = &pu;
         precond_block<T>(B, LU->view(), b, out, bl.get(), s, skip);
+        return;
+    }
+    if (mode == PRE_LEVELS) {
+        const unsigned blocks = slots_blocks(n);
+        const unsigned bs = LEV_WAVES_PER_BLOCK * 64, nwaves = blocks * LEV_WAVES_PER_BLOCK;
+        // y holds the sentinel between applies; the lower solve reads b
+        // through `in` without modifying it (reset = out prepares the upper).
+        // The chunk counters return to zero at the end of each launch.
+        k_trsv_slots<T, false><<<blocks, bs, 0, s>>>(n, pl.slot.get(), pl.col.get(), pl.val.get(), nullptr,
+                                                     LU->col.get(), LU->val.get(), const_cast<T *>(b), y.get(),
+                                                     out, lev_ctr.get(), nwaves, status.get(), skip);
+        k_trsv_slots<T, true><<<blocks, bs, 0, s>>>(n, pu.slot.get(), pu.col.get(), pu.val.get(), pu.aux.get(),
+                                                    LU->col.get(), LU->val.get(), y.get(), out, nullptr,
+                                                    lev_ctr.get(), nwaves, status.get(), skip);
+        SS_HIP(hipGetLastError());
         return;
     }
     const unsigned grid = (unsigned)div_up(n, TRSV_BS);

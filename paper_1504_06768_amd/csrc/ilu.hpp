@@ -28,6 +28,12 @@ void fill_sentinel(int64_t n, T *p, hipStream_t s);
 
 void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s);
 
+// Ways of applying (L U)^-1: sync-free in row order over all CUs, one
+// workgroup stepping through the levels, sync-free in level order over all
+// CUs, or the choice by size.
+enum : int { PRE_ROWS = 0, PRE_BLOCK = 1, PRE_LEVELS = 2, PRE_AUTO = 3 };
+constexpr int PRE_BLOCK_MAX_N = 65536;
+
 // M^-1 = (L U)^-1 applied with the sync-free triangular solves.
 template <typename T>
 struct Precond {
@@ -37,16 +43,19 @@ struct Precond {
     DevBuf<T> y;           // lower-solve result, kept at the sentinel between applies
     DevBuf<unsigned> status;
     BlockCounter counter;
-    // level-scheduled single-workgroup mode (apply() uses it once built)
-    bool block = false;
+    // level-scheduled modes (apply() uses them once built)
+    int mode = PRE_ROWS;
     LevelSched lo, up;
     PackedSide<T> pl, pu;
     DevBuf<T> bl;
+    DevBuf<unsigned> lev_ctr;  // chunk counter and finished-wavefront counter (PRE_LEVELS)
     void setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s);
     // Build the level schedules (from the fp64 factors' pattern, which the
-    // rounded copy shares) and packed factors, and switch apply() to the
-    // single-workgroup level-scheduled solve.
-    void use_levels(const Csr<double2> &lu64, hipStream_t s);
+    // rounded copy shares) and packed factors, and switch apply() to a
+    // level-scheduled solve: PRE_BLOCK (one workgroup, barrier per level),
+    // PRE_LEVELS (sync-free over all CUs in level order) or PRE_AUTO (the
+    // first for n <= PRE_BLOCK_MAX_N).
+    void use_levels(const Csr<double2> &lu64, hipStream_t s, int m = PRE_AUTO);
     // out = (LU)^-1 b; out must not alias b or y.  When *skip != 0 on the
     // device, both solves return at once (used after convergence).
     void apply(const T *b, T *out, hipStream_t s, const int *skip = nullptr);

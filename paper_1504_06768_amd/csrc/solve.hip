@@ -411,7 +411,12 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
     if (!done_wg) {
         Precond<T> M;
         M.setup(&LUin, h->lu_diag.get(), n, s);
-        if (!(o.flags & SS_FLAG_SYNCFREE)) M.use_levels(h->LU.view(), s);
+        if (!(o.flags & SS_FLAG_SYNCFREE)) {
+            const int mode = (o.flags & SS_FLAG_TRSV_BLOCK)    ? PRE_BLOCK
+                             : (o.flags & SS_FLAG_TRSV_LEVELS) ? PRE_LEVELS
+                                                               : PRE_AUTO;
+            M.use_levels(h->LU.view(), s, mode);
+        }
         Krylov<T> K;
         K.init(Ain.view(), &M, s);
         const Csr<double2> A64 = h->Ap.view();

@@ -176,6 +176,8 @@ def test_ilu0_property_on_jc40():
 
 
 # ------------------------------------------------------------ SpMV / trsv
+PRECOND_OPS = (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE, ssl.SS_OP_PRECOND_BLOCK, ssl.SS_OP_PRECOND_LEVELS)
+
 @pytest.mark.parametrize("name", ["kerr20", "jc8", "spin3"])
 def test_spmv_and_triangular_solves(name):
     s = SMALL[name]()
@@ -198,7 +200,7 @@ def test_spmv_and_triangular_solves(name):
     refu = spsolve_triangular(Uf, x, lower=False)
     assert np.max(np.abs(yu - refu)) <= 1e-11 * np.max(np.abs(refu))
     refp = spsolve_triangular(Uf, refl, lower=False)
-    for op in (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE):
+    for op in PRECOND_OPS:
         yp = ssl.apply(L, op, x)
         assert np.max(np.abs(yp - refp)) <= 1e-11 * np.max(np.abs(refp))
 
@@ -214,7 +216,7 @@ def test_mixed_precision_operators():
     assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
     Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
     refp = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
-    for op in (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE):
+    for op in PRECOND_OPS:
         yp = ssl.apply(L, op, x, prec="mixed")
         assert np.max(np.abs(yp - refp)) <= 1e-4 * np.max(np.abs(refp))
 
@@ -232,8 +234,10 @@ def test_level_scheduled_precond_on_workloads(k, prec, tol):
     Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
     x = np.random.default_rng(3).normal(size=Lf.shape[0]) + 0j
     refp = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
-    yp = ssl.apply(L, ssl.SS_OP_PRECOND, x, prec=prec)
-    assert np.max(np.abs(yp - refp)) <= tol * np.max(np.abs(refp))
+    for op in PRECOND_OPS:
+        _say("   op", op)
+        yp = ssl.apply(L, op, x, prec=prec)
+        assert np.max(np.abs(yp - refp)) <= tol * np.max(np.abs(refp))
 
 
 # ------------------------------------------------------------ end to end
@@ -247,8 +251,8 @@ CASES = [(name, m) for name in ["kerr20", "jc8", "random7", "opto3x5"] for m in 
 CASES += [("spin3", "invpow_bicgstab"), ("spin3", "invpow_gmres")]
 
 
-CASES = [(n, m, p) for (n, m) in CASES
-         for p in (["device", "device_syncfree", "workgroup"] if "bicgstab" in m else ["device", "device_syncfree"])]
+DEVICE_PATHS = ["device", "device_syncfree", "device_levels"]
+CASES = [(n, m, p) for (n, m) in CASES for p in DEVICE_PATHS + (["workgroup"] if "bicgstab" in m else [])]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
@@ -260,7 +264,7 @@ def test_steady_state_matches_dense_oracle(name, method, path, prec, tol):
     _say("solve", name, method, path, prec)
     ref = steady_state_dense(s.H, s.c_ops)
     L = ssl.build_liouvillian(s.H, s.c_ops)
-    trsv = "syncfree" if path == "device_syncfree" else "level"
+    trsv = path.split("_")[1] if "_" in path else "auto"
     rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False, path=path.split("_")[0],
                           trsv=trsv)
     _say("   info", info)
