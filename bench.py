@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -54,6 +56,64 @@ def trsv_pair_bytes(n, nnz_lu, s):
     return nnz_lu * (s + 4) + 8 * (n + 1) + 8 * n + 4 * n * s
 
 
+def _run_stream(ssl, systems, arrivals, prec):
+    """Submit each request at its arrival time, poll until all are done;
+    returns (wall seconds, latencies in ms, {index: (rho, info)} for all)."""
+    S = ssl.Server(hbm_budget_bytes=32 << 30, max_slots=1024)
+    pending, lat, res = {}, [], {}
+    nxt = 0
+    t0 = time.perf_counter()
+    while nxt < len(systems) or pending:
+        now = time.perf_counter() - t0
+        while nxt < len(systems) and arrivals[nxt] <= now:
+            s = systems[nxt]
+            pending[S.submit(s.H, s.c_ops, "trace_bicgstab", 1e-10, prec=prec)] = (nxt, time.perf_counter())
+            nxt += 1
+        for t in list(pending):
+            r = S.poll(t)
+            if r is not None:
+                i, ts = pending.pop(t)
+                lat.append(1e3 * (time.perf_counter() - ts))
+                res[i] = r
+        time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    S.close()
+    return wall, np.asarray(lat), res
+
+
+def serve_stream(ssl, qs, np_, n_requests):
+    """Serving stream of Kerr requests (cutoff N ~ U{10..60}, (Delta, E) on
+    a 21 x 20 grid, seed 1): burst capacity (all arrive at t = 0) in both
+    precisions, then Poisson arrivals at half the mixed capacity; p50/p99 of
+    submit-to-result latency; a sample checked against the dense oracle."""
+    from oracle.steady import steady_state_dense
+    stream = qs.serving_stream(n_requests, rate=0.0, seed=1)
+    systems = [qs.kerr(N, delta=dl, E=E) for (_, N, dl, E) in stream]
+    out = {"workload": f"{n_requests} Kerr requests, N ~ U{{10..60}}, (Delta, E) on a 21 x 20 grid, seed 1",
+           "method": "trace_bicgstab", "tol": 1e-10}
+    for prec in ("mixed", "fp64"):
+        wall, lat, res = _run_stream(ssl, systems, [0.0] * n_requests, prec)
+        ok = all(r[1]["status"] == 0 and r[1]["resid_l2"] <= 1e-10 for r in res.values())
+        sample = [i for i in range(n_requests) if systems[i].dim <= 30][:8]
+        err = max(float(np_.max(np_.abs(res[i][0] - steady_state_dense(systems[i].H, systems[i].c_ops))))
+                  for i in sample) if sample else None
+        out[f"burst_{prec}"] = {"solves_per_s": n_requests / wall, "p50_ms": float(np_.percentile(lat, 50)),
+                                "p99_ms": float(np_.percentile(lat, 99)), "all_converged": ok,
+                                "max_abs_err_vs_oracle_sample": err, "sample_size": len(sample)}
+        _log(f"serving burst {prec}: {n_requests / wall:.1f} solves/s, p50 {np_.percentile(lat, 50):.1f} ms, "
+             f"p99 {np_.percentile(lat, 99):.1f} ms, err {err}")
+    cap = out["burst_mixed"]["solves_per_s"]
+    rate = 0.5 * cap
+    pstream = qs.serving_stream(n_requests, rate=rate, seed=1)
+    wall, lat, res = _run_stream(ssl, systems, [a for (a, _, _, _) in pstream], "mixed")
+    out["poisson_mixed"] = {"rate_per_s": rate, "solves_per_s": n_requests / wall,
+                            "p50_ms": float(np_.percentile(lat, 50)), "p99_ms": float(np_.percentile(lat, 99)),
+                            "all_converged": all(r[1]["status"] == 0 for r in res.values())}
+    _log(f"serving poisson {rate:.1f}/s: p50 {np_.percentile(lat, 50):.1f} ms, p99 {np_.percentile(lat, 99):.1f} ms")
+    out["mixed_vs_fp64_capacity"] = cap / out["burst_fp64"]["solves_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +122,8 @@ def main():
     ap.add_argument("--method", default="trace_bicgstab")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 SpMV measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the Kerr serving stream (0 skips the serving measurement)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (each solve fits one MI355X; "
@@ -155,7 +217,18 @@ def main():
         large = {"workload": "kerr_chain_3x10 (n = 1e6)", "nnz": int(Apc.nnz),
                  "c64": {"ms": t64, "GB/s": b64 / (t64 * 1e-3) / 1e9, "bytes": b64},
                  "c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128}}
+        for prec in ("mixed", "fp64"):
+            t0 = time.perf_counter()
+            _, ci = ssl.solve(Lc, "invpow_bicgstab", tol=1e-10, prec=prec)
+            dt = time.perf_counter() - t0
+            large[f"solve_invpow_{prec}"] = {"s": dt, "resid_l2": ci["resid_l2"], "outer_its": ci["outer_its"],
+                                             "inner_its": ci["inner_its"], "t_setup_ms": ci["t_setup_ms"]}
+            _log(f"kerr chain invpow {prec}: {dt:.2f} s, resid {ci['resid_l2']:.2e}")
         Lc.free()
+
+    serving = None
+    if args.serve_requests > 0:
+        serving = serve_stream(ssl, qs, np, args.serve_requests)
 
     m, f = results["mixed"], results["fp64"]
     line = {
@@ -184,6 +257,7 @@ def main():
         "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"],
         "roofline": roofline,
         "spmv_large": large,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -122,7 +122,8 @@ typedef struct {
 #define SS_FLAG_DEVICE_WIDE 4  /* force the device-wide kernels (one kernel
                                   per step, all CUs) even for small systems   */
 #define SS_FLAG_WORKGROUP   8  /* force the workgroup-resident solve (whole
-                                  BiCGSTAB solve in one workgroup)            */
+                                  BiCGSTAB solve in one workgroup; chosen by
+                                  default for BiCGSTAB up to n = 4096)        */
 #define SS_FLAG_SYNCFREE   16  /* device-wide path: triangular solves
                                   sync-free over all CUs in row order         */
 #define SS_FLAG_TRSV_BLOCK 32  /* device-wide path: triangular solves in one

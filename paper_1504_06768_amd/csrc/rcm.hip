@@ -191,6 +191,140 @@ __global__ void k_fill_int(int n, int *p, int v) {
     if (q < n) p[q] = v;
 }
 
+// ------------------------------------------------- single-workgroup form
+// The same level-by-level search inside one workgroup (16 wavefronts, a
+// barrier between the claim / count / scan / place / mark phases), for
+// graphs small enough that launch and host round-trip latency would
+// dominate the multi-kernel form.  owner[] is only changed by atomics and is
+// read back with device-scope atomic loads.
+constexpr int RCM_BLOCK_T = 1024;
+constexpr int RCM_BLOCK_MAX_N = 65536;
+
+__device__ __forceinline__ int ld_owner(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(int n, const int *rowptr, const int *col, const int *deg,
+                                                           int *pos_of, int *owner, int *order, int *offs,
+                                                           int *perm, int *iperm) {
+    constexpr int NW = RCM_BLOCK_T / 64;
+    __shared__ unsigned long long sbest[NW];
+    __shared__ int wsum[NW];
+    __shared__ int s_total;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int r = tid; r < n; r += RCM_BLOCK_T) {
+        pos_of[r] = -1;
+        owner[r] = 0x7fffffff;
+    }
+    __syncthreads();
+    int visited = 0;
+    while (visited < n) {
+        // start node: minimum of (degree, -index) over the unvisited nodes
+        unsigned long long key = ~0ull;
+        for (int r = tid; r < n; r += RCM_BLOCK_T) {
+            if (pos_of[r] < 0) {
+                const unsigned long long k = ((unsigned long long)(unsigned)deg[r] << 32) |
+                                             (unsigned long long)(0xffffffffu - (unsigned)r);
+                key = k < key ? k : key;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_down(key, off, 64);
+            key = o < key ? o : key;
+        }
+        if (lane == 0) sbest[wave] = key;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = sbest[0];
+            for (int w = 1; w < NW; ++w) b = sbest[w] < b ? sbest[w] : b;
+            const int r = (int)(0xffffffffu - (unsigned)(b & 0xffffffffull));
+            order[visited] = r;
+            pos_of[r] = visited;
+        }
+        __syncthreads();
+        int lo = visited, hi = visited + 1;
+        visited += 1;
+        while (lo < hi) {
+            const int width = hi - lo;
+            // claim: each unvisited neighbour goes to the frontier node of lowest position
+            for (int p = lo + wave; p < hi; p += NW) {
+                const int u = order[p];
+                for (int e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) {
+                    const int v = col[e];
+                    if (pos_of[v] < 0) atomicMin(&owner[v], p);
+                }
+            }
+            __syncthreads();
+            // count the children each frontier node owns
+            for (int p = lo + wave; p < hi; p += NW) {
+                const int u = order[p];
+                int c = 0;
+                for (int e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) {
+                    const int v = col[e];
+                    c += (pos_of[v] < 0 && ld_owner(owner + v) == p);
+                }
+                for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+                if (lane == 0) offs[p - lo] = c;
+            }
+            __syncthreads();
+            // exclusive scan of the counts, in chunks of the workgroup size
+            int carry = 0;
+            for (int c0 = 0; c0 < width; c0 += RCM_BLOCK_T) {
+                const int i = c0 + tid;
+                const int v = (i < width) ? offs[i] : 0;
+                int x = v;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(x, off, 64);
+                    if (lane >= off) x += y;
+                }
+                if (lane == 63) wsum[wave] = x;
+                __syncthreads();
+                int before = 0;
+                for (int w = 0; w < wave; ++w) before += wsum[w];
+                int chunk = 0;
+                for (int w = 0; w < NW; ++w) chunk += wsum[w];
+                if (i < width) offs[i] = carry + before + x - v;
+                carry += chunk;
+                __syncthreads();
+            }
+            if (tid == 0) s_total = carry;
+            __syncthreads();
+            const int total = s_total;
+            // place the children of each frontier node by (degree, index)
+            for (int p = lo + wave; p < hi; p += NW) {
+                const int u = order[p];
+                const int rs = rowptr[u], re = rowptr[u + 1];
+                const int base = hi + offs[p - lo];
+                for (int e = rs + lane; e < re; e += 64) {
+                    const int v = col[e];
+                    if (!(pos_of[v] < 0 && ld_owner(owner + v) == p)) continue;
+                    const int dv = deg[v];
+                    int rank = 0;
+                    for (int f = rs; f < re; ++f) {
+                        const int w = col[f];
+                        if (pos_of[w] < 0 && ld_owner(owner + w) == p) {
+                            const int dw = deg[w];
+                            rank += (dw < dv) || (dw == dv && w < v);
+                        }
+                    }
+                    order[base + rank] = v;
+                }
+            }
+            __syncthreads();
+            for (int q = hi + tid; q < hi + total; q += RCM_BLOCK_T) pos_of[order[q]] = q;
+            __syncthreads();
+            lo = hi;
+            hi += total;
+            visited += total;
+        }
+    }
+    for (int q = tid; q < n; q += RCM_BLOCK_T) {
+        const int v = order[n - 1 - q];
+        perm[q] = v;
+        iperm[v] = q;
+    }
+}
+
 void rcm_order(const CsrBuf<double2> &S, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s) {
     const int n = S.n;
     perm.resize((size_t)n);
@@ -200,6 +334,13 @@ void rcm_order(const CsrBuf<double2> &S, DevBuf<int> &perm, DevBuf<int> &iperm, 
     DevBuf<int> cnt((size_t)n + 1), offs((size_t)n + 1);
     DevBuf<unsigned long long> best(1);
     k_degree<<<div_up(n, 256), 256, 0, s>>>(n, S.rowptr.get(), S.col.get(), deg.get());
+    if (n <= RCM_BLOCK_MAX_N) {
+        k_rcm_block<<<1, RCM_BLOCK_T, 0, s>>>(n, S.rowptr.get(), S.col.get(), deg.get(), pos_of.get(), owner.get(),
+                                              order.get(), offs.get(), perm.get(), iperm.get());
+        SS_HIP(hipGetLastError());
+        SS_HIP(hipStreamSynchronize(s));  // before the scratch buffers are released
+        return;
+    }
     k_fill_int<<<div_up(n, 256), 256, 0, s>>>(n, pos_of.get(), -1);
     k_fill_int<<<div_up(n, 256), 256, 0, s>>>(n, owner.get(), 0x7fffffff);
     SS_HIP(hipMemsetAsync(best.get(), 0xff, sizeof(unsigned long long), s));

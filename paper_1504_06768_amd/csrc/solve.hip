@@ -75,6 +75,15 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG, "unknown ordering");
     hipStream_t s = stream_of(h);
     const double t0 = now_ms();
+    const bool dbg = std::getenv("SS_DEBUG") != nullptr;
+    double tp = t0;
+    auto phase = [&](const char *name) {
+        if (!dbg) return;
+        SS_HIP(hipStreamSynchronize(s));
+        const double t = now_ms();
+        std::fprintf(stderr, "[ss] prepare %-10s %.3f ms\n", name, t - tp);
+        tp = t;
+    };
     h->prepared = false;
     const int n = h->n, d = h->d;
     h->d_w.resize(1);
@@ -95,10 +104,14 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
         h->trow = 0;
         make_shifted(h->L, o.sigma, h->A, s);
     }
+    phase("transform");
     symmetrize_pattern(h->A, h->S, s);
+    phase("symmetrize");
     if (o.ordering == SS_ORDER_RCM) rcm_order(h->S, h->perm, h->iperm, s);
     else identity_order(n, h->perm, h->iperm, s);
+    phase("ordering");
     permute_matrix(h->A, h->perm.get(), h->iperm.get(), h->Ap, s);
+    phase("permute");
     h->diag.resize((size_t)n);
     h->diag_added = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
     if (h->diag_added > 0) {
@@ -121,6 +134,7 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
             ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU, h->lu_diag, s)
                 .guarded;
     }
+    phase("ilu");
     if (o.prec == SS_MIXED) {
         copy_pattern_c64(h->Ap, h->Ap32, s);
         copy_pattern_c64(h->LU, h->LU32, s);
@@ -132,6 +146,7 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
     SS_HIP(hipGetLastError());
     d2h(&h->q0, h->iperm.get() + h->trow, 1, s);
+    phase("finish");
     h->p_method = method;
     h->p_opt = o;
     h->prepared = true;
@@ -201,7 +216,7 @@ __global__ void k_max_part(const double2 *p, int nb, double2 *out) {
 
 // ------------------------------------------------------------- driver
 // Largest system solved by the workgroup-resident kernel unless forced.
-constexpr int WG_AUTO_MAX_N = 65536;
+constexpr int WG_AUTO_MAX_N = 4096;
 
 bool use_workgroup(ss_liouv h, int method, const ss_options &o) {
     if (is_gmres(method)) return false;

@@ -1,7 +1,9 @@
 // Problem transforms of the Liouvillian (a2):
 //   modified  L~ = L + w T  (section "Direct factorization", eq. linear), T
-//             with ones in row 0 at the columns k (d + 1) of the diagonal of
-//             rho, w = mean of the diagonal of L unless given;
+//             with ones at the columns k (d + 1) of the diagonal of rho in one
+//             population row (the paper's row 0 on request, by default the
+//             population row with the smallest |L_rr|), w = mean of the
+//             diagonal of L unless given;
 //   shifted   L - sigma I   (section "Eigenvalue Methods", eq. inverse).
 #include "csr_tools.hpp"
 #include "transform.hpp"

@@ -298,7 +298,11 @@ __device__ __forceinline__ void solve_regs(const SlotRegs<T> &q, const int *col,
     for (int k = 0; k < WG_K; ++k) {
         const T y = Y[q.c[k]];
         const T t = csub(acc, cmul(q.v[k], y));
-        acc = (k < len) ? t : acc;
+        // select component-wise: a select of the whole vector type is lowered
+        // through private (scratch) memory
+        const bool take = k < len;
+        acc.x = take ? t.x : acc.x;
+        acc.y = take ? t.y : acc.y;
     }
     if (len > WG_K && q.sl.w) {
         for (int e = q.sl.y + WG_K; e < q.sl.y + len; ++e) acc = csub(acc, cmul(val[e], Y[col[e]]));

@@ -328,3 +328,17 @@ def test_iteration_limit_reports_not_converged():
         ssl.solve(L, "trace_bicgstab", tol=1e-12, maxiter=1, max_outer=1)
     assert e.value.code == -3
     assert e.value.info["inner_its"] >= 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("path", ["workgroup", "device"])
+def test_repeated_solves_are_bitwise_identical(prec, path):
+    """Every reduction and sweep runs in a fixed order, so repeating a solve
+    gives the same bits (this caught a complex128 select that the compiler
+    lowered through private memory inside the prefetching sweep)."""
+    s = qs.jaynes_cummings(30, seed=0)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    runs = [ssl.solve(L, "trace_bicgstab", tol=1e-10, prec=prec, path=path) for _ in range(3)]
+    for rho, info in runs[1:]:
+        assert info["inner_its"] == runs[0][1]["inner_its"]
+        assert np.array_equal(rho, runs[0][0])
