@@ -182,6 +182,20 @@ int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cop
 int ss_solve(ss_liouv L, int32_t method, double tol, const ss_options *opt,
              double *rho_out, ss_info *info);
 
+/* Solve `count` independent systems together (a parameter sweep, say): each
+ * handle is set up on its own stream, then one launch of the workgroup-
+ * resident solver runs one workgroup per system, side by side on the CUs.
+ * method: SS_TRACE_BICGSTAB or SS_INVPOW_BICGSTAB; tol and opt as in
+ * ss_solve, shared by all systems.  Ls: count distinct handles (borrowed).
+ * rho_out: NULL or count pointers, each NULL or an N_i*N_i complex buffer
+ * (host or device, caller-owned); infos: NULL or count entries; status:
+ * NULL or count entries receiving each system's status.  Each system's
+ * result equals that of a batch of one.  Returns SS_OK when every system
+ * converged, else the status of the first one that did not. */
+int ss_solve_batch(ss_liouv *Ls, int32_t count, int32_t method, double tol,
+                   const ss_options *opt, double **rho_out, ss_info *infos,
+                   int32_t *status);
+
 void ss_liouv_free(ss_liouv L);
 
 /* N, n = N^2 and nnz of the assembled Liouvillian */

@@ -139,6 +139,23 @@ int ss_solve(ss_liouv L, int32_t method, double tol, const ss_options *opt, doub
     return rc;
 }
 
+int ss_solve_batch(ss_liouv *Ls, int32_t count, int32_t method, double tol, const ss_options *opt,
+                   double **rho_out, ss_info *infos, int32_t *status) {
+    if (infos && count > 0) std::memset(infos, 0, sizeof(ss_info) * (size_t)count);
+    return guarded([&]() -> int {
+        SS_REQUIRE(count >= 0, SS_E_INVALID_ARG, "negative count");
+        if (count == 0) return SS_OK;
+        SS_REQUIRE(Ls != nullptr, SS_E_INVALID_ARG, "null handle array");
+        for (int i = 0; i < count; ++i) {
+            SS_REQUIRE(Ls[i] != nullptr, SS_E_INVALID_ARG, "null handle in the batch");
+            for (int j = 0; j < i; ++j) SS_REQUIRE(Ls[j] != Ls[i], SS_E_INVALID_ARG, "handle repeated in the batch");
+        }
+        const int st = ss::solve_batch(Ls, count, method, tol, resolve(opt), rho_out, infos, status);
+        if (st != SS_OK) g_err = ss::batch_error().empty() ? "a system of the batch did not converge" : ss::batch_error();
+        return st;
+    });
+}
+
 static const ss::CsrBuf<double2> *pick(ss_liouv L, int which) {
     switch (which) {
         case SS_MAT_L: return &L->L;

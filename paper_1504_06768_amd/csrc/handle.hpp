@@ -41,6 +41,9 @@ namespace ss {
 hipStream_t stream_of(ss_liouv h);
 void prepare(ss_liouv h, int method, const ss_options &o);
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info);
+int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
+                ss_info *infos, int *status);
+const std::string &batch_error();  // message of the first failed system of the last batch (this thread)
 bool use_workgroup(ss_liouv h, int method, const ss_options &o);
 
 // Counters of one solve, handed to finish().

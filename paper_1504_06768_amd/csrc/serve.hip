@@ -233,7 +233,17 @@ static void solve_batch(ss_server_s *S, std::vector<Request *> &batch) {
         st.t_solve_ms = ms;
         st.elem_bytes = (double)sizeof(T);
         r->rho.resize(2 * (size_t)r->N * r->N);
-        r->status = finish(r->h, B.x.get(), r->opt, r->tol, st, r->rho.data(), &r->info, s);
+        if (hr.status == SS_E_BREAKDOWN && !(r->opt.flags & SS_FLAG_NO_FALLBACK)) {
+            // BiCGSTAB broke down, diverged or stalled on this request: solve it
+            // again on its own with the device-wide GMRES
+            ss_options od = r->opt;
+            od.flags |= SS_FLAG_DEVICE_WIDE;
+            const int gm = (r->method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
+            r->status = solve(r->h, gm, r->tol, od, r->rho.data(), &r->info);
+            r->info.fell_back = 1;
+        } else {
+            r->status = finish(r->h, B.x.get(), r->opt, r->tol, st, r->rho.data(), &r->info, s);
+        }
         if (r->status == SS_E_NOT_CONVERGED) r->error = "iteration limit reached before ||L rho|| <= tol";
         if (r->status == SS_E_BREAKDOWN) r->error = "BiCGSTAB breakdown";
     }

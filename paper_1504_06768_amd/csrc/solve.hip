@@ -21,6 +21,7 @@
 // represented next to O(1) diagonal entries.  Inner tolerance one decade
 // below the outer one (relative to the current residual).
 #include <chrono>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 
@@ -213,6 +214,13 @@ __global__ void k_max_part(const double2 *p, int nb, double2 *out) {
     for (int b = 0; b < nb; ++b) m = fmax(m, p[b].x);
     *out = mk(m, 0.0);
 }
+
+// host threads preparing the systems of a batch
+constexpr int BATCH_SETUP_THREADS = 8;
+
+static thread_local std::string tl_batch_error;
+static void set_batch_error(const std::string &e) { tl_batch_error = e; }
+const std::string &batch_error() { return tl_batch_error; }
 
 // ------------------------------------------------------------- driver
 // Largest system solved by the workgroup-resident kernel unless forced.
@@ -526,6 +534,131 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
     }
     st.t_solve_ms = now_ms() - t0;
     return finish(h, x, o, tol, st, rho_out, info, s);
+}
+
+// ------------------------------------------------------------- batches
+// Independent systems solved together: set-up of every handle on its own
+// stream from a few host threads, then one launch of the workgroup-resident
+// solver with one workgroup per system (the systems run side by side on the
+// CUs), then the finish of every handle.  A system whose BiCGSTAB broke
+// down is solved again on its own with the device-wide kernels (unless
+// SS_FLAG_NO_FALLBACK).  Each system's arithmetic stays in its own
+// workgroup, so its result is the same as in a batch of one.
+template <typename T>
+static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
+                     ss_info *infos, int *status) {
+    const int nthreads = std::max(1, std::min(count, BATCH_SETUP_THREADS));
+    std::vector<WgBundle<T>> B((size_t)count);
+    std::vector<std::string> err((size_t)count);
+    std::vector<int> code((size_t)count, SS_OK);
+    auto parallel = [&](auto &&fn) {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nthreads; ++t)
+            th.emplace_back([&, t]() {
+                for (int i = t; i < count; i += nthreads) {
+                    if (code[(size_t)i] != SS_OK) continue;
+                    try {
+                        fn(i);
+                    } catch (const Error &e) {
+                        code[(size_t)i] = e.code;
+                        err[(size_t)i] = e.what();
+                    } catch (const std::exception &e) {
+                        code[(size_t)i] = SS_E_HIP;
+                        err[(size_t)i] = e.what();
+                    }
+                }
+            });
+        for (auto &x : th) x.join();
+    };
+    const double t0 = now_ms();
+    parallel([&](int i) {
+        ss_liouv h = hs[i];
+        prepare(h, method, o);
+        const bool mixed = o.prec == SS_MIXED;
+        if constexpr (std::is_same<T, float2>::value) {
+            (void)mixed;
+            make_wg<T>(h, method, tol, o, h->Ap32, h->LU32, B[(size_t)i], stream_of(h));
+        } else {
+            make_wg<T>(h, method, tol, o, h->Ap, h->LU, B[(size_t)i], stream_of(h));
+        }
+        SS_HIP(hipStreamSynchronize(stream_of(h)));
+    });
+    const double t_setup = now_ms() - t0;
+    std::vector<WgProblem<T>> probs;
+    std::vector<int> slot((size_t)count, -1);
+    int max_n = 0, max_lev = 0;
+    for (int i = 0; i < count; ++i) {
+        if (code[(size_t)i] != SS_OK) continue;
+        slot[(size_t)i] = (int)probs.size();
+        probs.push_back(B[(size_t)i].P);
+        max_n = std::max(max_n, B[(size_t)i].P.n);
+        max_lev = std::max(max_lev, B[(size_t)i].levels);
+    }
+    float kms = 0.f;
+    const double t1 = now_ms();
+    if (!probs.empty()) {
+        hipStream_t s = stream_of(hs[0]);
+        DevBuf<WgProblem<T>> dP(probs.size());
+        h2d(dP.get(), probs.data(), probs.size(), s);
+        hipEvent_t e0, e1;
+        SS_HIP(hipEventCreate(&e0));
+        SS_HIP(hipEventCreate(&e1));
+        SS_HIP(hipEventRecord(e0, s));
+        wg_solve<T>(dP.get(), (int)probs.size(), max_n, max_lev, s);
+        SS_HIP(hipEventRecord(e1, s));
+        SS_HIP(hipEventSynchronize(e1));
+        SS_HIP(hipEventElapsedTime(&kms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    const double t_solve = now_ms() - t1;
+    const int path = wg_fits_lds((size_t)max_n, sizeof(T), max_lev) ? 2 : 1;
+    parallel([&](int i) {
+        ss_liouv h = hs[i];
+        hipStream_t s = stream_of(h);
+        WgResult hr;
+        d2h(&hr, B[(size_t)i].res.get(), 1, s);
+        if (hr.status == SS_E_BREAKDOWN && !(o.flags & SS_FLAG_NO_FALLBACK)) {
+            // this system again on its own, with the device-wide GMRES
+            ss_options od = o;
+            od.flags |= SS_FLAG_DEVICE_WIDE;
+            const int gm = (method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
+            code[(size_t)i] = solve(h, gm, tol, od, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr);
+            if (infos) infos[i].fell_back = 1;
+            return;
+        }
+        SolveStats st;
+        st.status = hr.status;
+        st.outer = hr.outer;
+        st.inner = hr.inner;
+        st.breakdowns = hr.breakdowns;
+        st.path = path;
+        st.t_kernel_ms = kms;
+        st.t_solve_ms = t_solve;
+        st.elem_bytes = (double)sizeof(T);
+        code[(size_t)i] = finish(h, B[(size_t)i].x.get(), o, tol, st, rho_out ? rho_out[i] : nullptr,
+                                 infos ? infos + i : nullptr, s);
+        if (infos) infos[i].t_setup_ms = t_setup;
+    });
+    int first = SS_OK;
+    for (int i = 0; i < count; ++i) {
+        if (status) status[i] = code[(size_t)i];
+        if (infos) infos[i].status = code[(size_t)i];
+        if (code[(size_t)i] != SS_OK && first == SS_OK) {
+            first = code[(size_t)i];
+            if (!err[(size_t)i].empty()) set_batch_error(err[(size_t)i]);
+        }
+    }
+    return first;
+}
+
+int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
+                ss_info *infos, int *status) {
+    SS_REQUIRE(tol > 0 && std::isfinite(tol), SS_E_INVALID_ARG, "tol must be positive");
+    SS_REQUIRE(method == SS_TRACE_BICGSTAB || method == SS_INVPOW_BICGSTAB, SS_E_INVALID_ARG,
+               "batched solves use BiCGSTAB (the workgroup-resident solver)");
+    if (o.prec == SS_MIXED) return run_batch<float2>(hs, count, method, tol, o, rho_out, infos, status);
+    return run_batch<double2>(hs, count, method, tol, o, rho_out, infos, status);
 }
 
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {

@@ -383,6 +383,10 @@ struct InnerStats {
     long long t_spmv;
 };
 
+// relative residual growth (squared) at which an inner solve counts as
+// diverged: the preconditioner does not make BiCGSTAB work on this system
+constexpr double WG_DIVERGED2 = 1e8;
+
 // Right-preconditioned BiCGSTAB (van der Vorst) on A d = b from d = 0, to
 // ||r|| <= rtol ||b||; breakdown (r^ orthogonal to r, or omega = 0) restarts
 // with r^ = r up to three times.
@@ -478,6 +482,10 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
             const double r2 = q5[1].x;
             if (r2 <= tol2) {
                 st.converged = 1;
+                return st;
+            }
+            if (!(r2 <= WG_DIVERGED2 * b2)) {
+                st.breakdowns = 3 + 1;  // diverged (or NaN): give up like an unrecoverable breakdown
                 return st;
             }
             breakdown = !(omega.x != 0.0 || omega.y != 0.0) ||
@@ -622,7 +630,9 @@ __global__ void __launch_bounds__(BS) k_wg_solve(const WgProblem<T> *probs) {
         breakdowns += is.breakdowns;
         t_pre += is.t_pre;
         t_spmv += is.t_spmv;
-        if (!is.converged && is.breakdowns >= 3) {
+        if (!is.converged && (is.breakdowns >= 3 || is.its >= P.maxiter)) {
+            // unrecoverable breakdown, divergence or stagnation of the inner
+            // solve: report it so the caller can switch to GMRES
             status = SS_E_BREAKDOWN;
             break;
         }

@@ -79,6 +79,7 @@ def _load():
         "ss_options_default": (ctypes.c_int, [P]),
         "ss_build_liouvillian": (ctypes.c_int, [P, P, I32, I64, P]),
         "ss_solve": (ctypes.c_int, [P, I32, D, P, P, P]),
+        "ss_solve_batch": (ctypes.c_int, [P, I32, I32, D, P, P, P, P]),
         "ss_liouv_free": (None, [P]),
         "ss_liouv_shape": (ctypes.c_int, [P, P, P, P]),
         "ss_prepare": (ctypes.c_int, [P, I32, P]),
@@ -104,7 +105,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_solve", "ss_liouv_free", "ss_liouv_shape",
+EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_solve", "ss_solve_batch", "ss_liouv_free",
+            "ss_liouv_shape",
             "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile", "ss_time_operator",
             "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_destroy",
             "ss_last_error", "ss_set_stream", "ss_version")
@@ -249,6 +251,34 @@ def solve(L: Liouvillian, method="trace_bicgstab", tol: float = 1e-10, out=None,
     if out is None:
         rho = rho.reshape(L.N, L.N, order="F")
     return rho, d
+
+
+def solve_batch(Ls, method="trace_bicgstab", tol: float = 1e-10, outs=None, raise_on_error=True, **opts):
+    """ss_solve_batch: independent systems solved together, one workgroup
+    each.  `outs` may be a list of torch complex128 device tensors (N_i^2
+    elements each) to receive the rho's; returns (list of rho, list of info
+    dicts)."""
+    Ls = list(Ls)
+    k = len(Ls)
+    o = options(**opts)
+    infos = (_Info * max(k, 1))()
+    status = (ctypes.c_int32 * max(k, 1))()
+    handles = (ctypes.c_void_p * max(k, 1))(*[L.handle for L in Ls])
+    if outs is not None:
+        rhos = list(outs)
+        ptrs = [_ptr(t) for t in rhos]
+    else:
+        bufs = [np.empty(L.n, dtype=np.complex128) for L in Ls]
+        rhos = bufs
+        ptrs = [b.ctypes.data for b in bufs]
+    parr = (ctypes.c_void_p * max(k, 1))(*ptrs)
+    rc = _lib.ss_solve_batch(handles, k, _method(method), float(tol), ctypes.byref(o), parr, infos, status)
+    ds = [infos[i].as_dict() for i in range(k)]
+    if rc != SS_OK and raise_on_error:
+        raise SolverError(rc, f"ss_solve_batch: {_err()}", ds)
+    if outs is None:
+        rhos = [r.reshape(L.N, L.N, order="F") for r, L in zip(rhos, Ls)]
+    return rhos, ds
 
 
 def prepare(L: Liouvillian, method="trace_bicgstab", **opts):
