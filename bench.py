@@ -4,15 +4,18 @@
 Workload (default): the driven Jaynes-Cummings system, cavity N = 40 x qubit
 (Hilbert dimension 80, Liouvillian 6400 x 6400), parameters (g, E, Delta_c,
 omega_a, kappa, gamma) drawn from a seeded uniform [0.1, 2]; synthetic, no
-data files.  One step = one whole solve through the C ABI: Liouvillian
-assembly from H and the collapse operators already resident in HBM, trace-row
-transform, RCM, ILU(0), preconditioned BiCGSTAB with fp64 refinement, finish
-(unpermute, normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
+data files.  One step = --batch independent solves through the C ABI, each
+the whole path: Liouvillian assembly from H and the collapse operators
+already resident in HBM, trace-row transform, RCM, ILU(0), then all systems
+solved together by the workgroup-resident solver (preconditioned BiCGSTAB
+with fp64 refinement, one workgroup per system), finish (unpermute,
+normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
 
 Prints one JSON line: solves/s of the mixed-precision path (value) next to
-the fp64 path, the roofline position of the dominant kernel (timed live with
-HIP events), the SpMV bandwidth on the large Kerr-chain matrix (n = 10^6) and
-the CPU oracle (dense LU) timed on the host cores.
+the fp64 path, single-solve latency, the roofline position of the dominant
+kernel (timed live with HIP events), the SpMV bandwidth and inverse-power
+solve times on the Kerr-chain matrix (n = 10^6), the serving stream (burst
+capacity, Poisson p50/p99) and the CPU oracle (dense LU) on the host cores.
 """
 import argparse
 import json
@@ -47,6 +50,23 @@ def spmv_bytes(n, nnz, s):
     """Algorithmic bytes of one CSR SpMV: values + column indices, row
     pointers, x read once, y written once (s = bytes per complex value)."""
     return nnz * (s + 4) + 4 * (n + 1) + 2 * n * s
+
+
+def _traffic(t_kernel_ms):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter runs (profiles/traffic.json), or None when that file is
+    missing or the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, rec["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def trsv_pair_bytes(n, nnz_lu, s):
@@ -117,11 +137,12 @@ def serve_stream(ssl, qs, np_, n_requests):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=256, help="solves per step (one workgroup each)")
     ap.add_argument("--method", default="trace_bicgstab")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 SpMV measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 Kerr-chain measurements")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the Kerr serving stream (0 skips the serving measurement)")
     args = ap.parse_args()
@@ -130,7 +151,6 @@ def main():
               "independent requests would be routed to separate GPUs)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1504_06768_amd as ssl
@@ -139,17 +159,22 @@ def main():
     torch.cuda.set_device(0)
     s = qs.config(2)
     N = s.dim
-    _log(f"workload jc_N40xqubit: N = {N}, n = {N * N}")
+    B = args.batch
+    _log(f"workload jc_N40xqubit: N = {N}, n = {N * N}, {B} solves per step")
     Hd = _device_csr(s.H, torch)
     Cd = [_device_csr(c, torch) for c in s.c_ops]
-    out = torch.empty(N * N, dtype=torch.complex128, device="cuda")
+    outs = [torch.empty(N * N, dtype=torch.complex128, device="cuda") for _ in range(B)]
+    out1 = outs[0]
     torch.cuda.synchronize()
 
     def step(prec):
-        L = ssl.build_liouvillian(Hd, Cd)
-        _, info = ssl.solve(L, args.method, tol=1e-10, out=out, prec=prec)
-        L.free()
-        return info
+        """B independent solves: assembly from the device-resident H and
+        collapse operators, then set-up and solve of all B together."""
+        Ls = [ssl.build_liouvillian(Hd, Cd) for _ in range(B)]
+        _, infos = ssl.solve_batch(Ls, args.method, tol=1e-10, outs=outs, prec=prec)
+        for L in Ls:
+            L.free()
+        return infos
 
     results = {}
     for prec in ("mixed", "fp64"):
@@ -160,10 +185,29 @@ def main():
         infos = [step(prec) for _ in range(args.steps)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        rho = out.cpu().numpy().reshape(N, N, order="F")
-        results[prec] = dict(ms=1e3 * dt / args.steps, solves_per_s=args.steps / dt, info=infos[-1], rho=rho)
-        _log(f"{prec}: {1e3 * dt / args.steps:.2f} ms/solve, resid {infos[-1]['resid_l2']:.2e}, "
-             f"outer {infos[-1]['outer_its']}, inner {infos[-1]['inner_its']}")
+        last = infos[-1]
+        rho = out1.cpu().numpy().reshape(N, N, order="F")
+        worst = max(i["resid_l2"] for i in last)
+        results[prec] = dict(ms=1e3 * dt / args.steps, solves_per_s=B * args.steps / dt, infos=last, rho=rho,
+                             worst_resid=worst)
+        _log(f"{prec}: {1e3 * dt / args.steps:.1f} ms per step of {B} -> {B * args.steps / dt:.1f} solves/s, "
+             f"kernel {last[0]['t_kernel_ms']:.2f} ms, set-up {last[0]['t_setup_ms']:.1f} ms, "
+             f"worst resid {worst:.2e}, its {last[0]['outer_its']}/{last[0]['inner_its']}")
+
+    # single-solve latency (one system, the solver's own path choice)
+    single = {}
+    for prec in ("mixed", "fp64"):
+        ts = []
+        for k in range(6):
+            L = ssl.build_liouvillian(Hd, Cd)
+            t0 = time.perf_counter()
+            _, inf = ssl.solve(L, args.method, tol=1e-10, out=out1, prec=prec)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            L.free()
+        single[prec] = {"ms": 1e3 * float(np.median(ts[1:])), "path": inf["path"], "resid_l2": inf["resid_l2"],
+                        "outer_its": inf["outer_its"], "inner_its": inf["inner_its"]}
+        _log(f"single {prec}: {single[prec]['ms']:.2f} ms")
 
     # accuracy against the fp64 dense oracle, and the oracle's own time
     from oracle.steady import steady_state_dense
@@ -183,26 +227,19 @@ def main():
                          f"of the same workload (numpy/LAPACK)"}
     err = {p: float(np.max(np.abs(results[p]["rho"] - ref))) for p in results}
 
-    # dominant kernel: the workgroup-resident iteration kernel (one launch per
-    # solve) timed live with HIP events on the solver's stream; its
-    # algorithmic bytes come from the iteration counts (ss_info.bytes_alg)
-    mi = results["mixed"]["info"]
-    if mi["t_kernel_ms"] > 0:
-        kern = "k_wg_solve<c64>: workgroup-resident refinement + BiCGSTAB + level-scheduled ILU(0) solves"
-        alg, t_k = mi["bytes_alg"], mi["t_kernel_ms"]
-    else:
-        kern, alg, t_k = "device-wide iteration kernels", mi["bytes_alg"], mi["t_solve_ms"]
+    # dominant kernel: the workgroup-resident solver, one launch per step
+    # running all B systems; algorithmic bytes are summed over the systems
+    # from their iteration counts (ss_info.bytes_alg) and divided by the
+    # launch time measured with HIP events on the solver's stream
+    mi = results["mixed"]["infos"]
+    alg = float(sum(i["bytes_alg"] for i in mi))
+    t_k = mi[0]["t_kernel_ms"]
     achieved = alg / (t_k * 1e-3) / 1e9
-    # the device-wide operators on the same matrix, for reference
-    L = ssl.build_liouvillian(Hd, Cd)
-    ssl.prepare(L, args.method, prec="mixed")
-    t_spmv = ssl.time_operator(L, ssl.SS_OP_SPMV_APERM, "mixed", 200)
-    t_pre = ssl.time_operator(L, ssl.SS_OP_PRECOND, "mixed", 100)
-    L.free()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": kern,
-                "bytes_per_launch": alg, "avg_launch_ms": t_k,
-                "device_wide_spmv_c64_ms": t_spmv, "device_wide_precond_c64_ms": t_pre}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(t_k),
+                "kernel": f"k_wg_solve<c64> over {B} systems (refinement + BiCGSTAB + level-scheduled ILU(0) "
+                          f"sweeps, one workgroup per system)",
+                "bytes_per_launch": alg, "avg_launch_ms": t_k}
 
     large = None
     if not args.no_large:
@@ -215,8 +252,8 @@ def main():
         t128 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "fp64", 50)
         b64, b128 = spmv_bytes(nc, Apc.nnz, 8), spmv_bytes(nc, Apc.nnz, 16)
         large = {"workload": "kerr_chain_3x10 (n = 1e6)", "nnz": int(Apc.nnz),
-                 "c64": {"ms": t64, "GB/s": b64 / (t64 * 1e-3) / 1e9, "bytes": b64},
-                 "c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128}}
+                 "spmv_c64": {"ms": t64, "GB/s": b64 / (t64 * 1e-3) / 1e9, "bytes": b64},
+                 "spmv_c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128}}
         for prec in ("mixed", "fp64"):
             t0 = time.perf_counter()
             _, ci = ssl.solve(Lc, "invpow_bicgstab", tol=1e-10, prec=prec)
@@ -244,19 +281,17 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 inner / c128 refinement",
         "data": "synthetic",
-        "config": {"workload": "jc_N40xqubit: driven Jaynes-Cummings, cavity 40 x qubit, n = 6400",
-                   "method": args.method, "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0"},
+        "config": {"workload": f"jc_N40xqubit: driven Jaynes-Cummings, cavity 40 x qubit, n = 6400; "
+                               f"{B} independent solves per step (assembly, transform, RCM, ILU(0), solve, finish)",
+                   "method": args.method, "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0", "batch": B},
+        "max_abs_err_vs_oracle": err["mixed"],
+        "worst_resid_l2": m["worst_resid"],
         "fp64": {"solves_per_s": f["solves_per_s"], "ms_per_step": f["ms"], "max_abs_err_vs_oracle": err["fp64"],
-                 "t_kernel_ms": f["info"]["t_kernel_ms"], "path": f["info"]["path"],
-                 "resid_l2": f["info"]["resid_l2"], "outer_its": f["info"]["outer_its"],
-                 "inner_its": f["info"]["inner_its"]},
-        "mixed": {"max_abs_err_vs_oracle": err["mixed"], "resid_l2": m["info"]["resid_l2"],
-                  "outer_its": m["info"]["outer_its"], "inner_its": m["info"]["inner_its"],
-                  "t_setup_ms": m["info"]["t_setup_ms"], "t_solve_ms": m["info"]["t_solve_ms"],
-                  "t_kernel_ms": m["info"]["t_kernel_ms"], "path": m["info"]["path"]},
+                 "worst_resid_l2": f["worst_resid"], "t_kernel_ms": f["infos"][0]["t_kernel_ms"]},
         "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"],
+        "single_solve": single,
         "roofline": roofline,
-        "spmv_large": large,
+        "large": large,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -83,17 +83,11 @@ int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cop
         SS_REQUIRE(out != nullptr, SS_E_INVALID_ARG, "out is NULL");
         *out = nullptr;
         std::unique_ptr<ss_liouv_s> h(new ss_liouv_s());
-        SS_HIP(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+        h->own_stream = ss::pooled_stream();
         h->N = N;
         h->d = (int)N;
         h->n = (int)(N * N);
-        try {
-            ss::assemble_liouvillian(H, c_ops, n_cops, N, ss::stream_of(h.get()), h->L);
-        } catch (...) {
-            (void)hipStreamDestroy(h->own_stream);
-            h->own_stream = nullptr;
-            throw;
-        }
+        ss::assemble_liouvillian(H, c_ops, n_cops, N, ss::stream_of(h.get()), h->L);
         *out = h.release();
         return SS_OK;
     });
@@ -101,12 +95,10 @@ int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cop
 
 void ss_liouv_free(ss_liouv L) {
     if (!L) return;
-    if (L->own_stream) {
-        (void)hipStreamSynchronize(L->own_stream);
-    }
-    hipStream_t s = L->own_stream;
+    // the stream belongs to the pool: its work is left to finish, and every
+    // device block of the handle is released against it
+    if (L->own_stream) ss::set_current_stream(L->own_stream);
     delete L;
-    if (s) (void)hipStreamDestroy(s);
 }
 
 int ss_liouv_shape(ss_liouv L, int64_t *N, int64_t *n, int64_t *nnz) {

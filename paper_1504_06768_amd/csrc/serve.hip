@@ -253,6 +253,7 @@ static void solve_batch(ss_server_s *S, std::vector<Request *> &batch) {
 // precision over every ready request.
 static void scheduler_loop(ss_server_s *S) {
     (void)hipSetDevice(S->device);
+    set_current_stream(S->solve_stream);
     while (true) {
         std::vector<Request *> b64, b32;
         {
@@ -322,7 +323,7 @@ int ss_server_create(size_t hbm_budget_bytes, int32_t max_slots, ss_server *out)
         delete S;
         return SS_E_HIP;
     }
-    const int nworkers = 4;
+    const int nworkers = 8;
     for (int i = 0; i < nworkers; ++i) S->workers.emplace_back(ss::worker_loop, S);
     S->scheduler = std::thread(ss::scheduler_loop, S);
     *out = S;

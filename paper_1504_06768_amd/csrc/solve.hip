@@ -37,7 +37,11 @@ namespace ss {
 static thread_local hipStream_t tls_stream = nullptr;
 
 void set_thread_stream(hipStream_t s) { tls_stream = s; }
-hipStream_t stream_of(ss_liouv h) { return tls_stream ? tls_stream : h->own_stream; }
+hipStream_t stream_of(ss_liouv h) {
+    hipStream_t s = tls_stream ? tls_stream : h->own_stream;
+    set_current_stream(s);
+    return s;
+}
 
 static double now_ms() {
     using namespace std::chrono;

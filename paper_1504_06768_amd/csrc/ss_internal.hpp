@@ -36,6 +36,12 @@ struct Error : std::runtime_error {
 // ------------------------------------------------------------ device memory
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+// stream on which the calling thread issues its work (tags its allocations)
+void set_current_stream(hipStream_t s);
+// release every cached block (waits for their last uses)
+void trim_device_cache();
+// a stream from the library's fixed pool
+hipStream_t pooled_stream();
 
 template <typename T>
 class DevBuf {

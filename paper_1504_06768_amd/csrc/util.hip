@@ -1,12 +1,69 @@
 // Device memory, pointer classification and the integer exclusive scan used
 // to turn per-row counts into CSR row pointers.
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
 #include "ss_internal.hpp"
 
 namespace ss {
 
-void *dev_alloc(size_t bytes) {
+// ------------------------------------------------------ cached allocation
+// hipMalloc / hipFree cost tens to hundreds of microseconds and hipFree
+// waits for the device, which would serialise the set-up of independent
+// systems running on different streams.  Freed blocks (up to 64 MB, 4 GB in
+// total) are therefore kept in power-of-two size classes and handed out
+// again -- but only after an event, recorded at free time on the stream the
+// block was allocated for, has completed, so a block is never reused while
+// work queued before its release may still touch it.  Blocks are used on
+// the stream that was current in the allocating thread (stream_of()), and
+// the few cross-stream uses (a batched launch) are synchronised before the
+// owners release their blocks.
+namespace {
+
+constexpr size_t CACHE_MAX_BLOCK = size_t(64) << 20;
+constexpr size_t CACHE_MAX_TOTAL = size_t(4) << 30;
+
+struct Cached {
+    void *p;
+    hipEvent_t ev;
+};
+
+struct Live {
+    size_t cls;      // 0: not cached
+    hipStream_t s;   // stream current when allocated
+};
+
+struct Cache {
+    std::mutex mu;
+    std::unordered_map<void *, Live> live;
+    std::map<size_t, std::vector<Cached>> free_by_cls;
+    std::vector<hipEvent_t> events;
+    size_t cached = 0;
+};
+
+Cache &cache() {
+    static Cache *c = new Cache();  // process lifetime
+    return *c;
+}
+
+thread_local hipStream_t t_current = nullptr;
+
+size_t size_class(size_t b) {
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+
+void *raw_alloc(size_t bytes) {
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        trim_device_cache();
+        e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         throw Error(e == hipErrorOutOfMemory ? SS_E_OOM : SS_E_HIP,
@@ -15,8 +72,103 @@ void *dev_alloc(size_t bytes) {
     return p;
 }
 
+}  // namespace
+
+void set_current_stream(hipStream_t s) { t_current = s; }
+
+void trim_device_cache() {
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto &kv : c.free_by_cls) {
+        for (Cached &b : kv.second) {
+            (void)hipEventSynchronize(b.ev);
+            (void)hipFree(b.p);
+            c.events.push_back(b.ev);
+        }
+        kv.second.clear();
+    }
+    c.cached = 0;
+}
+
+void *dev_alloc(size_t bytes) {
+    Cache &c = cache();
+    const size_t cls = bytes <= CACHE_MAX_BLOCK ? size_class(bytes) : 0;
+    if (cls) {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.free_by_cls.find(cls);
+        if (it != c.free_by_cls.end()) {
+            std::vector<Cached> &v = it->second;
+            for (size_t k = v.size(); k-- > 0;) {
+                if (hipEventQuery(v[k].ev) == hipSuccess) {
+                    void *p = v[k].p;
+                    c.events.push_back(v[k].ev);
+                    v.erase(v.begin() + (long)k);
+                    c.cached -= cls;
+                    c.live[p] = Live{cls, t_current};
+                    return p;
+                }
+            }
+            (void)hipGetLastError();  // hipErrorNotReady from the queries
+        }
+    }
+    void *p = raw_alloc(cls ? cls : bytes);
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.live[p] = Live{cls, t_current};
+    return p;
+}
+
 void dev_free(void *p) {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    Cache &c = cache();
+    Live l{0, nullptr};
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.live.find(p);
+        if (it != c.live.end()) {
+            l = it->second;
+            c.live.erase(it);
+        }
+        if (l.cls && c.cached + l.cls <= CACHE_MAX_TOTAL) {
+            hipEvent_t ev = nullptr;
+            if (!c.events.empty()) {
+                ev = c.events.back();
+                c.events.pop_back();
+            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                ev = nullptr;
+            }
+            if (ev) {
+                if (!l.s) (void)hipDeviceSynchronize();  // no stream known: wait for everything
+                if (hipEventRecord(ev, l.s) == hipSuccess) {
+                    c.free_by_cls[l.cls].push_back(Cached{p, ev});
+                    c.cached += l.cls;
+                    return;
+                }
+                (void)hipGetLastError();
+                c.events.push_back(ev);
+            }
+        }
+    }
+    (void)hipFree(p);  // uncached: hipFree waits for the device
+}
+
+// ------------------------------------------------------------ stream pool
+// Handles take their stream from a fixed pool (created once, never
+// destroyed): creating and destroying a stream per handle costs milliseconds.
+hipStream_t pooled_stream() {
+    static std::mutex mu;
+    static std::vector<hipStream_t> pool;
+    static size_t next = 0;
+    constexpr size_t POOL = 16;
+    std::lock_guard<std::mutex> lk(mu);
+    if (pool.empty()) {
+        for (size_t k = 0; k < POOL; ++k) {
+            hipStream_t s = nullptr;
+            SS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            pool.push_back(s);
+        }
+    }
+    return pool[next++ % POOL];
 }
 
 bool is_device_ptr(const void *p) {
