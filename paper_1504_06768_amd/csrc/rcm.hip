@@ -142,30 +142,64 @@ __global__ void __launch_bounds__(256) k_count_owned(int lo, int hi, const int *
     if (lane == 0) cnt[p - lo] = c;
 }
 
+// Place the children a frontier node p owns (its unvisited neighbours whose
+// claim it won), ordered by (degree, index), at order_out[base ...].  One
+// wavefront per frontier node: each lane holds one row entry, and the rank
+// of an owned entry is counted against the owned entries of every chunk of
+// the row through cross-lane shuffles instead of re-reading the row.
+template <bool ATOMIC_OWNER>
+__device__ __forceinline__ void place_owned(int p, int rs, int re, int base, const int *col, const int *pos_of,
+                                            const int *owner, const int *deg, int *order_out) {
+    const int lane = threadIdx.x & 63;
+    for (int c0 = rs; c0 < re; c0 += 64) {
+        const int e = c0 + lane;
+        int v = 0x7fffffff, dv = 0x7fffffff;
+        bool own = false;
+        if (e < re) {
+            v = col[e];
+            const int ow = ATOMIC_OWNER ? __hip_atomic_load(owner + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : owner[v];
+            own = pos_of[v] < 0 && ow == p;
+            dv = deg[v];
+        }
+        if (__ballot(own) == 0) continue;  // nothing of this chunk to place
+        int rank = 0;
+        for (int c1 = rs; c1 < re; c1 += 64) {
+            const int f = c1 + lane;
+            int w = 0x7fffffff, dw = 0x7fffffff;
+            bool ownw = false;
+            if (c1 == c0) {
+                w = v;
+                dw = dv;
+                ownw = own;
+            } else if (f < re) {
+                w = col[f];
+                const int ow = ATOMIC_OWNER
+                                   ? __hip_atomic_load(owner + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                   : owner[w];
+                ownw = pos_of[w] < 0 && ow == p;
+                dw = deg[w];
+            }
+            if (!ownw) dw = 0x7fffffff;  // never ranks before anything
+            const int cnt = min(64, re - c1);
+            for (int k = 0; k < cnt; ++k) {
+                const int wk = __shfl(w, k, 64);
+                const int dk = __shfl(dw, k, 64);
+                rank += (dk < dv) || (dk == dv && dk != 0x7fffffff && wk < v);
+            }
+        }
+        if (own) order_out[base + rank] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_place_children(int lo, int hi, int next, const int *order_in,
                                                         const int *rowptr, const int *col, const int *pos_of,
                                                         const int *owner, const int *deg, const int *offs,
                                                         int *order_out) {
-    const int lane = threadIdx.x & 63;
     const int p = lo + blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= hi) return;
     const int u = order_in[p];
-    const int rs = rowptr[u], re = rowptr[u + 1];
-    const int base = next + offs[p - lo];
-    for (int e = rs + lane; e < re; e += 64) {
-        const int v = col[e];
-        if (!(pos_of[v] < 0 && owner[v] == p)) continue;
-        const int dv = deg[v];
-        int rank = 0;
-        for (int f = rs; f < re; ++f) {
-            const int w = col[f];
-            if (pos_of[w] < 0 && owner[w] == p) {
-                const int dw = deg[w];
-                rank += (dw < dv) || (dw == dv && w < v);
-            }
-        }
-        order_out[base + rank] = v;
-    }
+    place_owned<false>(p, rowptr[u], rowptr[u + 1], next + offs[p - lo], col, pos_of, owner, deg, order_out);
 }
 
 __global__ void k_mark_level(int from, int to, const int *order, int *pos_of) {
@@ -293,22 +327,7 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(int n, const int *row
             // place the children of each frontier node by (degree, index)
             for (int p = lo + wave; p < hi; p += NW) {
                 const int u = order[p];
-                const int rs = rowptr[u], re = rowptr[u + 1];
-                const int base = hi + offs[p - lo];
-                for (int e = rs + lane; e < re; e += 64) {
-                    const int v = col[e];
-                    if (!(pos_of[v] < 0 && ld_owner(owner + v) == p)) continue;
-                    const int dv = deg[v];
-                    int rank = 0;
-                    for (int f = rs; f < re; ++f) {
-                        const int w = col[f];
-                        if (pos_of[w] < 0 && ld_owner(owner + w) == p) {
-                            const int dw = deg[w];
-                            rank += (dw < dv) || (dw == dv && w < v);
-                        }
-                    }
-                    order[base + rank] = v;
-                }
+                place_owned<true>(p, rowptr[u], rowptr[u + 1], hi + offs[p - lo], col, pos_of, owner, deg, order);
             }
             __syncthreads();
             for (int q = hi + tid; q < hi + total; q += RCM_BLOCK_T) pos_of[order[q]] = q;
