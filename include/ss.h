@@ -192,6 +192,8 @@ int ss_solve(ss_liouv L, int32_t method, double tol, const ss_options *opt,
  * NULL or count entries receiving each system's status.  Each system's
  * result equals that of a batch of one.  Returns SS_OK when every system
  * converged, else the status of the first one that did not. */
+/* (The set-up runs on 8 host threads; the environment variable
+ * SS_SETUP_THREADS = 1..64 changes that.) */
 int ss_solve_batch(ss_liouv *Ls, int32_t count, int32_t method, double tol,
                    const ss_options *opt, double **rho_out, ss_info *infos,
                    int32_t *status);

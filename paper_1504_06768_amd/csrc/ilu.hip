@@ -25,14 +25,11 @@ namespace ss {
 
 constexpr int ILU_WPB = 4;  // wavefronts (rows) per workgroup
 
-__global__ void __launch_bounds__(ILU_WPB * 64) k_ilu0(int n, const int *rowptr, const int *col, const int *diag,
-                                                       const double2 *a, double2 *w, double2 *out, unsigned *ctr,
-                                                       unsigned base, double detect, double boost,
-                                                       unsigned *status, int *nguard) {
-    const unsigned bid = ordered_block(ctr, base);
+// One row of the ILU(0) elimination, by one wavefront (see the file header).
+__device__ __forceinline__ void ilu0_row(int row, const int *rowptr, const int *col, const int *diag,
+                                         const double2 *a, double2 *w, double2 *out, double detect, double boost,
+                                         unsigned *status, int *nguard) {
     const int lane = threadIdx.x & 63;
-    const int row = (int)bid * ILU_WPB + (int)(threadIdx.x >> 6);
-    if (row >= n) return;
     const int rs = rowptr[row], re = rowptr[row + 1], dg = diag[row];
     double rn = 0.0;
     for (int e = rs + lane; e < re; e += 64) {
@@ -87,6 +84,29 @@ __global__ void __launch_bounds__(ILU_WPB * 64) k_ilu0(int n, const int *rowptr,
     for (int e = rs + lane; e < re; e += 64) publish(out + e, w[e]);
 }
 
+__global__ void __launch_bounds__(ILU_WPB * 64) k_ilu0(int n, const int *rowptr, const int *col, const int *diag,
+                                                       const double2 *a, double2 *w, double2 *out, unsigned *ctr,
+                                                       unsigned base, double detect, double boost,
+                                                       unsigned *status, int *nguard) {
+    const unsigned bid = ordered_block(ctr, base);
+    const int row = (int)bid * ILU_WPB + (int)(threadIdx.x >> 6);
+    if (row >= n) return;
+    ilu0_row(row, rowptr, col, diag, a, w, out, detect, boost, status, nguard);
+}
+
+// Many systems at once, one workgroup each: its wavefronts take the rows in
+// increasing order (wavefront k: rows k, k + 16, ...), so the lowest
+// unfinished row always belongs to a wavefront that is working on it and
+// whose dependencies are done.
+constexpr int ILU_BATCH_WAVES = 16;
+
+__global__ void __launch_bounds__(ILU_BATCH_WAVES * 64) k_ilu0_batch(const Ilu0Job *jobs, double detect,
+                                                                     double boost) {
+    const Ilu0Job &J = jobs[blockIdx.x];
+    for (int row = (int)(threadIdx.x >> 6); row < J.n; row += ILU_BATCH_WAVES)
+        ilu0_row(row, J.rowptr, J.col, J.diag, J.a, J.w, J.out, detect, boost, J.status, J.nguard);
+}
+
 template <typename T>
 __global__ void k_fill_sentinel(int64_t n, T *p) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,6 +133,46 @@ void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s) {
         k_round_c64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, b);
         SS_HIP(hipGetLastError());
     }
+}
+
+Ilu0Job Ilu0Batch::prepare(const CsrBuf<double2> &A, const int *diag, CsrBuf<double2> &LU, hipStream_t s) {
+    const int n = A.n, nnz = A.nnz;
+    LU.alloc(n, nnz);
+    SS_HIP(hipMemcpyAsync(LU.rowptr.get(), A.rowptr.get(), sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) SS_HIP(hipMemcpyAsync(LU.col.get(), A.col.get(), sizeof(int) * nnz, hipMemcpyDeviceToDevice, s));
+    work.resize((size_t)std::max(nnz, 1));
+    fill_sentinel<double2>(nnz, LU.val.get(), s);
+    flags.resize(2);
+    SS_HIP(hipMemsetAsync(flags.get(), 0, 2 * sizeof(unsigned), s));
+    Ilu0Job j;
+    j.n = n;
+    j.rowptr = A.rowptr.get();
+    j.col = A.col.get();
+    j.diag = diag;
+    j.a = A.val.get();
+    j.w = work.get();
+    j.out = LU.val.get();
+    j.status = flags.get();
+    j.nguard = reinterpret_cast<int *>(flags.get() + 1);
+    return j;
+}
+
+IluResult Ilu0Batch::result(hipStream_t s) {
+    unsigned f[2] = {0, 0};
+    d2h(f, flags.get(), 2, s);
+    SS_REQUIRE(!(f[0] & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "ILU(0): dependency wait timed out");
+    IluResult r;
+    r.guarded = (int)f[1];
+    return r;
+}
+
+void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s) {
+    if (count <= 0) return;
+    DevBuf<Ilu0Job> dj((size_t)count);
+    h2d(dj.get(), jobs, (size_t)count, s);
+    k_ilu0_batch<<<count, ILU_BATCH_WAVES * 64, 0, s>>>(dj.get(), detect, boost);
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));  // the job array is released on return
 }
 
 IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double detect, double boost, CsrBuf<double2> &LU,

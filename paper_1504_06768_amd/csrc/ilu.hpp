@@ -15,6 +15,25 @@ struct IluResult {
 IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double detect, double boost, CsrBuf<double2> &LU,
                       hipStream_t s);
 
+// ILU(0) of many systems in one launch, one workgroup each.  prepare() sets
+// up one system (factor storage, scratch, flags) on its stream; after
+// ilu0_batch has run every job, result() reads that system's outcome.
+struct Ilu0Job {
+    int n;
+    const int *rowptr, *col, *diag;
+    const double2 *a;
+    double2 *w, *out;
+    unsigned *status;
+    int *nguard;
+};
+struct Ilu0Batch {
+    DevBuf<double2> work;
+    DevBuf<unsigned> flags;  // status word, guarded-pivot count
+    Ilu0Job prepare(const CsrBuf<double2> &A, const int *diag, CsrBuf<double2> &LU, hipStream_t s);
+    IluResult result(hipStream_t s);
+};
+void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s);
+
 // Dual-threshold ILUT (drop_tol relative to ||row||_inf, at most
 // ceil(fill * nnz(row)) entries kept in each of L and U per row).
 IluResult ilut_factor(const CsrBuf<double2> &A, const int *diag, double drop_tol, double fill, double detect,

@@ -1,6 +1,6 @@
 // Dual-threshold incomplete LU without pivoting, ILUT(drop_tol, fill)
 // (section "Iterative Solvers": the iLU preconditioner with a drop tolerance
-// and a fill limit; section "Results": the fill-factor study).
+// and a fill limit; section "Numerical Simulations": the fill-factor study).
 //
 // Row i is eliminated in increasing column order (row-wise IKJ form):
 //   w = a_i, tau = drop_tol * ||a_i||_inf, keep = ceil(fill * nnz(a_i));

@@ -232,16 +232,18 @@ __global__ void k_fill_int(int n, int *p, int v) {
 // dominate the multi-kernel form.  owner[] is only changed by atomics and is
 // read back with device-scope atomic loads.
 constexpr int RCM_BLOCK_T = 1024;
-constexpr int RCM_BLOCK_MAX_N = 65536;
 
 __device__ __forceinline__ int ld_owner(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(int n, const int *rowptr, const int *col, const int *deg,
-                                                           int *pos_of, int *owner, int *order, int *offs,
-                                                           int *perm, int *iperm) {
+__global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(const RcmJob *jobs) {
     constexpr int NW = RCM_BLOCK_T / 64;
+    const RcmJob &J = jobs[blockIdx.x];
+    const int n = J.n;
+    const int *rowptr = J.rowptr, *col = J.col;
+    int *deg = J.deg, *pos_of = J.pos_of, *owner = J.owner, *order = J.order, *offs = J.offs;
+    int *perm = J.perm, *iperm = J.iperm;
     __shared__ unsigned long long sbest[NW];
     __shared__ int wsum[NW];
     __shared__ int s_total;
@@ -249,6 +251,9 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(int n, const int *row
     for (int r = tid; r < n; r += RCM_BLOCK_T) {
         pos_of[r] = -1;
         owner[r] = 0x7fffffff;
+        int dg = rowptr[r + 1] - rowptr[r];
+        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) dg += (col[e] == r);  // a self-loop counts twice
+        deg[r] = dg;
     }
     __syncthreads();
     int visited = 0;
@@ -344,22 +349,57 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(int n, const int *row
     }
 }
 
+bool rcm_batchable(int n) { return n <= RCM_BLOCK_MAX_N; }
+
+void RcmScratch::alloc(int n) {
+    const size_t m = (size_t)std::max(n, 1);
+    deg.resize(m);
+    pos_of.resize(m);
+    owner.resize(m);
+    order.resize(m);
+    offs.resize(m + 1);
+}
+
+RcmJob RcmScratch::job(const CsrBuf<double2> &S, int *perm, int *iperm) const {
+    RcmJob j;
+    j.n = S.n;
+    j.rowptr = S.rowptr.get();
+    j.col = S.col.get();
+    j.deg = deg.get();
+    j.pos_of = pos_of.get();
+    j.owner = owner.get();
+    j.order = order.get();
+    j.offs = offs.get();
+    j.perm = perm;
+    j.iperm = iperm;
+    return j;
+}
+
+void rcm_batch(const RcmJob *jobs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    DevBuf<RcmJob> dj((size_t)count);
+    h2d(dj.get(), jobs, (size_t)count, s);
+    k_rcm_block<<<count, RCM_BLOCK_T, 0, s>>>(dj.get());
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));  // the job array is released on return
+}
+
 void rcm_order(const CsrBuf<double2> &S, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s) {
     const int n = S.n;
     perm.resize((size_t)n);
     iperm.resize((size_t)n);
     if (n == 0) return;
+    if (n <= RCM_BLOCK_MAX_N) {
+        RcmScratch w;
+        w.alloc(n);
+        RcmJob j = w.job(S, perm.get(), iperm.get());
+        rcm_batch(&j, 1, s);  // synchronises before the scratch is released
+        return;
+    }
     DevBuf<int> deg((size_t)n), pos_of((size_t)n), owner((size_t)n), order((size_t)n);
     DevBuf<int> cnt((size_t)n + 1), offs((size_t)n + 1);
     DevBuf<unsigned long long> best(1);
     k_degree<<<div_up(n, 256), 256, 0, s>>>(n, S.rowptr.get(), S.col.get(), deg.get());
-    if (n <= RCM_BLOCK_MAX_N) {
-        k_rcm_block<<<1, RCM_BLOCK_T, 0, s>>>(n, S.rowptr.get(), S.col.get(), deg.get(), pos_of.get(), owner.get(),
-                                              order.get(), offs.get(), perm.get(), iperm.get());
-        SS_HIP(hipGetLastError());
-        SS_HIP(hipStreamSynchronize(s));  // before the scratch buffers are released
-        return;
-    }
     k_fill_int<<<div_up(n, 256), 256, 0, s>>>(n, pos_of.get(), -1);
     k_fill_int<<<div_up(n, 256), 256, 0, s>>>(n, owner.get(), 0x7fffffff);
     SS_HIP(hipMemsetAsync(best.get(), 0xff, sizeof(unsigned long long), s));

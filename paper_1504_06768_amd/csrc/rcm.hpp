@@ -10,6 +10,23 @@ void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_
 // reverse Cuthill-McKee of a symmetric pattern: perm[new] = old, iperm[old] = new
 void rcm_order(const CsrBuf<double2> &S, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s);
 
+// Many graphs at once, one workgroup each (graphs of up to RCM_BLOCK_MAX_N
+// nodes): the same ordering as rcm_order.
+constexpr int RCM_BLOCK_MAX_N = 65536;
+struct RcmJob {
+    int n;
+    const int *rowptr, *col;  // symmetric pattern, sorted rows
+    int *deg, *pos_of, *owner, *order, *offs;  // scratch: n, n, n, n, n + 1
+    int *perm, *iperm;                          // results
+};
+struct RcmScratch {
+    DevBuf<int> deg, pos_of, owner, order, offs;
+    void alloc(int n);
+    RcmJob job(const CsrBuf<double2> &S, int *perm, int *iperm) const;
+};
+bool rcm_batchable(int n);
+void rcm_batch(const RcmJob *jobs, int count, hipStream_t s);
+
 void identity_order(int n, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s);
 
 // B = P A P^T (rows and columns permuted, rows sorted)

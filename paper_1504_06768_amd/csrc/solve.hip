@@ -73,24 +73,15 @@ static void copy_pattern_c64(const CsrBuf<double2> &a, CsrBuf<float2> &b, hipStr
 static bool is_trace(int method) { return method == SS_TRACE_BICGSTAB || method == SS_TRACE_GMRES; }
 static bool is_gmres(int method) { return method == SS_TRACE_GMRES || method == SS_INVPOW_GMRES; }
 
-void prepare(ss_liouv h, int method, const ss_options &o) {
+// The set-up in stages, so that a batch can run the ordering and the ILU(0)
+// of all its systems in one launch each (one workgroup per system).
+static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipStream_t s) {
     SS_REQUIRE(method >= 0 && method <= 3, SS_E_INVALID_ARG, "unknown method");
     SS_REQUIRE(o.prec == SS_FP64 || o.prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
     SS_REQUIRE(o.ilu == SS_ILU0 || o.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
     SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG, "unknown ordering");
-    hipStream_t s = stream_of(h);
-    const double t0 = now_ms();
-    const bool dbg = std::getenv("SS_DEBUG") != nullptr;
-    double tp = t0;
-    auto phase = [&](const char *name) {
-        if (!dbg) return;
-        SS_HIP(hipStreamSynchronize(s));
-        const double t = now_ms();
-        std::fprintf(stderr, "[ss] prepare %-10s %.3f ms\n", name, t - tp);
-        tp = t;
-    };
     h->prepared = false;
-    const int n = h->n, d = h->d;
+    const int d = h->d;
     h->d_w.resize(1);
     if (is_trace(method)) {
         if (o.weight != 0.0) {
@@ -109,37 +100,35 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
         h->trow = 0;
         make_shifted(h->L, o.sigma, h->A, s);
     }
-    phase("transform");
     symmetrize_pattern(h->A, h->S, s);
-    phase("symmetrize");
-    if (o.ordering == SS_ORDER_RCM) rcm_order(h->S, h->perm, h->iperm, s);
-    else identity_order(n, h->perm, h->iperm, s);
-    phase("ordering");
+    h->perm.resize((size_t)h->n);
+    h->iperm.resize((size_t)h->n);
+}
+
+static void prepare_permute(ss_liouv h, hipStream_t s) {
+    const int n = h->n;
     permute_matrix(h->A, h->perm.get(), h->iperm.get(), h->Ap, s);
-    phase("permute");
     h->diag.resize((size_t)n);
     h->diag_added = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
     if (h->diag_added > 0) {
         // Rows whose diagonal is structurally zero (e.g. the ground-state
-        // population of a Jaynes-Cummings system, which the trace row in row 0
-        // does not touch) get an explicit zero diagonal entry, so the
-        // zero-fill ILU has a pivot position; the matrix itself is unchanged.
+        // population of a Jaynes-Cummings system when the trace row sits
+        // elsewhere) get an explicit zero diagonal entry, so the zero-fill
+        // ILU has a pivot position; the matrix itself is unchanged.
         CsrBuf<double2> aug;
         make_shifted(h->Ap, 0.0, aug, s);
         h->Ap = std::move(aug);
         const int still = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
         SS_REQUIRE(still == 0, SS_E_ZERO_PIVOT, "could not give every row a diagonal entry");
     }
+}
+
+static void prepare_finish(ss_liouv h, int method, const ss_options &o, hipStream_t s, double t0) {
+    const int n = h->n, d = h->d;
     if (o.ilu == SS_ILU0) {
-        h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
         h->lu_diag.resize((size_t)n);
         if (n) SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
-    } else {
-        h->guarded =
-            ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU, h->lu_diag, s)
-                .guarded;
     }
-    phase("ilu");
     if (o.prec == SS_MIXED) {
         copy_pattern_c64(h->Ap, h->Ap32, s);
         copy_pattern_c64(h->LU, h->LU32, s);
@@ -151,11 +140,41 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
     SS_HIP(hipGetLastError());
     d2h(&h->q0, h->iperm.get() + h->trow, 1, s);
-    phase("finish");
     h->p_method = method;
     h->p_opt = o;
     h->prepared = true;
     h->t_setup_ms = now_ms() - t0;
+}
+
+void prepare(ss_liouv h, int method, const ss_options &o) {
+    hipStream_t s = stream_of(h);
+    const double t0 = now_ms();
+    const bool dbg = std::getenv("SS_DEBUG") != nullptr;
+    double tp = t0;
+    auto phase = [&](const char *name) {
+        if (!dbg) return;
+        SS_HIP(hipStreamSynchronize(s));
+        const double t = now_ms();
+        std::fprintf(stderr, "[ss] prepare %-10s %.3f ms\n", name, t - tp);
+        tp = t;
+    };
+    prepare_transform(h, method, o, s);
+    phase("transform");
+    if (o.ordering == SS_ORDER_RCM) rcm_order(h->S, h->perm, h->iperm, s);
+    else identity_order(h->n, h->perm, h->iperm, s);
+    phase("ordering");
+    prepare_permute(h, s);
+    phase("permute");
+    if (o.ilu == SS_ILU0) {
+        h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+    } else {
+        h->guarded =
+            ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU, h->lu_diag, s)
+                .guarded;
+    }
+    phase("ilu");
+    prepare_finish(h, method, o, s, t0);
+    phase("finish");
 }
 
 // ------------------------------------------------------------ helpers
@@ -219,8 +238,16 @@ __global__ void k_max_part(const double2 *p, int nb, double2 *out) {
     *out = mk(m, 0.0);
 }
 
-// host threads preparing the systems of a batch
+// host threads preparing the systems of a batch (environment variable
+// SS_SETUP_THREADS overrides it, 1..64)
 constexpr int BATCH_SETUP_THREADS = 8;
+
+static int setup_threads() {
+    const char *e = std::getenv("SS_SETUP_THREADS");
+    if (!e) return BATCH_SETUP_THREADS;
+    const int v = std::atoi(e);
+    return (v >= 1 && v <= 64) ? v : BATCH_SETUP_THREADS;
+}
 
 static thread_local std::string tl_batch_error;
 static void set_batch_error(const std::string &e) { tl_batch_error = e; }
@@ -551,7 +578,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
 template <typename T>
 static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
                      ss_info *infos, int *status) {
-    const int nthreads = std::max(1, std::min(count, BATCH_SETUP_THREADS));
+    const int nthreads = std::max(1, std::min(count, setup_threads()));
     std::vector<WgBundle<T>> B((size_t)count);
     std::vector<std::string> err((size_t)count);
     std::vector<int> code((size_t)count, SS_OK);
@@ -575,18 +602,72 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         for (auto &x : th) x.join();
     };
     const double t0 = now_ms();
+    hipStream_t s0 = stream_of(hs[0]);
+    // stage 1: transform and symmetrised pattern, per system
+    parallel([&](int i) {
+        hipStream_t s = stream_of(hs[i]);
+        prepare_transform(hs[i], method, o, s);
+        SS_HIP(hipStreamSynchronize(s));
+    });
+    // stage 2: RCM of every graph in one launch (small graphs), else per system
+    const bool rcm = o.ordering == SS_ORDER_RCM;
+    std::vector<RcmScratch> rs((size_t)count);
+    {
+        std::vector<RcmJob> jobs;
+        for (int i = 0; i < count; ++i) {
+            if (code[(size_t)i] != SS_OK || !rcm || !rcm_batchable(hs[i]->n) || hs[i]->n == 0) continue;
+            rs[(size_t)i].alloc(hs[i]->n);
+            jobs.push_back(rs[(size_t)i].job(hs[i]->S, hs[i]->perm.get(), hs[i]->iperm.get()));
+        }
+        rcm_batch(jobs.data(), (int)jobs.size(), s0);
+    }
+    // stage 3: remaining orderings, P A P^T, diagonal positions, per system
+    std::vector<Ilu0Batch> ib((size_t)count);
+    std::vector<Ilu0Job> ijobs((size_t)count);
+    std::vector<char> in_batch((size_t)count, 0);
     parallel([&](int i) {
         ss_liouv h = hs[i];
-        prepare(h, method, o);
-        const bool mixed = o.prec == SS_MIXED;
-        if constexpr (std::is_same<T, float2>::value) {
-            (void)mixed;
-            make_wg<T>(h, method, tol, o, h->Ap32, h->LU32, B[(size_t)i], stream_of(h));
-        } else {
-            make_wg<T>(h, method, tol, o, h->Ap, h->LU, B[(size_t)i], stream_of(h));
+        hipStream_t s = stream_of(h);
+        if (!rcm) identity_order(h->n, h->perm, h->iperm, s);
+        else if (!rcm_batchable(h->n) || h->n == 0) rcm_order(h->S, h->perm, h->iperm, s);
+        prepare_permute(h, s);
+        if (o.ilu == SS_ILU0 && h->n > 0) {
+            ijobs[(size_t)i] = ib[(size_t)i].prepare(h->Ap, h->diag.get(), h->LU, s);
+            in_batch[(size_t)i] = 1;
         }
-        SS_HIP(hipStreamSynchronize(stream_of(h)));
+        SS_HIP(hipStreamSynchronize(s));
     });
+    rs.clear();
+    // stage 4: ILU(0) of every system in one launch
+    {
+        std::vector<Ilu0Job> jobs;
+        for (int i = 0; i < count; ++i)
+            if (code[(size_t)i] == SS_OK && in_batch[(size_t)i]) jobs.push_back(ijobs[(size_t)i]);
+        ilu0_batch(jobs.data(), (int)jobs.size(), PIVOT_DETECT, PIVOT_BOOST, s0);
+    }
+    // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up and
+    // the workgroup problem, per system
+    parallel([&](int i) {
+        ss_liouv h = hs[i];
+        hipStream_t s = stream_of(h);
+        if (in_batch[(size_t)i]) {
+            h->guarded = ib[(size_t)i].result(s).guarded;
+        } else if (o.ilu == SS_ILU0) {
+            h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+        } else {
+            h->guarded = ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU,
+                                     h->lu_diag, s)
+                             .guarded;
+        }
+        prepare_finish(h, method, o, s, t0);
+        if constexpr (std::is_same<T, float2>::value) {
+            make_wg<T>(h, method, tol, o, h->Ap32, h->LU32, B[(size_t)i], s);
+        } else {
+            make_wg<T>(h, method, tol, o, h->Ap, h->LU, B[(size_t)i], s);
+        }
+        SS_HIP(hipStreamSynchronize(s));
+    });
+    ib.clear();
     const double t_setup = now_ms() - t0;
     std::vector<WgProblem<T>> probs;
     std::vector<int> slot((size_t)count, -1);
