@@ -145,6 +145,10 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 Kerr-chain measurements")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the Kerr serving stream (0 skips the serving measurement)")
+    ap.add_argument("--precs", default="mixed,fp64", help="precisions of the batched step")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MB (the known-size reference for "
+                         "the HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (each solve fits one MI355X; "
@@ -167,17 +171,32 @@ def main():
     out1 = outs[0]
     torch.cuda.synchronize()
 
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(8)
+
     def step(prec):
         """B independent solves: assembly from the device-resident H and
-        collapse operators, then set-up and solve of all B together."""
-        Ls = [ssl.build_liouvillian(Hd, Cd) for _ in range(B)]
+        collapse operators (8 host threads; each handle works on its own
+        stream), then set-up and solve of all B together."""
+        Ls = list(pool.map(lambda _: ssl.build_liouvillian(Hd, Cd), range(B)))
         _, infos = ssl.solve_batch(Ls, args.method, tol=1e-10, outs=outs, prec=prec)
         for L in Ls:
             L.free()
         return infos
 
+    if args.copy_calibration_mb > 0:
+        nb = args.copy_calibration_mb << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log(f"calibration copy: {nb} bytes read and written")
+        del src, dst
+
     results = {}
-    for prec in ("mixed", "fp64"):
+    precs = [p for p in args.precs.split(",") if p]
+    for prec in precs:
         for _ in range(args.warmup):
             step(prec)
         torch.cuda.synchronize()
@@ -196,7 +215,7 @@ def main():
 
     # single-solve latency (one system, the solver's own path choice)
     single = {}
-    for prec in ("mixed", "fp64"):
+    for prec in precs:
         ts = []
         for k in range(6):
             L = ssl.build_liouvillian(Hd, Cd)
@@ -267,7 +286,8 @@ def main():
     if args.serve_requests > 0:
         serving = serve_stream(ssl, qs, np, args.serve_requests)
 
-    m, f = results["mixed"], results["fp64"]
+    m = results["mixed"]
+    f = results.get("fp64")
     line = {
         "metric": "steady-state solves/sec + SpMV HBM GB/s at ||L.rho||<=1e-10, mixed vs FP64",
         "value": m["solves_per_s"],
@@ -286,9 +306,9 @@ def main():
                    "method": args.method, "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0", "batch": B},
         "max_abs_err_vs_oracle": err["mixed"],
         "worst_resid_l2": m["worst_resid"],
-        "fp64": {"solves_per_s": f["solves_per_s"], "ms_per_step": f["ms"], "max_abs_err_vs_oracle": err["fp64"],
-                 "worst_resid_l2": f["worst_resid"], "t_kernel_ms": f["infos"][0]["t_kernel_ms"]},
-        "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"],
+        "fp64": ({"solves_per_s": f["solves_per_s"], "ms_per_step": f["ms"], "max_abs_err_vs_oracle": err["fp64"],
+                  "worst_resid_l2": f["worst_resid"], "t_kernel_ms": f["infos"][0]["t_kernel_ms"]} if f else None),
+        "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"] if f else None,
         "single_solve": single,
         "roofline": roofline,
         "large": large,

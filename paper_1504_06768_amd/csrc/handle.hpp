@@ -69,7 +69,7 @@ struct WgBundle {
 // factors, start vector, scratch).
 template <typename T>
 void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
-             WgBundle<T> &B, hipStream_t s);
+             WgBundle<T> &B, hipStream_t s, bool levels_built = false);
 
 // Unpermute, normalise, certify and copy out the solution x (permuted, fp64).
 int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const SolveStats &st, double *rho_out,

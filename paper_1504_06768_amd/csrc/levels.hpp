@@ -19,6 +19,26 @@ struct LevelSched {
 // level among the rows it depends on.
 void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s);
 
+// The level analysis of many systems in one launch (one workgroup each):
+// job() sets up one system's scratch on its stream, levels_batch runs every
+// job of one side, finish() turns one system's levels into its schedule.
+struct LevelJob {
+    int n;
+    const int *rowptr, *col, *diag;
+    int *lvl;
+    unsigned *status;
+    int *maxlvl;
+};
+struct LevelBuild {
+    DevBuf<int> lvl, misc;
+    DevBuf<unsigned> status;
+    LevelJob job(const Csr<double2> &LU, const int *diag, hipStream_t s);
+    template <bool UPPER>
+    void finish(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s);
+};
+template <bool UPPER>
+void levels_batch(const LevelJob *jobs, int count, hipStream_t s);
+
 // factor entries per row kept in the packed level layout (fewer for
 // complex128 so that three levels of them fit in registers)
 template <typename T> struct WgK;

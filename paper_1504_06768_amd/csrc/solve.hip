@@ -280,14 +280,14 @@ static void init_vectors(ss_liouv h, bool trace, double2 *x, double2 *b, hipStre
 
 template <typename T>
 void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
-             WgBundle<T> &B, hipStream_t s) {
+             WgBundle<T> &B, hipStream_t s, bool levels_built) {
     const int n = h->n;
     const bool trace = is_trace(method);
     B.x.resize((size_t)n);
     B.r.resize((size_t)n);
     B.b.resize((size_t)n);
     init_vectors(h, trace, B.x.get(), B.b.get(), s);
-    build_levels(h->LU.view(), h->lu_diag.get(), B.lo, B.up, s);
+    if (!levels_built) build_levels(h->LU.view(), h->lu_diag.get(), B.lo, B.up, s);
     pack_side<T>(B.lo, LUin.view(), false, B.pl, s);
     pack_side<T>(B.up, LUin.view(), true, B.pu, s);
     B.work.resize((size_t)11 * n);
@@ -330,9 +330,9 @@ void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrB
     P.res = B.res.get();
 }
 template void make_wg<double2>(ss_liouv, int, double, const ss_options &, const CsrBuf<double2> &,
-                               const CsrBuf<double2> &, WgBundle<double2> &, hipStream_t);
+                               const CsrBuf<double2> &, WgBundle<double2> &, hipStream_t, bool);
 template void make_wg<float2>(ss_liouv, int, double, const ss_options &, const CsrBuf<float2> &,
-                              const CsrBuf<float2> &, WgBundle<float2> &, hipStream_t);
+                              const CsrBuf<float2> &, WgBundle<float2> &, hipStream_t, bool);
 
 // Finish a solve: unpermute, normalise the trace, certify with L itself,
 // Hermiticity error, copy rho out (host or device), fill info.
@@ -645,8 +645,10 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
             if (code[(size_t)i] == SS_OK && in_batch[(size_t)i]) jobs.push_back(ijobs[(size_t)i]);
         ilu0_batch(jobs.data(), (int)jobs.size(), PIVOT_DETECT, PIVOT_BOOST, s0);
     }
-    // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up and
-    // the workgroup problem, per system
+    // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up,
+    // scratch of the level analysis, per system
+    std::vector<LevelBuild> lb_lo((size_t)count), lb_up((size_t)count);
+    std::vector<LevelJob> lj_lo((size_t)count), lj_up((size_t)count);
     parallel([&](int i) {
         ss_liouv h = hs[i];
         hipStream_t s = stream_of(h);
@@ -660,14 +662,37 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
                              .guarded;
         }
         prepare_finish(h, method, o, s, t0);
-        if constexpr (std::is_same<T, float2>::value) {
-            make_wg<T>(h, method, tol, o, h->Ap32, h->LU32, B[(size_t)i], s);
-        } else {
-            make_wg<T>(h, method, tol, o, h->Ap, h->LU, B[(size_t)i], s);
-        }
+        lj_lo[(size_t)i] = lb_lo[(size_t)i].job(h->LU.view(), h->lu_diag.get(), s);
+        lj_up[(size_t)i] = lb_up[(size_t)i].job(h->LU.view(), h->lu_diag.get(), s);
         SS_HIP(hipStreamSynchronize(s));
     });
     ib.clear();
+    // stage 6: level analysis of every system, one launch per side
+    {
+        std::vector<LevelJob> lo, up;
+        for (int i = 0; i < count; ++i) {
+            if (code[(size_t)i] != SS_OK || hs[i]->n == 0) continue;
+            lo.push_back(lj_lo[(size_t)i]);
+            up.push_back(lj_up[(size_t)i]);
+        }
+        levels_batch<false>(lo.data(), (int)lo.size(), s0);
+        levels_batch<true>(up.data(), (int)up.size(), s0);
+    }
+    // stage 7: level schedules and the workgroup problem, per system
+    parallel([&](int i) {
+        ss_liouv h = hs[i];
+        hipStream_t s = stream_of(h);
+        lb_lo[(size_t)i].finish<false>(h->LU.view(), h->lu_diag.get(), B[(size_t)i].lo, s);
+        lb_up[(size_t)i].finish<true>(h->LU.view(), h->lu_diag.get(), B[(size_t)i].up, s);
+        if constexpr (std::is_same<T, float2>::value) {
+            make_wg<T>(h, method, tol, o, h->Ap32, h->LU32, B[(size_t)i], s, true);
+        } else {
+            make_wg<T>(h, method, tol, o, h->Ap, h->LU, B[(size_t)i], s, true);
+        }
+        SS_HIP(hipStreamSynchronize(s));
+    });
+    std::vector<LevelBuild>().swap(lb_lo);
+    std::vector<LevelBuild>().swap(lb_up);
     const double t_setup = now_ms() - t0;
     std::vector<WgProblem<T>> probs;
     std::vector<int> slot((size_t)count, -1);

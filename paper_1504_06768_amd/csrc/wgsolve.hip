@@ -71,6 +71,62 @@ __global__ void __launch_bounds__(256) k_levels(int n, const int *rowptr, const 
     }
 }
 
+// Many systems at once, one workgroup each: its threads take the rows in
+// chunks of the workgroup size, in order, so every dependency lies in an
+// earlier chunk (finished) or earlier in the same chunk.
+template <bool UPPER>
+__global__ void __launch_bounds__(1024) k_levels_batch(const LevelJob *jobs) {
+    const LevelJob &J = jobs[blockIdx.x];
+    const int n = J.n;
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+        const int lin = c0 + (int)threadIdx.x;
+        const bool active = lin < n;
+        const int row = UPPER ? n - 1 - lin : lin;
+        int e = 0, ee = 0, m = -1;
+        if (active) {
+            e = UPPER ? J.diag[row] + 1 : J.rowptr[row];
+            ee = UPPER ? J.rowptr[row + 1] : J.diag[row];
+        }
+        bool done = !active;
+        unsigned spins = 0;
+        while (true) {
+            if (!done) {
+                int v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = (e + q < ee) ? ld_int(J.lvl + J.col[e + q]) : -1;
+                int used = 0;
+                bool run = true;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (run && e + q < ee && v[q] >= 0) {
+                        m = max(m, v[q]);
+                        ++used;
+                    } else {
+                        run = false;
+                    }
+                }
+                e += used;
+                if (used) {
+                    spins = 0;
+                } else if (e < ee) {
+                    ++spins;
+                    if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(J.status))) {
+                        atomicOr(J.status, STATUS_SPIN_TIMEOUT);
+                        e = ee;
+                    }
+                }
+                if (e >= ee) {
+                    st_int(J.lvl + row, m + 1);
+                    atomicMax(J.maxlvl, m + 1);
+                    done = true;
+                }
+            }
+            if (__all(done)) break;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_level_count(int n, const int *lvl, int *cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) atomicAdd(&cnt[lvl[i]], 1);
@@ -89,22 +145,31 @@ __global__ void k_fill_i32(int n, int *p, int v) {
     if (i < n) p[i] = v;
 }
 
-template <bool UPPER>
-static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s) {
+LevelJob LevelBuild::job(const Csr<double2> &LU, const int *diag, hipStream_t s) {
     const int n = LU.n;
-    DevBuf<int> lvl((size_t)std::max(n, 1)), misc(2);
-    DevBuf<unsigned> status(1);
+    lvl.resize((size_t)std::max(n, 1));
+    misc.resize(2);
+    status.resize(1);
     SS_HIP(hipMemsetAsync(misc.get(), 0, 2 * sizeof(int), s));
     SS_HIP(hipMemsetAsync(status.get(), 0, sizeof(unsigned), s));
     if (n) {
         k_fill_i32<<<div_up(n, 256), 256, 0, s>>>(n, lvl.get(), -1);
-        BlockCounter bc;
-        bc.init(s);
-        const unsigned grid = (unsigned)div_up(n, 256);
-        k_levels<UPPER><<<grid, 256, 0, s>>>(n, LU.rowptr, LU.col, diag, lvl.get(), bc.ctr.get(), bc.take(grid),
-                                             status.get(), misc.get());
         SS_HIP(hipGetLastError());
     }
+    LevelJob j;
+    j.n = n;
+    j.rowptr = LU.rowptr;
+    j.col = LU.col;
+    j.diag = diag;
+    j.lvl = lvl.get();
+    j.status = status.get();
+    j.maxlvl = misc.get();
+    return j;
+}
+
+template <bool UPPER>
+void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s) {
+    const int n = LU.n;
     int maxl = 0;
     unsigned st = 0;
     d2h(&maxl, misc.get(), 1, s);
@@ -126,6 +191,36 @@ static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hi
         SS_HIP(hipGetLastError());
     }
     SS_HIP(hipStreamSynchronize(s));
+}
+template void LevelBuild::finish<false>(const Csr<double2> &, const int *, LevelSched &, hipStream_t);
+template void LevelBuild::finish<true>(const Csr<double2> &, const int *, LevelSched &, hipStream_t);
+
+template <bool UPPER>
+void levels_batch(const LevelJob *jobs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    DevBuf<LevelJob> dj((size_t)count);
+    h2d(dj.get(), jobs, (size_t)count, s);
+    k_levels_batch<UPPER><<<count, 1024, 0, s>>>(dj.get());
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s));  // the job array is released on return
+}
+template void levels_batch<false>(const LevelJob *, int, hipStream_t);
+template void levels_batch<true>(const LevelJob *, int, hipStream_t);
+
+template <bool UPPER>
+static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s) {
+    const int n = LU.n;
+    LevelBuild lb;
+    LevelJob j = lb.job(LU, diag, s);
+    if (n) {
+        BlockCounter bc;
+        bc.init(s);
+        const unsigned grid = (unsigned)div_up(n, 256);
+        k_levels<UPPER><<<grid, 256, 0, s>>>(n, LU.rowptr, LU.col, diag, j.lvl, bc.ctr.get(), bc.take(grid),
+                                             j.status, j.maxlvl);
+        SS_HIP(hipGetLastError());
+    }
+    lb.finish<UPPER>(LU, diag, ls, s);
 }
 
 void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s) {
