@@ -287,6 +287,20 @@ const char *ss_last_error(void);
  * (a hipStream_t cast to void*; NULL = the library's own stream per handle). */
 int ss_set_stream(void *hip_stream);
 
+/* Route the library's device allocations through caller callbacks (e.g. a
+ * framework's caching allocator): alloc(bytes, ctx) returns device memory or
+ * NULL, free(ptr, ctx) releases it.  Pass NULL callbacks to return to
+ * hipMalloc / hipFree.  Set it before any handle exists and do not change it
+ * while device memory of the library is alive (blocks are returned to the
+ * allocator that made them only by ss_trim_cache or at their release). */
+typedef void *(*ss_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*ss_free_fn)(void *ptr, void *ctx);
+int ss_set_allocator(ss_alloc_fn alloc, ss_free_fn free_fn, void *ctx);
+
+/* Release every device block the library keeps cached for reuse (waits for
+ * the last work that used them). */
+int ss_trim_cache(void);
+
 /* library version string */
 const char *ss_version(void);
 

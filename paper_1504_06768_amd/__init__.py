@@ -12,5 +12,6 @@ from .ss import (  # noqa: F401
     SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE, SS_OP_PRECOND_SYNCFREE,
     SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS,
     SolverError, Liouvillian, Server, apply, bandwidth_profile, build_liouvillian,
-    export_csr, export_perm, library_path, options, prepare, solve, solve_batch, time_operator, version,
+    export_csr, export_perm, library_path, options, prepare, set_allocator, solve, solve_batch, time_operator,
+    trim_cache, version,
 )

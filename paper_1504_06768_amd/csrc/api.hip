@@ -73,6 +73,21 @@ int ss_options_default(ss_options *opt) {
     return SS_OK;
 }
 
+int ss_set_allocator(ss_alloc_fn alloc, ss_free_fn free_fn, void *ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(SS_E_INVALID_ARG, "give both callbacks or neither");
+    return guarded([&]() -> int {
+        ss::set_allocator(alloc, free_fn, ctx);
+        return SS_OK;
+    });
+}
+
+int ss_trim_cache(void) {
+    return guarded([&]() -> int {
+        ss::trim_device_cache();
+        return SS_OK;
+    });
+}
+
 int ss_set_stream(void *hip_stream) {
     ss::set_thread_stream(reinterpret_cast<hipStream_t>(hip_stream));
     return SS_OK;

@@ -40,6 +40,8 @@ void dev_free(void *p);
 void set_current_stream(hipStream_t s);
 // release every cached block (waits for their last uses)
 void trim_device_cache();
+// caller allocator for the underlying blocks (NULL: hipMalloc / hipFree)
+void set_allocator(ss_alloc_fn a, ss_free_fn f, void *ctx);
 // a stream from the library's fixed pool
 hipStream_t pooled_stream();
 

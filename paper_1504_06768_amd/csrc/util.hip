@@ -28,11 +28,13 @@ constexpr size_t CACHE_MAX_TOTAL = size_t(4) << 30;
 struct Cached {
     void *p;
     hipEvent_t ev;
+    bool user;
 };
 
 struct Live {
     size_t cls;      // 0: not cached
     hipStream_t s;   // stream current when allocated
+    bool user;       // made by the caller's allocator
 };
 
 struct Cache {
@@ -50,6 +52,19 @@ Cache &cache() {
 
 thread_local hipStream_t t_current = nullptr;
 
+// optional caller allocator (ss_set_allocator)
+ss_alloc_fn g_user_alloc = nullptr;
+ss_free_fn g_user_free = nullptr;
+void *g_user_ctx = nullptr;
+
+void raw_free(void *p, bool user) {
+    if (user) {
+        if (g_user_free) g_user_free(p, g_user_ctx);
+    } else {
+        (void)hipFree(p);
+    }
+}
+
 size_t size_class(size_t b) {
     size_t c = 256;
     while (c < b) c <<= 1;
@@ -58,6 +73,15 @@ size_t size_class(size_t b) {
 
 void *raw_alloc(size_t bytes) {
     void *p = nullptr;
+    if (g_user_alloc) {
+        p = g_user_alloc(bytes, g_user_ctx);
+        if (!p) {
+            trim_device_cache();
+            p = g_user_alloc(bytes, g_user_ctx);
+        }
+        if (!p) throw Error(SS_E_OOM, "caller allocator returned NULL for " + std::to_string(bytes) + " B");
+        return p;
+    }
     hipError_t e = hipMalloc(&p, bytes);
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
@@ -76,13 +100,20 @@ void *raw_alloc(size_t bytes) {
 
 void set_current_stream(hipStream_t s) { t_current = s; }
 
+void set_allocator(ss_alloc_fn a, ss_free_fn f, void *ctx) {
+    trim_device_cache();
+    g_user_alloc = a;
+    g_user_free = f;
+    g_user_ctx = ctx;
+}
+
 void trim_device_cache() {
     Cache &c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto &kv : c.free_by_cls) {
         for (Cached &b : kv.second) {
             (void)hipEventSynchronize(b.ev);
-            (void)hipFree(b.p);
+            raw_free(b.p, b.user);
             c.events.push_back(b.ev);
         }
         kv.second.clear();
@@ -98,36 +129,37 @@ void *dev_alloc(size_t bytes) {
         auto it = c.free_by_cls.find(cls);
         if (it != c.free_by_cls.end()) {
             std::vector<Cached> &v = it->second;
+            const bool user = g_user_alloc != nullptr;
             for (size_t k = v.size(); k-- > 0;) {
-                if (hipEventQuery(v[k].ev) == hipSuccess) {
+                if (v[k].user == user && hipEventQuery(v[k].ev) == hipSuccess) {
                     void *p = v[k].p;
                     c.events.push_back(v[k].ev);
                     v.erase(v.begin() + (long)k);
                     c.cached -= cls;
-                    c.live[p] = Live{cls, t_current};
+                    c.live[p] = Live{cls, t_current, user};
                     return p;
                 }
             }
             (void)hipGetLastError();  // hipErrorNotReady from the queries
         }
     }
+    const bool user = g_user_alloc != nullptr;
     void *p = raw_alloc(cls ? cls : bytes);
     std::lock_guard<std::mutex> lk(c.mu);
-    c.live[p] = Live{cls, t_current};
+    c.live[p] = Live{cls, t_current, user};
     return p;
 }
 
 void dev_free(void *p) {
     if (!p) return;
     Cache &c = cache();
-    Live l{0, nullptr};
+    Live l{0, nullptr, false};
     {
         std::lock_guard<std::mutex> lk(c.mu);
         auto it = c.live.find(p);
-        if (it != c.live.end()) {
-            l = it->second;
-            c.live.erase(it);
-        }
+        if (it == c.live.end()) return;  // not a block of this allocator
+        l = it->second;
+        c.live.erase(it);
         if (l.cls && c.cached + l.cls <= CACHE_MAX_TOTAL) {
             hipEvent_t ev = nullptr;
             if (!c.events.empty()) {
@@ -140,7 +172,7 @@ void dev_free(void *p) {
             if (ev) {
                 if (!l.s) (void)hipDeviceSynchronize();  // no stream known: wait for everything
                 if (hipEventRecord(ev, l.s) == hipSuccess) {
-                    c.free_by_cls[l.cls].push_back(Cached{p, ev});
+                    c.free_by_cls[l.cls].push_back(Cached{p, ev, l.user});
                     c.cached += l.cls;
                     return;
                 }
@@ -149,7 +181,8 @@ void dev_free(void *p) {
             }
         }
     }
-    (void)hipFree(p);  // uncached: hipFree waits for the device
+    if (l.s) (void)hipStreamSynchronize(l.s);
+    raw_free(p, l.user);  // uncached (hipFree also waits for the device)
 }
 
 // ------------------------------------------------------------ stream pool

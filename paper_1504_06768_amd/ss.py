@@ -95,6 +95,8 @@ def _load():
         "ss_server_destroy": (None, [P]),
         "ss_last_error": (ctypes.c_char_p, []),
         "ss_set_stream": (ctypes.c_int, [P]),
+        "ss_set_allocator": (ctypes.c_int, [P, P, P]),
+        "ss_trim_cache": (ctypes.c_int, []),
         "ss_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -109,7 +111,47 @@ EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_solve", "ss_solve_
             "ss_liouv_shape",
             "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile", "ss_time_operator",
             "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_destroy",
-            "ss_last_error", "ss_set_stream", "ss_version")
+            "ss_last_error", "ss_set_stream", "ss_set_allocator", "ss_trim_cache", "ss_version")
+
+
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None
+
+
+def set_allocator(alloc=None, free=None):
+    """ss_set_allocator: alloc(nbytes) -> device pointer (int), free(ptr);
+    both None restores hipMalloc / hipFree.  The callables are kept alive
+    here; they may be called from the library's set-up threads."""
+    global _allocator_refs
+    if (alloc is None) != (free is None):
+        raise ValueError("give both callbacks or neither")
+    if alloc is None:
+        _check(_lib.ss_set_allocator(None, None, None), "ss_set_allocator")
+        _allocator_refs = None
+        return
+    def _a(n, ctx):
+        try:
+            return int(alloc(int(n))) or None
+        except Exception:  # reported to the library as an allocation failure
+            return None
+
+    def _f(p, ctx):
+        try:
+            free(int(p))
+        except Exception:
+            pass
+
+    a = _ALLOC_T(_a)
+    f = _FREE_T(_f)
+    _check(_lib.ss_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None),
+           "ss_set_allocator")
+    _allocator_refs = (a, f)
+
+
+def trim_cache():
+    """ss_trim_cache: release the device blocks the library keeps for reuse."""
+    _check(_lib.ss_trim_cache(), "ss_trim_cache")
 
 
 def library_path() -> str:

@@ -60,3 +60,46 @@ def test_batch_rejects_gmres_and_repeated_handles():
         ssl.solve_batch([L], "trace_gmres", 1e-10)
     with pytest.raises(ssl.SolverError):
         ssl.solve_batch([L, L], "trace_bicgstab", 1e-10)
+
+
+def test_caller_allocator_is_used_and_gives_the_same_result():
+    """ss_set_allocator with callbacks that call hipMalloc / hipFree of the
+    HIP runtime the library uses: every device block of a solve goes
+    through them, all are returned, and the result is bit-identical."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    s = qs.jaynes_cummings(8, seed=0)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ref, _ = ssl.solve(L, "trace_bicgstab", 1e-10, prec="mixed")
+    L.free()
+    ssl.trim_cache()
+    live = set()
+    calls = {"alloc": 0, "free": 0}
+
+    def alloc(n):
+        p = ctypes.c_void_p()
+        if hip.hipMalloc(ctypes.byref(p), n) != 0:
+            return 0
+        calls["alloc"] += 1
+        live.add(p.value)
+        return p.value
+
+    def free(p):
+        calls["free"] += 1
+        live.discard(p)
+        hip.hipFree(ctypes.c_void_p(p))
+
+    ssl.set_allocator(alloc, free)
+    try:
+        L = ssl.build_liouvillian(s.H, s.c_ops)
+        rho, info = ssl.solve(L, "trace_bicgstab", 1e-10, prec="mixed")
+        (rb,), _ = ssl.solve_batch([L], "trace_bicgstab", 1e-10, prec="mixed")
+        L.free()
+        ssl.trim_cache()
+    finally:
+        ssl.set_allocator(None, None)
+    assert calls["alloc"] > 0 and calls["free"] == calls["alloc"] and not live
+    assert np.array_equal(rho, ref)
+    assert np.array_equal(rb, ref)
