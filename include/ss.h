@@ -81,6 +81,13 @@ typedef struct ss_server_s *ss_server;
 #define SS_TRACE_GMRES      1
 #define SS_INVPOW_BICGSTAB  2
 #define SS_INVPOW_GMRES     3
+/* SS_AUTO: choose between the two drivers from the structure (section
+ * "Numerical Simulations": the trace row can inflate the bandwidth of the
+ * RCM-ordered matrix, and then inverse power is faster).  Both L~ and
+ * L - sigma I are RCM-ordered; if the bandwidth of L~ exceeds 1.5 times that
+ * of L - sigma I, SS_INVPOW_BICGSTAB is used, else SS_TRACE_BICGSTAB.
+ * ss_solve only; info.method reports the choice. */
+#define SS_AUTO             4
 
 /* precision: SS_FP64 runs everything in complex128.  SS_MIXED runs the
  * inner Krylov iterations, ILU factors and SpMV in complex64 and keeps the
@@ -128,6 +135,8 @@ typedef struct {
                                   sync-free over all CUs in row order         */
 #define SS_FLAG_TRSV_BLOCK 32  /* device-wide path: triangular solves in one
                                   workgroup, level by level                   */
+#define SS_FLAG_COND_EST  128  /* fill info.cond_est (one extra application
+                                  of the preconditioner)                      */
 #define SS_FLAG_TRSV_LEVELS 64 /* device-wide path: triangular solves
                                   sync-free over all CUs in level order
                                   (default: BLOCK up to n = 65536, else
@@ -140,7 +149,7 @@ typedef struct {
     int32_t breakdowns;      /* BiCGSTAB restarts after breakdown             */
     int32_t pivots_guarded;  /* ILU pivots replaced by the guard value        */
     int32_t fell_back;       /* 1 if BiCGSTAB fell back to GMRES              */
-    int32_t bandwidth;       /* B of the matrix that was factorised           */
+    int32_t bandwidth;       /* B of the ordered matrix that was factorised   */
     int32_t path;            /* 0 device-wide kernels, 1 workgroup-resident
                                 with the solve vector in global memory, 2
                                 workgroup-resident with it in LDS             */
@@ -150,7 +159,7 @@ typedef struct {
     double resid_l2;         /* ||L vec(rho)||_2 in fp64 with Tr rho = 1      */
     double herm_err;         /* max |rho - rho^+|                             */
     double trace_err;        /* |Tr rho - 1| before normalisation's rounding  */
-    double cond_est;         /* ||(LU)^-1 e||_inf, e = ones                   */
+    double cond_est;         /* ||(LU)^-1 e||_inf, e = ones (SS_FLAG_COND_EST) */
     double fill_factor;      /* nnz_factors / nnz_matrix                      */
     double weight;           /* w used by the trace row                       */
     double t_setup_ms;       /* transform + ordering + factorisation          */
@@ -159,6 +168,8 @@ typedef struct {
                                 events), workgroup-resident path only         */
     double bytes_alg;        /* algorithmic HBM bytes of the iterations:
                                 matrix, factors and vectors once per use      */
+    int32_t method;          /* the method that ran (resolves SS_AUTO)        */
+    int32_t reserved;
 } ss_info;
 
 /* fills *opt with the defaults listed above */

@@ -7,7 +7,7 @@ fails loudly otherwise.
 """
 from .ss import (  # noqa: F401
     SS_FP64, SS_MIXED, SS_ILU0, SS_ILUT, SS_ORDER_RCM, SS_ORDER_NATURAL,
-    SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES,
+    SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES, SS_AUTO,
     SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM,
     SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE, SS_OP_PRECOND_SYNCFREE,
     SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS,

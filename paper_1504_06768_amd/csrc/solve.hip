@@ -91,7 +91,13 @@ static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipSt
             mean_diagonal(h->L, h->d_w.get(), s);
         }
         d2h(&h->w, h->d_w.get(), 1, s);
-        SS_REQUIRE(h->w.x != 0.0 || h->w.y != 0.0, SS_E_INVALID_ARG, "trace-row weight is zero");
+        if (h->w.x == 0.0 && h->w.y == 0.0) {
+            // zero mean diagonal (e.g. N = 1, where L = 0, or no dissipation):
+            // any nonzero weight gives the same rho
+            SS_REQUIRE(o.weight == 0.0, SS_E_INVALID_ARG, "trace-row weight is zero");
+            h->w = mk(1.0, 0.0);
+            h2d(h->d_w.get(), &h->w, 1, s);
+        }
         SS_REQUIRE(o.trace_row < d, SS_E_INVALID_ARG, "trace_row must be < N");
         h->trow = pick_trace_row(h->L, d, o.trace_row, s);
         make_modified(h->L, d, h->trow, h->d_w.get(), h->A, s);
@@ -334,6 +340,30 @@ template void make_wg<double2>(ss_liouv, int, double, const ss_options &, const 
 template void make_wg<float2>(ss_liouv, int, double, const ss_options &, const CsrBuf<float2> &,
                               const CsrBuf<float2> &, WgBundle<float2> &, hipStream_t, bool);
 
+// ||(L U)^-1 e||_inf with e = (1, ..., 1): the paper's stability measure of
+// the preconditioner (section "Iterative Solvers"), with the fp64 factors
+// and the level-scheduled solve.
+__global__ void k_fill_ones(int n, double2 *x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = mk(1.0, 0.0);
+}
+
+static double condition_estimate(ss_liouv h, hipStream_t s) {
+    const int n = h->n;
+    if (n == 0 || h->LU.nnz == 0) return 0.0;
+    DevBuf<double2> e((size_t)n), y((size_t)n), part((size_t)VEC_MAX_BLOCKS), sc(1);
+    k_fill_ones<<<div_up(n, 256), 256, 0, s>>>(n, e.get());
+    SS_HIP(hipGetLastError());
+    Precond<double2> M;
+    M.setup(&h->LU, h->lu_diag.get(), n, s);
+    M.use_levels(h->LU.view(), s);
+    M.apply(e.get(), y.get(), s);
+    norm_inf<double2>(n, y.get(), part.get(), sc.get(), s);
+    double2 v;
+    d2h(&v, sc.get(), 1, s);
+    return v.x;
+}
+
 // Finish a solve: unpermute, normalise the trace, certify with L itself,
 // Hermiticity error, copy rho out (host or device), fill info.
 int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const SolveStats &st, double *rho_out,
@@ -381,6 +411,12 @@ int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const 
         info->herm_err = fin[1].x;
         info->trace_err = sqrt((trx.x - 1.0) * (trx.x - 1.0) + trx.y * trx.y);
         info->weight = h->w.x;
+        info->method = h->p_method;
+        int64_t bw = 0, pf = 0;
+        bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bw, &pf, s);
+        info->bandwidth = (int32_t)bw;
+        info->profile = pf;
+        info->cond_est = (o.flags & SS_FLAG_COND_EST) ? condition_estimate(h, s) : 0.0;
         info->t_setup_ms = h->t_setup_ms;
         info->t_solve_ms = st.t_solve_ms;
         info->t_kernel_ms = st.t_kernel_ms;
@@ -771,8 +807,28 @@ int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_option
     return run_batch<double2>(hs, count, method, tol, o, rho_out, infos, status);
 }
 
+// SS_AUTO: RCM bandwidths of L~ and of L - sigma I decide the driver.
+constexpr double AUTO_BANDWIDTH_RATIO = 1.5;
+
+static int choose_method(ss_liouv h, const ss_options &o) {
+    hipStream_t s = stream_of(h);
+    int64_t bt = 0, bs = 0, p = 0;
+    ss_options oo = o;
+    oo.ilu = SS_ILU0;
+    prepare_transform(h, SS_TRACE_BICGSTAB, oo, s);
+    rcm_order(h->S, h->perm, h->iperm, s);
+    prepare_permute(h, s);
+    bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bt, &p, s);
+    prepare_transform(h, SS_INVPOW_BICGSTAB, oo, s);
+    rcm_order(h->S, h->perm, h->iperm, s);
+    prepare_permute(h, s);
+    bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bs, &p, s);
+    return ((double)bt > AUTO_BANDWIDTH_RATIO * (double)bs) ? SS_INVPOW_BICGSTAB : SS_TRACE_BICGSTAB;
+}
+
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {
     SS_REQUIRE(tol > 0 && std::isfinite(tol), SS_E_INVALID_ARG, "tol must be positive");
+    if (method == SS_AUTO) method = choose_method(h, o);
     prepare(h, method, o);
     int st;
     if (o.prec == SS_MIXED) st = run<float2>(h, method, tol, o, h->Ap32, h->LU32, rho_out, info);

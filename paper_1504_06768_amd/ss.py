@@ -21,17 +21,17 @@ _LIB_PATH = os.path.join(_HERE, "libss.so")
 SS_OK, SS_PENDING = 0, 1
 SS_E_INVALID_ARG, SS_E_OOM, SS_E_NOT_CONVERGED, SS_E_BREAKDOWN = -1, -2, -3, -4
 SS_E_ZERO_PIVOT, SS_E_HIP, SS_E_STATE, SS_E_TIMEOUT = -5, -6, -7, -8
-SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES = 0, 1, 2, 3
+SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES, SS_AUTO = 0, 1, 2, 3, 4
 SS_FP64, SS_MIXED = 0, 1
 SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
-SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS = 16, 32, 64
+SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS, SS_FLAG_COND_EST = 16, 32, 64, 128
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
 SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS = 5, 6, 7
 
-METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3}
+METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3, "auto": 4}
 PRECS = {"fp64": 0, "mixed": 1}
 
 
@@ -63,7 +63,8 @@ class _Info(ctypes.Structure):
                 ("resid_l2", ctypes.c_double), ("herm_err", ctypes.c_double), ("trace_err", ctypes.c_double),
                 ("cond_est", ctypes.c_double), ("fill_factor", ctypes.c_double), ("weight", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
-                ("t_kernel_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double)]
+                ("t_kernel_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double),
+                ("method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -208,7 +209,7 @@ def _ptr(x) -> int:
 
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
-            no_fallback=False, trace_row=-1, path="auto", trsv="auto") -> _Options:
+            no_fallback=False, trace_row=-1, path="auto", trsv="auto", cond_est=False) -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -221,6 +222,8 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     o.flags |= {"auto": 0, "device": SS_FLAG_DEVICE_WIDE, "workgroup": SS_FLAG_WORKGROUP}[path]
     o.flags |= {"auto": 0, "syncfree": SS_FLAG_SYNCFREE, "block": SS_FLAG_TRSV_BLOCK,
                 "levels": SS_FLAG_TRSV_LEVELS}[trsv]
+    if cond_est:
+        o.flags |= SS_FLAG_COND_EST
     return o
 
 

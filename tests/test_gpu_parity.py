@@ -342,3 +342,74 @@ def test_repeated_solves_are_bitwise_identical(prec, path):
     for rho, info in runs[1:]:
         assert info["inner_its"] == runs[0][1]["inner_its"]
         assert np.array_equal(rho, runs[0][0])
+
+
+# ------------------------------------------------------------ degenerate cases
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("path", ["auto", "device"])
+def test_one_state_system(method, path):
+    """N = 1: L = 0 and the only density matrix is [[1]]."""
+    H = sp.csr_matrix(np.array([[0.3]], dtype=np.complex128))
+    L = ssl.build_liouvillian(H, [])
+    rho, info = ssl.solve(L, method, tol=1e-10, path=path)
+    assert info["status"] == 0
+    assert rho.shape == (1, 1) and rho[0, 0] == 1.0
+
+
+def test_pure_decay_gives_the_ground_state():
+    """H = 0 with one lowering operator: rho = |0><0| exactly."""
+    a = qs.destroy(6)
+    L = ssl.build_liouvillian(sp.csr_matrix((6, 6), dtype=np.complex128), [a])
+    for method in METHODS:
+        rho, info = ssl.solve(L, method, tol=1e-12)
+        ref = np.zeros((6, 6))
+        ref[0, 0] = 1.0
+        assert np.max(np.abs(rho - ref)) <= 1e-10, method
+
+
+def test_no_dissipation_returns_a_valid_steady_state():
+    """Without collapse operators every state diagonal in the energy basis is
+    stationary (no unique steady state); the solver returns one of them:
+    unit trace, Hermitian, ||L rho|| within the tolerance."""
+    s = qs.kerr(5)
+    L = ssl.build_liouvillian(s.H, [])
+    rho, info = ssl.solve(L, "invpow_gmres", tol=1e-10, raise_on_error=False)
+    if info["status"] == 0:
+        assert abs(np.trace(rho) - 1) <= 1e-12
+        Lo = liouvillian_sparse(s.H, [])
+        assert np.linalg.norm(Lo @ rho.reshape(-1, order="F")) <= 1e-8
+
+
+def test_batches_with_degenerate_members():
+    Ls = [ssl.build_liouvillian(sp.csr_matrix(np.array([[0.0]], dtype=np.complex128)), []),
+          ssl.build_liouvillian(qs.kerr(6).H, qs.kerr(6).c_ops)]
+    rhos, infos = ssl.solve_batch(Ls, "trace_bicgstab", 1e-10)
+    assert [i["status"] for i in infos] == [0, 0]
+    assert rhos[0][0, 0] == 1.0
+    assert ssl.solve_batch([], "trace_bicgstab", 1e-10) == ([], [])
+
+
+# ------------------------------------------------------------ method selection
+def test_auto_method_follows_the_bandwidth_rule():
+    """SS_AUTO: the spin chain's trace row inflates the RCM bandwidth
+    (the paper's Fig. 1 vs Fig. 3 captions: 167 -> 405 for five spins), so
+    inverse power is chosen; for the Jaynes-Cummings system the two
+    bandwidths are alike and the trace-row driver is chosen.  Results match
+    the dense oracle either way."""
+    for s, want in ((qs.spin_chain(4), ssl.SS_INVPOW_BICGSTAB), (qs.jaynes_cummings(8, seed=0), ssl.SS_TRACE_BICGSTAB)):
+        L = ssl.build_liouvillian(s.H, s.c_ops)
+        rho, info = ssl.solve(L, "auto", tol=1e-10)
+        _say("auto", s.name, info["method"], info["bandwidth"])
+        assert info["method"] == want
+        assert np.max(np.abs(rho - steady_state_dense(s.H, s.c_ops))) <= 1e-8
+
+
+def test_info_reports_bandwidth_profile_and_condition_estimate():
+    s = SMALL["kerr20"]()
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, cond_est=True)
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    assert info["bandwidth"] == oord.bandwidth(Ap)[2]
+    assert info["profile"] == oord.profile(Ap)[2]
+    ref = oilu.condition_estimate(ssl.export_csr(L, ssl.SS_MAT_LU))
+    assert abs(info["cond_est"] - ref) <= 1e-9 * ref
