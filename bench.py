@@ -282,6 +282,23 @@ def main():
             _log(f"kerr chain invpow {prec}: {dt:.2f} s, resid {ci['resid_l2']:.2e}")
         Lc.free()
 
+    # the driven spin chain (dephasing on every spin): the trace row inflates
+    # the RCM bandwidth, and the automatic method choice takes inverse power
+    spin = None
+    if not args.no_large:
+        sc = qs.spin_chain(8)
+        Ls = ssl.build_liouvillian(sc.H, sc.c_ops)
+        spin = {"workload": f"spin_chain_8 (d = {sc.dim}, n = {sc.dim ** 2})"}
+        for prec in ("mixed", "fp64"):
+            t0 = time.perf_counter()
+            _, si = ssl.solve(Ls, "auto", tol=1e-10, prec=prec, raise_on_error=False)
+            dt = time.perf_counter() - t0
+            spin[f"auto_{prec}"] = {"s": dt, "status": si["status"], "method": si["method"],
+                                    "bandwidth": si["bandwidth"], "resid_l2": si["resid_l2"],
+                                    "outer_its": si["outer_its"], "inner_its": si["inner_its"]}
+            _log(f"spin chain auto {prec}: {dt:.3f} s, method {si['method']}, resid {si['resid_l2']:.2e}")
+        Ls.free()
+
     serving = None
     if args.serve_requests > 0:
         serving = serve_stream(ssl, qs, np, args.serve_requests)
@@ -312,6 +329,7 @@ def main():
         "single_solve": single,
         "roofline": roofline,
         "large": large,
+        "spin_chain": spin,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -85,7 +85,10 @@ typedef struct ss_server_s *ss_server;
  * "Numerical Simulations": the trace row can inflate the bandwidth of the
  * RCM-ordered matrix, and then inverse power is faster).  Both L~ and
  * L - sigma I are RCM-ordered; if the bandwidth of L~ exceeds 1.5 times that
- * of L - sigma I, SS_INVPOW_BICGSTAB is used, else SS_TRACE_BICGSTAB.
+ * of L - sigma I, or L~ has a diagonal entry below 1e-12 of its row's
+ * largest (a zero diagonal the trace row does not cover, e.g. populations
+ * under pure dephasing), SS_INVPOW_BICGSTAB is used, else
+ * SS_TRACE_BICGSTAB.
  * ss_solve only; info.method reports the choice. */
 #define SS_AUTO             4
 

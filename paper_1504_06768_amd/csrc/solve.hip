@@ -809,6 +809,18 @@ int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_option
 
 // SS_AUTO: RCM bandwidths of L~ and of L - sigma I decide the driver.
 constexpr double AUTO_BANDWIDTH_RATIO = 1.5;
+// a diagonal entry below this fraction of its row's largest counts as zero
+constexpr double AUTO_ZERO_DIAG = 1e-12;
+
+__global__ void k_count_small_diag(int n, const int *rowptr, const double2 *val, const int *diag, double eps,
+                                   int *cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) m = fmax(m, sqrt(val[e].x * val[e].x + val[e].y * val[e].y));
+    const double2 a = val[diag[i]];
+    if (sqrt(a.x * a.x + a.y * a.y) <= eps * m) atomicAdd(cnt, 1);
+}
 
 static int choose_method(ss_liouv h, const ss_options &o) {
     hipStream_t s = stream_of(h);
@@ -819,11 +831,27 @@ static int choose_method(ss_liouv h, const ss_options &o) {
     rcm_order(h->S, h->perm, h->iperm, s);
     prepare_permute(h, s);
     bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bt, &p, s);
+    // zero diagonal entries that the trace row does not cover (e.g. the
+    // populations under pure dephasing) leave zero-fill ILU of L~ with
+    // boosted pivots: inverse power then
+    int zero_diag = h->diag_added;
+    if (zero_diag == 0) {
+        DevBuf<int> cnt(1);
+        SS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
+        k_count_small_diag<<<div_up(h->n, 256), 256, 0, s>>>(h->n, h->Ap.rowptr.get(), h->Ap.val.get(), h->diag.get(),
+                                                            AUTO_ZERO_DIAG, cnt.get());
+        SS_HIP(hipGetLastError());
+        d2h(&zero_diag, cnt.get(), 1, s);
+    }
     prepare_transform(h, SS_INVPOW_BICGSTAB, oo, s);
     rcm_order(h->S, h->perm, h->iperm, s);
     prepare_permute(h, s);
     bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bs, &p, s);
-    return ((double)bt > AUTO_BANDWIDTH_RATIO * (double)bs) ? SS_INVPOW_BICGSTAB : SS_TRACE_BICGSTAB;
+    if (std::getenv("SS_DEBUG"))
+        std::fprintf(stderr, "[ss] auto: B(L~) = %lld, B(L - sigma I) = %lld, zero diagonals of L~ = %d\n",
+                     (long long)bt, (long long)bs, zero_diag);
+    return (zero_diag > 0 || (double)bt > AUTO_BANDWIDTH_RATIO * (double)bs) ? SS_INVPOW_BICGSTAB
+                                                                              : SS_TRACE_BICGSTAB;
 }
 
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {

@@ -80,3 +80,16 @@ def test_optomechanics_workload(method, prec):
     assert info["status"] == 0
     assert info["resid_l2"] <= 1e-10
     assert abs(np.trace(rho) - 1) <= 1e-12
+
+
+def test_spin_chain_auto_chooses_inverse_power():
+    """Driven 5-spin chain with dephasing (eq. spinchain): SS_AUTO takes
+    inverse power (the trace row inflates the RCM bandwidth) and matches the
+    dense oracle."""
+    s = qs.spin_chain(5)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-6)):
+        rho, info = ssl.solve(L, "auto", tol=1e-10, prec=prec)
+        _say("spin5 auto", prec, info["method"], info["bandwidth"], info["inner_its"])
+        assert info["method"] == ssl.SS_INVPOW_BICGSTAB
+        assert np.max(np.abs(rho - steady_state_dense(s.H, s.c_ops))) <= tol
