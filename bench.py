@@ -52,6 +52,13 @@ def spmv_bytes(n, nnz, s):
     return nnz * (s + 4) + 4 * (n + 1) + 2 * n * s
 
 
+def apply_l_bytes(n):
+    """Algorithmic bytes of one matrix-free application of L: rho read once
+    and the result written once (complex128); the d x d operators are a few
+    kB and stay in the caches."""
+    return 32 * n
+
+
 def _traffic(t_kernel_ms):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter runs (profiles/traffic.json), or None when that file is
@@ -270,16 +277,26 @@ def main():
         t64 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "mixed", 50)
         t128 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "fp64", 50)
         b64, b128 = spmv_bytes(nc, Apc.nnz, 8), spmv_bytes(nc, Apc.nnz, 16)
+        tl = ssl.time_operator(Lc, ssl.SS_OP_SPMV_L, "fp64", 50)
+        tm = ssl.time_operator(Lc, ssl.SS_OP_APPLY_L, "fp64", 50)
+        bl, bm = spmv_bytes(nc, nnzc, 16), apply_l_bytes(nc)
         large = {"workload": "kerr_chain_3x10 (n = 1e6)", "nnz": int(Apc.nnz),
                  "spmv_c64": {"ms": t64, "GB/s": b64 / (t64 * 1e-3) / 1e9, "bytes": b64},
-                 "spmv_c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128}}
+                 "spmv_c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128},
+                 "spmv_L_c128": {"ms": tl, "GB/s": bl / (tl * 1e-3) / 1e9, "bytes": bl},
+                 "apply_L_matrix_free": {"ms": tm, "GB/s": bm / (tm * 1e-3) / 1e9, "bytes": bm,
+                                         "frac": bm / (tm * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                         "vs_spmv_L": tl / tm}}
         for prec in ("mixed", "fp64"):
-            t0 = time.perf_counter()
-            _, ci = ssl.solve(Lc, "invpow_bicgstab", tol=1e-10, prec=prec)
-            dt = time.perf_counter() - t0
-            large[f"solve_invpow_{prec}"] = {"s": dt, "resid_l2": ci["resid_l2"], "outer_its": ci["outer_its"],
-                                             "inner_its": ci["inner_its"], "t_setup_ms": ci["t_setup_ms"]}
-            _log(f"kerr chain invpow {prec}: {dt:.2f} s, resid {ci['resid_l2']:.2e}")
+            for mf in (False, True):
+                t0 = time.perf_counter()
+                _, ci = ssl.solve(Lc, "invpow_bicgstab", tol=1e-10, prec=prec, matrix_free=mf)
+                dt = time.perf_counter() - t0
+                key = f"solve_invpow_{prec}" + ("_matrix_free" if mf else "")
+                large[key] = {"s": dt, "resid_l2": ci["resid_l2"], "outer_its": ci["outer_its"],
+                              "inner_its": ci["inner_its"], "t_setup_ms": ci["t_setup_ms"]}
+                _log(f"kerr chain invpow {prec}{' matrix-free' if mf else ''}: {dt:.2f} s, "
+                     f"resid {ci['resid_l2']:.2e}")
         Lc.free()
 
     # the driven spin chain (dephasing on every spin): the trace row inflates

@@ -144,6 +144,12 @@ typedef struct {
                                   sync-free over all CUs in level order
                                   (default: BLOCK up to n = 65536, else
                                   LEVELS)                                     */
+#define SS_FLAG_MATRIX_FREE 256 /* the fp64 residual of every outer step
+                                  and the final certificate apply L from the
+                                  d x d operators of eq. (lindblad) instead of
+                                  streaming the assembled complex128 matrices
+                                  (same values up to rounding order); implies
+                                  the device-wide path                        */
 
 typedef struct {
     int32_t status;          /* the call's return code                        */
@@ -250,6 +256,12 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
                                     through the level schedule             */
 #define SS_OP_PRECOND_LEVELS   7 /* y = (LU)^-1 x, sync-free solves over all
                                     CUs in level order                     */
+#define SS_OP_APPLY_L          8 /* y = L x (natural order, fp64) evaluated
+                                    without the assembled matrix: vec of
+                                    Gpre X + X Gpost^T + sum_k C_k X C_k^+,
+                                    X the d x d matrix whose columns are the
+                                    consecutive d-blocks of x (eq. lindblad,
+                                    column stacking); needs no ss_prepare  */
 
 /* Apply one operator of the prepared handle to x (n complex, host or
  * device) giving y (n complex, host or device).  prec = SS_FP64 or SS_MIXED:
@@ -258,8 +270,8 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
 int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
 
 /* Time `reps` back-to-back applications of an operator of the prepared
- * handle (SS_OP_SPMV_L, SS_OP_SPMV_APERM or one of the SS_OP_PRECOND*
- * operators; prec as in
+ * handle (SS_OP_SPMV_L, SS_OP_APPLY_L, SS_OP_SPMV_APERM or one of the
+ * SS_OP_PRECOND* operators; prec as in
  * ss_apply) on the handle's stream, bracketed by HIP events; *avg_ms
  * receives the mean time per application.  Input and output vectors are
  * library-owned device scratch.  Used to measure achieved bandwidth. */

@@ -102,7 +102,7 @@ int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cop
         h->N = N;
         h->d = (int)N;
         h->n = (int)(N * N);
-        ss::assemble_liouvillian(H, c_ops, n_cops, N, ss::stream_of(h.get()), h->L);
+        ss::assemble_liouvillian(H, c_ops, n_cops, N, ss::stream_of(h.get()), h->L, h->lin);
         *out = h.release();
         return SS_OK;
     });
@@ -225,10 +225,11 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && x != nullptr && y != nullptr, SS_E_INVALID_ARG, "null argument");
         SS_REQUIRE(prec == SS_FP64 || prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
-        SS_REQUIRE(op >= 0 && op <= 7, SS_E_INVALID_ARG, "unknown operator");
+        SS_REQUIRE(op >= 0 && op <= 8, SS_E_INVALID_ARG, "unknown operator");
         const bool pre = is_precond_op(op);
-        SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
-        SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
+        const bool natural = (op == SS_OP_SPMV_L || op == SS_OP_APPLY_L);
+        SS_REQUIRE(natural || L->prepared, SS_E_STATE, "ss_prepare not called");
+        SS_REQUIRE(natural || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
                    "complex64 operators exist only after a mixed-precision ss_prepare");
         hipStream_t s = ss::stream_of(L);
         const int n = L->n;
@@ -238,6 +239,9 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
         if (op == SS_OP_SPMV_L) {
             const ss::Csr<double2> A = L->L.view();
             ss::spmv<double2>(A, xd.get(), yd.get(), ss::spmv_group(A.n, A.nnz), s);
+        } else if (op == SS_OP_APPLY_L) {
+            ss::lindblad_apply(L->lin.view(), xd.get(), nullptr, 0, ss::mk(0.0, 0.0), nullptr, nullptr, yd.get(),
+                               nullptr, s);
         } else if (prec == SS_FP64) {
             if (op == SS_OP_SPMV_APERM) {
                 const ss::Csr<double2> A = L->Ap.view();
@@ -279,10 +283,10 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && avg_ms != nullptr && reps > 0, SS_E_INVALID_ARG, "bad argument");
         const bool pre = is_precond_op(op);
-        SS_REQUIRE(op == SS_OP_SPMV_L || op == SS_OP_SPMV_APERM || pre, SS_E_INVALID_ARG,
-                   "operator cannot be timed");
-        SS_REQUIRE(op == SS_OP_SPMV_L || L->prepared, SS_E_STATE, "ss_prepare not called");
-        SS_REQUIRE(op == SS_OP_SPMV_L || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
+        const bool natural = (op == SS_OP_SPMV_L || op == SS_OP_APPLY_L);
+        SS_REQUIRE(natural || op == SS_OP_SPMV_APERM || pre, SS_E_INVALID_ARG, "operator cannot be timed");
+        SS_REQUIRE(natural || L->prepared, SS_E_STATE, "ss_prepare not called");
+        SS_REQUIRE(natural || prec == SS_FP64 || L->p_opt.prec == SS_MIXED, SS_E_STATE,
                    "complex64 operators exist only after a mixed-precision ss_prepare");
         hipStream_t s = ss::stream_of(L);
         const int n = L->n;
@@ -300,7 +304,7 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             const ss::CsrBuf<T> *A = nullptr;
             const ss::CsrBuf<T> *LU = nullptr;
             if constexpr (std::is_same<T, double2>::value) {
-                A = (op == SS_OP_SPMV_L) ? &L->L : &L->Ap;
+                A = natural ? &L->L : &L->Ap;
                 LU = &L->LU;
             } else {
                 A = &L->Ap32;
@@ -313,7 +317,12 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             const int g = ss::spmv_group(Av.n, Av.nnz);
             auto once = [&]() {
                 if (pre) M.apply(x.get(), y.get(), s);
-                else ss::spmv<T>(Av, x.get(), y.get(), g, s);
+                else if constexpr (std::is_same<T, double2>::value) {
+                    if (op == SS_OP_APPLY_L)
+                        ss::lindblad_apply(L->lin.view(), x.get(), nullptr, 0, ss::mk(0.0, 0.0), nullptr, nullptr,
+                                           y.get(), nullptr, s);
+                    else ss::spmv<T>(Av, x.get(), y.get(), g, s);
+                } else ss::spmv<T>(Av, x.get(), y.get(), g, s);
             };
             once();  // warm-up
             SS_HIP(hipEventRecord(e0, s));
@@ -323,7 +332,7 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             SS_HIP(hipEventElapsedTime(&ms, e0, e1));
         };
         try {
-            if (prec == SS_FP64 || op == SS_OP_SPMV_L) run(double2{0, 0});
+            if (prec == SS_FP64 || natural) run(double2{0, 0});
             else run(float2{0, 0});
         } catch (...) {
             (void)hipEventDestroy(e0);

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) k_l_fill(RowSources S, int n, const int *
 }
 
 void assemble_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int n_cops, int64_t N, hipStream_t s,
-                          CsrBuf<double2> &L) {
+                          CsrBuf<double2> &L, LindbladBuf &ops) {
     SS_REQUIRE(N >= 1 && N <= 46340, SS_E_INVALID_ARG, "N must be in [1, 46340] so that N^2 < 2^31");
     SS_REQUIRE(n_cops >= 0 && n_cops <= MAX_COPS, SS_E_INVALID_ARG,
                "n_cops must be in [0, " + std::to_string(MAX_COPS) + "]");
@@ -248,6 +248,10 @@ void assemble_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int n_cops, 
     k_l_fill<<<div_up(n, 256), 256, 0, s>>>(S, (int)n, L.rowptr.get(), L.col.get(), L.val.get());
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s));
+    ops.d = d;
+    ops.Gp = std::move(Gp);
+    ops.Gq = std::move(Gq);
+    ops.C = std::move(C);
 }
 
 }  // namespace ss

@@ -20,30 +20,6 @@ int spmv_group(int n, int nnz) {
 }
 
 // ---------------------------------------------------- block partial sums
-template <int K>
-__device__ inline void block_partials(double2 (&v)[K], double2 *partials) {
-    __shared__ double2 sh[K][VEC_BS / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double x = v[k].x, y = v[k].y;
-        for (int off = 32; off > 0; off >>= 1) {
-            x += __shfl_down(x, off, 64);
-            y += __shfl_down(y, off, 64);
-        }
-        if (lane == 0) sh[k][wave] = mk(x, y);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double2 acc = sh[k][0];
-            for (int w = 1; w < VEC_BS / 64; ++w) acc = cadd(acc, sh[k][w]);
-            partials[k * gridDim.x + blockIdx.x] = acc;
-        }
-    }
-}
-
 __global__ void __launch_bounds__(256) k_sum_partials(const double2 *partials, int nb, double2 *out) {
     __shared__ double sx[256], sy[256];
     const int k = blockIdx.x;

@@ -10,6 +10,32 @@ constexpr int VEC_MAX_BLOCKS = 1024;
 
 inline int vec_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(div_up(n, VEC_BS), VEC_MAX_BLOCKS)); }
 
+// Per-block sums of K complex values over a VEC_BS-thread block, written to
+// partials[k * gridDim.x + blockIdx.x] in a fixed order (deterministic).
+template <int K>
+__device__ inline void block_partials(double2 (&v)[K], double2 *partials) {
+    __shared__ double2 sh[K][VEC_BS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k].x, y = v[k].y;
+        for (int off = 32; off > 0; off >>= 1) {
+            x += __shfl_down(x, off, 64);
+            y += __shfl_down(y, off, 64);
+        }
+        if (lane == 0) sh[k][wave] = mk(x, y);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double2 acc = sh[k][0];
+            for (int w = 1; w < VEC_BS / 64; ++w) acc = cadd(acc, sh[k][w]);
+            partials[k * gridDim.x + blockIdx.x] = acc;
+        }
+    }
+}
+
 // lanes per row for the CSR SpMV, from the mean row length
 int spmv_group(int n, int nnz);
 

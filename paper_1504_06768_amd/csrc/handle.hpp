@@ -3,6 +3,7 @@
 #include "blas.hpp"
 #include "ilu.hpp"
 #include "krylov.hpp"
+#include "lindblad.hpp"
 
 struct ss_liouv_s {
     int64_t N = 0;
@@ -10,6 +11,7 @@ struct ss_liouv_s {
     int n = 0;
     hipStream_t own_stream = nullptr;
     ss::CsrBuf<double2> L;  // assembled Liouvillian, natural order
+    ss::LindbladBuf lin;    // its d x d operators (matrix-free application)
 
     // results of the set-up stage (ss_prepare)
     bool prepared = false;

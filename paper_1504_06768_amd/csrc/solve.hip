@@ -265,7 +265,7 @@ constexpr int WG_AUTO_MAX_N = 4096;
 
 bool use_workgroup(ss_liouv h, int method, const ss_options &o) {
     if (is_gmres(method)) return false;
-    if (o.flags & SS_FLAG_DEVICE_WIDE) return false;
+    if (o.flags & (SS_FLAG_DEVICE_WIDE | SS_FLAG_MATRIX_FREE)) return false;
     if (o.flags & SS_FLAG_WORKGROUP) return true;
     return h->n <= WG_AUTO_MAX_N;
 }
@@ -380,9 +380,14 @@ int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const 
         k_hermitize<<<div_up(n, 256), 256, 0, s>>>(d, rho.get(), Lr.get());
         SS_HIP(hipMemcpyAsync(rho.get(), Lr.get(), sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
     }
-    const Csr<double2> Lv = h->L.view();
-    spmv<double2>(Lv, rho.get(), Lr.get(), spmv_group(Lv.n, Lv.nnz), s);
-    norm2<double2>(n, Lr.get(), part.get(), sc + 1, s);
+    if (o.flags & SS_FLAG_MATRIX_FREE) {
+        lindblad_apply(h->lin.view(), rho.get(), nullptr, 0, mk(0.0, 0.0), nullptr, nullptr, Lr.get(), part.get(), s);
+        sum_partials(part.get(), lindblad_blocks(d), 1, sc + 1, s);
+    } else {
+        const Csr<double2> Lv = h->L.view();
+        spmv<double2>(Lv, rho.get(), Lr.get(), spmv_group(Lv.n, Lv.nnz), s);
+        norm2<double2>(n, Lr.get(), part.get(), sc + 1, s);
+    }
     const int nbh = vec_blocks(n);
     k_herm_err<<<nbh, 256, 0, s>>>(d, rho.get(), part.get());
     k_max_part<<<1, 64, 0, s>>>(part.get(), nbh, sc + 2);
@@ -511,6 +516,12 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         K.init(Ain.view(), &M, s);
         const Csr<double2> A64 = h->Ap.view();
         const int gA = spmv_group(A64.n, A64.nnz);
+        // matrix-free residual: x back to the natural order, then L applied
+        // from the d x d operators with the transform and the ordering folded
+        // into the same kernel
+        const bool mfree = (o.flags & SS_FLAG_MATRIX_FREE) != 0;
+        const LindbladOp lin = h->lin.view();
+        DevBuf<double2> rho_nat(mfree ? (size_t)n : 0);
         DevBuf<double2> r((size_t)n), part(4 * (size_t)VEC_MAX_BLOCKS), scal(16);
         DevBuf<T> bT((size_t)n), dT((size_t)n);
         double2 *sc = scal.get();
@@ -520,9 +531,16 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
             double2 hs[3];
             double resid;
             if (trace) {
-                spmv_residual(A64, bvec, x, r.get(), part.get(), gA, s);
-                sum_partials(part.get(), vec_blocks(n), 1, sc, s);
                 gather_sum(d, h->tpos.get(), x, sc + 1, s);
+                if (mfree) {
+                    unpermute(n, h->iperm.get(), x, rho_nat.get(), s);
+                    lindblad_apply(lin, rho_nat.get(), h->iperm.get(), h->trow, h->w, sc + 1, bvec, r.get(),
+                                   part.get(), s);
+                    sum_partials(part.get(), lindblad_blocks(d), 1, sc, s);
+                } else {
+                    spmv_residual(A64, bvec, x, r.get(), part.get(), gA, s);
+                    sum_partials(part.get(), vec_blocks(n), 1, sc, s);
+                }
                 k_copy_d2<<<1, 1, 0, s>>>(r.get() + h->q0, sc + 2);
                 SS_HIP(hipGetLastError());
                 d2h(hs, sc, 3, s);
@@ -542,11 +560,18 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
                 h2d(sc + 4, &den, 1, s);
             } else {
                 // r = L x = (L - sigma I) x + sigma x
-                spmv_residual(A64, nullptr, x, r.get(), part.get(), gA, s);
-                double2 sg = mk(o.sigma, 0.0);
-                h2d(sc + 5, &sg, 1, s);
-                axpy_widen<double2>(n, sc + 5, x, r.get(), s);
-                norm2<double2>(n, r.get(), part.get(), sc, s);
+                if (mfree) {
+                    unpermute(n, h->iperm.get(), x, rho_nat.get(), s);
+                    lindblad_apply(lin, rho_nat.get(), h->iperm.get(), 0, mk(0.0, 0.0), nullptr, nullptr, r.get(),
+                                   part.get(), s);
+                    sum_partials(part.get(), lindblad_blocks(d), 1, sc, s);
+                } else {
+                    spmv_residual(A64, nullptr, x, r.get(), part.get(), gA, s);
+                    double2 sg = mk(o.sigma, 0.0);
+                    h2d(sc + 5, &sg, 1, s);
+                    axpy_widen<double2>(n, sc + 5, x, r.get(), s);
+                    norm2<double2>(n, r.get(), part.get(), sc, s);
+                }
                 gather_sum(d, h->tpos.get(), x, sc + 1, s);
                 d2h(hs, sc, 2, s);
                 const double trm = sqrt(hs[1].x * hs[1].x + hs[1].y * hs[1].y);
@@ -803,6 +828,8 @@ int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_option
     SS_REQUIRE(tol > 0 && std::isfinite(tol), SS_E_INVALID_ARG, "tol must be positive");
     SS_REQUIRE(method == SS_TRACE_BICGSTAB || method == SS_INVPOW_BICGSTAB, SS_E_INVALID_ARG,
                "batched solves use BiCGSTAB (the workgroup-resident solver)");
+    SS_REQUIRE(!(o.flags & SS_FLAG_MATRIX_FREE), SS_E_INVALID_ARG,
+               "SS_FLAG_MATRIX_FREE implies the device-wide path; batched solves run the workgroup-resident solver");
     if (o.prec == SS_MIXED) return run_batch<float2>(hs, count, method, tol, o, rho_out, infos, status);
     return run_batch<double2>(hs, count, method, tol, o, rho_out, infos, status);
 }

@@ -27,9 +27,10 @@ SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
 SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS, SS_FLAG_COND_EST = 16, 32, 64, 128
+SS_FLAG_MATRIX_FREE = 256
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
-SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS = 5, 6, 7
+SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS, SS_OP_APPLY_L = 5, 6, 7, 8
 
 METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3, "auto": 4}
 PRECS = {"fp64": 0, "mixed": 1}
@@ -209,7 +210,8 @@ def _ptr(x) -> int:
 
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
-            no_fallback=False, trace_row=-1, path="auto", trsv="auto", cond_est=False) -> _Options:
+            no_fallback=False, trace_row=-1, path="auto", trsv="auto", cond_est=False,
+            matrix_free=False) -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -224,6 +226,8 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
                 "levels": SS_FLAG_TRSV_LEVELS}[trsv]
     if cond_est:
         o.flags |= SS_FLAG_COND_EST
+    if matrix_free:
+        o.flags |= SS_FLAG_MATRIX_FREE
     return o
 
 

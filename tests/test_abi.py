@@ -56,3 +56,15 @@ def test_product_package_does_not_touch_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert re.search(r"\boracle\b", text) is None, f
+
+
+def test_binding_constants_match_the_header():
+    """Every SS_* constant the binding defines has the header's value."""
+    from paper_1504_06768_amd import ss
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(SS_[A-Z0-9_]+)\s+(-?\d+)\b", src)}
+    assert "SS_OP_APPLY_L" in defs and "SS_FLAG_MATRIX_FREE" in defs
+    mismatched = {k: (v, getattr(ss, k)) for k, v in defs.items() if hasattr(ss, k) and getattr(ss, k) != v}
+    assert not mismatched
+    for k in ("SS_OP_APPLY_L", "SS_FLAG_MATRIX_FREE", "SS_AUTO", "SS_FLAG_COND_EST", "SS_OP_PRECOND_LEVELS"):
+        assert getattr(ss, k) == defs[k]
