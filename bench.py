@@ -178,14 +178,11 @@ def main():
     out1 = outs[0]
     torch.cuda.synchronize()
 
-    from concurrent.futures import ThreadPoolExecutor
-    pool = ThreadPoolExecutor(8)
-
     def step(prec):
-        """B independent solves: assembly from the device-resident H and
-        collapse operators (8 host threads; each handle works on its own
-        stream), then set-up and solve of all B together."""
-        Ls = list(pool.map(lambda _: ssl.build_liouvillian(Hd, Cd), range(B)))
+        """B independent solves: batched assembly of B Liouvillians from the
+        device-resident H and collapse operators, then set-up and solve of
+        all B together."""
+        Ls = ssl.build_liouvillian_batch([(Hd, Cd)] * B)
         _, infos = ssl.solve_batch(Ls, args.method, tol=1e-10, outs=outs, prec=prec)
         for L in Ls:
             L.free()

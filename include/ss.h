@@ -194,6 +194,18 @@ int ss_options_default(ss_options *opt);
 int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cops,
                          int64_t N, ss_liouv *out);
 
+/* Assemble count Liouvillians together: system k has H[k] (N_k = H[k].n)
+ * and the n_cops[k] collapse operators c_ops[k][0 .. n_cops[k]) (c_ops[k]
+ * may be NULL when n_cops[k] == 0).  Systems whose arrays are all device
+ * memory and N_k <= 1024 are assembled by one set of launches for the whole
+ * batch (the host waits twice per batch instead of several times per
+ * system); any other system is built as by ss_build_liouvillian.  The
+ * result is the same L as ss_build_liouvillian gives.  out[k] receives a new
+ * handle.  On error every out[k] is NULL, no handle is left allocated, and
+ * ss_last_error names the first invalid system. */
+int ss_build_liouvillian_batch(int32_t count, const ss_csr_z *H, const ss_csr_z *const *c_ops,
+                               const int32_t *n_cops, ss_liouv *out);
+
 /* Solve for the steady state.  method: SS_TRACE_* or SS_INVPOW_*; tol: the
  * target for ||L vec(rho)||_2 with Tr rho = 1; opt: NULL for defaults.
  * rho_out: N*N complex (2*N*N doubles), column-major (= vec order), host or

@@ -108,6 +108,67 @@ int ss_build_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cop
     });
 }
 
+int ss_build_liouvillian_batch(int32_t count, const ss_csr_z *H, const ss_csr_z *const *c_ops,
+                               const int32_t *n_cops, ss_liouv *out) {
+    std::vector<std::unique_ptr<ss_liouv_s>> hs;
+    const int rc = guarded([&]() -> int {
+        SS_REQUIRE(count >= 0, SS_E_INVALID_ARG, "negative count");
+        if (count == 0) return SS_OK;
+        SS_REQUIRE(out != nullptr && H != nullptr && n_cops != nullptr, SS_E_INVALID_ARG, "null argument");
+        for (int k = 0; k < count; ++k) out[k] = nullptr;
+        std::vector<int> batched, single;
+        for (int k = 0; k < count; ++k) {
+            bool dev = ss::batch_assembly_fits(H[k].n) && n_cops[k] >= 0 && n_cops[k] <= ss::MAX_COPS &&
+                       (n_cops[k] == 0 || (c_ops != nullptr && c_ops[k] != nullptr));
+            auto on_device = [](const ss_csr_z &m) {
+                return m.indptr && ss::is_device_ptr(m.indptr) &&
+                       (m.nnz == 0 || (m.indices && m.data && ss::is_device_ptr(m.indices) && ss::is_device_ptr(m.data)));
+            };
+            if (dev) dev = on_device(H[k]);
+            for (int c = 0; dev && c < n_cops[k]; ++c) dev = on_device(c_ops[k][c]);
+            (dev ? batched : single).push_back(k);
+            std::unique_ptr<ss_liouv_s> h(new ss_liouv_s());
+            h->own_stream = ss::pooled_stream();
+            h->N = H[k].n;
+            h->d = (int)H[k].n;
+            h->n = (int)(H[k].n * H[k].n);
+            hs.push_back(std::move(h));
+        }
+        if (!batched.empty()) {
+            std::vector<ss_csr_z> bH;
+            std::vector<const ss_csr_z *> bC;
+            std::vector<int> bn;
+            std::vector<ss::AsmTarget> tg;
+            for (int k : batched) {
+                bH.push_back(H[k]);
+                bC.push_back(n_cops[k] ? c_ops[k] : nullptr);
+                bn.push_back(n_cops[k]);
+                ss_liouv h = hs[(size_t)k].get();
+                tg.push_back(ss::AsmTarget{&h->L, &h->lin, ss::stream_of(h)});
+            }
+            hipStream_t s = ss::stream_of(hs[(size_t)batched[0]].get());
+            ss::assemble_batch((int)batched.size(), bH.data(), bC.data(), bn.data(), tg.data(), s);
+        }
+        for (int k : single) {
+            ss_liouv h = hs[(size_t)k].get();
+            SS_REQUIRE(n_cops[k] == 0 || c_ops != nullptr, SS_E_INVALID_ARG, "c_ops is NULL");
+            ss::assemble_liouvillian(&H[k], n_cops[k] ? c_ops[k] : nullptr, n_cops[k], H[k].n, ss::stream_of(h), h->L,
+                                     h->lin);
+        }
+        for (int k = 0; k < count; ++k) out[k] = hs[(size_t)k].release();
+        return SS_OK;
+    });
+    if (rc != SS_OK) {
+        for (auto &h : hs) {
+            if (h && h->own_stream) ss::set_current_stream(h->own_stream);
+            h.reset();
+        }
+        if (out)
+            for (int k = 0; k < count; ++k) out[k] = nullptr;
+    }
+    return rc;
+}
+
 void ss_liouv_free(ss_liouv L) {
     if (!L) return;
     // the stream belongs to the pool: its work is left to finish, and every

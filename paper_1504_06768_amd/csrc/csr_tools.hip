@@ -124,6 +124,7 @@ __global__ void k_scatter_transpose(int n, const int *rowptr, const int *col, co
 template <typename T>
 void transpose(const CsrBuf<T> &A, CsrBuf<T> &At, hipStream_t s, bool with_values) {
     const int n = A.n, nnz = A.nnz;
+    StreamScope scope(s);
     At.alloc(n, nnz);
     DevBuf<int> cnt((size_t)n + 1);
     SS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (n + 1), s));
@@ -143,7 +144,6 @@ void transpose(const CsrBuf<T> &A, CsrBuf<T> &At, hipStream_t s, bool with_value
     }
     sort_rows<T>(n, At.rowptr.get(), tcol.get(), with_values ? tval.get() : nullptr, At.col.get(),
                  with_values ? At.val.get() : nullptr, s);
-    SS_HIP(hipStreamSynchronize(s));
 }
 template void transpose<double2>(const CsrBuf<double2> &, CsrBuf<double2> &, hipStream_t, bool);
 

@@ -664,12 +664,22 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
     };
     const double t0 = now_ms();
     hipStream_t s0 = stream_of(hs[0]);
+    const bool dbg = std::getenv("SS_DEBUG") != nullptr;
+    double tmark = t0;
+    auto mark = [&](const char *name) {
+        if (!dbg) return;
+        SS_HIP(hipStreamSynchronize(s0));
+        const double t = now_ms();
+        std::fprintf(stderr, "[ss] batch of %d: %-22s %8.3f ms\n", count, name, t - tmark);
+        tmark = t;
+    };
     // stage 1: transform and symmetrised pattern, per system
     parallel([&](int i) {
         hipStream_t s = stream_of(hs[i]);
         prepare_transform(hs[i], method, o, s);
         SS_HIP(hipStreamSynchronize(s));
     });
+    mark("transform+pattern");
     // stage 2: RCM of every graph in one launch (small graphs), else per system
     const bool rcm = o.ordering == SS_ORDER_RCM;
     std::vector<RcmScratch> rs((size_t)count);
@@ -682,6 +692,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         }
         rcm_batch(jobs.data(), (int)jobs.size(), s0);
     }
+    mark("rcm (batched)");
     // stage 3: remaining orderings, P A P^T, diagonal positions, per system
     std::vector<Ilu0Batch> ib((size_t)count);
     std::vector<Ilu0Job> ijobs((size_t)count);
@@ -699,6 +710,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         SS_HIP(hipStreamSynchronize(s));
     });
     rs.clear();
+    mark("permute+ilu prep");
     // stage 4: ILU(0) of every system in one launch
     {
         std::vector<Ilu0Job> jobs;
@@ -706,6 +718,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
             if (code[(size_t)i] == SS_OK && in_batch[(size_t)i]) jobs.push_back(ijobs[(size_t)i]);
         ilu0_batch(jobs.data(), (int)jobs.size(), PIVOT_DETECT, PIVOT_BOOST, s0);
     }
+    mark("ilu0 (batched)");
     // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up,
     // scratch of the level analysis, per system
     std::vector<LevelBuild> lb_lo((size_t)count), lb_up((size_t)count);
@@ -728,6 +741,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         SS_HIP(hipStreamSynchronize(s));
     });
     ib.clear();
+    mark("ilu result+finish prep");
     // stage 6: level analysis of every system, one launch per side
     {
         std::vector<LevelJob> lo, up;
@@ -739,6 +753,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         levels_batch<false>(lo.data(), (int)lo.size(), s0);
         levels_batch<true>(up.data(), (int)up.size(), s0);
     }
+    mark("levels (batched)");
     // stage 7: level schedules and the workgroup problem, per system
     parallel([&](int i) {
         ss_liouv h = hs[i];
@@ -754,6 +769,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
     });
     std::vector<LevelBuild>().swap(lb_lo);
     std::vector<LevelBuild>().swap(lb_up);
+    mark("schedules+wg problem");
     const double t_setup = now_ms() - t0;
     std::vector<WgProblem<T>> probs;
     std::vector<int> slot((size_t)count, -1);
@@ -783,6 +799,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         (void)hipEventDestroy(e1);
     }
     const double t_solve = now_ms() - t1;
+    mark("workgroup solve");
     const int path = wg_fits_lds((size_t)max_n, sizeof(T), max_lev) ? 2 : 1;
     parallel([&](int i) {
         ss_liouv h = hs[i];
@@ -811,6 +828,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
                                  infos ? infos + i : nullptr, s);
         if (infos) infos[i].t_setup_ms = t_setup;
     });
+    mark("finish (+ fallbacks)");
     int first = SS_OK;
     for (int i = 0; i < count; ++i) {
         if (status) status[i] = code[(size_t)i];

@@ -36,8 +36,19 @@ struct Error : std::runtime_error {
 // ------------------------------------------------------------ device memory
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
-// stream on which the calling thread issues its work (tags its allocations)
+// stream on which the calling thread issues its work: blocks allocated
+// meanwhile are tagged with it, and their release waits (through an event on
+// it) for the work queued there, never for the host
 void set_current_stream(hipStream_t s);
+hipStream_t current_stream();
+// the calling thread's current stream is s for the lifetime of the scope
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s) : prev(current_stream()) { set_current_stream(s); }
+    ~StreamScope() { set_current_stream(prev); }
+    StreamScope(const StreamScope &) = delete;
+    StreamScope &operator=(const StreamScope &) = delete;
+};
 // release every cached block (waits for their last uses)
 void trim_device_cache();
 // caller allocator for the underlying blocks (NULL: hipMalloc / hipFree)

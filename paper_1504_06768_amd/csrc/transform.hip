@@ -47,12 +47,12 @@ __global__ void k_mean_finish(int nparts, const double2 *partial, int n, double2
 
 void mean_diagonal(const CsrBuf<double2> &L, double2 *d_out, hipStream_t s) {
     constexpr int NB = 256;
+    StreamScope scope(s);
     DevBuf<double2> part(NB);
     k_diag_partial<<<NB, 256, 0, s>>>(L.n, L.rowptr.get(), L.col.get(), L.val.get(), part.get());
     SS_HIP(hipGetLastError());
     k_mean_finish<<<1, 64, 0, s>>>(NB, part.get(), L.n, d_out);
     SS_HIP(hipGetLastError());
-    SS_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------- modified
@@ -204,6 +204,7 @@ static void finish_rows(CsrBuf<double2> &A, int n, DevBuf<int> &cnt, hipStream_t
 
 void make_modified(const CsrBuf<double2> &L, int d, int rt, const double2 *d_w, CsrBuf<double2> &A, hipStream_t s) {
     const int n = L.n;
+    StreamScope scope(s);
     DevBuf<int> cnt((size_t)n + 1);
     k_mod_count<<<div_up(n, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(), d_w, cnt.get());
     SS_HIP(hipGetLastError());
@@ -211,11 +212,11 @@ void make_modified(const CsrBuf<double2> &L, int d, int rt, const double2 *d_w, 
     k_mod_fill<<<div_up(n, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(), d_w,
                                               A.rowptr.get(), A.col.get(), A.val.get());
     SS_HIP(hipGetLastError());
-    SS_HIP(hipStreamSynchronize(s));
 }
 
 void make_shifted(const CsrBuf<double2> &L, double sigma, CsrBuf<double2> &A, hipStream_t s) {
     const int n = L.n;
+    StreamScope scope(s);
     DevBuf<int> cnt((size_t)n + 1);
     k_shift_count<<<div_up(n, 256), 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma, cnt.get());
     SS_HIP(hipGetLastError());
@@ -223,7 +224,6 @@ void make_shifted(const CsrBuf<double2> &L, double sigma, CsrBuf<double2> &A, hi
     k_shift_fill<<<div_up(n, 256), 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma,
                                                 A.rowptr.get(), A.col.get(), A.val.get());
     SS_HIP(hipGetLastError());
-    SS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace ss

@@ -99,6 +99,7 @@ void *raw_alloc(size_t bytes) {
 }  // namespace
 
 void set_current_stream(hipStream_t s) { t_current = s; }
+hipStream_t current_stream() { return t_current; }
 
 void set_allocator(ss_alloc_fn a, ss_free_fn f, void *ctx) {
     trim_device_cache();
@@ -130,7 +131,9 @@ void *dev_alloc(size_t bytes) {
         if (it != c.free_by_cls.end()) {
             std::vector<Cached> &v = it->second;
             const bool user = g_user_alloc != nullptr;
-            for (size_t k = v.size(); k-- > 0;) {
+            // oldest first: those are the blocks whose last use has most
+            // likely completed, so the first query usually succeeds
+            for (size_t k = 0; k < v.size(); ++k) {
                 if (v[k].user == user && hipEventQuery(v[k].ev) == hipSuccess) {
                     void *p = v[k].p;
                     c.events.push_back(v[k].ev);
@@ -269,6 +272,7 @@ __global__ void k_copy_int(int *dst, const int *src) { *dst = *src; }
 // Exclusive scan: out[i] = sum_{j<i} in[j] for i < n, out[n] = total.
 static void scan_rec(const int *in, int *out, int64_t n, hipStream_t s) {
     const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    StreamScope scope(s);  // sums is released behind the kernels that read it
     DevBuf<int> sums((size_t)nb + 1);
     k_scan_block<<<(unsigned)nb, SCAN_T, 0, s>>>(in, out, n, sums.get());
     SS_HIP(hipGetLastError());
@@ -281,8 +285,6 @@ static void scan_rec(const int *in, int *out, int64_t n, hipStream_t s) {
         k_copy_int<<<1, 1, 0, s>>>(out + n, sums.get());
     }
     SS_HIP(hipGetLastError());
-    // sums must outlive the kernels that read it
-    SS_HIP(hipStreamSynchronize(s));
 }
 
 int64_t scan_exclusive(const int *in, int *out, int64_t n, hipStream_t s, bool want_total) {

@@ -80,6 +80,7 @@ def _load():
     sig = {
         "ss_options_default": (ctypes.c_int, [P]),
         "ss_build_liouvillian": (ctypes.c_int, [P, P, I32, I64, P]),
+        "ss_build_liouvillian_batch": (ctypes.c_int, [ctypes.c_int32, P, P, P, P]),
         "ss_solve": (ctypes.c_int, [P, I32, D, P, P, P]),
         "ss_solve_batch": (ctypes.c_int, [P, I32, I32, D, P, P, P, P]),
         "ss_liouv_free": (None, [P]),
@@ -109,8 +110,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_solve", "ss_solve_batch", "ss_liouv_free",
-            "ss_liouv_shape",
+EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_build_liouvillian_batch", "ss_solve",
+            "ss_solve_batch", "ss_liouv_free", "ss_liouv_shape",
             "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile", "ss_time_operator",
             "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_destroy",
             "ss_last_error", "ss_set_stream", "ss_set_allocator", "ss_trim_cache", "ss_version")
@@ -276,6 +277,31 @@ def build_liouvillian(H, c_ops: Iterable = ()) -> Liouvillian:
     _check(_lib.ss_build_liouvillian(ctypes.byref(Hc.s), arr if cs else None, len(cs), N, ctypes.byref(h)),
            "ss_build_liouvillian")
     return Liouvillian(h.value, N)
+
+
+def build_liouvillian_batch(systems) -> list:
+    """ss_build_liouvillian_batch: assemble many Liouvillians together.
+    `systems` is a sequence of (H, c_ops) pairs in any form build_liouvillian
+    takes; returns one Liouvillian per system."""
+    systems = list(systems)
+    k = len(systems)
+    if k == 0:
+        return []
+    keep = []
+    Hs = (_Csr * k)()
+    arrs = (ctypes.c_void_p * k)()
+    ncs = (ctypes.c_int32 * k)()
+    for i, (H, c_ops) in enumerate(systems):
+        Hc = _HostCsr(H)
+        cs = [_HostCsr(c) for c in c_ops]
+        arr = (_Csr * max(len(cs), 1))(*[c.s for c in cs])
+        keep.append((Hc, cs, arr))
+        Hs[i] = Hc.s
+        arrs[i] = ctypes.cast(arr, ctypes.c_void_p) if cs else None
+        ncs[i] = len(cs)
+    hs = (ctypes.c_void_p * k)()
+    _check(_lib.ss_build_liouvillian_batch(k, Hs, arrs, ncs, hs), "ss_build_liouvillian_batch")
+    return [Liouvillian(hs[i], int(Hs[i].n)) for i in range(k)]
 
 
 def solve(L: Liouvillian, method="trace_bicgstab", tol: float = 1e-10, out=None, raise_on_error=True,

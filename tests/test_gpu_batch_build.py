@@ -1,0 +1,121 @@
+"""Batched assembly (ss_build_liouvillian_batch) against assembly one system
+at a time and against the oracle (GPU required).
+
+Both assemblies add every entry's terms in the same order, so the batched L
+must equal the single-system L bit for bit (row pointers, columns and
+values), and the d x d operators kept for the matrix-free product must give
+the same L x.  Against the oracle's Kronecker assembly the bar is the
+assembly parity bar, 1e-14 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import qsystems as qs
+from conftest import load_product
+from oracle.liouvillian import liouvillian_sparse
+
+pytestmark = pytest.mark.gpu
+ssl = load_product()
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _dev(m):
+    A = sp.csr_matrix(m, dtype=np.complex128)
+    A.sum_duplicates()
+    A.sort_indices()
+    return (torch.from_numpy(np.ascontiguousarray(A.indptr, dtype=np.int64)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(A.indices, dtype=np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(A.data)).cuda(), A.shape[0])
+
+
+def _systems():
+    k5 = qs.kerr(5)
+    return [qs.config(1), qs.jaynes_cummings(8, seed=0), qs.random_lindblad(7, 3, seed=4), qs.spin_chain(3),
+            qs.optomechanics(3, 5, nth=1.0), qs.two_level_atom(),
+            qs.System("one", sp.csr_matrix(np.array([[0.3]], dtype=np.complex128)), []),
+            qs.System("closed", k5.H, []),
+            qs.System("decay", sp.csr_matrix((6, 6), dtype=np.complex128), [qs.destroy(6)]),
+            qs.config(2)]
+
+
+def _same(La, Lb):
+    A = ssl.export_csr(La, ssl.SS_MAT_L)
+    B = ssl.export_csr(Lb, ssl.SS_MAT_L)
+    return (np.array_equal(A.indptr, B.indptr) and np.array_equal(A.indices, B.indices)
+            and np.array_equal(A.data, B.data))
+
+
+def _check_batch(systems, Ls):
+    for s, L in zip(systems, Ls):
+        ref = ssl.build_liouvillian(s.H, s.c_ops)
+        assert L.N == s.dim
+        assert _same(L, ref), s.name
+        Lo = liouvillian_sparse(s.H, s.c_ops)
+        Lg = ssl.export_csr(L, ssl.SS_MAT_L)
+        scale = max(abs(Lo).max(), 1e-300)
+        assert abs(Lg - Lo).max() <= 1e-14 * scale, s.name
+        x = np.random.default_rng(3).standard_normal(s.dim ** 2) * (1 + 0.5j)
+        assert np.array_equal(ssl.apply(L, ssl.SS_OP_APPLY_L, x), ssl.apply(ref, ssl.SS_OP_APPLY_L, x)), s.name
+
+
+def test_batch_build_equals_single_builds_device_inputs():
+    systems = _systems()
+    _say("batch build", [s.dim for s in systems])
+    Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
+    _check_batch(systems, Ls)
+
+
+def test_batch_build_host_inputs_and_mixed_batches():
+    """Host arrays take the one-system path; a batch may mix both kinds."""
+    systems = _systems()[:6]
+    items = [((s.H, s.c_ops) if k % 2 else (_dev(s.H), [_dev(c) for c in s.c_ops])) for k, s in enumerate(systems)]
+    _check_batch(systems, ssl.build_liouvillian_batch(items))
+    assert ssl.build_liouvillian_batch([]) == []
+
+
+def test_batch_build_in_chunks(monkeypatch):
+    """A staging cap of 1 MB splits 40 systems into several chunks."""
+    monkeypatch.setenv("SS_ASM_STAGE_MB", "1")
+    rng = np.random.default_rng(0)
+    systems = [qs.kerr(int(n), delta=float(dl)) for n, dl in zip(rng.integers(10, 61, 40), rng.uniform(-1, 1, 40))]
+    Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
+    _check_batch(systems[:6], Ls[:6])
+    for s, L in zip(systems, Ls):
+        assert _same(L, ssl.build_liouvillian(s.H, s.c_ops))
+
+
+def test_batch_build_then_batch_solve():
+    from oracle.steady import steady_state_dense
+    systems = [qs.kerr(int(n)) for n in (8, 12, 20, 31)] + [qs.jaynes_cummings(6, seed=1)]
+    Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
+    rhos, infos = ssl.solve_batch(Ls, "trace_bicgstab", 1e-10)
+    for s, rho, info in zip(systems, rhos, infos):
+        assert info["status"] == 0
+        assert np.max(np.abs(rho - steady_state_dense(s.H, s.c_ops))) <= 1e-8
+
+
+def _bad_cols(d, cols):
+    ip = torch.tensor([0] + [len(cols)] * d, dtype=torch.int64).cuda()
+    ix = torch.tensor(cols, dtype=torch.int32).cuda()
+    dv = torch.ones(len(cols), dtype=torch.complex128).cuda()
+    return (ip, ix, dv, d)
+
+
+@pytest.mark.parametrize("cols,msg", [([2, 1], "strictly increasing"), ([0, 5], "in range")])
+def test_batch_build_rejects_invalid_input(cols, msg):
+    """An invalid system fails the whole batch and is named in the error;
+    the valid systems of the batch are unaffected afterwards."""
+    good = qs.kerr(5)
+    items = [(_dev(good.H), [_dev(c) for c in good.c_ops]), (_bad_cols(5, cols), [])]
+    with pytest.raises(ssl.SolverError) as e:
+        ssl.build_liouvillian_batch(items)
+    assert "system 1" in str(e.value) and msg in str(e.value)
+    L = ssl.build_liouvillian_batch(items[:1])[0]
+    assert _same(L, ssl.build_liouvillian(good.H, good.c_ops))
