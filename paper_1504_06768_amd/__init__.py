@@ -6,6 +6,7 @@ been built (python paper_1504_06768_amd/build.py); importing this package
 fails loudly otherwise.
 """
 from .ss import (  # noqa: F401
+    SS_OK, SS_E_INVALID_ARG, SS_E_NOT_CONVERGED, SS_E_BREAKDOWN,
     SS_FP64, SS_MIXED, SS_ILU0, SS_ILUT, SS_ORDER_RCM, SS_ORDER_NATURAL,
     SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES, SS_AUTO,
     SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM,

@@ -15,6 +15,7 @@
 #include <cstring>
 
 #include "assemble.hpp"
+#include "batch.hpp"
 #include "csr_tools.hpp"
 
 namespace ss {
@@ -266,17 +267,6 @@ void assemble_liouvillian(const ss_csr_z *H, const ss_csr_z *c_ops, int n_cops, 
 // terms in the same order as in assemble_liouvillian, so a handle built in a
 // batch holds the same L as one built on its own.
 
-// Job index of block b from the exclusive block prefix bstart[0..njobs].
-__device__ inline int job_of_block(const int *bstart, int njobs, int b) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bstart[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 struct IngestJob {  // one input matrix: validated, then copied
     const int64_t *indptr;
     const int32_t *indices;
@@ -419,41 +409,6 @@ __global__ void __launch_bounds__(256) k_asm_dense(const DenseJob *jobs, const i
     }
 }
 
-struct ScanJob {  // in-place exclusive scan of len counts; a[len] = total
-    int *a;
-    int len;
-    int *total;
-};
-
-// One 1024-thread block per segment: each thread scans a contiguous chunk.
-__global__ void __launch_bounds__(1024) k_asm_scan(const ScanJob *jobs) {
-    __shared__ int sh[1024];
-    const ScanJob J = jobs[blockIdx.x];
-    const int t = threadIdx.x;
-    const int chunk = (J.len + 1023) / 1024;
-    const int b = min(J.len, t * chunk), e = min(J.len, b + chunk);
-    int sum = 0;
-    for (int i = b; i < e; ++i) sum += J.a[i];
-    sh[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    int run = sh[t] - sum;
-    for (int i = b; i < e; ++i) {
-        const int c = J.a[i];
-        J.a[i] = run;
-        run += c;
-    }
-    if (t == 1023) {
-        J.a[J.len] = sh[1023];
-        *J.total = sh[1023];
-    }
-}
-
 struct RowJob {  // one system's rows of L
     RowSources S;
     int n;
@@ -470,13 +425,6 @@ __global__ void __launch_bounds__(256) k_asm_rows(const RowJob *jobs, const int 
     if (r >= J.n) return;
     if (FILL) liouvillian_row<true>(J.S, r, J.col + J.rowptr[r], J.val + J.rowptr[r]);
     else J.rowptr[r] = liouvillian_row<false>(J.S, r, nullptr, nullptr);
-}
-
-// Block prefix of jobs needing blocks[j] blocks each, uploaded into `arena`.
-static int block_prefix(const std::vector<int> &blocks, std::vector<int> &pre) {
-    pre.assign(blocks.size() + 1, 0);
-    for (size_t j = 0; j < blocks.size(); ++j) pre[j + 1] = pre[j] + blocks[j];
-    return pre.back();
 }
 
 static void check_matrix(const ss_csr_z *m, int64_t N, int sys, const char *what) {
@@ -563,8 +511,8 @@ static void assemble_chunk(int k0, int k1, const ss_csr_z *H, const ss_csr_z *co
         dj.push_back(DenseJob{d, g.Gpost, lin.Gq.rowptr.get(), nullptr, nullptr});
         dblocks.push_back(div_up(d, 4));
         dblocks.push_back(div_up(d, 4));
-        sj.push_back(ScanJob{lin.Gp.rowptr.get(), d, gtot + 2 * q});
-        sj.push_back(ScanJob{lin.Gq.rowptr.get(), d, gtot + 2 * q + 1});
+        sj.push_back(ScanJob{lin.Gp.rowptr.get(), d, gtot + 2 * q, nullptr});
+        sj.push_back(ScanJob{lin.Gq.rowptr.get(), d, gtot + 2 * q + 1, nullptr});
     }
     DevBuf<GtermJob> d_gj((size_t)m);
     h2d(d_gj.get(), gj.data(), (size_t)m, s);
@@ -579,10 +527,7 @@ static void assemble_chunk(int k0, int k1, const ss_csr_z *H, const ss_csr_z *co
     h2d(d_dj.get(), dj.data(), dj.size(), s);
     k_asm_dense<false><<<(unsigned)dnb, 256, 0, s>>>(d_dj.get(), d_dpre.get(), (int)dj.size());
     SS_HIP(hipGetLastError());
-    DevBuf<ScanJob> d_sj(sj.size());
-    h2d(d_sj.get(), sj.data(), sj.size(), s);
-    k_asm_scan<<<(unsigned)sj.size(), 1024, 0, s>>>(d_sj.get());
-    SS_HIP(hipGetLastError());
+    seg_scan(sj, s);
 
     // host wait 1: validation flags and the sizes of Gpre / Gpost
     std::vector<unsigned> hmeta((size_t)3 * m);
@@ -649,7 +594,7 @@ static void assemble_chunk(int k0, int k1, const ss_csr_z *H, const ss_csr_z *co
         r.col = nullptr;
         r.val = nullptr;
         rblocks[(size_t)q] = div_up(r.n, 256);
-        lsj[(size_t)q] = ScanJob{r.rowptr, r.n, ltot + q};
+        lsj[(size_t)q] = ScanJob{r.rowptr, r.n, ltot + q, nullptr};
     }
     std::vector<int> rpre;
     const int rnb = block_prefix(rblocks, rpre);
@@ -659,10 +604,7 @@ static void assemble_chunk(int k0, int k1, const ss_csr_z *H, const ss_csr_z *co
     h2d(d_rj.get(), rj.data(), (size_t)m, s);
     k_asm_rows<false><<<(unsigned)rnb, 256, 0, s>>>(d_rj.get(), d_rpre.get(), m);
     SS_HIP(hipGetLastError());
-    DevBuf<ScanJob> d_lsj((size_t)m);
-    h2d(d_lsj.get(), lsj.data(), (size_t)m, s);
-    k_asm_scan<<<(unsigned)m, 1024, 0, s>>>(d_lsj.get());
-    SS_HIP(hipGetLastError());
+    seg_scan(lsj, s);
 
     // host wait 2: nnz(L)
     std::vector<int> lnnz((size_t)m);

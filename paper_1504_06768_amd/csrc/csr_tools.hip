@@ -1,6 +1,7 @@
 // Generic CSR kernels: input validation/upload, transpose, row sorting and
 // per-row structural queries.  Used by assembly, transforms and ordering.
 #include "csr_tools.hpp"
+#include "rowops.hpp"
 
 namespace ss {
 
@@ -80,17 +81,8 @@ void upload_csr(const ss_csr_z *in, int64_t N, CsrBuf<double2> &out, hipStream_t
 template <typename T>
 __global__ void __launch_bounds__(256) k_sort_rows(int n, const int *rowptr, const int *col_in, const T *val_in,
                                                    int *col_out, T *val_out) {
-    const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const int rs = rowptr[row], re = rowptr[row + 1];
-    for (int e = rs + lane; e < re; e += 64) {
-        const int c = col_in[e];
-        int rank = 0;
-        for (int f = rs; f < re; ++f) rank += (col_in[f] < c);
-        col_out[rs + rank] = c;
-        if (val_in) val_out[rs + rank] = val_in[e];
-    }
+    if (row < n) sort_row_wave<T>(rowptr[row], rowptr[row + 1], col_in, val_in, col_out, val_out);
 }
 
 template <typename T>

@@ -40,7 +40,8 @@ struct ss_liouv_s {
 
 namespace ss {
 
-hipStream_t stream_of(ss_liouv h);
+hipStream_t stream_of(ss_liouv h);    // the handle's stream, made the thread's current one
+hipStream_t stream_peek(ss_liouv h);  // the handle's stream (current stream unchanged)
 void prepare(ss_liouv h, int method, const ss_options &o);
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info);
 int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,

@@ -18,39 +18,20 @@
 // equal-degree neighbours are queued in increasing index.
 #include "csr_tools.hpp"
 #include "rcm.hpp"
+#include "rowops.hpp"
 
 namespace ss {
 
 // --------------------------------------------------- symmetrised pattern
 __global__ void k_union_count(int n, const int *ar, const int *ac, const int *br, const int *bc, int *cnt) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int a = ar[r], ae = ar[r + 1], b = br[r], be = br[r + 1], c = 0;
-    while (a < ae || b < be) {
-        const int x = (a < ae) ? ac[a] : 0x7fffffff;
-        const int y = (b < be) ? bc[b] : 0x7fffffff;
-        if (x <= y) ++a;
-        if (y <= x) ++b;
-        ++c;
-    }
-    cnt[r] = c;
+    if (r < n) cnt[r] = union_row<false>(r, ar, ac, br, bc, nullptr, nullptr);
 }
 
 __global__ void k_union_fill(int n, const int *ar, const int *ac, const int *br, const int *bc, const int *orow,
                              int *ocol, double2 *oval) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int a = ar[r], ae = ar[r + 1], b = br[r], be = br[r + 1], o = orow[r];
-    while (a < ae || b < be) {
-        const int x = (a < ae) ? ac[a] : 0x7fffffff;
-        const int y = (b < be) ? bc[b] : 0x7fffffff;
-        const int m = min(x, y);
-        if (x <= y) ++a;
-        if (y <= x) ++b;
-        ocol[o] = m;
-        if (oval) oval[o] = mk(1.0, 0.0);
-        ++o;
-    }
+    if (r < n) union_row<true>(r, ar, ac, br, bc, ocol + orow[r], oval ? oval + orow[r] : nullptr);
 }
 
 void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_t s) {

@@ -1,0 +1,279 @@
+// Batched set-up stages: the transform of eq. (linear) or eq. (inverse) and
+// the symmetrised pattern for every system of a batch, in a fixed number of
+// launches (flattened over the systems' rows) and one host wait.
+//
+// Output sizes are bounded before anything runs -- nnz(A) <= nnz(L) + d for
+// the trace row (d trace columns), <= nnz(L) + n for the shift (a diagonal
+// per row), nnz(S) <= 2 nnz(A) -- so every buffer is allocated up front and
+// the exact sizes are read back once at the end.  The row functions and the
+// summation order are those of the one-system kernels, so each handle gets
+// the same A, w, trace row and S as ss_prepare computes.
+#include "batch.hpp"
+#include "handle.hpp"
+#include "rowops.hpp"
+#include "setup_batch.hpp"
+
+namespace ss {
+
+struct ScalarJob {
+    int n, d;
+    Csr<double2> L;
+    int forced;     // trace row requested (-1: choose)
+    double weight;  // trace-row weight requested (0: mean diagonal)
+    double2 *w;     // out: the weight (the handle's device copy)
+    double2 *wcopy; // out: the weight again, for the host
+    int *trow;      // out: the trace row
+};
+
+// One block per trace-row system.  The mean diagonal is summed in the order
+// of the one-system reduction (256 partial sums over rows b 256 + t + k 65536,
+// each reduced as a tree, then added in block order).
+__global__ void __launch_bounds__(256) k_bt_scalars(const ScalarJob *jobs) {
+    __shared__ double sx[256], sy[256], px[256], py[256];
+    const ScalarJob J = jobs[blockIdx.x];
+    const int t = threadIdx.x;
+    double2 w = mk(J.weight, 0.0);
+    if (J.weight == 0.0) {
+        for (int b = 0; b < 256; ++b) {
+            double ax = 0, ay = 0;
+            for (int r = b * 256 + t; r < J.n; r += 256 * 256) {
+                int lo = J.L.rowptr[r], hi = J.L.rowptr[r + 1] - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int c = J.L.col[mid];
+                    if (c == r) { ax += J.L.val[mid].x; ay += J.L.val[mid].y; break; }
+                    if (c < r) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            sx[t] = ax;
+            sy[t] = ay;
+            __syncthreads();
+            for (int off = 128; off > 0; off >>= 1) {
+                if (t < off) {
+                    sx[t] += sx[t + off];
+                    sy[t] += sy[t + off];
+                }
+                __syncthreads();
+            }
+            if (t == 0) {
+                px[b] = sx[0];
+                py[b] = sy[0];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            double ax = 0, ay = 0;
+            for (int b = 0; b < 256; ++b) { ax += px[b]; ay += py[b]; }
+            w = mk(ax / J.n, ay / J.n);
+            // zero mean diagonal: any nonzero weight gives the same rho
+            if (w.x == 0.0 && w.y == 0.0) w = mk(1.0, 0.0);
+        }
+    }
+    const int r = pick_trace_row_block(J.d, J.L.rowptr, J.L.col, J.L.val, J.forced);
+    if (t == 0) {
+        *J.w = w;
+        *J.wcopy = w;
+        *J.trow = r;
+    }
+}
+
+struct ModJob {
+    int n, d;
+    Csr<double2> L;
+    int trace;
+    double sigma;
+    const double2 *w;
+    const int *trow;
+    int *rowptr;  // counts, then row pointers of A
+    int *col;
+    double2 *val;
+};
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_bt_modify(const ModJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const ModJob &J = jobs[jb];
+    const int r = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (r >= J.n) return;
+    const int *rp = J.L.rowptr;
+    if (!J.trace) {
+        if (FILL) shift_row<true>(r, rp, J.L.col, J.L.val, J.sigma, J.col + J.rowptr[r], J.val + J.rowptr[r]);
+        else J.rowptr[r] = shift_row<false>(r, rp, J.L.col, J.L.val, J.sigma, nullptr, nullptr);
+        return;
+    }
+    const int rt = *J.trow;
+    if (r == rt) {
+        if (FILL) trace_row0<true>(J.d, rt, rp, J.L.col, J.L.val, *J.w, J.col + J.rowptr[r], J.val + J.rowptr[r]);
+        else J.rowptr[r] = trace_row0<false>(J.d, rt, rp, J.L.col, J.L.val, *J.w, nullptr, nullptr);
+        return;
+    }
+    if (!FILL) {
+        J.rowptr[r] = rp[r + 1] - rp[r];
+        return;
+    }
+    const int o = J.rowptr[r];
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        J.col[o + e - rp[r]] = J.L.col[e];
+        J.val[o + e - rp[r]] = J.L.val[e];
+    }
+}
+
+struct PatJob {
+    int n;
+    const int *arow;  // A (pattern)
+    const int *acol;
+    int *trow;        // A^T: counts, then row pointers
+    int *cursor;      // scatter cursors (a copy of the row pointers)
+    int *tcol_raw;    // scattered columns of A^T (unsorted rows)
+    int *tcol;        // sorted
+    int *srow;        // S: counts, then row pointers
+    int *scol;
+    double2 *sval;
+};
+
+// STEP 0: count the columns of A; 1: scatter A^T; 2: sort the rows of A^T
+// (a wavefront per row); 3: count S rows; 4: fill S.
+template <int STEP>
+__global__ void __launch_bounds__(256) k_bt_pattern(const PatJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const PatJob &J = jobs[jb];
+    if (STEP == 2) {
+        const int row = (blockIdx.x - bstart[jb]) * 4 + (threadIdx.x >> 6);
+        if (row < J.n) sort_row_wave<int>(J.trow[row], J.trow[row + 1], J.tcol_raw, nullptr, J.tcol, nullptr);
+        return;
+    }
+    const int r = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (r >= J.n) return;
+    if (STEP == 0) {
+        for (int e = J.arow[r]; e < J.arow[r + 1]; ++e) atomicAdd(&J.trow[J.acol[e]], 1);
+    } else if (STEP == 1) {
+        for (int e = J.arow[r]; e < J.arow[r + 1]; ++e) J.tcol_raw[atomicAdd(&J.cursor[J.acol[e]], 1)] = r;
+    } else if (STEP == 3) {
+        J.srow[r] = union_row<false>(r, J.arow, J.acol, J.trow, J.tcol, nullptr, nullptr);
+    } else {
+        union_row<true>(r, J.arow, J.acol, J.trow, J.tcol, J.scol + J.srow[r], J.sval + J.srow[r]);
+    }
+}
+
+template <typename Job>
+static void launch_rows(void (*kernel)(const Job *, const int *, int), const std::vector<Job> &jobs,
+                        const std::vector<int> &blocks, hipStream_t s) {
+    std::vector<int> pre;
+    const int nb = block_prefix(blocks, pre);
+    if (nb == 0) return;
+    DevBuf<int> dpre = upload(pre, s);
+    DevBuf<Job> dj = upload(jobs, s);
+    kernel<<<(unsigned)nb, 256, 0, s>>>(dj.get(), dpre.get(), (int)jobs.size());
+    SS_HIP(hipGetLastError());
+}
+
+void transform_batch(ss_liouv *hs, int count, bool trace, const ss_options &o, hipStream_t s) {
+    if (count == 0) return;
+    StreamScope scope(s);
+    // per-system outputs, allocated up front with the size bounds
+    std::vector<int64_t> boundA((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        StreamScope own(stream_peek(h));
+        h->prepared = false;
+        h->d_w.resize(1);
+        const int64_t bA = (int64_t)h->L.nnz + (trace ? h->d : h->n);
+        SS_REQUIRE(2 * bA < (int64_t(1) << 31), SS_E_INVALID_ARG, "transformed matrix too large for a batch");
+        boundA[(size_t)k] = bA;
+        h->A.rowptr.resize((size_t)h->n + 1);
+        h->A.col.resize((size_t)bA);
+        h->A.val.resize((size_t)bA);
+        h->S.rowptr.resize((size_t)h->n + 1);
+        h->S.col.resize((size_t)(2 * bA));
+        h->S.val.resize((size_t)(2 * bA));
+        h->perm.resize((size_t)h->n);
+        h->iperm.resize((size_t)h->n);
+    }
+    // meta: trace row, nnz(A), nnz(S) per system; the weights
+    DevBuf<int> meta((size_t)3 * count);
+    DevBuf<double2> wmeta((size_t)count);
+    SS_HIP(hipMemsetAsync(meta.get(), 0, meta.bytes(), s));
+    int *m_trow = meta.get(), *m_nnzA = meta.get() + count, *m_nnzS = meta.get() + 2 * count;
+
+    if (trace) {
+        std::vector<ScalarJob> sj((size_t)count);
+        for (int k = 0; k < count; ++k) {
+            ss_liouv h = hs[k];
+            sj[(size_t)k] =
+                ScalarJob{h->n, h->d, h->L.view(), o.trace_row, o.weight, h->d_w.get(), wmeta.get() + k, m_trow + k};
+        }
+        DevBuf<ScalarJob> dsj = upload(sj, s);
+        k_bt_scalars<<<(unsigned)count, 256, 0, s>>>(dsj.get());
+        SS_HIP(hipGetLastError());
+    }
+
+    std::vector<ModJob> mj((size_t)count);
+    std::vector<int> rblocks((size_t)count), wblocks((size_t)count);
+    std::vector<ScanJob> scA((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        mj[(size_t)k] = ModJob{h->n, h->d, h->L.view(), trace ? 1 : 0, o.sigma, h->d_w.get(), m_trow + k,
+                               h->A.rowptr.get(), h->A.col.get(), h->A.val.get()};
+        rblocks[(size_t)k] = div_up(h->n, 256);
+        wblocks[(size_t)k] = div_up(h->n, 4);
+        scA[(size_t)k] = ScanJob{h->A.rowptr.get(), h->n, m_nnzA + k, nullptr};
+    }
+    launch_rows(k_bt_modify<false>, mj, rblocks, s);
+    seg_scan(scA, s);
+    launch_rows(k_bt_modify<true>, mj, rblocks, s);
+
+    // A^T (pattern) in one arena, then S = A + A^T
+    std::vector<size_t> off((size_t)count + 1, 0);
+    for (int k = 0; k < count; ++k)
+        off[(size_t)k + 1] = off[(size_t)k] + 2 * ((size_t)hs[k]->n + 1) + 2 * (size_t)boundA[(size_t)k];
+    DevBuf<int> arena(off[(size_t)count]);
+    SS_HIP(hipMemsetAsync(arena.get(), 0, arena.bytes(), s));
+    std::vector<PatJob> pj((size_t)count);
+    std::vector<ScanJob> scT((size_t)count), scS((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        int *base = arena.get() + off[(size_t)k];
+        PatJob &p = pj[(size_t)k];
+        p.n = h->n;
+        p.arow = h->A.rowptr.get();
+        p.acol = h->A.col.get();
+        p.trow = base;
+        p.cursor = base + h->n + 1;
+        p.tcol_raw = base + 2 * (h->n + 1);
+        p.tcol = p.tcol_raw + boundA[(size_t)k];
+        p.srow = h->S.rowptr.get();
+        p.scol = h->S.col.get();
+        p.sval = h->S.val.get();
+        scT[(size_t)k] = ScanJob{p.trow, h->n, nullptr, p.cursor};
+        scS[(size_t)k] = ScanJob{p.srow, h->n, m_nnzS + k, nullptr};
+    }
+    launch_rows(k_bt_pattern<0>, pj, rblocks, s);
+    seg_scan(scT, s);
+    launch_rows(k_bt_pattern<1>, pj, rblocks, s);
+    launch_rows(k_bt_pattern<2>, pj, wblocks, s);
+    launch_rows(k_bt_pattern<3>, pj, rblocks, s);
+    seg_scan(scS, s);
+    launch_rows(k_bt_pattern<4>, pj, rblocks, s);
+
+    // the one host wait: sizes, trace rows and weights
+    std::vector<int> hm((size_t)3 * count);
+    std::vector<double2> hw((size_t)count);
+    SS_HIP(hipMemcpyAsync(hw.data(), wmeta.get(), sizeof(double2) * count, hipMemcpyDeviceToHost, s));
+    d2h(hm.data(), meta.get(), hm.size(), s);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        h->A.n = h->n;
+        h->A.nnz = hm[(size_t)count + k];
+        h->S.n = h->n;
+        h->S.nnz = hm[(size_t)2 * count + k];
+        if (trace) {
+            h->trow = hm[(size_t)k];
+            h->w = hw[(size_t)k];
+        } else {
+            h->trow = 0;
+            h->w = mk(0.0, 0.0);
+        }
+    }
+}
+
+}  // namespace ss

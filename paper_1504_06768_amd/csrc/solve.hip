@@ -29,6 +29,7 @@
 #include "csr_tools.hpp"
 #include "handle.hpp"
 #include "rcm.hpp"
+#include "setup_batch.hpp"
 #include "transform.hpp"
 #include "wgsolve.hpp"
 
@@ -37,6 +38,8 @@ namespace ss {
 static thread_local hipStream_t tls_stream = nullptr;
 
 void set_thread_stream(hipStream_t s) { tls_stream = s; }
+hipStream_t stream_peek(ss_liouv h) { return tls_stream ? tls_stream : h->own_stream; }
+
 hipStream_t stream_of(ss_liouv h) {
     hipStream_t s = tls_stream ? tls_stream : h->own_stream;
     set_current_stream(s);
@@ -75,11 +78,15 @@ static bool is_gmres(int method) { return method == SS_TRACE_GMRES || method == 
 
 // The set-up in stages, so that a batch can run the ordering and the ILU(0)
 // of all its systems in one launch each (one workgroup per system).
-static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipStream_t s) {
+static void check_options(int method, const ss_options &o) {
     SS_REQUIRE(method >= 0 && method <= 3, SS_E_INVALID_ARG, "unknown method");
     SS_REQUIRE(o.prec == SS_FP64 || o.prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
     SS_REQUIRE(o.ilu == SS_ILU0 || o.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
     SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG, "unknown ordering");
+}
+
+static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipStream_t s) {
+    check_options(method, o);
     h->prepared = false;
     const int d = h->d;
     h->d_w.resize(1);
@@ -673,12 +680,29 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         std::fprintf(stderr, "[ss] batch of %d: %-22s %8.3f ms\n", count, name, t - tmark);
         tmark = t;
     };
-    // stage 1: transform and symmetrised pattern, per system
-    parallel([&](int i) {
-        hipStream_t s = stream_of(hs[i]);
-        prepare_transform(hs[i], method, o, s);
-        SS_HIP(hipStreamSynchronize(s));
-    });
+    // stage 1: transform and symmetrised pattern of every system together
+    check_options(method, o);
+    {
+        std::vector<ss_liouv> ok;
+        std::vector<int> idx;
+        for (int i = 0; i < count; ++i) {
+            if (is_trace(method) && o.trace_row >= hs[i]->d) {
+                code[(size_t)i] = SS_E_INVALID_ARG;
+                err[(size_t)i] = "trace_row must be < N";
+                continue;
+            }
+            ok.push_back(hs[i]);
+            idx.push_back(i);
+        }
+        try {
+            transform_batch(ok.data(), (int)ok.size(), is_trace(method), o, s0);
+        } catch (const Error &e) {
+            for (int i : idx) {
+                code[(size_t)i] = e.code;
+                err[(size_t)i] = e.what();
+            }
+        }
+    }
     mark("transform+pattern");
     // stage 2: RCM of every graph in one launch (small graphs), else per system
     const bool rcm = o.ordering == SS_ORDER_RCM;

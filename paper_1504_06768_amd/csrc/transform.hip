@@ -6,6 +6,7 @@
 //             diagonal of L unless given;
 //   shifted   L - sigma I   (section "Eigenvalue Methods", eq. inverse).
 #include "csr_tools.hpp"
+#include "rowops.hpp"
 #include "transform.hpp"
 
 namespace ss {
@@ -62,37 +63,8 @@ void mean_diagonal(const CsrBuf<double2> &L, double2 *d_out, hipStream_t s) {
 // channel leaves, e.g. a ground state) gets the trace entry as its pivot.
 __global__ void k_pick_trace_row(int d, const int *rowptr, const int *col, const double2 *val, int forced,
                                  int *row_out) {
-    __shared__ double sm[256];
-    __shared__ int sk[256];
-    double best = INFINITY;
-    int bk = 0x7fffffff;
-    for (int k = threadIdx.x; k < d; k += 256) {
-        const int r = k * (d + 1);
-        double mag = 0.0;
-        int lo = rowptr[r], hi = rowptr[r + 1] - 1;
-        while (lo <= hi) {
-            const int mid = (lo + hi) >> 1;
-            const int c = col[mid];
-            if (c == r) { mag = sqrt(val[mid].x * val[mid].x + val[mid].y * val[mid].y); break; }
-            if (c < r) lo = mid + 1; else hi = mid - 1;
-        }
-        if (mag < best || (mag == best && k < bk)) { best = mag; bk = k; }
-    }
-    sm[threadIdx.x] = best;
-    sk[threadIdx.x] = bk;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            const double m2 = sm[threadIdx.x + off];
-            const int k2 = sk[threadIdx.x + off];
-            if (m2 < sm[threadIdx.x] || (m2 == sm[threadIdx.x] && k2 < sk[threadIdx.x])) {
-                sm[threadIdx.x] = m2;
-                sk[threadIdx.x] = k2;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *row_out = (forced >= 0 ? forced : sk[0]) * (d + 1);
+    const int r = pick_trace_row_block(d, rowptr, col, val, forced);
+    if (threadIdx.x == 0) *row_out = r;
 }
 
 int pick_trace_row(const CsrBuf<double2> &L, int d, int forced, hipStream_t s) {
@@ -102,30 +74,6 @@ int pick_trace_row(const CsrBuf<double2> &L, int d, int forced, hipStream_t s) {
     int h = 0;
     d2h(&h, r.get(), 1, s);
     return h;
-}
-
-// Row rt of L~ is the merge of row rt of L with w at the trace columns; all
-// other rows are copied.  Entries that cancel to exactly zero are dropped.
-template <bool FILL>
-__device__ int trace_row0(int d, int rt, const int *rowptr, const int *col, const double2 *val, double2 w, int *ocol,
-                          double2 *oval) {
-    int e = rowptr[rt];
-    const int ee = rowptr[rt + 1];
-    int k = 0;
-    int cnt = 0;
-    while (e < ee || k < d) {
-        const int ce = (e < ee) ? col[e] : 0x7fffffff;
-        const int ct = (k < d) ? k * (d + 1) : 0x7fffffff;
-        const int c = min(ce, ct);
-        double2 v = mk(0.0, 0.0);
-        if (ce == c) { v = val[e]; ++e; }
-        if (ct == c) { v = cadd(v, w); ++k; }
-        if (v.x != 0.0 || v.y != 0.0) {
-            if (FILL) { ocol[cnt] = c; oval[cnt] = v; }
-            ++cnt;
-        }
-    }
-    return cnt;
 }
 
 __global__ void k_mod_count(int n, int d, int rt, const int *rowptr, const int *col, const double2 *val,
@@ -152,35 +100,6 @@ __global__ void k_mod_fill(int n, int d, int rt, const int *rowptr, const int *c
 }
 
 // ----------------------------------------------------------------- shifted
-template <bool FILL>
-__device__ int shift_row(int r, const int *rowptr, const int *col, const double2 *val, double sigma, int *ocol,
-                         double2 *oval) {
-    int cnt = 0;
-    bool placed = false;
-    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        const int c = col[e];
-        if (!placed && c > r) {
-            if (FILL) { ocol[cnt] = r; oval[cnt] = mk(-sigma, 0.0); }
-            ++cnt;
-            placed = true;
-        }
-        double2 v = val[e];
-        if (c == r) {
-            v.x -= sigma;
-            placed = true;
-        }
-        if (v.x != 0.0 || v.y != 0.0) {
-            if (FILL) { ocol[cnt] = c; oval[cnt] = v; }
-            ++cnt;
-        }
-    }
-    if (!placed) {
-        if (FILL) { ocol[cnt] = r; oval[cnt] = mk(-sigma, 0.0); }
-        ++cnt;
-    }
-    return cnt;
-}
-
 __global__ void k_shift_count(int n, const int *rowptr, const int *col, const double2 *val, double sigma, int *cnt) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) cnt[r] = shift_row<false>(r, rowptr, col, val, sigma, nullptr, nullptr);

@@ -119,3 +119,36 @@ def test_batch_build_rejects_invalid_input(cols, msg):
     assert "system 1" in str(e.value) and msg in str(e.value)
     L = ssl.build_liouvillian_batch(items[:1])[0]
     assert _same(L, ssl.build_liouvillian(good.H, good.c_ops))
+
+
+def _mats(L):
+    return [ssl.export_csr(L, w) for w in (ssl.SS_MAT_A, ssl.SS_MAT_SYM, ssl.SS_MAT_A_PERM, ssl.SS_MAT_LU)]
+
+
+@pytest.mark.parametrize("method,opts", [("trace_bicgstab", {}), ("invpow_bicgstab", {}),
+                                         ("trace_bicgstab", {"weight": 0.7, "trace_row": 2}),
+                                         ("trace_bicgstab", {"prec": "mixed"})])
+def test_batched_setup_equals_prepare(method, opts):
+    """The batch's set-up stages (transform, pattern, ordering, ILU(0)) give
+    every handle the matrices ss_prepare gives it on its own, bit for bit."""
+    systems = _systems()[:6] + [qs.kerr(int(n)) for n in (9, 17, 33)]
+    Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
+    _, infos = ssl.solve_batch(Ls, method, 1e-10, raise_on_error=False, **opts)
+    for s, L, info in zip(systems, Ls, infos):
+        if opts.get("trace_row", -1) >= s.dim:
+            assert info["status"] == ssl.SS_E_INVALID_ARG
+            continue
+        ref = ssl.build_liouvillian(s.H, s.c_ops)
+        ssl.prepare(ref, method, **opts)
+        for a, b in zip(_mats(L), _mats(ref)):
+            assert np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices), s.name
+            assert np.array_equal(a.data, b.data), s.name
+        assert np.array_equal(ssl.export_perm(L), ssl.export_perm(ref)), s.name
+
+
+def test_batched_setup_rejects_a_bad_trace_row_for_that_system_only():
+    systems = [qs.kerr(3), qs.kerr(8)]
+    Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
+    _, infos = ssl.solve_batch(Ls, "trace_bicgstab", 1e-10, raise_on_error=False, trace_row=5)
+    assert infos[0]["status"] == ssl.SS_E_INVALID_ARG
+    assert infos[1]["status"] == 0
