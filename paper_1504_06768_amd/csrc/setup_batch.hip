@@ -12,6 +12,7 @@
 #include "handle.hpp"
 #include "rowops.hpp"
 #include "setup_batch.hpp"
+#include "syncfree.hpp"
 
 namespace ss {
 
@@ -273,6 +274,129 @@ void transform_batch(ss_liouv *hs, int count, bool trace, const ss_options &o, h
             h->trow = 0;
             h->w = mk(0.0, 0.0);
         }
+    }
+}
+
+
+// ------------------------------------------------------------ P A P^T
+struct PermJob {
+    int n, d;
+    const int *perm, *iperm;
+    Csr<double2> A;
+    int *prow;        // P A P^T: counts, then row pointers
+    int *pcol;
+    double2 *pval;
+    int *lucol;       // ILU(0) factor: pattern of P A P^T, values at the sentinel
+    double2 *luval;   // (null when the factor is not ILU(0))
+    int *diag;        // diagonal positions in P A P^T
+    int *lu_diag;     // the same for the factor (null: not ILU(0))
+    int *tpos;        // permuted positions of the diagonal of rho
+    int trow;
+    int *missing;     // rows without a diagonal entry
+    int *q0;          // permuted position of the trace row
+};
+
+// STEP 0: row lengths; 1: rows (a wavefront each, columns mapped through
+// iperm and rank-sorted as in k_perm_fill); 2: diagonal positions, trace
+// positions and q0.
+template <int STEP>
+__global__ void __launch_bounds__(256) k_bt_permute(const PermJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const PermJob &J = jobs[jb];
+    if (STEP == 1) {
+        const int lane = threadIdx.x & 63;
+        const int q = (blockIdx.x - bstart[jb]) * 4 + (threadIdx.x >> 6);
+        if (q >= J.n) return;
+        const int r = J.perm[q];
+        const int rs = J.A.rowptr[r], re = J.A.rowptr[r + 1];
+        const int o = J.prow[q];
+        for (int e = rs + lane; e < re; e += 64) {
+            const int c = J.iperm[J.A.col[e]];
+            int rank = 0;
+            for (int f = rs; f < re; ++f) rank += (J.iperm[J.A.col[f]] < c);
+            J.pcol[o + rank] = c;
+            J.pval[o + rank] = J.A.val[e];
+            if (J.lucol) {
+                J.lucol[o + rank] = c;
+                set_sentinel(J.luval + o + rank);
+            }
+        }
+        return;
+    }
+    const int r = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (r >= J.n) return;
+    if (STEP == 0) {
+        const int a = J.perm[r];
+        J.prow[r] = J.A.rowptr[a + 1] - J.A.rowptr[a];
+        return;
+    }
+    int lo = J.prow[r], hi = J.prow[r + 1] - 1, pos = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = J.pcol[mid];
+        if (c == r) { pos = mid; break; }
+        if (c < r) lo = mid + 1; else hi = mid - 1;
+    }
+    J.diag[r] = pos;
+    if (J.lu_diag) J.lu_diag[r] = pos;
+    if (pos < 0) atomicAdd(J.missing, 1);
+    if (r < J.d) J.tpos[r] = J.iperm[(int64_t)r * (J.d + 1)];
+    if (r == 0) *J.q0 = J.iperm[J.trow];
+}
+
+void permute_batch(ss_liouv *hs, int count, bool ilu0, hipStream_t s, std::vector<PermResult> &res) {
+    res.assign((size_t)count, PermResult{});
+    if (count == 0) return;
+    StreamScope scope(s);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        StreamScope own(stream_peek(h));
+        h->Ap.alloc(h->n, h->A.nnz);
+        h->diag.resize((size_t)h->n);
+        h->tpos.resize((size_t)h->d);
+        if (ilu0) {
+            h->LU.alloc(h->n, h->A.nnz);
+            h->lu_diag.resize((size_t)h->n);
+        }
+    }
+    DevBuf<int> meta((size_t)2 * count);
+    SS_HIP(hipMemsetAsync(meta.get(), 0, meta.bytes(), s));
+    std::vector<PermJob> pj((size_t)count);
+    std::vector<int> rblocks((size_t)count), wblocks((size_t)count);
+    std::vector<ScanJob> sc((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        PermJob &p = pj[(size_t)k];
+        p.n = h->n;
+        p.d = h->d;
+        p.perm = h->perm.get();
+        p.iperm = h->iperm.get();
+        p.A = h->A.view();
+        p.prow = h->Ap.rowptr.get();
+        p.pcol = h->Ap.col.get();
+        p.pval = h->Ap.val.get();
+        p.lucol = ilu0 ? h->LU.col.get() : nullptr;
+        p.luval = ilu0 ? h->LU.val.get() : nullptr;
+        p.diag = h->diag.get();
+        p.lu_diag = ilu0 ? h->lu_diag.get() : nullptr;
+        p.tpos = h->tpos.get();
+        p.trow = h->trow;
+        p.missing = meta.get() + k;
+        p.q0 = meta.get() + count + k;
+        rblocks[(size_t)k] = div_up(h->n, 256);
+        wblocks[(size_t)k] = div_up(h->n, 4);
+        sc[(size_t)k] = ScanJob{p.prow, h->n, nullptr, ilu0 ? h->LU.rowptr.get() : nullptr};
+    }
+    launch_rows(k_bt_permute<0>, pj, rblocks, s);
+    seg_scan(sc, s);
+    launch_rows(k_bt_permute<1>, pj, wblocks, s);
+    launch_rows(k_bt_permute<2>, pj, rblocks, s);
+    std::vector<int> hm((size_t)2 * count);
+    d2h(hm.data(), meta.get(), hm.size(), s);
+    for (int k = 0; k < count; ++k) {
+        res[(size_t)k].missing = hm[(size_t)k];
+        hs[k]->q0 = hm[(size_t)count + k];
+        hs[k]->diag_added = hm[(size_t)k];
     }
 }
 

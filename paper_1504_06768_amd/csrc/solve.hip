@@ -118,27 +118,30 @@ static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipSt
     h->iperm.resize((size_t)h->n);
 }
 
+// Rows whose diagonal is structurally zero (e.g. the ground-state population
+// of a Jaynes-Cummings system when the trace row sits elsewhere) get an
+// explicit zero diagonal entry, so the zero-fill ILU has a pivot position;
+// the matrix itself is unchanged.
+static void add_zero_diagonal(ss_liouv h, hipStream_t s) {
+    CsrBuf<double2> aug;
+    make_shifted(h->Ap, 0.0, aug, s);
+    h->Ap = std::move(aug);
+    const int still = find_diagonal(h->n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
+    SS_REQUIRE(still == 0, SS_E_ZERO_PIVOT, "could not give every row a diagonal entry");
+}
+
 static void prepare_permute(ss_liouv h, hipStream_t s) {
     const int n = h->n;
     permute_matrix(h->A, h->perm.get(), h->iperm.get(), h->Ap, s);
     h->diag.resize((size_t)n);
     h->diag_added = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
-    if (h->diag_added > 0) {
-        // Rows whose diagonal is structurally zero (e.g. the ground-state
-        // population of a Jaynes-Cummings system when the trace row sits
-        // elsewhere) get an explicit zero diagonal entry, so the zero-fill
-        // ILU has a pivot position; the matrix itself is unchanged.
-        CsrBuf<double2> aug;
-        make_shifted(h->Ap, 0.0, aug, s);
-        h->Ap = std::move(aug);
-        const int still = find_diagonal(n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
-        SS_REQUIRE(still == 0, SS_E_ZERO_PIVOT, "could not give every row a diagonal entry");
-    }
+    if (h->diag_added > 0) add_zero_diagonal(h, s);
 }
 
-static void prepare_finish(ss_liouv h, int method, const ss_options &o, hipStream_t s, double t0) {
+static void prepare_finish(ss_liouv h, int method, const ss_options &o, hipStream_t s, double t0,
+                           bool positions_done = false) {
     const int n = h->n, d = h->d;
-    if (o.ilu == SS_ILU0) {
+    if (o.ilu == SS_ILU0 && !positions_done) {
         h->lu_diag.resize((size_t)n);
         if (n) SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
     }
@@ -149,10 +152,12 @@ static void prepare_finish(ss_liouv h, int method, const ss_options &o, hipStrea
         h->Ap32 = CsrBuf<float2>();
         h->LU32 = CsrBuf<float2>();
     }
-    h->tpos.resize((size_t)d);
-    k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
-    SS_HIP(hipGetLastError());
-    d2h(&h->q0, h->iperm.get() + h->trow, 1, s);
+    if (!positions_done) {
+        h->tpos.resize((size_t)d);
+        k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
+        SS_HIP(hipGetLastError());
+        d2h(&h->q0, h->iperm.get() + h->trow, 1, s);
+    }
     h->p_method = method;
     h->p_opt = o;
     h->prepared = true;
@@ -717,30 +722,95 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         rcm_batch(jobs.data(), (int)jobs.size(), s0);
     }
     mark("rcm (batched)");
-    // stage 3: remaining orderings, P A P^T, diagonal positions, per system
-    std::vector<Ilu0Batch> ib((size_t)count);
-    std::vector<Ilu0Job> ijobs((size_t)count);
-    std::vector<char> in_batch((size_t)count, 0);
+    // stage 3: orderings the batched RCM does not cover, per system (rare)
     parallel([&](int i) {
         ss_liouv h = hs[i];
+        if (rcm && rcm_batchable(h->n) && h->n > 0) return;
         hipStream_t s = stream_of(h);
         if (!rcm) identity_order(h->n, h->perm, h->iperm, s);
-        else if (!rcm_batchable(h->n) || h->n == 0) rcm_order(h->S, h->perm, h->iperm, s);
-        prepare_permute(h, s);
-        if (o.ilu == SS_ILU0 && h->n > 0) {
-            ijobs[(size_t)i] = ib[(size_t)i].prepare(h->Ap, h->diag.get(), h->LU, s);
-            in_batch[(size_t)i] = 1;
-        }
+        else rcm_order(h->S, h->perm, h->iperm, s);
         SS_HIP(hipStreamSynchronize(s));
     });
     rs.clear();
+    // P A P^T, diagonal and trace positions and the ILU(0) pattern of every
+    // system together; rows without a diagonal entry (rare) are fixed per system
+    const bool ilu0 = (o.ilu == SS_ILU0);
+    std::vector<Ilu0Batch> ib((size_t)count);
+    std::vector<Ilu0Job> ijobs((size_t)count);
+    std::vector<char> own_ilu((size_t)count, 0);
+    DevBuf<double2> ilu_work;
+    DevBuf<unsigned> ilu_flags;
+    {
+        std::vector<ss_liouv> ok;
+        std::vector<int> idx;
+        for (int i = 0; i < count; ++i)
+            if (code[(size_t)i] == SS_OK) {
+                ok.push_back(hs[i]);
+                idx.push_back(i);
+            }
+        std::vector<PermResult> pres;
+        try {
+            permute_batch(ok.data(), (int)ok.size(), ilu0, s0, pres);
+        } catch (const Error &e) {
+            for (int i : idx) {
+                code[(size_t)i] = e.code;
+                err[(size_t)i] = e.what();
+            }
+            pres.assign(ok.size(), PermResult{});
+        }
+        // rows without a diagonal: explicit zeros, then the factor's own scratch
+        parallel([&](int i) {
+            ss_liouv h = hs[i];
+            if (h->diag_added == 0) return;
+            hipStream_t s = stream_of(h);
+            add_zero_diagonal(h, s);
+            if (ilu0) {
+                ijobs[(size_t)i] = ib[(size_t)i].prepare(h->Ap, h->diag.get(), h->LU, s);
+                SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * h->n, hipMemcpyDeviceToDevice,
+                                      s));
+                own_ilu[(size_t)i] = 1;
+            }
+            SS_HIP(hipStreamSynchronize(s));
+        });
+        if (ilu0) {
+            // ILU(0) scratch of the other systems in two arenas
+            size_t wtot = 0;
+            for (int i : idx)
+                if (code[(size_t)i] == SS_OK && !own_ilu[(size_t)i]) wtot += (size_t)std::max(hs[i]->Ap.nnz, 1);
+            StreamScope scope(s0);
+            ilu_work.resize(std::max<size_t>(wtot, 1));
+            ilu_flags.resize(2 * (size_t)count);
+            SS_HIP(hipMemsetAsync(ilu_flags.get(), 0, ilu_flags.bytes(), s0));
+            size_t w = 0;
+            for (int i : idx) {
+                if (code[(size_t)i] != SS_OK || own_ilu[(size_t)i]) continue;
+                ss_liouv h = hs[i];
+                Ilu0Job &j = ijobs[(size_t)i];
+                j.n = h->n;
+                j.rowptr = h->Ap.rowptr.get();
+                j.col = h->Ap.col.get();
+                j.diag = h->diag.get();
+                j.a = h->Ap.val.get();
+                j.w = ilu_work.get() + w;
+                j.out = h->LU.val.get();
+                j.status = ilu_flags.get() + 2 * i;
+                j.nguard = reinterpret_cast<int *>(ilu_flags.get() + 2 * i + 1);
+                w += (size_t)std::max(h->Ap.nnz, 1);
+            }
+        }
+    }
     mark("permute+ilu prep");
     // stage 4: ILU(0) of every system in one launch
+    std::vector<unsigned> hflags;
     {
         std::vector<Ilu0Job> jobs;
         for (int i = 0; i < count; ++i)
-            if (code[(size_t)i] == SS_OK && in_batch[(size_t)i]) jobs.push_back(ijobs[(size_t)i]);
+            if (code[(size_t)i] == SS_OK && ilu0) jobs.push_back(ijobs[(size_t)i]);
         ilu0_batch(jobs.data(), (int)jobs.size(), PIVOT_DETECT, PIVOT_BOOST, s0);
+        if (ilu0) {
+            hflags.resize(2 * (size_t)count);
+            d2h(hflags.data(), ilu_flags.get(), hflags.size(), s0);
+        }
     }
     mark("ilu0 (batched)");
     // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up,
@@ -750,16 +820,18 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
     parallel([&](int i) {
         ss_liouv h = hs[i];
         hipStream_t s = stream_of(h);
-        if (in_batch[(size_t)i]) {
+        if (ilu0 && own_ilu[(size_t)i]) {
             h->guarded = ib[(size_t)i].result(s).guarded;
-        } else if (o.ilu == SS_ILU0) {
-            h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+        } else if (ilu0) {
+            SS_REQUIRE(!(hflags[2 * (size_t)i] & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT,
+                       "ILU(0): dependency wait timed out");
+            h->guarded = (int)hflags[2 * (size_t)i + 1];
         } else {
             h->guarded = ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU,
                                      h->lu_diag, s)
                              .guarded;
         }
-        prepare_finish(h, method, o, s, t0);
+        prepare_finish(h, method, o, s, t0, true);
         lj_lo[(size_t)i] = lb_lo[(size_t)i].job(h->LU.view(), h->lu_diag.get(), s);
         lj_up[(size_t)i] = lb_up[(size_t)i].job(h->LU.view(), h->lu_diag.get(), s);
         SS_HIP(hipStreamSynchronize(s));
