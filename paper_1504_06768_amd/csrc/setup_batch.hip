@@ -8,6 +8,8 @@
 // the exact sizes are read back once at the end.  The row functions and the
 // summation order are those of the one-system kernels, so each handle gets
 // the same A, w, trace row and S as ss_prepare computes.
+#include <cstring>
+
 #include "batch.hpp"
 #include "handle.hpp"
 #include "rowops.hpp"
@@ -399,5 +401,260 @@ void permute_batch(ss_liouv *hs, int count, bool ilu0, hipStream_t s, std::vecto
         hs[k]->diag_added = hm[(size_t)k];
     }
 }
+
+
+// ------------------------------------------- workgroup-resident problems
+struct SideJob {
+    int n, upper;
+    const int *lvl;     // level of each row
+    int *cnt;           // nlev + 1 counts, then scatter cursors
+    int *ptr;           // level pointers
+    int4 *slot;         // level-ordered slots {row, first, end, 0}
+    const int *rowptr;  // factor pattern
+    const int *diag;
+};
+
+// STEP 0: rows per level; 1: scatter the rows into level order (the order
+// inside a level does not matter: its rows are independent).
+template <int STEP>
+__global__ void __launch_bounds__(256) k_bt_levels(const SideJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const SideJob &J = jobs[jb];
+    const int i = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (i >= J.n) return;
+    if (STEP == 0) {
+        atomicAdd(&J.cnt[J.lvl[i]], 1);
+        return;
+    }
+    const int pos = atomicAdd(&J.cnt[J.lvl[i]], 1);
+    J.slot[pos] = J.upper ? make_int4(i, J.diag[i] + 1, J.rowptr[i + 1], 0) : make_int4(i, J.rowptr[i], J.diag[i], 0);
+}
+
+template <typename T>
+struct PackJob {
+    int n, upper;
+    const int4 *in;  // level-ordered slots
+    const int *col;  // factor (precision T)
+    const T *val;
+    int4 *slot;
+    int *pcol;
+    T *pval, *aux;
+};
+
+// The packed level-order layout of one factor side (see PackedSide).
+template <typename T>
+__global__ void __launch_bounds__(256) k_bt_pack(const PackJob<T> *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const PackJob<T> &J = jobs[jb];
+    const int idx = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (idx >= J.n) return;
+    const int4 sl = J.in[idx];
+    const int len = sl.z - sl.y;
+    J.slot[idx] = make_int4(sl.x, sl.y, len, 0);
+    constexpr int K = WgK<T>::value;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        J.pcol[(size_t)k * J.n + idx] = (k < len) ? J.col[sl.y + k] : 0;
+        J.pval[(size_t)k * J.n + idx] = (k < len) ? J.val[sl.y + k] : czero<T>();
+    }
+    J.aux[idx] = J.upper ? J.val[sl.y - 1] : czero<T>();
+}
+
+struct StartJob {
+    int n, d, trace, trow;
+    double2 w;
+    const int *perm;
+    double2 *x, *b;  // zeroed
+};
+
+// Start vector and right-hand side in the permuted order: trace row
+// b = w e_trow, x = 0; inverse power x = vec(I / d).
+__global__ void __launch_bounds__(256) k_bt_start(const StartJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const StartJob &J = jobs[jb];
+    const int q = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (q >= J.n) return;
+    const int r = J.perm[q];
+    if (J.trace) {
+        if (r == J.trow) J.b[q] = J.w;
+    } else if (r % (J.d + 1) == 0) {
+        J.x[q] = mk(1.0 / J.d, 0.0);
+    }
+}
+
+// Carves aligned pieces out of one allocation.
+struct Carver {
+    size_t off = 0;
+    template <typename U>
+    size_t take(size_t count) {
+        const size_t at = (off + 255) & ~size_t(255);
+        off = at + sizeof(U) * std::max<size_t>(count, 1);
+        return at;
+    }
+};
+
+template <typename T>
+void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, hipStream_t s,
+                    WgBatch<T> &out) {
+    out.probs.assign((size_t)count, WgProblem<T>{});
+    out.levels.assign((size_t)count, 0);
+    if (count == 0) return;
+    StreamScope scope(s);
+    const bool trace = (method == SS_TRACE_BICGSTAB || method == SS_TRACE_GMRES);
+    // level analysis of both sides of every factor: levels at -1, one launch per side
+    std::vector<size_t> loff((size_t)count + 1, 0);
+    for (int k = 0; k < count; ++k) loff[(size_t)k + 1] = loff[(size_t)k] + 2 * (size_t)std::max(hs[k]->n, 1);
+    DevBuf<int> lvl(loff[(size_t)count]);
+    DevBuf<unsigned> meta((size_t)4 * count);  // per side: status, max level
+    SS_HIP(hipMemsetAsync(lvl.get(), 0xff, lvl.bytes(), s));
+    SS_HIP(hipMemsetAsync(meta.get(), 0, meta.bytes(), s));
+    std::vector<LevelJob> jl((size_t)count), ju((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        for (int side = 0; side < 2; ++side) {
+            LevelJob &j = side ? ju[(size_t)k] : jl[(size_t)k];
+            j.n = h->n;
+            j.rowptr = h->LU.rowptr.get();
+            j.col = h->LU.col.get();
+            j.diag = h->lu_diag.get();
+            j.lvl = lvl.get() + loff[(size_t)k] + (size_t)side * std::max(h->n, 1);
+            j.status = meta.get() + 4 * k + 2 * side;
+            j.maxlvl = reinterpret_cast<int *>(meta.get() + 4 * k + 2 * side + 1);
+        }
+    }
+    levels_batch<false>(jl.data(), count, s);
+    levels_batch<true>(ju.data(), count, s);
+    std::vector<unsigned> hm((size_t)4 * count);
+    d2h(hm.data(), meta.get(), hm.size(), s);
+    std::vector<int> nl((size_t)count), nu((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        SS_REQUIRE(!(hm[4 * (size_t)k] & STATUS_SPIN_TIMEOUT) && !(hm[4 * (size_t)k + 2] & STATUS_SPIN_TIMEOUT),
+                   SS_E_TIMEOUT, "level analysis: dependency wait timed out");
+        nl[(size_t)k] = hs[k]->n ? (int)hm[4 * (size_t)k + 1] + 1 : 0;
+        nu[(size_t)k] = hs[k]->n ? (int)hm[4 * (size_t)k + 3] + 1 : 0;
+    }
+    // one arena for every system's schedules, packed factors and vectors
+    constexpr int K = WgK<T>::value;
+    struct Lay {
+        size_t lptr, uptr, lcnt, ucnt, lslot, uslot, pls, pus, plc, puc, plv, puv, pla, pua, work, ysc, x, r, b, res;
+    };
+    std::vector<Lay> lay((size_t)count);
+    Carver cv;
+    for (int k = 0; k < count; ++k) {
+        const size_t n = (size_t)std::max(hs[k]->n, 1);
+        Lay &L = lay[(size_t)k];
+        L.lptr = cv.take<int>((size_t)nl[(size_t)k] + 1);
+        L.uptr = cv.take<int>((size_t)nu[(size_t)k] + 1);
+        L.lcnt = cv.take<int>((size_t)nl[(size_t)k] + 1);
+        L.ucnt = cv.take<int>((size_t)nu[(size_t)k] + 1);
+        L.lslot = cv.take<int4>(n);
+        L.uslot = cv.take<int4>(n);
+        L.pls = cv.take<int4>(n);
+        L.pus = cv.take<int4>(n);
+        L.plc = cv.take<int>(n * K);
+        L.puc = cv.take<int>(n * K);
+        L.plv = cv.take<T>(n * K);
+        L.puv = cv.take<T>(n * K);
+        L.pla = cv.take<T>(n);
+        L.pua = cv.take<T>(n);
+        L.work = cv.take<T>(11 * n);
+        L.ysc = cv.take<T>(n);
+        L.x = cv.take<double2>(n);
+        L.r = cv.take<double2>(n);
+        L.b = cv.take<double2>(n);
+        L.res = cv.take<WgResult>(1);
+    }
+    out.arena.resize(cv.off);
+    SS_HIP(hipMemsetAsync(out.arena.get(), 0, out.arena.bytes(), s));
+    unsigned char *base = out.arena.get();
+    auto at = [&](size_t off) { return base + off; };
+
+    std::vector<SideJob> sj;
+    std::vector<ScanJob> sc;
+    std::vector<PackJob<T>> pj;
+    std::vector<StartJob> st;
+    std::vector<int> sblocks, stblocks;
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        const Lay &L = lay[(size_t)k];
+        const CsrBuf<T> &LUin = lu_of<T>(h);
+        for (int side = 0; side < 2; ++side) {
+            SideJob j;
+            j.n = h->n;
+            j.upper = side;
+            j.lvl = (side ? ju : jl)[(size_t)k].lvl;
+            j.cnt = (int *)at(side ? L.ucnt : L.lcnt);
+            j.ptr = (int *)at(side ? L.uptr : L.lptr);
+            j.slot = (int4 *)at(side ? L.uslot : L.lslot);
+            j.rowptr = h->LU.rowptr.get();
+            j.diag = h->lu_diag.get();
+            sj.push_back(j);
+            sblocks.push_back(div_up(h->n, 256));
+            sc.push_back(ScanJob{j.cnt, side ? nu[(size_t)k] : nl[(size_t)k], nullptr, j.ptr});
+            PackJob<T> p;
+            p.n = h->n;
+            p.upper = side;
+            p.in = j.slot;
+            p.col = LUin.col.get();
+            p.val = LUin.val.get();
+            p.slot = (int4 *)at(side ? L.pus : L.pls);
+            p.pcol = (int *)at(side ? L.puc : L.plc);
+            p.pval = (T *)at(side ? L.puv : L.plv);
+            p.aux = (T *)at(side ? L.pua : L.pla);
+            pj.push_back(p);
+        }
+        st.push_back(StartJob{h->n, h->d, trace ? 1 : 0, h->trow, h->w, h->perm.get(), (double2 *)at(L.x),
+                              (double2 *)at(L.b)});
+        stblocks.push_back(div_up(h->n, 256));
+    }
+    launch_rows(k_bt_levels<0>, sj, sblocks, s);
+    seg_scan(sc, s);
+    launch_rows(k_bt_levels<1>, sj, sblocks, s);
+    launch_rows(k_bt_pack<T>, pj, sblocks, s);
+    launch_rows(k_bt_start, st, stblocks, s);
+
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        const Lay &L = lay[(size_t)k];
+        WgProblem<T> &P = out.probs[(size_t)k];
+        std::memset(&P, 0, sizeof(P));
+        P.n = h->n;
+        P.d = h->d;
+        P.q0 = h->q0;
+        P.trace = trace ? 1 : 0;
+        P.nlev_l = nl[(size_t)k];
+        P.nlev_u = nu[(size_t)k];
+        P.maxiter = o.maxiter;
+        P.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+        P.tol = tol;
+        P.rtol_in = (o.inner_tol > 0) ? o.inner_tol : (o.prec == SS_MIXED ? 1e-4 : 0.0);
+        P.sigma = o.sigma;
+        P.w = h->w;
+        P.A = ap_of<T>(h).view();
+        P.A64 = h->Ap.view();
+        P.LU = lu_of<T>(h).view();
+        P.diag = h->lu_diag.get();
+        P.lptr = (const int *)at(L.lptr);
+        P.lslot = (const int4 *)at(L.pls);
+        P.lcol = (const int *)at(L.plc);
+        P.lval = (const T *)at(L.plv);
+        P.uptr = (const int *)at(L.uptr);
+        P.uslot = (const int4 *)at(L.pus);
+        P.ucol = (const int *)at(L.puc);
+        P.uval = (const T *)at(L.puv);
+        P.uaux = (const T *)at(L.pua);
+        P.tpos = h->tpos.get();
+        P.b64 = trace ? (const double2 *)at(L.b) : nullptr;
+        P.x64 = (double2 *)at(L.x);
+        P.r64 = (double2 *)at(L.r);
+        P.work = (T *)at(L.work);
+        P.ysc = (T *)at(L.ysc);
+        P.res = (WgResult *)at(L.res);
+        out.levels[(size_t)k] = nl[(size_t)k] + nu[(size_t)k];
+    }
+}
+template void wg_setup_batch<float2>(ss_liouv *, int, int, double, const ss_options &, hipStream_t, WgBatch<float2> &);
+template void wg_setup_batch<double2>(ss_liouv *, int, int, double, const ss_options &, hipStream_t,
+                                      WgBatch<double2> &);
 
 }  // namespace ss

@@ -22,4 +22,28 @@ struct PermResult {
 };
 void permute_batch(ss_liouv *hs, int count, bool ilu0, hipStream_t s, std::vector<PermResult> &res);
 
+// Workgroup-resident problems of many prepared handles (factors and their
+// diagonal positions in place): level analysis of both factor sides, level
+// schedules, packed factors, start vectors and scratch -- what make_wg
+// builds for one handle -- in one arena for the whole batch.  probs[k] and
+// levels[k] (nlev_l + nlev_u) belong to hs[k]; the arena must outlive the
+// solve.
+template <typename T>
+struct WgBatch {
+    DevBuf<unsigned char> arena;
+    std::vector<WgProblem<T>> probs;
+    std::vector<int> levels;
+};
+template <typename T>
+void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, hipStream_t s,
+                    WgBatch<T> &out);
+
+// the handle's P A P^T and ILU factor in precision T
+template <typename T> const CsrBuf<T> &ap_of(ss_liouv h);
+template <typename T> const CsrBuf<T> &lu_of(ss_liouv h);
+template <> inline const CsrBuf<float2> &ap_of<float2>(ss_liouv h) { return h->Ap32; }
+template <> inline const CsrBuf<double2> &ap_of<double2>(ss_liouv h) { return h->Ap; }
+template <> inline const CsrBuf<float2> &lu_of<float2>(ss_liouv h) { return h->LU32; }
+template <> inline const CsrBuf<double2> &lu_of<double2>(ss_liouv h) { return h->LU; }
+
 }  // namespace ss

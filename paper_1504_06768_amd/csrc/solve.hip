@@ -652,7 +652,6 @@ template <typename T>
 static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
                      ss_info *infos, int *status) {
     const int nthreads = std::max(1, std::min(count, setup_threads()));
-    std::vector<WgBundle<T>> B((size_t)count);
     std::vector<std::string> err((size_t)count);
     std::vector<int> code((size_t)count, SS_OK);
     auto parallel = [&](auto &&fn) {
@@ -813,10 +812,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         }
     }
     mark("ilu0 (batched)");
-    // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up,
-    // scratch of the level analysis, per system
-    std::vector<LevelBuild> lb_lo((size_t)count), lb_up((size_t)count);
-    std::vector<LevelJob> lj_lo((size_t)count), lj_up((size_t)count);
+    // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up, per system
     parallel([&](int i) {
         ss_liouv h = hs[i];
         hipStream_t s = stream_of(h);
@@ -832,50 +828,42 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
                              .guarded;
         }
         prepare_finish(h, method, o, s, t0, true);
-        lj_lo[(size_t)i] = lb_lo[(size_t)i].job(h->LU.view(), h->lu_diag.get(), s);
-        lj_up[(size_t)i] = lb_up[(size_t)i].job(h->LU.view(), h->lu_diag.get(), s);
         SS_HIP(hipStreamSynchronize(s));
     });
     ib.clear();
     mark("ilu result+finish prep");
-    // stage 6: level analysis of every system, one launch per side
+    // stage 6: level analysis, schedules, packed factors and the workgroup
+    // problems of every system together
+    WgBatch<T> wb;
+    std::vector<int> slot((size_t)count, -1);
     {
-        std::vector<LevelJob> lo, up;
-        for (int i = 0; i < count; ++i) {
-            if (code[(size_t)i] != SS_OK || hs[i]->n == 0) continue;
-            lo.push_back(lj_lo[(size_t)i]);
-            up.push_back(lj_up[(size_t)i]);
+        std::vector<ss_liouv> ok;
+        std::vector<int> idx;
+        for (int i = 0; i < count; ++i)
+            if (code[(size_t)i] == SS_OK) {
+                slot[(size_t)i] = (int)ok.size();
+                ok.push_back(hs[i]);
+                idx.push_back(i);
+            }
+        try {
+            wg_setup_batch<T>(ok.data(), (int)ok.size(), method, tol, o, s0, wb);
+        } catch (const Error &e) {
+            for (int i : idx) {
+                code[(size_t)i] = e.code;
+                err[(size_t)i] = e.what();
+            }
         }
-        levels_batch<false>(lo.data(), (int)lo.size(), s0);
-        levels_batch<true>(up.data(), (int)up.size(), s0);
     }
-    mark("levels (batched)");
-    // stage 7: level schedules and the workgroup problem, per system
-    parallel([&](int i) {
-        ss_liouv h = hs[i];
-        hipStream_t s = stream_of(h);
-        lb_lo[(size_t)i].finish<false>(h->LU.view(), h->lu_diag.get(), B[(size_t)i].lo, s);
-        lb_up[(size_t)i].finish<true>(h->LU.view(), h->lu_diag.get(), B[(size_t)i].up, s);
-        if constexpr (std::is_same<T, float2>::value) {
-            make_wg<T>(h, method, tol, o, h->Ap32, h->LU32, B[(size_t)i], s, true);
-        } else {
-            make_wg<T>(h, method, tol, o, h->Ap, h->LU, B[(size_t)i], s, true);
-        }
-        SS_HIP(hipStreamSynchronize(s));
-    });
-    std::vector<LevelBuild>().swap(lb_lo);
-    std::vector<LevelBuild>().swap(lb_up);
     mark("schedules+wg problem");
     const double t_setup = now_ms() - t0;
     std::vector<WgProblem<T>> probs;
-    std::vector<int> slot((size_t)count, -1);
     int max_n = 0, max_lev = 0;
     for (int i = 0; i < count; ++i) {
         if (code[(size_t)i] != SS_OK) continue;
-        slot[(size_t)i] = (int)probs.size();
-        probs.push_back(B[(size_t)i].P);
-        max_n = std::max(max_n, B[(size_t)i].P.n);
-        max_lev = std::max(max_lev, B[(size_t)i].levels);
+        const int k = slot[(size_t)i];
+        probs.push_back(wb.probs[(size_t)k]);
+        max_n = std::max(max_n, wb.probs[(size_t)k].n);
+        max_lev = std::max(max_lev, wb.levels[(size_t)k]);
     }
     float kms = 0.f;
     const double t1 = now_ms();
@@ -900,8 +888,9 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
     parallel([&](int i) {
         ss_liouv h = hs[i];
         hipStream_t s = stream_of(h);
+        const WgProblem<T> &P = wb.probs[(size_t)slot[(size_t)i]];
         WgResult hr;
-        d2h(&hr, B[(size_t)i].res.get(), 1, s);
+        d2h(&hr, P.res, 1, s);
         if (hr.status == SS_E_BREAKDOWN && !(o.flags & SS_FLAG_NO_FALLBACK)) {
             // this system again on its own, with the device-wide GMRES
             ss_options od = o;
@@ -920,8 +909,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         st.t_kernel_ms = kms;
         st.t_solve_ms = t_solve;
         st.elem_bytes = (double)sizeof(T);
-        code[(size_t)i] = finish(h, B[(size_t)i].x.get(), o, tol, st, rho_out ? rho_out[i] : nullptr,
-                                 infos ? infos + i : nullptr, s);
+        code[(size_t)i] = finish(h, P.x64, o, tol, st, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr, s);
         if (infos) infos[i].t_setup_ms = t_setup;
     });
     mark("finish (+ fallbacks)");
