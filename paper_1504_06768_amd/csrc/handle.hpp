@@ -74,6 +74,12 @@ template <typename T>
 void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
              WgBundle<T> &B, hipStream_t s, bool levels_built = false);
 
+// The outcome (status) of a solve and its info record (when info != null)
+// from the certificate ||L rho||, the Hermiticity and trace errors and the
+// bandwidth and profile of P A P^T.
+int fill_info(ss_liouv h, const ss_options &o, double tol, const SolveStats &st, double final_res, double herm_err,
+              double2 trx, int64_t bandwidth, int64_t profile, ss_info *info, hipStream_t s);
+
 // Unpermute, normalise, certify and copy out the solution x (permuted, fp64).
 int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const SolveStats &st, double *rho_out,
            ss_info *info, hipStream_t s);

@@ -657,4 +657,195 @@ template void wg_setup_batch<float2>(ss_liouv *, int, int, double, const ss_opti
 template void wg_setup_batch<double2>(ss_liouv *, int, int, double, const ss_options &, hipStream_t,
                                       WgBatch<double2> &);
 
+
+// --------------------------------------------------------------- finish
+struct FinishJob {
+    int n, d, hermitize;
+    const double2 *x;  // solution, permuted
+    const int *perm, *tpos;
+    Csr<double2> L;    // assembled L (certificate)
+    const int *prow, *pcol;  // P A P^T pattern (bandwidth, profile)
+    int *colmax;       // n scratch, zeroed
+    double2 *tmp;      // n scratch (before the Hermitian part is taken)
+    double2 *rho;      // the result, natural order (the caller's device buffer or staging)
+    double *out;       // tr.x, tr.y, ||L rho||^2, herm err, ub, lb, up, lp
+};
+
+constexpr int FIN_BS = 512;
+
+template <typename V, typename Op>
+__device__ inline V fin_reduce(V v, V *sh, Op op) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = FIN_BS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = op(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    const V r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// One block per system: the steps of finish() with the same formulas; the
+// trace is summed in the order of the one-system kernel (256 strided partial
+// sums and a tree), so rho itself is identical; the certificate's sums run
+// in another order than the device-wide SpMV and norm.
+__global__ void __launch_bounds__(FIN_BS) k_bt_finish(const FinishJob *jobs) {
+    __shared__ double sx[FIN_BS], sy[FIN_BS];
+    __shared__ long long sl[FIN_BS];
+    const FinishJob &J = jobs[blockIdx.x];
+    const int t = threadIdx.x, n = J.n, d = J.d;
+    // trace of the permuted solution
+    double ax = 0, ay = 0;
+    if (t < 256)
+        for (int k = t; k < d; k += 256) {
+            const double2 v = J.x[J.tpos[k]];
+            ax += v.x;
+            ay += v.y;
+        }
+    sx[t] = ax;
+    sy[t] = ay;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            sx[t] += sx[t + off];
+            sy[t] += sy[t + off];
+        }
+        __syncthreads();
+    }
+    const double2 tr = mk(sx[0], sy[0]);
+    __syncthreads();
+    const double2 inv = cdiv(mk(1.0, 0.0), tr);
+    double2 *r1 = J.hermitize ? J.tmp : J.rho;
+    for (int q = t; q < n; q += FIN_BS) r1[J.perm[q]] = cmul(J.x[q], inv);
+    __syncthreads();
+    if (J.hermitize) {
+        for (int q = t; q < n; q += FIN_BS) {
+            const int i = q % d, j = q / d;
+            const double2 a = J.tmp[q], b = J.tmp[(int64_t)i * d + j];
+            J.rho[q] = mk(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        }
+        __syncthreads();
+    }
+    // certificate, Hermiticity error, bandwidth and profile
+    double r2 = 0, herm = 0;
+    long long ub = 0, lb = 0, up = 0;
+    for (int r = t; r < n; r += FIN_BS) {
+        double2 acc = mk(0.0, 0.0);
+        for (int e = J.L.rowptr[r]; e < J.L.rowptr[r + 1]; ++e) acc = cadd(acc, cmul(J.L.val[e], J.rho[J.L.col[e]]));
+        r2 += acc.x * acc.x + acc.y * acc.y;
+        const int i = r % d, j = r / d;
+        const double2 a = J.rho[r], b = J.rho[(int64_t)i * d + j];
+        const double dx = a.x - b.x, dy = a.y + b.y;
+        herm = fmax(herm, sqrt(dx * dx + dy * dy));
+        const int rs = J.prow[r], re = J.prow[r + 1];
+        if (re > rs) {
+            const int cmin = J.pcol[rs], cmax = J.pcol[re - 1];
+            ub = max(ub, (long long)(cmax - r));
+            lb = max(lb, (long long)(r - cmin));
+            if (cmax > r) up += cmax - r;
+            for (int e = rs; e < re; ++e) {
+                const int c = J.pcol[e];
+                if (r > c) atomicMax(&J.colmax[c], r - c);
+            }
+        }
+    }
+    r2 = fin_reduce(r2, sx, [](double p, double q) { return p + q; });
+    herm = fin_reduce(herm, sx, [](double p, double q) { return fmax(p, q); });
+    ub = fin_reduce(ub, sl, [](long long p, long long q) { return max(p, q); });
+    lb = fin_reduce(lb, sl, [](long long p, long long q) { return max(p, q); });
+    up = fin_reduce(up, sl, [](long long p, long long q) { return p + q; });
+    __syncthreads();
+    long long lp = 0;
+    for (int c = t; c < n; c += FIN_BS) lp += J.colmax[c];
+    lp = fin_reduce(lp, sl, [](long long p, long long q) { return p + q; });
+    if (t == 0) {
+        J.out[0] = tr.x;
+        J.out[1] = tr.y;
+        J.out[2] = r2;
+        J.out[3] = herm;
+        J.out[4] = (double)ub;
+        J.out[5] = (double)lb;
+        J.out[6] = (double)up;
+        J.out[7] = (double)lp;
+    }
+}
+
+void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, double tol,
+                  const SolveStats *st, double *const *rho_out, ss_info *const *infos, int *status, hipStream_t s) {
+    if (count == 0) return;
+    StreamScope scope(s);
+    const bool herm = (o.flags & SS_FLAG_HERMITIZE) != 0;
+    std::vector<char> on_dev((size_t)count, 0);
+    std::vector<size_t> off((size_t)count + 1, 0), soff((size_t)count + 1, 0);
+    for (int k = 0; k < count; ++k) {
+        const size_t n = (size_t)hs[k]->n;
+        on_dev[(size_t)k] = rho_out[k] && is_device_ptr(rho_out[k]);
+        off[(size_t)k + 1] = off[(size_t)k] + (herm ? n : 0);
+        soff[(size_t)k + 1] = soff[(size_t)k] + (on_dev[(size_t)k] ? 0 : n);
+    }
+    size_t nint = 0;
+    for (int k = 0; k < count; ++k) nint += (size_t)hs[k]->n;
+    DevBuf<int> colmax(nint);
+    DevBuf<double2> tmp(off[(size_t)count]), stage(soff[(size_t)count]);
+    DevBuf<double> out((size_t)8 * count);
+    SS_HIP(hipMemsetAsync(colmax.get(), 0, colmax.bytes(), s));
+    std::vector<FinishJob> fj((size_t)count);
+    size_t ci = 0;
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        FinishJob &j = fj[(size_t)k];
+        j.n = h->n;
+        j.d = h->d;
+        j.hermitize = herm ? 1 : 0;
+        j.x = xs[k];
+        j.perm = h->perm.get();
+        j.tpos = h->tpos.get();
+        j.L = h->L.view();
+        j.prow = h->Ap.rowptr.get();
+        j.pcol = h->Ap.col.get();
+        j.colmax = colmax.get() + ci;
+        ci += (size_t)h->n;
+        j.tmp = tmp.get() + off[(size_t)k];
+        j.rho = on_dev[(size_t)k] ? reinterpret_cast<double2 *>(rho_out[k]) : stage.get() + soff[(size_t)k];
+        j.out = out.get() + 8 * (size_t)k;
+    }
+    DevBuf<FinishJob> dj = upload(fj, s);
+    k_bt_finish<<<(unsigned)count, FIN_BS, 0, s>>>(dj.get());
+    SS_HIP(hipGetLastError());
+    std::vector<double> ho((size_t)8 * count);
+    d2h(ho.data(), out.get(), ho.size(), s);
+    if (soff[(size_t)count]) {
+        std::vector<double2> hr(soff[(size_t)count]);
+        d2h(hr.data(), stage.get(), hr.size(), s);
+        for (int k = 0; k < count; ++k)
+            if (rho_out[k] && !on_dev[(size_t)k])
+                std::memcpy(rho_out[k], hr.data() + soff[(size_t)k], sizeof(double2) * hs[k]->n);
+    }
+    for (int k = 0; k < count; ++k) {
+        const double *v = ho.data() + 8 * (size_t)k;
+        const int64_t bw = (int64_t)v[4] + (int64_t)v[5] + 1;
+        const int64_t pf = (int64_t)v[6] + (int64_t)v[7];
+        status[k] = fill_info(hs[k], o, tol, st[k], sqrt(v[2]), v[3], mk(v[0], v[1]), bw, pf, infos[k],
+                              stream_peek(hs[k]));
+    }
+}
+
+
+__global__ void k_bt_results(const WgResult *const *src, int count, WgResult *dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) dst[k] = *src[k];
+}
+
+void read_results(const std::vector<const WgResult *> &src, std::vector<WgResult> &out, hipStream_t s) {
+    out.resize(src.size());
+    if (src.empty()) return;
+    StreamScope scope(s);
+    DevBuf<const WgResult *> dsrc = upload(src, s);
+    DevBuf<WgResult> dst(src.size());
+    k_bt_results<<<div_up((int64_t)src.size(), 256), 256, 0, s>>>(dsrc.get(), (int)src.size(), dst.get());
+    SS_HIP(hipGetLastError());
+    d2h(out.data(), dst.get(), out.size(), s);
+}
+
 }  // namespace ss

@@ -38,6 +38,15 @@ template <typename T>
 void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, hipStream_t s,
                     WgBatch<T> &out);
 
+// finish() for many systems in one launch (one block each): xs[k] is the
+// permuted fp64 solution of hs[k], rho_out[k] (host, device or null) and
+// infos[k] (or null) receive its results, status[k] its outcome.
+void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, double tol,
+                  const SolveStats *st, double *const *rho_out, ss_info *const *infos, int *status, hipStream_t s);
+
+// out[k] = *src[k] (device result records), one host wait.
+void read_results(const std::vector<const WgResult *> &src, std::vector<WgResult> &out, hipStream_t s);
+
 // the handle's P A P^T and ILU factor in precision T
 template <typename T> const CsrBuf<T> &ap_of(ss_liouv h);
 template <typename T> const CsrBuf<T> &lu_of(ss_liouv h);

@@ -376,6 +376,47 @@ static double condition_estimate(ss_liouv h, hipStream_t s) {
     return v.x;
 }
 
+// The outcome and the info record of a finished solve.
+int fill_info(ss_liouv h, const ss_options &o, double tol, const SolveStats &st, double final_res, double herm_err,
+              double2 trx, int64_t bandwidth, int64_t profile, ss_info *info, hipStream_t s) {
+    const int n = h->n;
+    int status = st.status;
+    if (status == SS_E_NOT_CONVERGED && final_res <= tol) status = SS_OK;
+    if (info) {
+        info->status = status;
+        info->outer_its = st.outer;
+        info->inner_its = st.inner;
+        info->breakdowns = st.breakdowns;
+        info->pivots_guarded = h->guarded;
+        info->fell_back = st.fell_back;
+        info->nnz_matrix = h->Ap.nnz;
+        info->nnz_factors = h->LU.nnz;
+        info->fill_factor = h->Ap.nnz ? (double)h->LU.nnz / h->Ap.nnz : 0.0;
+        info->resid_l2 = final_res;
+        info->herm_err = herm_err;
+        info->trace_err = sqrt((trx.x - 1.0) * (trx.x - 1.0) + trx.y * trx.y);
+        info->weight = h->w.x;
+        info->method = h->p_method;
+        info->bandwidth = (int32_t)bandwidth;
+        info->profile = profile;
+        info->cond_est = (o.flags & SS_FLAG_COND_EST) ? condition_estimate(h, s) : 0.0;
+        info->t_setup_ms = h->t_setup_ms;
+        info->t_solve_ms = st.t_solve_ms;
+        info->t_kernel_ms = st.t_kernel_ms;
+        info->path = st.path;
+        // algorithmic bytes: per BiCGSTAB iteration two SpMV and two triangular
+        // solve pairs plus about 24 vector passes; per outer step one fp64
+        // SpMV and about 6 vector passes (values, indices, row pointers and
+        // vectors each counted once per use)
+        const double sT = st.elem_bytes;
+        const double spmvT = (double)h->Ap.nnz * (sT + 4) + 4.0 * (n + 1) + 2.0 * n * sT;
+        const double trsvT = (double)h->LU.nnz * (sT + 4) + 8.0 * (n + 1) + 8.0 * n + 4.0 * n * sT;
+        const double spmv64 = (double)h->Ap.nnz * 20.0 + 4.0 * (n + 1) + 32.0 * n;
+        info->bytes_alg = st.inner * (2 * spmvT + 2 * trsvT + 24.0 * n * sT) + (st.outer + 1) * (spmv64 + 96.0 * n);
+    }
+    return status;
+}
+
 // Finish a solve: unpermute, normalise the trace, certify with L itself,
 // Hermiticity error, copy rho out (host or device), fill info.
 int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const SolveStats &st, double *rho_out,
@@ -411,43 +452,9 @@ int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const 
         SS_HIP(hipMemcpyAsync(rho_out, rho.get(), sizeof(double2) * n, k, s));
         SS_HIP(hipStreamSynchronize(s));
     }
-    const double final_res = sqrt(fin[0].x);
-    int status = st.status;
-    if (status == SS_E_NOT_CONVERGED && final_res <= tol) status = SS_OK;
-    if (info) {
-        info->status = status;
-        info->outer_its = st.outer;
-        info->inner_its = st.inner;
-        info->breakdowns = st.breakdowns;
-        info->pivots_guarded = h->guarded;
-        info->fell_back = st.fell_back;
-        info->nnz_matrix = h->Ap.nnz;
-        info->nnz_factors = h->LU.nnz;
-        info->fill_factor = h->Ap.nnz ? (double)h->LU.nnz / h->Ap.nnz : 0.0;
-        info->resid_l2 = final_res;
-        info->herm_err = fin[1].x;
-        info->trace_err = sqrt((trx.x - 1.0) * (trx.x - 1.0) + trx.y * trx.y);
-        info->weight = h->w.x;
-        info->method = h->p_method;
-        int64_t bw = 0, pf = 0;
-        bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bw, &pf, s);
-        info->bandwidth = (int32_t)bw;
-        info->profile = pf;
-        info->cond_est = (o.flags & SS_FLAG_COND_EST) ? condition_estimate(h, s) : 0.0;
-        info->t_setup_ms = h->t_setup_ms;
-        info->t_solve_ms = st.t_solve_ms;
-        info->t_kernel_ms = st.t_kernel_ms;
-        info->path = st.path;
-        // algorithmic bytes: per BiCGSTAB iteration two SpMV and two triangular
-        // solve pairs plus about 24 vector passes; per outer step one fp64
-        // SpMV and about 6 vector passes (values, indices, row pointers and
-        // vectors each counted once per use)
-        const double sT = st.elem_bytes;
-        const double spmvT = (double)h->Ap.nnz * (sT + 4) + 4.0 * (n + 1) + 2.0 * n * sT;
-        const double trsvT = (double)h->LU.nnz * (sT + 4) + 8.0 * (n + 1) + 8.0 * n + 4.0 * n * sT;
-        const double spmv64 = (double)h->Ap.nnz * 20.0 + 4.0 * (n + 1) + 32.0 * n;
-        info->bytes_alg = st.inner * (2 * spmvT + 2 * trsvT + 24.0 * n * sT) + (st.outer + 1) * (spmv64 + 96.0 * n);
-    }
+    int64_t bw = 0, pf = 0;
+    if (info) bandwidth_profile(h->Ap.n, h->Ap.rowptr.get(), h->Ap.col.get(), &bw, &pf, s);
+    const int status = fill_info(h, o, tol, st, sqrt(fin[0].x), fin[1].x, trx, bw, pf, info, s);
     return status;
 }
 
@@ -885,20 +892,31 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
     const double t_solve = now_ms() - t1;
     mark("workgroup solve");
     const int path = wg_fits_lds((size_t)max_n, sizeof(T), max_lev) ? 2 : 1;
-    parallel([&](int i) {
-        ss_liouv h = hs[i];
-        hipStream_t s = stream_of(h);
-        const WgProblem<T> &P = wb.probs[(size_t)slot[(size_t)i]];
-        WgResult hr;
-        d2h(&hr, P.res, 1, s);
+    // outcomes of every system, read back together
+    std::vector<int> solved;
+    std::vector<const WgResult *> rptr;
+    for (int i = 0; i < count; ++i)
+        if (code[(size_t)i] == SS_OK) {
+            solved.push_back(i);
+            rptr.push_back(wb.probs[(size_t)slot[(size_t)i]].res);
+        }
+    std::vector<WgResult> hres;
+    read_results(rptr, hres, s0);
+    // systems whose BiCGSTAB broke down: again on their own with the
+    // device-wide GMRES; the others finish together
+    std::vector<char> again((size_t)count, 0);
+    std::vector<ss_liouv> fh;
+    std::vector<const double2 *> fx;
+    std::vector<SolveStats> fst;
+    std::vector<double *> fout;
+    std::vector<ss_info *> finfo;
+    std::vector<int> fidx;
+    for (size_t k = 0; k < solved.size(); ++k) {
+        const int i = solved[k];
+        const WgResult &hr = hres[k];
         if (hr.status == SS_E_BREAKDOWN && !(o.flags & SS_FLAG_NO_FALLBACK)) {
-            // this system again on its own, with the device-wide GMRES
-            ss_options od = o;
-            od.flags |= SS_FLAG_DEVICE_WIDE;
-            const int gm = (method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
-            code[(size_t)i] = solve(h, gm, tol, od, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr);
-            if (infos) infos[i].fell_back = 1;
-            return;
+            again[(size_t)i] = 1;
+            continue;
         }
         SolveStats st;
         st.status = hr.status;
@@ -909,8 +927,37 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         st.t_kernel_ms = kms;
         st.t_solve_ms = t_solve;
         st.elem_bytes = (double)sizeof(T);
-        code[(size_t)i] = finish(h, P.x64, o, tol, st, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr, s);
-        if (infos) infos[i].t_setup_ms = t_setup;
+        fh.push_back(hs[i]);
+        fx.push_back(wb.probs[(size_t)slot[(size_t)i]].x64);
+        fst.push_back(st);
+        fout.push_back(rho_out ? rho_out[i] : nullptr);
+        finfo.push_back(infos ? infos + i : nullptr);
+        fidx.push_back(i);
+    }
+    {
+        std::vector<int> fstat(fh.size(), SS_OK);
+        try {
+            finish_batch(fh.data(), (int)fh.size(), fx.data(), o, tol, fst.data(), fout.data(), finfo.data(),
+                         fstat.data(), s0);
+        } catch (const Error &e) {
+            for (size_t k = 0; k < fh.size(); ++k) {
+                fstat[k] = e.code;
+                err[(size_t)fidx[k]] = e.what();
+            }
+        }
+        for (size_t k = 0; k < fh.size(); ++k) {
+            code[(size_t)fidx[k]] = fstat[k];
+            if (infos) infos[fidx[k]].t_setup_ms = t_setup;
+        }
+    }
+    parallel([&](int i) {
+        if (!again[(size_t)i]) return;
+        ss_liouv h = hs[i];
+        ss_options od = o;
+        od.flags |= SS_FLAG_DEVICE_WIDE;
+        const int gm = (method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
+        code[(size_t)i] = solve(h, gm, tol, od, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr);
+        if (infos) infos[i].fell_back = 1;
     });
     mark("finish (+ fallbacks)");
     int first = SS_OK;

@@ -67,7 +67,9 @@ def test_caller_allocator_is_used_and_gives_the_same_result():
     HIP runtime the library uses: every device block of a solve goes
     through them, all are returned, and the result is bit-identical."""
     import ctypes
-    hip = ctypes.CDLL("libamdhip64.so")
+    # hipMalloc / hipFree looked up through libss.so's own dependencies: the
+    # HIP runtime the library uses, whatever other copy (torch's) is loaded
+    hip = ctypes.CDLL(ssl.library_path())
     hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
     hip.hipFree.argtypes = [ctypes.c_void_p]
     s = qs.jaynes_cummings(8, seed=0)
