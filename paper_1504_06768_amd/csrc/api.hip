@@ -172,8 +172,9 @@ int ss_build_liouvillian_batch(int32_t count, const ss_csr_z *H, const ss_csr_z 
 void ss_liouv_free(ss_liouv L) {
     if (!L) return;
     // the stream belongs to the pool: its work is left to finish, and every
-    // device block of the handle is released against it
+    // device block of the handle is released against one event on it
     if (L->own_stream) ss::set_current_stream(L->own_stream);
+    ss::FreeScope scope(ss::stream_peek(L));
     delete L;
 }
 

@@ -41,6 +41,19 @@ void dev_free(void *p);
 // it) for the work queued there, never for the host
 void set_current_stream(hipStream_t s);
 hipStream_t current_stream();
+// Releases by this thread, during the scope, of blocks tagged with stream s
+// share one event recorded on s when the scope opens (instead of one event
+// per block): for tearing down an object whose work on s is all queued.
+struct FreeScope {
+    explicit FreeScope(hipStream_t s);
+    ~FreeScope();
+    FreeScope(const FreeScope &) = delete;
+    FreeScope &operator=(const FreeScope &) = delete;
+
+  private:
+    hipEvent_t ev_ = nullptr, prev_ev = nullptr;
+    hipStream_t prev_s = nullptr;
+};
 // the calling thread's current stream is s for the lifetime of the scope
 struct StreamScope {
     hipStream_t prev;

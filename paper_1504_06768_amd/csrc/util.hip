@@ -37,11 +37,20 @@ struct Live {
     bool user;       // made by the caller's allocator
 };
 
+// An event may mark the release of several blocks (all those a free scope
+// releases); it returns to the pool when the last of them is reused.  Once
+// seen complete it is not queried again.
+struct EvState {
+    int refs;
+    bool done;
+};
+
 struct Cache {
     std::mutex mu;
     std::unordered_map<void *, Live> live;
     std::map<size_t, std::vector<Cached>> free_by_cls;
     std::vector<hipEvent_t> events;
+    std::unordered_map<hipEvent_t, EvState> evs;
     size_t cached = 0;
 };
 
@@ -51,6 +60,40 @@ Cache &cache() {
 }
 
 thread_local hipStream_t t_current = nullptr;
+thread_local hipEvent_t t_free_ev = nullptr;   // event of the open free scope
+thread_local hipStream_t t_free_s = nullptr;   // its stream
+
+// (the cache lock is held by the callers of these three)
+hipEvent_t take_event(Cache &c) {
+    if (!c.events.empty()) {
+        hipEvent_t ev = c.events.back();
+        c.events.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return ev;
+}
+
+void release_event(Cache &c, hipEvent_t ev) {
+    auto it = c.evs.find(ev);
+    if (it == c.evs.end()) return;
+    if (--it->second.refs == 0) {
+        c.evs.erase(it);
+        c.events.push_back(ev);
+    }
+}
+
+bool event_done(Cache &c, hipEvent_t ev) {
+    auto it = c.evs.find(ev);
+    if (it != c.evs.end() && it->second.done) return true;
+    if (hipEventQuery(ev) != hipSuccess) return false;
+    if (it != c.evs.end()) it->second.done = true;
+    return true;
+}
 
 // optional caller allocator (ss_set_allocator)
 ss_alloc_fn g_user_alloc = nullptr;
@@ -98,6 +141,38 @@ void *raw_alloc(size_t bytes) {
 
 }  // namespace
 
+FreeScope::FreeScope(hipStream_t s) {
+    if (!s) return;
+    Cache &c = cache();
+    hipEvent_t ev;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        ev = take_event(c);
+        if (!ev) return;
+        c.evs[ev] = EvState{1, false};  // the scope's own reference
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(c.mu);
+        release_event(c, ev);
+        return;
+    }
+    prev_ev = t_free_ev;
+    prev_s = t_free_s;
+    t_free_ev = ev;
+    t_free_s = s;
+    ev_ = ev;
+}
+
+FreeScope::~FreeScope() {
+    if (!ev_) return;
+    t_free_ev = prev_ev;
+    t_free_s = prev_s;
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    release_event(c, ev_);
+}
+
 void set_current_stream(hipStream_t s) { t_current = s; }
 hipStream_t current_stream() { return t_current; }
 
@@ -115,7 +190,7 @@ void trim_device_cache() {
         for (Cached &b : kv.second) {
             (void)hipEventSynchronize(b.ev);
             raw_free(b.p, b.user);
-            c.events.push_back(b.ev);
+            release_event(c, b.ev);
         }
         kv.second.clear();
     }
@@ -134,9 +209,9 @@ void *dev_alloc(size_t bytes) {
             // oldest first: those are the blocks whose last use has most
             // likely completed, so the first query usually succeeds
             for (size_t k = 0; k < v.size(); ++k) {
-                if (v[k].user == user && hipEventQuery(v[k].ev) == hipSuccess) {
+                if (v[k].user == user && event_done(c, v[k].ev)) {
                     void *p = v[k].p;
-                    c.events.push_back(v[k].ev);
+                    release_event(c, v[k].ev);
                     v.erase(v.begin() + (long)k);
                     c.cached -= cls;
                     c.live[p] = Live{cls, t_current, user};
@@ -164,17 +239,19 @@ void dev_free(void *p) {
         l = it->second;
         c.live.erase(it);
         if (l.cls && c.cached + l.cls <= CACHE_MAX_TOTAL) {
-            hipEvent_t ev = nullptr;
-            if (!c.events.empty()) {
-                ev = c.events.back();
-                c.events.pop_back();
-            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                (void)hipGetLastError();
-                ev = nullptr;
+            if (t_free_ev && l.s == t_free_s) {
+                // a free scope on the block's stream: its event covers every
+                // use queued before the scope opened
+                c.evs[t_free_ev].refs++;
+                c.free_by_cls[l.cls].push_back(Cached{p, t_free_ev, l.user});
+                c.cached += l.cls;
+                return;
             }
+            hipEvent_t ev = take_event(c);
             if (ev) {
                 if (!l.s) (void)hipDeviceSynchronize();  // no stream known: wait for everything
                 if (hipEventRecord(ev, l.s) == hipSuccess) {
+                    c.evs[ev] = EvState{1, false};
                     c.free_by_cls[l.cls].push_back(Cached{p, ev, l.user});
                     c.cached += l.cls;
                     return;
