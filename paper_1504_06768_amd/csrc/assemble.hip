@@ -427,14 +427,15 @@ __global__ void __launch_bounds__(256) k_asm_rows(const RowJob *jobs, const int 
     else J.rowptr[r] = liouvillian_row<false>(J.S, r, nullptr, nullptr);
 }
 
-static void check_matrix(const ss_csr_z *m, int64_t N, int sys, const char *what) {
+static void check_matrix(const ss_csr_z *m, int64_t N, int sys, const char *what, bool on_device) {
     const std::string w = "system " + std::to_string(sys) + ", " + what;
     SS_REQUIRE(m != nullptr, SS_E_INVALID_ARG, w + ": null matrix");
     SS_REQUIRE(m->n == N, SS_E_INVALID_ARG, w + ": dimension " + std::to_string(m->n) + " != N = " + std::to_string(N));
     SS_REQUIRE(m->nnz >= 0 && m->nnz < (int64_t(1) << 31), SS_E_INVALID_ARG, w + ": bad nnz");
     SS_REQUIRE(m->indptr != nullptr, SS_E_INVALID_ARG, w + ": null indptr");
     SS_REQUIRE(m->nnz == 0 || (m->indices && m->data), SS_E_INVALID_ARG, w + ": null arrays");
-    SS_REQUIRE(is_device_ptr(m->indptr) && (m->nnz == 0 || (is_device_ptr(m->indices) && is_device_ptr(m->data))),
+    SS_REQUIRE(on_device ||
+                   (is_device_ptr(m->indptr) && (m->nnz == 0 || (is_device_ptr(m->indices) && is_device_ptr(m->data)))),
                SS_E_INVALID_ARG, w + ": batched assembly takes device arrays only");
 }
 
@@ -627,9 +628,9 @@ static void assemble_chunk(int k0, int k1, const ss_csr_z *H, const ss_csr_z *co
 }
 
 void assemble_batch(int count, const ss_csr_z *H, const ss_csr_z *const *c_ops, const int *n_cops,
-                    const AsmTarget *out, hipStream_t s) {
+                    const AsmTarget *out, hipStream_t s, bool on_device) {
     for (int k = 0; k < count; ++k) {
-        check_matrix(&H[k], H[k].n, k, "H");
+        check_matrix(&H[k], H[k].n, k, "H", on_device);
         const int64_t N = H[k].n;
         SS_REQUIRE(batch_assembly_fits(N), SS_E_INVALID_ARG,
                    "system " + std::to_string(k) + ": batched assembly takes N in [1, " +
@@ -638,7 +639,7 @@ void assemble_batch(int count, const ss_csr_z *H, const ss_csr_z *const *c_ops, 
                    "system " + std::to_string(k) + ": n_cops must be in [0, " + std::to_string(MAX_COPS) + "]");
         SS_REQUIRE(n_cops[k] == 0 || c_ops[k] != nullptr, SS_E_INVALID_ARG,
                    "system " + std::to_string(k) + ": c_ops is NULL");
-        for (int c = 0; c < n_cops[k]; ++c) check_matrix(&c_ops[k][c], N, k, "c_ops[k]");
+        for (int c = 0; c < n_cops[k]; ++c) check_matrix(&c_ops[k][c], N, k, "c_ops[k]", on_device);
     }
     // chunks whose dense staging stays under the cap (SS_ASM_STAGE_MB
     // lowers it, so that small batches can exercise the chunking)

@@ -31,7 +31,8 @@ struct AsmTarget {
 };
 
 bool batch_assembly_fits(int64_t N);
+// (on_device: the caller guarantees every array is device memory)
 void assemble_batch(int count, const ss_csr_z *H, const ss_csr_z *const *c_ops, const int *n_cops,
-                    const AsmTarget *out, hipStream_t s);
+                    const AsmTarget *out, hipStream_t s, bool on_device = false);
 
 }  // namespace ss

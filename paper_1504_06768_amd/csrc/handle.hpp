@@ -44,10 +44,12 @@ hipStream_t stream_of(ss_liouv h);    // the handle's stream, made the thread's 
 hipStream_t stream_peek(ss_liouv h);  // the handle's stream (current stream unchanged)
 void prepare(ss_liouv h, int method, const ss_options &o);
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info);
+// tols (optional, count entries) gives each system its own tolerance.
 int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
-                ss_info *infos, int *status);
+                ss_info *infos, int *status, const double *tols = nullptr);
 const std::string &batch_error();  // message of the first failed system of the last batch (this thread)
 bool use_workgroup(ss_liouv h, int method, const ss_options &o);
+bool use_workgroup_n(int64_t n, int method, const ss_options &o);  // the same rule for a size n = N^2
 
 // Counters of one solve, handed to finish().
 struct SolveStats {

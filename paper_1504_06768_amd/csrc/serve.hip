@@ -1,18 +1,17 @@
 // Continuous-batching request server (ss_server_*): many small steady-state
 // solves resident on the device at once.
 //
-// Pipeline of one request: submitted (inputs copied) -> admitted, when a slot
-// is free and its predicted device footprint fits the budget -> set up by a
-// worker thread on its own stream (assembly, transform, RCM, ILU, level
-// schedules: the same kernels as ss_solve) -> ready -> solved together with
-// every other ready request of the same precision in one launch of the
-// workgroup-resident solver (one workgroup per request) -> finished
-// (certificate, rho copied to the host) -> its device memory returns to the
-// budget.  Requests that arrive while a batch runs are admitted and set up
-// concurrently on the worker streams and join the next launch, so set-up and
-// solve work of different requests overlap on the device.  Each request's
-// arithmetic is confined to its own workgroup, so its result does not depend
-// on what else is in the batch.
+// Pipeline: submitted (inputs copied to the host and validated there) ->
+// admitted, in arrival order while a slot is free and the predicted device
+// footprint fits the budget -> every admitted request with the same method
+// and options goes through the batched path together: its inputs reach the
+// device in one copy, the Liouvillians are assembled by the batched
+// assembly, and the batched solve runs the set-up stages, one launch of the
+// workgroup-resident solver (one workgroup per request) and the finish for
+// all of them -> done (rho and info kept for ss_poll) -> the device memory
+// returns to the budget.  Requests that arrive while a group runs wait in
+// the queue and form the next group.  Each request's arithmetic stays in its
+// own workgroup, so its result does not depend on what else is in the group.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -21,6 +20,11 @@
 #include <mutex>
 #include <thread>
 
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "assemble.hpp"
 #include "handle.hpp"
 
 namespace ss {
@@ -60,6 +64,21 @@ static HostCsr copy_in(const ss_csr_z *m, int64_t N, const char *what) {
         cp(h.indices.data(), m->indices, sizeof(int32_t) * h.indices.size());
         cp(h.data.data(), m->data, sizeof(double) * h.data.size());
     }
+    // the checks of the device-side validation, on the copy, so that a bad
+    // request is refused here and never reaches a group
+    SS_REQUIRE(h.indptr[0] == 0 && h.indptr[(size_t)h.n] == m->nnz, SS_E_INVALID_ARG,
+               std::string(what) + ": malformed indptr");
+    for (int64_t r = 0; r < h.n; ++r) {
+        const int64_t p = h.indptr[(size_t)r], q = h.indptr[(size_t)r + 1];
+        SS_REQUIRE(p <= q && q <= m->nnz, SS_E_INVALID_ARG, std::string(what) + ": malformed indptr");
+        for (int64_t e = p; e < q; ++e) {
+            const int32_t c = h.indices[(size_t)e];
+            SS_REQUIRE(c >= 0 && c < h.n && (e == p || c > h.indices[(size_t)e - 1]), SS_E_INVALID_ARG,
+                       std::string(what) + ": column indices must be in range and strictly increasing per row");
+            SS_REQUIRE(std::isfinite(h.data[2 * (size_t)e]) && std::isfinite(h.data[2 * (size_t)e + 1]),
+                       SS_E_INVALID_ARG, std::string(what) + ": non-finite value");
+        }
+    }
     return h;
 }
 
@@ -97,11 +116,7 @@ struct Request {
     double tol = 1e-10;
     ss_options opt{};
     size_t footprint = 0;
-    enum State { QUEUED, SETUP, READY, DONE } state = QUEUED;
-    // device state while resident
-    ss_liouv h = nullptr;
-    WgBundle<double2> b64;
-    WgBundle<float2> b32;
+    enum State { QUEUED, RUNNING, DONE } state = QUEUED;
     // result
     int status = SS_OK;
     std::string error;
@@ -115,19 +130,19 @@ struct ss_server_s {
     size_t budget = 0;
     int max_slots = 0;
     std::mutex mu;
-    std::condition_variable cv;       // wakes the scheduler and the setup workers
+    std::condition_variable cv;       // wakes the scheduler
     std::condition_variable done_cv;  // wakes ss_server_drain
-    std::deque<ss::Request *> queued, to_setup;
+    std::deque<ss::Request *> queued;
     std::map<uint64_t, ss::Request *> all;
-    std::vector<ss::Request *> ready;
     size_t used = 0;
     int resident = 0;
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::vector<std::thread> workers;
     std::thread scheduler;
     hipStream_t solve_stream = nullptr;
     int device = 0;
+    void *pinned = nullptr;  // staging of a group's inputs (page-locked)
+    size_t pinned_bytes = 0;
 };
 
 namespace ss {
@@ -138,132 +153,119 @@ static void set_error(Request *r, int code, const std::string &msg) {
     r->info.status = code;
 }
 
-static void release_device(ss_server_s *S, Request *r) {
-    if (r->h) ss_liouv_free(r->h);
-    r->h = nullptr;
-    r->b64 = WgBundle<double2>();
-    r->b32 = WgBundle<float2>();
-    S->used -= r->footprint;
-    S->resident -= 1;
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static size_t staged_bytes(const HostCsr &m) {
+    return align256(sizeof(int64_t) * m.indptr.size()) + align256(sizeof(int32_t) * m.indices.size()) +
+           align256(sizeof(double) * m.data.size());
 }
 
-// Set-up worker: assembly, transform, ordering, factorisation and the
-// workgroup problem of admitted requests, on the handle's own stream.
-static void worker_loop(ss_server_s *S) {
-    (void)hipSetDevice(S->device);
-    while (true) {
-        Request *r = nullptr;
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            S->cv.wait(lk, [&] { return S->stop || !S->to_setup.empty(); });
-            if (S->stop) return;
-            r = S->to_setup.front();
-            S->to_setup.pop_front();
-        }
-        int code = SS_OK;
-        std::string msg;
-        try {
-            ss_csr_z Hv = r->H.view();
-            std::vector<ss_csr_z> Cv;
-            for (const HostCsr &c : r->C) Cv.push_back(c.view());
-            ss_liouv h = nullptr;
-            const int rc = ss_build_liouvillian(&Hv, Cv.empty() ? nullptr : Cv.data(), (int32_t)Cv.size(), r->N, &h);
-            if (rc != SS_OK) throw Error(rc, ss_last_error());
-            r->h = h;
-            SS_REQUIRE(use_workgroup(h, r->method, r->opt), SS_E_INVALID_ARG,
-                       "the server solves BiCGSTAB methods of systems that fit one workgroup");
-            prepare(h, r->method, r->opt);
-            hipStream_t s = stream_of(h);
-            if (r->opt.prec == SS_MIXED) make_wg<float2>(h, r->method, r->tol, r->opt, h->Ap32, h->LU32, r->b32, s);
-            else make_wg<double2>(h, r->method, r->tol, r->opt, h->Ap, h->LU, r->b64, s);
-            SS_HIP(hipStreamSynchronize(s));
-        } catch (const Error &e) {
-            code = e.code;
-            msg = e.what();
-        } catch (const std::exception &e) {
-            code = SS_E_HIP;
-            msg = e.what();
-        }
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (code != SS_OK) {
-            set_error(r, code, msg);
-            release_device(S, r);
-            r->state = Request::DONE;
-            S->done_cv.notify_all();
-        } else {
-            r->state = Request::READY;
-            S->ready.push_back(r);
-        }
-        S->cv.notify_all();
-    }
-}
-
-template <typename T> WgBundle<T> &bundle(Request *r);
-template <> WgBundle<double2> &bundle<double2>(Request *r) { return r->b64; }
-template <> WgBundle<float2> &bundle<float2>(Request *r) { return r->b32; }
-
-template <typename T>
-static void solve_batch(ss_server_s *S, std::vector<Request *> &batch) {
+// One group (same method and options): inputs to the device in one copy,
+// batched assembly, batched solve; results kept in the requests.
+static void run_group(ss_server_s *S, std::vector<Request *> &g) {
     hipStream_t s = S->solve_stream;
-    std::vector<WgProblem<T>> probs;
-    int max_n = 0, max_lev = 0;
-    for (Request *r : batch) {
-        WgBundle<T> &B = bundle<T>(r);
-        probs.push_back(B.P);
-        max_n = std::max(max_n, B.P.n);
-        max_lev = std::max(max_lev, B.levels);
+    set_current_stream(s);
+    const int m = (int)g.size();
+    size_t bytes = 0;
+    for (Request *r : g) {
+        bytes += staged_bytes(r->H);
+        for (const HostCsr &c : r->C) bytes += staged_bytes(c);
     }
-    DevBuf<WgProblem<T>> dP(probs.size());
-    h2d(dP.get(), probs.data(), probs.size(), s);
-    const auto t0 = std::chrono::steady_clock::now();
-    wg_solve<T>(dP.get(), (int)probs.size(), max_n, max_lev, s);
-    SS_HIP(hipStreamSynchronize(s));
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (Request *r : batch) {
-        WgBundle<T> &B = bundle<T>(r);
-        WgResult hr;
-        d2h(&hr, B.res.get(), 1, s);
-        SolveStats st;
-        st.status = hr.status;
-        st.outer = hr.outer;
-        st.inner = hr.inner;
-        st.breakdowns = hr.breakdowns;
-        st.path = wg_fits_lds((size_t)max_n, sizeof(T), max_lev) ? 2 : 1;
-        st.t_kernel_ms = ms;
-        st.t_solve_ms = ms;
-        st.elem_bytes = (double)sizeof(T);
+    bytes = std::max<size_t>(bytes, 256);
+    if (S->pinned_bytes < bytes) {
+        if (S->pinned) SS_HIP(hipHostFree(S->pinned));
+        S->pinned = nullptr;
+        S->pinned_bytes = 0;
+        SS_HIP(hipHostMalloc(&S->pinned, bytes, hipHostMallocDefault));
+        S->pinned_bytes = bytes;
+    }
+    DevBuf<unsigned char> dev(bytes);
+    unsigned char *host = static_cast<unsigned char *>(S->pinned);
+    size_t off = 0;
+    auto stage = [&](const HostCsr &a) {
+        ss_csr_z d;
+        d.n = a.n;
+        d.nnz = (int64_t)a.indices.size();
+        std::memcpy(host + off, a.indptr.data(), sizeof(int64_t) * a.indptr.size());
+        d.indptr = reinterpret_cast<const int64_t *>(dev.get() + off);
+        off += align256(sizeof(int64_t) * a.indptr.size());
+        std::memcpy(host + off, a.indices.data(), sizeof(int32_t) * a.indices.size());
+        d.indices = reinterpret_cast<const int32_t *>(dev.get() + off);
+        off += align256(sizeof(int32_t) * a.indices.size());
+        std::memcpy(host + off, a.data.data(), sizeof(double) * a.data.size());
+        d.data = reinterpret_cast<const double *>(dev.get() + off);
+        off += align256(sizeof(double) * a.data.size());
+        return d;
+    };
+    std::vector<ss_csr_z> Hd((size_t)m);
+    std::vector<std::vector<ss_csr_z>> Cd((size_t)m);
+    std::vector<const ss_csr_z *> Cp((size_t)m);
+    std::vector<int> nc((size_t)m);
+    for (int k = 0; k < m; ++k) {
+        Hd[(size_t)k] = stage(g[(size_t)k]->H);
+        for (const HostCsr &c : g[(size_t)k]->C) Cd[(size_t)k].push_back(stage(c));
+        Cp[(size_t)k] = Cd[(size_t)k].empty() ? nullptr : Cd[(size_t)k].data();
+        nc[(size_t)k] = (int)Cd[(size_t)k].size();
+    }
+    SS_HIP(hipMemcpyAsync(dev.get(), host, off, hipMemcpyHostToDevice, s));
+    // handles and their batched assembly (the copy above is ordered before it on s)
+    std::vector<std::unique_ptr<ss_liouv_s>> hs;
+    std::vector<AsmTarget> tg;
+    for (Request *r : g) {
+        std::unique_ptr<ss_liouv_s> h(new ss_liouv_s());
+        h->own_stream = pooled_stream();
+        h->N = r->N;
+        h->d = (int)r->N;
+        h->n = (int)(r->N * r->N);
+        tg.push_back(AsmTarget{&h->L, &h->lin, stream_peek(h.get())});
+        hs.push_back(std::move(h));
+    }
+    assemble_batch(m, Hd.data(), Cp.data(), nc.data(), tg.data(), s, true);
+    // the batched solve, each request with its own tolerance
+    std::vector<ss_liouv> hp;
+    std::vector<double *> outs;
+    std::vector<double> tols;
+    for (int k = 0; k < m; ++k) {
+        Request *r = g[(size_t)k];
         r->rho.resize(2 * (size_t)r->N * r->N);
-        if (hr.status == SS_E_BREAKDOWN && !(r->opt.flags & SS_FLAG_NO_FALLBACK)) {
-            // BiCGSTAB broke down, diverged or stalled on this request: solve it
-            // again on its own with the device-wide GMRES
-            ss_options od = r->opt;
-            od.flags |= SS_FLAG_DEVICE_WIDE;
-            const int gm = (r->method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
-            r->status = solve(r->h, gm, r->tol, od, r->rho.data(), &r->info);
-            r->info.fell_back = 1;
-        } else {
-            r->status = finish(r->h, B.x.get(), r->opt, r->tol, st, r->rho.data(), &r->info, s);
-        }
+        hp.push_back(hs[(size_t)k].get());
+        outs.push_back(r->rho.data());
+        tols.push_back(r->tol);
+    }
+    std::vector<ss_info> infos((size_t)m);
+    std::vector<int> status((size_t)m, SS_OK);
+    const ss_options o = g[0]->opt;
+    ss::solve_batch(hp.data(), m, g[0]->method, tols[0], o, outs.data(), infos.data(), status.data(), tols.data());
+    const std::string &first_err = batch_error();
+    for (int k = 0; k < m; ++k) {
+        Request *r = g[(size_t)k];
+        r->info = infos[(size_t)k];
+        r->status = status[(size_t)k];
+        r->info.status = r->status;
         if (r->status == SS_E_NOT_CONVERGED) r->error = "iteration limit reached before ||L rho|| <= tol";
-        if (r->status == SS_E_BREAKDOWN) r->error = "BiCGSTAB breakdown";
+        else if (r->status == SS_E_BREAKDOWN) r->error = "BiCGSTAB breakdown";
+        else if (r->status != SS_OK) r->error = first_err;
+    }
+    for (auto &h : hs) {
+        FreeScope fs(stream_peek(h.get()));
+        h.reset();
     }
 }
 
-// Scheduler: admission by slots and footprint, then one batched launch per
-// precision over every ready request.
+static bool same_group(const Request *a, const Request *b) {
+    return a->method == b->method && std::memcmp(&a->opt, &b->opt, sizeof(ss_options)) == 0;
+}
+
+// Scheduler: admission by slots and footprint, then the admitted requests
+// in groups of equal method and options.
 static void scheduler_loop(ss_server_s *S) {
     (void)hipSetDevice(S->device);
     set_current_stream(S->solve_stream);
     while (true) {
-        std::vector<Request *> b64, b32;
+        std::vector<Request *> admitted;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv.wait(lk, [&] {
-                if (S->stop) return true;
-                if (!S->ready.empty()) return true;
-                return !S->queued.empty() && S->resident < S->max_slots &&
-                       (S->resident == 0 || S->used + S->queued.front()->footprint <= S->budget);
-            });
+            S->cv.wait(lk, [&] { return S->stop || !S->queued.empty(); });
             if (S->stop) return;
             // admit in arrival order while slots and memory allow (a request
             // larger than the whole budget is admitted alone)
@@ -273,31 +275,33 @@ static void scheduler_loop(ss_server_s *S) {
                 S->queued.pop_front();
                 S->used += r->footprint;
                 S->resident += 1;
-                r->state = Request::SETUP;
-                S->to_setup.push_back(r);
+                r->state = Request::RUNNING;
+                admitted.push_back(r);
             }
-            for (Request *r : S->ready) (r->opt.prec == SS_MIXED ? b32 : b64).push_back(r);
-            S->ready.clear();
-            S->cv.notify_all();
         }
-        for (int pass = 0; pass < 2; ++pass) {
-            std::vector<Request *> &batch = pass ? b32 : b64;
-            if (batch.empty()) continue;
+        std::vector<char> taken(admitted.size(), 0);
+        for (size_t a = 0; a < admitted.size(); ++a) {
+            if (taken[a]) continue;
+            std::vector<Request *> grp;
+            for (size_t b = a; b < admitted.size(); ++b)
+                if (!taken[b] && same_group(admitted[a], admitted[b])) {
+                    taken[b] = 1;
+                    grp.push_back(admitted[b]);
+                }
             try {
-                if (pass) solve_batch<float2>(S, batch);
-                else solve_batch<double2>(S, batch);
+                run_group(S, grp);
             } catch (const Error &e) {
-                for (Request *r : batch) set_error(r, e.code, e.what());
+                for (Request *r : grp) set_error(r, e.code, e.what());
             } catch (const std::exception &e) {
-                for (Request *r : batch) set_error(r, SS_E_HIP, e.what());
+                for (Request *r : grp) set_error(r, SS_E_HIP, e.what());
             }
             std::lock_guard<std::mutex> lk(S->mu);
-            for (Request *r : batch) {
-                release_device(S, r);
+            for (Request *r : grp) {
+                S->used -= r->footprint;
+                S->resident -= 1;
                 r->state = Request::DONE;
             }
             S->done_cv.notify_all();
-            S->cv.notify_all();
         }
     }
 }
@@ -323,8 +327,6 @@ int ss_server_create(size_t hbm_budget_bytes, int32_t max_slots, ss_server *out)
         delete S;
         return SS_E_HIP;
     }
-    const int nworkers = 8;
-    for (int i = 0; i < nworkers; ++i) S->workers.emplace_back(ss::worker_loop, S);
     S->scheduler = std::thread(ss::scheduler_loop, S);
     *out = S;
     return SS_OK;
@@ -335,6 +337,11 @@ int ss_submit(ss_server S, const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_c
     if (!S || !ticket || !H || N < 1 || n_cops < 0 || (n_cops > 0 && !c_ops) || !(tol > 0)) return SS_E_INVALID_ARG;
     if (method != SS_TRACE_BICGSTAB && method != SS_INVPOW_BICGSTAB) return SS_E_INVALID_ARG;
     try {
+        ss_options o;
+        ss_options_default(&o);
+        if (opt) o = *opt;
+        // the server runs the workgroup-resident solver only
+        if (!ss::use_workgroup_n(N * N, method, o) || N > 46340) return SS_E_INVALID_ARG;
         std::unique_ptr<ss::Request> r(new ss::Request());
         r->H = ss::copy_in(H, N, "H");
         for (int k = 0; k < n_cops; ++k) r->C.push_back(ss::copy_in(&c_ops[k], N, "c_ops[k]"));
@@ -401,16 +408,12 @@ void ss_server_destroy(ss_server S) {
         S->stop = true;
         S->cv.notify_all();
     }
-    for (std::thread &t : S->workers) t.join();
     S->scheduler.join();
-    for (auto &kv : S->all) {
-        ss::Request *r = kv.second;
-        if (r->h) ss_liouv_free(r->h);
-        delete r;
-    }
+    for (auto &kv : S->all) delete kv.second;
     for (ss::Request *r : S->queued)
         if (S->all.find(r->ticket) == S->all.end()) delete r;
     if (S->solve_stream) (void)hipStreamDestroy(S->solve_stream);
+    if (S->pinned) (void)hipHostFree(S->pinned);
     delete S;
 }
 

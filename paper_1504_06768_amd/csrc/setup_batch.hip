@@ -494,7 +494,7 @@ struct Carver {
 };
 
 template <typename T>
-void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, hipStream_t s,
+void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o, hipStream_t s,
                     WgBatch<T> &out) {
     out.probs.assign((size_t)count, WgProblem<T>{});
     out.levels.assign((size_t)count, 0);
@@ -626,7 +626,7 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_op
         P.nlev_u = nu[(size_t)k];
         P.maxiter = o.maxiter;
         P.max_outer = o.max_outer > 0 ? o.max_outer : 20;
-        P.tol = tol;
+        P.tol = tols[k];
         P.rtol_in = (o.inner_tol > 0) ? o.inner_tol : (o.prec == SS_MIXED ? 1e-4 : 0.0);
         P.sigma = o.sigma;
         P.w = h->w;
@@ -653,8 +653,9 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_op
         out.levels[(size_t)k] = nl[(size_t)k] + nu[(size_t)k];
     }
 }
-template void wg_setup_batch<float2>(ss_liouv *, int, int, double, const ss_options &, hipStream_t, WgBatch<float2> &);
-template void wg_setup_batch<double2>(ss_liouv *, int, int, double, const ss_options &, hipStream_t,
+template void wg_setup_batch<float2>(ss_liouv *, int, int, const double *, const ss_options &, hipStream_t,
+                                     WgBatch<float2> &);
+template void wg_setup_batch<double2>(ss_liouv *, int, int, const double *, const ss_options &, hipStream_t,
                                       WgBatch<double2> &);
 
 
@@ -771,7 +772,7 @@ __global__ void __launch_bounds__(FIN_BS) k_bt_finish(const FinishJob *jobs) {
     }
 }
 
-void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, double tol,
+void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, const double *tols,
                   const SolveStats *st, double *const *rho_out, ss_info *const *infos, int *status, hipStream_t s) {
     if (count == 0) return;
     StreamScope scope(s);
@@ -826,7 +827,7 @@ void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_op
         const double *v = ho.data() + 8 * (size_t)k;
         const int64_t bw = (int64_t)v[4] + (int64_t)v[5] + 1;
         const int64_t pf = (int64_t)v[6] + (int64_t)v[7];
-        status[k] = fill_info(hs[k], o, tol, st[k], sqrt(v[2]), v[3], mk(v[0], v[1]), bw, pf, infos[k],
+        status[k] = fill_info(hs[k], o, tols[k], st[k], sqrt(v[2]), v[3], mk(v[0], v[1]), bw, pf, infos[k],
                               stream_peek(hs[k]));
     }
 }

@@ -25,7 +25,8 @@ void permute_batch(ss_liouv *hs, int count, bool ilu0, hipStream_t s, std::vecto
 // Workgroup-resident problems of many prepared handles (factors and their
 // diagonal positions in place): level analysis of both factor sides, level
 // schedules, packed factors, start vectors and scratch -- what make_wg
-// builds for one handle -- in one arena for the whole batch.  probs[k] and
+// builds for one handle -- in one arena for the whole batch; tols[k] is the
+// tolerance of hs[k].  probs[k] and
 // levels[k] (nlev_l + nlev_u) belong to hs[k]; the arena must outlive the
 // solve.
 template <typename T>
@@ -35,13 +36,13 @@ struct WgBatch {
     std::vector<int> levels;
 };
 template <typename T>
-void wg_setup_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, hipStream_t s,
+void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o, hipStream_t s,
                     WgBatch<T> &out);
 
 // finish() for many systems in one launch (one block each): xs[k] is the
 // permuted fp64 solution of hs[k], rho_out[k] (host, device or null) and
 // infos[k] (or null) receive its results, status[k] its outcome.
-void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, double tol,
+void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, const double *tols,
                   const SolveStats *st, double *const *rho_out, ss_info *const *infos, int *status, hipStream_t s);
 
 // out[k] = *src[k] (device result records), one host wait.

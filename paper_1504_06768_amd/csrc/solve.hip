@@ -275,12 +275,14 @@ const std::string &batch_error() { return tl_batch_error; }
 // Largest system solved by the workgroup-resident kernel unless forced.
 constexpr int WG_AUTO_MAX_N = 4096;
 
-bool use_workgroup(ss_liouv h, int method, const ss_options &o) {
+bool use_workgroup_n(int64_t n, int method, const ss_options &o) {
     if (is_gmres(method)) return false;
     if (o.flags & (SS_FLAG_DEVICE_WIDE | SS_FLAG_MATRIX_FREE)) return false;
     if (o.flags & SS_FLAG_WORKGROUP) return true;
-    return h->n <= WG_AUTO_MAX_N;
+    return n <= WG_AUTO_MAX_N;
 }
+
+bool use_workgroup(ss_liouv h, int method, const ss_options &o) { return use_workgroup_n(h->n, method, o); }
 
 // Start vector and right-hand side in the permuted order: trace row
 // b = w e_rt, x = 0; inverse power x = vec(I / d).
@@ -656,8 +658,8 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
 // SS_FLAG_NO_FALLBACK).  Each system's arithmetic stays in its own
 // workgroup, so its result is the same as in a batch of one.
 template <typename T>
-static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
-                     ss_info *infos, int *status) {
+static int run_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o,
+                     double **rho_out, ss_info *infos, int *status) {
     const int nthreads = std::max(1, std::min(count, setup_threads()));
     std::vector<std::string> err((size_t)count);
     std::vector<int> code((size_t)count, SS_OK);
@@ -852,8 +854,10 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
                 ok.push_back(hs[i]);
                 idx.push_back(i);
             }
+        std::vector<double> tl;
+        for (int i : idx) tl.push_back(tols[i]);
         try {
-            wg_setup_batch<T>(ok.data(), (int)ok.size(), method, tol, o, s0, wb);
+            wg_setup_batch<T>(ok.data(), (int)ok.size(), method, tl.data(), o, s0, wb);
         } catch (const Error &e) {
             for (int i : idx) {
                 code[(size_t)i] = e.code;
@@ -911,6 +915,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
     std::vector<double *> fout;
     std::vector<ss_info *> finfo;
     std::vector<int> fidx;
+    std::vector<double> ftol;
     for (size_t k = 0; k < solved.size(); ++k) {
         const int i = solved[k];
         const WgResult &hr = hres[k];
@@ -933,11 +938,12 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         fout.push_back(rho_out ? rho_out[i] : nullptr);
         finfo.push_back(infos ? infos + i : nullptr);
         fidx.push_back(i);
+        ftol.push_back(tols[i]);
     }
     {
         std::vector<int> fstat(fh.size(), SS_OK);
         try {
-            finish_batch(fh.data(), (int)fh.size(), fx.data(), o, tol, fst.data(), fout.data(), finfo.data(),
+            finish_batch(fh.data(), (int)fh.size(), fx.data(), o, ftol.data(), fst.data(), fout.data(), finfo.data(),
                          fstat.data(), s0);
         } catch (const Error &e) {
             for (size_t k = 0; k < fh.size(); ++k) {
@@ -956,7 +962,7 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
         ss_options od = o;
         od.flags |= SS_FLAG_DEVICE_WIDE;
         const int gm = (method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
-        code[(size_t)i] = solve(h, gm, tol, od, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr);
+        code[(size_t)i] = solve(h, gm, tols[i], od, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr);
         if (infos) infos[i].fell_back = 1;
     });
     mark("finish (+ fallbacks)");
@@ -973,14 +979,19 @@ static int run_batch(ss_liouv *hs, int count, int method, double tol, const ss_o
 }
 
 int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
-                ss_info *infos, int *status) {
-    SS_REQUIRE(tol > 0 && std::isfinite(tol), SS_E_INVALID_ARG, "tol must be positive");
+                ss_info *infos, int *status, const double *tols) {
+    SS_REQUIRE(tols || (tol > 0 && std::isfinite(tol)), SS_E_INVALID_ARG, "tol must be positive");
     SS_REQUIRE(method == SS_TRACE_BICGSTAB || method == SS_INVPOW_BICGSTAB, SS_E_INVALID_ARG,
                "batched solves use BiCGSTAB (the workgroup-resident solver)");
     SS_REQUIRE(!(o.flags & SS_FLAG_MATRIX_FREE), SS_E_INVALID_ARG,
                "SS_FLAG_MATRIX_FREE implies the device-wide path; batched solves run the workgroup-resident solver");
-    if (o.prec == SS_MIXED) return run_batch<float2>(hs, count, method, tol, o, rho_out, infos, status);
-    return run_batch<double2>(hs, count, method, tol, o, rho_out, infos, status);
+    std::vector<double> uniform;
+    if (!tols) {
+        uniform.assign((size_t)std::max(count, 0), tol);
+        tols = uniform.data();
+    }
+    if (o.prec == SS_MIXED) return run_batch<float2>(hs, count, method, tols, o, rho_out, infos, status);
+    return run_batch<double2>(hs, count, method, tols, o, rho_out, infos, status);
 }
 
 // SS_AUTO: RCM bandwidths of L~ and of L - sigma I decide the driver.
