@@ -625,6 +625,8 @@ static void assemble_chunk(int k0, int k1, const ss_csr_z *H, const ss_csr_z *co
     k_asm_rows<true><<<(unsigned)rnb, 256, 0, s>>>(d_rj.get(), d_rpre.get(), m);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s));
+    FreeScope fs(s);  // the staged copies of H: one release event for all
+    Hs.clear();
 }
 
 void assemble_batch(int count, const ss_csr_z *H, const ss_csr_z *const *c_ops, const int *n_cops,

@@ -175,6 +175,83 @@ void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hip
     SS_HIP(hipStreamSynchronize(s));  // the job array is released on return
 }
 
+// Many systems at once with their level schedules (the level sets of the
+// strict lower part: row i depends exactly on the rows k < i it holds).  One
+// workgroup per system walks the levels with a barrier in between; inside a
+// level, groups of ILU_LG lanes take one row each.  No row waits for
+// another, so the factor is read with plain loads.  Each row takes the steps
+// of ilu0_row in the same order with the same arithmetic, so the factors are
+// the same.
+constexpr int ILU_LG = 8;
+constexpr int ILU_LVL_BS = 1024;
+
+__global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs, double detect, double boost) {
+    const Ilu0Job &J = jobs[blockIdx.x];
+    const int g = threadIdx.x / ILU_LG, lane = threadIdx.x % ILU_LG;
+    constexpr int NG = ILU_LVL_BS / ILU_LG;
+    for (int lv = 0; lv < J.nlev; ++lv) {
+        const int s0 = J.lptr[lv], s1 = J.lptr[lv + 1];
+        for (int sl = s0 + g; sl < s1; sl += NG) {
+            const int row = J.lslot[sl].x;
+            const int rs = J.rowptr[row], re = J.rowptr[row + 1], dg = J.diag[row];
+            double rn = 0.0;
+            for (int e = rs + lane; e < re; e += ILU_LG) {
+                const double2 v = J.a[e];
+                J.w[e] = v;
+                rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
+            }
+            for (int off = ILU_LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, ILU_LG));
+            for (int ek = rs; ek < dg; ++ek) {
+                const int k = J.col[ek];
+                const int dk = J.diag[k];
+                const int ke = J.rowptr[k + 1];
+                const double2 ukk = J.out[dk];
+                const int owner = (ek - rs) % ILU_LG;
+                double2 l = mk(0.0, 0.0);
+                if (lane == owner) {
+                    l = cdiv(J.w[ek], ukk);
+                    J.w[ek] = l;
+                }
+                l.x = __shfl(l.x, owner, ILU_LG);
+                l.y = __shfl(l.y, owner, ILU_LG);
+                for (int e = rs + lane; e < re; e += ILU_LG) {
+                    if (e <= ek) continue;
+                    const int j = J.col[e];
+                    int lo = dk + 1, hi = ke - 1, f = -1;
+                    while (lo <= hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const int c = J.col[mid];
+                        if (c == j) { f = mid; break; }
+                        if (c < j) lo = mid + 1; else hi = mid - 1;
+                    }
+                    if (f >= 0) J.w[e] = csub(J.w[e], cmul(l, J.out[f]));
+                }
+            }
+            if (lane == (dg - rs) % ILU_LG) {
+                const double2 p = J.w[dg];
+                const double mag = sqrt(p.x * p.x + p.y * p.y);
+                const double bound = detect * rn;
+                if (!(mag >= bound)) {
+                    const double b = (rn > 0.0) ? boost * rn : 1.0;
+                    J.w[dg] = (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0);
+                    atomicAdd(J.nguard, 1);
+                }
+            }
+            for (int e = rs + lane; e < re; e += ILU_LG) J.out[e] = J.w[e];
+        }
+        __syncthreads();
+    }
+}
+
+void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s) {
+    if (count <= 0) return;
+    StreamScope scope(s);
+    DevBuf<Ilu0Job> dj((size_t)count);
+    h2d(dj.get(), jobs, (size_t)count, s);
+    k_ilu0_levels<<<count, ILU_LVL_BS, 0, s>>>(dj.get(), detect, boost);
+    SS_HIP(hipGetLastError());
+}
+
 IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double detect, double boost, CsrBuf<double2> &LU,
                       hipStream_t s) {
     const int n = A.n, nnz = A.nnz;

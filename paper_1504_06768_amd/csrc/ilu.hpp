@@ -25,6 +25,10 @@ struct Ilu0Job {
     double2 *w, *out;
     unsigned *status;
     int *nguard;
+    // level schedule of the strict lower part (ilu0_levels_batch only)
+    int nlev;
+    const int *lptr;
+    const int4 *lslot;
 };
 struct Ilu0Batch {
     DevBuf<double2> work;
@@ -33,6 +37,9 @@ struct Ilu0Batch {
     IluResult result(hipStream_t s);
 };
 void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s);
+// The same factorisation level by level (jobs carry their lower-part level
+// schedules; no dependency waits); the factor values need no sentinel.
+void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s);
 
 // Dual-threshold ILUT (drop_tol relative to ||row||_inf, at most
 // ceil(fill * nnz(row)) entries kept in each of L and U per row).

@@ -493,14 +493,12 @@ struct Carver {
     }
 };
 
-template <typename T>
-void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o, hipStream_t s,
-                    WgBatch<T> &out) {
-    out.probs.assign((size_t)count, WgProblem<T>{});
-    out.levels.assign((size_t)count, 0);
+void levels_setup_batch(ss_liouv *hs, int count, hipStream_t s, LevelBatch &out) {
+    out = LevelBatch();
+    out.hs.assign(hs, hs + count);
     if (count == 0) return;
     StreamScope scope(s);
-    const bool trace = (method == SS_TRACE_BICGSTAB || method == SS_TRACE_GMRES);
+    for (int k = 0; k < count; ++k) out.pos[hs[k]] = k;
     // level analysis of both sides of every factor: levels at -1, one launch per side
     std::vector<size_t> loff((size_t)count + 1, 0);
     for (int k = 0; k < count; ++k) loff[(size_t)k + 1] = loff[(size_t)k] + 2 * (size_t)std::max(hs[k]->n, 1);
@@ -526,29 +524,86 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
     levels_batch<true>(ju.data(), count, s);
     std::vector<unsigned> hm((size_t)4 * count);
     d2h(hm.data(), meta.get(), hm.size(), s);
-    std::vector<int> nl((size_t)count), nu((size_t)count);
+    out.nl.resize((size_t)count);
+    out.nu.resize((size_t)count);
     for (int k = 0; k < count; ++k) {
         SS_REQUIRE(!(hm[4 * (size_t)k] & STATUS_SPIN_TIMEOUT) && !(hm[4 * (size_t)k + 2] & STATUS_SPIN_TIMEOUT),
                    SS_E_TIMEOUT, "level analysis: dependency wait timed out");
-        nl[(size_t)k] = hs[k]->n ? (int)hm[4 * (size_t)k + 1] + 1 : 0;
-        nu[(size_t)k] = hs[k]->n ? (int)hm[4 * (size_t)k + 3] + 1 : 0;
+        out.nl[(size_t)k] = hs[k]->n ? (int)hm[4 * (size_t)k + 1] + 1 : 0;
+        out.nu[(size_t)k] = hs[k]->n ? (int)hm[4 * (size_t)k + 3] + 1 : 0;
     }
-    // one arena for every system's schedules, packed factors and vectors
-    constexpr int K = WgK<T>::value;
+    // schedules of both sides in one arena: counts, scan, scatter
     struct Lay {
-        size_t lptr, uptr, lcnt, ucnt, lslot, uslot, pls, pus, plc, puc, plv, puv, pla, pua, work, ysc, x, r, b, res;
+        size_t lptr, uptr, lcnt, ucnt, lslot, uslot;
     };
     std::vector<Lay> lay((size_t)count);
     Carver cv;
     for (int k = 0; k < count; ++k) {
         const size_t n = (size_t)std::max(hs[k]->n, 1);
         Lay &L = lay[(size_t)k];
-        L.lptr = cv.take<int>((size_t)nl[(size_t)k] + 1);
-        L.uptr = cv.take<int>((size_t)nu[(size_t)k] + 1);
-        L.lcnt = cv.take<int>((size_t)nl[(size_t)k] + 1);
-        L.ucnt = cv.take<int>((size_t)nu[(size_t)k] + 1);
+        L.lptr = cv.take<int>((size_t)out.nl[(size_t)k] + 1);
+        L.uptr = cv.take<int>((size_t)out.nu[(size_t)k] + 1);
+        L.lcnt = cv.take<int>((size_t)out.nl[(size_t)k] + 1);
+        L.ucnt = cv.take<int>((size_t)out.nu[(size_t)k] + 1);
         L.lslot = cv.take<int4>(n);
         L.uslot = cv.take<int4>(n);
+    }
+    out.arena.resize(cv.off);
+    SS_HIP(hipMemsetAsync(out.arena.get(), 0, out.arena.bytes(), s));
+    unsigned char *base = out.arena.get();
+    std::vector<SideJob> sj;
+    std::vector<ScanJob> sc;
+    std::vector<int> sblocks;
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        const Lay &L = lay[(size_t)k];
+        for (int side = 0; side < 2; ++side) {
+            SideJob j;
+            j.n = h->n;
+            j.upper = side;
+            j.lvl = (side ? ju : jl)[(size_t)k].lvl;
+            j.cnt = (int *)(base + (side ? L.ucnt : L.lcnt));
+            j.ptr = (int *)(base + (side ? L.uptr : L.lptr));
+            j.slot = (int4 *)(base + (side ? L.uslot : L.lslot));
+            j.rowptr = h->LU.rowptr.get();
+            j.diag = h->lu_diag.get();
+            sj.push_back(j);
+            sblocks.push_back(div_up(h->n, 256));
+            sc.push_back(ScanJob{j.cnt, side ? out.nu[(size_t)k] : out.nl[(size_t)k], nullptr, j.ptr});
+        }
+        out.lptr.push_back((const int *)(base + L.lptr));
+        out.uptr.push_back((const int *)(base + L.uptr));
+        out.lslot.push_back((const int4 *)(base + L.lslot));
+        out.uslot.push_back((const int4 *)(base + L.uslot));
+    }
+    launch_rows(k_bt_levels<0>, sj, sblocks, s);
+    seg_scan(sc, s);
+    launch_rows(k_bt_levels<1>, sj, sblocks, s);
+    SS_HIP(hipStreamSynchronize(s));  // lvl is released on return
+}
+
+template <typename T>
+void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o,
+                    const LevelBatch &lb, hipStream_t s, WgBatch<T> &out) {
+    out.probs.assign((size_t)count, WgProblem<T>{});
+    out.levels.assign((size_t)count, 0);
+    if (count == 0) return;
+    StreamScope scope(s);
+    const bool trace = (method == SS_TRACE_BICGSTAB || method == SS_TRACE_GMRES);
+    // one arena for every system's packed factors, vectors and scratch
+    constexpr int K = WgK<T>::value;
+    struct Lay {
+        size_t pls, pus, plc, puc, plv, puv, pla, pua, work, ysc, x, r, b, res;
+    };
+    std::vector<Lay> lay((size_t)count);
+    std::vector<int> li((size_t)count);
+    Carver cv;
+    for (int k = 0; k < count; ++k) {
+        auto it = lb.pos.find(hs[k]);
+        SS_REQUIRE(it != lb.pos.end(), SS_E_STATE, "no level schedule for a system of the batch");
+        li[(size_t)k] = it->second;
+        const size_t n = (size_t)std::max(hs[k]->n, 1);
+        Lay &L = lay[(size_t)k];
         L.pls = cv.take<int4>(n);
         L.pus = cv.take<int4>(n);
         L.plc = cv.take<int>(n * K);
@@ -569,32 +624,19 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
     unsigned char *base = out.arena.get();
     auto at = [&](size_t off) { return base + off; };
 
-    std::vector<SideJob> sj;
-    std::vector<ScanJob> sc;
     std::vector<PackJob<T>> pj;
     std::vector<StartJob> st;
-    std::vector<int> sblocks, stblocks;
+    std::vector<int> pblocks, stblocks;
     for (int k = 0; k < count; ++k) {
         ss_liouv h = hs[k];
         const Lay &L = lay[(size_t)k];
+        const int q = li[(size_t)k];
         const CsrBuf<T> &LUin = lu_of<T>(h);
         for (int side = 0; side < 2; ++side) {
-            SideJob j;
-            j.n = h->n;
-            j.upper = side;
-            j.lvl = (side ? ju : jl)[(size_t)k].lvl;
-            j.cnt = (int *)at(side ? L.ucnt : L.lcnt);
-            j.ptr = (int *)at(side ? L.uptr : L.lptr);
-            j.slot = (int4 *)at(side ? L.uslot : L.lslot);
-            j.rowptr = h->LU.rowptr.get();
-            j.diag = h->lu_diag.get();
-            sj.push_back(j);
-            sblocks.push_back(div_up(h->n, 256));
-            sc.push_back(ScanJob{j.cnt, side ? nu[(size_t)k] : nl[(size_t)k], nullptr, j.ptr});
             PackJob<T> p;
             p.n = h->n;
             p.upper = side;
-            p.in = j.slot;
+            p.in = side ? lb.uslot[(size_t)q] : lb.lslot[(size_t)q];
             p.col = LUin.col.get();
             p.val = LUin.val.get();
             p.slot = (int4 *)at(side ? L.pus : L.pls);
@@ -602,28 +644,27 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
             p.pval = (T *)at(side ? L.puv : L.plv);
             p.aux = (T *)at(side ? L.pua : L.pla);
             pj.push_back(p);
+            pblocks.push_back(div_up(h->n, 256));
         }
         st.push_back(StartJob{h->n, h->d, trace ? 1 : 0, h->trow, h->w, h->perm.get(), (double2 *)at(L.x),
                               (double2 *)at(L.b)});
         stblocks.push_back(div_up(h->n, 256));
     }
-    launch_rows(k_bt_levels<0>, sj, sblocks, s);
-    seg_scan(sc, s);
-    launch_rows(k_bt_levels<1>, sj, sblocks, s);
-    launch_rows(k_bt_pack<T>, pj, sblocks, s);
+    launch_rows(k_bt_pack<T>, pj, pblocks, s);
     launch_rows(k_bt_start, st, stblocks, s);
 
     for (int k = 0; k < count; ++k) {
         ss_liouv h = hs[k];
         const Lay &L = lay[(size_t)k];
+        const int q = li[(size_t)k];
         WgProblem<T> &P = out.probs[(size_t)k];
         std::memset(&P, 0, sizeof(P));
         P.n = h->n;
         P.d = h->d;
         P.q0 = h->q0;
         P.trace = trace ? 1 : 0;
-        P.nlev_l = nl[(size_t)k];
-        P.nlev_u = nu[(size_t)k];
+        P.nlev_l = lb.nl[(size_t)q];
+        P.nlev_u = lb.nu[(size_t)q];
         P.maxiter = o.maxiter;
         P.max_outer = o.max_outer > 0 ? o.max_outer : 20;
         P.tol = tols[k];
@@ -634,11 +675,11 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
         P.A64 = h->Ap.view();
         P.LU = lu_of<T>(h).view();
         P.diag = h->lu_diag.get();
-        P.lptr = (const int *)at(L.lptr);
+        P.lptr = lb.lptr[(size_t)q];
         P.lslot = (const int4 *)at(L.pls);
         P.lcol = (const int *)at(L.plc);
         P.lval = (const T *)at(L.plv);
-        P.uptr = (const int *)at(L.uptr);
+        P.uptr = lb.uptr[(size_t)q];
         P.uslot = (const int4 *)at(L.pus);
         P.ucol = (const int *)at(L.puc);
         P.uval = (const T *)at(L.puv);
@@ -650,13 +691,13 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
         P.work = (T *)at(L.work);
         P.ysc = (T *)at(L.ysc);
         P.res = (WgResult *)at(L.res);
-        out.levels[(size_t)k] = nl[(size_t)k] + nu[(size_t)k];
+        out.levels[(size_t)k] = P.nlev_l + P.nlev_u;
     }
 }
-template void wg_setup_batch<float2>(ss_liouv *, int, int, const double *, const ss_options &, hipStream_t,
-                                     WgBatch<float2> &);
-template void wg_setup_batch<double2>(ss_liouv *, int, int, const double *, const ss_options &, hipStream_t,
-                                      WgBatch<double2> &);
+template void wg_setup_batch<float2>(ss_liouv *, int, int, const double *, const ss_options &, const LevelBatch &,
+                                     hipStream_t, WgBatch<float2> &);
+template void wg_setup_batch<double2>(ss_liouv *, int, int, const double *, const ss_options &, const LevelBatch &,
+                                      hipStream_t, WgBatch<double2> &);
 
 
 // --------------------------------------------------------------- finish
@@ -847,6 +888,51 @@ void read_results(const std::vector<const WgResult *> &src, std::vector<WgResult
     k_bt_results<<<div_up((int64_t)src.size(), 256), 256, 0, s>>>(dsrc.get(), (int)src.size(), dst.get());
     SS_HIP(hipGetLastError());
     d2h(out.data(), dst.get(), out.size(), s);
+}
+
+
+// ------------------------------------------------------ complex64 copies
+struct C64Job {
+    int n, nnz;
+    const int *rowptr, *col;
+    const double2 *val;
+    int *rowptr32, *col32;
+    float2 *val32;
+};
+
+// One job per matrix: pattern copied, values rounded to complex64 (as
+// copy_pattern_c64 does for one matrix).
+__global__ void __launch_bounds__(256) k_bt_c64(const C64Job *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const C64Job &J = jobs[jb];
+    const int i = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (i <= J.n) J.rowptr32[i] = J.rowptr[i];
+    if (i < J.nnz) {
+        J.col32[i] = J.col[i];
+        J.val32[i] = from_c128<float2>(J.val[i]);
+    }
+}
+
+void c64_copies_batch(ss_liouv *hs, int count, hipStream_t s) {
+    if (count == 0) return;
+    StreamScope scope(s);
+    std::vector<C64Job> jobs;
+    std::vector<int> blocks;
+    for (int k = 0; k < count; ++k) {
+        ss_liouv h = hs[k];
+        StreamScope own(stream_peek(h));
+        h->Ap32.alloc(h->Ap.n, h->Ap.nnz);
+        h->LU32.alloc(h->LU.n, h->LU.nnz);
+        for (int m = 0; m < 2; ++m) {
+            const CsrBuf<double2> &a = m ? h->LU : h->Ap;
+            CsrBuf<float2> &b = m ? h->LU32 : h->Ap32;
+            jobs.push_back(C64Job{a.n, a.nnz, a.rowptr.get(), a.col.get(), a.val.get(), b.rowptr.get(), b.col.get(),
+                                  b.val.get()});
+            blocks.push_back(div_up((int64_t)std::max(a.n + 1, a.nnz), 256));
+        }
+    }
+    launch_rows(k_bt_c64, jobs, blocks, s);
+    SS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace ss

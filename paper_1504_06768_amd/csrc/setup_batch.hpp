@@ -1,5 +1,7 @@
 // Batched set-up stages (setup_batch.hip).
 #pragma once
+#include <unordered_map>
+
 #include "handle.hpp"
 
 namespace ss {
@@ -22,13 +24,25 @@ struct PermResult {
 };
 void permute_batch(ss_liouv *hs, int count, bool ilu0, hipStream_t s, std::vector<PermResult> &res);
 
-// Workgroup-resident problems of many prepared handles (factors and their
-// diagonal positions in place): level analysis of both factor sides, level
-// schedules, packed factors, start vectors and scratch -- what make_wg
+// Level analysis of both factor sides of many handles (their LU pattern
+// and diagonal positions in place -- for ILU(0) the pattern of P A P^T, so
+// the lower side also schedules the factorisation itself) and the level
+// schedules: ptr (nlev + 1) and slots {row, first, end, 0} in level order.
+struct LevelBatch {
+    DevBuf<unsigned char> arena;
+    std::vector<ss_liouv> hs;
+    std::unordered_map<ss_liouv, int> pos;
+    std::vector<int> nl, nu;
+    std::vector<const int *> lptr, uptr;
+    std::vector<const int4 *> lslot, uslot;
+};
+void levels_setup_batch(ss_liouv *hs, int count, hipStream_t s, LevelBatch &out);
+
+// Workgroup-resident problems of many prepared handles with their level
+// schedules (lb): packed factors, start vectors and scratch -- what make_wg
 // builds for one handle -- in one arena for the whole batch; tols[k] is the
-// tolerance of hs[k].  probs[k] and
-// levels[k] (nlev_l + nlev_u) belong to hs[k]; the arena must outlive the
-// solve.
+// tolerance of hs[k].  probs[k] and levels[k] (nlev_l + nlev_u) belong to
+// hs[k]; the arenas must outlive the solve.
 template <typename T>
 struct WgBatch {
     DevBuf<unsigned char> arena;
@@ -36,14 +50,18 @@ struct WgBatch {
     std::vector<int> levels;
 };
 template <typename T>
-void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o, hipStream_t s,
-                    WgBatch<T> &out);
+void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, const ss_options &o,
+                    const LevelBatch &lb, hipStream_t s, WgBatch<T> &out);
 
 // finish() for many systems in one launch (one block each): xs[k] is the
 // permuted fp64 solution of hs[k], rho_out[k] (host, device or null) and
 // infos[k] (or null) receive its results, status[k] its outcome.
 void finish_batch(ss_liouv *hs, int count, const double2 *const *xs, const ss_options &o, const double *tols,
                   const SolveStats *st, double *const *rho_out, ss_info *const *infos, int *status, hipStream_t s);
+
+// The complex64 copies of P A P^T and of the ILU factor of every handle
+// (mixed precision), one launch.
+void c64_copies_batch(ss_liouv *hs, int count, hipStream_t s);
 
 // out[k] = *src[k] (device result records), one host wait.
 void read_results(const std::vector<const WgResult *> &src, std::vector<WgResult> &out, hipStream_t s);

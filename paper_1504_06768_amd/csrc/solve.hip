@@ -139,20 +139,22 @@ static void prepare_permute(ss_liouv h, hipStream_t s) {
 }
 
 static void prepare_finish(ss_liouv h, int method, const ss_options &o, hipStream_t s, double t0,
-                           bool positions_done = false) {
+                           bool batched = false) {
     const int n = h->n, d = h->d;
-    if (o.ilu == SS_ILU0 && !positions_done) {
+    if (o.ilu == SS_ILU0 && !batched) {
         h->lu_diag.resize((size_t)n);
         if (n) SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
     }
     if (o.prec == SS_MIXED) {
-        copy_pattern_c64(h->Ap, h->Ap32, s);
-        copy_pattern_c64(h->LU, h->LU32, s);
+        if (!batched) {  // (a batch makes these copies together)
+            copy_pattern_c64(h->Ap, h->Ap32, s);
+            copy_pattern_c64(h->LU, h->LU32, s);
+        }
     } else {
         h->Ap32 = CsrBuf<float2>();
         h->LU32 = CsrBuf<float2>();
     }
-    if (!positions_done) {
+    if (!batched) {
         h->tpos.resize((size_t)d);
         k_trace_positions<<<div_up(d, 256), 256, 0, s>>>(d, h->iperm.get(), h->tpos.get());
         SS_HIP(hipGetLastError());
@@ -739,7 +741,10 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         else rcm_order(h->S, h->perm, h->iperm, s);
         SS_HIP(hipStreamSynchronize(s));
     });
-    rs.clear();
+    {
+        FreeScope fs(s0);  // the batched RCM is complete: one event for all its scratch
+        rs.clear();
+    }
     // P A P^T, diagonal and trace positions and the ILU(0) pattern of every
     // system together; rows without a diagonal entry (rare) are fixed per system
     const bool ilu0 = (o.ilu == SS_ILU0);
@@ -808,17 +813,45 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         }
     }
     mark("permute+ilu prep");
-    // stage 4: ILU(0) of every system in one launch
-    std::vector<unsigned> hflags;
-    {
-        std::vector<Ilu0Job> jobs;
+    // level schedules of both factor sides; with ILU(0) the factor has the
+    // pattern of P A P^T, so they exist before the factorisation and its lower
+    // side schedules the factorisation itself
+    LevelBatch lb;
+    auto schedule = [&]() {
+        std::vector<ss_liouv> ok;
+        std::vector<int> idx;
         for (int i = 0; i < count; ++i)
-            if (code[(size_t)i] == SS_OK && ilu0) jobs.push_back(ijobs[(size_t)i]);
-        ilu0_batch(jobs.data(), (int)jobs.size(), PIVOT_DETECT, PIVOT_BOOST, s0);
-        if (ilu0) {
-            hflags.resize(2 * (size_t)count);
-            d2h(hflags.data(), ilu_flags.get(), hflags.size(), s0);
+            if (code[(size_t)i] == SS_OK) {
+                ok.push_back(hs[i]);
+                idx.push_back(i);
+            }
+        try {
+            levels_setup_batch(ok.data(), (int)ok.size(), s0, lb);
+        } catch (const Error &e) {
+            for (int i : idx) {
+                code[(size_t)i] = e.code;
+                err[(size_t)i] = e.what();
+            }
         }
+    };
+    if (ilu0) schedule();
+    mark("levels (batched)");
+    // stage 4: ILU(0) of every system in one launch, level by level
+    std::vector<unsigned> hflags;
+    if (ilu0) {
+        std::vector<Ilu0Job> jobs;
+        for (int i = 0; i < count; ++i) {
+            if (code[(size_t)i] != SS_OK) continue;
+            Ilu0Job j = ijobs[(size_t)i];
+            const int q = lb.pos.at(hs[i]);
+            j.nlev = lb.nl[(size_t)q];
+            j.lptr = lb.lptr[(size_t)q];
+            j.lslot = lb.lslot[(size_t)q];
+            jobs.push_back(j);
+        }
+        ilu0_levels_batch(jobs.data(), (int)jobs.size(), PIVOT_DETECT, PIVOT_BOOST, s0);
+        hflags.resize(2 * (size_t)count);
+        d2h(hflags.data(), ilu_flags.get(), hflags.size(), s0);
     }
     mark("ilu0 (batched)");
     // stage 5: ILUT or the outcome of the ILU(0), the rest of the set-up, per system
@@ -840,9 +873,27 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         SS_HIP(hipStreamSynchronize(s));
     });
     ib.clear();
+    if (o.prec == SS_MIXED) {
+        std::vector<ss_liouv> ok;
+        std::vector<int> idx;
+        for (int i = 0; i < count; ++i)
+            if (code[(size_t)i] == SS_OK) {
+                ok.push_back(hs[i]);
+                idx.push_back(i);
+            }
+        try {
+            c64_copies_batch(ok.data(), (int)ok.size(), s0);
+        } catch (const Error &e) {
+            for (int i : idx) {
+                code[(size_t)i] = e.code;
+                err[(size_t)i] = e.what();
+            }
+        }
+    }
     mark("ilu result+finish prep");
-    // stage 6: level analysis, schedules, packed factors and the workgroup
-    // problems of every system together
+    // stage 6: (ILUT: level schedules now) packed factors and the
+    // workgroup problems of every system together
+    if (!ilu0) schedule();
     WgBatch<T> wb;
     std::vector<int> slot((size_t)count, -1);
     {
@@ -857,7 +908,7 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         std::vector<double> tl;
         for (int i : idx) tl.push_back(tols[i]);
         try {
-            wg_setup_batch<T>(ok.data(), (int)ok.size(), method, tl.data(), o, s0, wb);
+            wg_setup_batch<T>(ok.data(), (int)ok.size(), method, tl.data(), o, lb, s0, wb);
         } catch (const Error &e) {
             for (int i : idx) {
                 code[(size_t)i] = e.code;

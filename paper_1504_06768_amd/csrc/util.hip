@@ -1,5 +1,6 @@
 // Device memory, pointer classification and the integer exclusive scan used
 // to turn per-row counts into CSR row pointers.
+#include <deque>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -48,7 +49,7 @@ struct EvState {
 struct Cache {
     std::mutex mu;
     std::unordered_map<void *, Live> live;
-    std::map<size_t, std::vector<Cached>> free_by_cls;
+    std::map<size_t, std::deque<Cached>> free_by_cls;
     std::vector<hipEvent_t> events;
     std::unordered_map<hipEvent_t, EvState> evs;
     size_t cached = 0;
@@ -204,7 +205,7 @@ void *dev_alloc(size_t bytes) {
         std::lock_guard<std::mutex> lk(c.mu);
         auto it = c.free_by_cls.find(cls);
         if (it != c.free_by_cls.end()) {
-            std::vector<Cached> &v = it->second;
+            std::deque<Cached> &v = it->second;
             const bool user = g_user_alloc != nullptr;
             // oldest first: those are the blocks whose last use has most
             // likely completed, so the first query usually succeeds
