@@ -957,6 +957,19 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         }
     std::vector<WgResult> hres;
     read_results(rptr, hres, s0);
+    if (dbg && !hres.empty()) {
+        // device wall-clock ticks (100 MHz) inside the solver, mean over the batch
+        double tp = 0, ts = 0, tt = 0, its = 0;
+        for (const WgResult &r : hres) {
+            tp += (double)r.ticks_precond;
+            ts += (double)r.ticks_spmv;
+            tt += (double)r.ticks_total;
+            its += r.inner;
+        }
+        const double m = (double)hres.size() * 100.0;  // ticks -> us
+        std::fprintf(stderr, "[ss] batch of %d: solver per system: %.0f us total, %.0f us preconditioner, %.0f us SpMV, "
+                     "%.1f inner iterations\n", count, tt / m, tp / m, ts / m, its / (double)hres.size());
+    }
     // systems whose BiCGSTAB broke down: again on their own with the
     // device-wide GMRES; the others finish together
     std::vector<char> again((size_t)count, 0);

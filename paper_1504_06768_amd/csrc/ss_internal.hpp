@@ -135,6 +135,28 @@ template <typename T> __host__ __device__ inline T cdiv(T a, T b) {
 }
 template <typename T> __host__ __device__ inline typename RealOf<T>::type cabs2(T a) { return a.x * a.x + a.y * a.y; }
 template <typename T> __host__ __device__ inline typename RealOf<T>::type cabs1(T a) { return fabs(a.x) + fabs(a.y); }
+// Loads and stores through address-space-1 (global) pointers.  A pointer
+// read from memory is generic to the compiler, and a plain access through it
+// becomes a flat instruction, which also counts against the LDS wait counter:
+// every wait for an LDS access would then wait for every global load in
+// flight.  Vector types go through clang vector types so that the copy does
+// not fall back to a generic reference.
+template <typename U> struct GlobalRaw { using type = U; };
+template <> struct GlobalRaw<float2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct GlobalRaw<double2> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct GlobalRaw<int4> { typedef int __attribute__((ext_vector_type(4))) type; };
+template <typename U>
+__device__ __forceinline__ U gld(const U *p) {
+    using R = typename GlobalRaw<U>::type;
+    const R r = *(const __attribute__((address_space(1))) R *)p;
+    return __builtin_bit_cast(U, r);
+}
+template <typename U>
+__device__ __forceinline__ void gst(U *p, const U &v) {
+    using R = typename GlobalRaw<U>::type;
+    *(__attribute__((address_space(1))) R *)p = __builtin_bit_cast(R, v);
+}
+
 template <typename T> __host__ __device__ inline T czero() { T r; r.x = 0; r.y = 0; return r; }
 
 __host__ __device__ inline float2 to_c64(double2 a) { return make_float2((float)a.x, (float)a.y); }

@@ -308,6 +308,9 @@ constexpr int WG_G = 4;  // lanes per row in the workgroup SpMV
 // the row-pointer, index/value and gather loads of several rows are in
 // flight together.
 constexpr int WG_U = 8;
+// entries per lane and row whose loads are issued up front (rows up to
+// WgE * WG_G long), bounded by the registers they hold
+template <typename V> struct WgE { static constexpr int value = sizeof(V) == 16 ? 2 : 3; };
 
 template <typename V, int BS>
 __device__ __forceinline__ void blk_spmv(const Csr<V> &A, const V *x, V *y, const V *u1, const V *u2, double2 &d0,
@@ -320,8 +323,8 @@ __device__ __forceinline__ void blk_spmv(const Csr<V> &A, const V *x, V *y, cons
 #pragma unroll
         for (int u = 0; u < WG_U; ++u) {
             const int row = base + u * R;
-            rs[u] = (row < A.n) ? A.rowptr[row] : 0;
-            re[u] = (row < A.n) ? A.rowptr[row + 1] : 0;
+            rs[u] = (row < A.n) ? gld(A.rowptr + row) : 0;
+            re[u] = (row < A.n) ? gld(A.rowptr + row + 1) : 0;
         }
         V acc[WG_U];
 #pragma unroll
@@ -329,11 +332,32 @@ __device__ __forceinline__ void blk_spmv(const Csr<V> &A, const V *x, V *y, cons
         int mx = 0;
 #pragma unroll
         for (int u = 0; u < WG_U; ++u) mx = max(mx, re[u] - rs[u]);
-        for (int k = l; k < mx; k += WG_G) {
+        // the first WG_E entries of every row of the group: all loads issued
+        // before any is used (one memory round trip instead of one per step)
+        constexpr int WG_E = WgE<V>::value;
+        {
+            int cc[WG_U][WG_E];
+            V vv[WG_U][WG_E];
+#pragma unroll
+            for (int u = 0; u < WG_U; ++u)
+#pragma unroll
+                for (int t = 0; t < WG_E; ++t) {
+                    const int e = rs[u] + l + t * WG_G;
+                    const bool ok = e < re[u];
+                    cc[u][t] = ok ? gld(A.col + e) : -1;
+                    vv[u][t] = ok ? gld(A.val + e) : czero<V>();
+                }
+#pragma unroll
+            for (int u = 0; u < WG_U; ++u)
+#pragma unroll
+                for (int t = 0; t < WG_E; ++t)
+                    if (cc[u][t] >= 0) acc[u] = cadd(acc[u], cmul(vv[u][t], x[cc[u][t]]));
+        }
+        for (int k = l + WG_E * WG_G; k < mx; k += WG_G) {
 #pragma unroll
             for (int u = 0; u < WG_U; ++u) {
                 const int e = rs[u] + k;
-                if (e < re[u]) acc[u] = cadd(acc[u], cmul(A.val[e], x[A.col[e]]));
+                if (e < re[u]) acc[u] = cadd(acc[u], cmul(gld(A.val + e), x[gld(A.col + e)]));
             }
         }
 #pragma unroll
@@ -345,11 +369,11 @@ __device__ __forceinline__ void blk_spmv(const Csr<V> &A, const V *x, V *y, cons
             }
             const int row = base + u * R;
             if (l == 0 && row < A.n) {
-                y[row] = acc[u];
+                gst(y + row, acc[u]);
                 const double2 yy = widen(acc[u]);
-                if (u1) d0 = cadd(d0, cmulc(widen(u1[row]), yy));
+                if (u1) d0 = cadd(d0, cmulc(widen(gld(u1 + row)), yy));
                 if (u2y) d1.x += yy.x * yy.x + yy.y * yy.y;
-                else if (u2) d1 = cadd(d1, cmulc(widen(u2[row]), yy));
+                else if (u2) d1 = cadd(d1, cmulc(widen(gld(u2 + row)), yy));
             }
         }
     }
@@ -374,13 +398,13 @@ __device__ __forceinline__ void fetch_slot(SlotRegs<T> &q, int idx, int end, int
                                            const int *pcol, const T *pval, const T *aux) {
     constexpr int WG_K = WgK<T>::value;
     const int j = min(idx, n - 1);
-    q.sl = slot[j];
+    q.sl = gld(slot + j);
 #pragma unroll
     for (int k = 0; k < WG_K; ++k) {
-        q.c[k] = pcol[(size_t)k * n + j];
-        q.v[k] = pval[(size_t)k * n + j];
+        q.c[k] = gld(pcol + (size_t)k * n + j);
+        q.v[k] = gld(pval + (size_t)k * n + j);
     }
-    q.aux = aux[j];
+    q.aux = gld(aux + j);
     q.sl.w = idx < end;  // validity flag
 }
 
@@ -400,7 +424,7 @@ __device__ __forceinline__ void solve_regs(const SlotRegs<T> &q, const int *col,
         acc.y = take ? t.y : acc.y;
     }
     if (len > WG_K && q.sl.w) {
-        for (int e = q.sl.y + WG_K; e < q.sl.y + len; ++e) acc = csub(acc, cmul(val[e], Y[col[e]]));
+        for (int e = q.sl.y + WG_K; e < q.sl.y + len; ++e) acc = csub(acc, cmul(gld(val + e), Y[gld(col + e)]));
     }
     const T res = UPPER ? cdiv(acc, q.aux) : acc;
     if (q.sl.w) Y[q.sl.x] = res;
@@ -459,14 +483,14 @@ __device__ __forceinline__ void blk_precond(const WgProblem<T> &P, const int *lp
     // right-hand side in the forward sweep's level order, so the sweep reads
     // it by slot index
     T *bl = P.work + 10 * (size_t)n;
-    for (int idx = threadIdx.x; idx < n; idx += BS) bl[idx] = b[P.lslot[idx].x];
+    for (int idx = threadIdx.x; idx < n; idx += BS) gst(bl + idx, gld(b + gld(P.lslot + idx).x));
     __syncthreads();
     if (threadIdx.x < 64) {
         wave_sweep<T, false, LDSY>(P.nlev_l, n, lptr, P.lslot, P.lcol, P.lval, bl, P.LU.col, P.LU.val, Y);
         wave_sweep<T, true, LDSY>(P.nlev_u, n, uptr, P.uslot, P.ucol, P.uval, P.uaux, P.LU.col, P.LU.val, Y);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += BS) out[i] = Y[i];
+    for (int i = threadIdx.x; i < n; i += BS) gst(out + i, Y[i]);
     __syncthreads();
 }
 
@@ -495,12 +519,12 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
     InnerStats st = {0, 0, 0, 0, 0};
     double2 q1[1] = {mk(0.0, 0.0)};
     for (int i = threadIdx.x; i < n; i += BS) {
-        const T bi = b[i];
-        r[i] = bi;
-        rh[i] = bi;
-        p[i] = czero<T>();
-        v[i] = czero<T>();
-        x[i] = czero<T>();
+        const T bi = gld(b + i);
+        gst(r + i, bi);
+        gst(rh + i, bi);
+        gst(p + i, czero<T>());
+        gst(v + i, czero<T>());
+        gst(x + i, czero<T>());
         const double2 w = widen(bi);
         q1[0].x += w.x * w.x + w.y * w.y;
     }
@@ -516,8 +540,8 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
     while (st.its < P.maxiter) {
         const double2 beta = cmul(cdiv(rho, rho_old), cdiv(alpha, omega));
         for (int i = threadIdx.x; i < n; i += BS) {
-            const double2 q = csub(widen(p[i]), cmul(omega, widen(v[i])));
-            p[i] = from_c128<T>(cadd(widen(r[i]), cmul(beta, q)));
+            const double2 q = csub(widen(gld(p + i)), cmul(omega, widen(gld(v + i))));
+            gst(p + i, from_c128<T>(cadd(widen(gld(r + i)), cmul(beta, q))));
         }
         __syncthreads();
         long long c0 = wall_clock64();
@@ -535,14 +559,15 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
             alpha = cdiv(rho, rv);
             double2 q3[1] = {mk(0.0, 0.0)};
             for (int i = threadIdx.x; i < n; i += BS) {
-                const T si = from_c128<T>(csub(widen(r[i]), cmul(alpha, widen(v[i]))));
-                sv[i] = si;
+                const T si = from_c128<T>(csub(widen(gld(r + i)), cmul(alpha, widen(gld(v + i)))));
+                gst(sv + i, si);
                 const double2 w = widen(si);
                 q3[0].x += w.x * w.x + w.y * w.y;
             }
             blk_sum<BS, 1>(q3, red);
             if (q3[0].x <= tol2) {
-                for (int i = threadIdx.x; i < n; i += BS) x[i] = from_c128<T>(cadd(widen(x[i]), cmul(alpha, widen(ph[i]))));
+                for (int i = threadIdx.x; i < n; i += BS)
+                    gst(x + i, from_c128<T>(cadd(widen(gld(x + i)), cmul(alpha, widen(gld(ph + i))))));
                 __syncthreads();
                 st.its += 1;
                 st.converged = 1;
@@ -562,12 +587,12 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
             double2 q5[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
             for (int i = threadIdx.x; i < n; i += BS) {
                 const double2 xi =
-                    cadd(cadd(widen(x[i]), cmul(alpha, widen(ph[i]))), cmul(omega, widen(sh[i])));
-                x[i] = from_c128<T>(xi);
-                const T ri = from_c128<T>(csub(widen(sv[i]), cmul(omega, widen(t[i]))));
-                r[i] = ri;
+                    cadd(cadd(widen(gld(x + i)), cmul(alpha, widen(gld(ph + i)))), cmul(omega, widen(gld(sh + i))));
+                gst(x + i, from_c128<T>(xi));
+                const T ri = from_c128<T>(csub(widen(gld(sv + i)), cmul(omega, widen(gld(t + i)))));
+                gst(r + i, ri);
                 const double2 rw = widen(ri);
-                q5[0] = cadd(q5[0], cmulc(widen(rh[i]), rw));
+                q5[0] = cadd(q5[0], cmulc(widen(gld(rh + i)), rw));
                 q5[1].x += rw.x * rw.x + rw.y * rw.y;
             }
             blk_sum<BS, 2>(q5, red);
@@ -591,10 +616,10 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
             st.breakdowns += 1;
             double2 q6[1] = {mk(0.0, 0.0)};
             for (int i = threadIdx.x; i < n; i += BS) {
-                const T ri = r[i];
-                rh[i] = ri;
-                p[i] = czero<T>();
-                v[i] = czero<T>();
+                const T ri = gld(r + i);
+                gst(rh + i, ri);
+                gst(p + i, czero<T>());
+                gst(v + i, czero<T>());
                 const double2 w = widen(ri);
                 q6[0].x += w.x * w.x + w.y * w.y;
             }
