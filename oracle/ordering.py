@@ -33,7 +33,9 @@ def _load():
 def pattern(A) -> sp.csr_matrix:
     """Boolean structure of the non-zero entries of A (explicit zeros excluded)."""
     A = sp.csr_matrix(A)
-    P = sp.csr_matrix((A.data != 0, A.indices, A.indptr), shape=A.shape)
+    # copies of the index arrays: eliminate_zeros works in place, and A may
+    # share its arrays with the caller's matrix
+    P = sp.csr_matrix((A.data != 0, A.indices.copy(), A.indptr.copy()), shape=A.shape)
     P.eliminate_zeros()
     P = P.astype(np.int8)
     P.sort_indices()

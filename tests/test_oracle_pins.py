@@ -211,6 +211,22 @@ def test_bandwidth_profile_hand_examples():
     assert oord.profile(T) == (4, 4, 8)
 
 
+def test_bandwidth_profile_skip_explicit_zeros_and_leave_the_input_alone():
+    """Bandwidth and profile count non-zero entries only (an explicit zero,
+    e.g. an added zero diagonal, is structure without value), and computing
+    them does not change the matrix passed in."""
+    indptr = np.array([0, 2, 3, 5])
+    indices = np.array([0, 2, 1, 0, 2])
+    data = np.array([1.0, 0.0, 1.0, 5.0, 1.0])  # (0, 2) stored as 0
+    A = sp.csr_matrix((data, indices, indptr), shape=(3, 3))
+    before = (A.indptr.copy(), A.indices.copy(), A.data.copy())
+    # non-zeros: (0,0), (1,1), (2,0), (2,2): ub = 0, lb = 2; up = 0; lp = 2
+    assert oord.bandwidth(A) == (0, 2, 3)
+    assert oord.profile(A) == (0, 2, 2)
+    assert oord.profile(A) == (0, 2, 2)  # a second call sees the same matrix
+    assert all(np.array_equal(x, y) for x, y in zip(before, (A.indptr, A.indices, A.data)))
+
+
 def test_cuthill_mckee_on_a_path_and_tie_free_graphs():
     """On a path graph RCM walks the path from one end (B = 3).  On graphs with
     a unique lowest-degree node and distinct neighbour degrees no tie-break is
