@@ -183,9 +183,12 @@ class _HostCsr:
         if _is_torch(m):
             raise TypeError("pass device CSR matrices as a tuple of torch tensors (indptr, indices, data, n)")
         if isinstance(m, tuple):
+            # (indptr int64, indices int32, data complex128, n) as torch device
+            # tensors or numpy host arrays, passed through unchanged
             indptr, indices, data, n = m
             self.keep = (indptr, indices, data)
-            self.s = _Csr(int(n), int(indices.numel()), _ptr(indptr), _ptr(indices), _ptr(data))
+            nnz = indices.numel() if _is_torch(indices) else indices.size
+            self.s = _Csr(int(n), int(nnz), _ptr(indptr), _ptr(indices), _ptr(data))
             return
         A = sp.csr_matrix(m, dtype=np.complex128)
         A.sum_duplicates()

@@ -152,3 +152,24 @@ def test_batched_setup_rejects_a_bad_trace_row_for_that_system_only():
     _, infos = ssl.solve_batch(Ls, "trace_bicgstab", 1e-10, raise_on_error=False, trace_row=5)
     assert infos[0]["status"] == ssl.SS_E_INVALID_ARG
     assert infos[1]["status"] == 0
+
+
+def test_batched_finish_reports_what_the_one_system_finish_reports():
+    """bandwidth and profile of P A P^T, trace and Hermiticity errors, and the
+    certificate from the batched finish against the oracle's definitions."""
+    from oracle import ordering as oord
+    from oracle import invariants as oinv
+    systems = _systems()[:6]
+    Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
+    rhos, infos = ssl.solve_batch(Ls, "trace_bicgstab", 1e-10, hermitize=True)
+    for s, L, rho, info in zip(systems, Ls, rhos, infos):
+        Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+        assert info["bandwidth"] == oord.bandwidth(Ap)[2], s.name
+        assert info["profile"] == oord.profile(Ap)[2], s.name
+        assert info["herm_err"] == oinv.hermiticity_error(rho) == 0.0
+        # trace_err: |Tr x - 1| of the solution before normalisation (the
+        # trace row holds it to the tolerance); the returned rho has unit trace
+        assert info["trace_err"] <= 1e-9
+        assert abs(np.trace(rho) - 1.0) <= 1e-13
+        Lo = liouvillian_sparse(s.H, s.c_ops)
+        assert abs(info["resid_l2"] - oinv.residual_l2(Lo, rho)) <= 1e-13 * max(1.0, float(abs(Lo).max()))

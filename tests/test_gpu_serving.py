@@ -79,3 +79,31 @@ def test_server_rejects_bad_requests():
     with pytest.raises(ssl.SolverError):
         S.submit(s.H, s.c_ops, "trace_gmres", 1e-10)
     S.close()
+
+
+def test_server_refuses_malformed_inputs_at_submission():
+    """Inputs are checked on the host copy when submitted, so a malformed
+    request never joins a group (the other requests are unaffected)."""
+    import numpy as np
+    import scipy.sparse as sp
+    S = ssl.Server(hbm_budget_bytes=1 << 30, max_slots=8)
+    good = qs.kerr(6)
+    A = sp.csr_matrix(good.H)
+    A.sort_indices()
+    ip = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    ix = np.ascontiguousarray(A.indices, dtype=np.int32).copy()
+    dv = np.ascontiguousarray(A.data, dtype=np.complex128)
+    r = next(i for i in range(6) if ip[i + 1] - ip[i] >= 2)
+    seg = slice(ip[r], ip[r + 1])
+    ix[seg] = ix[seg][::-1].copy()  # one row out of order
+    t_ok = S.submit(good.H, good.c_ops, "trace_bicgstab", 1e-10)
+    with pytest.raises(ssl.SolverError):
+        S.submit((ip, ix, dv, 6), good.c_ops, "trace_bicgstab", 1e-10)
+    bad_col = np.ascontiguousarray(A.indices, dtype=np.int32).copy()
+    bad_col[0] = 6  # out of range
+    with pytest.raises(ssl.SolverError):
+        S.submit((ip, bad_col, dv, 6), good.c_ops, "trace_bicgstab", 1e-10)
+    S.drain()
+    rho, info = S.poll(t_ok)
+    assert info["status"] == 0
+    S.close()
