@@ -26,9 +26,10 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 
-# per-source flags: the ILUT factorisation rounds every product and sum on
-# its own (no fused multiply-add), like a plain sequential implementation
-EXTRA = {"ilut.hip": ["-ffp-contract=off"]}
+# per-source flags: the factorisations round every product and sum on their
+# own (no fused multiply-add), like a plain sequential implementation, so the
+# one-system and batched ILU(0) kernels give the same factors
+EXTRA = {"ilut.hip": ["-ffp-contract=off"], "ilu.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

@@ -6,8 +6,9 @@
 // increasing order.  For every k < i with a_ik != 0 (increasing k): wait for
 // row k's published U part, l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the
 // j > k present in both row i and row k.  This is the serial ILU(0) order,
-// so the factors equal a serial ILU(0) up to rounding of each fused
-// multiply-add.  Done in fp64 for both precisions; the mixed path rounds the
+// and every product and difference is rounded on its own (the file is built
+// without floating-point contraction), so all the ILU(0) kernels here give
+// the same factors.  Done in fp64 for both precisions; the mixed path rounds the
 // finished factors to complex64.
 //
 // Pivot boost: a pivot with |u_ii| < detect * ||a_i||_inf is replaced by
@@ -190,54 +191,54 @@ __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs,
     const int g = threadIdx.x / ILU_LG, lane = threadIdx.x % ILU_LG;
     constexpr int NG = ILU_LVL_BS / ILU_LG;
     for (int lv = 0; lv < J.nlev; ++lv) {
-        const int s0 = J.lptr[lv], s1 = J.lptr[lv + 1];
+        const int s0 = gld(J.lptr + lv), s1 = gld(J.lptr + lv + 1);
         for (int sl = s0 + g; sl < s1; sl += NG) {
-            const int row = J.lslot[sl].x;
-            const int rs = J.rowptr[row], re = J.rowptr[row + 1], dg = J.diag[row];
+            const int row = gld(J.lslot + sl).x;
+            const int rs = gld(J.rowptr + row), re = gld(J.rowptr + row + 1), dg = gld(J.diag + row);
             double rn = 0.0;
             for (int e = rs + lane; e < re; e += ILU_LG) {
-                const double2 v = J.a[e];
-                J.w[e] = v;
+                const double2 v = gld(J.a + e);
+                gst(J.w + e, v);
                 rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
             }
             for (int off = ILU_LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, ILU_LG));
             for (int ek = rs; ek < dg; ++ek) {
-                const int k = J.col[ek];
-                const int dk = J.diag[k];
-                const int ke = J.rowptr[k + 1];
-                const double2 ukk = J.out[dk];
+                const int k = gld(J.col + ek);
+                const int dk = gld(J.diag + k);
+                const int ke = gld(J.rowptr + k + 1);
+                const double2 ukk = gld(J.out + dk);
                 const int owner = (ek - rs) % ILU_LG;
                 double2 l = mk(0.0, 0.0);
                 if (lane == owner) {
-                    l = cdiv(J.w[ek], ukk);
-                    J.w[ek] = l;
+                    l = cdiv(gld(J.w + ek), ukk);
+                    gst(J.w + ek, l);
                 }
                 l.x = __shfl(l.x, owner, ILU_LG);
                 l.y = __shfl(l.y, owner, ILU_LG);
                 for (int e = rs + lane; e < re; e += ILU_LG) {
                     if (e <= ek) continue;
-                    const int j = J.col[e];
+                    const int j = gld(J.col + e);
                     int lo = dk + 1, hi = ke - 1, f = -1;
                     while (lo <= hi) {
                         const int mid = (lo + hi) >> 1;
-                        const int c = J.col[mid];
+                        const int c = gld(J.col + mid);
                         if (c == j) { f = mid; break; }
                         if (c < j) lo = mid + 1; else hi = mid - 1;
                     }
-                    if (f >= 0) J.w[e] = csub(J.w[e], cmul(l, J.out[f]));
+                    if (f >= 0) gst(J.w + e, csub(gld(J.w + e), cmul(l, gld(J.out + f))));
                 }
             }
             if (lane == (dg - rs) % ILU_LG) {
-                const double2 p = J.w[dg];
+                const double2 p = gld(J.w + dg);
                 const double mag = sqrt(p.x * p.x + p.y * p.y);
                 const double bound = detect * rn;
                 if (!(mag >= bound)) {
                     const double b = (rn > 0.0) ? boost * rn : 1.0;
-                    J.w[dg] = (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0);
+                    gst(J.w + dg, (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0));
                     atomicAdd(J.nguard, 1);
                 }
             }
-            for (int e = rs + lane; e < re; e += ILU_LG) J.out[e] = J.w[e];
+            for (int e = rs + lane; e < re; e += ILU_LG) gst(J.out + e, gld(J.w + e));
         }
         __syncthreads();
     }

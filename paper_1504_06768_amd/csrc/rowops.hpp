@@ -123,6 +123,19 @@ __device__ inline int union_row(int r, const int *ar, const int *ac, const int *
 template <typename T>
 __device__ inline void sort_row_wave(int rs, int re, const int *col_in, const T *val_in, int *col_out, T *val_out) {
     const int lane = threadIdx.x & 63;
+    if (re - rs <= 64) {
+        // one pass: ranks from the other lanes' columns by shuffle (the
+        // whole wavefront calls this with the same row)
+        const int e = rs + lane;
+        const int c = (e < re) ? col_in[e] : 0x7fffffff;
+        int rank = 0;
+        for (int f = 0; f < re - rs; ++f) rank += (__shfl(c, f, 64) < c);
+        if (e < re) {
+            col_out[rs + rank] = c;
+            if (val_in) val_out[rs + rank] = val_in[e];
+        }
+        return;
+    }
     for (int e = rs + lane; e < re; e += 64) {
         const int c = col_in[e];
         int rank = 0;

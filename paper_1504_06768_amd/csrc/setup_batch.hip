@@ -308,10 +308,27 @@ __global__ void __launch_bounds__(256) k_bt_permute(const PermJob *jobs, const i
     if (STEP == 1) {
         const int lane = threadIdx.x & 63;
         const int q = (blockIdx.x - bstart[jb]) * 4 + (threadIdx.x >> 6);
-        if (q >= J.n) return;
-        const int r = J.perm[q];
-        const int rs = J.A.rowptr[r], re = J.A.rowptr[r + 1];
-        const int o = J.prow[q];
+        if (q >= J.n) return;  // (wave-uniform)
+        const int r = gld(J.perm + q);
+        const int rs = gld(J.A.rowptr + r), re = gld(J.A.rowptr + r + 1);
+        const int o = gld(J.prow + q);
+        if (re - rs <= 64) {
+            // the whole row in one pass: each lane maps its own column, the
+            // ranks come from the other lanes' values by shuffle
+            const int e = rs + lane;
+            const int c = (e < re) ? gld(J.iperm + gld(J.A.col + e)) : 0x7fffffff;
+            int rank = 0;
+            for (int f = 0; f < re - rs; ++f) rank += (__shfl(c, f, 64) < c);
+            if (e < re) {
+                J.pcol[o + rank] = c;
+                J.pval[o + rank] = gld(J.A.val + e);
+                if (J.lucol) {
+                    J.lucol[o + rank] = c;
+                    set_sentinel(J.luval + o + rank);
+                }
+            }
+            return;
+        }
         for (int e = rs + lane; e < re; e += 64) {
             const int c = J.iperm[J.A.col[e]];
             int rank = 0;
