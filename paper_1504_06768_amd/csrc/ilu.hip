@@ -183,8 +183,67 @@ void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hip
 // another, so the factor is read with plain loads.  Each row takes the steps
 // of ilu0_row in the same order with the same arithmetic, so the factors are
 // the same.
+//
+// Short rows (the common case) take a register path: the row's entries stay
+// in registers (ILU_FM per lane), the structure of every row k it holds is
+// fetched at once, and the U part of each such row (up to ILU_LG entries
+// after the pivot, one per lane) is read in one pass and matched against the
+// row's columns by shuffles.  That is a handful of dependent memory rounds
+// per row instead of several per eliminated entry.  Other rows (the trace
+// row, rows that hold it) take the general loop through the work array.
 constexpr int ILU_LG = 8;
 constexpr int ILU_LVL_BS = 1024;
+constexpr int ILU_FM = 2;       // row entries per lane on the register path
+constexpr int ILU_FK = ILU_LG;  // lower entries (rows k) on the register path
+
+// The general loop: one row by one group, the working row in J.w.
+__device__ __forceinline__ void ilu0_row_group(const Ilu0Job &J, int row, int rs, int re, int dg, int lane,
+                                               double detect, double boost) {
+    double rn = 0.0;
+    for (int e = rs + lane; e < re; e += ILU_LG) {
+        const double2 v = gld(J.a + e);
+        gst(J.w + e, v);
+        rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
+    }
+    for (int off = ILU_LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, ILU_LG));
+    for (int ek = rs; ek < dg; ++ek) {
+        const int k = gld(J.col + ek);
+        const int dk = gld(J.diag + k);
+        const int ke = gld(J.rowptr + k + 1);
+        const double2 ukk = gld(J.out + dk);
+        const int owner = (ek - rs) % ILU_LG;
+        double2 l = mk(0.0, 0.0);
+        if (lane == owner) {
+            l = cdiv(gld(J.w + ek), ukk);
+            gst(J.w + ek, l);
+        }
+        l.x = __shfl(l.x, owner, ILU_LG);
+        l.y = __shfl(l.y, owner, ILU_LG);
+        for (int e = rs + lane; e < re; e += ILU_LG) {
+            if (e <= ek) continue;
+            const int j = gld(J.col + e);
+            int lo = dk + 1, hi = ke - 1, f = -1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int c = gld(J.col + mid);
+                if (c == j) { f = mid; break; }
+                if (c < j) lo = mid + 1; else hi = mid - 1;
+            }
+            if (f >= 0) gst(J.w + e, csub(gld(J.w + e), cmul(l, gld(J.out + f))));
+        }
+    }
+    if (lane == (dg - rs) % ILU_LG) {
+        const double2 p = gld(J.w + dg);
+        const double mag = sqrt(p.x * p.x + p.y * p.y);
+        const double bound = detect * rn;
+        if (!(mag >= bound)) {
+            const double b = (rn > 0.0) ? boost * rn : 1.0;
+            gst(J.w + dg, (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0));
+            atomicAdd(J.nguard, 1);
+        }
+    }
+    for (int e = rs + lane; e < re; e += ILU_LG) gst(J.out + e, gld(J.w + e));
+}
 
 __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs, double detect, double boost) {
     const Ilu0Job &J = jobs[blockIdx.x];
@@ -195,50 +254,109 @@ __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs,
         for (int sl = s0 + g; sl < s1; sl += NG) {
             const int row = gld(J.lslot + sl).x;
             const int rs = gld(J.rowptr + row), re = gld(J.rowptr + row + 1), dg = gld(J.diag + row);
+            const int nl = dg - rs;  // entries before the pivot: the rows k this row eliminates with
+            bool fast = (re - rs <= ILU_LG * ILU_FM) && nl <= ILU_FK;
+            // the row in registers: entry rs + lane + ILU_LG m in slot m
+            int cj[ILU_FM];
+            double2 wv[ILU_FM];
             double rn = 0.0;
-            for (int e = rs + lane; e < re; e += ILU_LG) {
-                const double2 v = gld(J.a + e);
-                gst(J.w + e, v);
-                rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
+            int dk0 = 0, ke0 = 0;  // structure of row k = col[rs + lane] (lane < nl)
+            if (fast) {
+#pragma unroll
+                for (int m = 0; m < ILU_FM; ++m) {
+                    const int e = rs + lane + ILU_LG * m;
+                    cj[m] = -1;
+                    wv[m] = mk(0.0, 0.0);
+                    if (e < re) {
+                        cj[m] = gld(J.col + e);
+                        wv[m] = gld(J.a + e);
+                    }
+                }
+                if (lane < nl) {
+                    dk0 = gld(J.diag + cj[0]);
+                    ke0 = gld(J.rowptr + cj[0] + 1);
+                }
+#pragma unroll
+                for (int m = 0; m < ILU_FM; ++m)
+                    if (rs + lane + ILU_LG * m < re) rn = fmax(rn, sqrt(wv[m].x * wv[m].x + wv[m].y * wv[m].y));
+                // every U part must fit one entry per lane
+                int wide = (lane < nl && ke0 - dk0 - 1 > ILU_LG) ? 1 : 0;
+                for (int off = ILU_LG / 2; off > 0; off >>= 1) wide |= __shfl_xor(wide, off, ILU_LG);
+                fast = !wide;
+            }
+            if (!fast) {
+                ilu0_row_group(J, row, rs, re, dg, lane, detect, boost);
+                continue;
             }
             for (int off = ILU_LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, ILU_LG));
-            for (int ek = rs; ek < dg; ++ek) {
-                const int k = gld(J.col + ek);
-                const int dk = gld(J.diag + k);
-                const int ke = gld(J.rowptr + k + 1);
-                const double2 ukk = gld(J.out + dk);
-                const int owner = (ek - rs) % ILU_LG;
-                double2 l = mk(0.0, 0.0);
-                if (lane == owner) {
-                    l = cdiv(gld(J.w + ek), ukk);
-                    gst(J.w + ek, l);
-                }
-                l.x = __shfl(l.x, owner, ILU_LG);
-                l.y = __shfl(l.y, owner, ILU_LG);
-                for (int e = rs + lane; e < re; e += ILU_LG) {
-                    if (e <= ek) continue;
-                    const int j = gld(J.col + e);
-                    int lo = dk + 1, hi = ke - 1, f = -1;
-                    while (lo <= hi) {
-                        const int mid = (lo + hi) >> 1;
-                        const int c = gld(J.col + mid);
-                        if (c == j) { f = mid; break; }
-                        if (c < j) lo = mid + 1; else hi = mid - 1;
+            // U parts: for lower entry p, lane t holds entry dk + 1 + t of row k
+            int uc[ILU_FK];
+            double2 uv[ILU_FK], ukk[ILU_FK];
+#pragma unroll
+            for (int p = 0; p < ILU_FK; ++p) {
+                const int dk = __shfl(dk0, p, ILU_LG), ke = __shfl(ke0, p, ILU_LG);
+                uc[p] = -1;
+                uv[p] = mk(0.0, 0.0);
+                ukk[p] = mk(1.0, 0.0);
+                if (p < nl) {
+                    ukk[p] = gld(J.out + dk);
+                    const int f = dk + 1 + lane;
+                    if (f < ke) {
+                        uc[p] = gld(J.col + f);
+                        uv[p] = gld(J.out + f);
                     }
-                    if (f >= 0) gst(J.w + e, csub(gld(J.w + e), cmul(l, gld(J.out + f))));
                 }
             }
-            if (lane == (dg - rs) % ILU_LG) {
-                const double2 p = gld(J.w + dg);
-                const double mag = sqrt(p.x * p.x + p.y * p.y);
-                const double bound = detect * rn;
-                if (!(mag >= bound)) {
-                    const double b = (rn > 0.0) ? boost * rn : 1.0;
-                    gst(J.w + dg, (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0));
-                    atomicAdd(J.nguard, 1);
+            // eliminate with rows k in increasing order (the lower entries
+            // are sorted): l = a_ik / u_kk, then a_ij -= l u_kj on the
+            // columns j > k the two rows share
+#pragma unroll
+            for (int p = 0; p < ILU_FK; ++p) {
+                if (p < nl) {
+                    double2 l = mk(0.0, 0.0);
+                    if (lane == p) {
+                        l = cdiv(wv[0], ukk[p]);
+                        wv[0] = l;
+                    }
+                    l.x = __shfl(l.x, p, ILU_LG);
+                    l.y = __shfl(l.y, p, ILU_LG);
+                    int sm[ILU_FM];
+#pragma unroll
+                    for (int m = 0; m < ILU_FM; ++m) sm[m] = -1;
+                    for (int t = 0; t < ILU_LG; ++t) {
+                        const int c = __shfl(uc[p], t, ILU_LG);
+#pragma unroll
+                        for (int m = 0; m < ILU_FM; ++m)
+                            if (c >= 0 && c == cj[m]) sm[m] = t;
+                    }
+#pragma unroll
+                    for (int m = 0; m < ILU_FM; ++m) {
+                        double2 u;
+                        u.x = __shfl(uv[p].x, sm[m] < 0 ? 0 : sm[m], ILU_LG);
+                        u.y = __shfl(uv[p].y, sm[m] < 0 ? 0 : sm[m], ILU_LG);
+                        if (sm[m] >= 0) wv[m] = csub(wv[m], cmul(l, u));
+                    }
                 }
             }
-            for (int e = rs + lane; e < re; e += ILU_LG) gst(J.out + e, gld(J.w + e));
+            // pivot guard on the lane holding the diagonal entry
+#pragma unroll
+            for (int m = 0; m < ILU_FM; ++m) {
+                if (nl == lane + ILU_LG * m) {
+                    const double2 p = wv[m];
+                    const double mag = sqrt(p.x * p.x + p.y * p.y);
+                    const double bound = detect * rn;
+                    if (!(mag >= bound)) {
+                        const double b = (rn > 0.0) ? boost * rn : 1.0;
+                        wv[m] = (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0);
+                        atomicAdd(J.nguard, 1);
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < ILU_FM; ++m) {
+                const int e = rs + lane + ILU_LG * m;
+                if (e < re) gst(J.out + e, wv[m]);
+            }
         }
         __syncthreads();
     }

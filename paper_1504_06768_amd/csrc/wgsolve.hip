@@ -127,6 +127,85 @@ __global__ void __launch_bounds__(1024) k_levels_batch(const LevelJob *jobs) {
     }
 }
 
+// The same analysis with the levels of the system in LDS (systems up to
+// LEVELS_LDS_MAX rows): a dependency check is an LDS read, each row's columns
+// come from memory once (eight at a time, kept in registers), and the
+// largest level is reduced in the workgroup before one atomic.  As above, a
+// lane never blocks: every pass over the wavefront consumes the dependencies
+// that are ready and publishes the rows that are complete, so a lane waiting
+// on a row held by another lane of its own wavefront cannot stall it.
+constexpr int LEVELS_LDS_MAX = 16384;
+
+template <bool UPPER>
+__global__ void __launch_bounds__(1024) k_levels_batch_lds(const LevelJob *jobs) {
+    extern __shared__ int slvl[];
+    __shared__ int smax;
+    const LevelJob &J = jobs[blockIdx.x];
+    const int n = J.n;
+    for (int i = threadIdx.x; i < n; i += 1024) slvl[i] = -1;
+    if (threadIdx.x == 0) smax = -1;
+    __syncthreads();
+    int mymax = -1;
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+        const int lin = c0 + (int)threadIdx.x;
+        const bool active = lin < n;
+        const int row = UPPER ? n - 1 - lin : lin;
+        int e = 0, ee = 0, m = -1;
+        if (active) {
+            e = UPPER ? gld(J.diag + row) + 1 : gld(J.rowptr + row);
+            ee = UPPER ? gld(J.rowptr + row + 1) : gld(J.diag + row);
+        }
+        bool done = !active;
+        int c[8];
+        unsigned pend = 0;  // dependencies among c[] not yet seen complete
+        unsigned spins = 0;
+        while (true) {
+            if (!done) {
+                if (pend == 0 && e < ee) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        c[q] = (e + q < ee) ? gld(J.col + e + q) : 0;
+                        if (e + q < ee) pend |= 1u << q;
+                    }
+                    e += 8;
+                }
+                const unsigned before = pend;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (pend & (1u << q)) {
+                        const int v = __hip_atomic_load(slvl + c[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (v >= 0) {
+                            m = max(m, v);
+                            pend &= ~(1u << q);
+                        }
+                    }
+                }
+                if (pend != before) {
+                    spins = 0;
+                } else if (pend) {
+                    ++spins;
+                    if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(J.status))) {
+                        atomicOr(J.status, STATUS_SPIN_TIMEOUT);
+                        pend = 0;
+                        e = ee;
+                    }
+                }
+                if (pend == 0 && e >= ee) {
+                    __hip_atomic_store(slvl + row, m + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    gst(J.lvl + row, m + 1);
+                    mymax = max(mymax, m + 1);
+                    done = true;
+                }
+            }
+            if (__all(done)) break;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) mymax = max(mymax, __shfl_xor(mymax, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&smax, mymax);
+    __syncthreads();
+    if (threadIdx.x == 0 && smax >= 0) atomicMax(J.maxlvl, smax);
+}
+
 __global__ void k_level_count(int n, const int *lvl, int *cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) atomicAdd(&cnt[lvl[i]], 1);
@@ -198,11 +277,21 @@ template void LevelBuild::finish<true>(const Csr<double2> &, const int *, LevelS
 template <bool UPPER>
 void levels_batch(const LevelJob *jobs, int count, hipStream_t s) {
     if (count <= 0) return;
+    StreamScope scope(s);
+    int max_n = 0;
+    for (int k = 0; k < count; ++k) max_n = std::max(max_n, jobs[k].n);
     DevBuf<LevelJob> dj((size_t)count);
     h2d(dj.get(), jobs, (size_t)count, s);
-    k_levels_batch<UPPER><<<count, 1024, 0, s>>>(dj.get());
+    if (max_n <= LEVELS_LDS_MAX) {
+        const size_t bytes = sizeof(int) * (size_t)std::max(max_n, 1);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_levels_batch_lds<UPPER>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        (void)hipGetLastError();
+        k_levels_batch_lds<UPPER><<<count, 1024, bytes, s>>>(dj.get());
+    } else {
+        k_levels_batch<UPPER><<<count, 1024, 0, s>>>(dj.get());
+    }
     SS_HIP(hipGetLastError());
-    SS_HIP(hipStreamSynchronize(s));  // the job array is released on return
 }
 template void levels_batch<false>(const LevelJob *, int, hipStream_t);
 template void levels_batch<true>(const LevelJob *, int, hipStream_t);
