@@ -473,7 +473,9 @@ __device__ __forceinline__ void blk_spmv(const Csr<V> &A, const V *x, V *y, cons
 template <typename T>
 struct SlotRegs {
     static constexpr int WG_K = WgK<T>::value;
-    int4 sl;  // {row, first CSR entry, length, 0}; row < 0: no slot
+    int4 sl;  // {row, first CSR entry, length, 0}
+    int ok;   // the slot is in the level (a register of its own: writing a
+              // lane of sl would wait for its load)
     int c[WG_K];
     T v[WG_K];
     T aux;    // lower: right-hand side (level order); upper: pivot
@@ -494,13 +496,16 @@ __device__ __forceinline__ void fetch_slot(SlotRegs<T> &q, int idx, int end, int
         q.v[k] = gld(pval + (size_t)k * n + j);
     }
     q.aux = gld(aux + j);
-    q.sl.w = idx < end;  // validity flag
+    q.ok = idx < end;
 }
 
 template <typename T, bool UPPER>
 __device__ __forceinline__ void solve_regs(const SlotRegs<T> &q, const int *col, const T *val, T *Y) {
     constexpr int WG_K = WgK<T>::value;
-    const int len = q.sl.z;
+    // the record's last field is 0; adding it keeps all four loaded
+    // registers live until here, so none is reused (which would wait for
+    // the load) while the ring's loads are in flight
+    const int len = q.sl.z + q.sl.w;
     T acc = UPPER ? Y[q.sl.x] : q.aux;
 #pragma unroll
     for (int k = 0; k < WG_K; ++k) {
@@ -512,11 +517,11 @@ __device__ __forceinline__ void solve_regs(const SlotRegs<T> &q, const int *col,
         acc.x = take ? t.x : acc.x;
         acc.y = take ? t.y : acc.y;
     }
-    if (len > WG_K && q.sl.w) {
+    if (len > WG_K && q.ok) {
         for (int e = q.sl.y + WG_K; e < q.sl.y + len; ++e) acc = csub(acc, cmul(gld(val + e), Y[gld(col + e)]));
     }
     const T res = UPPER ? cdiv(acc, q.aux) : acc;
-    if (q.sl.w) Y[q.sl.x] = res;
+    if (q.ok) Y[q.sl.x] = res;
 }
 
 // Slots of a level beyond the first 64: fetched and solved directly.
@@ -565,9 +570,47 @@ __device__ __forceinline__ void wave_sweep(int nlev, int n, const int *ptr, cons
     }
 }
 
+// The sweeps' level pointers as the solve kernel keeps them in LDS: every
+// level split into runs of at most 64 slots, so that a single wavefront's
+// register ring prefetches every slot (the rows of one level are
+// independent, so any split of a level is a valid schedule).
+struct WgSched {
+    const int *lptr, *uptr;
+    int nl, nu;
+};
+constexpr int WG_SPLIT_PAD = 6;  // the sweep reads up to five pointers past the last run
+// LDS ints of one side's split pointers
+__host__ __device__ constexpr int wg_split_ints(int nlev, int n) { return nlev + n / 64 + WG_SPLIT_PAD + 1; }
+
+// Writes the split pointers of g[0 .. nlev] to out (one wavefront): out[s]
+// is the first slot of run s; the count of runs is returned and out[count ..
+// count + 5] repeat the end (room for WG_SPLIT_PAD entries past the runs).
+// At most nlev + n / 64 runs.
+__device__ __forceinline__ int split_levels(const int *g, int nlev, int *out) {
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    for (int l0 = 0; l0 < nlev; l0 += 64) {
+        const int l = l0 + lane;
+        int a = 0, cnt = 0;
+        if (l < nlev) {
+            a = g[l];
+            cnt = (g[l + 1] - a + 63) >> 6;
+        }
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        for (int q = 0; q < cnt; ++q) out[base + incl - cnt + q] = a + 64 * q;
+        base += __shfl(incl, 63, 64);
+    }
+    const int end = g[nlev];
+    if (lane < WG_SPLIT_PAD) out[base + lane] = end;
+    return base;
+}
+
 template <typename T, int BS, bool LDSY>
-__device__ __forceinline__ void blk_precond(const WgProblem<T> &P, const int *lptr, const int *uptr, const T *b,
-                                            T *out, T *Y) {
+__device__ __forceinline__ void blk_precond(const WgProblem<T> &P, const WgSched &S, const T *b, T *out, T *Y) {
     const int n = P.n;
     // right-hand side in the forward sweep's level order, so the sweep reads
     // it by slot index
@@ -575,8 +618,8 @@ __device__ __forceinline__ void blk_precond(const WgProblem<T> &P, const int *lp
     for (int idx = threadIdx.x; idx < n; idx += BS) gst(bl + idx, gld(b + gld(P.lslot + idx).x));
     __syncthreads();
     if (threadIdx.x < 64) {
-        wave_sweep<T, false, LDSY>(P.nlev_l, n, lptr, P.lslot, P.lcol, P.lval, bl, P.LU.col, P.LU.val, Y);
-        wave_sweep<T, true, LDSY>(P.nlev_u, n, uptr, P.uslot, P.ucol, P.uval, P.uaux, P.LU.col, P.LU.val, Y);
+        wave_sweep<T, false, LDSY>(S.nl, n, S.lptr, P.lslot, P.lcol, P.lval, bl, P.LU.col, P.LU.val, Y);
+        wave_sweep<T, true, LDSY>(S.nu, n, S.uptr, P.uslot, P.ucol, P.uval, P.uaux, P.LU.col, P.LU.val, Y);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += BS) gst(out + i, Y[i]);
@@ -599,8 +642,8 @@ constexpr double WG_DIVERGED2 = 1e8;
 // ||r|| <= rtol ||b||; breakdown (r^ orthogonal to r, or omega = 0) restarts
 // with r^ = r up to three times.
 template <typename T, int BS, bool LDSY>
-__device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const int *lptr, const int *uptr,
-                                                   const T *b, T *x, double rtol, T *Y,
+__device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const WgSched &S, const T *b, T *x,
+                                                   double rtol, T *Y,
                                                    double2 (*red)[BS / 64 + 1]) {
     const int n = P.n;
     T *r = P.work, *rh = r + n, *p = rh + n, *v = p + n, *sv = v + n, *t = sv + n, *ph = t + n, *sh = ph + n;
@@ -634,7 +677,7 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
         }
         __syncthreads();
         long long c0 = wall_clock64();
-        blk_precond<T, BS, LDSY>(P, lptr, uptr, p, ph, Y);
+        blk_precond<T, BS, LDSY>(P, S, p, ph, Y);
         long long c1 = wall_clock64();
         double2 q2[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
         blk_spmv<T, BS>(P.A, LDSY ? Y : ph, v, rh, v, q2[0], q2[1]);
@@ -663,7 +706,7 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
                 return st;
             }
             c0 = wall_clock64();
-            blk_precond<T, BS, LDSY>(P, lptr, uptr, sv, sh, Y);
+            blk_precond<T, BS, LDSY>(P, S, sv, sh, Y);
             c1 = wall_clock64();
             double2 q4[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
             blk_spmv<T, BS>(P.A, LDSY ? Y : sh, t, sv, t, q4[0], q4[1]);
@@ -780,19 +823,22 @@ __global__ void __launch_bounds__(BS) k_wg_solve(const WgProblem<T> *probs) {
     const WgProblem<T> &P = probs[blockIdx.x];
     T *Y = LDSY ? reinterpret_cast<T *>(dyn_lds) : P.ysc;
     const int n = P.n;
-    // level pointers in LDS next to Y: reading them is then an LDS access,
-    // ordered with the other LDS traffic of the sweeps
-    const int *lptr = P.lptr, *uptr = P.uptr;
+    // level pointers in LDS next to Y (reading them is then an LDS access,
+    // ordered with the other LDS traffic of the sweeps), split into runs of
+    // at most 64 slots and padded with repeats of the end so the sweeps can
+    // read ahead without bounds checks
+    __shared__ int nsplit[2];
+    WgSched S;
     {
-        // level pointers in LDS (padded with five repeats of the end so the
-        // sweeps can read ahead without bounds checks)
         int *lp = reinterpret_cast<int *>(dyn_lds + (LDSY ? (size_t)n * sizeof(T) : 0));
-        int *up = lp + P.nlev_l + 6;
-        for (int k = threadIdx.x; k <= P.nlev_l + 5; k += BS) lp[k] = P.lptr[min(k, P.nlev_l)];
-        for (int k = threadIdx.x; k <= P.nlev_u + 5; k += BS) up[k] = P.uptr[min(k, P.nlev_u)];
+        int *up = lp + wg_split_ints(P.nlev_l, n);
+        const int wave = threadIdx.x >> 6;
+        if (wave < 2) {
+            const int c = wave == 0 ? split_levels(P.lptr, P.nlev_l, lp) : split_levels(P.uptr, P.nlev_u, up);
+            if ((threadIdx.x & 63) == 0) nsplit[wave] = c;
+        }
         __syncthreads();
-        lptr = lp;
-        uptr = up;
+        S = WgSched{lp, up, nsplit[0], nsplit[1]};
     }
     T *bT = P.work + 8 * (size_t)n, *dT = bT + n;
     int status = SS_E_NOT_CONVERGED, inner = 0, breakdowns = 0, outer = 0;
@@ -834,7 +880,7 @@ __global__ void __launch_bounds__(BS) k_wg_solve(const WgProblem<T> *probs) {
         const double inv = 1.0 / rn;
         for (int i = threadIdx.x; i < n; i += BS) bT[i] = from_c128<T>(cscale(P.r64[i], inv));
         __syncthreads();
-        const InnerStats is = blk_bicgstab<T, BS, LDSY>(P, lptr, uptr, bT, dT, fmin(rtol, 0.5), Y, red);
+        const InnerStats is = blk_bicgstab<T, BS, LDSY>(P, S, bT, dT, fmin(rtol, 0.5), Y, red);
         inner += is.its;
         breakdowns += is.breakdowns;
         t_pre += is.t_pre;
@@ -893,14 +939,18 @@ int wg_lds_capacity() {
 template int wg_lds_capacity<double2>();
 template int wg_lds_capacity<float2>();
 
+// LDS ints of both sides' split level pointers (at most nlev + n / 64 runs
+// per side, plus the padding)
+static size_t wg_ptr_ints(size_t n, int levels) { return (size_t)levels + 2 * (n / 64) + 2 * WG_SPLIT_PAD + 2; }
+
 bool wg_fits_lds(size_t n, size_t elem, int levels) {
-    return n * elem + sizeof(int) * ((size_t)levels + 12) <= lds_budget();
+    return n * elem + sizeof(int) * wg_ptr_ints(n, levels) <= lds_budget();
 }
 
 template <typename T>
 void wg_solve(const WgProblem<T> *probs, int count, int max_n, int max_levels, hipStream_t s) {
     if (count <= 0) return;
-    const size_t ptr_bytes = sizeof(int) * ((size_t)max_levels + 12);
+    const size_t ptr_bytes = sizeof(int) * wg_ptr_ints((size_t)max_n, max_levels);
     const size_t bytes = (size_t)max_n * sizeof(T) + ptr_bytes;
     if (bytes <= lds_budget()) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, true>),
