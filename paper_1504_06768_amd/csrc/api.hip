@@ -21,6 +21,16 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
+}  // namespace
+
+namespace ss {
+// The calling thread's message for ss_last_error (the server reports a
+// request's failure, recorded on its scheduler thread, this way at ss_poll).
+void set_last_error(const std::string &msg) { g_err = msg; }
+}  // namespace ss
+
+namespace {
+
 template <typename F>
 int guarded(F &&f) {
     try {

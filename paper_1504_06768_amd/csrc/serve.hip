@@ -308,8 +308,8 @@ static void scheduler_loop(ss_server_s *S) {
 
 }  // namespace ss
 
-namespace {
-thread_local std::string s_err;
+namespace ss {
+void set_last_error(const std::string &msg);
 }
 
 extern "C" {
@@ -380,6 +380,7 @@ int ss_poll(ss_server S, uint64_t ticket, double *rho_out, ss_info *info) {
         S->all.erase(it);
     }
     const int st = r->status;
+    if (st != SS_OK) ss::set_last_error(r->error);
     if (info) *info = r->info;
     if (rho_out && !r->rho.empty()) {
         const size_t bytes = sizeof(double) * r->rho.size();

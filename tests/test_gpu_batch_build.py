@@ -173,3 +173,26 @@ def test_batched_finish_reports_what_the_one_system_finish_reports():
         assert abs(np.trace(rho) - 1.0) <= 1e-13
         Lo = liouvillian_sparse(s.H, s.c_ops)
         assert abs(info["resid_l2"] - oinv.residual_l2(Lo, rho)) <= 1e-13 * max(1.0, float(abs(Lo).max()))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_setup_and_solve_equal_one_system_on_the_workload(prec):
+    """Driven Jaynes-Cummings, cavity 40 x qubit (n = 6400, several
+    1024-row chunks in every batched set-up kernel): the batch's matrices,
+    ordering and ILU(0) factors equal ss_prepare's bit for bit, and its solve
+    takes the same iterations to the same bits as the one-system workgroup
+    solve (the same kernel on the same factors)."""
+    s = qs.config(2)
+    Ls = ssl.build_liouvillian_batch([(s.H, s.c_ops)] * 3)
+    rhos, infos = ssl.solve_batch(Ls, "trace_bicgstab", 1e-10, prec=prec)
+    ref = ssl.build_liouvillian(s.H, s.c_ops)
+    rho1, info1 = ssl.solve(ref, "trace_bicgstab", tol=1e-10, prec=prec, path="workgroup")
+    print("batched", [(i["outer_its"], i["inner_its"]) for i in infos], "one system",
+          (info1["outer_its"], info1["inner_its"]), file=sys.stderr, flush=True)
+    for L, rho, info in zip(Ls, rhos, infos):
+        for a, b in zip(_mats(L), _mats(ref)):
+            assert np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+            assert np.array_equal(a.data, b.data)
+        assert np.array_equal(ssl.export_perm(L), ssl.export_perm(ref))
+        assert (info["outer_its"], info["inner_its"]) == (info1["outer_its"], info1["inner_its"])
+        assert np.array_equal(rho, rho1)
