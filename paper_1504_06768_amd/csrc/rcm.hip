@@ -137,7 +137,7 @@ __device__ __forceinline__ void place_owned(int p, int rs, int re, int base, con
         int v = 0x7fffffff, dv = 0x7fffffff;
         bool own = false;
         if (e < re) {
-            v = col[e];
+            v = gld(col + e);
             const int ow = ATOMIC_OWNER ? __hip_atomic_load(owner + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                         : owner[v];
             own = pos_of[v] < 0 && ow == p;
@@ -154,7 +154,7 @@ __device__ __forceinline__ void place_owned(int p, int rs, int re, int base, con
                 dw = dv;
                 ownw = own;
             } else if (f < re) {
-                w = col[f];
+                w = gld(col + f);
                 const int ow = ATOMIC_OWNER
                                    ? __hip_atomic_load(owner + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                    : owner[w];
@@ -211,19 +211,38 @@ __global__ void k_fill_int(int n, int *p, int v) {
 // barrier between the claim / count / scan / place / mark phases), for
 // graphs small enough that launch and host round-trip latency would
 // dominate the multi-kernel form.  owner[] is only changed by atomics and is
-// read back with device-scope atomic loads.
+// read back with device-scope atomic loads.  With LDS set, the search state
+// (degrees, positions, owners, the order and the frontier offsets: 5n + 1
+// ints) lives in LDS and only the graph and the result are in memory; the
+// graph is read with global loads, so that waiting for an LDS access never
+// waits for them.
 constexpr int RCM_BLOCK_T = 1024;
 
 __device__ __forceinline__ int ld_owner(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <bool LDS>
 __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(const RcmJob *jobs) {
     constexpr int NW = RCM_BLOCK_T / 64;
+    extern __shared__ int rcm_lds[];
     const RcmJob &J = jobs[blockIdx.x];
     const int n = J.n;
     const int *rowptr = J.rowptr, *col = J.col;
-    int *deg = J.deg, *pos_of = J.pos_of, *owner = J.owner, *order = J.order, *offs = J.offs;
+    int *deg, *pos_of, *owner, *order, *offs;
+    if (LDS) {
+        deg = rcm_lds;
+        pos_of = deg + n;
+        owner = pos_of + n;
+        order = owner + n;
+        offs = order + n;
+    } else {
+        deg = J.deg;
+        pos_of = J.pos_of;
+        owner = J.owner;
+        order = J.order;
+        offs = J.offs;
+    }
     int *perm = J.perm, *iperm = J.iperm;
     __shared__ unsigned long long sbest[NW];
     __shared__ int wsum[NW];
@@ -232,8 +251,9 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(const RcmJob *jobs) {
     for (int r = tid; r < n; r += RCM_BLOCK_T) {
         pos_of[r] = -1;
         owner[r] = 0x7fffffff;
-        int dg = rowptr[r + 1] - rowptr[r];
-        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) dg += (col[e] == r);  // a self-loop counts twice
+        const int rs = gld(rowptr + r), re = gld(rowptr + r + 1);
+        int dg = re - rs;
+        for (int e = rs; e < re; ++e) dg += (gld(col + e) == r);  // a self-loop counts twice
         deg[r] = dg;
     }
     __syncthreads();
@@ -269,8 +289,9 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(const RcmJob *jobs) {
             // claim: each unvisited neighbour goes to the frontier node of lowest position
             for (int p = lo + wave; p < hi; p += NW) {
                 const int u = order[p];
-                for (int e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) {
-                    const int v = col[e];
+                const int ue = gld(rowptr + u + 1);
+                for (int e = gld(rowptr + u) + lane; e < ue; e += 64) {
+                    const int v = gld(col + e);
                     if (pos_of[v] < 0) atomicMin(&owner[v], p);
                 }
             }
@@ -278,9 +299,10 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(const RcmJob *jobs) {
             // count the children each frontier node owns
             for (int p = lo + wave; p < hi; p += NW) {
                 const int u = order[p];
+                const int ue = gld(rowptr + u + 1);
                 int c = 0;
-                for (int e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) {
-                    const int v = col[e];
+                for (int e = gld(rowptr + u) + lane; e < ue; e += 64) {
+                    const int v = gld(col + e);
                     c += (pos_of[v] < 0 && ld_owner(owner + v) == p);
                 }
                 for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
@@ -313,7 +335,8 @@ __global__ void __launch_bounds__(RCM_BLOCK_T) k_rcm_block(const RcmJob *jobs) {
             // place the children of each frontier node by (degree, index)
             for (int p = lo + wave; p < hi; p += NW) {
                 const int u = order[p];
-                place_owned<true>(p, rowptr[u], rowptr[u + 1], hi + offs[p - lo], col, pos_of, owner, deg, order);
+                place_owned<true>(p, gld(rowptr + u), gld(rowptr + u + 1), hi + offs[p - lo], col, pos_of, owner, deg,
+                                  order);
             }
             __syncthreads();
             for (int q = hi + tid; q < hi + total; q += RCM_BLOCK_T) pos_of[order[q]] = q;
@@ -356,11 +379,37 @@ RcmJob RcmScratch::job(const CsrBuf<double2> &S, int *perm, int *iperm) const {
     return j;
 }
 
+// LDS a workgroup may take (the kernel's static LDS is below 1 KB)
+static size_t rcm_lds_budget() {
+    static size_t cached = 0;
+    if (!cached) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            cached = prop.sharedMemPerBlock > 2048 ? prop.sharedMemPerBlock - 2048 : 0;
+        } else {
+            (void)hipGetLastError();
+            cached = 64 * 1024 - 2048;
+        }
+    }
+    return cached;
+}
+
 void rcm_batch(const RcmJob *jobs, int count, hipStream_t s) {
     if (count <= 0) return;
+    int max_n = 0;
+    for (int k = 0; k < count; ++k) max_n = std::max(max_n, jobs[k].n);
     DevBuf<RcmJob> dj((size_t)count);
     h2d(dj.get(), jobs, (size_t)count, s);
-    k_rcm_block<<<count, RCM_BLOCK_T, 0, s>>>(dj.get());
+    const size_t lds = sizeof(int) * (5 * (size_t)max_n + 1);
+    if (lds <= rcm_lds_budget()) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rcm_block<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+        k_rcm_block<true><<<count, RCM_BLOCK_T, lds, s>>>(dj.get());
+    } else {
+        k_rcm_block<false><<<count, RCM_BLOCK_T, 0, s>>>(dj.get());
+    }
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s));  // the job array is released on return
 }
