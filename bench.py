@@ -108,6 +108,16 @@ def _run_stream(ssl, systems, arrivals, prec):
     return wall, np.asarray(lat), res
 
 
+def _prec_summary(r, err):
+    """Throughput, accuracy and iteration counts of one precision's batched step."""
+    if not r:
+        return None
+    i0 = r["infos"][0]
+    return {"solves_per_s": r["solves_per_s"], "ms_per_step": r["ms"], "max_abs_err_vs_oracle": err,
+            "worst_resid_l2": r["worst_resid"], "t_kernel_ms": i0["t_kernel_ms"], "outer_its": i0["outer_its"],
+            "inner_its": i0["inner_its"]}
+
+
 def serve_stream(ssl, qs, np_, n_requests):
     """Serving stream of Kerr requests (cutoff N ~ U{10..60}, (Delta, E) on
     a 21 x 20 grid, seed 1): burst capacity (all arrive at t = 0) in both
@@ -152,7 +162,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 Kerr-chain measurements")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the Kerr serving stream (0 skips the serving measurement)")
-    ap.add_argument("--precs", default="mixed,fp64", help="precisions of the batched step")
+    ap.add_argument("--precs", default="mixed,fp64,fp64_refined",
+                    help="precisions of the batched step (fp64_refined: fp64 inner solves restarted from the "
+                         "fp64 residual at the mixed path's inner tolerance)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MB (the known-size reference for "
                          "the HBM counter runs)")
@@ -183,7 +195,8 @@ def main():
         device-resident H and collapse operators, then set-up and solve of
         all B together."""
         Ls = ssl.build_liouvillian_batch([(Hd, Cd)] * B)
-        _, infos = ssl.solve_batch(Ls, args.method, tol=1e-10, outs=outs, prec=prec)
+        kw = {"prec": "fp64", "inner_tol": 1e-4} if prec == "fp64_refined" else {"prec": prec}
+        _, infos = ssl.solve_batch(Ls, args.method, tol=1e-10, outs=outs, **kw)
         for L in Ls:
             L.free()
         return infos
@@ -219,7 +232,7 @@ def main():
 
     # single-solve latency (one system, the solver's own path choice)
     single = {}
-    for prec in precs:
+    for prec in [p for p in precs if p != "fp64_refined"]:
         ts = []
         for k in range(6):
             L = ssl.build_liouvillian(Hd, Cd)
@@ -319,6 +332,7 @@ def main():
 
     m = results["mixed"]
     f = results.get("fp64")
+    fr = results.get("fp64_refined")
     line = {
         "metric": "steady-state solves/sec + SpMV HBM GB/s at ||L.rho||<=1e-10, mixed vs FP64",
         "value": m["solves_per_s"],
@@ -337,9 +351,12 @@ def main():
                    "method": args.method, "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0", "batch": B},
         "max_abs_err_vs_oracle": err["mixed"],
         "worst_resid_l2": m["worst_resid"],
-        "fp64": ({"solves_per_s": f["solves_per_s"], "ms_per_step": f["ms"], "max_abs_err_vs_oracle": err["fp64"],
-                  "worst_resid_l2": f["worst_resid"], "t_kernel_ms": f["infos"][0]["t_kernel_ms"]} if f else None),
+        "fp64": _prec_summary(f, err.get("fp64")),
         "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"] if f else None,
+        # fp64 with the mixed path's refinement schedule: the difference to
+        # "mixed" is the precision of the inner solves alone
+        "fp64_refined": _prec_summary(fr, err.get("fp64_refined")),
+        "mixed_vs_fp64_refined": m["solves_per_s"] / fr["solves_per_s"] if fr else None,
         "single_solve": single,
         "roofline": roofline,
         "large": large,
