@@ -71,6 +71,22 @@ class _Info(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+_INFO_KEYS = [name for name, _ in _Info._fields_]
+
+
+def _info_dicts(infos, k: int) -> list:
+    """as_dict of the first k entries of an _Info array, read in one pass."""
+    if k == 0:
+        return []
+    rows = np.ctypeslib.as_array(infos)[:k].tolist()
+    out = []
+    for r in rows:
+        d = dict(zip(_INFO_KEYS, r))
+        del d["reserved"]
+        out.append(d)
+    return out
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with `python paper_1504_06768_amd/build.py` "
@@ -290,18 +306,29 @@ def build_liouvillian_batch(systems) -> list:
     k = len(systems)
     if k == 0:
         return []
-    keep = []
     Hs = (_Csr * k)()
     arrs = (ctypes.c_void_p * k)()
     ncs = (ctypes.c_int32 * k)()
+    # an operator object (or list of collapse operators) that appears in
+    # several systems is converted once; `systems` keeps every object alive
+    # for the call, so the identities stay unique
+    conv, lists = {}, {}
+
+    def host(m):
+        c = conv.get(id(m))
+        if c is None:
+            c = conv[id(m)] = _HostCsr(m)
+        return c
+
     for i, (H, c_ops) in enumerate(systems):
-        Hc = _HostCsr(H)
-        cs = [_HostCsr(c) for c in c_ops]
-        arr = (_Csr * max(len(cs), 1))(*[c.s for c in cs])
-        keep.append((Hc, cs, arr))
-        Hs[i] = Hc.s
-        arrs[i] = ctypes.cast(arr, ctypes.c_void_p) if cs else None
-        ncs[i] = len(cs)
+        ent = lists.get(id(c_ops))
+        if ent is None:
+            cs = [host(c) for c in c_ops]
+            arr = (_Csr * max(len(cs), 1))(*[c.s for c in cs])
+            ent = lists[id(c_ops)] = (cs, arr, ctypes.cast(arr, ctypes.c_void_p).value if cs else None, len(cs))
+        Hs[i] = host(H).s
+        arrs[i] = ent[2]
+        ncs[i] = ent[3]
     hs = (ctypes.c_void_p * k)()
     _check(_lib.ss_build_liouvillian_batch(k, Hs, arrs, ncs, hs), "ss_build_liouvillian_batch")
     return [Liouvillian(hs[i], int(Hs[i].n)) for i in range(k)]
@@ -351,7 +378,7 @@ def solve_batch(Ls, method="trace_bicgstab", tol: float = 1e-10, outs=None, rais
         ptrs = [b.ctypes.data for b in bufs]
     parr = (ctypes.c_void_p * max(k, 1))(*ptrs)
     rc = _lib.ss_solve_batch(handles, k, _method(method), float(tol), ctypes.byref(o), parr, infos, status)
-    ds = [infos[i].as_dict() for i in range(k)]
+    ds = _info_dicts(infos, k)
     if rc != SS_OK and raise_on_error:
         raise SolverError(rc, f"ss_solve_batch: {_err()}", ds)
     if outs is None:
