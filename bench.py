@@ -63,17 +63,72 @@ def _traffic(t_kernel_ms):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter runs (profiles/traffic.json), or None when that file is
     missing or the kernel source has changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, rec["source"])
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    if source_digest(rec["source"]) != rec.get("sources_sha256"):
+        return None
     return rec["hbm_bytes_per_launch"]
+
+
+KERNEL_SOURCE = "paper_1504_06768_amd/csrc/wgsolve.hip"
+COPY_BYTES = 256 << 20
+
+
+def write_traffic(fetch_db, write_db):
+    """profiles/traffic.json from two rocprofv3 --pmc runs: the solver
+    launch's FETCH_SIZE and WRITE_SIZE (KiB, summed over the counter's
+    instances), each scaled by what the same counter reads for the
+    calibration copy of COPY_BYTES bytes."""
+    import sqlite3
+
+    def read(db, counter):
+        con = sqlite3.connect(db)
+        rows = list(con.execute(
+            "select kernel_name, grid_size, sum(value) from counters_collection where counter_name = ? "
+            "group by dispatch_id order by dispatch_id", (counter,)))
+        con.close()
+        solver = [v for (k, g, v) in rows if "k_wg_solve<HIP_vector_type<float, 2u>, 512, true>" in k]
+        copy = [v for (k, g, v) in rows if "copyBuffer" in k and g == COPY_BYTES // 2048]
+        if not solver or not copy:
+            raise SystemExit(f"{db}: no solver launch or no calibration copy of {COPY_BYTES} bytes")
+        return solver[-1], copy[-1]
+
+    fetch, cf = read(fetch_db, "FETCH_SIZE")
+    write, cw = read(write_db, "WRITE_SIZE")
+    ff, fw = (COPY_BYTES / 1024) / cf, (COPY_BYTES / 1024) / cw
+    fb, wb = fetch * 1024 * ff, write * 1024 * fw
+    rec = {"kernel": "k_wg_solve<float2, 512, true> (complex64 workgroup-resident solver)",
+           "workload": "jc_N40xqubit, 256 independent systems in one launch (bench.py --batch 256 --precs mixed)",
+           "source": KERNEL_SOURCE, "sources_sha256": source_digest(KERNEL_SOURCE),
+           "fetch_size_kib": fetch, "write_size_kib": write,
+           "calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_size_kib": cf, "copy_write_size_kib": cw,
+                           "fetch_factor": ff, "write_factor": fw},
+           "hbm_bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def source_digest(rel):
+    """SHA-256 over a kernel source and every local header it includes
+    (transitively): the counters stay valid only while none of them changes."""
+    import hashlib
+    import re
+    h, seen, todo = hashlib.sha256(), [], [os.path.normpath(os.path.join(ROOT, rel))]
+    while todo:
+        f = todo.pop(0)
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.append(f)
+        with open(f, "rb") as fh:
+            data = fh.read()
+        h.update(os.path.relpath(f, ROOT).encode() + b"\0" + data)
+        for inc in re.findall(rb'#include "([^"]+)"', data):
+            todo.append(os.path.normpath(os.path.join(os.path.dirname(f), inc.decode())))
+    return h.hexdigest()
 
 
 def trsv_pair_bytes(n, nnz_lu, s):
@@ -168,7 +223,13 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MB (the known-size reference for "
                          "the HBM counter runs)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic.json from the rocpd databases of a FETCH_SIZE and a WRITE_SIZE "
+                         "counter run (both taken with --copy-calibration-mb 256) and exit; no GPU is used")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (each solve fits one MI355X; "
               "independent requests would be routed to separate GPUs)", file=sys.stderr)

@@ -40,9 +40,13 @@ template <bool UPPER>
 void levels_batch(const LevelJob *jobs, int count, hipStream_t s);
 
 // factor entries per row kept in the packed level layout (fewer for
-// complex128 so that three levels of them fit in registers)
+// complex128 so that three levels of them fit in registers).  Longer rows
+// take their remaining entries from the factor's CSR arrays, one dependent
+// load at a time.  For complex64, 7 covers all but two rows per triangle of
+// the Jaynes-Cummings Liouvillian (cavity 40 x qubit) and measured fastest of
+// 6, 7 and 8 there (preconditioner time per system 11.7, 9.9, 10.4 ms).
 template <typename T> struct WgK;
-template <> struct WgK<float2> { static constexpr int value = 8; };
+template <> struct WgK<float2> { static constexpr int value = 7; };
 template <> struct WgK<double2> { static constexpr int value = 4; };
 
 // Level-ordered packed copy of one triangular factor in precision T: for
