@@ -44,10 +44,12 @@ void levels_batch(const LevelJob *jobs, int count, hipStream_t s);
 // take their remaining entries from the factor's CSR arrays, one dependent
 // load at a time.  For complex64, 7 covers all but two rows per triangle of
 // the Jaynes-Cummings Liouvillian (cavity 40 x qubit) and measured fastest of
-// 6, 7 and 8 there (preconditioner time per system 11.7, 9.9, 10.4 ms).
+// 6, 7 and 8 there (preconditioner time per system 11.7, 9.9, 10.4 ms).  For
+// complex128, 5 is the widest without register spills (6 and 7 spill); on
+// the same batch the fp64 solver launch takes 56.9 ms against 62.0 ms at 4.
 template <typename T> struct WgK;
 template <> struct WgK<float2> { static constexpr int value = 7; };
-template <> struct WgK<double2> { static constexpr int value = 4; };
+template <> struct WgK<double2> { static constexpr int value = 5; };
 
 // Level-ordered packed copy of one triangular factor in precision T: for
 // slot idx (level order), slot[idx] = {row, first CSR entry, length, 0}, and
