@@ -38,6 +38,14 @@ __global__ void __launch_bounds__(256) k_bt_scalars(const ScalarJob *jobs) {
     double2 w = mk(J.weight, 0.0);
     if (J.weight == 0.0) {
         for (int b = 0; b < 256; ++b) {
+            if (b * 256 >= J.n) {
+                // no row falls to this partial: its sum is +0.0, as computed
+                if (t == 0) {
+                    px[b] = 0.0;
+                    py[b] = 0.0;
+                }
+                continue;
+            }
             double ax = 0, ay = 0;
             for (int r = b * 256 + t; r < J.n; r += 256 * 256) {
                 int lo = J.L.rowptr[r], hi = J.L.rowptr[r + 1] - 1;
@@ -104,21 +112,41 @@ __global__ void __launch_bounds__(256) k_bt_modify(const ModJob *jobs, const int
         else J.rowptr[r] = shift_row<false>(r, rp, J.L.col, J.L.val, J.sigma, nullptr, nullptr);
         return;
     }
+    // trace-row transform: row lengths only (k_bt_trace_row and k_bt_copy fill)
+    if (FILL) return;
     const int rt = *J.trow;
-    if (r == rt) {
-        if (FILL) trace_row0<true>(J.d, rt, rp, J.L.col, J.L.val, *J.w, J.col + J.rowptr[r], J.val + J.rowptr[r]);
-        else J.rowptr[r] = trace_row0<false>(J.d, rt, rp, J.L.col, J.L.val, *J.w, nullptr, nullptr);
-        return;
+    J.rowptr[r] = (r == rt) ? trace_row0<false>(J.d, rt, rp, J.L.col, J.L.val, *J.w, nullptr, nullptr)
+                            : rp[r + 1] - rp[r];
+}
+
+// Trace-row transform, fill, of the trace row itself (one thread per system;
+// a trace row index outside the matrix leaves every row as it is).
+__global__ void __launch_bounds__(256) k_bt_trace_row(const ModJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const ModJob &J = jobs[jb];
+    if (threadIdx.x != 0 || J.n == 0) return;
+    const int rt = *J.trow;
+    if (rt < 0 || rt >= J.n) return;
+    trace_row0<true>(J.d, rt, J.L.rowptr, J.L.col, J.L.val, *J.w, J.col + J.rowptr[rt], J.val + J.rowptr[rt]);
+}
+
+// Trace-row transform, fill, of every other row: an unchanged copy, one
+// thread per entry (coalesced).  Rows before the trace row keep their
+// positions; rows after it move by the trace row's change of length.
+__global__ void __launch_bounds__(256) k_bt_copy(const ModJob *jobs, const int *bstart, int njobs) {
+    const int jb = job_of_block(bstart, njobs, blockIdx.x);
+    const ModJob &J = jobs[jb];
+    const int e = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
+    if (e >= J.L.nnz) return;
+    const int rt = *J.trow;
+    int dest = e;
+    if (rt >= 0 && rt < J.n) {
+        const int a = J.L.rowptr[rt], b = J.L.rowptr[rt + 1];
+        if (e >= a && e < b) return;
+        if (e >= b) dest = e + (J.rowptr[rt + 1] - J.rowptr[rt]) - (b - a);
     }
-    if (!FILL) {
-        J.rowptr[r] = rp[r + 1] - rp[r];
-        return;
-    }
-    const int o = J.rowptr[r];
-    for (int e = rp[r]; e < rp[r + 1]; ++e) {
-        J.col[o + e - rp[r]] = J.L.col[e];
-        J.val[o + e - rp[r]] = J.L.val[e];
-    }
+    J.col[dest] = J.L.col[e];
+    J.val[dest] = J.L.val[e];
 }
 
 struct PatJob {
@@ -223,7 +251,14 @@ void transform_batch(ss_liouv *hs, int count, bool trace, const ss_options &o, h
     }
     launch_rows(k_bt_modify<false>, mj, rblocks, s);
     seg_scan(scA, s);
-    launch_rows(k_bt_modify<true>, mj, rblocks, s);
+    if (trace) {
+        std::vector<int> one((size_t)count, 1), eblocks((size_t)count);
+        for (int k = 0; k < count; ++k) eblocks[(size_t)k] = div_up(hs[k]->L.nnz, 256);
+        launch_rows(k_bt_trace_row, mj, one, s);
+        launch_rows(k_bt_copy, mj, eblocks, s);
+    } else {
+        launch_rows(k_bt_modify<true>, mj, rblocks, s);
+    }
 
     // A^T (pattern) in one arena, then S = A + A^T
     std::vector<size_t> off((size_t)count + 1, 0);
