@@ -249,11 +249,15 @@ __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs,
     const Ilu0Job &J = jobs[blockIdx.x];
     const int g = threadIdx.x / ILU_LG, lane = threadIdx.x % ILU_LG;
     constexpr int NG = ILU_LVL_BS / ILU_LG;
+    // the next level's end is fetched a level ahead, and a lower slot holds
+    // {row, row start, pivot position, row end}: a row's bounds come with
+    // its slot
+    int s0 = J.nlev > 0 ? gld(J.lptr) : 0, s1 = J.nlev > 0 ? gld(J.lptr + 1) : 0;
     for (int lv = 0; lv < J.nlev; ++lv) {
-        const int s0 = gld(J.lptr + lv), s1 = gld(J.lptr + lv + 1);
+        const int s2 = (lv + 2 <= J.nlev) ? gld(J.lptr + lv + 2) : 0;
         for (int sl = s0 + g; sl < s1; sl += NG) {
-            const int row = gld(J.lslot + sl).x;
-            const int rs = gld(J.rowptr + row), re = gld(J.rowptr + row + 1), dg = gld(J.diag + row);
+            const int4 slot = gld(J.lslot + sl);
+            const int row = slot.x, rs = slot.y, dg = slot.z, re = slot.w;
             const int nl = dg - rs;  // entries before the pivot: the rows k this row eliminates with
             bool fast = (re - rs <= ILU_LG * ILU_FM) && nl <= ILU_FK;
             // the row in registers: entry rs + lane + ILU_LG m in slot m
@@ -359,6 +363,8 @@ __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs,
             }
         }
         __syncthreads();
+        s0 = s1;
+        s1 = s2;
     }
 }
 

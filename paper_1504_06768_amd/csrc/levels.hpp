@@ -7,7 +7,9 @@
 namespace ss {
 
 // Level schedule of one triangular factor: slots in level order, each slot
-// {row, first entry, end entry, 0}; levels delimited by ptr.
+// {row, first entry, end entry, w} with w the row's end in the factor for
+// the lower side (the ILU(0) of a batch reads it) and 0 for the upper side;
+// levels delimited by ptr.
 struct LevelSched {
     int nlev = 0;
     DevBuf<int> ptr;    // nlev + 1

@@ -479,7 +479,8 @@ __global__ void __launch_bounds__(256) k_bt_levels(const SideJob *jobs, const in
         return;
     }
     const int pos = atomicAdd(&J.cnt[J.lvl[i]], 1);
-    J.slot[pos] = J.upper ? make_int4(i, J.diag[i] + 1, J.rowptr[i + 1], 0) : make_int4(i, J.rowptr[i], J.diag[i], 0);
+    J.slot[pos] = J.upper ? make_int4(i, J.diag[i] + 1, J.rowptr[i + 1], 0)
+                          : make_int4(i, J.rowptr[i], J.diag[i], J.rowptr[i + 1]);
 }
 
 template <typename T>

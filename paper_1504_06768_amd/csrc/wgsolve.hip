@@ -216,7 +216,7 @@ __global__ void k_level_scatter(int n, const int *rowptr, const int *diag, const
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int pos = atomicAdd(&cursor[lvl[i]], 1);
-    slot[pos] = UPPER ? make_int4(i, diag[i] + 1, rowptr[i + 1], 0) : make_int4(i, rowptr[i], diag[i], 0);
+    slot[pos] = UPPER ? make_int4(i, diag[i] + 1, rowptr[i + 1], 0) : make_int4(i, rowptr[i], diag[i], rowptr[i + 1]);
 }
 
 __global__ void k_fill_i32(int n, int *p, int v) {
