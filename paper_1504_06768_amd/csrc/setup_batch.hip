@@ -336,24 +336,28 @@ struct PermJob {
 // STEP 0: row lengths; 1: rows (a wavefront each, columns mapped through
 // iperm and rank-sorted as in k_perm_fill); 2: diagonal positions, trace
 // positions and q0.
+constexpr int PERM_G = 16;  // lanes per row in the permutation's fill (rows up to 16 entries in one pass)
+
 template <int STEP>
 __global__ void __launch_bounds__(256) k_bt_permute(const PermJob *jobs, const int *bstart, int njobs) {
     const int jb = job_of_block(bstart, njobs, blockIdx.x);
     const PermJob &J = jobs[jb];
     if (STEP == 1) {
-        const int lane = threadIdx.x & 63;
-        const int q = (blockIdx.x - bstart[jb]) * 4 + (threadIdx.x >> 6);
-        if (q >= J.n) return;  // (wave-uniform)
+        // PERM_G lanes per row, 256 / PERM_G rows per workgroup
+        const int lane = threadIdx.x & (PERM_G - 1);
+        const int q = (blockIdx.x - bstart[jb]) * (256 / PERM_G) + (int)(threadIdx.x / PERM_G);
+        if (q >= J.n) return;  // (uniform over the row's lanes)
         const int r = gld(J.perm + q);
         const int rs = gld(J.A.rowptr + r), re = gld(J.A.rowptr + r + 1);
         const int o = gld(J.prow + q);
-        if (re - rs <= 64) {
+        if (re - rs <= PERM_G) {
             // the whole row in one pass: each lane maps its own column, the
-            // ranks come from the other lanes' values by shuffle
+            // ranks come from the other lanes' values by shuffle (the trip
+            // count is the same for all lanes of the row)
             const int e = rs + lane;
             const int c = (e < re) ? gld(J.iperm + gld(J.A.col + e)) : 0x7fffffff;
             int rank = 0;
-            for (int f = 0; f < re - rs; ++f) rank += (__shfl(c, f, 64) < c);
+            for (int f = 0; f < re - rs; ++f) rank += (__shfl(c, f, PERM_G) < c);
             if (e < re) {
                 J.pcol[o + rank] = c;
                 J.pval[o + rank] = gld(J.A.val + e);
@@ -364,10 +368,10 @@ __global__ void __launch_bounds__(256) k_bt_permute(const PermJob *jobs, const i
             }
             return;
         }
-        for (int e = rs + lane; e < re; e += 64) {
-            const int c = J.iperm[J.A.col[e]];
+        for (int e = rs + lane; e < re; e += PERM_G) {
+            const int c = gld(J.iperm + gld(J.A.col + e));
             int rank = 0;
-            for (int f = rs; f < re; ++f) rank += (J.iperm[J.A.col[f]] < c);
+            for (int f = rs; f < re; ++f) rank += (gld(J.iperm + gld(J.A.col + f)) < c);
             J.pcol[o + rank] = c;
             J.pval[o + rank] = J.A.val[e];
             if (J.lucol) {
@@ -438,7 +442,7 @@ void permute_batch(ss_liouv *hs, int count, bool ilu0, hipStream_t s, std::vecto
         p.missing = meta.get() + k;
         p.q0 = meta.get() + count + k;
         rblocks[(size_t)k] = div_up(h->n, 256);
-        wblocks[(size_t)k] = div_up(h->n, 4);
+        wblocks[(size_t)k] = div_up(h->n, 256 / PERM_G);
         sc[(size_t)k] = ScanJob{p.prow, h->n, nullptr, ilu0 ? h->LU.rowptr.get() : nullptr};
     }
     launch_rows(k_bt_permute<0>, pj, rblocks, s);
