@@ -118,25 +118,26 @@ __device__ inline int union_row(int r, const int *ar, const int *ac, const int *
     return o;
 }
 
-// One wavefront sorts the entries [rs, re) by column (unique within a row):
-// rank sort, so the result does not depend on the order of the input.
-template <typename T>
+// A group of G lanes (a whole wavefront by default) sorts the entries
+// [rs, re) by column (unique within a row): rank sort, so the result does
+// not depend on the order of the input.
+template <typename T, int G = 64>
 __device__ inline void sort_row_wave(int rs, int re, const int *col_in, const T *val_in, int *col_out, T *val_out) {
-    const int lane = threadIdx.x & 63;
-    if (re - rs <= 64) {
-        // one pass: ranks from the other lanes' columns by shuffle (the
-        // whole wavefront calls this with the same row)
+    const int lane = threadIdx.x & (G - 1);
+    if (re - rs <= G) {
+        // one pass: ranks from the other lanes' columns by shuffle (all G
+        // lanes call this with the same row)
         const int e = rs + lane;
         const int c = (e < re) ? col_in[e] : 0x7fffffff;
         int rank = 0;
-        for (int f = 0; f < re - rs; ++f) rank += (__shfl(c, f, 64) < c);
+        for (int f = 0; f < re - rs; ++f) rank += (__shfl(c, f, G) < c);
         if (e < re) {
             col_out[rs + rank] = c;
             if (val_in) val_out[rs + rank] = val_in[e];
         }
         return;
     }
-    for (int e = rs + lane; e < re; e += 64) {
+    for (int e = rs + lane; e < re; e += G) {
         const int c = col_in[e];
         int rank = 0;
         for (int f = rs; f < re; ++f) rank += (col_in[f] < c);

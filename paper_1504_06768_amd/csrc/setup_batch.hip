@@ -169,8 +169,9 @@ __global__ void __launch_bounds__(256) k_bt_pattern(const PatJob *jobs, const in
     const int jb = job_of_block(bstart, njobs, blockIdx.x);
     const PatJob &J = jobs[jb];
     if (STEP == 2) {
-        const int row = (blockIdx.x - bstart[jb]) * 4 + (threadIdx.x >> 6);
-        if (row < J.n) sort_row_wave<int>(J.trow[row], J.trow[row + 1], J.tcol_raw, nullptr, J.tcol, nullptr);
+        // 16 lanes per row of A^T (rows up to 16 entries sorted in one pass)
+        const int row = (blockIdx.x - bstart[jb]) * 16 + (int)(threadIdx.x >> 4);
+        if (row < J.n) sort_row_wave<int, 16>(J.trow[row], J.trow[row + 1], J.tcol_raw, nullptr, J.tcol, nullptr);
         return;
     }
     const int r = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
@@ -246,7 +247,7 @@ void transform_batch(ss_liouv *hs, int count, bool trace, const ss_options &o, h
         mj[(size_t)k] = ModJob{h->n, h->d, h->L.view(), trace ? 1 : 0, o.sigma, h->d_w.get(), m_trow + k,
                                h->A.rowptr.get(), h->A.col.get(), h->A.val.get()};
         rblocks[(size_t)k] = div_up(h->n, 256);
-        wblocks[(size_t)k] = div_up(h->n, 4);
+        wblocks[(size_t)k] = div_up(h->n, 16);
         scA[(size_t)k] = ScanJob{h->A.rowptr.get(), h->n, m_nnzA + k, nullptr};
     }
     launch_rows(k_bt_modify<false>, mj, rblocks, s);
