@@ -473,17 +473,35 @@ struct SideJob {
 
 // STEP 0: rows per level; 1: scatter the rows into level order (the order
 // inside a level does not matter: its rows are independent).
+// atomicAdd(cnt + key, 1) for every active lane of the wavefront, with one
+// atomic per distinct key: the lanes sharing a key take consecutive values in
+// lane order (rows of one level sit close together in the ordering, so a
+// wavefront holds few distinct levels).
+__device__ inline int wave_claim(int *cnt, int key) {
+    const int lane = threadIdx.x & 63;
+    int pos = 0;
+    unsigned long long todo = __ballot(1);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int k = __shfl(key, leader, 64);
+        const unsigned long long m = __ballot(key == k) & todo;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(cnt + k, __popcll(m));
+        base = __shfl(base, leader, 64);
+        if ((m >> lane) & 1ull) pos = base + __popcll(m & ((1ull << lane) - 1ull));
+        todo &= ~m;
+    }
+    return pos;
+}
+
 template <int STEP>
 __global__ void __launch_bounds__(256) k_bt_levels(const SideJob *jobs, const int *bstart, int njobs) {
     const int jb = job_of_block(bstart, njobs, blockIdx.x);
     const SideJob &J = jobs[jb];
     const int i = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
     if (i >= J.n) return;
-    if (STEP == 0) {
-        atomicAdd(&J.cnt[J.lvl[i]], 1);
-        return;
-    }
-    const int pos = atomicAdd(&J.cnt[J.lvl[i]], 1);
+    const int pos = wave_claim(J.cnt, J.lvl[i]);
+    if (STEP == 0) return;
     J.slot[pos] = J.upper ? make_int4(i, J.diag[i] + 1, J.rowptr[i + 1], 0)
                           : make_int4(i, J.rowptr[i], J.diag[i], J.rowptr[i + 1]);
 }
