@@ -118,6 +118,47 @@ __device__ inline int union_row(int r, const int *ar, const int *ac, const int *
     return o;
 }
 
+// The same union by a group of G lanes when each row has at most G entries
+// (rows [as, as + na) of ac and [bs, bs + nb) of bc, columns sorted and
+// unique within each): lane t holds entry t of both rows, and each output
+// position is counted from the other lanes' columns by shuffle.  An entry of
+// the first row lands at its index plus the entries of the second row below
+// it that the first row lacks; such an entry of the second row lands at the
+// entries of the first row below it plus those of its own row before it.
+// Returns the union's length on every lane; with FILL it is written to ocol
+// (and 1 to oval).  All G lanes call this with the same rows.
+template <bool FILL, int G>
+__device__ inline int union_row_group(int as, int na, int bs, int nb, const int *ac, const int *bc, int *ocol,
+                                      double2 *oval) {
+    const int t = threadIdx.x & (G - 1);
+    const int x = (t < na) ? ac[as + t] : 0x7fffffff;
+    const int y = (t < nb) ? bc[bs + t] : 0x7fffffff;
+    int dup = 0;  // y is also in the first row
+    for (int v = 0; v < na; ++v) dup |= (__shfl(x, v, G) == y);
+    dup &= (t < nb);
+    int ndup = 0, bx = 0, before = 0, ay = 0;
+    for (int u = 0; u < nb; ++u) {
+        const int yu = __shfl(y, u, G);
+        const int du = __shfl(dup, u, G);
+        ndup += du;
+        bx += (!du && yu < x);
+        before += (du && u < t);
+    }
+    for (int v = 0; v < na; ++v) ay += (__shfl(x, v, G) < y);
+    if (FILL) {
+        if (t < na) {
+            ocol[t + bx] = x;
+            if (oval) oval[t + bx] = mk(1.0, 0.0);
+        }
+        if (t < nb && !dup) {
+            const int p = ay + (t - before);
+            ocol[p] = y;
+            if (oval) oval[p] = mk(1.0, 0.0);
+        }
+    }
+    return na + nb - ndup;
+}
+
 // A group of G lanes (a whole wavefront by default) sorts the entries
 // [rs, re) by column (unique within a row): rank sort, so the result does
 // not depend on the order of the input.

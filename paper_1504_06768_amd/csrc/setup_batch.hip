@@ -174,16 +174,27 @@ __global__ void __launch_bounds__(256) k_bt_pattern(const PatJob *jobs, const in
         if (row < J.n) sort_row_wave<int, 16>(J.trow[row], J.trow[row + 1], J.tcol_raw, nullptr, J.tcol, nullptr);
         return;
     }
+    if (STEP == 4) {
+        // S = A + A^T filled row by row: 16 lanes per row, rows of up to 16
+        // entries on both sides merged by shuffle, longer ones by one lane
+        // (the counting pass stays one thread per row: it writes one value)
+        const int r = (blockIdx.x - bstart[jb]) * 16 + (int)(threadIdx.x >> 4);
+        if (r >= J.n) return;  // (uniform over the row's lanes)
+        const int as = J.arow[r], na = J.arow[r + 1] - as, bs = J.trow[r], nb = J.trow[r + 1] - bs;
+        if (na <= 16 && nb <= 16)
+            union_row_group<true, 16>(as, na, bs, nb, J.acol, J.tcol, J.scol + J.srow[r], J.sval + J.srow[r]);
+        else if ((threadIdx.x & 15) == 0)
+            union_row<true>(r, J.arow, J.acol, J.trow, J.tcol, J.scol + J.srow[r], J.sval + J.srow[r]);
+        return;
+    }
     const int r = (blockIdx.x - bstart[jb]) * 256 + threadIdx.x;
     if (r >= J.n) return;
     if (STEP == 0) {
         for (int e = J.arow[r]; e < J.arow[r + 1]; ++e) atomicAdd(&J.trow[J.acol[e]], 1);
     } else if (STEP == 1) {
         for (int e = J.arow[r]; e < J.arow[r + 1]; ++e) J.tcol_raw[atomicAdd(&J.cursor[J.acol[e]], 1)] = r;
-    } else if (STEP == 3) {
-        J.srow[r] = union_row<false>(r, J.arow, J.acol, J.trow, J.tcol, nullptr, nullptr);
     } else {
-        union_row<true>(r, J.arow, J.acol, J.trow, J.tcol, J.scol + J.srow[r], J.sval + J.srow[r]);
+        J.srow[r] = union_row<false>(r, J.arow, J.acol, J.trow, J.tcol, nullptr, nullptr);
     }
 }
 
@@ -292,7 +303,7 @@ void transform_batch(ss_liouv *hs, int count, bool trace, const ss_options &o, h
     launch_rows(k_bt_pattern<2>, pj, wblocks, s);
     launch_rows(k_bt_pattern<3>, pj, rblocks, s);
     seg_scan(scS, s);
-    launch_rows(k_bt_pattern<4>, pj, rblocks, s);
+    launch_rows(k_bt_pattern<4>, pj, wblocks, s);
 
     // the one host wait: sizes, trace rows and weights
     std::vector<int> hm((size_t)3 * count);
