@@ -77,7 +77,7 @@ KERNEL_SOURCE = "paper_1504_06768_amd/csrc/wgsolve.hip"
 COPY_BYTES = 256 << 20
 
 
-def write_traffic(fetch_db, write_db):
+def write_traffic(fetch_db, write_db, out_path=None, root=None):
     """profiles/traffic.json from two rocprofv3 --pmc runs: the solver
     launch's FETCH_SIZE and WRITE_SIZE (KiB, summed over the counter's
     instances), each scaled by what the same counter reads for the
@@ -102,22 +102,24 @@ def write_traffic(fetch_db, write_db):
     fb, wb = fetch * 1024 * ff, write * 1024 * fw
     rec = {"kernel": "k_wg_solve<float2, 512, true> (complex64 workgroup-resident solver)",
            "workload": "jc_N40xqubit, 256 independent systems in one launch (bench.py --batch 256 --precs mixed)",
-           "source": KERNEL_SOURCE, "sources_sha256": source_digest(KERNEL_SOURCE),
+           "source": KERNEL_SOURCE, "sources_sha256": source_digest(KERNEL_SOURCE, root),
            "fetch_size_kib": fetch, "write_size_kib": write,
            "calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_size_kib": cf, "copy_write_size_kib": cw,
                            "fetch_factor": ff, "write_factor": fw},
            "hbm_bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
+    return rec
 
 
-def source_digest(rel):
+def source_digest(rel, root=None):
     """SHA-256 over a kernel source and every local header it includes
     (transitively): the counters stay valid only while none of them changes."""
     import hashlib
     import re
-    h, seen, todo = hashlib.sha256(), [], [os.path.normpath(os.path.join(ROOT, rel))]
+    root = root or ROOT
+    h, seen, todo = hashlib.sha256(), [], [os.path.normpath(os.path.join(root, rel))]
     while todo:
         f = todo.pop(0)
         if f in seen or not os.path.exists(f):
@@ -125,7 +127,7 @@ def source_digest(rel):
         seen.append(f)
         with open(f, "rb") as fh:
             data = fh.read()
-        h.update(os.path.relpath(f, ROOT).encode() + b"\0" + data)
+        h.update(os.path.relpath(f, root).encode() + b"\0" + data)
         for inc in re.findall(rb'#include "([^"]+)"', data):
             todo.append(os.path.normpath(os.path.join(os.path.dirname(f), inc.decode())))
     return h.hexdigest()
