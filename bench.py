@@ -1,27 +1,37 @@
 #!/usr/bin/env python3
 """Steady-state solver benchmark on one MI355X.
 
-Workload (default): the driven Jaynes-Cummings system, cavity N = 40 x qubit
-(Hilbert dimension 80, Liouvillian 6400 x 6400), parameters (g, E, Delta_c,
-omega_a, kappa, gamma) drawn from a seeded uniform [0.1, 2]; synthetic, no
-data files.  One step = --batch independent solves through the C ABI, each
-the whole path: Liouvillian assembly from H and the collapse operators
-already resident in HBM, trace-row transform, RCM, ILU(0), then all systems
-solved together by the workgroup-resident solver (preconditioned BiCGSTAB
-with fp64 refinement, one workgroup per system), finish (unpermute,
-normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
+Headline workload: the chain of three coupled driven Kerr cavities, N = 10
+each (Hilbert dimension 1000, Liouvillian 10^6 x 10^6 with 20.7 M non-zeros),
+hopping J = 0.3; synthetic, no data files.  One step = one full solve through
+the C ABI: Liouvillian assembly from H and the collapse operators already
+resident in HBM, shift transform, RCM, ILU(0), the doubly-iterative inverse-
+power method (fp64 outer steps, preconditioned BiCGSTAB inner solves), finish
+(unpermute, normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
 
-Prints one JSON line: solves/s of the mixed-precision path (value) next to
-the fp64 path, single-solve latency, the roofline position of the dominant
-kernel (timed live with HIP events), the SpMV bandwidth and inverse-power
-solve times on the Kerr-chain matrix (n = 10^6), the serving stream (burst
-capacity, Poisson p50/p99) and the CPU oracle (dense LU) on the host cores.
+`value` is fp64 solves/s (complex128 throughout); the mixed path (complex64
+inner solves and factors, fp64 outer steps) is timed beside it on the same
+GPU.  Every result is checked against the oracle: for this size the CPU fp64
+sparse reference (RCM-ordered ILU(0)-BiCGSTAB on the trace-row system, one
+CPU thread), which is also the timed CPU baseline.
+
+Secondary measurements, each recorded inside the one JSON line (a failure
+is recorded there too, and makes the exit status non-zero):
+  * the SpMV of the same matrix in complex128 and complex64 (GB/s) and the
+    matrix-free L x;
+  * a batched step of 256 seeded Jaynes-Cummings systems (cavity 40 x qubit,
+    n = 6400, each with its own parameter draw), mixed and fp64;
+  * the driven spin chain (8 spins) with the automatic method choice;
+  * the serving stream (2000 Kerr requests): burst capacity in both
+    precisions and Poisson arrivals at 0.5, 1 and 2 times that capacity,
+    with p50/p99 submit-to-result latency.
 """
 import argparse
 import json
 import os
 import sys
 import time
+import traceback
 
 import numpy as np
 
@@ -36,7 +46,6 @@ def _log(*a):
 
 
 def _device_csr(m, torch):
-    import numpy as np
     import scipy.sparse as sp
     A = sp.csr_matrix(m, dtype=np.complex128)
     A.sort_indices()
@@ -52,6 +61,13 @@ def spmv_bytes(n, nnz, s):
     return nnz * (s + 4) + 4 * (n + 1) + 2 * n * s
 
 
+def trsv_pair_bytes(n, nnz_lu, s):
+    """Algorithmic bytes of one L-solve + U-solve pair: factor values and
+    indices once, row pointers and diagonal positions for both sweeps, and
+    right-hand side, intermediate and result vectors."""
+    return nnz_lu * (s + 4) + 8 * (n + 1) + 8 * n + 4 * n * s
+
+
 def apply_l_bytes(n):
     """Algorithmic bytes of one matrix-free application of L: rho read once
     and the result written once (complex128); the d x d operators are a few
@@ -59,58 +75,14 @@ def apply_l_bytes(n):
     return 32 * n
 
 
-def _traffic(t_kernel_ms):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter runs (profiles/traffic.json), or None when that file is
-    missing or the kernel source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    if source_digest(rec["source"]) != rec.get("sources_sha256"):
-        return None
-    return rec["hbm_bytes_per_launch"]
-
-
-KERNEL_SOURCE = "paper_1504_06768_amd/csrc/wgsolve.hip"
+# ------------------------------------------------------------------ traffic
+# HBM bytes of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE), each scaled by what the same counter reads for a plain
+# copy of COPY_BYTES bytes.  The record names the kernel and the SHA-256 of
+# its sources; it is used only while both still match.
+KERNEL_SOURCE = "paper_1504_06768_amd/csrc/ilu.hip"
+KERNEL_MATCH = "k_trsv_"
 COPY_BYTES = 256 << 20
-
-
-def write_traffic(fetch_db, write_db, out_path=None, root=None):
-    """profiles/traffic.json from two rocprofv3 --pmc runs: the solver
-    launch's FETCH_SIZE and WRITE_SIZE (KiB, summed over the counter's
-    instances), each scaled by what the same counter reads for the
-    calibration copy of COPY_BYTES bytes."""
-    import sqlite3
-
-    def read(db, counter):
-        con = sqlite3.connect(db)
-        rows = list(con.execute(
-            "select kernel_name, grid_size, sum(value) from counters_collection where counter_name = ? "
-            "group by dispatch_id order by dispatch_id", (counter,)))
-        con.close()
-        solver = [v for (k, g, v) in rows if "k_wg_solve<HIP_vector_type<float, 2u>, 512, true>" in k]
-        copy = [v for (k, g, v) in rows if "copyBuffer" in k and g == COPY_BYTES // 2048]
-        if not solver or not copy:
-            raise SystemExit(f"{db}: no solver launch or no calibration copy of {COPY_BYTES} bytes")
-        return solver[-1], copy[-1]
-
-    fetch, cf = read(fetch_db, "FETCH_SIZE")
-    write, cw = read(write_db, "WRITE_SIZE")
-    ff, fw = (COPY_BYTES / 1024) / cf, (COPY_BYTES / 1024) / cw
-    fb, wb = fetch * 1024 * ff, write * 1024 * fw
-    rec = {"kernel": "k_wg_solve<float2, 512, true> (complex64 workgroup-resident solver)",
-           "workload": "jc_N40xqubit, 256 independent systems in one launch (bench.py --batch 256 --precs mixed)",
-           "source": KERNEL_SOURCE, "sources_sha256": source_digest(KERNEL_SOURCE, root),
-           "fetch_size_kib": fetch, "write_size_kib": write,
-           "calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_size_kib": cf, "copy_write_size_kib": cw,
-                           "fetch_factor": ff, "write_factor": fw},
-           "hbm_bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
-    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
-        json.dump(rec, f, indent=1)
-    print(json.dumps(rec, indent=1))
-    return rec
 
 
 def source_digest(rel, root=None):
@@ -133,53 +105,281 @@ def source_digest(rel, root=None):
     return h.hexdigest()
 
 
-def trsv_pair_bytes(n, nnz_lu, s):
-    """Algorithmic bytes of one L-solve + U-solve pair: factor values and
-    indices once, row pointers and diagonal positions for both sweeps, and
-    right-hand side, intermediate and result vectors."""
-    return nnz_lu * (s + 4) + 8 * (n + 1) + 8 * n + 4 * n * s
+def write_traffic(fetch_db, write_db, out_path=None, root=None, match=KERNEL_MATCH, source=KERNEL_SOURCE,
+                  workload="kerr_chain_3x10 fp64 inverse power (bench.py headline step)"):
+    """profiles/traffic.json from two rocprofv3 --pmc runs: FETCH_SIZE and
+    WRITE_SIZE (KiB, summed over the counter's instances) of every dispatch
+    whose kernel name contains `match`, averaged per dispatch, each scaled by
+    what the same counter reads for the calibration copy of COPY_BYTES."""
+    import sqlite3
+
+    def read(db, counter):
+        con = sqlite3.connect(db)
+        rows = list(con.execute(
+            "select kernel_name, grid_size, sum(value) from counters_collection where counter_name = ? "
+            "group by dispatch_id order by dispatch_id", (counter,)))
+        con.close()
+        kern = [v for (k, g, v) in rows if match in k]
+        copy = [v for (k, g, v) in rows if "copyBuffer" in k and g == COPY_BYTES // 2048]
+        if not kern or not copy:
+            raise SystemExit(f"{db}: no dispatch of {match} or no calibration copy of {COPY_BYTES} bytes")
+        return float(np.mean(kern)), copy[-1], len(kern)
+
+    fetch, cf, nf = read(fetch_db, "FETCH_SIZE")
+    write, cw, nw = read(write_db, "WRITE_SIZE")
+    ff, fw = (COPY_BYTES / 1024) / cf, (COPY_BYTES / 1024) / cw
+    fb, wb = fetch * 1024 * ff, write * 1024 * fw
+    rec = {"kernel_match": match, "workload": workload, "source": source,
+           "sources_sha256": source_digest(source, root), "dispatches": {"fetch": nf, "write": nw},
+           "fetch_size_kib": fetch, "write_size_kib": write,
+           "calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_size_kib": cf, "copy_write_size_kib": cw,
+                           "fetch_factor": ff, "write_factor": fw},
+           "hbm_bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+    return rec
+
+
+def _traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record, or None when it is missing, names another kernel, or its sources
+    have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_match") != KERNEL_MATCH or rec.get("source") != KERNEL_SOURCE:
+        return None
+    if source_digest(rec["source"]) != rec.get("sources_sha256"):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+# ---------------------------------------------------------------- headline
+def headline(ssl, qs, torch, args):
+    """Full C4 solves, fp64 and mixed: per-step times, iteration counts,
+    residuals; rho of the last step of each precision (host copy)."""
+    ch = qs.config(4)
+    N = ch.dim
+    Hd = _device_csr(ch.H, torch)
+    Cd = [_device_csr(c, torch) for c in ch.c_ops]
+    out = torch.empty(N * N, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(prec):
+        L = ssl.build_liouvillian(Hd, Cd)
+        _, info = ssl.solve(L, "invpow_bicgstab", tol=1e-10, out=out, prec=prec)
+        L.free()
+        return info
+
+    res = {}
+    for prec in ("fp64", "mixed"):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        times, infos = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            infos.append(step(prec))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rho = out.cpu().numpy().reshape(N, N, order="F")
+        last = infos[-1]
+        res[prec] = {"solves_per_s": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                     "median_ms": 1e3 * float(np.median(times)), "min_ms": 1e3 * float(np.min(times)),
+                     "worst_resid_l2": max(i["resid_l2"] for i in infos), "outer_its": last["outer_its"],
+                     "inner_its": last["inner_its"], "t_setup_ms": last["t_setup_ms"],
+                     "t_solve_ms": last["t_solve_ms"], "bandwidth": last["bandwidth"],
+                     "nnz_matrix": last["nnz_matrix"], "nnz_factors": last["nnz_factors"], "rho": rho}
+        _log(f"kerr_chain_3x10 {prec}: {1e3 * dt / args.steps:.1f} ms per solve "
+             f"(median {res[prec]['median_ms']:.1f}), set-up {last['t_setup_ms']:.1f} ms, "
+             f"its {last['outer_its']}/{last['inner_its']}, resid {last['resid_l2']:.2e}")
+    return ch, Hd, Cd, res
+
+
+def dominant_kernel(ssl, ch, Hd, Cd, res):
+    """The headline step's dominant kernels, timed live with HIP events on
+    the handle's stream (ss_time_operator): the preconditioner application
+    (lower then upper level-scheduled triangular solve) and the SpMV, both
+    complex128; algorithmic bytes from the factor and matrix sizes."""
+    L = ssl.build_liouvillian(Hd, Cd)
+    try:
+        ssl.prepare(L, "invpow_bicgstab", prec="mixed")
+        _, n, nnzL = L.shape()
+        A = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+        LU = ssl.export_csr(L, ssl.SS_MAT_LU)
+        t_pre = ssl.time_operator(L, ssl.SS_OP_PRECOND, "fp64", 20)
+        t_pre32 = ssl.time_operator(L, ssl.SS_OP_PRECOND, "mixed", 20)
+        t128 = ssl.time_operator(L, ssl.SS_OP_SPMV_APERM, "fp64", 50)
+        t64 = ssl.time_operator(L, ssl.SS_OP_SPMV_APERM, "mixed", 50)
+        tl = ssl.time_operator(L, ssl.SS_OP_SPMV_L, "fp64", 50)
+        tm = ssl.time_operator(L, ssl.SS_OP_APPLY_L, "fp64", 50)
+    finally:
+        L.free()
+    bp, bp32 = trsv_pair_bytes(n, LU.nnz, 16), trsv_pair_bytes(n, LU.nnz, 8)
+    b128, b64 = spmv_bytes(n, A.nnz, 16), spmv_bytes(n, A.nnz, 8)
+    bl, bm = spmv_bytes(n, nnzL, 16), apply_l_bytes(n)
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
+    kern = {
+        "precond_c128": {"ms": t_pre, "bytes": bp, "GB/s": gbs(bp, t_pre), "frac": gbs(bp, t_pre) / PEAK_HBM_GBS},
+        "precond_c64": {"ms": t_pre32, "bytes": bp32, "GB/s": gbs(bp32, t_pre32),
+                        "frac": gbs(bp32, t_pre32) / PEAK_HBM_GBS},
+        "spmv_c128": {"ms": t128, "bytes": b128, "GB/s": gbs(b128, t128), "frac": gbs(b128, t128) / PEAK_HBM_GBS},
+        "spmv_c64": {"ms": t64, "bytes": b64, "GB/s": gbs(b64, t64), "frac": gbs(b64, t64) / PEAK_HBM_GBS,
+                     "note": "268 MB working set: partly served by the 256 MB Infinity Cache"},
+        "spmv_L_c128": {"ms": tl, "bytes": bl, "GB/s": gbs(bl, tl)},
+        "apply_L_matrix_free": {"ms": tm, "bytes": bm, "GB/s": gbs(bm, tm), "vs_spmv_L": tl / tm},
+        "nnz_matrix": int(A.nnz), "nnz_factors": int(LU.nnz), "n": int(n),
+    }
+    _log(f"precond c128 {t_pre:.3f} ms ({gbs(bp, t_pre):.0f} GB/s), c64 {t_pre32:.3f} ms; "
+         f"spmv c128 {t128 * 1e3:.1f} us ({gbs(b128, t128):.0f} GB/s), c64 {t64 * 1e3:.1f} us "
+         f"({gbs(b64, t64):.0f} GB/s)")
+    # per fp64 solve: inner iterations x (2 preconditioner applications + 2
+    # SpMV); the preconditioner dominates
+    its = res["fp64"]["inner_its"]
+    share = (2 * its * t_pre) / max(res["fp64"]["median_ms"], 1e-9)
+    roof = {"bound": "hbm", "achieved": gbs(bp, t_pre), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs(bp, t_pre) / PEAK_HBM_GBS, "traffic": None,
+            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128): "
+                      "two launches of the level-scheduled solve per application",
+            "bytes_per_launch": bp, "avg_launch_ms": t_pre, "launches_per_unit": 2,
+            "share_of_fp64_step": share}
+    tr = _traffic()
+    if tr is not None:
+        roof["traffic"] = tr
+    return kern, roof
+
+
+def cpu_baseline(ch, res):
+    """The oracle's CPU fp64 sparse reference on the same workload, one full
+    solve on one thread (BLAS limited to one thread)."""
+    import threadpoolctl
+    from oracle.sparse_ref import steady_state_iterative
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        rho, info = steady_state_iterative(ch.H, ch.c_ops, tol=1e-12)
+        dt = time.perf_counter() - t0
+    errs = {p: float(np.max(np.abs(res[p]["rho"] - rho))) for p in res}
+    _log(f"cpu sparse reference: {dt:.1f} s, {info['iterations']} its, resid {info['resid_l2']:.1e}; "
+         f"max|rho_gpu - rho_cpu| fp64 {errs['fp64']:.2e}, mixed {errs['mixed']:.2e}")
+    cb = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+          "sample": "one full solve of the same workload (kerr_chain_3x10, n = 1e6) by the oracle's fp64 "
+                    "sparse reference: RCM, ILU(0) in C, BiCGSTAB with refinement to ||L rho|| <= 1e-12, "
+                    "one thread",
+          "seconds": dt, "iterations": info["iterations"], "resid_l2": info["resid_l2"]}
+    return cb, errs
+
+
+# -------------------------------------------------------------- side legs
+def jc_batch(ssl, qs, torch, args):
+    """B independent Jaynes-Cummings systems (cavity 40 x qubit), each with
+    its own seeded parameter draw, assembled and solved together."""
+    B = args.batch
+    systems = [qs.jaynes_cummings(40, seed=k) for k in range(B)]
+    dev = [(_device_csr(s.H, torch), [_device_csr(c, torch) for c in s.c_ops]) for s in systems]
+    N = systems[0].dim
+    outs = [torch.empty(N * N, dtype=torch.complex128, device="cuda") for _ in range(B)]
+    torch.cuda.synchronize()
+    out = {"workload": f"{B} driven Jaynes-Cummings systems, cavity 40 x qubit (n = 6400), parameters "
+                       f"drawn per system from U[0.1, 2] with seeds 0..{B - 1}"}
+    for prec in ("mixed", "fp64"):
+        def step():
+            Ls = ssl.build_liouvillian_batch(dev)
+            _, infos = ssl.solve_batch(Ls, "trace_bicgstab", tol=1e-10, outs=outs, prec=prec)
+            for L in Ls:
+                L.free()
+            return infos
+        for _ in range(max(args.warmup, 1)):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(3, min(args.steps, 10))
+        infos = [step() for _ in range(reps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        last = infos[-1]
+        its = [i["inner_its"] for i in last]
+        alg = float(sum(i["bytes_alg"] for i in last))
+        tk = last[0]["t_kernel_ms"]
+        out[prec] = {"solves_per_s": B / dt, "ms_per_step": 1e3 * dt, "t_kernel_ms": tk,
+                     "kernel_GB/s": alg / (tk * 1e-3) / 1e9, "kernel_frac": alg / (tk * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "inner_its_min_median_max": [int(min(its)), float(np.median(its)), int(max(its))],
+                     "worst_resid_l2": max(i["resid_l2"] for i in last),
+                     "all_ok": all(i["status"] == 0 for i in last)}
+        _log(f"jc batch {prec}: {B / dt:.0f} solves/s, kernel {tk:.2f} ms "
+             f"({out[prec]['kernel_frac'] * 100:.1f} % of peak), its {out[prec]['inner_its_min_median_max']}")
+    from oracle.steady import steady_state_dense
+    sample = [0, B // 2, B - 1]
+    errs = []
+    for prec in ("mixed",):
+        Ls = ssl.build_liouvillian_batch([dev[i] for i in sample])
+        rhos, _ = ssl.solve_batch(Ls, "trace_bicgstab", tol=1e-10, prec=prec)
+        for L in Ls:
+            L.free()
+        for r, i in zip(rhos, sample):
+            errs.append(float(np.max(np.abs(r - steady_state_dense(systems[i].H, systems[i].c_ops)))))
+    out["max_abs_err_vs_oracle_sample"] = max(errs)
+    out["mixed_vs_fp64"] = out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    return out
+
+
+def spin_chain_leg(ssl, qs):
+    sc = qs.spin_chain(8)
+    Ls = ssl.build_liouvillian(sc.H, sc.c_ops)
+    out = {"workload": f"spin_chain_8 (d = {sc.dim}, n = {sc.dim ** 2})"}
+    try:
+        for prec in ("mixed", "fp64"):
+            t0 = time.perf_counter()
+            _, si = ssl.solve(Ls, "auto", tol=1e-10, prec=prec, raise_on_error=False)
+            dt = time.perf_counter() - t0
+            out[f"auto_{prec}"] = {"s": dt, "status": si["status"], "method": si["method"],
+                                   "bandwidth": si["bandwidth"], "resid_l2": si["resid_l2"],
+                                   "outer_its": si["outer_its"], "inner_its": si["inner_its"]}
+            _log(f"spin chain auto {prec}: {dt:.3f} s, method {si['method']}, resid {si['resid_l2']:.2e}, "
+                 f"its {si['outer_its']}/{si['inner_its']}")
+    finally:
+        Ls.free()
+    return out
 
 
 def _run_stream(ssl, systems, arrivals, prec):
     """Submit each request at its arrival time, poll until all are done;
-    returns (wall seconds, latencies in ms, {index: (rho, info)} for all)."""
+    returns (wall seconds, latencies in ms, {index: (rho, info)})."""
     S = ssl.Server(hbm_budget_bytes=32 << 30, max_slots=1024)
     pending, lat, res = {}, [], {}
     nxt = 0
-    t0 = time.perf_counter()
-    while nxt < len(systems) or pending:
-        now = time.perf_counter() - t0
-        while nxt < len(systems) and arrivals[nxt] <= now:
-            s = systems[nxt]
-            pending[S.submit(s.H, s.c_ops, "trace_bicgstab", 1e-10, prec=prec)] = (nxt, time.perf_counter())
-            nxt += 1
-        for t in list(pending):
-            r = S.poll(t)
-            if r is not None:
-                i, ts = pending.pop(t)
-                lat.append(1e3 * (time.perf_counter() - ts))
-                res[i] = r
-        time.sleep(0.0002)
-    wall = time.perf_counter() - t0
-    S.close()
+    try:
+        t0 = time.perf_counter()
+        while nxt < len(systems) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(systems) and arrivals[nxt] <= now:
+                s = systems[nxt]
+                pending[S.submit(s.H, s.c_ops, "trace_bicgstab", 1e-10, prec=prec)] = (nxt, time.perf_counter())
+                nxt += 1
+            for t in list(pending):
+                r = S.poll(t)
+                if r is not None:
+                    i, ts = pending.pop(t)
+                    lat.append(1e3 * (time.perf_counter() - ts))
+                    res[i] = r
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+    finally:
+        S.close()
     return wall, np.asarray(lat), res
 
 
-def _prec_summary(r, err):
-    """Throughput, accuracy and iteration counts of one precision's batched step."""
-    if not r:
-        return None
-    i0 = r["infos"][0]
-    return {"solves_per_s": r["solves_per_s"], "ms_per_step": r["ms"], "max_abs_err_vs_oracle": err,
-            "worst_resid_l2": r["worst_resid"], "t_kernel_ms": i0["t_kernel_ms"], "outer_its": i0["outer_its"],
-            "inner_its": i0["inner_its"]}
-
-
-def serve_stream(ssl, qs, np_, n_requests):
+def serve_stream(ssl, qs, n_requests):
     """Serving stream of Kerr requests (cutoff N ~ U{10..60}, (Delta, E) on
     a 21 x 20 grid, seed 1): burst capacity (all arrive at t = 0) in both
-    precisions, then Poisson arrivals at half the mixed capacity; p50/p99 of
-    submit-to-result latency; a sample checked against the dense oracle."""
+    precisions, then Poisson arrivals at 0.5, 1 and 2 times the mixed
+    capacity; p50/p99 of submit-to-result latency; a sample checked against
+    the dense oracle."""
     from oracle.steady import steady_state_dense
     stream = qs.serving_stream(n_requests, rate=0.0, seed=1)
     systems = [qs.kerr(N, delta=dl, E=E) for (_, N, dl, E) in stream]
@@ -189,21 +389,24 @@ def serve_stream(ssl, qs, np_, n_requests):
         wall, lat, res = _run_stream(ssl, systems, [0.0] * n_requests, prec)
         ok = all(r[1]["status"] == 0 and r[1]["resid_l2"] <= 1e-10 for r in res.values())
         sample = [i for i in range(n_requests) if systems[i].dim <= 30][:8]
-        err = max(float(np_.max(np_.abs(res[i][0] - steady_state_dense(systems[i].H, systems[i].c_ops))))
+        err = max(float(np.max(np.abs(res[i][0] - steady_state_dense(systems[i].H, systems[i].c_ops))))
                   for i in sample) if sample else None
-        out[f"burst_{prec}"] = {"solves_per_s": n_requests / wall, "p50_ms": float(np_.percentile(lat, 50)),
-                                "p99_ms": float(np_.percentile(lat, 99)), "all_converged": ok,
+        out[f"burst_{prec}"] = {"solves_per_s": n_requests / wall, "p50_ms": float(np.percentile(lat, 50)),
+                                "p99_ms": float(np.percentile(lat, 99)), "all_converged": ok,
                                 "max_abs_err_vs_oracle_sample": err, "sample_size": len(sample)}
-        _log(f"serving burst {prec}: {n_requests / wall:.1f} solves/s, p50 {np_.percentile(lat, 50):.1f} ms, "
-             f"p99 {np_.percentile(lat, 99):.1f} ms, err {err}")
+        _log(f"serving burst {prec}: {n_requests / wall:.1f} solves/s, p50 {np.percentile(lat, 50):.1f} ms, "
+             f"p99 {np.percentile(lat, 99):.1f} ms, err {err}")
     cap = out["burst_mixed"]["solves_per_s"]
-    rate = 0.5 * cap
-    pstream = qs.serving_stream(n_requests, rate=rate, seed=1)
-    wall, lat, res = _run_stream(ssl, systems, [a for (a, _, _, _) in pstream], "mixed")
-    out["poisson_mixed"] = {"rate_per_s": rate, "solves_per_s": n_requests / wall,
-                            "p50_ms": float(np_.percentile(lat, 50)), "p99_ms": float(np_.percentile(lat, 99)),
-                            "all_converged": all(r[1]["status"] == 0 for r in res.values())}
-    _log(f"serving poisson {rate:.1f}/s: p50 {np_.percentile(lat, 50):.1f} ms, p99 {np_.percentile(lat, 99):.1f} ms")
+    for f in (0.5, 1.0, 2.0):
+        rate = f * cap
+        pstream = qs.serving_stream(n_requests, rate=rate, seed=1)
+        wall, lat, res = _run_stream(ssl, systems, [a for (a, _, _, _) in pstream], "mixed")
+        out[f"poisson_mixed_{f}x"] = {"rate_per_s": rate, "solves_per_s": n_requests / wall,
+                                      "p50_ms": float(np.percentile(lat, 50)),
+                                      "p99_ms": float(np.percentile(lat, 99)),
+                                      "all_converged": all(r[1]["status"] == 0 for r in res.values())}
+        _log(f"serving poisson {f}x ({rate:.0f}/s): {n_requests / wall:.0f} solves/s, "
+             f"p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms")
     out["mixed_vs_fp64_capacity"] = cap / out["burst_fp64"]["solves_per_s"]
     return out
 
@@ -213,15 +416,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=256, help="solves per step (one workgroup each)")
-    ap.add_argument("--method", default="trace_bicgstab")
+    ap.add_argument("--batch", type=int, default=256, help="systems of the batched Jaynes-Cummings step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the n = 10^6 Kerr-chain measurements")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests of the Kerr serving stream (0 skips the serving measurement)")
-    ap.add_argument("--precs", default="mixed,fp64,fp64_refined",
-                    help="precisions of the batched step (fp64_refined: fp64 inner solves restarted from the "
-                         "fp64 residual at the mixed path's inner tolerance)")
+    ap.add_argument("--legs", default="kernels,jc_batch,spin_chain,serving",
+                    help="secondary measurements to run (comma list; empty for none)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MB (the known-size reference for "
                          "the HBM counter runs)")
@@ -231,11 +430,12 @@ def main():
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(*args.traffic_from)
-        return
+        return 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (each solve fits one MI355X; "
-              "independent requests would be routed to separate GPUs)", file=sys.stderr)
-        sys.exit(2)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: this build measures one "
+              "MI355X (a single solve fits one GPU; independent requests would be routed to separate GPUs)",
+              file=sys.stderr)
+        return 2
 
     import torch
 
@@ -243,27 +443,6 @@ def main():
     import qsystems as qs
 
     torch.cuda.set_device(0)
-    s = qs.config(2)
-    N = s.dim
-    B = args.batch
-    _log(f"workload jc_N40xqubit: N = {N}, n = {N * N}, {B} solves per step")
-    Hd = _device_csr(s.H, torch)
-    Cd = [_device_csr(c, torch) for c in s.c_ops]
-    outs = [torch.empty(N * N, dtype=torch.complex128, device="cuda") for _ in range(B)]
-    out1 = outs[0]
-    torch.cuda.synchronize()
-
-    def step(prec):
-        """B independent solves: batched assembly of B Liouvillians from the
-        device-resident H and collapse operators, then set-up and solve of
-        all B together."""
-        Ls = ssl.build_liouvillian_batch([(Hd, Cd)] * B)
-        kw = {"prec": "fp64", "inner_tol": 1e-4} if prec == "fp64_refined" else {"prec": prec}
-        _, infos = ssl.solve_batch(Ls, args.method, tol=1e-10, outs=outs, **kw)
-        for L in Ls:
-            L.free()
-        return infos
-
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -274,161 +453,64 @@ def main():
         _log(f"calibration copy: {nb} bytes read and written")
         del src, dst
 
-    results = {}
-    precs = [p for p in args.precs.split(",") if p]
-    for prec in precs:
-        for _ in range(args.warmup):
-            step(prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = [step(prec) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        last = infos[-1]
-        rho = out1.cpu().numpy().reshape(N, N, order="F")
-        worst = max(i["resid_l2"] for i in last)
-        results[prec] = dict(ms=1e3 * dt / args.steps, solves_per_s=B * args.steps / dt, infos=last, rho=rho,
-                             worst_resid=worst)
-        _log(f"{prec}: {1e3 * dt / args.steps:.1f} ms per step of {B} -> {B * args.steps / dt:.1f} solves/s, "
-             f"kernel {last[0]['t_kernel_ms']:.2f} ms, set-up {last[0]['t_setup_ms']:.1f} ms, "
-             f"worst resid {worst:.2e}, its {last[0]['outer_its']}/{last[0]['inner_its']}")
-
-    # single-solve latency (one system, the solver's own path choice)
-    single = {}
-    for prec in [p for p in precs if p != "fp64_refined"]:
-        ts = []
-        for k in range(6):
-            L = ssl.build_liouvillian(Hd, Cd)
-            t0 = time.perf_counter()
-            _, inf = ssl.solve(L, args.method, tol=1e-10, out=out1, prec=prec)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-            L.free()
-        single[prec] = {"ms": 1e3 * float(np.median(ts[1:])), "path": inf["path"], "resid_l2": inf["resid_l2"],
-                        "outer_its": inf["outer_its"], "inner_its": inf["inner_its"]}
-        _log(f"single {prec}: {single[prec]['ms']:.2f} ms")
-
-    # accuracy against the fp64 dense oracle, and the oracle's own time
-    from oracle.steady import steady_state_dense
-    cpu = None
-    t0 = time.perf_counter()
-    ref = steady_state_dense(s.H, s.c_ops)
-    t_oracle = time.perf_counter() - t0
-    if not args.no_cpu_baseline:
-        reps = max(1, min(3, int(20.0 / max(t_oracle, 1e-3))))
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            steady_state_dense(s.H, s.c_ops)
-        t_cpu = (time.perf_counter() - t0) / reps
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": cores, "kind": "oracle",
-               "sample": f"{reps} dense fp64 LU solve(s) of the trace-replaced 6400 x 6400 Liouvillian "
-                         f"of the same workload (numpy/LAPACK)"}
-    err = {p: float(np.max(np.abs(results[p]["rho"] - ref))) for p in results}
-
-    # dominant kernel: the workgroup-resident solver, one launch per step
-    # running all B systems; algorithmic bytes are summed over the systems
-    # from their iteration counts (ss_info.bytes_alg) and divided by the
-    # launch time measured with HIP events on the solver's stream
-    mi = results["mixed"]["infos"]
-    alg = float(sum(i["bytes_alg"] for i in mi))
-    t_k = mi[0]["t_kernel_ms"]
-    achieved = alg / (t_k * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(t_k),
-                "kernel": f"k_wg_solve<c64> over {B} systems (refinement + BiCGSTAB + level-scheduled ILU(0) "
-                          f"sweeps, one workgroup per system)",
-                "bytes_per_launch": alg, "avg_launch_ms": t_k}
-
-    large = None
-    if not args.no_large:
-        ch = qs.config(4)
-        Lc = ssl.build_liouvillian(ch.H, ch.c_ops)
-        ssl.prepare(Lc, "invpow_bicgstab", prec="mixed")
-        _, nc, nnzc = Lc.shape()
-        Apc = ssl.export_csr(Lc, ssl.SS_MAT_A_PERM)
-        t64 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "mixed", 50)
-        t128 = ssl.time_operator(Lc, ssl.SS_OP_SPMV_APERM, "fp64", 50)
-        b64, b128 = spmv_bytes(nc, Apc.nnz, 8), spmv_bytes(nc, Apc.nnz, 16)
-        tl = ssl.time_operator(Lc, ssl.SS_OP_SPMV_L, "fp64", 50)
-        tm = ssl.time_operator(Lc, ssl.SS_OP_APPLY_L, "fp64", 50)
-        bl, bm = spmv_bytes(nc, nnzc, 16), apply_l_bytes(nc)
-        large = {"workload": "kerr_chain_3x10 (n = 1e6)", "nnz": int(Apc.nnz),
-                 "spmv_c64": {"ms": t64, "GB/s": b64 / (t64 * 1e-3) / 1e9, "bytes": b64},
-                 "spmv_c128": {"ms": t128, "GB/s": b128 / (t128 * 1e-3) / 1e9, "bytes": b128},
-                 "spmv_L_c128": {"ms": tl, "GB/s": bl / (tl * 1e-3) / 1e9, "bytes": bl},
-                 "apply_L_matrix_free": {"ms": tm, "GB/s": bm / (tm * 1e-3) / 1e9, "bytes": bm,
-                                         "frac": bm / (tm * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                                         "vs_spmv_L": tl / tm}}
-        for prec in ("mixed", "fp64"):
-            for mf in (False, True):
-                t0 = time.perf_counter()
-                _, ci = ssl.solve(Lc, "invpow_bicgstab", tol=1e-10, prec=prec, matrix_free=mf)
-                dt = time.perf_counter() - t0
-                key = f"solve_invpow_{prec}" + ("_matrix_free" if mf else "")
-                large[key] = {"s": dt, "resid_l2": ci["resid_l2"], "outer_its": ci["outer_its"],
-                              "inner_its": ci["inner_its"], "t_setup_ms": ci["t_setup_ms"]}
-                _log(f"kerr chain invpow {prec}{' matrix-free' if mf else ''}: {dt:.2f} s, "
-                     f"resid {ci['resid_l2']:.2e}")
-        Lc.free()
-
-    # the driven spin chain (dephasing on every spin): the trace row inflates
-    # the RCM bandwidth, and the automatic method choice takes inverse power
-    spin = None
-    if not args.no_large:
-        sc = qs.spin_chain(8)
-        Ls = ssl.build_liouvillian(sc.H, sc.c_ops)
-        spin = {"workload": f"spin_chain_8 (d = {sc.dim}, n = {sc.dim ** 2})"}
-        for prec in ("mixed", "fp64"):
-            t0 = time.perf_counter()
-            _, si = ssl.solve(Ls, "auto", tol=1e-10, prec=prec, raise_on_error=False)
-            dt = time.perf_counter() - t0
-            spin[f"auto_{prec}"] = {"s": dt, "status": si["status"], "method": si["method"],
-                                    "bandwidth": si["bandwidth"], "resid_l2": si["resid_l2"],
-                                    "outer_its": si["outer_its"], "inner_its": si["inner_its"]}
-            _log(f"spin chain auto {prec}: {dt:.3f} s, method {si['method']}, resid {si['resid_l2']:.2e}")
-        Ls.free()
-
-    serving = None
-    if args.serve_requests > 0:
-        serving = serve_stream(ssl, qs, np, args.serve_requests)
-
-    m = results["mixed"]
-    f = results.get("fp64")
-    fr = results.get("fp64_refined")
+    ch, Hd, Cd, res = headline(ssl, qs, torch, args)
+    f64, mx = res["fp64"], res["mixed"]
+    errors = {}
     line = {
         "metric": "steady-state solves/sec + SpMV HBM GB/s at ||L.rho||<=1e-10, mixed vs FP64",
-        "value": m["solves_per_s"],
+        "value": f64["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": m["ms"],
+        "ms_per_step": f64["ms_per_step"],
+        "median_ms_per_step": f64["median_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 inner / c128 refinement",
+        "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": f"jc_N40xqubit: driven Jaynes-Cummings, cavity 40 x qubit, n = 6400; "
-                               f"{B} independent solves per step (assembly, transform, RCM, ILU(0), solve, finish)",
-                   "method": args.method, "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0", "batch": B},
-        "max_abs_err_vs_oracle": err["mixed"],
-        "worst_resid_l2": m["worst_resid"],
-        "fp64": _prec_summary(f, err.get("fp64")),
-        "mixed_vs_fp64": m["solves_per_s"] / f["solves_per_s"] if f else None,
-        # fp64 with the mixed path's refinement schedule: the difference to
-        # "mixed" is the precision of the inner solves alone
-        "fp64_refined": _prec_summary(fr, err.get("fp64_refined")),
-        "mixed_vs_fp64_refined": m["solves_per_s"] / fr["solves_per_s"] if fr else None,
-        "single_solve": single,
-        "roofline": roofline,
-        "large": large,
-        "spin_chain": spin,
-        "serving": serving,
-        "cpu_baseline": cpu,
+        "config": {"workload": "kerr_chain_3x10: three coupled driven Kerr cavities, N = 10 each, J = 0.3 "
+                               "(d = 1000, Liouvillian n = 1e6, 20.7 M non-zeros); one full solve per step "
+                               "(assembly, shift, RCM, ILU(0), inverse power with BiCGSTAB inner solves, finish)",
+                   "method": "invpow_bicgstab", "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0"},
+        "worst_resid_l2": f64["worst_resid_l2"],
+        "fp64": {k: v for k, v in f64.items() if k != "rho"},
+        "mixed": {k: v for k, v in mx.items() if k != "rho"},
+        "mixed_vs_fp64": mx["solves_per_s"] / f64["solves_per_s"],
     }
+    legs = [x for x in args.legs.split(",") if x]
+    try:
+        kern, roof = dominant_kernel(ssl, ch, Hd, Cd, res)
+        line["roofline"] = roof
+        if "kernels" in legs:
+            line["kernels"] = kern
+    except Exception as e:  # recorded, never silent
+        errors["roofline"] = f"{type(e).__name__}: {e}"
+        traceback.print_exc()
+    if not args.no_cpu_baseline:
+        try:
+            cb, errs = cpu_baseline(ch, res)
+            line["cpu_baseline"] = cb
+            line["max_abs_err_vs_oracle"] = errs["fp64"]
+            line["mixed"]["max_abs_err_vs_oracle"] = errs["mixed"]
+        except Exception as e:
+            errors["cpu_baseline"] = f"{type(e).__name__}: {e}"
+            traceback.print_exc()
+    for name, fn in (("jc_batch", lambda: jc_batch(ssl, qs, torch, args)),
+                     ("spin_chain", lambda: spin_chain_leg(ssl, qs)),
+                     ("serving", lambda: serve_stream(ssl, qs, args.serve_requests))):
+        if name not in legs or (name == "serving" and args.serve_requests <= 0):
+            continue
+        try:
+            line[name] = fn()
+        except Exception as e:
+            errors[name] = f"{type(e).__name__}: {e}"
+            traceback.print_exc()
+    line["errors"] = errors
     print(json.dumps(line), flush=True)
+    return 3 if errors else 0
 
 
 if __name__ == "__main__":
-    main()
+    sys.exit(main())

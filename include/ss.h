@@ -144,6 +144,11 @@ typedef struct {
                                   sync-free over all CUs in level order
                                   (default: BLOCK up to n = 65536, else
                                   LEVELS)                                     */
+#define SS_FLAG_FORCE_BREAKDOWN 512 /* testing hook: every BiCGSTAB breakdown
+                                  test fires (as if the shadow residual were
+                                  orthogonal to the residual), so the restart
+                                  and GMRES fallback paths run; not for
+                                  production solves                          */
 #define SS_FLAG_MATRIX_FREE 256 /* the fp64 residual of every outer step
                                   and the final certificate apply L from the
                                   d x d operators of eq. (lindblad) instead of
@@ -295,26 +300,68 @@ int ss_bandwidth_profile(ss_liouv L, int32_t which, int64_t *B, int64_t *P);
 
 /* ------------------------------------------------------------- serving */
 /* A server keeps many small solves resident on the device and advances them
- * together (continuous batching): requests are admitted while their
- * predicted footprint fits in hbm_budget_bytes and fewer than max_slots run;
- * requests that arrive later wait and are admitted as slots and memory free
- * up, between batched iteration rounds. */
+ * side by side (continuous batching; not in the paper: a deployment of its
+ * method for parameter sweeps).  Requests are admitted in arrival order while
+ * fewer than max_slots are resident and their predicted device footprint
+ * (an upper bound of the bytes a request holds while it runs) fits in
+ * hbm_budget_bytes; a request larger than the whole budget is admitted
+ * alone.  Several workers (host threads, environment SS_SERVER_WORKERS =
+ * 1..16, default 4) each take a group -- the admitted head of the queue plus
+ * later queued requests with the same method and options, at most one per
+ * compute unit -- and run it on their own stream: batched assembly and set-up
+ * stages, one launch of the workgroup-resident solver with one workgroup per
+ * request, the finish.  A request that arrives while groups are on the
+ * device is admitted as soon as a worker, a slot and memory are free, and
+ * its work overlaps theirs on the device; a group's slots and memory return
+ * to the budget when it finishes.  A worker that finds the queue still
+ * growing waits until no request has arrived for SS_SERVER_WINDOW_US
+ * microseconds (0..100000, default 200) or a full group is queued.
+ * Each request's arithmetic stays in its own workgroup, so its result is
+ * the same alone and in any group.  Returns SS_E_INVALID_ARG for a zero
+ * budget or max_slots <= 0. */
 int ss_server_create(size_t hbm_budget_bytes, int32_t max_slots, ss_server *out);
 
-/* Queue a steady-state request (inputs are copied before return).  method
- * and opt as in ss_solve.  *ticket identifies the request. */
+/* Queue a steady-state request (inputs, host or device, are copied to the
+ * host and validated before return: a malformed matrix gives
+ * SS_E_INVALID_ARG here, never a failed group).  method, tol and opt as in
+ * ss_solve (SS_AUTO included).  Requests with SS_TRACE_BICGSTAB or
+ * SS_INVPOW_BICGSTAB that the workgroup-resident solver takes (N^2 <= 4096,
+ * or SS_FLAG_WORKGROUP; N <= 1024, at most 16 collapse operators) are
+ * batched; any other request (GMRES, SS_AUTO, larger systems) is solved on
+ * its own by a worker with the kernels of ss_solve.  *ticket identifies the
+ * request. */
 int ss_submit(ss_server S, const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cops,
               int64_t N, int32_t method, double tol, const ss_options *opt,
               uint64_t *ticket);
 
 /* Non-blocking.  Returns SS_PENDING while the request runs; otherwise the
- * request's status, with rho_out (N*N complex, host) and info filled, and
- * the ticket retired. */
+ * request's status, with rho_out (N*N complex, host or device; NULL to
+ * discard) and info filled, and the ticket retired.  An unknown or retired
+ * ticket gives SS_E_INVALID_ARG. */
 int ss_poll(ss_server S, uint64_t ticket, double *rho_out, ss_info *info);
 
 /* Block until every queued request has finished. */
 int ss_server_drain(ss_server S);
 
+/* Occupancy of a server: the budget, the predicted footprint of the
+ * requests resident now and the largest it has been, resident and queued
+ * requests, groups run so far and the largest of them, workers, and the
+ * largest group a worker forms. */
+typedef struct {
+    uint64_t budget_bytes;
+    uint64_t resident_bytes;
+    uint64_t peak_resident_bytes;
+    int32_t resident;
+    int32_t queued;
+    uint64_t groups;
+    uint64_t largest_group;
+    int32_t workers;
+    int32_t max_group;
+} ss_server_stats_t;
+int ss_server_stats(ss_server S, ss_server_stats_t *st);
+
+/* Stops the workers after their current groups (queued requests are
+ * dropped) and releases the server. */
 void ss_server_destroy(ss_server S);
 
 /* ---------------------------------------------------------------- misc */
@@ -322,7 +369,10 @@ void ss_server_destroy(ss_server S);
 const char *ss_last_error(void);
 
 /* Make subsequent calls of this thread enqueue their work on a HIP stream
- * (a hipStream_t cast to void*; NULL = the library's own stream per handle). */
+ * (a hipStream_t cast to void*; NULL = the library's own stream per handle).
+ * The stream must outlive every handle used with it: device blocks released
+ * by those handles are returned to the library's cache behind events
+ * recorded on it. */
 int ss_set_stream(void *hip_stream);
 
 /* Route the library's device allocations through caller callbacks (e.g. a

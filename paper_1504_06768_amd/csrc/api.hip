@@ -33,6 +33,9 @@ namespace {
 
 template <typename F>
 int guarded(F &&f) {
+    // an error left by an earlier HIP call of the caller's thread is not this
+    // call's: cleared, so that the launch checks inside report only their own
+    (void)hipGetLastError();
     try {
         return f();
     } catch (const ss::Error &e) {
@@ -407,12 +410,12 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             if (prec == SS_FP64 || natural) run(double2{0, 0});
             else run(float2{0, 0});
         } catch (...) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
+            ss::hip_quiet(hipEventDestroy(e0));
+            ss::hip_quiet(hipEventDestroy(e1));
             throw;
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        ss::hip_quiet(hipEventDestroy(e0));
+        ss::hip_quiet(hipEventDestroy(e1));
         *avg_ms = (double)ms / reps;
         return SS_OK;
     });

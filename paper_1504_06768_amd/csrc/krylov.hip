@@ -235,9 +235,10 @@ void Krylov<T>::init(const Csr<T> &A_, Precond<T> *M_, hipStream_t s_) {
 }
 
 template <typename T>
-KrylovResult Krylov<T>::bicgstab(const T *b, T *x, double rtol, int maxiter) {
+KrylovResult Krylov<T>::bicgstab(const T *b, T *x, double rtol, int maxiter, bool force_breakdown) {
     const int nb = vec_blocks(n);
-    const double bd_eps = sizeof(typename RealOf<T>::type) == 8 ? 1e-30 : 1e-14;
+    // (a threshold whose square overflows makes every breakdown test fire)
+    const double bd_eps = force_breakdown ? 1e300 : (sizeof(typename RealOf<T>::type) == 8 ? 1e-30 : 1e-14);
     BicgState *st = bst.get();
     const int *skip = &st->skip;
     double2 *sc = scal.get();

@@ -49,7 +49,8 @@ struct Krylov {
     void init(const Csr<T> &A_, Precond<T> *M_, hipStream_t s_);
     // x = solution of A x = b from x = 0, relative tolerance rtol on the
     // recursive residual; returns iterations and flags
-    KrylovResult bicgstab(const T *b, T *x, double rtol, int maxiter);
+    // force_breakdown: every breakdown test fires (SS_FLAG_FORCE_BREAKDOWN)
+    KrylovResult bicgstab(const T *b, T *x, double rtol, int maxiter, bool force_breakdown = false);
     KrylovResult gmres(const T *b, T *x, double rtol, int maxiter, int m);
 };
 

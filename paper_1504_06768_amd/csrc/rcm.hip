@@ -381,17 +381,13 @@ RcmJob RcmScratch::job(const CsrBuf<double2> &S, int *perm, int *iperm) const {
 
 // LDS a workgroup may take (the kernel's static LDS is below 1 KB)
 static size_t rcm_lds_budget() {
-    static size_t cached = 0;
-    if (!cached) {
+    static const size_t cached = []() -> size_t {
         int dev = 0;
         hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-            cached = prop.sharedMemPerBlock > 2048 ? prop.sharedMemPerBlock - 2048 : 0;
-        } else {
-            (void)hipGetLastError();
-            cached = 64 * 1024 - 2048;
-        }
-    }
+        if (hip_quiet(hipGetDevice(&dev)) == hipSuccess && hip_quiet(hipGetDeviceProperties(&prop, dev)) == hipSuccess)
+            return prop.sharedMemPerBlock > 2048 ? prop.sharedMemPerBlock - 2048 : 0;
+        return 64 * 1024 - 2048;
+    }();
     return cached;
 }
 
@@ -403,9 +399,8 @@ void rcm_batch(const RcmJob *jobs, int count, hipStream_t s) {
     h2d(dj.get(), jobs, (size_t)count, s);
     const size_t lds = sizeof(int) * (5 * (size_t)max_n + 1);
     if (lds <= rcm_lds_budget()) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rcm_block<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipGetLastError();
+        hip_quiet(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rcm_block<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)rcm_lds_budget()));
         k_rcm_block<true><<<count, RCM_BLOCK_T, lds, s>>>(dj.get());
     } else {
         k_rcm_block<false><<<count, RCM_BLOCK_T, 0, s>>>(dj.get());

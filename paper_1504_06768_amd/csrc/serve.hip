@@ -3,14 +3,18 @@
 //
 // Pipeline: submitted (inputs copied to the host and validated there) ->
 // admitted, in arrival order while a slot is free and the predicted device
-// footprint fits the budget -> every admitted request with the same method
-// and options goes through the batched path together: its inputs reach the
-// device in one copy, the Liouvillians are assembled by the batched
-// assembly, and the batched solve runs the set-up stages, one launch of the
-// workgroup-resident solver (one workgroup per request) and the finish for
-// all of them -> done (rho and info kept for ss_poll) -> the device memory
-// returns to the budget.  Requests that arrive while a group runs wait in
-// the queue and form the next group.  Each request's arithmetic stays in its
+// footprint fits the budget -> taken by one of several workers as a group of
+// requests with the same method and options (at most one per compute unit):
+// its inputs reach the device in one copy, the Liouvillians are assembled by
+// the batched assembly, and the batched solve runs the set-up stages, one
+// launch of the workgroup-resident solver (one workgroup per request) and
+// the finish for all of them -> done (rho and info kept for ss_poll) -> the
+// group's device memory returns to the budget.  Workers run their groups on
+// their own streams side by side, so a request that arrives while a group is
+// on the device is admitted as soon as slots and memory allow and its work
+// overlaps the running group's.  Requests the batched path does not take
+// (GMRES, SS_AUTO, sizes above the workgroup solver's default) are solved
+// one by one with ss_solve's kernels.  Each request's arithmetic stays in its
 // own workgroup, so its result does not depend on what else is in the group.
 #include <atomic>
 #include <chrono>
@@ -21,6 +25,7 @@
 #include <thread>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -116,6 +121,7 @@ struct Request {
     double tol = 1e-10;
     ss_options opt{};
     size_t footprint = 0;
+    std::chrono::steady_clock::time_point arrival;
     enum State { QUEUED, RUNNING, DONE } state = QUEUED;
     // result
     int status = SS_OK;
@@ -129,20 +135,22 @@ struct Request {
 struct ss_server_s {
     size_t budget = 0;
     int max_slots = 0;
+    int max_group = 256;              // requests per batched launch (one per CU)
     std::mutex mu;
-    std::condition_variable cv;       // wakes the scheduler
+    std::condition_variable cv;       // wakes the workers
     std::condition_variable done_cv;  // wakes ss_server_drain
     std::deque<ss::Request *> queued;
     std::map<uint64_t, ss::Request *> all;
     size_t used = 0;
+    size_t peak_used = 0;             // largest admitted footprint so far
     int resident = 0;
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::thread scheduler;
-    hipStream_t solve_stream = nullptr;
+    std::vector<std::thread> workers;
     int device = 0;
-    void *pinned = nullptr;  // staging of a group's inputs (page-locked)
-    size_t pinned_bytes = 0;
+    std::chrono::microseconds window{200};  // batching window (see worker_loop)
+    std::chrono::steady_clock::time_point last_arrival;
+    uint64_t groups = 0, max_group_seen = 0;
 };
 
 namespace ss {
@@ -160,11 +168,56 @@ static size_t staged_bytes(const HostCsr &m) {
            align256(sizeof(double) * m.data.size());
 }
 
+// A worker's own stream (from the library's pool, never destroyed: blocks of
+// the allocator cache keep events recorded on it) and page-locked staging.
+struct Worker {
+    hipStream_t stream = nullptr;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    ~Worker() {
+        if (pinned) hip_quiet(hipHostFree(pinned));
+    }
+};
+
+// Requests that the batched workgroup-resident path takes: BiCGSTAB methods,
+// sizes it solves by default, operators the batched assembly accepts.
+static bool batchable(const Request *r) {
+    return (r->method == SS_TRACE_BICGSTAB || r->method == SS_INVPOW_BICGSTAB) &&
+           use_workgroup_n(r->N * r->N, r->method, r->opt) && batch_assembly_fits(r->N) &&
+           (int)r->C.size() <= MAX_COPS;
+}
+
+// A request the batched path does not take: assembled and solved on its own
+// with ss_solve's kernels (device-wide or workgroup-resident, by its size).
+static void run_single(Request *r) {
+    std::vector<ss_csr_z> C;
+    for (const HostCsr &c : r->C) C.push_back(c.view());
+    const ss_csr_z H = r->H.view();
+    std::unique_ptr<ss_liouv_s> h(new ss_liouv_s());
+    h->own_stream = pooled_stream();
+    h->N = r->N;
+    h->d = (int)r->N;
+    h->n = (int)(r->N * r->N);
+    assemble_liouvillian(&H, C.empty() ? nullptr : C.data(), (int)C.size(), r->N, stream_of(h.get()), h->L, h->lin);
+    r->rho.resize(2 * (size_t)r->N * r->N);
+    std::memset(&r->info, 0, sizeof(r->info));
+    r->status = solve(h.get(), r->method, r->tol, r->opt, r->rho.data(), &r->info);
+    r->info.status = r->status;
+    if (r->status == SS_E_NOT_CONVERGED) r->error = "iteration limit reached before ||L rho|| <= tol";
+    else if (r->status == SS_E_BREAKDOWN) r->error = "BiCGSTAB breakdown";
+    FreeScope fs(stream_peek(h.get()));
+    h.reset();
+}
+
 // One group (same method and options): inputs to the device in one copy,
 // batched assembly, batched solve; results kept in the requests.
-static void run_group(ss_server_s *S, std::vector<Request *> &g) {
-    hipStream_t s = S->solve_stream;
-    set_current_stream(s);
+static void run_group(Worker &W, std::vector<Request *> &g) {
+    if (g.size() == 1 && !batchable(g[0])) {
+        run_single(g[0]);
+        return;
+    }
+    hipStream_t s = W.stream;
+    StreamScope scope(s);
     const int m = (int)g.size();
     size_t bytes = 0;
     for (Request *r : g) {
@@ -172,15 +225,18 @@ static void run_group(ss_server_s *S, std::vector<Request *> &g) {
         for (const HostCsr &c : r->C) bytes += staged_bytes(c);
     }
     bytes = std::max<size_t>(bytes, 256);
-    if (S->pinned_bytes < bytes) {
-        if (S->pinned) SS_HIP(hipHostFree(S->pinned));
-        S->pinned = nullptr;
-        S->pinned_bytes = 0;
-        SS_HIP(hipHostMalloc(&S->pinned, bytes, hipHostMallocDefault));
-        S->pinned_bytes = bytes;
+    if (W.pinned_bytes < bytes) {
+        if (W.pinned) {
+            // the previous group's copy from it is complete (its solve was read back)
+            SS_HIP(hipHostFree(W.pinned));
+        }
+        W.pinned = nullptr;
+        W.pinned_bytes = 0;
+        SS_HIP(hipHostMalloc(&W.pinned, bytes, hipHostMallocDefault));
+        W.pinned_bytes = bytes;
     }
     DevBuf<unsigned char> dev(bytes);
-    unsigned char *host = static_cast<unsigned char *>(S->pinned);
+    unsigned char *host = static_cast<unsigned char *>(W.pinned);
     size_t off = 0;
     auto stage = [&](const HostCsr &a) {
         ss_csr_z d;
@@ -208,7 +264,8 @@ static void run_group(ss_server_s *S, std::vector<Request *> &g) {
         nc[(size_t)k] = (int)Cd[(size_t)k].size();
     }
     SS_HIP(hipMemcpyAsync(dev.get(), host, off, hipMemcpyHostToDevice, s));
-    // handles and their batched assembly (the copy above is ordered before it on s)
+    // handles and their batched assembly (the copy above is ordered before it
+    // on s; assemble_batch returns with its work complete)
     std::vector<std::unique_ptr<ss_liouv_s>> hs;
     std::vector<AsmTarget> tg;
     for (Request *r : g) {
@@ -256,54 +313,97 @@ static bool same_group(const Request *a, const Request *b) {
     return a->method == b->method && std::memcmp(&a->opt, &b->opt, sizeof(ss_options)) == 0;
 }
 
-// Scheduler: admission by slots and footprint, then the admitted requests
-// in groups of equal method and options.
-static void scheduler_loop(ss_server_s *S) {
-    (void)hipSetDevice(S->device);
-    set_current_stream(S->solve_stream);
+// Whether the request at the head of the queue may start now (the lock is
+// held): a free slot and room in the budget; a request larger than the whole
+// budget starts alone.
+static bool head_fits(const ss_server_s *S) {
+    if (S->queued.empty() || S->resident >= S->max_slots) return false;
+    const Request *r = S->queued.front();
+    return S->resident == 0 || S->used + r->footprint <= S->budget;
+}
+
+// Worker: whenever the head of the queue fits, form a group -- the head plus
+// later queued requests of the same method and options, in arrival order,
+// while slots and budget allow, at most max_group -- and run it on this
+// worker's stream.  Several workers run groups side by side, so a request
+// that arrives while a group is on the device starts as soon as slots and
+// memory allow instead of waiting for that group; its budget returns when
+// its group finishes.
+static void worker_loop(ss_server_s *S) {
+    hip_quiet(hipSetDevice(S->device));
+    Worker W;
+    W.stream = pooled_stream();
+    set_current_stream(W.stream);
     while (true) {
-        std::vector<Request *> admitted;
+        std::vector<Request *> grp;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv.wait(lk, [&] { return S->stop || !S->queued.empty(); });
+            S->cv.wait(lk, [&] { return S->stop || head_fits(S); });
             if (S->stop) return;
-            // admit in arrival order while slots and memory allow (a request
-            // larger than the whole budget is admitted alone)
-            while (!S->queued.empty() && S->resident < S->max_slots) {
-                Request *r = S->queued.front();
-                if (S->resident > 0 && S->used + r->footprint > S->budget) break;
-                S->queued.pop_front();
+            // batching window: while requests keep arriving (less than the
+            // window apart) and the queue holds fewer than a full group, let
+            // it fill, so that a burst forms few large groups
+            while (!S->stop && head_fits(S) && (int)S->queued.size() < S->max_group) {
+                const auto quiet = std::chrono::steady_clock::now() - S->last_arrival;
+                if (quiet >= S->window) break;
+                S->cv.wait_for(lk, S->window - quiet);
+            }
+            if (S->stop) return;
+            if (!head_fits(S)) continue;
+            Request *head = S->queued.front();
+            S->queued.pop_front();
+            grp.push_back(head);
+            if (batchable(head)) {
+                for (auto it = S->queued.begin(); it != S->queued.end() && (int)grp.size() < S->max_group;) {
+                    Request *r = *it;
+                    if (S->resident + (int)grp.size() >= S->max_slots) break;
+                    if (same_group(head, r) && batchable(r)) {
+                        size_t fp = 0;
+                        for (Request *q : grp) fp += q->footprint;
+                        if (S->used + fp + r->footprint > S->budget) break;
+                        grp.push_back(r);
+                        it = S->queued.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            for (Request *r : grp) {
                 S->used += r->footprint;
                 S->resident += 1;
                 r->state = Request::RUNNING;
-                admitted.push_back(r);
             }
+            S->peak_used = std::max(S->peak_used, S->used);
+            S->groups += 1;
+            S->max_group_seen = std::max<uint64_t>(S->max_group_seen, grp.size());
+            // another worker may take the new head
+            if (head_fits(S)) S->cv.notify_one();
         }
-        std::vector<char> taken(admitted.size(), 0);
-        for (size_t a = 0; a < admitted.size(); ++a) {
-            if (taken[a]) continue;
-            std::vector<Request *> grp;
-            for (size_t b = a; b < admitted.size(); ++b)
-                if (!taken[b] && same_group(admitted[a], admitted[b])) {
-                    taken[b] = 1;
-                    grp.push_back(admitted[b]);
-                }
-            try {
-                run_group(S, grp);
-            } catch (const Error &e) {
-                for (Request *r : grp) set_error(r, e.code, e.what());
-            } catch (const std::exception &e) {
-                for (Request *r : grp) set_error(r, SS_E_HIP, e.what());
-            }
-            std::lock_guard<std::mutex> lk(S->mu);
-            for (Request *r : grp) {
-                S->used -= r->footprint;
-                S->resident -= 1;
-                r->state = Request::DONE;
-            }
-            S->done_cv.notify_all();
+        try {
+            run_group(W, grp);
+        } catch (const Error &e) {
+            for (Request *r : grp) set_error(r, e.code, e.what());
+        } catch (const std::exception &e) {
+            for (Request *r : grp) set_error(r, SS_E_HIP, e.what());
         }
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (Request *r : grp) {
+            S->used -= r->footprint;
+            S->resident -= 1;
+            r->state = Request::DONE;
+        }
+        S->done_cv.notify_all();
+        S->cv.notify_all();
     }
+}
+
+// Workers per server: SS_SERVER_WORKERS (1..16), default 4; batching window
+// SS_SERVER_WINDOW_US (0..100000), default 200.
+static int env_int(const char *name, int lo, int hi, int dflt) {
+    const char *e = std::getenv(name);
+    if (!e) return dflt;
+    const int v = std::atoi(e);
+    return (v >= lo && v <= hi) ? v : dflt;
 }
 
 }  // namespace ss
@@ -322,26 +422,39 @@ int ss_server_create(size_t hbm_budget_bytes, int32_t max_slots, ss_server *out)
     if (!S) return SS_E_OOM;
     S->budget = hbm_budget_bytes;
     S->max_slots = max_slots;
-    (void)hipGetDevice(&S->device);
-    if (hipStreamCreateWithFlags(&S->solve_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (ss::hip_quiet(hipGetDevice(&S->device)) != hipSuccess) {
         delete S;
         return SS_E_HIP;
     }
-    S->scheduler = std::thread(ss::scheduler_loop, S);
+    int cus = 0;
+    if (ss::hip_quiet(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device)) == hipSuccess &&
+        cus > 0)
+        S->max_group = cus;
+    try {
+        S->window = std::chrono::microseconds(ss::env_int("SS_SERVER_WINDOW_US", 0, 100000, 200));
+        const int nw = ss::env_int("SS_SERVER_WORKERS", 1, 16, 4);
+        for (int k = 0; k < nw; ++k) S->workers.emplace_back(ss::worker_loop, S);
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+            S->cv.notify_all();
+        }
+        for (auto &t : S->workers) t.join();
+        delete S;
+        return SS_E_OOM;
+    }
     *out = S;
     return SS_OK;
 }
 
 int ss_submit(ss_server S, const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_cops, int64_t N, int32_t method,
               double tol, const ss_options *opt, uint64_t *ticket) {
-    if (!S || !ticket || !H || N < 1 || n_cops < 0 || (n_cops > 0 && !c_ops) || !(tol > 0)) return SS_E_INVALID_ARG;
-    if (method != SS_TRACE_BICGSTAB && method != SS_INVPOW_BICGSTAB) return SS_E_INVALID_ARG;
+    if (!S || !ticket || !H || N < 1 || N > 46340 || n_cops < 0 || (n_cops > 0 && !c_ops) || !(tol > 0) ||
+        !std::isfinite(tol))
+        return SS_E_INVALID_ARG;
+    if (method < SS_TRACE_BICGSTAB || method > SS_AUTO) return SS_E_INVALID_ARG;
     try {
-        ss_options o;
-        ss_options_default(&o);
-        if (opt) o = *opt;
-        // the server runs the workgroup-resident solver only
-        if (!ss::use_workgroup_n(N * N, method, o) || N > 46340) return SS_E_INVALID_ARG;
         std::unique_ptr<ss::Request> r(new ss::Request());
         r->H = ss::copy_in(H, N, "H");
         for (int k = 0; k < n_cops; ++k) r->C.push_back(ss::copy_in(&c_ops[k], N, "c_ops[k]"));
@@ -353,15 +466,24 @@ int ss_submit(ss_server S, const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_c
         if (r->opt.maxiter <= 0) r->opt.maxiter = 1000;
         if (r->opt.max_outer <= 0) r->opt.max_outer = 20;
         if (r->opt.gmres_m <= 0) r->opt.gmres_m = 20;
+        if (r->opt.fill <= 0) r->opt.fill = 10.0;
+        if (r->opt.drop_tol < 0) r->opt.drop_tol = 1e-4;
+        SS_REQUIRE(r->opt.prec == SS_FP64 || r->opt.prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
+        SS_REQUIRE(r->opt.ilu == SS_ILU0 || r->opt.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
+        SS_REQUIRE(r->opt.ordering == SS_ORDER_RCM || r->opt.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG,
+                   "unknown ordering");
         r->footprint = ss::predict_footprint(r->H, r->C, r->opt.prec);
         std::lock_guard<std::mutex> lk(S->mu);
+        r->arrival = std::chrono::steady_clock::now();
+        S->last_arrival = r->arrival;
         r->ticket = S->next_ticket++;
         *ticket = r->ticket;
         S->all[r->ticket] = r.get();
         S->queued.push_back(r.release());
-        S->cv.notify_all();
+        S->cv.notify_one();
         return SS_OK;
     } catch (const ss::Error &e) {
+        ss::set_last_error(e.what());
         return e.code;
     } catch (...) {
         return SS_E_OOM;
@@ -382,13 +504,37 @@ int ss_poll(ss_server S, uint64_t ticket, double *rho_out, ss_info *info) {
     const int st = r->status;
     if (st != SS_OK) ss::set_last_error(r->error);
     if (info) *info = r->info;
+    int rc = st;
     if (rho_out && !r->rho.empty()) {
         const size_t bytes = sizeof(double) * r->rho.size();
-        if (ss::is_device_ptr(rho_out)) (void)hipMemcpy(rho_out, r->rho.data(), bytes, hipMemcpyHostToDevice);
-        else std::memcpy(rho_out, r->rho.data(), bytes);
+        if (ss::is_device_ptr(rho_out)) {
+            const hipError_t e = ss::hip_quiet(hipMemcpy(rho_out, r->rho.data(), bytes, hipMemcpyHostToDevice));
+            if (e != hipSuccess) {
+                ss::set_last_error(std::string("ss_poll: hipMemcpy of rho to the device: ") + hipGetErrorString(e));
+                rc = SS_E_HIP;
+                if (info) info->status = rc;
+            }
+        } else {
+            std::memcpy(rho_out, r->rho.data(), bytes);
+        }
     }
     delete r;
-    return st;
+    return rc;
+}
+
+int ss_server_stats(ss_server S, ss_server_stats_t *st) {
+    if (!S || !st) return SS_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    st->budget_bytes = S->budget;
+    st->resident_bytes = S->used;
+    st->peak_resident_bytes = S->peak_used;
+    st->resident = S->resident;
+    st->queued = (int32_t)S->queued.size();
+    st->groups = S->groups;
+    st->largest_group = S->max_group_seen;
+    st->workers = (int32_t)S->workers.size();
+    st->max_group = S->max_group;
+    return SS_OK;
 }
 
 int ss_server_drain(ss_server S) {
@@ -409,12 +555,10 @@ void ss_server_destroy(ss_server S) {
         S->stop = true;
         S->cv.notify_all();
     }
-    S->scheduler.join();
+    for (auto &t : S->workers) t.join();
     for (auto &kv : S->all) delete kv.second;
     for (ss::Request *r : S->queued)
         if (S->all.find(r->ticket) == S->all.end()) delete r;
-    if (S->solve_stream) (void)hipStreamDestroy(S->solve_stream);
-    if (S->pinned) (void)hipHostFree(S->pinned);
     delete S;
 }
 

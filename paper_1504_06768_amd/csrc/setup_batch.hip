@@ -756,6 +756,7 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
         P.max_outer = o.max_outer > 0 ? o.max_outer : 20;
         P.tol = tols[k];
         P.rtol_in = (o.inner_tol > 0) ? o.inner_tol : (o.prec == SS_MIXED ? 1e-4 : 0.0);
+        P.force_breakdown = (o.flags & SS_FLAG_FORCE_BREAKDOWN) ? 1 : 0;
         P.sigma = o.sigma;
         P.w = h->w;
         P.A = ap_of<T>(h).view();

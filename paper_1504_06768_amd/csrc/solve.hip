@@ -328,6 +328,7 @@ void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrB
     P.max_outer = o.max_outer > 0 ? o.max_outer : 20;
     P.tol = tol;
     P.rtol_in = (o.inner_tol > 0) ? o.inner_tol : (o.prec == SS_MIXED ? 1e-4 : 0.0);
+    P.force_breakdown = (o.flags & SS_FLAG_FORCE_BREAKDOWN) ? 1 : 0;
     P.sigma = o.sigma;
     P.w = h->w;
     P.A = Ain.view();
@@ -497,8 +498,8 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         d2h(&hr, B.res.get(), 1, s);
         float kms = 0.f;
         SS_HIP(hipEventElapsedTime(&kms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        hip_quiet(hipEventDestroy(e0));
+        hip_quiet(hipEventDestroy(e1));
         st.t_kernel_ms = kms;
         if (std::getenv("SS_DEBUG")) {
             std::fprintf(stderr,
@@ -613,7 +614,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
             convert<T, double2>(n, r.get(), bT.get(), sc + 4, s);
             KrylovResult kr;
             if (!use_gmres) {
-                kr = K.bicgstab(bT.get(), dT.get(), rtol_in, o.maxiter);
+                kr = K.bicgstab(bT.get(), dT.get(), rtol_in, o.maxiter, (o.flags & SS_FLAG_FORCE_BREAKDOWN) != 0);
                 st.breakdowns += kr.breakdown;
                 if (!kr.converged && kr.breakdown) {
                     st.inner += kr.iters;
@@ -941,8 +942,8 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         SS_HIP(hipEventRecord(e1, s));
         SS_HIP(hipEventSynchronize(e1));
         SS_HIP(hipEventElapsedTime(&kms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        hip_quiet(hipEventDestroy(e0));
+        hip_quiet(hipEventDestroy(e1));
     }
     const double t_solve = now_ms() - t1;
     mark("workgroup solve");

@@ -20,12 +20,24 @@ struct Error : std::runtime_error {
     Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// A failed HIP call also leaves its code behind as the calling thread's
+// "last error", which the hipGetLastError() that follows a kernel launch
+// would report as that launch's failure.  Every failure is therefore read
+// back (cleared) where it is handled: SS_HIP clears before it throws, and a
+// call whose failure is tolerated goes through hip_quiet.
+inline hipError_t hip_quiet(hipError_t e) {
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
 #define SS_HIP(call)                                                                   \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \
-        if (e_ != hipSuccess)                                                          \
+        if (e_ != hipSuccess) {                                                        \
+            (void)hipGetLastError();                                                   \
             throw ::ss::Error(e_ == hipErrorOutOfMemory ? SS_E_OOM : SS_E_HIP,         \
                               std::string(#call) + ": " + hipGetErrorString(e_));      \
+        }                                                                              \
     } while (0)
 
 #define SS_REQUIRE(cond, code, msg)                                                    \

@@ -91,7 +91,9 @@ void release_event(Cache &c, hipEvent_t ev) {
 bool event_done(Cache &c, hipEvent_t ev) {
     auto it = c.evs.find(ev);
     if (it != c.evs.end() && it->second.done) return true;
-    if (hipEventQuery(ev) != hipSuccess) return false;
+    // hipErrorNotReady (work still queued) is also left as the thread's last
+    // error: cleared here, so no later launch check reports it
+    if (hip_quiet(hipEventQuery(ev)) != hipSuccess) return false;
     if (it != c.evs.end()) it->second.done = true;
     return true;
 }
@@ -105,7 +107,7 @@ void raw_free(void *p, bool user) {
     if (user) {
         if (g_user_free) g_user_free(p, g_user_ctx);
     } else {
-        (void)hipFree(p);
+        hip_quiet(hipFree(p));
     }
 }
 
@@ -189,7 +191,7 @@ void trim_device_cache() {
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto &kv : c.free_by_cls) {
         for (Cached &b : kv.second) {
-            (void)hipEventSynchronize(b.ev);
+            hip_quiet(hipEventSynchronize(b.ev));
             raw_free(b.p, b.user);
             release_event(c, b.ev);
         }
@@ -219,7 +221,6 @@ void *dev_alloc(size_t bytes) {
                     return p;
                 }
             }
-            (void)hipGetLastError();  // hipErrorNotReady from the queries
         }
     }
     const bool user = g_user_alloc != nullptr;
@@ -250,7 +251,8 @@ void dev_free(void *p) {
             }
             hipEvent_t ev = take_event(c);
             if (ev) {
-                if (!l.s) (void)hipDeviceSynchronize();  // no stream known: wait for everything
+                // (dev_free runs in destructors: failures are cleared, never thrown)
+                if (!l.s) hip_quiet(hipDeviceSynchronize());  // no stream known: wait for everything
                 if (hipEventRecord(ev, l.s) == hipSuccess) {
                     c.evs[ev] = EvState{1, false};
                     c.free_by_cls[l.cls].push_back(Cached{p, ev, l.user});
@@ -262,7 +264,7 @@ void dev_free(void *p) {
             }
         }
     }
-    if (l.s) (void)hipStreamSynchronize(l.s);
+    if (l.s) hip_quiet(hipStreamSynchronize(l.s));
     raw_free(p, l.user);  // uncached (hipFree also waits for the device)
 }
 

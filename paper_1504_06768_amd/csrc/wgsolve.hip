@@ -284,9 +284,10 @@ void levels_batch(const LevelJob *jobs, int count, hipStream_t s) {
     h2d(dj.get(), jobs, (size_t)count, s);
     if (max_n <= LEVELS_LDS_MAX) {
         const size_t bytes = sizeof(int) * (size_t)std::max(max_n, 1);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_levels_batch_lds<UPPER>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        (void)hipGetLastError();
+        // the attribute is the largest size any call uses, so that a launch
+        // from another thread never meets a smaller limit set in between
+        hip_quiet(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_levels_batch_lds<UPPER>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(int) * LEVELS_LDS_MAX)));
         k_levels_batch_lds<UPPER><<<count, 1024, bytes, s>>>(dj.get());
     } else {
         k_levels_batch<UPPER><<<count, 1024, 0, s>>>(dj.get());
@@ -647,7 +648,8 @@ __device__ __forceinline__ InnerStats blk_bicgstab(const WgProblem<T> &P, const 
                                                    double2 (*red)[BS / 64 + 1]) {
     const int n = P.n;
     T *r = P.work, *rh = r + n, *p = rh + n, *v = p + n, *sv = v + n, *t = sv + n, *ph = t + n, *sh = ph + n;
-    const double bd_eps = sizeof(typename RealOf<T>::type) == 8 ? 1e-30 : 1e-14;
+    // (a threshold whose square overflows makes every breakdown test fire)
+    const double bd_eps = P.force_breakdown ? 1e300 : (sizeof(typename RealOf<T>::type) == 8 ? 1e-30 : 1e-14);
     InnerStats st = {0, 0, 0, 0, 0};
     double2 q1[1] = {mk(0.0, 0.0)};
     for (int i = threadIdx.x; i < n; i += BS) {
@@ -916,19 +918,17 @@ __global__ void __launch_bounds__(BS) k_wg_solve(const WgProblem<T> *probs) {
 }
 
 static size_t lds_budget() {
-    static size_t cached = 0;
-    if (!cached) {
+    // (initialised once, thread-safe: servers set up groups from several threads)
+    static const size_t cached = []() -> size_t {
         int dev = 0;
         hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-            size_t b = prop.sharedMemPerBlock;
+        if (hip_quiet(hipGetDevice(&dev)) == hipSuccess && hip_quiet(hipGetDeviceProperties(&prop, dev)) == hipSuccess) {
+            const size_t b = prop.sharedMemPerBlock;
             // static LDS of the kernel (reduction scratch) stays below 1 KB
-            cached = b > 2048 ? b - 2048 : 0;
-        } else {
-            (void)hipGetLastError();
-            cached = 64 * 1024 - 2048;
+            return b > 2048 ? b - 2048 : 0;
         }
-    }
+        return 64 * 1024 - 2048;
+    }();
     return cached;
 }
 
@@ -953,15 +953,13 @@ void wg_solve(const WgProblem<T> *probs, int count, int max_n, int max_levels, h
     const size_t ptr_bytes = sizeof(int) * wg_ptr_ints((size_t)max_n, max_levels);
     const size_t bytes = (size_t)max_n * sizeof(T) + ptr_bytes;
     if (bytes <= lds_budget()) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        (void)hipGetLastError();
+        hip_quiet(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_budget()));
         k_wg_solve<T, WG_BS, true><<<count, WG_BS, bytes, s>>>(probs);
     } else {
         SS_REQUIRE(ptr_bytes <= lds_budget(), SS_E_INVALID_ARG, "too many levels for the workgroup solver");
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ptr_bytes);
-        (void)hipGetLastError();
+        hip_quiet(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wg_solve<T, WG_BS, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_budget()));
         k_wg_solve<T, WG_BS, false><<<count, WG_BS, ptr_bytes, s>>>(probs);
     }
     SS_HIP(hipGetLastError());

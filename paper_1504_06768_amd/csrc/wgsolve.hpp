@@ -24,6 +24,7 @@ struct WgProblem {
     int n, d, q0, trace;      // trace: 1 = trace-row system, 0 = inverse power
     int nlev_l, nlev_u;
     int maxiter, max_outer;
+    int force_breakdown;      // SS_FLAG_FORCE_BREAKDOWN: every breakdown test fires
     double tol, rtol_in, sigma;
     double2 w;
     Csr<T> A;                 // inner-precision P A P^T

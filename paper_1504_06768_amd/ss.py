@@ -27,7 +27,7 @@ SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
 SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS, SS_FLAG_COND_EST = 16, 32, 64, 128
-SS_FLAG_MATRIX_FREE = 256
+SS_FLAG_MATRIX_FREE, SS_FLAG_FORCE_BREAKDOWN = 256, 512
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
 SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS, SS_OP_APPLY_L = 5, 6, 7, 8
@@ -111,6 +111,7 @@ def _load():
         "ss_submit": (ctypes.c_int, [P, P, P, I32, I64, I32, D, P, P]),
         "ss_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, P]),
         "ss_server_drain": (ctypes.c_int, [P]),
+        "ss_server_stats": (ctypes.c_int, [P, P]),
         "ss_server_destroy": (None, [P]),
         "ss_last_error": (ctypes.c_char_p, []),
         "ss_set_stream": (ctypes.c_int, [P]),
@@ -129,7 +130,7 @@ _lib = _load()
 EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_build_liouvillian_batch", "ss_solve",
             "ss_solve_batch", "ss_liouv_free", "ss_liouv_shape",
             "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile", "ss_time_operator",
-            "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_destroy",
+            "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_stats", "ss_server_destroy",
             "ss_last_error", "ss_set_stream", "ss_set_allocator", "ss_trim_cache", "ss_version")
 
 
@@ -231,7 +232,7 @@ def _ptr(x) -> int:
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
             no_fallback=False, trace_row=-1, path="auto", trsv="auto", cond_est=False,
-            matrix_free=False) -> _Options:
+            matrix_free=False, force_breakdown=False) -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -248,6 +249,8 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
         o.flags |= SS_FLAG_COND_EST
     if matrix_free:
         o.flags |= SS_FLAG_MATRIX_FREE
+    if force_breakdown:
+        o.flags |= SS_FLAG_FORCE_BREAKDOWN
     return o
 
 
@@ -432,6 +435,13 @@ def bandwidth_profile(L: Liouvillian, which=SS_MAT_A_PERM):
     return B.value, P.value
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
+                ("peak_resident_bytes", ctypes.c_uint64), ("resident", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("groups", ctypes.c_uint64), ("largest_group", ctypes.c_uint64),
+                ("workers", ctypes.c_int32), ("max_group", ctypes.c_int32)]
+
+
 class Server:
     """ss_server_*: continuous-batching request server."""
 
@@ -468,6 +478,12 @@ class Server:
 
     def drain(self):
         _check(_lib.ss_server_drain(self.handle), "ss_server_drain")
+
+    def stats(self) -> dict:
+        """ss_server_stats: budget, resident and peak footprint, counts."""
+        st = _ServerStats()
+        _check(_lib.ss_server_stats(self.handle, ctypes.byref(st)), "ss_server_stats")
+        return {name: getattr(st, name) for name, _ in st._fields_}
 
     def close(self):
         if self.handle:

@@ -12,7 +12,7 @@ _spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(
 bench = importlib.util.module_from_spec(_spec)
 _spec.loader.exec_module(bench)
 
-SOLVER = "void ss::k_wg_solve<HIP_vector_type<float, 2u>, 512, true>(ss::WgProblem<HIP_vector_type<float, 2u> > const*)"
+KERNEL = "void ss::k_trsv_slots<HIP_vector_type<double, 2u>, false>(int, int4 const*, int const*, ...)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
@@ -32,8 +32,10 @@ def test_traffic_record_scales_each_counter_by_the_copy(tmp_path):
     copy_kib = bench.COPY_BYTES / 1024
     grid = bench.COPY_BYTES // 2048
     # the copy reads its bytes twice over in FETCH_SIZE (factor 1/2) and once in WRITE_SIZE
-    _db(tmp_path / "f.db", "FETCH_SIZE", [(COPY, 512, 3.0), (COPY, grid, copy_kib / 2), (SOLVER, grid, 1000.0)])
-    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, copy_kib), (SOLVER, grid, 250.0)])
+    # two dispatches of the kernel: the record holds their mean
+    _db(tmp_path / "f.db", "FETCH_SIZE", [(COPY, 512, 3.0), (COPY, grid, copy_kib / 2), (KERNEL, grid, 900.0),
+                                          (KERNEL, grid, 1100.0)])
+    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, copy_kib), (KERNEL, grid, 250.0)])
     out = tmp_path / "traffic.json"
     rec = bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(out))
     assert json.load(open(out)) == rec
@@ -43,12 +45,14 @@ def test_traffic_record_scales_each_counter_by_the_copy(tmp_path):
     assert rec["write_bytes_per_launch"] == pytest.approx(250.0 * 1024)
     assert rec["hbm_bytes_per_launch"] == pytest.approx(1000.0 * 1024 * 2.0 + 250.0 * 1024)
     assert rec["sources_sha256"] == bench.source_digest(bench.KERNEL_SOURCE)
+    assert rec["kernel_match"] == bench.KERNEL_MATCH
+    assert rec["dispatches"] == {"fetch": 2, "write": 1}
 
 
 def test_traffic_record_needs_the_solver_and_the_copy(tmp_path):
     grid = bench.COPY_BYTES // 2048
-    _db(tmp_path / "f.db", "FETCH_SIZE", [(SOLVER, grid, 1000.0)])
-    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, 1.0), (SOLVER, grid, 1.0)])
+    _db(tmp_path / "f.db", "FETCH_SIZE", [(KERNEL, grid, 1000.0)])
+    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, 1.0), (KERNEL, grid, 1.0)])
     with pytest.raises(SystemExit):
         bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(tmp_path / "t.json"))
 
@@ -75,5 +79,9 @@ def test_source_digest_follows_included_headers(tmp_path):
 
 
 def test_committed_record_matches_the_current_sources():
-    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        pytest.skip("no counter record committed for the current dominant kernel")
+    rec = json.load(open(path))
+    assert rec["kernel_match"] == bench.KERNEL_MATCH
     assert rec["sources_sha256"] == bench.source_digest(rec["source"])
