@@ -12,6 +12,7 @@ product-form special cases:
 import sys
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import qsystems as qs
@@ -93,3 +94,73 @@ def test_spin_chain_auto_chooses_inverse_power():
         _say("spin5 auto", prec, info["method"], info["bandwidth"], info["inner_its"])
         assert info["method"] == ssl.SS_INVPOW_BICGSTAB
         assert np.max(np.abs(rho - steady_state_dense(s.H, s.c_ops))) <= tol
+
+
+# ------------------------------------------------ Kerr chain at J = 0.3
+@pytest.fixture(scope="module")
+def chain_reference():
+    """The oracle's CPU fp64 sparse reference on the Kerr-chain workload,
+    solved to ||L rho||_2 <= 1e-12 (RCM-ordered ILU(0)-BiCGSTAB, C loops)."""
+    from oracle.sparse_ref import steady_state_iterative
+    s = qs.config(4)
+    rho, info = steady_state_iterative(s.H, s.c_ops, tol=1e-12)
+    _say("chain cpu reference", {k: v for k, v in info.items() if k != "weight"})
+    assert info["resid_l2"] <= 1e-12
+    return s, rho
+
+
+@pytest.mark.parametrize("method", ["invpow_bicgstab", "trace_bicgstab", "invpow_gmres"])
+def test_kerr_chain_methods_agree_with_the_cpu_reference(chain_reference, method):
+    """Cross-method agreement at the workload's own parameters: inverse power
+    and the trace row, BiCGSTAB and GMRES, all fp64 to 1e-12, each within 1e-8
+    of the CPU fp64 sparse reference (so within 2e-8 of each other)."""
+    s, ref = chain_reference
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, method, tol=1e-12, prec="fp64", raise_on_error=False)
+    err = float(np.max(np.abs(rho - ref)))
+    _say("chain", method, "fp64", info["status"], info["outer_its"], info["inner_its"], info["resid_l2"], err)
+    assert info["status"] == 0 and info["resid_l2"] <= 1e-12
+    assert err <= 1e-8
+
+
+def test_kerr_chain_mixed_agrees_with_the_cpu_reference(chain_reference):
+    s, ref = chain_reference
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, "invpow_bicgstab", tol=1e-10, prec="mixed", raise_on_error=False)
+    err = float(np.max(np.abs(rho - ref)))
+    _say("chain invpow mixed", info["outer_its"], info["inner_its"], info["resid_l2"], err)
+    assert info["status"] == 0 and info["resid_l2"] <= 1e-10
+    assert err <= 1e-6
+
+
+def test_kerr_chain_ilu0_reproduces_a_on_sampled_rows():
+    """(L U)_ij = a_ij on the pattern of P L~ P^T for 2000 sampled rows of the
+    Kerr chain (n = 10^6): the zero-fill factorisation at full size.  (The
+    trace-row matrix has no guarded pivot here; the shifted one has the
+    guarded -sigma of the ground-state population, whose replacement the
+    property does not hold for.)"""
+    s = qs.config(4)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    _, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, raise_on_error=False)
+    assert info["pivots_guarded"] == 0
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    LU = ssl.export_csr(L, ssl.SS_MAT_LU)
+    L.free()
+    n = Ap.shape[0]
+    rows = np.sort(np.random.default_rng(11).choice(n, 2000, replace=False))
+    ip, ix, dv = LU.indptr, LU.indices, LU.data
+    r_, c_, v_ = [], [], []
+    for k, i in enumerate(rows):
+        cols, vals = ix[ip[i]:ip[i + 1]], dv[ip[i]:ip[i + 1]]
+        low = cols < i
+        r_ += [k] * (int(low.sum()) + 1)
+        c_ += cols[low].tolist() + [i]
+        v_ += vals[low].tolist() + [1.0]
+    R = sp.csr_matrix((np.asarray(v_, dtype=np.complex128), (r_, c_)), shape=(len(rows), n))
+    U = sp.triu(LU, format="csr")
+    P = (R @ U).tocsr()
+    A_rows = Ap[rows].tocoo()
+    got = np.asarray(P[A_rows.row, A_rows.col]).ravel()
+    scale = np.abs(Ap.data).max()
+    _say("chain ilu0 sampled rows: max |(LU)_ij - a_ij| / max|a| =", np.max(np.abs(got - A_rows.data)) / scale)
+    assert np.max(np.abs(got - A_rows.data)) <= 1e-11 * scale

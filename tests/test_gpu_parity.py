@@ -135,14 +135,17 @@ def test_rcm_permutation_bit_exact(system, method):
     assert (B, P) == (oord.bandwidth(stored)[2], oord.profile(stored)[2])
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_rcm_on_workloads(k):
+@pytest.mark.parametrize("k,method", [(1, "trace_bicgstab"), (2, "trace_bicgstab"), (3, "trace_bicgstab"),
+                                      (4, "trace_bicgstab"), (4, "invpow_bicgstab")])
+def test_rcm_on_workloads(k, method):
+    """Bit-exact RCM on the workloads: C1 and C2 take the one-workgroup
+    search, C3 (n = 360000) and C4 (n = 10^6) the multi-kernel level search."""
     s = qs.config(k)
-    _say("rcm workload", k)
+    _say("rcm workload", k, method)
     Lo = liouvillian_sparse(s.H, s.c_ops)
-    Ao = otr.modified(Lo, pop=otr.trace_population(Lo))[0]
+    Ao = otr.modified(Lo, pop=otr.trace_population(Lo))[0] if method.startswith("trace") else otr.shifted(Lo)
     L = ssl.build_liouvillian(s.H, s.c_ops)
-    ssl.prepare(L, "trace_bicgstab")
+    ssl.prepare(L, method)
     assert np.array_equal(ssl.export_perm(L), oord.rcm(Ao))
 
 
@@ -160,6 +163,27 @@ def test_ilu0_matches_oracle(name):
     rel = np.abs(LUg.data - LUo.data) / np.maximum(np.abs(LUo.data), 1e-300)
     big = np.abs(LUo.data) > 1e-10 * np.abs(LUo.data).max()
     assert np.max(rel[big]) <= 1e-11
+    # every entry, small ones included, to an absolute bound scaled to the factors
+    assert np.max(np.abs(LUg.data - LUo.data)) <= 1e-12 * np.abs(LUo.data).max()
+
+
+def test_ilu0_pivot_guard_on_the_spin_chain():
+    """Dephasing leaves population rows of L~ with zero diagonals that the
+    trace row does not cover: zero-fill ILU guards those pivots.  The GPU
+    counts them as the oracle does and its factors equal the oracle's guarded
+    ILU(0) (guard 1e-8, boost 0.1) entry by entry."""
+    s = qs.spin_chain(3)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(L, "trace_bicgstab")
+    Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
+    LUg = ssl.export_csr(L, ssl.SS_MAT_LU)
+    LUo, g = oilu.ilu0(Ap, guard=1e-8, boost=0.1)
+    _say("spin3 guarded pivots", g)
+    assert g > 0
+    assert np.array_equal(LUg.indices, LUo.indices)
+    assert np.max(np.abs(LUg.data - LUo.data)) <= 1e-12 * np.abs(LUo.data).max()
+    _, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, raise_on_error=False, path="device")
+    assert info["pivots_guarded"] == g
 
 
 def test_ilu0_property_on_jc40():
@@ -413,3 +437,45 @@ def test_info_reports_bandwidth_profile_and_condition_estimate():
     assert info["profile"] == oord.profile(Ap)[2]
     ref = oilu.condition_estimate(ssl.export_csr(L, ssl.SS_MAT_LU))
     assert abs(info["cond_est"] - ref) <= 1e-9 * ref
+
+
+# ------------------------------------------------------------ breakdown
+@pytest.mark.parametrize("path", ["workgroup", "device"])
+def test_forced_breakdown_falls_back_to_gmres(path):
+    """SS_FLAG_FORCE_BREAKDOWN makes every BiCGSTAB breakdown test fire: the
+    solve restarts, gives up on BiCGSTAB and finishes with GMRES (or reports
+    SS_E_BREAKDOWN when no fallback is allowed)."""
+    s = qs.config(1)
+    ref = steady_state_dense(s.H, s.c_ops)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, path=path, force_breakdown=True)
+    _say("forced breakdown", path, info["breakdowns"], info["fell_back"], info["inner_its"])
+    assert info["status"] == 0 and info["fell_back"] == 1 and info["breakdowns"] >= 1
+    assert np.max(np.abs(rho - ref)) <= 1e-8
+    with pytest.raises(ssl.SolverError) as e:
+        ssl.solve(L, "trace_bicgstab", tol=1e-10, path=path, force_breakdown=True, no_fallback=True)
+    assert e.value.code == ssl.SS_E_BREAKDOWN
+    # without the flag the same solve needs no fallback
+    _, info = ssl.solve(L, "trace_bicgstab", tol=1e-10, path=path)
+    assert info["fell_back"] == 0 and info["breakdowns"] == 0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_forced_breakdown_in_a_batch_and_in_the_server(prec, tol):
+    systems = [qs.kerr(N, delta=0.2 * k, E=0.5 + 0.1 * k) for k, N in enumerate((8, 12, 16))]
+    refs = [steady_state_dense(s.H, s.c_ops) for s in systems]
+    Ls = [ssl.build_liouvillian(s.H, s.c_ops) for s in systems]
+    rhos, infos = ssl.solve_batch(Ls, "trace_bicgstab", tol=1e-10, prec=prec, force_breakdown=True)
+    for rho, info, ref in zip(rhos, infos, refs):
+        assert info["status"] == 0 and info["fell_back"] == 1
+        assert np.max(np.abs(rho - ref)) <= tol
+    for L in Ls:
+        L.free()
+    S = ssl.Server(hbm_budget_bytes=1 << 30, max_slots=16)
+    tk = [S.submit(s.H, s.c_ops, "trace_bicgstab", 1e-10, prec=prec, force_breakdown=True) for s in systems]
+    S.drain()
+    for t, ref in zip(tk, refs):
+        rho, info = S.poll(t)
+        assert info["status"] == 0 and info["fell_back"] == 1
+        assert np.max(np.abs(rho - ref)) <= tol
+    S.close()
