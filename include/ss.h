@@ -141,9 +141,12 @@ typedef struct {
 #define SS_FLAG_COND_EST  128  /* fill info.cond_est (one extra application
                                   of the preconditioner)                      */
 #define SS_FLAG_TRSV_LEVELS 64 /* device-wide path: triangular solves
-                                  sync-free over all CUs in level order
-                                  (default: BLOCK up to n = 65536, else
-                                  LEVELS)                                     */
+                                  sync-free over all CUs in level order     */
+#define SS_FLAG_TRSV_GROUPS 1024 /* device-wide path: triangular solves
+                                  sync-free over all CUs in level order, 16
+                                  lanes per row, polling gated near the
+                                  frontier (default: BLOCK up to n = 65536,
+                                  else GROUPS)                               */
 #define SS_FLAG_FORCE_BREAKDOWN 512 /* testing hook: every BiCGSTAB breakdown
                                   test fires (as if the shadow residual were
                                   orthogonal to the residual), so the restart
@@ -264,7 +267,7 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
 #define SS_OP_SPMV_APERM  1  /* y = (P A P^T) x  (prec selects c128 / c64)     */
 #define SS_OP_PRECOND     2  /* y = (LU)^-1 x    (prec selects c128 / c64),
                                 the solver's own choice of the ways below:
-                                BLOCK up to n = 65536, LEVELS above        */
+                                BLOCK up to n = 65536, GROUPS above        */
 #define SS_OP_LSOLVE      3  /* y = L_f^-1 x     unit lower factor             */
 #define SS_OP_USOLVE      4  /* y = U_f^-1 x     upper factor                  */
 #define SS_OP_PRECOND_SYNCFREE 5 /* y = (LU)^-1 x, sync-free solves over all
@@ -279,6 +282,10 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
                                     X the d x d matrix whose columns are the
                                     consecutive d-blocks of x (eq. lindblad,
                                     column stacking); needs no ss_prepare  */
+#define SS_OP_PRECOND_GROUPS   9 /* y = (LU)^-1 x, sync-free solves over all
+                                    CUs in level order, 16 lanes per row
+                                    (one factor entry each), polling gated
+                                    two levels behind the frontier         */
 
 /* Apply one operator of the prepared handle to x (n complex, host or
  * device) giving y (n complex, host or device).  prec = SS_FP64 or SS_MIXED:

@@ -29,7 +29,8 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
 # per-source flags: the factorisations round every product and sum on their
 # own (no fused multiply-add), like a plain sequential implementation, so the
 # one-system and batched ILU(0) kernels give the same factors
-EXTRA = {"ilut.hip": ["-ffp-contract=off"], "ilu.hip": ["-ffp-contract=off"]}
+EXTRA = {"ilut.hip": ["-ffp-contract=off"], "ilu.hip": ["-ffp-contract=off"],
+         "trsv_groups.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

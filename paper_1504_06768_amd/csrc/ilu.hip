@@ -682,13 +682,22 @@ inline unsigned slots_blocks(int n) {
 template <typename T>
 void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s, int m) {
     build_levels(lu64, diag, lo, up, s);
-    pack_side<T>(lo, LU->view(), false, pl, s);
-    pack_side<T>(up, LU->view(), true, pu, s);
-    if (m == PRE_AUTO) m = (n <= PRE_BLOCK_MAX_N) ? PRE_BLOCK : PRE_LEVELS;
+    if (m == PRE_AUTO) m = (n <= PRE_BLOCK_MAX_N) ? PRE_BLOCK : PRE_GROUPS;
+    if (m == PRE_GROUPS) {
+        // the 16-byte coherent accesses address the vector through a buffer
+        // resource limited to 2^31 bytes
+        SS_REQUIRE((int64_t)n * (int64_t)sizeof(T) < ((int64_t)1 << 31), SS_E_INVALID_ARG,
+                   "row-group triangular solves: system too large");
+        group_gates(lo, n, gate_lo, s);
+        group_gates(up, n, gate_up, s);
+    } else {
+        pack_side<T>(lo, LU->view(), false, pl, s);
+        pack_side<T>(up, LU->view(), true, pu, s);
+    }
     if (m == PRE_BLOCK) bl.resize((size_t)std::max(n, 1));
-    if (m == PRE_LEVELS) {
-        lev_ctr.resize(2);
-        SS_HIP(hipMemsetAsync(lev_ctr.get(), 0, 2 * sizeof(unsigned), s));
+    if (m == PRE_LEVELS || m == PRE_GROUPS) {
+        lev_ctr.resize(4);
+        SS_HIP(hipMemsetAsync(lev_ctr.get(), 0, 4 * sizeof(unsigned), s));
     }
     mode = m;
 }
@@ -703,6 +712,14 @@ void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
         B.pl = &pl;
         B.pu = &pu;
         precond_block<T>(B, LU->view(), b, out, bl.get(), s, skip);
+        return;
+    }
+    if (mode == PRE_GROUPS) {
+        // y holds the sentinel between applies (the upper solve puts it
+        // back); the lower solve resets `out` for the upper one
+        trsv_groups<T>(lo, gate_lo.get(), false, LU->view(), b, y.get(), out, lev_ctr.get(), status.get(), skip, s);
+        trsv_groups<T>(up, gate_up.get(), true, LU->view(), y.get(), out, nullptr, lev_ctr.get(), status.get(), skip,
+                       s);
         return;
     }
     if (mode == PRE_LEVELS) {

@@ -57,8 +57,23 @@ void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s);
 // Ways of applying (L U)^-1: sync-free in row order over all CUs, one
 // workgroup stepping through the levels, sync-free in level order over all
 // CUs, or the choice by size.
-enum : int { PRE_ROWS = 0, PRE_BLOCK = 1, PRE_LEVELS = 2, PRE_AUTO = 3 };
+enum : int { PRE_ROWS = 0, PRE_BLOCK = 1, PRE_LEVELS = 2, PRE_AUTO = 3, PRE_GROUPS = 4 };
 constexpr int PRE_BLOCK_MAX_N = 65536;
+
+// Sync-free triangular solves over all CUs with 16 lanes per row, in level
+// order, polling gated two levels behind the frontier (trsv_groups.hip).
+// group_gates: for every task of 4 consecutive slots, the last row of the
+// level two below the level of its first slot (-1 if none).
+constexpr int GROUP_WAVES = 2048;  // persistent wavefronts per launch
+void group_gates(const LevelSched &ls, int n, DevBuf<int> &gate, hipStream_t s);
+// One triangular solve over the level schedule `ls` (lower: out = L^-1 in,
+// and `reset` -- the output of the following upper solve -- back to the
+// sentinel; upper: out = U^-1 in, and `in` back to the sentinel).  `out`
+// must hold the sentinel on entry; ctl: four control words at zero (zero
+// again on return).
+template <typename T>
+void trsv_groups(const LevelSched &ls, const int *gate, bool upper, const Csr<T> &LU, const T *in, T *out, T *reset,
+                 unsigned *ctl, unsigned *status, const int *skip, hipStream_t s);
 
 // M^-1 = (L U)^-1 applied with the sync-free triangular solves.
 template <typename T>
@@ -73,14 +88,16 @@ struct Precond {
     int mode = PRE_ROWS;
     LevelSched lo, up;
     PackedSide<T> pl, pu;
+    DevBuf<int> gate_lo, gate_up;  // PRE_GROUPS
     DevBuf<T> bl;
-    DevBuf<unsigned> lev_ctr;  // chunk counter and finished-wavefront counter (PRE_LEVELS)
+    DevBuf<unsigned> lev_ctr;  // control words of the level-order launches (PRE_LEVELS, PRE_GROUPS)
     void setup(const CsrBuf<T> *lu, const int *dg, int n_, hipStream_t s);
     // Build the level schedules (from the fp64 factors' pattern, which the
     // rounded copy shares) and packed factors, and switch apply() to a
     // level-scheduled solve: PRE_BLOCK (one workgroup, barrier per level),
-    // PRE_LEVELS (sync-free over all CUs in level order) or PRE_AUTO (the
-    // first for n <= PRE_BLOCK_MAX_N).
+    // PRE_LEVELS (sync-free over all CUs in level order), PRE_GROUPS (the
+    // same with 16 lanes per row and gated polling) or PRE_AUTO (PRE_BLOCK
+    // for n <= PRE_BLOCK_MAX_N, else PRE_GROUPS).
     void use_levels(const Csr<double2> &lu64, hipStream_t s, int m = PRE_AUTO);
     // out = (LU)^-1 b; out must not alias b or y.  When *skip != 0 on the
     // device, both solves return at once (used after convergence).

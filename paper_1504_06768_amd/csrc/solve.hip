@@ -533,6 +533,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         if (!(o.flags & SS_FLAG_SYNCFREE)) {
             const int mode = (o.flags & SS_FLAG_TRSV_BLOCK)    ? PRE_BLOCK
                              : (o.flags & SS_FLAG_TRSV_LEVELS) ? PRE_LEVELS
+                             : (o.flags & SS_FLAG_TRSV_GROUPS)   ? PRE_GROUPS
                                                                : PRE_AUTO;
             M.use_levels(h->LU.view(), s, mode);
         }

@@ -27,10 +27,11 @@ SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
 SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS, SS_FLAG_COND_EST = 16, 32, 64, 128
-SS_FLAG_MATRIX_FREE, SS_FLAG_FORCE_BREAKDOWN = 256, 512
+SS_FLAG_MATRIX_FREE, SS_FLAG_FORCE_BREAKDOWN, SS_FLAG_TRSV_GROUPS = 256, 512, 1024
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
 SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS, SS_OP_APPLY_L = 5, 6, 7, 8
+SS_OP_PRECOND_GROUPS = 9
 
 METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3, "auto": 4}
 PRECS = {"fp64": 0, "mixed": 1}
@@ -244,7 +245,7 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     o.flags = (SS_FLAG_HERMITIZE if hermitize else 0) | (SS_FLAG_NO_FALLBACK if no_fallback else 0)
     o.flags |= {"auto": 0, "device": SS_FLAG_DEVICE_WIDE, "workgroup": SS_FLAG_WORKGROUP}[path]
     o.flags |= {"auto": 0, "syncfree": SS_FLAG_SYNCFREE, "block": SS_FLAG_TRSV_BLOCK,
-                "levels": SS_FLAG_TRSV_LEVELS}[trsv]
+                "levels": SS_FLAG_TRSV_LEVELS, "groups": SS_FLAG_TRSV_GROUPS}[trsv]
     if cond_est:
         o.flags |= SS_FLAG_COND_EST
     if matrix_free:

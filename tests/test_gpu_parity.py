@@ -200,7 +200,8 @@ def test_ilu0_property_on_jc40():
 
 
 # ------------------------------------------------------------ SpMV / trsv
-PRECOND_OPS = (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE, ssl.SS_OP_PRECOND_BLOCK, ssl.SS_OP_PRECOND_LEVELS)
+PRECOND_OPS = (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE, ssl.SS_OP_PRECOND_BLOCK, ssl.SS_OP_PRECOND_LEVELS,
+               ssl.SS_OP_PRECOND_GROUPS)
 
 @pytest.mark.parametrize("name", ["kerr20", "jc8", "spin3"])
 def test_spmv_and_triangular_solves(name):
@@ -258,10 +259,16 @@ def test_level_scheduled_precond_on_workloads(k, prec, tol):
     Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
     x = np.random.default_rng(3).normal(size=Lf.shape[0]) + 0j
     refp = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
+    outs = {}
     for op in PRECOND_OPS:
         _say("   op", op)
         yp = ssl.apply(L, op, x, prec=prec)
         assert np.max(np.abs(yp - refp)) <= tol * np.max(np.abs(refp))
+        outs[op] = yp
+    # the sync-free variants consume a row's entries in the factor's order
+    # with the same arithmetic (no contraction): the same bits
+    for op in (ssl.SS_OP_PRECOND_LEVELS, ssl.SS_OP_PRECOND_GROUPS):
+        assert np.array_equal(outs[op], outs[ssl.SS_OP_PRECOND_SYNCFREE]), op
 
 
 # ------------------------------------------------------------ end to end
@@ -275,7 +282,7 @@ CASES = [(name, m) for name in ["kerr20", "jc8", "random7", "opto3x5"] for m in 
 CASES += [("spin3", "invpow_bicgstab"), ("spin3", "invpow_gmres")]
 
 
-DEVICE_PATHS = ["device", "device_syncfree", "device_levels"]
+DEVICE_PATHS = ["device", "device_syncfree", "device_levels", "device_groups"]
 CASES = [(n, m, p) for (n, m) in CASES for p in DEVICE_PATHS + (["workgroup"] if "bicgstab" in m else [])]
 
 
