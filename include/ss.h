@@ -128,7 +128,9 @@ typedef struct {
 } ss_options;
 
 #define SS_FLAG_HERMITIZE   1  /* return (rho + rho^+)/2                      */
-#define SS_FLAG_NO_FALLBACK 2  /* no GMRES fallback after BiCGSTAB breakdown  */
+#define SS_FLAG_NO_FALLBACK 2  /* no fallback: neither GMRES after a BiCGSTAB
+                                  breakdown nor iLUT + GMRES after an ILU(0)
+                                  solve that fails                            */
 #define SS_FLAG_DEVICE_WIDE 4  /* force the device-wide kernels (one kernel
                                   per step, all CUs) even for small systems   */
 #define SS_FLAG_WORKGROUP   8  /* force the workgroup-resident solve (whole
@@ -165,7 +167,10 @@ typedef struct {
     int32_t inner_its;       /* total Krylov iterations                       */
     int32_t breakdowns;      /* BiCGSTAB restarts after breakdown             */
     int32_t pivots_guarded;  /* ILU pivots replaced by the guard value        */
-    int32_t fell_back;       /* 1 if BiCGSTAB fell back to GMRES              */
+    int32_t fell_back;       /* 1 if the solve left its first method: BiCGSTAB
+                                breakdown -> GMRES, or, when ILU(0) cannot
+                                precondition the system, the whole solve
+                                again with iLUT and GMRES (device-wide)      */
     int32_t bandwidth;       /* B of the ordered matrix that was factorised   */
     int32_t path;            /* 0 device-wide kernels, 1 workgroup-resident
                                 with the solve vector in global memory, 2

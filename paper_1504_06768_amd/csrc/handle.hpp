@@ -34,6 +34,12 @@ struct ss_liouv_s {
     int guarded = 0;
     int diag_added = 0;        // explicit zero diagonals added to Ap
     double t_setup_ms = 0;
+    // level schedules of the factors and the gates of the row-group
+    // triangular solves, built by ss_prepare for the device-wide path and
+    // used by its solves and by ss_apply_noalloc
+    bool sched_ready = false;
+    ss::LevelSched sched_lo, sched_up;
+    ss::DevBuf<int> gate_lo, gate_up;
 };
 
 #include "wgsolve.hpp"
@@ -44,6 +50,9 @@ hipStream_t stream_of(ss_liouv h);    // the handle's stream, made the thread's 
 hipStream_t stream_peek(ss_liouv h);  // the handle's stream (current stream unchanged)
 void prepare(ss_liouv h, int method, const ss_options &o);
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info);
+// The same system again with iLUT and GMRES on the device-wide path (the
+// fallback when ILU(0)-preconditioned solves fail); sets info->fell_back.
+int solve_ilut_gmres(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info);
 // tols (optional, count entries) gives each system its own tolerance.
 int solve_batch(ss_liouv *hs, int count, int method, double tol, const ss_options &o, double **rho_out,
                 ss_info *infos, int *status, const double *tols = nullptr);

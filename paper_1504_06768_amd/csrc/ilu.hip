@@ -703,6 +703,18 @@ void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s, int m) {
 }
 
 template <typename T>
+void Precond<T>::borrow_groups(const LevelSched *lo_, const LevelSched *up_, const int *glo, const int *gup,
+                               hipStream_t s) {
+    blo = lo_;
+    bup = up_;
+    bglo = glo;
+    bgup = gup;
+    lev_ctr.resize(4);
+    SS_HIP(hipMemsetAsync(lev_ctr.get(), 0, 4 * sizeof(unsigned), s));
+    mode = PRE_GROUPS;
+}
+
+template <typename T>
 void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
     if (n == 0) return;
     if (mode == PRE_BLOCK) {
@@ -717,9 +729,10 @@ void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
     if (mode == PRE_GROUPS) {
         // y holds the sentinel between applies (the upper solve puts it
         // back); the lower solve resets `out` for the upper one
-        trsv_groups<T>(lo, gate_lo.get(), false, LU->view(), b, y.get(), out, lev_ctr.get(), status.get(), skip, s);
-        trsv_groups<T>(up, gate_up.get(), true, LU->view(), y.get(), out, nullptr, lev_ctr.get(), status.get(), skip,
-                       s);
+        const LevelSched &L0 = blo ? *blo : lo, &U0 = bup ? *bup : up;
+        const int *g0 = blo ? bglo : gate_lo.get(), *g1 = bup ? bgup : gate_up.get();
+        trsv_groups<T>(L0, g0, false, LU->view(), b, y.get(), out, lev_ctr.get(), status.get(), skip, s);
+        trsv_groups<T>(U0, g1, true, LU->view(), y.get(), out, nullptr, lev_ctr.get(), status.get(), skip, s);
         return;
     }
     if (mode == PRE_LEVELS) {

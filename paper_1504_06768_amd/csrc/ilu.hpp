@@ -99,6 +99,11 @@ struct Precond {
     // same with 16 lanes per row and gated polling) or PRE_AUTO (PRE_BLOCK
     // for n <= PRE_BLOCK_MAX_N, else PRE_GROUPS).
     void use_levels(const Csr<double2> &lu64, hipStream_t s, int m = PRE_AUTO);
+    // PRE_GROUPS over level schedules and gates owned by the caller (they
+    // must outlive this object)
+    void borrow_groups(const LevelSched *lo_, const LevelSched *up_, const int *glo, const int *gup, hipStream_t s);
+    const LevelSched *blo = nullptr, *bup = nullptr;
+    const int *bglo = nullptr, *bgup = nullptr;
     // out = (LU)^-1 b; out must not alias b or y.  When *skip != 0 on the
     // device, both solves return at once (used after convergence).
     void apply(const T *b, T *out, hipStream_t s, const int *skip = nullptr);

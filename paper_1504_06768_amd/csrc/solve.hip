@@ -195,6 +195,15 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     phase("ilu");
     prepare_finish(h, method, o, s, t0);
     phase("finish");
+    h->sched_ready = false;
+    if (!use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31)) {
+        build_levels(h->LU.view(), h->lu_diag.get(), h->sched_lo, h->sched_up, s);
+        group_gates(h->sched_lo, h->n, h->gate_lo, s);
+        group_gates(h->sched_up, h->n, h->gate_up, s);
+        h->sched_ready = true;
+        h->t_setup_ms = now_ms() - t0;
+        phase("levels");
+    }
 }
 
 // ------------------------------------------------------------ helpers
@@ -533,9 +542,13 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         if (!(o.flags & SS_FLAG_SYNCFREE)) {
             const int mode = (o.flags & SS_FLAG_TRSV_BLOCK)    ? PRE_BLOCK
                              : (o.flags & SS_FLAG_TRSV_LEVELS) ? PRE_LEVELS
-                             : (o.flags & SS_FLAG_TRSV_GROUPS)   ? PRE_GROUPS
+                             : (o.flags & SS_FLAG_TRSV_GROUPS) ? PRE_GROUPS
                                                                : PRE_AUTO;
-            M.use_levels(h->LU.view(), s, mode);
+            const bool groups = mode == PRE_GROUPS || (mode == PRE_AUTO && n > PRE_BLOCK_MAX_N);
+            if (groups && h->sched_ready)
+                M.borrow_groups(&h->sched_lo, &h->sched_up, h->gate_lo.get(), h->gate_up.get(), s);
+            else
+                M.use_levels(h->LU.view(), s, mode);
         }
         Krylov<T> K;
         K.init(Ain.view(), &M, s);
@@ -972,8 +985,8 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         std::fprintf(stderr, "[ss] batch of %d: solver per system: %.0f us total, %.0f us preconditioner, %.0f us SpMV, "
                      "%.1f inner iterations\n", count, tt / m, tp / m, ts / m, its / (double)hres.size());
     }
-    // systems whose BiCGSTAB broke down: again on their own with the
-    // device-wide GMRES; the others finish together
+    // systems whose BiCGSTAB broke down or stagnated: again on their own
+    // with iLUT and the device-wide GMRES; the others finish together
     std::vector<char> again((size_t)count, 0);
     std::vector<ss_liouv> fh;
     std::vector<const double2 *> fx;
@@ -1025,11 +1038,8 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
     parallel([&](int i) {
         if (!again[(size_t)i]) return;
         ss_liouv h = hs[i];
-        ss_options od = o;
-        od.flags |= SS_FLAG_DEVICE_WIDE;
-        const int gm = (method == SS_TRACE_BICGSTAB) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
-        code[(size_t)i] = solve(h, gm, tols[i], od, rho_out ? rho_out[i] : nullptr, infos ? infos + i : nullptr);
-        if (infos) infos[i].fell_back = 1;
+        code[(size_t)i] = solve_ilut_gmres(h, method, tols[i], o, rho_out ? rho_out[i] : nullptr,
+                                           infos ? infos + i : nullptr);
     });
     mark("finish (+ fallbacks)");
     int first = SS_OK;
@@ -1107,6 +1117,27 @@ static int choose_method(ss_liouv h, const ss_options &o) {
                                                                               : SS_TRACE_BICGSTAB;
 }
 
+// When zero-fill ILU cannot precondition a system (no diagonal dominance:
+// element growth in the factors, the failure the paper attributes to iLU),
+// the paper's own combination takes over: the dual-threshold iLUT with
+// restarted GMRES (section "Iterative Solvers"; GMRES on the trace-row
+// system is its recommended first choice, section "Conclusion").  Used
+// after BiCGSTAB and the GMRES fallback on the ILU(0) factors have both
+// failed; the solve is flagged info.fell_back.
+int solve_ilut_gmres(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {
+    ss_options od = o;
+    od.ilu = SS_ILUT;
+    od.flags |= SS_FLAG_DEVICE_WIDE;
+    od.flags &= ~SS_FLAG_WORKGROUP;
+    const int gm = is_trace(method) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;
+    prepare(h, gm, od);
+    int st;
+    if (od.prec == SS_MIXED) st = run<float2>(h, gm, tol, od, h->Ap32, h->LU32, rho_out, info);
+    else st = run<double2>(h, gm, tol, od, h->Ap, h->LU, rho_out, info);
+    if (info) info->fell_back = 1;
+    return st;
+}
+
 int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {
     SS_REQUIRE(tol > 0 && std::isfinite(tol), SS_E_INVALID_ARG, "tol must be positive");
     if (method == SS_AUTO) method = choose_method(h, o);
@@ -1114,6 +1145,8 @@ int solve(ss_liouv h, int method, double tol, const ss_options &o, double *rho_o
     int st;
     if (o.prec == SS_MIXED) st = run<float2>(h, method, tol, o, h->Ap32, h->LU32, rho_out, info);
     else st = run<double2>(h, method, tol, o, h->Ap, h->LU, rho_out, info);
+    if ((st == SS_E_NOT_CONVERGED || st == SS_E_BREAKDOWN) && o.ilu == SS_ILU0 && !(o.flags & SS_FLAG_NO_FALLBACK))
+        st = solve_ilut_gmres(h, method, tol, o, rho_out, info);
     return st;
 }
 

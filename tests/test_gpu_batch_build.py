@@ -130,13 +130,19 @@ def _mats(L):
                                          ("trace_bicgstab", {"prec": "mixed"})])
 def test_batched_setup_equals_prepare(method, opts):
     """The batch's set-up stages (transform, pattern, ordering, ILU(0)) give
-    every handle the matrices ss_prepare gives it on its own, bit for bit."""
+    every handle the matrices ss_prepare gives it on its own, bit for bit.
+    A system that ILU(0) cannot precondition (the three-spin chain's trace
+    row) is solved again with iLUT and GMRES, which re-prepares its handle:
+    it is checked for its result instead."""
     systems = _systems()[:6] + [qs.kerr(int(n)) for n in (9, 17, 33)]
     Ls = ssl.build_liouvillian_batch([(_dev(s.H), [_dev(c) for c in s.c_ops]) for s in systems])
     _, infos = ssl.solve_batch(Ls, method, 1e-10, raise_on_error=False, **opts)
     for s, L, info in zip(systems, Ls, infos):
         if opts.get("trace_row", -1) >= s.dim:
             assert info["status"] == ssl.SS_E_INVALID_ARG
+            continue
+        if info["fell_back"]:
+            assert info["status"] == 0 and info["resid_l2"] <= 1e-10, s.name
             continue
         ref = ssl.build_liouvillian(s.H, s.c_ops)
         ssl.prepare(ref, method, **opts)
