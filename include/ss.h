@@ -298,6 +298,24 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
  * y is widened back to complex128. */
 int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
 
+/* ss_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same operators with the same kernels, no hipMalloc, hipFree or allocating
+ * library call.  op = SS_OP_SPMV_L or SS_OP_APPLY_L (fp64), SS_OP_SPMV_APERM
+ * or SS_OP_PRECOND (fp64 or SS_MIXED); SS_OP_PRECOND always takes the
+ * row-group triangular solves (SS_OP_PRECOND_GROUPS) and needs the
+ * schedules ss_prepare builds for the device-wide path (n > 4096, a GMRES
+ * method or SS_FLAG_DEVICE_WIDE), else SS_E_STATE.  x and y: n complex128
+ * (interleaved re, im), DEVICE pointers (else SS_E_INVALID_ARG), not
+ * aliased.  Scratch: one library-owned device array of 32 MiB per device,
+ * held until the process ends; a call needs 256 B plus 16 n B (fp64
+ * PRECOND) or 24 n B (mixed PRECOND) or 16 n B (mixed SPMV_APERM) and
+ * returns SS_E_INVALID_ARG beyond that (n above ~2.09e6 fp64, ~1.39e6 mixed).
+ * Every call on a device shares that array: calls that overlap on one
+ * device (other threads, other handles) race.  Synchronous: returns after
+ * the result is in y. */
+int ss_apply_noalloc(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
+
 /* Time `reps` back-to-back applications of an operator of the prepared
  * handle (SS_OP_SPMV_L, SS_OP_APPLY_L, SS_OP_SPMV_APERM or one of the
  * SS_OP_PRECOND* operators; prec as in

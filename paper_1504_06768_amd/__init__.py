@@ -13,6 +13,6 @@ from .ss import (  # noqa: F401
     SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE, SS_OP_PRECOND_SYNCFREE,
     SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS, SS_OP_PRECOND_GROUPS, SS_OP_APPLY_L, SS_FLAG_MATRIX_FREE,
     SolverError, Liouvillian, Server, apply, bandwidth_profile, build_liouvillian, build_liouvillian_batch,
-    export_csr, export_perm, library_path, options, prepare, set_allocator, solve, solve_batch, time_operator,
+    apply_noalloc, export_csr, export_perm, library_path, options, prepare, set_allocator, solve, solve_batch, time_operator,
     trim_cache, version,
 )

@@ -106,6 +106,7 @@ def _load():
         "ss_export_csr": (ctypes.c_int, [P, I32, P, P, P, P]),
         "ss_export_perm": (ctypes.c_int, [P, P]),
         "ss_apply": (ctypes.c_int, [P, I32, I32, P, P]),
+        "ss_apply_noalloc": (ctypes.c_int, [P, I32, I32, P, P]),
         "ss_bandwidth_profile": (ctypes.c_int, [P, I32, P, P]),
         "ss_time_operator": (ctypes.c_int, [P, I32, I32, I32, P]),
         "ss_server_create": (ctypes.c_int, [ctypes.c_size_t, I32, P]),
@@ -130,7 +131,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("ss_options_default", "ss_build_liouvillian", "ss_build_liouvillian_batch", "ss_solve",
             "ss_solve_batch", "ss_liouv_free", "ss_liouv_shape",
-            "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_bandwidth_profile", "ss_time_operator",
+            "ss_prepare", "ss_export_csr", "ss_export_perm", "ss_apply", "ss_apply_noalloc", "ss_bandwidth_profile",
+            "ss_time_operator",
             "ss_server_create", "ss_submit", "ss_poll", "ss_server_drain", "ss_server_stats", "ss_server_destroy",
             "ss_last_error", "ss_set_stream", "ss_set_allocator", "ss_trim_cache", "ss_version")
 
@@ -419,6 +421,14 @@ def apply(L: Liouvillian, op: int, x, prec="fp64"):
     y = np.empty(L.n, dtype=np.complex128)
     _check(_lib.ss_apply(L.handle, op, PRECS[prec] if isinstance(prec, str) else prec, xh.ctypes.data,
                          y.ctypes.data), "ss_apply")
+    return y
+
+
+def apply_noalloc(L: Liouvillian, op: int, x, y, prec="fp64"):
+    """ss_apply_noalloc: y = op(x) with x, y device buffers of n complex128
+    values (torch tensors on the GPU); nothing is allocated."""
+    _check(_lib.ss_apply_noalloc(L.handle, op, PRECS[prec] if isinstance(prec, str) else prec, _ptr(x), _ptr(y)),
+           "ss_apply_noalloc")
     return y
 
 
