@@ -78,10 +78,13 @@ def apply_l_bytes(n):
 # ------------------------------------------------------------------ traffic
 # HBM bytes of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE,
 # then WRITE_SIZE), each scaled by what the same counter reads for a plain
-# copy of COPY_BYTES bytes.  The record names the kernel and the SHA-256 of
-# its sources; it is used only while both still match.
-KERNEL_SOURCE = "paper_1504_06768_amd/csrc/ilu.hip"
-KERNEL_MATCH = "k_trsv_"
+# copy of COPY_BYTES bytes.  The dominant kernel is the complex128
+# preconditioner application, two launches (lower and upper row-group
+# triangular solve); the record holds the mean of each launch's dispatches
+# and their sum per application.  It names the kernel and the SHA-256 of its
+# sources and is used only while both still match.
+KERNEL_SOURCE = "paper_1504_06768_amd/csrc/trsv_groups.hip"
+KERNEL_MATCH = "k_trsv_groups<HIP_vector_type<double"
 COPY_BYTES = 256 << 20
 
 
@@ -106,10 +109,12 @@ def source_digest(rel, root=None):
 
 
 def write_traffic(fetch_db, write_db, out_path=None, root=None, match=KERNEL_MATCH, source=KERNEL_SOURCE,
-                  workload="kerr_chain_3x10 fp64 inverse power (bench.py headline step)"):
+                  workload="kerr_chain_3x10 (n = 1e6): complex128 preconditioner application, lower + upper "
+                           "row-group triangular solve (bench.py headline step)"):
     """profiles/traffic.json from two rocprofv3 --pmc runs: FETCH_SIZE and
     WRITE_SIZE (KiB, summed over the counter's instances) of every dispatch
-    whose kernel name contains `match`, averaged per dispatch, each scaled by
+    whose kernel name contains `match`, averaged per kernel name and summed
+    over the names (one application = one launch of each), each scaled by
     what the same counter reads for the calibration copy of COPY_BYTES."""
     import sqlite3
 
@@ -119,18 +124,24 @@ def write_traffic(fetch_db, write_db, out_path=None, root=None, match=KERNEL_MAT
             "select kernel_name, grid_size, sum(value) from counters_collection where counter_name = ? "
             "group by dispatch_id order by dispatch_id", (counter,)))
         con.close()
-        kern = [v for (k, g, v) in rows if match in k]
+        per = {}
+        for (k, g, v) in rows:
+            if match in k:
+                per.setdefault(k, []).append(v)
+        # the calibration copy is bench.py's first device-to-device copy with
+        # that grid (later copies of other sizes can share the grid)
         copy = [v for (k, g, v) in rows if "copyBuffer" in k and g == COPY_BYTES // 2048]
-        if not kern or not copy:
+        if not per or not copy:
             raise SystemExit(f"{db}: no dispatch of {match} or no calibration copy of {COPY_BYTES} bytes")
-        return float(np.mean(kern)), copy[-1], len(kern)
+        return float(sum(np.mean(v) for v in per.values())), copy[0], sum(len(v) for v in per.values()), len(per)
 
-    fetch, cf, nf = read(fetch_db, "FETCH_SIZE")
-    write, cw, nw = read(write_db, "WRITE_SIZE")
+    fetch, cf, nf, kf = read(fetch_db, "FETCH_SIZE")
+    write, cw, nw, kw = read(write_db, "WRITE_SIZE")
     ff, fw = (COPY_BYTES / 1024) / cf, (COPY_BYTES / 1024) / cw
     fb, wb = fetch * 1024 * ff, write * 1024 * fw
     rec = {"kernel_match": match, "workload": workload, "source": source,
            "sources_sha256": source_digest(source, root), "dispatches": {"fetch": nf, "write": nw},
+           "kernels": {"fetch": kf, "write": kw},
            "fetch_size_kib": fetch, "write_size_kib": write,
            "calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_size_kib": cf, "copy_write_size_kib": cw,
                            "fetch_factor": ff, "write_factor": fw},
@@ -245,8 +256,9 @@ def dominant_kernel(ssl, ch, Hd, Cd, res):
     share = (2 * its * t_pre) / max(res["fp64"]["median_ms"], 1e-9)
     roof = {"bound": "hbm", "achieved": gbs(bp, t_pre), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": gbs(bp, t_pre) / PEAK_HBM_GBS, "traffic": None,
-            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128): "
-                      "two launches of the level-scheduled solve per application",
+            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128): one launch "
+                      "each of k_trsv_groups (row-group sync-free solve in level order) per application; "
+                      "latency-bound by the levels (1290 lower + 868 upper), not by HBM",
             "bytes_per_launch": bp, "avg_launch_ms": t_pre, "launches_per_unit": 2,
             "share_of_fp64_step": share}
     tr = _traffic()
@@ -294,19 +306,30 @@ def jc_batch(ssl, qs, torch, args):
             for L in Ls:
                 L.free()
             return infos
-        for _ in range(max(args.warmup, 1)):
-            step()
+        if prec == "mixed":
+            step()  # warm-up (library caches, code objects)
+            _log(f"jc batch {prec}: warm-up step done")
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = max(3, min(args.steps, 10))
-        infos = [step() for _ in range(reps)]
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+        # a step takes seconds: the draws ILU(0) cannot precondition are solved
+        # again with iLUT and GMRES, one by one
+        reps = max(1, args.batch_reps)
+        infos, times = [], []
+        for r in range(reps):
+            ts = time.perf_counter()
+            infos.append(step())
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+            _log(f"jc batch {prec}: step {r + 1}/{reps} {1e3 * times[-1]:.1f} ms")
+        dt = float(np.median(times))
         last = infos[-1]
         its = [i["inner_its"] for i in last]
-        alg = float(sum(i["bytes_alg"] for i in last))
-        tk = last[0]["t_kernel_ms"]
-        out[prec] = {"solves_per_s": B / dt, "ms_per_step": 1e3 * dt, "t_kernel_ms": tk,
+        # the workgroup-resident launch: the bytes of the systems it solved
+        inwg = [i for i in last if not i["fell_back"]]
+        alg = float(sum(i["bytes_alg"] for i in inwg))
+        tk = inwg[0]["t_kernel_ms"] if inwg else float("nan")
+        fb = [i for i in last if i["fell_back"]]
+        out[prec] = {"solves_per_s": B / dt, "ms_per_step_median": 1e3 * dt, "t_kernel_ms": tk,
+                     "fell_back": len(fb),
                      "kernel_GB/s": alg / (tk * 1e-3) / 1e9, "kernel_frac": alg / (tk * 1e-3) / 1e9 / PEAK_HBM_GBS,
                      "inner_its_min_median_max": [int(min(its)), float(np.median(its)), int(max(its))],
                      "worst_resid_l2": max(i["resid_l2"] for i in last),
@@ -417,6 +440,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=256, help="systems of the batched Jaynes-Cummings step")
+    ap.add_argument("--batch-reps", type=int, default=1, help="timed repetitions of the batched step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="kernels,jc_batch,spin_chain,serving",
                     help="secondary measurements to run (comma list; empty for none)")

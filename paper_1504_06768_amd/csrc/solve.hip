@@ -544,7 +544,10 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
                              : (o.flags & SS_FLAG_TRSV_LEVELS) ? PRE_LEVELS
                              : (o.flags & SS_FLAG_TRSV_GROUPS) ? PRE_GROUPS
                                                                : PRE_AUTO;
-            const bool groups = mode == PRE_GROUPS || (mode == PRE_AUTO && n > PRE_BLOCK_MAX_N);
+            // the one-workgroup solve takes long factor rows one entry at a
+            // time: iLUT factors (rows of ~100 entries) go to the row groups
+            const bool groups =
+                mode == PRE_GROUPS || (mode == PRE_AUTO && (n > PRE_BLOCK_MAX_N || o.ilu == SS_ILUT));
             if (groups && h->sched_ready)
                 M.borrow_groups(&h->sched_lo, &h->sched_up, h->gate_lo.get(), h->gate_up.get(), s);
             else

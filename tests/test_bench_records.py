@@ -12,7 +12,9 @@ _spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(
 bench = importlib.util.module_from_spec(_spec)
 _spec.loader.exec_module(bench)
 
-KERNEL = "void ss::k_trsv_slots<HIP_vector_type<double, 2u>, false>(int, int4 const*, int const*, ...)"
+KERNEL = "void ss::(anonymous namespace)::k_trsv_groups<HIP_vector_type<double, 2u>, false>(int, int, ...)"
+KERNEL_UP = "void ss::(anonymous namespace)::k_trsv_groups<HIP_vector_type<double, 2u>, true>(int, int, ...)"
+KERNEL_C64 = "void ss::(anonymous namespace)::k_trsv_groups<HIP_vector_type<float, 2u>, false>(int, int, ...)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
@@ -32,21 +34,27 @@ def test_traffic_record_scales_each_counter_by_the_copy(tmp_path):
     copy_kib = bench.COPY_BYTES / 1024
     grid = bench.COPY_BYTES // 2048
     # the copy reads its bytes twice over in FETCH_SIZE (factor 1/2) and once in WRITE_SIZE
-    # two dispatches of the kernel: the record holds their mean
+    # two dispatches of the lower launch (mean 1000), one of the upper (500),
+    # one of the complex64 instance (not counted)
+    # the calibration copy is the first copy with its grid; a later copy with
+    # the same grid (another size) is not used
     _db(tmp_path / "f.db", "FETCH_SIZE", [(COPY, 512, 3.0), (COPY, grid, copy_kib / 2), (KERNEL, grid, 900.0),
-                                          (KERNEL, grid, 1100.0)])
-    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, copy_kib), (KERNEL, grid, 250.0)])
+                                          (KERNEL, grid, 1100.0), (KERNEL_UP, grid, 500.0), (KERNEL_C64, grid, 7.0),
+                                          (COPY, grid, 77.0)])
+    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, copy_kib), (KERNEL, grid, 250.0), (KERNEL_UP, grid, 50.0),
+                                          (COPY, grid, 99.0)])
     out = tmp_path / "traffic.json"
     rec = bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(out))
     assert json.load(open(out)) == rec
     assert rec["calibration"]["fetch_factor"] == pytest.approx(2.0)
     assert rec["calibration"]["write_factor"] == pytest.approx(1.0)
-    assert rec["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024 * 2.0)
-    assert rec["write_bytes_per_launch"] == pytest.approx(250.0 * 1024)
-    assert rec["hbm_bytes_per_launch"] == pytest.approx(1000.0 * 1024 * 2.0 + 250.0 * 1024)
+    assert rec["fetch_bytes_per_launch"] == pytest.approx(1500.0 * 1024 * 2.0)
+    assert rec["write_bytes_per_launch"] == pytest.approx(300.0 * 1024)
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(1500.0 * 1024 * 2.0 + 300.0 * 1024)
     assert rec["sources_sha256"] == bench.source_digest(bench.KERNEL_SOURCE)
     assert rec["kernel_match"] == bench.KERNEL_MATCH
-    assert rec["dispatches"] == {"fetch": 2, "write": 1}
+    assert rec["dispatches"] == {"fetch": 3, "write": 2}
+    assert rec["kernels"] == {"fetch": 2, "write": 2}
 
 
 def test_traffic_record_needs_the_solver_and_the_copy(tmp_path):
