@@ -6,7 +6,7 @@ each (Hilbert dimension 1000, Liouvillian 10^6 x 10^6 with 20.7 M non-zeros),
 hopping J = 0.3; synthetic, no data files.  One step = one full solve through
 the C ABI: Liouvillian assembly from H and the collapse operators already
 resident in HBM, shift transform, RCM, ILU(0), the doubly-iterative inverse-
-power method (fp64 outer steps, preconditioned BiCGSTAB inner solves), finish
+power method (fp64 outer steps, preconditioned GMRES(40) inner solves), finish
 (unpermute, normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
 
 `value` is fp64 solves/s (complex128 throughout); the mixed path (complex64
@@ -169,6 +169,14 @@ def _traffic():
 
 
 # ---------------------------------------------------------------- headline
+# inverse power with GMRES(40) inner solves: on this workload it measured
+# 450 ms (fp64) and 474 ms (mixed) per solve against 504 / 870 ms with
+# BiCGSTAB and 495 / 566 ms with GMRES(20); each GMRES iteration applies the
+# latency-bound preconditioner once, a BiCGSTAB iteration twice
+HEADLINE_METHOD = "invpow_gmres"
+HEADLINE_GMRES_M = 40
+
+
 def headline(ssl, qs, torch, args):
     """Full C4 solves, fp64 and mixed: per-step times, iteration counts,
     residuals; rho of the last step of each precision (host copy)."""
@@ -181,7 +189,7 @@ def headline(ssl, qs, torch, args):
 
     def step(prec):
         L = ssl.build_liouvillian(Hd, Cd)
-        _, info = ssl.solve(L, "invpow_bicgstab", tol=1e-10, out=out, prec=prec)
+        _, info = ssl.solve(L, HEADLINE_METHOD, tol=1e-10, out=out, prec=prec, gmres_m=HEADLINE_GMRES_M)
         L.free()
         return info
 
@@ -220,7 +228,7 @@ def dominant_kernel(ssl, ch, Hd, Cd, res):
     complex128; algorithmic bytes from the factor and matrix sizes."""
     L = ssl.build_liouvillian(Hd, Cd)
     try:
-        ssl.prepare(L, "invpow_bicgstab", prec="mixed")
+        ssl.prepare(L, HEADLINE_METHOD, prec="mixed", gmres_m=HEADLINE_GMRES_M)
         _, n, nnzL = L.shape()
         A = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
         LU = ssl.export_csr(L, ssl.SS_MAT_LU)
@@ -252,14 +260,19 @@ def dominant_kernel(ssl, ch, Hd, Cd, res):
          f"({gbs(b64, t64):.0f} GB/s)")
     # per fp64 solve: inner iterations x (2 preconditioner applications + 2
     # SpMV); the preconditioner dominates
+    # per fp64 solve: one application per GMRES iteration plus one per
+    # restart cycle (the correction M^-1 V y); BiCGSTAB applies it twice per
+    # iteration
     its = res["fp64"]["inner_its"]
-    share = (2 * its * t_pre) / max(res["fp64"]["median_ms"], 1e-9)
+    applies = (its + -(-its // HEADLINE_GMRES_M)) if "gmres" in HEADLINE_METHOD else 2 * its
+    share = (applies * t_pre) / max(res["fp64"]["median_ms"], 1e-9)
     roof = {"bound": "hbm", "achieved": gbs(bp, t_pre), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": gbs(bp, t_pre) / PEAK_HBM_GBS, "traffic": None,
             "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128): one launch "
                       "each of k_trsv_groups (row-group sync-free solve in level order) per application; "
                       "latency-bound by the levels (1290 lower + 868 upper), not by HBM",
             "bytes_per_launch": bp, "avg_launch_ms": t_pre, "launches_per_unit": 2,
+            "applications_per_fp64_solve": applies,
             "share_of_fp64_step": share}
     tr = _traffic()
     if tr is not None:
@@ -367,6 +380,24 @@ def spin_chain_leg(ssl, qs):
                  f"its {si['outer_its']}/{si['inner_its']}")
     finally:
         Ls.free()
+    # the chain's steady state is I / d, inverse power's default start, so the
+    # solve above has nothing to do; from a random trace-1 Hermitian start it
+    # iterates (five spins with iLUT: from such a start zero-fill ILU stalls,
+    # and at six spins and more every ILU variant does)
+    s5 = qs.spin_chain(5)
+    L5 = ssl.build_liouvillian(s5.H, s5.c_ops)
+    try:
+        for prec in ("mixed", "fp64"):
+            t0 = time.perf_counter()
+            _, si = ssl.solve(L5, "invpow_bicgstab", tol=1e-10, prec=prec, raise_on_error=False, random_start=True,
+                              seed=1, ilu="ilut", no_fallback=True)
+            dt = time.perf_counter() - t0
+            out[f"spin5_random_start_ilut_{prec}"] = {"s": dt, "status": si["status"], "resid_l2": si["resid_l2"],
+                                                       "outer_its": si["outer_its"], "inner_its": si["inner_its"]}
+            _log(f"spin chain 5 random start (iLUT) {prec}: {dt:.3f} s, resid {si['resid_l2']:.2e}, "
+                 f"its {si['outer_its']}/{si['inner_its']}")
+    finally:
+        L5.free()
     return out
 
 
@@ -496,8 +527,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "kerr_chain_3x10: three coupled driven Kerr cavities, N = 10 each, J = 0.3 "
                                "(d = 1000, Liouvillian n = 1e6, 20.7 M non-zeros); one full solve per step "
-                               "(assembly, shift, RCM, ILU(0), inverse power with BiCGSTAB inner solves, finish)",
-                   "method": "invpow_bicgstab", "tol": 1e-10, "ordering": "rcm", "ilu": "ilu0"},
+                               "(assembly, shift, RCM, ILU(0), inverse power with GMRES(40) inner solves, finish)",
+                   "method": HEADLINE_METHOD, "gmres_m": HEADLINE_GMRES_M, "tol": 1e-10, "ordering": "rcm",
+                   "ilu": "ilu0"},
         "worst_resid_l2": f64["worst_resid_l2"],
         "fp64": {k: v for k, v in f64.items() if k != "rho"},
         "mixed": {k: v for k, v in mx.items() if k != "rho"},

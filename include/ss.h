@@ -87,8 +87,11 @@ typedef struct ss_server_s *ss_server;
  * L - sigma I are RCM-ordered; if the bandwidth of L~ exceeds 1.5 times that
  * of L - sigma I, or L~ has a diagonal entry below 1e-12 of its row's
  * largest (a zero diagonal the trace row does not cover, e.g. populations
- * under pure dephasing), SS_INVPOW_BICGSTAB is used, else
- * SS_TRACE_BICGSTAB.
+ * under pure dephasing), SS_INVPOW_BICGSTAB is used.  Otherwise the trace
+ * row: with GMRES, the paper's recommended first choice (section
+ * "Conclusion"), for systems the device-wide kernels solve (n > 4096), and
+ * with BiCGSTAB below that, where the whole solve runs in one
+ * workgroup-resident launch (which has no GMRES) and is faster.
  * ss_solve only; info.method reports the choice. */
 #define SS_AUTO             4
 
@@ -110,7 +113,9 @@ typedef struct {
     int32_t prec;       /* SS_FP64 | SS_MIXED                       (SS_FP64)  */
     int32_t ilu;        /* SS_ILU0 | SS_ILUT                        (SS_ILU0)  */
     int32_t ordering;   /* SS_ORDER_RCM | SS_ORDER_NATURAL          (RCM)      */
-    int32_t gmres_m;    /* GMRES restart length                     (20)       */
+    int32_t gmres_m;    /* GMRES restart length m                   (20);
+                           after an outer step whose GMRES did not converge
+                           the next uses 2 m, up to 128                        */
     int32_t maxiter;    /* inner Krylov iteration limit per solve   (1000)     */
     int32_t max_outer;  /* outer refinement / inverse-power steps   (20)       */
     int32_t flags;      /* SS_FLAG_* bits                           (0)        */
@@ -125,6 +130,7 @@ typedef struct {
                            tol/10 relative to the outer residual in FP64,
                            1e-4 in SS_MIXED                                     */
     double weight;      /* trace-row weight w; 0 = mean diagonal of L          */
+    int64_t seed;       /* seed of the random start (SS_FLAG_RANDOM_START) (0) */
 } ss_options;
 
 #define SS_FLAG_HERMITIZE   1  /* return (rho + rho^+)/2                      */
@@ -154,6 +160,12 @@ typedef struct {
                                   orthogonal to the residual), so the restart
                                   and GMRES fallback paths run; not for
                                   production solves                          */
+#define SS_FLAG_RANDOM_START 2048 /* inverse power starts from a random
+                                  trace-1 Hermitian matrix (unit diagonal / N,
+                                  off-diagonal entries drawn from opt.seed by
+                                  a counter-based generator) instead of I / N;
+                                  section "Eigenvalue Methods" starts the
+                                  power iteration from a random vector        */
 #define SS_FLAG_MATRIX_FREE 256 /* the fp64 residual of every outer step
                                   and the final certificate apply L from the
                                   d x d operators of eq. (lindblad) instead of

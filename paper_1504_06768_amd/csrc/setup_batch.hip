@@ -10,6 +10,7 @@
 // the same A, w, trace row and S as ss_prepare computes.
 #include <cstring>
 
+#include "start.hpp"
 #include "batch.hpp"
 #include "handle.hpp"
 #include "rowops.hpp"
@@ -552,6 +553,8 @@ struct StartJob {
     double2 w;
     const int *perm;
     double2 *x, *b;  // zeroed
+    int random;      // SS_FLAG_RANDOM_START (inverse power)
+    uint64_t seed;
 };
 
 // Start vector and right-hand side in the permuted order: trace row
@@ -564,6 +567,8 @@ __global__ void __launch_bounds__(256) k_bt_start(const StartJob *jobs, const in
     const int r = J.perm[q];
     if (J.trace) {
         if (r == J.trow) J.b[q] = J.w;
+    } else if (J.random) {
+        J.x[q] = random_start_value(J.d, r, J.seed);
     } else if (r % (J.d + 1) == 0) {
         J.x[q] = mk(1.0 / J.d, 0.0);
     }
@@ -734,7 +739,7 @@ void wg_setup_batch(ss_liouv *hs, int count, int method, const double *tols, con
             pblocks.push_back(div_up(h->n, 256));
         }
         st.push_back(StartJob{h->n, h->d, trace ? 1 : 0, h->trow, h->w, h->perm.get(), (double2 *)at(L.x),
-                              (double2 *)at(L.b)});
+                              (double2 *)at(L.b), (o.flags & SS_FLAG_RANDOM_START) ? 1 : 0, (uint64_t)o.seed});
         stblocks.push_back(div_up(h->n, 256));
     }
     launch_rows(k_bt_pack<T>, pj, pblocks, s);

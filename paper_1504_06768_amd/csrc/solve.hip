@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "start.hpp"
 #include "assemble.hpp"
 #include "csr_tools.hpp"
 #include "handle.hpp"
@@ -295,14 +296,22 @@ bool use_workgroup_n(int64_t n, int method, const ss_options &o) {
 
 bool use_workgroup(ss_liouv h, int method, const ss_options &o) { return use_workgroup_n(h->n, method, o); }
 
+__global__ void k_random_start(int n, int d, const int *perm, uint64_t seed, double2 *x) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) x[q] = random_start_value(d, perm[q], seed);
+}
+
 // Start vector and right-hand side in the permuted order: trace row
-// b = w e_rt, x = 0; inverse power x = vec(I / d).
-static void init_vectors(ss_liouv h, bool trace, double2 *x, double2 *b, hipStream_t s) {
+// b = w e_rt, x = 0; inverse power x = vec(I / d), or the random trace-1
+// Hermitian start of SS_FLAG_RANDOM_START.
+static void init_vectors(ss_liouv h, bool trace, double2 *x, double2 *b, const ss_options &o, hipStream_t s) {
     const int n = h->n, d = h->d;
     zero<double2>(n, x, s);
     if (trace) {
         zero<double2>(n, b, s);
         k_set_at<<<1, 1, 0, s>>>(1, h->iperm.get() + h->trow, b, h->w);
+    } else if (o.flags & SS_FLAG_RANDOM_START) {
+        k_random_start<<<div_up(n, 256), 256, 0, s>>>(n, d, h->perm.get(), (uint64_t)o.seed, x);
     } else {
         k_set_at<<<div_up(d, 256), 256, 0, s>>>(d, h->tpos.get(), x, mk(1.0 / d, 0.0));
     }
@@ -317,7 +326,7 @@ void make_wg(ss_liouv h, int method, double tol, const ss_options &o, const CsrB
     B.x.resize((size_t)n);
     B.r.resize((size_t)n);
     B.b.resize((size_t)n);
-    init_vectors(h, trace, B.x.get(), B.b.get(), s);
+    init_vectors(h, trace, B.x.get(), B.b.get(), o, s);
     if (!levels_built) build_levels(h->LU.view(), h->lu_diag.get(), B.lo, B.up, s);
     pack_side<T>(B.lo, LUin.view(), false, B.pl, s);
     pack_side<T>(B.up, LUin.view(), true, B.pu, s);
@@ -472,6 +481,10 @@ int finish(ss_liouv h, const double2 *x, const ss_options &o, double tol, const 
     return status;
 }
 
+// Outer steps in a row without halving the best fp64 residual after which
+// a device-wide solve stops (SS_E_NOT_CONVERGED with the last iterate).
+constexpr int STALL_STEPS = 4;
+
 template <typename T>
 static int run(ss_liouv h, int method, double tol, const ss_options &o, const CsrBuf<T> &Ain, const CsrBuf<T> &LUin,
                double *rho_out, ss_info *info) {
@@ -534,7 +547,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         bbuf.resize((size_t)n);
         x = xbuf.get();
         bvec = bbuf.get();
-        init_vectors(h, trace, x, bvec, s);
+        init_vectors(h, trace, x, bvec, o, s);
     }
     if (!done_wg) {
         Precond<T> M;
@@ -566,7 +579,8 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         DevBuf<double2> r((size_t)n), part(4 * (size_t)VEC_MAX_BLOCKS), scal(16);
         DevBuf<T> bT((size_t)n), dT((size_t)n);
         double2 *sc = scal.get();
-        int outer;
+        int outer, stalled = 0;
+        double best_resid = INFINITY;
         for (outer = 0; outer <= maxouter; ++outer) {
             // fp64 residual and trace
             double2 hs[3];
@@ -621,6 +635,14 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
                 if (outer == maxouter) break;
                 double2 den = mk(sqrt(hs[0].x), 0.0);
                 h2d(sc + 4, &den, 1, s);
+            }
+            // give up when the outer steps stop making progress: no halving of
+            // the best residual in STALL_STEPS consecutive steps
+            if (resid < 0.5 * best_resid) {
+                best_resid = resid;
+                stalled = 0;
+            } else if (++stalled >= STALL_STEPS) {
+                break;
             }
             // inner solve of A d = r / ||r||
             double2 hden;
@@ -1116,8 +1138,10 @@ static int choose_method(ss_liouv h, const ss_options &o) {
     if (std::getenv("SS_DEBUG"))
         std::fprintf(stderr, "[ss] auto: B(L~) = %lld, B(L - sigma I) = %lld, zero diagonals of L~ = %d\n",
                      (long long)bt, (long long)bs, zero_diag);
-    return (zero_diag > 0 || (double)bt > AUTO_BANDWIDTH_RATIO * (double)bs) ? SS_INVPOW_BICGSTAB
-                                                                              : SS_TRACE_BICGSTAB;
+    if (zero_diag > 0 || (double)bt > AUTO_BANDWIDTH_RATIO * (double)bs) return SS_INVPOW_BICGSTAB;
+    // the trace row: GMRES (the paper's first choice) where the device-wide
+    // kernels solve; BiCGSTAB where the workgroup-resident launch does
+    return use_workgroup_n(h->n, SS_TRACE_BICGSTAB, o) ? SS_TRACE_BICGSTAB : SS_TRACE_GMRES;
 }
 
 // When zero-fill ILU cannot precondition a system (no diagonal dominance:

@@ -27,7 +27,7 @@ SS_ILU0, SS_ILUT = 0, 1
 SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
 SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS, SS_FLAG_COND_EST = 16, 32, 64, 128
-SS_FLAG_MATRIX_FREE, SS_FLAG_FORCE_BREAKDOWN, SS_FLAG_TRSV_GROUPS = 256, 512, 1024
+SS_FLAG_MATRIX_FREE, SS_FLAG_FORCE_BREAKDOWN, SS_FLAG_TRSV_GROUPS, SS_FLAG_RANDOM_START = 256, 512, 1024, 2048
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
 SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS, SS_OP_APPLY_L = 5, 6, 7, 8
@@ -54,7 +54,7 @@ class _Options(ctypes.Structure):
                 ("gmres_m", ctypes.c_int32), ("maxiter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("trace_row", ctypes.c_int32),
                 ("drop_tol", ctypes.c_double), ("fill", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("inner_tol", ctypes.c_double), ("weight", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("weight", ctypes.c_double), ("seed", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -235,7 +235,7 @@ def _ptr(x) -> int:
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
             no_fallback=False, trace_row=-1, path="auto", trsv="auto", cond_est=False,
-            matrix_free=False, force_breakdown=False) -> _Options:
+            matrix_free=False, force_breakdown=False, random_start=False, seed=0) -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -254,6 +254,9 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
         o.flags |= SS_FLAG_MATRIX_FREE
     if force_breakdown:
         o.flags |= SS_FLAG_FORCE_BREAKDOWN
+    if random_start:
+        o.flags |= SS_FLAG_RANDOM_START
+    o.seed = int(seed)
     return o
 
 

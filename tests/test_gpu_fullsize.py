@@ -96,6 +96,43 @@ def test_spin_chain_auto_chooses_inverse_power():
         assert np.max(np.abs(rho - steady_state_dense(s.H, s.c_ops))) <= tol
 
 
+@pytest.mark.parametrize("method", ["invpow_bicgstab", "invpow_gmres"])
+def test_spin_chain_inverse_power_from_a_random_start(method):
+    """The spin chain's steady state is I / d (dephasing and a Hamiltonian
+    only), the default start of inverse power; from a random trace-1
+    Hermitian start (section "Eigenvalue Methods" starts from a random
+    vector) the solve has to remove the off-diagonal part: it iterates, and
+    ends at the dense oracle's rho.  Five spins with iLUT (which the oracle's
+    steps solve in a few iterations; from this start zero-fill ILU stalls,
+    and at six spins and more every ILU variant does)."""
+    spins = 5
+    s = qs.spin_chain(spins)
+    ref = steady_state_dense(s.H, s.c_ops)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-6)):
+        rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, random_start=True, seed=7, ilu="ilut",
+                              no_fallback=True)
+        _say("spin", spins, method, prec, "its", info["outer_its"], info["inner_its"], "resid", info["resid_l2"])
+        assert info["status"] == 0 and info["inner_its"] > 0
+        assert np.max(np.abs(rho - ref)) <= tol
+        assert info["resid_l2"] <= 1e-10
+
+
+def test_spin_chain_trace_row_with_ilut():
+    """The trace row with zero-fill ILU stalls on the spin chain (populations
+    under pure dephasing keep zero diagonals); with the dual-threshold iLUT,
+    which fills them during the elimination, trace-row GMRES reaches the
+    oracle's rho (five spins, n = 1024)."""
+    s = qs.spin_chain(5)
+    ref = steady_state_dense(s.H, s.c_ops)
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-6)):
+        rho, info = ssl.solve(L, "trace_gmres", tol=1e-10, prec=prec, ilu="ilut", no_fallback=True)
+        _say("spin5 trace ilut", prec, "its", info["outer_its"], info["inner_its"], "resid", info["resid_l2"])
+        assert info["status"] == 0
+        assert np.max(np.abs(rho - ref)) <= tol
+
+
 # ------------------------------------------------ Kerr chain at J = 0.3
 @pytest.fixture(scope="module")
 def chain_reference():

@@ -433,9 +433,12 @@ def test_auto_method_follows_the_bandwidth_rule():
     """SS_AUTO: the spin chain's trace row inflates the RCM bandwidth
     (the paper's Fig. 1 vs Fig. 3 captions: 167 -> 405 for five spins), so
     inverse power is chosen; for the Jaynes-Cummings system the two
-    bandwidths are alike and the trace-row driver is chosen.  Results match
+    bandwidths are alike and the trace-row driver is chosen, with BiCGSTAB
+    in the workgroup-resident launch (n <= 4096) and GMRES, the paper's first
+    choice, on the device-wide path (cavity 33: n = 4356).  Results match
     the dense oracle either way."""
-    for s, want in ((qs.spin_chain(4), ssl.SS_INVPOW_BICGSTAB), (qs.jaynes_cummings(8, seed=0), ssl.SS_TRACE_BICGSTAB)):
+    for s, want in ((qs.spin_chain(4), ssl.SS_INVPOW_BICGSTAB), (qs.jaynes_cummings(8, seed=0), ssl.SS_TRACE_BICGSTAB),
+                    (qs.jaynes_cummings(33, seed=0), ssl.SS_TRACE_GMRES)):
         L = ssl.build_liouvillian(s.H, s.c_ops)
         rho, info = ssl.solve(L, "auto", tol=1e-10)
         _say("auto", s.name, info["method"], info["bandwidth"])
