@@ -9,9 +9,10 @@ state is computed the way the paper computes it with an iterative solver:
   * section "Direct factorization": reverse Cuthill-McKee ordering of L~ on
     the pattern of L~ + L~^T, P L~ P^T;
   * section "Iterative Solvers", eq. (modified): an incomplete LU
-    preconditioner (zero fill, oracle/c/sparse_ref.c) and BiCGSTAB (van der
-    Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631), here preconditioned on
-    the right so that its residual is the residual of L~ x = b;
+    preconditioner (zero fill, oracle/c/sparse_ref.c, or the oracle's ILUT)
+    and BiCGSTAB (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631),
+    here preconditioned on the right so that its residual is the residual of
+    L~ x = b, or scipy's restarted GMRES;
   * the solve is restarted from its own true residual until
     ||L vec(rho)||_2 <= tol with rho = unvec(x) / Tr, the certificate of
     eq. (ss).
@@ -87,8 +88,26 @@ class Ilu0:
         if rc < 0:
             raise MemoryError(f"oracle_ilu0 failed ({rc})")
         self.guarded = rc
+        self._diagonal()
+
+    def _diagonal(self):
         rows = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.indptr))
         self.diag = np.ascontiguousarray(np.flatnonzero(self.indices == rows).astype(np.int64))
+
+
+class Ilut(Ilu0):
+    """The dual-threshold ILUT of oracle.ilu (C routine), applied like Ilu0."""
+
+    def __init__(self, A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0,
+                 boost: float | None = None):
+        from .ilu import ilut_c
+        LU, self.guarded = ilut_c(with_diagonal(A), drop_tol, fill, guard=guard, boost=boost)
+        LU.sort_indices()
+        self.n = LU.shape[0]
+        self.indptr = np.ascontiguousarray(LU.indptr, dtype=np.int64)
+        self.indices = np.ascontiguousarray(LU.indices, dtype=np.int32)
+        self.vals = np.ascontiguousarray(LU.data, dtype=np.complex128).copy()
+        self._diagonal()
 
     def matrix(self) -> sp.csr_matrix:
         """The factors in one CSR: strict lower part of L, then U."""
@@ -144,11 +163,24 @@ def bicgstab(A, b: np.ndarray, M, x0: np.ndarray, rtol: float, maxiter: int):
     return x, maxiter, False
 
 
+def gmres(A, b: np.ndarray, M, x0: np.ndarray, rtol: float, maxiter: int, restart: int = 50):
+    """Restarted GMRES (scipy's) preconditioned with M.solve; returns
+    (x, iterations, False) like bicgstab()."""
+    import scipy.sparse.linalg as spla
+    count = [0]
+    Mop = spla.LinearOperator(A.shape, matvec=M.solve, dtype=np.complex128)
+    x, _ = spla.gmres(A, b, x0=x0, M=Mop, rtol=rtol, restart=restart, maxiter=max(1, maxiter // restart),
+                      callback=lambda _r: count.__setitem__(0, count[0] + 1), callback_type="pr_norm")
+    return x, count[0], False
+
+
 def steady_state_iterative(H, c_ops, tol: float = 1e-12, rtol_in: float = 1e-10, maxiter: int = 2000,
-                           max_restarts: int = 10, pop: int | None = None, L=None):
-    """rho_ss by RCM-ordered ILU(0)-preconditioned BiCGSTAB on the trace-row
-    system, in fp64.  Returns (rho, info) with the iteration counts, the
-    certificate ||L vec rho||_2 and the times of the set-up and the solve."""
+                           max_restarts: int = 10, pop: int | None = None, L=None, ilu: str = "ilu0",
+                           krylov: str = "bicgstab", drop_tol: float = 1e-4, fill: float = 10.0):
+    """rho_ss by RCM-ordered ILU-preconditioned BiCGSTAB (or GMRES) on the
+    trace-row system, in fp64; ilu = "ilu0" or "ilut" (drop_tol, fill).
+    Returns (rho, info) with the iteration counts, the certificate
+    ||L vec rho||_2 and the times of the set-up and the solve."""
     t0 = time.perf_counter()
     if L is None:
         L = liouvillian_sparse(H, c_ops)
@@ -160,7 +192,8 @@ def steady_state_iterative(H, c_ops, tol: float = 1e-12, rtol_in: float = 1e-10,
     perm = rcm(A)
     Ap = with_diagonal(permute(A, perm))
     bp = b[perm]
-    M = Ilu0(Ap, guard=1e-8, boost=0.1)
+    M = Ilu0(Ap, guard=1e-8, boost=0.1) if ilu == "ilu0" else Ilut(Ap, drop_tol, fill, guard=1e-8, boost=0.1)
+    krylov_solve = bicgstab if krylov == "bicgstab" else gmres
     t1 = time.perf_counter()
     x = np.zeros(n, dtype=np.complex128)
     its, outer, res, breakdowns = 0, 0, np.inf, 0
@@ -168,7 +201,7 @@ def steady_state_iterative(H, c_ops, tol: float = 1e-12, rtol_in: float = 1e-10,
     for outer in range(1, max_restarts + 1):
         # refinement: the correction solves A delta = b - A x to rtol_in
         # relative to the current residual
-        delta, k, bd = bicgstab(Ap, bp - Ap @ x, M, np.zeros_like(x), rtol_in, maxiter)
+        delta, k, bd = krylov_solve(Ap, bp - Ap @ x, M, np.zeros_like(x), rtol_in, maxiter)
         x = x + delta
         its += k
         breakdowns += int(bd)

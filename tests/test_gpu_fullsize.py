@@ -70,8 +70,9 @@ def test_kerr_chain_workload(method, prec):
 
 
 @pytest.mark.skip(reason="optomechanics 10 x 60 at g0 = 0.4, gamma = 1e-4: zero-fill ILU leaves BiCGSTAB/GMRES "
-                         "stalled near 1e-1, and ILUT without pivoting (drop 1e-4 / 1e-5, fill 10 / 20) shows "
-                         "element growth to 1e58 in the factors, so no preconditioner of the method converges")
+                         "stalled near 1e-1, and every ILUT / ILUTP of the oracle (drop 1e-4 ... 1e-6, fill 10 ... 30, "
+                         "permtol 0, 0.1, 0.5, 1; trace row and shift) overflows its condition estimate "
+                         "||(LU)^-1 e||_inf, so no preconditioner of the method converges")
 @pytest.mark.parametrize("method,prec", [("trace_bicgstab", "mixed"), ("trace_gmres", "mixed")])
 def test_optomechanics_workload(method, prec):
     s = qs.config(3)
@@ -81,6 +82,26 @@ def test_optomechanics_workload(method, prec):
     assert info["status"] == 0
     assert info["resid_l2"] <= 1e-10
     assert abs(np.trace(rho) - 1) <= 1e-12
+
+
+def test_optomechanics_at_20_phonons_with_ilut_gmres():
+    """The optomechanical model of the full-size workload with the mechanical
+    cutoff at 20 (10 x 20, n = 40 000): the paper's iLUT with GMRES converges
+    on the GPU in both precisions and matches the oracle's CPU fp64 sparse
+    reference (RCM, the oracle's ILUT, GMRES; ||L rho|| <= 1e-11)."""
+    from oracle.sparse_ref import steady_state_iterative
+    s = qs.optomechanics(10, 20)
+    ref, rinfo = steady_state_iterative(s.H, s.c_ops, tol=1e-11, rtol_in=1e-11, ilu="ilut", krylov="gmres",
+                                        maxiter=3000, max_restarts=4)
+    _say("opto 10x20 cpu reference", rinfo["iterations"], rinfo["resid_l2"])
+    assert rinfo["resid_l2"] <= 1e-11
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-6)):
+        rho, info = ssl.solve(L, "trace_gmres", tol=1e-10, prec=prec, ilu="ilut", gmres_m=50, no_fallback=True)
+        err = float(np.max(np.abs(rho - ref)))
+        _say("opto 10x20", prec, info["outer_its"], info["inner_its"], info["resid_l2"], err)
+        assert info["status"] == 0 and info["resid_l2"] <= 1e-10
+        assert err <= tol
 
 
 def test_spin_chain_auto_chooses_inverse_power():
@@ -146,7 +167,7 @@ def chain_reference():
     return s, rho
 
 
-@pytest.mark.parametrize("method", ["invpow_bicgstab", "trace_bicgstab", "invpow_gmres"])
+@pytest.mark.parametrize("method", ["invpow_bicgstab", "trace_bicgstab", "invpow_gmres", "trace_gmres"])
 def test_kerr_chain_methods_agree_with_the_cpu_reference(chain_reference, method):
     """Cross-method agreement at the workload's own parameters: inverse power
     and the trace row, BiCGSTAB and GMRES, all fp64 to 1e-12, each within 1e-8
@@ -160,10 +181,14 @@ def test_kerr_chain_methods_agree_with_the_cpu_reference(chain_reference, method
     assert err <= 1e-8
 
 
-def test_kerr_chain_mixed_agrees_with_the_cpu_reference(chain_reference):
+@pytest.mark.parametrize("method,m", [("invpow_bicgstab", 20), ("invpow_gmres", 40)])
+def test_kerr_chain_mixed_agrees_with_the_cpu_reference(chain_reference, method, m):
+    """Mixed precision (complex64 inner solves and factors, fp64 outer steps)
+    at the workload's own parameters, including the configuration bench.py
+    times (inverse power with GMRES(40)): within 1e-6 of the CPU reference."""
     s, ref = chain_reference
     L = ssl.build_liouvillian(s.H, s.c_ops)
-    rho, info = ssl.solve(L, "invpow_bicgstab", tol=1e-10, prec="mixed", raise_on_error=False)
+    rho, info = ssl.solve(L, method, tol=1e-10, prec="mixed", raise_on_error=False, gmres_m=m)
     err = float(np.max(np.abs(rho - ref)))
     _say("chain invpow mixed", info["outer_its"], info["inner_its"], info["resid_l2"], err)
     assert info["status"] == 0 and info["resid_l2"] <= 1e-10
