@@ -95,6 +95,18 @@ class Ilu0:
         self.diag = np.ascontiguousarray(np.flatnonzero(self.indices == rows).astype(np.int64))
 
 
+    def matrix(self) -> sp.csr_matrix:
+        """The factors in one CSR: strict lower part of L, then U."""
+        return sp.csr_matrix((self.vals.copy(), self.indices.copy(), self.indptr.copy()), shape=(self.n, self.n))
+
+    def solve(self, b: np.ndarray) -> np.ndarray:
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        x = np.empty_like(b)
+        _lib().oracle_lu_solve(self.n, self.indptr.ctypes.data, self.indices.ctypes.data, self.vals.ctypes.data,
+                               self.diag.ctypes.data, b.ctypes.data, x.ctypes.data)
+        return x
+
+
 class Ilut(Ilu0):
     """The dual-threshold ILUT of oracle.ilu (C routine), applied like Ilu0."""
 
@@ -108,17 +120,6 @@ class Ilut(Ilu0):
         self.indices = np.ascontiguousarray(LU.indices, dtype=np.int32)
         self.vals = np.ascontiguousarray(LU.data, dtype=np.complex128).copy()
         self._diagonal()
-
-    def matrix(self) -> sp.csr_matrix:
-        """The factors in one CSR: strict lower part of L, then U."""
-        return sp.csr_matrix((self.vals.copy(), self.indices.copy(), self.indptr.copy()), shape=(self.n, self.n))
-
-    def solve(self, b: np.ndarray) -> np.ndarray:
-        b = np.ascontiguousarray(b, dtype=np.complex128)
-        x = np.empty_like(b)
-        _lib().oracle_lu_solve(self.n, self.indptr.ctypes.data, self.indices.ctypes.data, self.vals.ctypes.data,
-                               self.diag.ctypes.data, b.ctypes.data, x.ctypes.data)
-        return x
 
 
 def bicgstab(A, b: np.ndarray, M, x0: np.ndarray, rtol: float, maxiter: int):
