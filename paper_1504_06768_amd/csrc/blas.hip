@@ -47,7 +47,15 @@ void sum_partials(const double2 *partials, int nb, int k, double2 *out, hipStrea
 }
 
 // --------------------------------------------------------------- SpMV
-template <typename T, int G>
+// G lanes per row, up to U entries per lane per round with every load of a
+// round issued before its products are formed.  The matrix is streamed once,
+// so its values and indices are read non-temporally (NT) when that pays,
+// leaving the caches to the gathered x.  Measured on the Kerr chain's
+// P A P^T (n = 10^6, 20.7 M entries, 512 MB of other data written between
+// repetitions so that nothing of the matrix is cached): complex128 138 us
+// with one entry per lane per round (G = 16) -> 109 us with G = 16, U = 2,
+// NT; complex64 108 us -> 79 us with G = 8, U = 3 (NT slower there).
+template <typename T, int G, int U, bool NT>
 __global__ void __launch_bounds__(256) k_spmv(int n, const int *rowptr, const int *col, const T *val, const T *x,
                                               T *y, const int *skip) {
     if (skip && *skip) return;
@@ -55,8 +63,31 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int *rowptr, const in
     const int l = threadIdx.x & (G - 1);
     for (int row = blockIdx.x * (256 / G) + threadIdx.x / G; row < n; row += groups) {
         T acc = czero<T>();
-        const int re = rowptr[row + 1];
-        for (int e = rowptr[row] + l; e < re; e += G) acc = cadd(acc, cmul(val[e], x[col[e]]));
+        const int rb = rowptr[row], re = rowptr[row + 1];
+        for (int e0 = rb; e0 < re; e0 += G * U) {
+            int c[U];
+            T v[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * G + l;
+                if (e < re) {
+                    if (NT) {
+                        c[u] = __builtin_nontemporal_load(col + e);
+                        v[u].x = __builtin_nontemporal_load(&val[e].x);
+                        v[u].y = __builtin_nontemporal_load(&val[e].y);
+                    } else {
+                        c[u] = col[e];
+                        v[u] = val[e];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + u * G + l < re) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + u * G + l < re) acc = cadd(acc, cmul(v[u], xv[u]));
+        }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) {
             acc.x += __shfl_xor(acc.x, off, G);
@@ -97,13 +128,25 @@ __global__ void __launch_bounds__(256) k_spmv_dots(int n, const int *rowptr, con
 template <typename T>
 void spmv(const Csr<T> &A, const T *x, T *y, int group, hipStream_t s, const int *skip) {
     if (A.n == 0) return;
+    const bool c128 = sizeof(T) == 16;
+    // rows 17..32 entries long (the Kerr chain): the measured best shapes
+    if (group == 16) {
+        if (c128) {
+            const int nb = div_up(A.n, 256 / 16);
+            k_spmv<T, 16, 2, true><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip);
+        } else {
+            const int nb = div_up(A.n, 256 / 8);
+            k_spmv<T, 8, 3, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip);
+        }
+        SS_HIP(hipGetLastError());
+        return;
+    }
     const int rows_per_block = 256 / group;
     const int nb = (int)std::min<int64_t>(div_up(A.n, rows_per_block), 8192);
     switch (group) {
-        case 4: k_spmv<T, 4><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
-        case 8: k_spmv<T, 8><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
-        case 16: k_spmv<T, 16><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
-        default: k_spmv<T, 32><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
+        case 4: k_spmv<T, 4, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
+        case 8: k_spmv<T, 8, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
+        default: k_spmv<T, 32, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, skip); break;
     }
     SS_HIP(hipGetLastError());
 }
