@@ -42,5 +42,8 @@ def load():
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
+            lib.oracle_greedy_colour.restype = ctypes.c_int
+            lib.oracle_greedy_colour.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p]
             _lib = lib
     return _lib

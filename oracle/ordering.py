@@ -102,3 +102,41 @@ def permute(A, perm) -> sp.csr_matrix:
     B = A[perm, :][:, perm].tocsr()
     B.sort_indices()
     return B
+
+
+def greedy_colouring(S, order) -> tuple[np.ndarray, int]:
+    """(colour, number of colours) of the sequential greedy colouring of the
+    symmetric pattern S visited in `order` (order[k] = vertex visited k-th):
+    each vertex gets the smallest non-negative colour that none of its
+    already visited neighbours carries; self-loops are not edges (plain C,
+    oracle/c/colour.c).  Not a step of the paper: it serves the colour-class
+    ordering below."""
+    S = sp.csr_matrix(S)
+    n = S.shape[0]
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    if n == 0:
+        return np.zeros(0, dtype=np.int32), 0
+    if order.shape != (n,) or not np.array_equal(np.sort(order), np.arange(n)):
+        raise ValueError("order must be a permutation of the vertices")
+    indptr = np.ascontiguousarray(S.indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(S.indices, dtype=np.int32)
+    colour = np.empty(n, dtype=np.int32)
+    used = _load().oracle_greedy_colour(n, indptr.ctypes.data, indices.ctypes.data, order.ctypes.data,
+                                        colour.ctypes.data)
+    if used < 0:
+        raise MemoryError("oracle greedy colouring: allocation failed")
+    return colour, int(used)
+
+
+def colour_order(A, base=None) -> np.ndarray:
+    """Colour-class ordering perm[new] = old: the greedy colouring of the
+    structure of A + A^T visited in the base order (RCM of A by default),
+    classes in increasing colour, each class in base order.  Every
+    off-diagonal entry of the reordered matrix then joins two different
+    classes, so a zero-fill triangular factor has at most as many levels as
+    there are colours."""
+    if base is None:
+        base = rcm(A)
+    base = np.asarray(base, dtype=np.int32)
+    colour, _ = greedy_colouring(symmetrized_pattern(A), base)
+    return base[np.argsort(colour[base], kind="stable")].astype(np.int32)
