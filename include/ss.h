@@ -108,11 +108,22 @@ typedef struct ss_server_s *ss_server;
 
 #define SS_ORDER_RCM      0  /* reverse Cuthill-McKee on L~ + L~^T      */
 #define SS_ORDER_NATURAL  1
+#define SS_ORDER_COLOUR   2  /* colour classes: the greedy colouring of the
+                                structure of L~ + L~^T visited in RCM order,
+                                classes in increasing colour, each in RCM
+                                order.  Not in the paper: no off-diagonal
+                                entry joins two rows of one class, so the
+                                ILU(0) substitutions have at most as many
+                                dependent levels as colours (about ten on
+                                the Liouvillians here, against ~10^3 in RCM
+                                order), at the price of more Krylov
+                                iterations.  ss_info.colours reports the
+                                count.                                    */
 
 typedef struct {
     int32_t prec;       /* SS_FP64 | SS_MIXED                       (SS_FP64)  */
     int32_t ilu;        /* SS_ILU0 | SS_ILUT                        (SS_ILU0)  */
-    int32_t ordering;   /* SS_ORDER_RCM | SS_ORDER_NATURAL          (RCM)      */
+    int32_t ordering;   /* SS_ORDER_RCM | _NATURAL | _COLOUR        (RCM)      */
     int32_t gmres_m;    /* GMRES restart length m                   (20);
                            after an outer step whose GMRES did not converge
                            the next uses 2 m, up to 128                        */
@@ -166,6 +177,10 @@ typedef struct {
                                   a counter-based generator) instead of I / N;
                                   section "Eigenvalue Methods" starts the
                                   power iteration from a random vector        */
+#define SS_FLAG_TRSV_CLASSES 4096 /* device-wide path: triangular solves with
+                                  one launch per level (the default above
+                                  n = 65536 when neither factor has more than
+                                  64 levels, as in the colour-class order)  */
 #define SS_FLAG_MATRIX_FREE 256 /* the fp64 residual of every outer step
                                   and the final certificate apply L from the
                                   d x d operators of eq. (lindblad) instead of
@@ -203,7 +218,7 @@ typedef struct {
     double bytes_alg;        /* algorithmic HBM bytes of the iterations:
                                 matrix, factors and vectors once per use      */
     int32_t method;          /* the method that ran (resolves SS_AUTO)        */
-    int32_t reserved;
+    int32_t colours;         /* colour classes of SS_ORDER_COLOUR (else 0)    */
 } ss_info;
 
 /* fills *opt with the defaults listed above */
@@ -303,6 +318,11 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
                                     CUs in level order, 16 lanes per row
                                     (one factor entry each), polling gated
                                     two levels behind the frontier         */
+#define SS_OP_PRECOND_CLASSES 10 /* y = (LU)^-1 x with one launch per level
+                                    of each factor: fast when the levels are
+                                    few (the colour-class order); each row
+                                    sums its products in a tree, so the
+                                    result equals the others' to rounding */
 
 /* Apply one operator of the prepared handle to x (n complex, host or
  * device) giving y (n complex, host or device).  prec = SS_FP64 or SS_MIXED:

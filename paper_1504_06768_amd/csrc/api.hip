@@ -289,13 +289,14 @@ int ss_bandwidth_profile(ss_liouv L, int32_t which, int64_t *B, int64_t *P) {
 
 static bool is_precond_op(int op) {
     return op == SS_OP_PRECOND || op == SS_OP_PRECOND_SYNCFREE || op == SS_OP_PRECOND_BLOCK ||
-           op == SS_OP_PRECOND_LEVELS || op == SS_OP_PRECOND_GROUPS;
+           op == SS_OP_PRECOND_LEVELS || op == SS_OP_PRECOND_GROUPS || op == SS_OP_PRECOND_CLASSES;
 }
 
 static int precond_mode(int op) {
     return op == SS_OP_PRECOND_BLOCK    ? ss::PRE_BLOCK
            : op == SS_OP_PRECOND_LEVELS ? ss::PRE_LEVELS
            : op == SS_OP_PRECOND_GROUPS   ? ss::PRE_GROUPS
+           : op == SS_OP_PRECOND_CLASSES  ? ss::PRE_CLASSES
                                         : ss::PRE_AUTO;
 }
 
@@ -303,7 +304,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && x != nullptr && y != nullptr, SS_E_INVALID_ARG, "null argument");
         SS_REQUIRE(prec == SS_FP64 || prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
-        SS_REQUIRE(op >= 0 && op <= 9, SS_E_INVALID_ARG, "unknown operator");
+        SS_REQUIRE(op >= 0 && op <= 10, SS_E_INVALID_ARG, "unknown operator");
         const bool pre = is_precond_op(op);
         const bool natural = (op == SS_OP_SPMV_L || op == SS_OP_APPLY_L);
         SS_REQUIRE(natural || L->prepared, SS_E_STATE, "ss_prepare not called");

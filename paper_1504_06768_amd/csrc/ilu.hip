@@ -683,6 +683,10 @@ template <typename T>
 void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s, int m) {
     build_levels(lu64, diag, lo, up, s);
     if (m == PRE_AUTO) m = (n <= PRE_BLOCK_MAX_N) ? PRE_BLOCK : PRE_GROUPS;
+    if (m == PRE_CLASSES) {
+        mode = m;
+        return;
+    }
     if (m == PRE_GROUPS) {
         // the 16-byte coherent accesses address the vector through a buffer
         // resource limited to 2^31 bytes
@@ -715,8 +719,22 @@ void Precond<T>::borrow_groups(const LevelSched *lo_, const LevelSched *up_, con
 }
 
 template <typename T>
+void Precond<T>::borrow_classes(const LevelSched *lo_, const LevelSched *up_) {
+    blo = lo_;
+    bup = up_;
+    mode = PRE_CLASSES;
+}
+
+template <typename T>
 void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
     if (n == 0) return;
+    if (mode == PRE_CLASSES) {
+        // y takes the lower result (the sentinel is not kept in this mode)
+        const LevelSched &L0 = blo ? *blo : lo, &U0 = bup ? *bup : up;
+        trsv_classes<T>(L0, false, LU->view(), b, y.get(), skip, s);
+        trsv_classes<T>(U0, true, LU->view(), y.get(), out, skip, s);
+        return;
+    }
     if (mode == PRE_BLOCK) {
         BlockPrecond<T> B;
         B.lo = &lo;

@@ -56,9 +56,20 @@ void round_to_c64(int64_t n, const double2 *a, float2 *b, hipStream_t s);
 
 // Ways of applying (L U)^-1: sync-free in row order over all CUs, one
 // workgroup stepping through the levels, sync-free in level order over all
-// CUs, or the choice by size.
-enum : int { PRE_ROWS = 0, PRE_BLOCK = 1, PRE_LEVELS = 2, PRE_AUTO = 3, PRE_GROUPS = 4 };
+// CUs, the choice by size, row groups in level order, or one launch per
+// level (shallow schedules).
+enum : int { PRE_ROWS = 0, PRE_BLOCK = 1, PRE_LEVELS = 2, PRE_AUTO = 3, PRE_GROUPS = 4, PRE_CLASSES = 5 };
 constexpr int PRE_BLOCK_MAX_N = 65536;
+// deepest schedule (levels per factor) the automatic choice solves with one
+// launch per level
+constexpr int PRE_CLASSES_MAX_LEVELS = 64;
+
+// One triangular solve over the level schedule `ls` with one launch per level
+// (trsv_classes.hip): lower out = L^-1 in, upper out = U^-1 in.  No sentinels
+// are used or restored; nothing runs when *skip != 0 on the device.
+template <typename T>
+void trsv_classes(const LevelSched &ls, bool upper, const Csr<T> &LU, const T *in, T *out, const int *skip,
+                  hipStream_t s);
 
 // Sync-free triangular solves over all CUs with 16 lanes per row, in level
 // order, polling gated two levels behind the frontier (trsv_groups.hip).
@@ -102,6 +113,9 @@ struct Precond {
     // PRE_GROUPS over level schedules and gates owned by the caller (they
     // must outlive this object)
     void borrow_groups(const LevelSched *lo_, const LevelSched *up_, const int *glo, const int *gup, hipStream_t s);
+    // PRE_CLASSES over level schedules owned by the caller (they must
+    // outlive this object)
+    void borrow_classes(const LevelSched *lo_, const LevelSched *up_);
     const LevelSched *blo = nullptr, *bup = nullptr;
     const int *bglo = nullptr, *bgup = nullptr;
     // out = (LU)^-1 b; out must not alias b or y.  When *skip != 0 on the

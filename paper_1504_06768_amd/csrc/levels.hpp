@@ -13,7 +13,8 @@ namespace ss {
 struct LevelSched {
     int nlev = 0;
     DevBuf<int> ptr;    // nlev + 1
-    DevBuf<int4> slot;  // n
+    DevBuf<int4> slot;  // n; rows in increasing order within a level
+    std::vector<int> hptr;  // host copy of ptr
 };
 
 // Level sets of the strict lower part (forward) and of the strict upper part

@@ -470,8 +470,9 @@ int ss_submit(ss_server S, const ss_csr_z *H, const ss_csr_z *c_ops, int32_t n_c
         if (r->opt.drop_tol < 0) r->opt.drop_tol = 1e-4;
         SS_REQUIRE(r->opt.prec == SS_FP64 || r->opt.prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
         SS_REQUIRE(r->opt.ilu == SS_ILU0 || r->opt.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
-        SS_REQUIRE(r->opt.ordering == SS_ORDER_RCM || r->opt.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG,
-                   "unknown ordering");
+        SS_REQUIRE(r->opt.ordering == SS_ORDER_RCM || r->opt.ordering == SS_ORDER_NATURAL ||
+                       r->opt.ordering == SS_ORDER_COLOUR,
+                   SS_E_INVALID_ARG, "unknown ordering");
         r->footprint = ss::predict_footprint(r->H, r->C, r->opt.prec);
         std::lock_guard<std::mutex> lk(S->mu);
         r->arrival = std::chrono::steady_clock::now();

@@ -83,7 +83,8 @@ static void check_options(int method, const ss_options &o) {
     SS_REQUIRE(method >= 0 && method <= 3, SS_E_INVALID_ARG, "unknown method");
     SS_REQUIRE(o.prec == SS_FP64 || o.prec == SS_MIXED, SS_E_INVALID_ARG, "unknown precision");
     SS_REQUIRE(o.ilu == SS_ILU0 || o.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
-    SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL, SS_E_INVALID_ARG, "unknown ordering");
+    SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL || o.ordering == SS_ORDER_COLOUR,
+               SS_E_INVALID_ARG, "unknown ordering");
 }
 
 static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipStream_t s) {
@@ -129,6 +130,14 @@ static void add_zero_diagonal(ss_liouv h, hipStream_t s) {
     h->Ap = std::move(aug);
     const int still = find_diagonal(h->n, h->Ap.rowptr.get(), h->Ap.col.get(), h->diag.get(), s);
     SS_REQUIRE(still == 0, SS_E_ZERO_PIVOT, "could not give every row a diagonal entry");
+}
+
+// RCM order -> colour-class order (SS_ORDER_COLOUR)
+static void recolour(ss_liouv h, hipStream_t s) {
+    DevBuf<int> perm, iperm;
+    h->colours = colour_order(h->S, h->perm, h->iperm, perm, iperm, s);
+    h->perm = std::move(perm);
+    h->iperm = std::move(iperm);
 }
 
 static void prepare_permute(ss_liouv h, hipStream_t s) {
@@ -181,8 +190,10 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     };
     prepare_transform(h, method, o, s);
     phase("transform");
-    if (o.ordering == SS_ORDER_RCM) rcm_order(h->S, h->perm, h->iperm, s);
-    else identity_order(h->n, h->perm, h->iperm, s);
+    if (o.ordering == SS_ORDER_NATURAL) identity_order(h->n, h->perm, h->iperm, s);
+    else rcm_order(h->S, h->perm, h->iperm, s);
+    h->colours = 0;
+    if (o.ordering == SS_ORDER_COLOUR) recolour(h, s);
     phase("ordering");
     prepare_permute(h, s);
     phase("permute");
@@ -420,6 +431,7 @@ int fill_info(ss_liouv h, const ss_options &o, double tol, const SolveStats &st,
         info->trace_err = sqrt((trx.x - 1.0) * (trx.x - 1.0) + trx.y * trx.y);
         info->weight = h->w.x;
         info->method = h->p_method;
+        info->colours = h->colours;
         info->bandwidth = (int32_t)bandwidth;
         info->profile = profile;
         info->cond_est = (o.flags & SS_FLAG_COND_EST) ? condition_estimate(h, s) : 0.0;
@@ -553,15 +565,24 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
         Precond<T> M;
         M.setup(&LUin, h->lu_diag.get(), n, s);
         if (!(o.flags & SS_FLAG_SYNCFREE)) {
-            const int mode = (o.flags & SS_FLAG_TRSV_BLOCK)    ? PRE_BLOCK
-                             : (o.flags & SS_FLAG_TRSV_LEVELS) ? PRE_LEVELS
-                             : (o.flags & SS_FLAG_TRSV_GROUPS) ? PRE_GROUPS
-                                                               : PRE_AUTO;
+            const int mode = (o.flags & SS_FLAG_TRSV_BLOCK)     ? PRE_BLOCK
+                             : (o.flags & SS_FLAG_TRSV_LEVELS)  ? PRE_LEVELS
+                             : (o.flags & SS_FLAG_TRSV_GROUPS)  ? PRE_GROUPS
+                             : (o.flags & SS_FLAG_TRSV_CLASSES) ? PRE_CLASSES
+                                                                : PRE_AUTO;
+            // shallow schedules (the colour-class order) above the
+            // one-workgroup size take one launch per level
+            const bool shallow = h->sched_ready && std::max(h->sched_lo.nlev, h->sched_up.nlev) <= PRE_CLASSES_MAX_LEVELS;
+            const bool classes = mode == PRE_CLASSES || (mode == PRE_AUTO && shallow && n > PRE_BLOCK_MAX_N);
             // the one-workgroup solve takes long factor rows one entry at a
             // time: iLUT factors (rows of ~100 entries) go to the row groups
             const bool groups =
                 mode == PRE_GROUPS || (mode == PRE_AUTO && (n > PRE_BLOCK_MAX_N || o.ilu == SS_ILUT));
-            if (groups && h->sched_ready)
+            if (classes && h->sched_ready)
+                M.borrow_classes(&h->sched_lo, &h->sched_up);
+            else if (classes)
+                M.use_levels(h->LU.view(), s, PRE_CLASSES);
+            else if (groups && h->sched_ready)
                 M.borrow_groups(&h->sched_lo, &h->sched_up, h->gate_lo.get(), h->gate_up.get(), s);
             else
                 M.use_levels(h->LU.view(), s, mode);
@@ -760,7 +781,7 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
     }
     mark("transform+pattern");
     // stage 2: RCM of every graph in one launch (small graphs), else per system
-    const bool rcm = o.ordering == SS_ORDER_RCM;
+    const bool rcm = o.ordering != SS_ORDER_NATURAL;  // the colour order starts from RCM
     std::vector<RcmScratch> rs((size_t)count);
     {
         std::vector<RcmJob> jobs;
@@ -772,13 +793,17 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
         rcm_batch(jobs.data(), (int)jobs.size(), s0);
     }
     mark("rcm (batched)");
-    // stage 3: orderings the batched RCM does not cover, per system (rare)
+    // stage 3: orderings the batched RCM does not cover, per system (rare),
+    // and the colour classes over RCM
     parallel([&](int i) {
         ss_liouv h = hs[i];
-        if (rcm && rcm_batchable(h->n) && h->n > 0) return;
         hipStream_t s = stream_of(h);
-        if (!rcm) identity_order(h->n, h->perm, h->iperm, s);
-        else rcm_order(h->S, h->perm, h->iperm, s);
+        h->colours = 0;
+        if (!(rcm && rcm_batchable(h->n) && h->n > 0)) {
+            if (!rcm) identity_order(h->n, h->perm, h->iperm, s);
+            else rcm_order(h->S, h->perm, h->iperm, s);
+        }
+        if (o.ordering == SS_ORDER_COLOUR) recolour(h, s);
         SS_HIP(hipStreamSynchronize(s));
     });
     {

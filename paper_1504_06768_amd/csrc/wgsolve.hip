@@ -9,6 +9,7 @@
 // barrier separates levels, and the solution vector lives in LDS so that
 // every dependency read is an LDS access.  Many systems launch together, one
 // workgroup each, which is how the request server batches small solves.
+#include "bucket.hpp"
 #include "syncfree.hpp"
 #include "wgsolve.hpp"
 
@@ -206,17 +207,13 @@ __global__ void __launch_bounds__(1024) k_levels_batch_lds(const LevelJob *jobs)
     if (threadIdx.x == 0 && smax >= 0) atomicMax(J.maxlvl, smax);
 }
 
-__global__ void k_level_count(int n, const int *lvl, int *cnt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[lvl[i]], 1);
-}
-
+// slot[q] for the q-th row in level order
 template <bool UPPER>
-__global__ void k_level_scatter(int n, const int *rowptr, const int *diag, const int *lvl, int *cursor, int4 *slot) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int pos = atomicAdd(&cursor[lvl[i]], 1);
-    slot[pos] = UPPER ? make_int4(i, diag[i] + 1, rowptr[i + 1], 0) : make_int4(i, rowptr[i], diag[i], rowptr[i + 1]);
+__global__ void k_level_slots(int n, const int *rows, const int *rowptr, const int *diag, int4 *slot) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int i = rows[q];
+    slot[q] = UPPER ? make_int4(i, diag[i] + 1, rowptr[i + 1], 0) : make_int4(i, rowptr[i], diag[i], rowptr[i + 1]);
 }
 
 __global__ void k_fill_i32(int n, int *p, int v) {
@@ -255,21 +252,17 @@ void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls,
     d2h(&st, status.get(), 1, s);
     SS_REQUIRE(!(st & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "level analysis: dependency wait timed out");
     ls.nlev = n ? maxl + 1 : 0;
-    DevBuf<int> cnt((size_t)ls.nlev + 1);
-    SS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (ls.nlev + 1), s));
     ls.ptr.resize((size_t)ls.nlev + 1);
     ls.slot.resize((size_t)std::max(n, 1));
+    // rows in (level, row) order, then their slots
+    DevBuf<int> rows((size_t)std::max(n, 1));
+    bucket_sort(n, lvl.get(), ls.nlev, nullptr, rows.get(), nullptr, ls.ptr.get(), s);
     if (n) {
-        k_level_count<<<div_up(n, 256), 256, 0, s>>>(n, lvl.get(), cnt.get());
+        k_level_slots<UPPER><<<div_up(n, 256), 256, 0, s>>>(n, rows.get(), LU.rowptr, diag, ls.slot.get());
         SS_HIP(hipGetLastError());
     }
-    scan_exclusive(cnt.get(), ls.ptr.get(), ls.nlev, s, false);
-    SS_HIP(hipMemcpyAsync(cnt.get(), ls.ptr.get(), sizeof(int) * (ls.nlev + 1), hipMemcpyDeviceToDevice, s));
-    if (n) {
-        k_level_scatter<UPPER><<<div_up(n, 256), 256, 0, s>>>(n, LU.rowptr, diag, lvl.get(), cnt.get(), ls.slot.get());
-        SS_HIP(hipGetLastError());
-    }
-    SS_HIP(hipStreamSynchronize(s));
+    ls.hptr.resize((size_t)ls.nlev + 1);
+    d2h(ls.hptr.data(), ls.ptr.get(), (size_t)ls.nlev + 1, s);  // (synchronises)
 }
 template void LevelBuild::finish<false>(const Csr<double2> &, const int *, LevelSched &, hipStream_t);
 template void LevelBuild::finish<true>(const Csr<double2> &, const int *, LevelSched &, hipStream_t);

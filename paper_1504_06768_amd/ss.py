@@ -24,14 +24,16 @@ SS_E_ZERO_PIVOT, SS_E_HIP, SS_E_STATE, SS_E_TIMEOUT = -5, -6, -7, -8
 SS_TRACE_BICGSTAB, SS_TRACE_GMRES, SS_INVPOW_BICGSTAB, SS_INVPOW_GMRES, SS_AUTO = 0, 1, 2, 3, 4
 SS_FP64, SS_MIXED = 0, 1
 SS_ILU0, SS_ILUT = 0, 1
-SS_ORDER_RCM, SS_ORDER_NATURAL = 0, 1
+SS_ORDER_RCM, SS_ORDER_NATURAL, SS_ORDER_COLOUR = 0, 1, 2
 SS_FLAG_HERMITIZE, SS_FLAG_NO_FALLBACK, SS_FLAG_DEVICE_WIDE, SS_FLAG_WORKGROUP = 1, 2, 4, 8
 SS_FLAG_SYNCFREE, SS_FLAG_TRSV_BLOCK, SS_FLAG_TRSV_LEVELS, SS_FLAG_COND_EST = 16, 32, 64, 128
 SS_FLAG_MATRIX_FREE, SS_FLAG_FORCE_BREAKDOWN, SS_FLAG_TRSV_GROUPS, SS_FLAG_RANDOM_START = 256, 512, 1024, 2048
+SS_FLAG_TRSV_CLASSES = 4096
 SS_MAT_L, SS_MAT_A, SS_MAT_A_PERM, SS_MAT_LU, SS_MAT_SYM = 0, 1, 2, 3, 4
 SS_OP_SPMV_L, SS_OP_SPMV_APERM, SS_OP_PRECOND, SS_OP_LSOLVE, SS_OP_USOLVE = 0, 1, 2, 3, 4
 SS_OP_PRECOND_SYNCFREE, SS_OP_PRECOND_BLOCK, SS_OP_PRECOND_LEVELS, SS_OP_APPLY_L = 5, 6, 7, 8
 SS_OP_PRECOND_GROUPS = 9
+SS_OP_PRECOND_CLASSES = 10
 
 METHODS = {"trace_bicgstab": 0, "trace_gmres": 1, "invpow_bicgstab": 2, "invpow_gmres": 3, "auto": 4}
 PRECS = {"fp64": 0, "mixed": 1}
@@ -66,10 +68,10 @@ class _Info(ctypes.Structure):
                 ("cond_est", ctypes.c_double), ("fill_factor", ctypes.c_double), ("weight", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_kernel_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double),
-                ("method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("colours", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _INFO_KEYS = [name for name, _ in _Info._fields_]
@@ -82,9 +84,7 @@ def _info_dicts(infos, k: int) -> list:
     rows = np.ctypeslib.as_array(infos)[:k].tolist()
     out = []
     for r in rows:
-        d = dict(zip(_INFO_KEYS, r))
-        del d["reserved"]
-        out.append(d)
+        out.append(dict(zip(_INFO_KEYS, r)))
     return out
 
 
@@ -240,14 +240,15 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
     o.ilu = {"ilu0": 0, "ilut": 1}[ilu] if isinstance(ilu, str) else int(ilu)
-    o.ordering = {"rcm": 0, "natural": 1}[ordering] if isinstance(ordering, str) else int(ordering)
+    o.ordering = {"rcm": 0, "natural": 1, "colour": 2}[ordering] if isinstance(ordering, str) else int(ordering)
     o.gmres_m, o.maxiter, o.max_outer = gmres_m, maxiter, max_outer
     o.drop_tol, o.fill, o.sigma, o.inner_tol, o.weight = drop_tol, fill, sigma, inner_tol, weight
     o.trace_row = int(trace_row)
     o.flags = (SS_FLAG_HERMITIZE if hermitize else 0) | (SS_FLAG_NO_FALLBACK if no_fallback else 0)
     o.flags |= {"auto": 0, "device": SS_FLAG_DEVICE_WIDE, "workgroup": SS_FLAG_WORKGROUP}[path]
     o.flags |= {"auto": 0, "syncfree": SS_FLAG_SYNCFREE, "block": SS_FLAG_TRSV_BLOCK,
-                "levels": SS_FLAG_TRSV_LEVELS, "groups": SS_FLAG_TRSV_GROUPS}[trsv]
+                "levels": SS_FLAG_TRSV_LEVELS, "groups": SS_FLAG_TRSV_GROUPS,
+                "classes": SS_FLAG_TRSV_CLASSES}[trsv]
     if cond_est:
         o.flags |= SS_FLAG_COND_EST
     if matrix_free:

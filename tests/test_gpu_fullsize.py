@@ -195,6 +195,23 @@ def test_kerr_chain_mixed_agrees_with_the_cpu_reference(chain_reference, method,
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("method,prec,tol", [("invpow_gmres", "fp64", 1e-8), ("trace_gmres", "fp64", 1e-8),
+                                             ("invpow_gmres", "mixed", 1e-6)])
+def test_kerr_chain_colour_order_agrees_with_the_cpu_reference(chain_reference, method, prec, tol):
+    """The colour-class order (about ten colours, so about ten levels per
+    substitution instead of ~10^3 in RCM order) at the workload's own
+    parameters, GMRES(40): within 1e-8 (fp64) or 1e-6 (mixed) of the CPU
+    reference."""
+    s, ref = chain_reference
+    L = ssl.build_liouvillian(s.H, s.c_ops)
+    rho, info = ssl.solve(L, method, tol=1e-10, prec=prec, raise_on_error=False, gmres_m=40, ordering="colour")
+    err = float(np.max(np.abs(rho - ref)))
+    _say("chain colour", method, prec, info["status"], info["colours"], info["outer_its"], info["inner_its"],
+         info["resid_l2"], err, "setup %.1f solve %.1f ms" % (info["t_setup_ms"], info["t_solve_ms"]))
+    assert info["status"] == 0 and info["resid_l2"] <= 1e-10
+    assert err <= tol
+
+
 def test_kerr_chain_ilu0_reproduces_a_on_sampled_rows():
     """(L U)_ij = a_ij on the pattern of P L~ P^T for 2000 sampled rows of the
     Kerr chain (n = 10^6): the zero-fill factorisation at full size.  (The

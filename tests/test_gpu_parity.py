@@ -209,7 +209,7 @@ def test_ilu0_property_on_jc40():
 
 # ------------------------------------------------------------ SpMV / trsv
 PRECOND_OPS = (ssl.SS_OP_PRECOND, ssl.SS_OP_PRECOND_SYNCFREE, ssl.SS_OP_PRECOND_BLOCK, ssl.SS_OP_PRECOND_LEVELS,
-               ssl.SS_OP_PRECOND_GROUPS)
+               ssl.SS_OP_PRECOND_GROUPS, ssl.SS_OP_PRECOND_CLASSES)
 
 @pytest.mark.parametrize("name", ["kerr20", "jc8", "spin3"])
 def test_spmv_and_triangular_solves(name):
@@ -290,7 +290,7 @@ CASES = [(name, m) for name in ["kerr20", "jc8", "random7", "opto3x5"] for m in 
 CASES += [("spin3", "invpow_bicgstab"), ("spin3", "invpow_gmres")]
 
 
-DEVICE_PATHS = ["device", "device_syncfree", "device_levels", "device_groups"]
+DEVICE_PATHS = ["device", "device_syncfree", "device_levels", "device_groups", "device_classes"]
 CASES = [(n, m, p) for (n, m) in CASES for p in DEVICE_PATHS + (["workgroup"] if "bicgstab" in m else [])]
 
 
