@@ -109,16 +109,17 @@ typedef struct ss_server_s *ss_server;
 #define SS_ORDER_RCM      0  /* reverse Cuthill-McKee on L~ + L~^T      */
 #define SS_ORDER_NATURAL  1
 #define SS_ORDER_COLOUR   2  /* colour classes: the greedy colouring of the
-                                structure of L~ + L~^T visited in RCM order,
-                                classes in increasing colour, each in RCM
-                                order.  Not in the paper: no off-diagonal
-                                entry joins two rows of one class, so the
-                                ILU(0) substitutions have at most as many
-                                dependent levels as colours (about ten on
-                                the Liouvillians here, against ~10^3 in RCM
-                                order), at the price of more Krylov
-                                iterations.  ss_info.colours reports the
-                                count.                                    */
+                                structure of L~ + L~^T visited in a seeded
+                                random order (vertex v has priority
+                                SplitMix64(v)), classes in increasing colour,
+                                each in RCM order.  Not in the paper: no
+                                off-diagonal entry joins two rows of one
+                                class, so the ILU(0) substitutions have at
+                                most as many dependent levels as colours
+                                (about 14 on the Liouvillians here, against
+                                ~10^3 in RCM order), at the price of more
+                                Krylov iterations.  ss_info.colours reports
+                                the count.                                */
 
 typedef struct {
     int32_t prec;       /* SS_FP64 | SS_MIXED                       (SS_FP64)  */

@@ -128,15 +128,40 @@ def greedy_colouring(S, order) -> tuple[np.ndarray, int]:
     return colour, int(used)
 
 
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(k) -> np.ndarray:
+    """Outputs k = 0, 1, ... of SplitMix64 seeded with 0 (Steele, Lea and
+    Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+    z = (k + 1) * 0x9E3779B97F4A7C15 mod 2^64, then z ^= z >> 30,
+    z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *= 0x94D049BB133111EB,
+    z ^= z >> 31."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (k + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def random_visit(n: int) -> np.ndarray:
+    """The vertices 0..n-1 in increasing (splitmix64(v), v) order: a seeded
+    random visit order whose priorities each side can compute from the
+    vertex index alone."""
+    v = np.arange(n, dtype=np.int64)
+    return np.lexsort((v, splitmix64(v))).astype(np.int32)
+
+
 def colour_order(A, base=None) -> np.ndarray:
     """Colour-class ordering perm[new] = old: the greedy colouring of the
-    structure of A + A^T visited in the base order (RCM of A by default),
-    classes in increasing colour, each class in base order.  Every
-    off-diagonal entry of the reordered matrix then joins two different
-    classes, so a zero-fill triangular factor has at most as many levels as
-    there are colours."""
+    structure of A + A^T visited in the random order random_visit(n),
+    classes in increasing colour, each class in the base order (RCM of A by
+    default).  Every off-diagonal entry of the reordered matrix then joins
+    two different classes, so a zero-fill triangular factor has at most as
+    many levels as there are colours."""
     if base is None:
         base = rcm(A)
     base = np.asarray(base, dtype=np.int32)
-    colour, _ = greedy_colouring(symmetrized_pattern(A), base)
+    colour, _ = greedy_colouring(symmetrized_pattern(A), random_visit(A.shape[0]))
     return base[np.argsort(colour[base], kind="stable")].astype(np.int32)

@@ -55,6 +55,43 @@ void sum_partials(const double2 *partials, int nb, int k, double2 *out, hipStrea
 // repetitions so that nothing of the matrix is cached): complex128 138 us
 // with one entry per lane per round (G = 16) -> 109 us with G = 16, U = 2,
 // NT; complex64 108 us -> 79 us with G = 8, U = 3 (NT slower there).
+// One row's sum of products, split over the G lanes of its group (each
+// lane's share; the caller reduces across the group).
+template <typename T, int G, int U, bool NT>
+__device__ __forceinline__ T row_products(int rb, int re, int l, const int *col, const T *val, const T *x) {
+    T acc = czero<T>();
+    for (int e0 = rb; e0 < re; e0 += G * U) {
+        int c[U];
+        T v[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * G + l;
+            if (e < re) {
+                if (NT) {
+                    c[u] = __builtin_nontemporal_load(col + e);
+                    v[u].x = __builtin_nontemporal_load(&val[e].x);
+                    v[u].y = __builtin_nontemporal_load(&val[e].y);
+                } else {
+                    c[u] = col[e];
+                    v[u] = val[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * G + l < re) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * G + l < re) acc = cadd(acc, cmul(v[u], xv[u]));
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, G);
+        acc.y += __shfl_xor(acc.y, off, G);
+    }
+    return acc;
+}
+
 template <typename T, int G, int U, bool NT>
 __global__ void __launch_bounds__(256) k_spmv(int n, const int *rowptr, const int *col, const T *val, const T *x,
                                               T *y, const int *skip) {
@@ -62,42 +99,13 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int *rowptr, const in
     const int groups = gridDim.x * (256 / G);
     const int l = threadIdx.x & (G - 1);
     for (int row = blockIdx.x * (256 / G) + threadIdx.x / G; row < n; row += groups) {
-        T acc = czero<T>();
-        const int rb = rowptr[row], re = rowptr[row + 1];
-        for (int e0 = rb; e0 < re; e0 += G * U) {
-            int c[U];
-            T v[U], xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * G + l;
-                if (e < re) {
-                    if (NT) {
-                        c[u] = __builtin_nontemporal_load(col + e);
-                        v[u].x = __builtin_nontemporal_load(&val[e].x);
-                        v[u].y = __builtin_nontemporal_load(&val[e].y);
-                    } else {
-                        c[u] = col[e];
-                        v[u] = val[e];
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (e0 + u * G + l < re) xv[u] = x[c[u]];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (e0 + u * G + l < re) acc = cadd(acc, cmul(v[u], xv[u]));
-        }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            acc.x += __shfl_xor(acc.x, off, G);
-            acc.y += __shfl_xor(acc.y, off, G);
-        }
+        const T acc = row_products<T, G, U, NT>(rowptr[row], rowptr[row + 1], l, col, val, x);
         if (l == 0) y[row] = acc;
     }
 }
 
-template <typename T, int G>
+// y = A x with u1^H y and u2^H y (or y^H y) accumulated per block
+template <typename T, int G, int U, bool NT>
 __global__ void __launch_bounds__(256) k_spmv_dots(int n, const int *rowptr, const int *col, const T *val,
                                                    const T *x, T *y, const T *u1, const T *u2, bool u2_is_y,
                                                    double2 *partials, const int *skip) {
@@ -106,14 +114,7 @@ __global__ void __launch_bounds__(256) k_spmv_dots(int n, const int *rowptr, con
     const int l = threadIdx.x & (G - 1);
     double2 d[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
     for (int row = blockIdx.x * (256 / G) + threadIdx.x / G; row < n; row += groups) {
-        T acc = czero<T>();
-        const int re = rowptr[row + 1];
-        for (int e = rowptr[row] + l; e < re; e += G) acc = cadd(acc, cmul(val[e], x[col[e]]));
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            acc.x += __shfl_xor(acc.x, off, G);
-            acc.y += __shfl_xor(acc.y, off, G);
-        }
+        const T acc = row_products<T, G, U, NT>(rowptr[row], rowptr[row + 1], l, col, val, x);
         if (l == 0) {
             y[row] = acc;
             const double2 yy = widen(acc);
@@ -156,11 +157,16 @@ void spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, doub
                hipStream_t s, const int *skip) {
     const int nb = vec_blocks(A.n);
     const bool u2y = (u2 == y);
+    // the shapes of spmv() for rows of 17..32 entries
+    const bool c128 = sizeof(T) == 16;
     switch (group) {
-        case 4: k_spmv_dots<T, 4><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
-        case 8: k_spmv_dots<T, 8><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
-        case 16: k_spmv_dots<T, 16><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
-        default: k_spmv_dots<T, 32><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
+        case 4: k_spmv_dots<T, 4, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
+        case 8: k_spmv_dots<T, 8, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
+        case 16:
+            if (c128) k_spmv_dots<T, 16, 2, true><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip);
+            else k_spmv_dots<T, 8, 3, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip);
+            break;
+        default: k_spmv_dots<T, 32, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
     }
     SS_HIP(hipGetLastError());
 }

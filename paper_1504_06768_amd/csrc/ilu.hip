@@ -194,32 +194,32 @@ void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hip
 constexpr int ILU_LG = 8;
 constexpr int ILU_LVL_BS = 1024;
 constexpr int ILU_FM = 2;       // row entries per lane on the register path
-constexpr int ILU_FK = ILU_LG;  // lower entries (rows k) on the register path
 
-// The general loop: one row by one group, the working row in J.w.
+// The general loop: one row by one group of LG lanes, the working row in J.w.
+template <int LG>
 __device__ __forceinline__ void ilu0_row_group(const Ilu0Job &J, int row, int rs, int re, int dg, int lane,
                                                double detect, double boost) {
     double rn = 0.0;
-    for (int e = rs + lane; e < re; e += ILU_LG) {
+    for (int e = rs + lane; e < re; e += LG) {
         const double2 v = gld(J.a + e);
         gst(J.w + e, v);
         rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
     }
-    for (int off = ILU_LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, ILU_LG));
+    for (int off = LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, LG));
     for (int ek = rs; ek < dg; ++ek) {
         const int k = gld(J.col + ek);
         const int dk = gld(J.diag + k);
         const int ke = gld(J.rowptr + k + 1);
         const double2 ukk = gld(J.out + dk);
-        const int owner = (ek - rs) % ILU_LG;
+        const int owner = (ek - rs) % LG;
         double2 l = mk(0.0, 0.0);
         if (lane == owner) {
             l = cdiv(gld(J.w + ek), ukk);
             gst(J.w + ek, l);
         }
-        l.x = __shfl(l.x, owner, ILU_LG);
-        l.y = __shfl(l.y, owner, ILU_LG);
-        for (int e = rs + lane; e < re; e += ILU_LG) {
+        l.x = __shfl(l.x, owner, LG);
+        l.y = __shfl(l.y, owner, LG);
+        for (int e = rs + lane; e < re; e += LG) {
             if (e <= ek) continue;
             const int j = gld(J.col + e);
             int lo = dk + 1, hi = ke - 1, f = -1;
@@ -232,7 +232,7 @@ __device__ __forceinline__ void ilu0_row_group(const Ilu0Job &J, int row, int rs
             if (f >= 0) gst(J.w + e, csub(gld(J.w + e), cmul(l, gld(J.out + f))));
         }
     }
-    if (lane == (dg - rs) % ILU_LG) {
+    if (lane == (dg - rs) % LG) {
         const double2 p = gld(J.w + dg);
         const double mag = sqrt(p.x * p.x + p.y * p.y);
         const double bound = detect * rn;
@@ -242,130 +242,237 @@ __device__ __forceinline__ void ilu0_row_group(const Ilu0Job &J, int row, int rs
             atomicAdd(J.nguard, 1);
         }
     }
-    for (int e = rs + lane; e < re; e += ILU_LG) gst(J.out + e, gld(J.w + e));
+    for (int e = rs + lane; e < re; e += LG) gst(J.out + e, gld(J.w + e));
+}
+
+// One row of a level, by the LG lanes of its group (slot = {row, row start,
+// pivot position, row end}; every row it depends on is final).  The
+// register path takes rows of up to LG * FM entries with at most LG entries
+// before the pivot, each of whose rows k has at most LG entries after its
+// pivot.
+template <int LG, int FM>
+__device__ __forceinline__ void ilu0_slot(const Ilu0Job &J, int4 slot, int lane, double detect, double boost) {
+    constexpr int FK = LG;
+    const int row = slot.x, rs = slot.y, dg = slot.z, re = slot.w;
+    const int nl = dg - rs;  // entries before the pivot: the rows k this row eliminates with
+    bool fast = (re - rs <= LG * FM) && nl <= FK;
+    // the row in registers: entry rs + lane + LG m in slot m
+    int cj[FM];
+    double2 wv[FM];
+    double rn = 0.0;
+    int dk0 = 0, ke0 = 0;  // structure of row k = col[rs + lane] (lane < nl)
+    if (fast) {
+#pragma unroll
+        for (int m = 0; m < FM; ++m) {
+            const int e = rs + lane + LG * m;
+            cj[m] = -1;
+            wv[m] = mk(0.0, 0.0);
+            if (e < re) {
+                cj[m] = gld(J.col + e);
+                wv[m] = gld(J.a + e);
+            }
+        }
+        if (lane < nl) {
+            dk0 = gld(J.diag + cj[0]);
+            ke0 = gld(J.rowptr + cj[0] + 1);
+        }
+#pragma unroll
+        for (int m = 0; m < FM; ++m)
+            if (rs + lane + LG * m < re) rn = fmax(rn, sqrt(wv[m].x * wv[m].x + wv[m].y * wv[m].y));
+        // every U part must fit one entry per lane
+        int wide = (lane < nl && ke0 - dk0 - 1 > LG) ? 1 : 0;
+        for (int off = LG / 2; off > 0; off >>= 1) wide |= __shfl_xor(wide, off, LG);
+        fast = !wide;
+    }
+    if (!fast) {
+        ilu0_row_group<LG>(J, row, rs, re, dg, lane, detect, boost);
+        return;
+    }
+    for (int off = LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, LG));
+    // U parts: for lower entry p, lane t holds entry dk + 1 + t of row k
+    int uc[FK];
+    double2 uv[FK], ukk[FK];
+#pragma unroll
+    for (int p = 0; p < FK; ++p) {
+        const int dk = __shfl(dk0, p, LG), ke = __shfl(ke0, p, LG);
+        uc[p] = -1;
+        uv[p] = mk(0.0, 0.0);
+        ukk[p] = mk(1.0, 0.0);
+        if (p < nl) {
+            ukk[p] = gld(J.out + dk);
+            const int f = dk + 1 + lane;
+            if (f < ke) {
+                uc[p] = gld(J.col + f);
+                uv[p] = gld(J.out + f);
+            }
+        }
+    }
+    // eliminate with rows k in increasing order (the lower entries
+    // are sorted): l = a_ik / u_kk, then a_ij -= l u_kj on the
+    // columns j > k the two rows share
+#pragma unroll
+    for (int p = 0; p < FK; ++p) {
+        if (p < nl) {
+            double2 l = mk(0.0, 0.0);
+            if (lane == p) {
+                l = cdiv(wv[0], ukk[p]);
+                wv[0] = l;
+            }
+            l.x = __shfl(l.x, p, LG);
+            l.y = __shfl(l.y, p, LG);
+            int sm[FM];
+#pragma unroll
+            for (int m = 0; m < FM; ++m) sm[m] = -1;
+            for (int t = 0; t < LG; ++t) {
+                const int c = __shfl(uc[p], t, LG);
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+                    if (c >= 0 && c == cj[m]) sm[m] = t;
+            }
+#pragma unroll
+            for (int m = 0; m < FM; ++m) {
+                double2 u;
+                u.x = __shfl(uv[p].x, sm[m] < 0 ? 0 : sm[m], LG);
+                u.y = __shfl(uv[p].y, sm[m] < 0 ? 0 : sm[m], LG);
+                if (sm[m] >= 0) wv[m] = csub(wv[m], cmul(l, u));
+            }
+        }
+    }
+    // pivot guard on the lane holding the diagonal entry
+#pragma unroll
+    for (int m = 0; m < FM; ++m) {
+        if (nl == lane + LG * m) {
+            const double2 p = wv[m];
+            const double mag = sqrt(p.x * p.x + p.y * p.y);
+            const double bound = detect * rn;
+            if (!(mag >= bound)) {
+                const double b = (rn > 0.0) ? boost * rn : 1.0;
+                wv[m] = (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0);
+                atomicAdd(J.nguard, 1);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < FM; ++m) {
+        const int e = rs + lane + LG * m;
+        if (e < re) gst(J.out + e, wv[m]);
+    }
 }
 
 __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs, double detect, double boost) {
     const Ilu0Job &J = jobs[blockIdx.x];
     const int g = threadIdx.x / ILU_LG, lane = threadIdx.x % ILU_LG;
     constexpr int NG = ILU_LVL_BS / ILU_LG;
-    // the next level's end is fetched a level ahead, and a lower slot holds
-    // {row, row start, pivot position, row end}: a row's bounds come with
-    // its slot
+    // the next level's end is fetched a level ahead
     int s0 = J.nlev > 0 ? gld(J.lptr) : 0, s1 = J.nlev > 0 ? gld(J.lptr + 1) : 0;
     for (int lv = 0; lv < J.nlev; ++lv) {
         const int s2 = (lv + 2 <= J.nlev) ? gld(J.lptr + lv + 2) : 0;
-        for (int sl = s0 + g; sl < s1; sl += NG) {
-            const int4 slot = gld(J.lslot + sl);
-            const int row = slot.x, rs = slot.y, dg = slot.z, re = slot.w;
-            const int nl = dg - rs;  // entries before the pivot: the rows k this row eliminates with
-            bool fast = (re - rs <= ILU_LG * ILU_FM) && nl <= ILU_FK;
-            // the row in registers: entry rs + lane + ILU_LG m in slot m
-            int cj[ILU_FM];
-            double2 wv[ILU_FM];
-            double rn = 0.0;
-            int dk0 = 0, ke0 = 0;  // structure of row k = col[rs + lane] (lane < nl)
-            if (fast) {
-#pragma unroll
-                for (int m = 0; m < ILU_FM; ++m) {
-                    const int e = rs + lane + ILU_LG * m;
-                    cj[m] = -1;
-                    wv[m] = mk(0.0, 0.0);
-                    if (e < re) {
-                        cj[m] = gld(J.col + e);
-                        wv[m] = gld(J.a + e);
-                    }
-                }
-                if (lane < nl) {
-                    dk0 = gld(J.diag + cj[0]);
-                    ke0 = gld(J.rowptr + cj[0] + 1);
-                }
-#pragma unroll
-                for (int m = 0; m < ILU_FM; ++m)
-                    if (rs + lane + ILU_LG * m < re) rn = fmax(rn, sqrt(wv[m].x * wv[m].x + wv[m].y * wv[m].y));
-                // every U part must fit one entry per lane
-                int wide = (lane < nl && ke0 - dk0 - 1 > ILU_LG) ? 1 : 0;
-                for (int off = ILU_LG / 2; off > 0; off >>= 1) wide |= __shfl_xor(wide, off, ILU_LG);
-                fast = !wide;
-            }
-            if (!fast) {
-                ilu0_row_group(J, row, rs, re, dg, lane, detect, boost);
-                continue;
-            }
-            for (int off = ILU_LG / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, ILU_LG));
-            // U parts: for lower entry p, lane t holds entry dk + 1 + t of row k
-            int uc[ILU_FK];
-            double2 uv[ILU_FK], ukk[ILU_FK];
-#pragma unroll
-            for (int p = 0; p < ILU_FK; ++p) {
-                const int dk = __shfl(dk0, p, ILU_LG), ke = __shfl(ke0, p, ILU_LG);
-                uc[p] = -1;
-                uv[p] = mk(0.0, 0.0);
-                ukk[p] = mk(1.0, 0.0);
-                if (p < nl) {
-                    ukk[p] = gld(J.out + dk);
-                    const int f = dk + 1 + lane;
-                    if (f < ke) {
-                        uc[p] = gld(J.col + f);
-                        uv[p] = gld(J.out + f);
-                    }
-                }
-            }
-            // eliminate with rows k in increasing order (the lower entries
-            // are sorted): l = a_ik / u_kk, then a_ij -= l u_kj on the
-            // columns j > k the two rows share
-#pragma unroll
-            for (int p = 0; p < ILU_FK; ++p) {
-                if (p < nl) {
-                    double2 l = mk(0.0, 0.0);
-                    if (lane == p) {
-                        l = cdiv(wv[0], ukk[p]);
-                        wv[0] = l;
-                    }
-                    l.x = __shfl(l.x, p, ILU_LG);
-                    l.y = __shfl(l.y, p, ILU_LG);
-                    int sm[ILU_FM];
-#pragma unroll
-                    for (int m = 0; m < ILU_FM; ++m) sm[m] = -1;
-                    for (int t = 0; t < ILU_LG; ++t) {
-                        const int c = __shfl(uc[p], t, ILU_LG);
-#pragma unroll
-                        for (int m = 0; m < ILU_FM; ++m)
-                            if (c >= 0 && c == cj[m]) sm[m] = t;
-                    }
-#pragma unroll
-                    for (int m = 0; m < ILU_FM; ++m) {
-                        double2 u;
-                        u.x = __shfl(uv[p].x, sm[m] < 0 ? 0 : sm[m], ILU_LG);
-                        u.y = __shfl(uv[p].y, sm[m] < 0 ? 0 : sm[m], ILU_LG);
-                        if (sm[m] >= 0) wv[m] = csub(wv[m], cmul(l, u));
-                    }
-                }
-            }
-            // pivot guard on the lane holding the diagonal entry
-#pragma unroll
-            for (int m = 0; m < ILU_FM; ++m) {
-                if (nl == lane + ILU_LG * m) {
-                    const double2 p = wv[m];
-                    const double mag = sqrt(p.x * p.x + p.y * p.y);
-                    const double bound = detect * rn;
-                    if (!(mag >= bound)) {
-                        const double b = (rn > 0.0) ? boost * rn : 1.0;
-                        wv[m] = (mag > 0.0) ? cscale(p, b / mag) : mk(b, 0.0);
-                        atomicAdd(J.nguard, 1);
-                    }
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < ILU_FM; ++m) {
-                const int e = rs + lane + ILU_LG * m;
-                if (e < re) gst(J.out + e, wv[m]);
-            }
-        }
+        for (int sl = s0 + g; sl < s1; sl += NG) ilu0_slot<ILU_LG, ILU_FM>(J, gld(J.lslot + sl), lane, detect, boost);
         __syncthreads();
         s0 = s1;
         s1 = s2;
     }
+}
+
+// One system, one launch per level of its lower schedule: a group of LG
+// lanes per row, every dependency finished by an earlier launch.  A row of
+// up to LG entries (at most LG of them before the pivot, and every row k it
+// eliminates with holding at most LG entries after its pivot) stays in
+// registers, one entry per lane; the U parts of the rows k are fetched eight
+// at a time (one entry per lane each) and matched against the row's columns
+// by shuffles.  Other rows take the general loop.  The steps and their
+// arithmetic are those of ilu0_row, so the factors are the same.
+constexpr int ILU_LEVEL_BS = 256;
+constexpr int ILU_WIDE_LG = 32;
+constexpr int ILU_WIDE_PF = 8;  // U parts fetched per memory round
+
+template <int LG>
+__device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int lane, double detect,
+                                               double boost) {
+    const int row = slot.x, rs = slot.y, dg = slot.z, re = slot.w;
+    const int nl = dg - rs;  // entries before the pivot: the rows k this row eliminates with
+    const bool in = rs + lane < re;
+    const int cj = in ? gld(J.col + rs + lane) : -1;
+    double2 wv = in ? gld(J.a + rs + lane) : mk(0.0, 0.0);
+    double rn = in ? sqrt(wv.x * wv.x + wv.y * wv.y) : 0.0;
+    int dk0 = 0, ke0 = 0;
+    double2 ukk0 = mk(1.0, 0.0);
+    if (lane < nl && lane < LG) {
+        dk0 = gld(J.diag + cj);
+        ke0 = gld(J.rowptr + cj + 1);
+    }
+    int wide = (re - rs > LG || nl > LG || (lane < nl && ke0 - dk0 - 1 > LG)) ? 1 : 0;
+    for (int off = LG / 2; off > 0; off >>= 1) {
+        wide |= __shfl_xor(wide, off, LG);
+        rn = fmax(rn, __shfl_xor(rn, off, LG));
+    }
+    if (wide) {
+        ilu0_row_group<LG>(J, row, rs, re, dg, lane, detect, boost);
+        return;
+    }
+    if (lane < nl) ukk0 = gld(J.out + dk0);
+    for (int p0 = 0; p0 < nl; p0 += ILU_WIDE_PF) {
+        int uc[ILU_WIDE_PF];
+        double2 uv[ILU_WIDE_PF];
+#pragma unroll
+        for (int q = 0; q < ILU_WIDE_PF; ++q) {
+            const int p = p0 + q;
+            const int dk = __shfl(dk0, p < nl ? p : 0, LG), ke = __shfl(ke0, p < nl ? p : 0, LG);
+            uc[q] = -1;
+            uv[q] = mk(0.0, 0.0);
+            const int f = dk + 1 + lane;
+            if (p < nl && f < ke) {
+                uc[q] = gld(J.col + f);
+                uv[q] = gld(J.out + f);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ILU_WIDE_PF; ++q) {
+            const int p = p0 + q;
+            if (p < nl) {
+                // l = a_ik / u_kk on the lane holding lower entry p
+                double2 ukk;
+                ukk.x = __shfl(ukk0.x, p, LG);
+                ukk.y = __shfl(ukk0.y, p, LG);
+                double2 l = mk(0.0, 0.0);
+                if (lane == p) {
+                    l = cdiv(wv, ukk);
+                    wv = l;
+                }
+                l.x = __shfl(l.x, p, LG);
+                l.y = __shfl(l.y, p, LG);
+                // a_ij -= l u_kj where row k's U part holds column j
+                int sm = -1;
+                for (int t = 0; t < LG; ++t) {
+                    const int c = __shfl(uc[q], t, LG);
+                    if (c >= 0 && c == cj) sm = t;
+                }
+                double2 u;
+                u.x = __shfl(uv[q].x, sm < 0 ? 0 : sm, LG);
+                u.y = __shfl(uv[q].y, sm < 0 ? 0 : sm, LG);
+                if (sm >= 0) wv = csub(wv, cmul(l, u));
+            }
+        }
+    }
+    // pivot guard on the lane holding the diagonal entry
+    if (lane == nl) {
+        const double mag = sqrt(wv.x * wv.x + wv.y * wv.y);
+        const double bound = detect * rn;
+        if (!(mag >= bound)) {
+            const double b = (rn > 0.0) ? boost * rn : 1.0;
+            wv = (mag > 0.0) ? cscale(wv, b / mag) : mk(b, 0.0);
+            atomicAdd(J.nguard, 1);
+        }
+    }
+    if (in) gst(J.out + rs + lane, wv);
+}
+
+template <int LG>
+__global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu0_level(Ilu0Job J, int lo, int hi, double detect, double boost) {
+    const int t = blockIdx.x * ILU_LEVEL_BS + threadIdx.x;
+    const int sl = lo + t / LG, lane = t % LG;
+    if (sl >= hi) return;  // (whole groups)
+    ilu0_slot_wide<LG>(J, gld(J.lslot + sl), lane, detect, boost);
 }
 
 void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s) {
@@ -375,6 +482,41 @@ void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boo
     h2d(dj.get(), jobs, (size_t)count, s);
     k_ilu0_levels<<<count, ILU_LVL_BS, 0, s>>>(dj.get(), detect, boost);
     SS_HIP(hipGetLastError());
+}
+
+IluResult ilu0_factor_levels(const CsrBuf<double2> &A, const int *diag, const LevelSched &lo, double detect,
+                             double boost, CsrBuf<double2> &LU, hipStream_t s) {
+    SS_REQUIRE((int)lo.hptr.size() == lo.nlev + 1, SS_E_STATE, "level schedule without its host copy");
+    const int n = A.n, nnz = A.nnz;
+    LU.alloc(n, nnz);
+    SS_HIP(hipMemcpyAsync(LU.rowptr.get(), A.rowptr.get(), sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) SS_HIP(hipMemcpyAsync(LU.col.get(), A.col.get(), sizeof(int) * nnz, hipMemcpyDeviceToDevice, s));
+    DevBuf<double2> work((size_t)std::max(nnz, 1));
+    DevBuf<int> nguard(1);
+    SS_HIP(hipMemsetAsync(nguard.get(), 0, sizeof(int), s));
+    Ilu0Job j;
+    j.n = n;
+    j.rowptr = A.rowptr.get();
+    j.col = A.col.get();
+    j.diag = diag;
+    j.a = A.val.get();
+    j.w = work.get();
+    j.out = LU.val.get();
+    j.status = nullptr;
+    j.nguard = nguard.get();
+    j.nlev = lo.nlev;
+    j.lptr = lo.ptr.get();
+    j.lslot = lo.slot.get();
+    for (int l = 0; l < lo.nlev; ++l) {
+        const int a = lo.hptr[(size_t)l], b = lo.hptr[(size_t)l + 1];
+        if (b <= a) continue;
+        k_ilu0_level<ILU_WIDE_LG><<<div_up((int64_t)(b - a) * ILU_WIDE_LG, ILU_LEVEL_BS), ILU_LEVEL_BS, 0, s>>>(
+            j, a, b, detect, boost);
+    }
+    SS_HIP(hipGetLastError());
+    IluResult r;
+    d2h(&r.guarded, nguard.get(), 1, s);  // (synchronises before the work array is released)
+    return r;
 }
 
 IluResult ilu0_factor(const CsrBuf<double2> &A, const int *diag, double detect, double boost, CsrBuf<double2> &LU,

@@ -41,6 +41,12 @@ void ilu0_batch(const Ilu0Job *jobs, int count, double detect, double boost, hip
 // schedules; no dependency waits); the factor values need no sentinel.
 void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s);
 
+// The same factors with one launch per level of the lower schedule `lo`
+// (built from A's pattern, which zero fill keeps): no dependency waits, so
+// fast when the levels are few and wide (the colour-class order).
+IluResult ilu0_factor_levels(const CsrBuf<double2> &A, const int *diag, const LevelSched &lo, double detect,
+                             double boost, CsrBuf<double2> &LU, hipStream_t s);
+
 // Dual-threshold ILUT (drop_tol relative to ||row||_inf, at most
 // ceil(fill * nnz(row)) entries kept in each of L and U per row).
 IluResult ilut_factor(const CsrBuf<double2> &A, const int *diag, double drop_tol, double fill, double detect,

@@ -197,7 +197,19 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     phase("ordering");
     prepare_permute(h, s);
     phase("permute");
-    if (o.ilu == SS_ILU0) {
+    // device-wide solves use level schedules of the factors; zero fill keeps
+    // A's pattern, so for ILU(0) they are built first and drive the
+    // factorisation too when they are shallow
+    const bool want_sched = !use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31);
+    bool sched_built = false;
+    if (o.ilu == SS_ILU0 && want_sched) {
+        build_levels(h->Ap.view(), h->diag.get(), h->sched_lo, h->sched_up, s);
+        sched_built = true;
+        phase("levels");
+    }
+    if (o.ilu == SS_ILU0 && sched_built && h->sched_lo.nlev <= PRE_CLASSES_MAX_LEVELS) {
+        h->guarded = ilu0_factor_levels(h->Ap, h->diag.get(), h->sched_lo, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+    } else if (o.ilu == SS_ILU0) {
         h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
     } else {
         h->guarded =
@@ -208,8 +220,8 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     prepare_finish(h, method, o, s, t0);
     phase("finish");
     h->sched_ready = false;
-    if (!use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31)) {
-        build_levels(h->LU.view(), h->lu_diag.get(), h->sched_lo, h->sched_up, s);
+    if (want_sched) {
+        if (!sched_built) build_levels(h->LU.view(), h->lu_diag.get(), h->sched_lo, h->sched_up, s);
         group_gates(h->sched_lo, h->n, h->gate_lo, s);
         group_gates(h->sched_up, h->n, h->gate_up, s);
         h->sched_ready = true;

@@ -6,8 +6,8 @@
 // ~10^5 rows each.  A substitution is then bound by memory bandwidth, not by
 // the time a result takes to reach the rows that need it, so each level is
 // one plain launch: every value a row needs was written by an earlier
-// launch, and nothing is polled.  CLS_G lanes take a row's entries in turn,
-// a butterfly sums their products, and the first lane writes the row.  The
+// launch, and nothing is polled.  A group of lanes takes a row's entries, a
+// butterfly sums their products, and the first lane writes the row.  The
 // products are summed in a tree instead of in entry order, so the results
 // agree with the sync-free solves to rounding, not bit for bit.
 #include "ilu.hpp"
@@ -16,34 +16,67 @@ namespace ss {
 
 namespace {
 
-constexpr int CLS_G = 8;      // lanes per row
-constexpr int CLS_BS = 256;   // threads per workgroup
+constexpr int CLS_BS = 256;  // threads per workgroup
 
 // slot {row, first entry, end entry, .}: lower rows subtract entries
 // [first, end) of L (unit diagonal); upper rows those of U and divide by the
-// pivot just before them
-template <typename T, bool UPPER>
+// pivot just before them.  G lanes per row take up to U entries each per
+// round, with every load of a round issued before its products are formed;
+// a level then needs few enough threads to be resident at once, and each
+// thread's memory latencies overlap.
+template <typename T, bool UPPER, int G, int U>
 __global__ void __launch_bounds__(CLS_BS) k_trsv_level(int lo, int hi, const int4 *slot, const int *col,
-                                                        const T *val, const T *in, T *out, const int *skip) {
+                                                       const T *val, const T *in, T *out, const int *skip) {
     if (skip && *skip) return;
     const int t = blockIdx.x * CLS_BS + threadIdx.x;
-    const int idx = lo + t / CLS_G, k = t % CLS_G;
+    const int idx = lo + t / G, l = t % G;
     const bool active = idx < hi;
     int4 sl = make_int4(0, 0, 0, 0);
-    T acc = czero<T>();
+    T acc = czero<T>(), b = czero<T>(), piv = czero<T>();
     if (active) {
         sl = slot[idx];
-        for (int e = sl.y + k; e < sl.z; e += CLS_G) acc = cadd(acc, cmul(val[e], out[col[e]]));
+        if (l == 0) {
+            b = in[sl.x];
+            if (UPPER) piv = val[sl.y - 1];
+        }
+        for (int e0 = sl.y; e0 < sl.z; e0 += G * U) {
+            int c[U];
+            T v[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * G + l;
+                if (e < sl.z) {
+                    c[u] = col[e];
+                    v[u] = val[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + u * G + l < sl.z) xv[u] = out[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + u * G + l < sl.z) acc = cadd(acc, cmul(v[u], xv[u]));
+        }
     }
 #pragma unroll
-    for (int off = CLS_G / 2; off > 0; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off, 64);
-        acc.y += __shfl_xor(acc.y, off, 64);
+    for (int off = G / 2; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, G);
+        acc.y += __shfl_xor(acc.y, off, G);
     }
-    if (active && k == 0) {
-        T r = csub(in[sl.x], acc);
-        if (UPPER) r = cdiv(r, val[sl.y - 1]);
+    if (active && l == 0) {
+        T r = csub(b, acc);
+        if (UPPER) r = cdiv(r, piv);
         out[sl.x] = r;
+    }
+}
+
+template <typename T, bool UPPER, int G, int U>
+void levels_launch(const LevelSched &ls, const Csr<T> &LU, const T *in, T *out, const int *skip, hipStream_t s) {
+    for (int l = 0; l < ls.nlev; ++l) {
+        const int lo = ls.hptr[(size_t)l], hi = ls.hptr[(size_t)l + 1];
+        if (hi <= lo) continue;
+        const unsigned grid = (unsigned)div_up((int64_t)(hi - lo) * G, CLS_BS);
+        k_trsv_level<T, UPPER, G, U><<<grid, CLS_BS, 0, s>>>(lo, hi, ls.slot.get(), LU.col, LU.val, in, out, skip);
     }
 }
 
@@ -53,14 +86,18 @@ template <typename T>
 void trsv_classes(const LevelSched &ls, bool upper, const Csr<T> &LU, const T *in, T *out, const int *skip,
                   hipStream_t s) {
     SS_REQUIRE((int)ls.hptr.size() == ls.nlev + 1, SS_E_STATE, "level schedule without its host copy");
-    for (int l = 0; l < ls.nlev; ++l) {
-        const int lo = ls.hptr[(size_t)l], hi = ls.hptr[(size_t)l + 1];
-        if (hi <= lo) continue;
-        const unsigned grid = (unsigned)div_up((int64_t)(hi - lo) * CLS_G, CLS_BS);
-        if (upper)
-            k_trsv_level<T, true><<<grid, CLS_BS, 0, s>>>(lo, hi, ls.slot.get(), LU.col, LU.val, in, out, skip);
-        else
-            k_trsv_level<T, false><<<grid, CLS_BS, 0, s>>>(lo, hi, ls.slot.get(), LU.col, LU.val, in, out, skip);
+    if (LU.n == 0) return;
+    // mean entries per row of one triangle (the other's are about as many)
+    const double mean = std::max(0.0, (double)(LU.nnz - LU.n) / (2.0 * LU.n));
+    if (mean <= 12) {
+        if (upper) levels_launch<T, true, 4, 3>(ls, LU, in, out, skip, s);
+        else levels_launch<T, false, 4, 3>(ls, LU, in, out, skip, s);
+    } else if (mean <= 32) {
+        if (upper) levels_launch<T, true, 8, 4>(ls, LU, in, out, skip, s);
+        else levels_launch<T, false, 8, 4>(ls, LU, in, out, skip, s);
+    } else {
+        if (upper) levels_launch<T, true, 32, 2>(ls, LU, in, out, skip, s);
+        else levels_launch<T, false, 32, 2>(ls, LU, in, out, skip, s);
     }
     SS_HIP(hipGetLastError());
 }

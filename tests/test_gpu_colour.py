@@ -1,7 +1,8 @@
 """The colour-class ordering (SS_ORDER_COLOUR) through the C ABI against the
 oracle: the permutation bit for bit (greedy colouring of the structure of
-A + A^T visited in RCM order, classes in increasing colour, each in RCM
-order), the depth of the factors bounded by the colour count, and steady
+A + A^T visited in the seeded random order of SplitMix64 priorities, classes
+in increasing colour, each in RCM order), the depth of the factors bounded by
+the colour count, and steady
 states against the dense oracle and, on the Kerr chain (n = 10^6), against
 the oracle's CPU sparse reference.  Tolerances as everywhere: 1e-8 max-abs
 in fp64 mode, 1e-6 in mixed mode, ||L rho||_2 <= 1e-10."""
@@ -71,7 +72,7 @@ def test_colour_permutation_bit_exact(name, method):
     perm = ssl.export_perm(L)
     want = oord.colour_order(Ao)
     assert np.array_equal(perm, want)
-    _, k = oord.greedy_colouring(oord.symmetrized_pattern(Ao), oord.rcm(Ao))
+    _, k = oord.greedy_colouring(oord.symmetrized_pattern(Ao), oord.random_visit(Ao.shape[0]))
     # zero fill keeps the pattern, so each substitution has at most k levels
     lo, up = _depths(ssl.export_csr(L, ssl.SS_MAT_LU))
     _say("   colours", k, "levels", lo, up)
@@ -92,11 +93,12 @@ def test_colour_permutation_on_workloads(k, method):
 
 def test_colour_permutation_beyond_one_counter_window():
     """A dense Liouvillian (d = 36, n = 1296): its structure is a complete
-    graph, so the greedy colouring takes n colours -- more than one window of
-    the class counters, and colours past 64 for every late vertex."""
+    graph, so the greedy colouring takes n colours (one per round) -- more
+    than one window of the class counters, and colours past 64 for every late
+    vertex."""
     s = qs.random_lindblad(36, 2, density=1.0, seed=0)
     Ao = _transformed(s, "trace_bicgstab")
-    _, k = oord.greedy_colouring(oord.symmetrized_pattern(Ao), oord.rcm(Ao))
+    _, k = oord.greedy_colouring(oord.symmetrized_pattern(Ao), oord.random_visit(Ao.shape[0]))
     assert k > 1024
     L = ssl.build_liouvillian(s.H, s.c_ops)
     ssl.prepare(L, "trace_bicgstab", ordering="colour")
@@ -123,8 +125,8 @@ def test_colour_steady_state_matches_dense_oracle(name, method, path, prec, tol)
                           trsv=trsv, ordering="colour")
     _say("   its", info["outer_its"], info["inner_its"], "colours", info["colours"], "resid", info["resid_l2"])
     assert info["status"] == 0
-    _, k = oord.greedy_colouring(oord.symmetrized_pattern(_transformed(s, method)),
-                                 oord.rcm(_transformed(s, method)))
+    At = _transformed(s, method)
+    _, k = oord.greedy_colouring(oord.symmetrized_pattern(At), oord.random_visit(At.shape[0]))
     assert info["colours"] == k
     assert np.max(np.abs(rho - ref)) <= tol
     assert info["resid_l2"] <= 1e-10

@@ -11,7 +11,8 @@ import scipy.sparse as sp
 
 import qsystems as qs
 from oracle.liouvillian import liouvillian_sparse
-from oracle.ordering import colour_order, greedy_colouring, permute, rcm, symmetrized_pattern
+from oracle.ordering import (colour_order, greedy_colouring, permute, random_visit, rcm, splitmix64,
+                             symmetrized_pattern)
 from oracle.transforms import modified, trace_population
 
 
@@ -128,6 +129,20 @@ def _depth_lower(A):
     return int(lev.max()) + 1
 
 
+def test_splitmix64_published_outputs():
+    # the first outputs of the reference generator seeded with 0
+    assert [int(x) for x in splitmix64([0, 1, 2])] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                      0x06C45D188009454F]
+
+
+def test_random_visit_is_the_priority_order():
+    n = 5000
+    order = random_visit(n)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    pri = [int(x) for x in splitmix64(order)]
+    assert all(a < b for a, b in zip(pri, pri[1:]))  # distinct here, so strictly increasing
+
+
 @pytest.mark.parametrize("system", ["jc", "kerr_chain"])
 def test_colour_order_on_liouvillians(system):
     s = qs.jaynes_cummings(6, seed=1) if system == "jc" else qs.kerr_chain(3, 3)
@@ -137,7 +152,7 @@ def test_colour_order_on_liouvillians(system):
     perm = colour_order(A)
     n = A.shape[0]
     assert np.array_equal(np.sort(perm), np.arange(n))
-    col, k = greedy_colouring(symmetrized_pattern(A), base)
+    col, k = greedy_colouring(symmetrized_pattern(A), random_visit(n))
     # classes in increasing colour, each in base order
     assert np.all(np.diff(col[perm]) >= 0)
     pos = np.empty(n, dtype=np.int64)
