@@ -5,13 +5,15 @@ Headline workload: the chain of three coupled driven Kerr cavities, N = 10
 each (Hilbert dimension 1000, Liouvillian 10^6 x 10^6 with 20.7 M non-zeros),
 hopping J = 0.3; synthetic, no data files.  One step = one full solve through
 the C ABI: Liouvillian assembly from H and the collapse operators already
-resident in HBM, shift transform, RCM, ILU(0), the doubly-iterative inverse-
-power method (fp64 outer steps, preconditioned GMRES(40) inner solves), finish
-(unpermute, normalise, certificate ||L rho||_2 <= 1e-10), rho left in HBM.
+resident in HBM, shift transform, RCM and the colour-class order over it,
+ILU(0), the doubly-iterative inverse-power method (fp64 outer steps,
+preconditioned inner Krylov solves), finish (unpermute, normalise,
+certificate ||L rho||_2 <= 1e-10), rho left in HBM.
 
-`value` is fp64 solves/s (complex128 throughout); the mixed path (complex64
-inner solves and factors, fp64 outer steps) is timed beside it on the same
-GPU.  Every result is checked against the oracle: for this size the CPU fp64
+`value` is fp64 solves/s (complex128 throughout, BiCGSTAB inner solves); the
+mixed path (complex64 inner solves and factors, fp64 outer steps, GMRES(40)
+inner solves) is timed beside it on the same GPU, and so is the same solve
+in plain RCM order.  Every result is checked against the oracle: for this size the CPU fp64
 sparse reference (RCM-ordered ILU(0)-BiCGSTAB on the trace-row system, one
 CPU thread), which is also the timed CPU baseline.
 
@@ -83,8 +85,8 @@ def apply_l_bytes(n):
 # triangular solve); the record holds the mean of each launch's dispatches
 # and their sum per application.  It names the kernel and the SHA-256 of its
 # sources and is used only while both still match.
-KERNEL_SOURCE = "paper_1504_06768_amd/csrc/trsv_groups.hip"
-KERNEL_MATCH = "k_trsv_groups<HIP_vector_type<double"
+KERNEL_SOURCE = "paper_1504_06768_amd/csrc/trsv_classes.hip"
+KERNEL_MATCH = "k_trsv_level<HIP_vector_type<double"
 COPY_BYTES = 256 << 20
 
 
@@ -108,14 +110,15 @@ def source_digest(rel, root=None):
     return h.hexdigest()
 
 
-def write_traffic(fetch_db, write_db, out_path=None, root=None, match=KERNEL_MATCH, source=KERNEL_SOURCE,
-                  workload="kerr_chain_3x10 (n = 1e6): complex128 preconditioner application, lower + upper "
-                           "row-group triangular solve (bench.py headline step)"):
-    """profiles/traffic.json from two rocprofv3 --pmc runs: FETCH_SIZE and
-    WRITE_SIZE (KiB, summed over the counter's instances) of every dispatch
-    whose kernel name contains `match`, averaged per kernel name and summed
-    over the names (one application = one launch of each), each scaled by
-    what the same counter reads for the calibration copy of COPY_BYTES."""
+def write_traffic(fetch_db, write_db, apps, out_path=None, root=None, match=KERNEL_MATCH, source=KERNEL_SOURCE,
+                  workload="kerr_chain_3x10 (n = 1e6), colour-class order: complex128 preconditioner "
+                           "application, one launch per level of the lower and the upper factor"):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of
+    `bench.py --counter-apps apps`: FETCH_SIZE and WRITE_SIZE (KiB, summed
+    over the counter's instances) of every dispatch whose kernel name
+    contains `match`, summed and divided by the number of applications, each
+    scaled by what the same counter reads for the calibration copy of
+    COPY_BYTES."""
     import sqlite3
 
     def read(db, counter):
@@ -124,16 +127,13 @@ def write_traffic(fetch_db, write_db, out_path=None, root=None, match=KERNEL_MAT
             "select kernel_name, grid_size, sum(value) from counters_collection where counter_name = ? "
             "group by dispatch_id order by dispatch_id", (counter,)))
         con.close()
-        per = {}
-        for (k, g, v) in rows:
-            if match in k:
-                per.setdefault(k, []).append(v)
+        per = [v for (k, g, v) in rows if match in k]
         # the calibration copy is bench.py's first device-to-device copy with
         # that grid (later copies of other sizes can share the grid)
         copy = [v for (k, g, v) in rows if "copyBuffer" in k and g == COPY_BYTES // 2048]
         if not per or not copy:
             raise SystemExit(f"{db}: no dispatch of {match} or no calibration copy of {COPY_BYTES} bytes")
-        return float(sum(np.mean(v) for v in per.values())), copy[0], sum(len(v) for v in per.values()), len(per)
+        return float(sum(per)) / apps, copy[0], len(per), apps
 
     fetch, cf, nf, kf = read(fetch_db, "FETCH_SIZE")
     write, cw, nw, kw = read(write_db, "WRITE_SIZE")
@@ -141,7 +141,7 @@ def write_traffic(fetch_db, write_db, out_path=None, root=None, match=KERNEL_MAT
     fb, wb = fetch * 1024 * ff, write * 1024 * fw
     rec = {"kernel_match": match, "workload": workload, "source": source,
            "sources_sha256": source_digest(source, root), "dispatches": {"fetch": nf, "write": nw},
-           "kernels": {"fetch": kf, "write": kw},
+           "applications": apps,
            "fetch_size_kib": fetch, "write_size_kib": write,
            "calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_size_kib": cf, "copy_write_size_kib": cw,
                            "fetch_factor": ff, "write_factor": fw},
@@ -169,17 +169,24 @@ def _traffic():
 
 
 # ---------------------------------------------------------------- headline
-# inverse power with GMRES(40) inner solves: on this workload it measured
-# 450 ms (fp64) and 474 ms (mixed) per solve against 504 / 870 ms with
-# BiCGSTAB and 495 / 566 ms with GMRES(20); each GMRES iteration applies the
-# latency-bound preconditioner once, a BiCGSTAB iteration twice
-HEADLINE_METHOD = "invpow_gmres"
-HEADLINE_GMRES_M = 40
+# Inverse power on the colour-class order (greedy colouring visited in a
+# seeded random order, classes in RCM order): every ILU(0) substitution has
+# about 14 levels instead of ~2200 in RCM order.  Measured per solve on this
+# workload: fp64 131 ms with BiCGSTAB inner solves against 159 ms with
+# GMRES(40); mixed 134 ms with GMRES(40) against 193 ms with BiCGSTAB (in
+# complex64, BiCGSTAB needs 175 iterations for the three outer steps against
+# 78 for one fp64 step).  In RCM order the same solve took 443 ms (fp64,
+# GMRES(40)): bound by the ~2200 dependent levels of each preconditioner
+# application.
+HEADLINE_ORDERING = "colour"
+HEADLINE = {"fp64": ("invpow_bicgstab", 20), "mixed": ("invpow_gmres", 40)}
+RCM_COMPARE = ("invpow_gmres", 40)
 
 
 def headline(ssl, qs, torch, args):
     """Full C4 solves, fp64 and mixed: per-step times, iteration counts,
-    residuals; rho of the last step of each precision (host copy)."""
+    residuals; rho of the last step of each precision (host copy).  Then one
+    solve per precision in plain RCM order, for comparison."""
     ch = qs.config(4)
     N = ch.dim
     Hd = _device_csr(ch.H, torch)
@@ -187,48 +194,65 @@ def headline(ssl, qs, torch, args):
     out = torch.empty(N * N, dtype=torch.complex128, device="cuda")
     torch.cuda.synchronize()
 
-    def step(prec):
+    def step(prec, method, m, ordering):
         L = ssl.build_liouvillian(Hd, Cd)
-        _, info = ssl.solve(L, HEADLINE_METHOD, tol=1e-10, out=out, prec=prec, gmres_m=HEADLINE_GMRES_M)
+        _, info = ssl.solve(L, method, tol=1e-10, out=out, prec=prec, gmres_m=m, ordering=ordering)
         L.free()
         return info
 
     res = {}
     for prec in ("fp64", "mixed"):
+        method, m = HEADLINE[prec]
         for _ in range(args.warmup):
-            step(prec)
+            step(prec, method, m, HEADLINE_ORDERING)
         torch.cuda.synchronize()
         times, infos = [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ts = time.perf_counter()
-            infos.append(step(prec))
+            infos.append(step(prec, method, m, HEADLINE_ORDERING))
             torch.cuda.synchronize()
             times.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         rho = out.cpu().numpy().reshape(N, N, order="F")
         last = infos[-1]
-        res[prec] = {"solves_per_s": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+        res[prec] = {"method": method, "gmres_m": m if "gmres" in method else None, "ordering": HEADLINE_ORDERING,
+                     "solves_per_s": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
                      "median_ms": 1e3 * float(np.median(times)), "min_ms": 1e3 * float(np.min(times)),
                      "worst_resid_l2": max(i["resid_l2"] for i in infos), "outer_its": last["outer_its"],
                      "inner_its": last["inner_its"], "t_setup_ms": last["t_setup_ms"],
-                     "t_solve_ms": last["t_solve_ms"], "bandwidth": last["bandwidth"],
+                     "t_solve_ms": last["t_solve_ms"], "colours": last["colours"], "bandwidth": last["bandwidth"],
                      "nnz_matrix": last["nnz_matrix"], "nnz_factors": last["nnz_factors"], "rho": rho}
-        _log(f"kerr_chain_3x10 {prec}: {1e3 * dt / args.steps:.1f} ms per solve "
+        _log(f"kerr_chain_3x10 {prec} ({method}, colour order): {1e3 * dt / args.steps:.1f} ms per solve "
              f"(median {res[prec]['median_ms']:.1f}), set-up {last['t_setup_ms']:.1f} ms, "
              f"its {last['outer_its']}/{last['inner_its']}, resid {last['resid_l2']:.2e}")
+    rcm = {"method": RCM_COMPARE[0], "gmres_m": RCM_COMPARE[1], "ordering": "rcm"}
+    for prec in ("fp64", "mixed"):
+        ts = time.perf_counter()
+        info = step(prec, RCM_COMPARE[0], RCM_COMPARE[1], "rcm")
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - ts)
+        rcm[prec] = {"ms": ms, "solves_per_s": 1e3 / ms, "inner_its": info["inner_its"],
+                     "t_setup_ms": info["t_setup_ms"], "resid_l2": info["resid_l2"], "status": info["status"]}
+        _log(f"kerr_chain_3x10 {prec} in RCM order ({RCM_COMPARE[0]}): {ms:.1f} ms, its {info['inner_its']}")
+    res["rcm_order"] = rcm
     return ch, Hd, Cd, res
+
+
+def _prepared_chain(ssl, Hd, Cd):
+    L = ssl.build_liouvillian(Hd, Cd)
+    ssl.prepare(L, HEADLINE["fp64"][0], prec="mixed", ordering=HEADLINE_ORDERING)
+    return L
 
 
 def dominant_kernel(ssl, ch, Hd, Cd, res):
     """The headline step's dominant kernels, timed live with HIP events on
     the handle's stream (ss_time_operator): the preconditioner application
-    (lower then upper level-scheduled triangular solve) and the SpMV, both
-    complex128; algorithmic bytes from the factor and matrix sizes."""
-    L = ssl.build_liouvillian(Hd, Cd)
+    (lower then upper triangular solve, one launch per level) and the SpMV,
+    both complex128; algorithmic bytes from the factor and matrix sizes."""
+    L = _prepared_chain(ssl, Hd, Cd)
     try:
-        ssl.prepare(L, HEADLINE_METHOD, prec="mixed", gmres_m=HEADLINE_GMRES_M)
         _, n, nnzL = L.shape()
         A = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
         LU = ssl.export_csr(L, ssl.SS_MAT_LU)
@@ -253,31 +277,48 @@ def dominant_kernel(ssl, ch, Hd, Cd, res):
                      "note": "268 MB working set: partly served by the 256 MB Infinity Cache"},
         "spmv_L_c128": {"ms": tl, "bytes": bl, "GB/s": gbs(bl, tl)},
         "apply_L_matrix_free": {"ms": tm, "bytes": bm, "GB/s": gbs(bm, tm), "vs_spmv_L": tl / tm},
-        "nnz_matrix": int(A.nnz), "nnz_factors": int(LU.nnz), "n": int(n),
+        "nnz_matrix": int(A.nnz), "nnz_factors": int(LU.nnz), "n": int(n), "ordering": HEADLINE_ORDERING,
     }
     _log(f"precond c128 {t_pre:.3f} ms ({gbs(bp, t_pre):.0f} GB/s), c64 {t_pre32:.3f} ms; "
          f"spmv c128 {t128 * 1e3:.1f} us ({gbs(b128, t128):.0f} GB/s), c64 {t64 * 1e3:.1f} us "
          f"({gbs(b64, t64):.0f} GB/s)")
-    # per fp64 solve: inner iterations x (2 preconditioner applications + 2
-    # SpMV); the preconditioner dominates
-    # per fp64 solve: one application per GMRES iteration plus one per
-    # restart cycle (the correction M^-1 V y); BiCGSTAB applies it twice per
-    # iteration
+    # per fp64 solve: BiCGSTAB applies the preconditioner twice per iteration
+    # (GMRES once per iteration plus once per restart cycle)
     its = res["fp64"]["inner_its"]
-    applies = (its + -(-its // HEADLINE_GMRES_M)) if "gmres" in HEADLINE_METHOD else 2 * its
+    m = HEADLINE["fp64"][1]
+    applies = (its + -(-its // m)) if "gmres" in HEADLINE["fp64"][0] else 2 * its
     share = (applies * t_pre) / max(res["fp64"]["median_ms"], 1e-9)
     roof = {"bound": "hbm", "achieved": gbs(bp, t_pre), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": gbs(bp, t_pre) / PEAK_HBM_GBS, "traffic": None,
-            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128): one launch "
-                      "each of k_trsv_groups (row-group sync-free solve in level order) per application; "
-                      "latency-bound by the levels (1290 lower + 868 upper), not by HBM",
-            "bytes_per_launch": bp, "avg_launch_ms": t_pre, "launches_per_unit": 2,
+            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128, colour-class "
+                      "order): k_trsv_level, one launch per level of each factor (about 14 each); the unit is one "
+                      "application",
+            "bytes_per_launch": bp, "avg_launch_ms": t_pre, "unit_of_launch": "one application (all levels)",
             "applications_per_fp64_solve": applies,
             "share_of_fp64_step": share}
     tr = _traffic()
     if tr is not None:
         roof["traffic"] = tr
     return kern, roof
+
+
+def counter_run(ssl, qs, torch, apps):
+    """Only the dominant kernel: `apps` applications of the complex128
+    preconditioner on the headline's prepared Kerr chain (for the rocprofv3
+    counter runs that write profiles/traffic.json)."""
+    ch = qs.config(4)
+    Hd = _device_csr(ch.H, torch)
+    Cd = [_device_csr(c, torch) for c in ch.c_ops]
+    L = _prepared_chain(ssl, Hd, Cd)
+    x = torch.ones(L.n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    try:
+        for _ in range(apps):
+            ssl.apply(L, ssl.SS_OP_PRECOND, x.cpu().numpy(), prec="fp64")
+    finally:
+        L.free()
+    torch.cuda.synchronize()
+    _log(f"counter run: {apps} applications of the complex128 preconditioner")
 
 
 def cpu_baseline(ch, res):
@@ -289,7 +330,7 @@ def cpu_baseline(ch, res):
         t0 = time.perf_counter()
         rho, info = steady_state_iterative(ch.H, ch.c_ops, tol=1e-12)
         dt = time.perf_counter() - t0
-    errs = {p: float(np.max(np.abs(res[p]["rho"] - rho))) for p in res}
+    errs = {p: float(np.max(np.abs(res[p]["rho"] - rho))) for p in ("fp64", "mixed")}
     _log(f"cpu sparse reference: {dt:.1f} s, {info['iterations']} its, resid {info['resid_l2']:.1e}; "
          f"max|rho_gpu - rho_cpu| fp64 {errs['fp64']:.2e}, mixed {errs['mixed']:.2e}")
     cb = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
@@ -481,10 +522,16 @@ def main():
                          "the HBM counter runs)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write profiles/traffic.json from the rocpd databases of a FETCH_SIZE and a WRITE_SIZE "
-                         "counter run (both taken with --copy-calibration-mb 256) and exit; no GPU is used")
+                         "counter run (both taken with --copy-calibration-mb 256 --counter-apps N) and exit; no "
+                         "GPU is used")
+    ap.add_argument("--counter-apps", type=int, default=0,
+                    help="run only N applications of the dominant kernel (for the counter runs) and exit; with "
+                         "--traffic-from, the N those runs used")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(*args.traffic_from)
+        if args.counter_apps <= 0:
+            raise SystemExit("--traffic-from needs --counter-apps N (the applications the counter runs made)")
+        write_traffic(*args.traffic_from, apps=args.counter_apps)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: this build measures one "
@@ -508,6 +555,10 @@ def main():
         _log(f"calibration copy: {nb} bytes read and written")
         del src, dst
 
+    if args.counter_apps > 0:
+        counter_run(ssl, qs, torch, args.counter_apps)
+        return 0
+
     ch, Hd, Cd, res = headline(ssl, qs, torch, args)
     f64, mx = res["fp64"], res["mixed"]
     errors = {}
@@ -527,13 +578,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "kerr_chain_3x10: three coupled driven Kerr cavities, N = 10 each, J = 0.3 "
                                "(d = 1000, Liouvillian n = 1e6, 20.7 M non-zeros); one full solve per step "
-                               "(assembly, shift, RCM, ILU(0), inverse power with GMRES(40) inner solves, finish)",
-                   "method": HEADLINE_METHOD, "gmres_m": HEADLINE_GMRES_M, "tol": 1e-10, "ordering": "rcm",
-                   "ilu": "ilu0"},
+                               "(assembly, shift, RCM and the colour-class order, ILU(0), inverse power with "
+                               "BiCGSTAB (fp64) or GMRES(40) (mixed) inner solves, finish)",
+                   "method": {p: HEADLINE[p][0] for p in HEADLINE}, "gmres_m": HEADLINE["mixed"][1], "tol": 1e-10,
+                   "ordering": HEADLINE_ORDERING, "ilu": "ilu0"},
         "worst_resid_l2": f64["worst_resid_l2"],
         "fp64": {k: v for k, v in f64.items() if k != "rho"},
         "mixed": {k: v for k, v in mx.items() if k != "rho"},
         "mixed_vs_fp64": mx["solves_per_s"] / f64["solves_per_s"],
+        "rcm_order": res["rcm_order"],
     }
     legs = [x for x in args.legs.split(",") if x]
     try:

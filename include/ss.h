@@ -300,7 +300,9 @@ int ss_export_perm(ss_liouv L, int32_t *perm);
 #define SS_OP_SPMV_APERM  1  /* y = (P A P^T) x  (prec selects c128 / c64)     */
 #define SS_OP_PRECOND     2  /* y = (LU)^-1 x    (prec selects c128 / c64),
                                 the solver's own choice of the ways below:
-                                BLOCK up to n = 65536, GROUPS above        */
+                                BLOCK up to n = 65536; above, CLASSES when
+                                no factor has more than 64 levels, else
+                                GROUPS                                     */
 #define SS_OP_LSOLVE      3  /* y = L_f^-1 x     unit lower factor             */
 #define SS_OP_USOLVE      4  /* y = U_f^-1 x     upper factor                  */
 #define SS_OP_PRECOND_SYNCFREE 5 /* y = (LU)^-1 x, sync-free solves over all

@@ -17,15 +17,16 @@
 // that no neighbour of higher priority -- earlier in the visit -- carries.
 // The classes then follow in increasing colour, each in RCM order.  Both
 // steps give the same result as their sequential definitions, bit for bit:
-//  * k_colour_round, repeated until every vertex is coloured: a listed
-//    vertex walks its row from where it stopped, eight entries at a time,
-//    collecting the colours of its earlier neighbours, and stops at the
-//    first one still uncoloured (it is listed for the next round).  A vertex
-//    that reaches the end of its row is final.  The priority graph of a
-//    random order is shallow (62 levels on the Kerr chain at n = 10^6,
-//    against ~4000 for the RCM order), so the rounds are few.  Colours past
-//    63 (dense rows only) are found by the wavefront together through a
-//    bitmap in LDS; up to 4096 colours are supported.
+//  * The visit's dependency graph (each vertex after its earlier
+//    neighbours) is walked frontier by frontier: k_colour_init counts each
+//    vertex's earlier neighbours; k_colour_front colours a frontier (every
+//    earlier neighbour done) and counts each vertex off at its later
+//    neighbours, those reaching zero forming the next frontier.  Each edge
+//    is looked at a bounded number of times, and the frontiers are few: the
+//    graph of a random order is shallow (62 levels on the Kerr chain at
+//    n = 10^6, against ~4000 for the RCM order).  Colours past 63 (dense
+//    rows only) are found by the wavefront together through a bitmap in
+//    LDS; up to 4096 colours are supported.
 //  * bucket_sort puts the vertices in (colour, RCM position) order.
 #include "bucket.hpp"
 #include "rcm.hpp"
@@ -36,24 +37,16 @@ namespace ss {
 
 namespace {
 
-constexpr int COL_PASS = 8;      // row entries examined per pass
 constexpr int COL_MAX = 4096;    // colours the ordering supports
 constexpr int COL_BS = 256;
 
 __device__ inline int ld_colour(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ inline void st_colour(int *p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
-// visit priority of vertex v: output v of SplitMix64 seeded with 0
-__global__ void k_priorities(int n, const int *rowptr, uint64_t *key, int *colour, int *cursor,
-                             unsigned long long *taken) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    key[v] = splitmix64((uint64_t)v * 0x9E3779B97F4A7C15ull);
-    colour[v] = -1;
-    cursor[v] = rowptr[v];
-    taken[v] = 0;
+// visit priority of vertex v: output v of SplitMix64 seeded with 0; u comes
+// before v in the visit when (priority, index) is smaller
+__device__ inline uint64_t priority(int v) { return splitmix64((uint64_t)v * 0x9E3779B97F4A7C15ull); }
+__device__ inline bool visits_before(int u, uint64_t ku, int v, uint64_t kv) {
+    return ku < kv || (ku == kv && u < v);
 }
 
 // orders the LDS accesses of one wavefront (no other wavefront takes part)
@@ -63,89 +56,78 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One round over the m listed vertices (list == nullptr: all vertices).
-// cursor[v] / taken[v] keep where a vertex stopped and the colours below 64
-// its earlier neighbours carry, so a row is read once over all rounds.
-__global__ void __launch_bounds__(COL_BS) k_colour_round(int m, const int *list, const int *rowptr, const int *col,
-                                                         const uint64_t *key, int *colour, int *cursor,
-                                                         unsigned long long *taken, int *next, int *nnext,
-                                                         int *ncol, unsigned *status) {
+// appends the lanes with `take` set to list[*count ...] (one atomic per wavefront)
+__device__ inline void append(bool take, int v, int *list, int *count) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long b = __ballot(take);
+    int at = 0;
+    if (lane == 0 && b) at = atomicAdd(count, __popcll(b));
+    at = __shfl(at, 0, 64) + __popcll(b & ((1ull << lane) - 1ull));
+    if (take) list[at] = v;
+}
+
+// cnt[v] = neighbours visited before v; vertices with none start the frontier
+__global__ void __launch_bounds__(COL_BS) k_colour_init(int n, const int *rowptr, const int *col, int *colour,
+                                                        int *cnt, int *front, int *nfront) {
+    const int v = blockIdx.x * COL_BS + threadIdx.x;
+    int c = 0;
+    if (v < n) {
+        const uint64_t kv = priority(v);
+        for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+            const int u = col[e];
+            if (u != v && visits_before(u, priority(u), v, kv)) ++c;
+        }
+        cnt[v] = c;
+        colour[v] = -1;
+    }
+    append(v < n && c == 0, v, front, nfront);
+}
+
+// One frontier: every listed vertex has all its earlier neighbours coloured
+// (in earlier launches).  It takes the lowest colour none of them carries,
+// then counts itself off at each later neighbour; a neighbour whose count
+// reaches zero joins the next frontier.  Colours from 64 on (dense rows
+// only) are found by the wavefront together through a bitmap in LDS.
+__global__ void __launch_bounds__(COL_BS) k_colour_front(int m, const int *front, const int *rowptr, const int *col,
+                                                         int *colour, int *cnt, int *next, int *nnext, int *ncol,
+                                                         unsigned *status) {
     __shared__ unsigned long long bm[COL_BS / 64][COL_MAX / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t = blockIdx.x * COL_BS + threadIdx.x;
     const bool active = t < m;
-    int v = 0, e = 0, e1 = 0;
+    int v = 0, e0 = 0, e1 = 0;
     uint64_t kv = 0;
-    unsigned long long tk = 0;
+    unsigned long long taken = 0;
     if (active) {
-        v = list ? list[t] : t;
-        kv = key[v];
-        e = cursor[v];
+        v = front[t];
+        kv = priority(v);
+        e0 = rowptr[v];
         e1 = rowptr[v + 1];
-        tk = taken[v];
-    }
-    bool blocked = false;
-    // a vertex listed again first looks only at the neighbour that stopped it
-    if (list && active && e < e1 && ld_colour(colour + col[e]) < 0) blocked = true;
-    while (active && !blocked && e < e1) {
-        int c[COL_PASS];
-#pragma unroll
-        for (int q = 0; q < COL_PASS; ++q) {
-            c[q] = 0x7fffffff;  // later in the visit, or v itself: no constraint
-            if (e + q < e1) {
-                const int u = col[e + q];
-                if (u != v) {
-                    const uint64_t ku = key[u];
-                    if (ku < kv || (ku == kv && u < v)) c[q] = ld_colour(colour + u);
-                }
-            }
+        for (int e = e0; e < e1; ++e) {
+            const int u = col[e];
+            if (u == v || !visits_before(u, priority(u), v, kv)) continue;
+            const int c = colour[u];
+            if (c < 64) taken |= 1ull << c;
         }
-        int used = 0;
-#pragma unroll
-        for (int q = 0; q < COL_PASS; ++q) {
-            if (!blocked && e + q < e1) {
-                if (c[q] < 0) {
-                    blocked = true;
-                } else {
-                    if (c[q] < 64) tk |= 1ull << c[q];
-                    ++used;
-                }
-            }
-        }
-        e += used;
     }
-    // blocked vertices go to the next round's list: one atomic per wavefront
-    const unsigned long long bl = __ballot(blocked);
-    int at = 0;
-    if (lane == 0 && bl) at = atomicAdd(nnext, __popcll(bl));
-    at = __shfl(at, 0, 64) + __popcll(bl & ((1ull << lane) - 1ull));
-    if (blocked) {
-        cursor[v] = e;
-        taken[v] = tk;
-        next[at] = v;
-    } else if (active && ~tk) {
-        const int mine = __builtin_ctzll(~tk);
-        st_colour(colour + v, mine);
-        atomicMax(ncol, mine + 1);
-    }
+    int mine = -1;
+    if (active && ~taken) mine = __builtin_ctzll(~taken);
     // colours 0..63 all taken: the wavefront scans each such row into a
-    // bitmap of COL_MAX colours (every earlier neighbour is coloured)
-    unsigned long long slow = __ballot(active && !blocked && !~tk);
+    // bitmap of COL_MAX colours
+    unsigned long long slow = __ballot(active && !~taken);
     while (slow) {
         const int L = __ffsll((long long)slow) - 1;
         slow &= slow - 1;
         const int vv = __shfl(v, L, 64);
-        const uint64_t kk = ((uint64_t)__shfl((unsigned)(kv >> 32), L, 64) << 32) | (unsigned)__shfl((unsigned)kv, L, 64);
+        const uint64_t kk = priority(vv);
         const int a = rowptr[vv], b = rowptr[vv + 1];
         bm[wave][lane] = 0;
         wave_sync();
         bool over = false;
         for (int f = a + lane; f < b; f += 64) {
             const int u = col[f];
-            if (u == vv) continue;
-            const uint64_t ku = key[u];
-            if (!(ku < kk || (ku == kk && u < vv))) continue;
-            const int cc = ld_colour(colour + u);
+            if (u == vv || !visits_before(u, priority(u), vv, kk)) continue;
+            const int cc = colour[u];
             if (cc >= 0 && cc < COL_MAX) atomicOr(&bm[wave][cc >> 6], 1ull << (cc & 63));
             else over = true;
         }
@@ -156,15 +138,29 @@ __global__ void __launch_bounds__(COL_BS) k_colour_round(int m, const int *list,
         if (lane == L) {
             if (overflow) {
                 atomicOr(status, STATUS_OVERFLOW);  // more colours than supported: the host rejects
-                st_colour(colour + v, COL_MAX);
+                mine = COL_MAX;
             } else {
                 const int word = __ffsll((long long)open) - 1;
-                const int mine = word * 64 + __builtin_ctzll(~bm[wave][word]);
-                st_colour(colour + v, mine);
-                atomicMax(ncol, mine + 1);
+                mine = word * 64 + __builtin_ctzll(~bm[wave][word]);
             }
         }
         wave_sync();
+    }
+    if (active) {
+        colour[v] = mine;
+        atomicMax(ncol, mine + 1);
+    }
+    // count off at the later neighbours, one row entry per lane and step
+    for (int k = 0;; ++k) {
+        const bool more = active && e0 + k < e1;
+        if (!__any(more)) break;
+        bool ready = false;
+        int w = 0;
+        if (more) {
+            w = col[e0 + k];
+            if (w != v && visits_before(v, kv, w, priority(w))) ready = atomicSub(cnt + w, 1) == 1;
+        }
+        append(ready, w, next, nnext);
     }
 }
 
@@ -182,35 +178,32 @@ int colour_order(const CsrBuf<double2> &S, const DevBuf<int> &base_perm, const D
     perm.resize((size_t)std::max(n, 1));
     iperm.resize((size_t)std::max(n, 1));
     if (n == 0) return 0;
-    DevBuf<uint64_t> key((size_t)n);
-    DevBuf<unsigned long long> taken((size_t)n);
-    DevBuf<int> colour((size_t)n), cursor((size_t)n), la((size_t)n), lb((size_t)n), cnt(2);
+    DevBuf<int> colour((size_t)n), cnt((size_t)n), la((size_t)n), lb((size_t)n), ctr(3);
     DevBuf<unsigned> status(1);
-    k_priorities<<<div_up(n, 256), 256, 0, s>>>(n, S.rowptr.get(), key.get(), colour.get(), cursor.get(),
-                                                taken.get());
-    SS_HIP(hipMemsetAsync(cnt.get(), 0, 2 * sizeof(int), s));  // [0] listed for the next round, [1] colours
+    SS_HIP(hipMemsetAsync(ctr.get(), 0, 3 * sizeof(int), s));  // [0] frontier sizes, [1] next, [2] colours
     SS_HIP(hipMemsetAsync(status.get(), 0, sizeof(unsigned), s));
+    k_colour_init<<<div_up(n, COL_BS), COL_BS, 0, s>>>(n, S.rowptr.get(), S.col.get(), colour.get(), cnt.get(),
+                                                       la.get(), ctr.get());
     SS_HIP(hipGetLastError());
-    // every round colours at least the listed vertex of highest priority
-    int m = n;
-    const int *list = nullptr;
-    int *out = la.get(), *spare = lb.get();
-    for (int round = 0; m > 0; ++round) {
-        SS_REQUIRE(round <= n, SS_E_HIP, "greedy colouring: no progress");
-        k_colour_round<<<div_up(m, COL_BS), COL_BS, 0, s>>>(m, list, S.rowptr.get(), S.col.get(), key.get(),
-                                                           colour.get(), cursor.get(), taken.get(), out, cnt.get(),
-                                                           cnt.get() + 1, status.get());
+    int m = 0, done = 0;
+    d2h(&m, ctr.get(), 1, s);
+    int *front = la.get(), *next = lb.get();
+    // each frontier is one level of the visit's dependency graph
+    while (m > 0) {
+        done += m;
+        SS_REQUIRE(done <= n, SS_E_HIP, "greedy colouring: a vertex was listed twice");
+        k_colour_front<<<div_up(m, COL_BS), COL_BS, 0, s>>>(m, front, S.rowptr.get(), S.col.get(), colour.get(),
+                                                           cnt.get(), next, ctr.get() + 1, ctr.get() + 2,
+                                                           status.get());
         SS_HIP(hipGetLastError());
-        int left = 0;
-        d2h(&left, cnt.get(), 1, s);
-        SS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
-        m = left;
-        list = out;
-        std::swap(out, spare);
+        d2h(&m, ctr.get() + 1, 1, s);
+        SS_HIP(hipMemsetAsync(ctr.get() + 1, 0, sizeof(int), s));
+        std::swap(front, next);
     }
+    SS_REQUIRE(done == n, SS_E_HIP, "greedy colouring: vertices left uncoloured");
     int C = 0;
     unsigned st = 0;
-    d2h(&C, cnt.get() + 1, 1, s);
+    d2h(&C, ctr.get() + 2, 1, s);
     d2h(&st, status.get(), 1, s);
     SS_REQUIRE(!(st & STATUS_OVERFLOW), SS_E_INVALID_ARG, "colour order: more than 4096 colours");
     SS_REQUIRE(C >= 1 && C <= n, SS_E_HIP, "greedy colouring: colour count out of range");

@@ -113,8 +113,10 @@ struct Precond {
     // rounded copy shares) and packed factors, and switch apply() to a
     // level-scheduled solve: PRE_BLOCK (one workgroup, barrier per level),
     // PRE_LEVELS (sync-free over all CUs in level order), PRE_GROUPS (the
-    // same with 16 lanes per row and gated polling) or PRE_AUTO (PRE_BLOCK
-    // for n <= PRE_BLOCK_MAX_N, else PRE_GROUPS).
+    // same with 16 lanes per row and gated polling), PRE_CLASSES (one launch
+    // per level) or PRE_AUTO (PRE_BLOCK for n <= PRE_BLOCK_MAX_N, else
+    // PRE_CLASSES when no factor has more than PRE_CLASSES_MAX_LEVELS
+    // levels, else PRE_GROUPS).
     void use_levels(const Csr<double2> &lu64, hipStream_t s, int m = PRE_AUTO);
     // PRE_GROUPS over level schedules and gates owned by the caller (they
     // must outlive this object)

@@ -12,9 +12,9 @@ _spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(
 bench = importlib.util.module_from_spec(_spec)
 _spec.loader.exec_module(bench)
 
-KERNEL = "void ss::(anonymous namespace)::k_trsv_groups<HIP_vector_type<double, 2u>, false>(int, int, ...)"
-KERNEL_UP = "void ss::(anonymous namespace)::k_trsv_groups<HIP_vector_type<double, 2u>, true>(int, int, ...)"
-KERNEL_C64 = "void ss::(anonymous namespace)::k_trsv_groups<HIP_vector_type<float, 2u>, false>(int, int, ...)"
+KERNEL = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<double, 2u>, false, 4, 3>(int, int, ...)"
+KERNEL_UP = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<double, 2u>, true, 4, 3>(int, int, ...)"
+KERNEL_C64 = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<float, 2u>, false, 4, 3>(int, int, ...)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
@@ -33,28 +33,27 @@ def _db(path, counter, rows):
 def test_traffic_record_scales_each_counter_by_the_copy(tmp_path):
     copy_kib = bench.COPY_BYTES / 1024
     grid = bench.COPY_BYTES // 2048
-    # the copy reads its bytes twice over in FETCH_SIZE (factor 1/2) and once in WRITE_SIZE
-    # two dispatches of the lower launch (mean 1000), one of the upper (500),
-    # one of the complex64 instance (not counted)
-    # the calibration copy is the first copy with its grid; a later copy with
-    # the same grid (another size) is not used
-    _db(tmp_path / "f.db", "FETCH_SIZE", [(COPY, 512, 3.0), (COPY, grid, copy_kib / 2), (KERNEL, grid, 900.0),
-                                          (KERNEL, grid, 1100.0), (KERNEL_UP, grid, 500.0), (KERNEL_C64, grid, 7.0),
-                                          (COPY, grid, 77.0)])
-    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, copy_kib), (KERNEL, grid, 250.0), (KERNEL_UP, grid, 50.0),
-                                          (COPY, grid, 99.0)])
+    # the copy reads its bytes twice over in FETCH_SIZE (factor 1/2) and once in WRITE_SIZE.
+    # Two applications, each one launch per level: lower levels 300 and 200, upper 250;
+    # a complex64 launch is not counted.  The calibration copy is the first copy with its
+    # grid; a later copy with the same grid (another size) is not used.
+    app_f = [(KERNEL, 4096, 300.0), (KERNEL, 2048, 200.0), (KERNEL_UP, 4096, 250.0)]
+    app_w = [(KERNEL, 4096, 40.0), (KERNEL, 2048, 20.0), (KERNEL_UP, 4096, 30.0)]
+    _db(tmp_path / "f.db", "FETCH_SIZE", [(COPY, 512, 3.0), (COPY, grid, copy_kib / 2)] + app_f
+        + [(KERNEL_C64, grid, 7.0)] + app_f + [(COPY, grid, 77.0)])
+    _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, copy_kib)] + app_w + app_w + [(COPY, grid, 99.0)])
     out = tmp_path / "traffic.json"
-    rec = bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(out))
+    rec = bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), 2, str(out))
     assert json.load(open(out)) == rec
     assert rec["calibration"]["fetch_factor"] == pytest.approx(2.0)
     assert rec["calibration"]["write_factor"] == pytest.approx(1.0)
-    assert rec["fetch_bytes_per_launch"] == pytest.approx(1500.0 * 1024 * 2.0)
-    assert rec["write_bytes_per_launch"] == pytest.approx(300.0 * 1024)
-    assert rec["hbm_bytes_per_launch"] == pytest.approx(1500.0 * 1024 * 2.0 + 300.0 * 1024)
+    assert rec["fetch_bytes_per_launch"] == pytest.approx(750.0 * 1024 * 2.0)
+    assert rec["write_bytes_per_launch"] == pytest.approx(90.0 * 1024)
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(750.0 * 1024 * 2.0 + 90.0 * 1024)
     assert rec["sources_sha256"] == bench.source_digest(bench.KERNEL_SOURCE)
     assert rec["kernel_match"] == bench.KERNEL_MATCH
-    assert rec["dispatches"] == {"fetch": 3, "write": 2}
-    assert rec["kernels"] == {"fetch": 2, "write": 2}
+    assert rec["dispatches"] == {"fetch": 6, "write": 6}
+    assert rec["applications"] == 2
 
 
 def test_traffic_record_needs_the_solver_and_the_copy(tmp_path):
@@ -62,7 +61,7 @@ def test_traffic_record_needs_the_solver_and_the_copy(tmp_path):
     _db(tmp_path / "f.db", "FETCH_SIZE", [(KERNEL, grid, 1000.0)])
     _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, grid, 1.0), (KERNEL, grid, 1.0)])
     with pytest.raises(SystemExit):
-        bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(tmp_path / "t.json"))
+        bench.write_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), 1, str(tmp_path / "t.json"))
 
 
 def test_source_digest_follows_included_headers(tmp_path):
