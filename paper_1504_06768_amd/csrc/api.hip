@@ -328,7 +328,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<double2> M;
                 M.setup(&L->LU, L->lu_diag.get(), n, s);
-                if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op));
+                if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op), L->colours ? L->lorder.get() : nullptr);
                 if (pre) M.apply(xd.get(), yd.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xd.get(), yd.get(), s);
                 else M.upper(xd.get(), yd.get(), s);
@@ -343,7 +343,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<float2> M;
                 M.setup(&L->LU32, L->lu_diag.get(), n, s);
-                if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op));
+                if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op), L->colours ? L->lorder.get() : nullptr);
                 if (pre) M.apply(xf.get(), yf.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xf.get(), yf.get(), s);
                 else M.upper(xf.get(), yf.get(), s);
@@ -391,7 +391,7 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             }
             ss::Precond<T> M;
             if (pre) M.setup(LU, L->lu_diag.get(), n, s);
-            if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op));
+            if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op), L->colours ? L->lorder.get() : nullptr);
             const ss::Csr<T> Av = A->view();
             const int g = ss::spmv_group(Av.n, Av.nnz);
             auto once = [&]() {

@@ -34,6 +34,7 @@ struct ss_liouv_s {
     int guarded = 0;
     int diag_added = 0;        // explicit zero diagonals added to Ap
     int colours = 0;           // colour classes of SS_ORDER_COLOUR (else 0)
+    ss::DevBuf<int> lorder;    // SS_ORDER_COLOUR: row of each RCM position (rows' order inside a level)
     double t_setup_ms = 0;
     // level schedules of the factors and the gates of the row-group
     // triangular solves, built by ss_prepare for the device-wide path and

@@ -822,8 +822,8 @@ inline unsigned slots_blocks(int n) {
 }
 
 template <typename T>
-void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s, int m) {
-    build_levels(lu64, diag, lo, up, s);
+void Precond<T>::use_levels(const Csr<double2> &lu64, hipStream_t s, int m, const int *order) {
+    build_levels(lu64, diag, lo, up, s, order);
     if (m == PRE_AUTO) {
         const bool shallow = std::max(lo.nlev, up.nlev) <= PRE_CLASSES_MAX_LEVELS;
         m = (n <= PRE_BLOCK_MAX_N) ? PRE_BLOCK : shallow ? PRE_CLASSES : PRE_GROUPS;

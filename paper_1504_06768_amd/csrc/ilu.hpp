@@ -117,7 +117,7 @@ struct Precond {
     // per level) or PRE_AUTO (PRE_BLOCK for n <= PRE_BLOCK_MAX_N, else
     // PRE_CLASSES when no factor has more than PRE_CLASSES_MAX_LEVELS
     // levels, else PRE_GROUPS).
-    void use_levels(const Csr<double2> &lu64, hipStream_t s, int m = PRE_AUTO);
+    void use_levels(const Csr<double2> &lu64, hipStream_t s, int m = PRE_AUTO, const int *order = nullptr);
     // PRE_GROUPS over level schedules and gates owned by the caller (they
     // must outlive this object)
     void borrow_groups(const LevelSched *lo_, const LevelSched *up_, const int *glo, const int *gup, hipStream_t s);

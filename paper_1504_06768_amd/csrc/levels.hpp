@@ -20,7 +20,10 @@ struct LevelSched {
 // Level sets of the strict lower part (forward) and of the strict upper part
 // (backward) of the ILU factors; a row's level is one more than the largest
 // level among the rows it depends on.
-void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s);
+// order (optional, n entries): the rows in the order they take inside a
+// level (default: increasing row index).
+void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s,
+                  const int *order = nullptr);
 
 // The level analysis of many systems in one launch (one workgroup each):
 // job() sets up one system's scratch on its stream, levels_batch runs every
@@ -37,7 +40,7 @@ struct LevelBuild {
     DevBuf<unsigned> status;
     LevelJob job(const Csr<double2> &LU, const int *diag, hipStream_t s);
     template <bool UPPER>
-    void finish(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s);
+    void finish(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s, const int *order = nullptr);
 };
 template <bool UPPER>
 void levels_batch(const LevelJob *jobs, int count, hipStream_t s);

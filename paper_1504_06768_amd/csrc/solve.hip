@@ -132,10 +132,23 @@ static void add_zero_diagonal(ss_liouv h, hipStream_t s) {
     SS_REQUIRE(still == 0, SS_E_ZERO_PIVOT, "could not give every row a diagonal entry");
 }
 
-// RCM order -> colour-class order (SS_ORDER_COLOUR)
+__global__ void k_rows_by_rcm(int n, const int *rcm_perm, const int *iperm, int *lorder) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) lorder[p] = iperm[rcm_perm[p]];
+}
+
+// RCM order -> colour-class order (SS_ORDER_COLOUR).  lorder keeps, for
+// each RCM position, the row it became: rows inside a level of the factors'
+// schedules are taken in RCM order, so that the rows running together
+// gather from nearby parts of every class.
 static void recolour(ss_liouv h, hipStream_t s) {
     DevBuf<int> perm, iperm;
     h->colours = colour_order(h->S, h->perm, h->iperm, perm, iperm, s);
+    h->lorder.resize((size_t)std::max(h->n, 1));
+    if (h->n) {
+        k_rows_by_rcm<<<div_up(h->n, 256), 256, 0, s>>>(h->n, h->perm.get(), iperm.get(), h->lorder.get());
+        SS_HIP(hipGetLastError());
+    }
     h->perm = std::move(perm);
     h->iperm = std::move(iperm);
 }
@@ -203,7 +216,7 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     const bool want_sched = !use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31);
     bool sched_built = false;
     if (o.ilu == SS_ILU0 && want_sched) {
-        build_levels(h->Ap.view(), h->diag.get(), h->sched_lo, h->sched_up, s);
+        build_levels(h->Ap.view(), h->diag.get(), h->sched_lo, h->sched_up, s, h->colours ? h->lorder.get() : nullptr);
         sched_built = true;
         phase("levels");
     }
@@ -221,7 +234,9 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     phase("finish");
     h->sched_ready = false;
     if (want_sched) {
-        if (!sched_built) build_levels(h->LU.view(), h->lu_diag.get(), h->sched_lo, h->sched_up, s);
+        if (!sched_built)
+            build_levels(h->LU.view(), h->lu_diag.get(), h->sched_lo, h->sched_up, s,
+                         h->colours ? h->lorder.get() : nullptr);
         group_gates(h->sched_lo, h->n, h->gate_lo, s);
         group_gates(h->sched_up, h->n, h->gate_up, s);
         h->sched_ready = true;
@@ -593,11 +608,11 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
             if (classes && h->sched_ready)
                 M.borrow_classes(&h->sched_lo, &h->sched_up);
             else if (classes)
-                M.use_levels(h->LU.view(), s, PRE_CLASSES);
+                M.use_levels(h->LU.view(), s, PRE_CLASSES, h->colours ? h->lorder.get() : nullptr);
             else if (groups && h->sched_ready)
                 M.borrow_groups(&h->sched_lo, &h->sched_up, h->gate_lo.get(), h->gate_up.get(), s);
             else
-                M.use_levels(h->LU.view(), s, mode);
+                M.use_levels(h->LU.view(), s, mode, h->colours ? h->lorder.get() : nullptr);
         }
         Krylov<T> K;
         K.init(Ain.view(), &M, s);

@@ -28,7 +28,12 @@ template <typename T, bool UPPER, int G, int U>
 __global__ void __launch_bounds__(CLS_BS) k_trsv_level(int lo, int hi, const int4 *slot, const int *col,
                                                        const T *val, const T *in, T *out, const int *skip) {
     if (skip && *skip) return;
-    const int t = blockIdx.x * CLS_BS + threadIdx.x;
+    // workgroups go round-robin to the eight XCDs (b -> b % 8); renumbered
+    // so that each XCD takes a contiguous eighth of the level, whose rows
+    // gather from a narrower part of the vector through that XCD's L2
+    const unsigned g = gridDim.x, bx = blockIdx.x;
+    const unsigned lb = (g % 8) ? bx : (bx % 8) * (g / 8) + bx / 8;
+    const int t = (int)lb * CLS_BS + threadIdx.x;
     const int idx = lo + t / G, l = t % G;
     const bool active = idx < hi;
     int4 sl = make_int4(0, 0, 0, 0);
@@ -75,7 +80,7 @@ void levels_launch(const LevelSched &ls, const Csr<T> &LU, const T *in, T *out, 
     for (int l = 0; l < ls.nlev; ++l) {
         const int lo = ls.hptr[(size_t)l], hi = ls.hptr[(size_t)l + 1];
         if (hi <= lo) continue;
-        const unsigned grid = (unsigned)div_up((int64_t)(hi - lo) * G, CLS_BS);
+        const unsigned grid = (unsigned)((div_up((int64_t)(hi - lo) * G, CLS_BS) + 7) / 8 * 8);  // a multiple of 8
         k_trsv_level<T, UPPER, G, U><<<grid, CLS_BS, 0, s>>>(lo, hi, ls.slot.get(), LU.col, LU.val, in, out, skip);
     }
 }

@@ -207,6 +207,12 @@ __global__ void __launch_bounds__(1024) k_levels_batch_lds(const LevelJob *jobs)
     if (threadIdx.x == 0 && smax >= 0) atomicMax(J.maxlvl, smax);
 }
 
+// out[p] = in[idx[p]]
+__global__ void k_gather_i32(int n, const int *idx, const int *in, int *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) out[p] = in[idx[p]];
+}
+
 // slot[q] for the q-th row in level order
 template <bool UPPER>
 __global__ void k_level_slots(int n, const int *rows, const int *rowptr, const int *diag, int4 *slot) {
@@ -244,7 +250,7 @@ LevelJob LevelBuild::job(const Csr<double2> &LU, const int *diag, hipStream_t s)
 }
 
 template <bool UPPER>
-void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s) {
+void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s, const int *order) {
     const int n = LU.n;
     int maxl = 0;
     unsigned st = 0;
@@ -256,7 +262,14 @@ void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls,
     ls.slot.resize((size_t)std::max(n, 1));
     // rows in (level, row) order, then their slots
     DevBuf<int> rows((size_t)std::max(n, 1));
-    bucket_sort(n, lvl.get(), ls.nlev, nullptr, rows.get(), nullptr, ls.ptr.get(), s);
+    if (order && n) {
+        DevBuf<int> key((size_t)n);
+        k_gather_i32<<<div_up(n, 256), 256, 0, s>>>(n, order, lvl.get(), key.get());
+        SS_HIP(hipGetLastError());
+        bucket_sort(n, key.get(), ls.nlev, order, rows.get(), nullptr, ls.ptr.get(), s);
+    } else {
+        bucket_sort(n, lvl.get(), ls.nlev, nullptr, rows.get(), nullptr, ls.ptr.get(), s);
+    }
     if (n) {
         k_level_slots<UPPER><<<div_up(n, 256), 256, 0, s>>>(n, rows.get(), LU.rowptr, diag, ls.slot.get());
         SS_HIP(hipGetLastError());
@@ -264,8 +277,8 @@ void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls,
     ls.hptr.resize((size_t)ls.nlev + 1);
     d2h(ls.hptr.data(), ls.ptr.get(), (size_t)ls.nlev + 1, s);  // (synchronises)
 }
-template void LevelBuild::finish<false>(const Csr<double2> &, const int *, LevelSched &, hipStream_t);
-template void LevelBuild::finish<true>(const Csr<double2> &, const int *, LevelSched &, hipStream_t);
+template void LevelBuild::finish<false>(const Csr<double2> &, const int *, LevelSched &, hipStream_t, const int *);
+template void LevelBuild::finish<true>(const Csr<double2> &, const int *, LevelSched &, hipStream_t, const int *);
 
 template <bool UPPER>
 void levels_batch(const LevelJob *jobs, int count, hipStream_t s) {
@@ -291,7 +304,7 @@ template void levels_batch<false>(const LevelJob *, int, hipStream_t);
 template void levels_batch<true>(const LevelJob *, int, hipStream_t);
 
 template <bool UPPER>
-static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s) {
+static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s, const int *order) {
     const int n = LU.n;
     LevelBuild lb;
     LevelJob j = lb.job(LU, diag, s);
@@ -303,12 +316,13 @@ static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hi
                                              j.status, j.maxlvl);
         SS_HIP(hipGetLastError());
     }
-    lb.finish<UPPER>(LU, diag, ls, s);
+    lb.finish<UPPER>(LU, diag, ls, s, order);
 }
 
-void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s) {
-    one_side<false>(LU, diag, lo, s);
-    one_side<true>(LU, diag, up, s);
+void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s,
+                  const int *order) {
+    one_side<false>(LU, diag, lo, s, order);
+    one_side<true>(LU, diag, up, s, order);
 }
 
 template <typename T>
