@@ -170,3 +170,25 @@ def test_colour_precond_matches_triangular_solves():
         assert np.max(np.abs(outs[op] - ref)) <= 1e-11 * np.max(np.abs(ref)), op
     for op in (ssl.SS_OP_PRECOND_LEVELS, ssl.SS_OP_PRECOND_GROUPS):
         assert np.array_equal(outs[op], outs[ssl.SS_OP_PRECOND_SYNCFREE]), op
+
+
+@pytest.mark.parametrize("name", ["jc8", "kerr20", "opto3x5"])
+def test_level_ilu0_equals_sync_free_ilu0(name):
+    """The ILU(0) run one launch per level (device-wide path, shallow
+    schedule) gives the same factors, bit for bit, as the sync-free
+    factorisation (the workgroup path's set-up) on the same colour-ordered
+    matrix, and both match the oracle's ILU(0)."""
+    s = SMALL[name]()
+    La = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(La, "trace_gmres", ordering="colour", path="device")
+    Lb = ssl.build_liouvillian(s.H, s.c_ops)
+    ssl.prepare(Lb, "trace_bicgstab", ordering="colour", path="workgroup")
+    Aa, Ab = ssl.export_csr(La, ssl.SS_MAT_A_PERM), ssl.export_csr(Lb, ssl.SS_MAT_A_PERM)
+    assert (Aa != Ab).nnz == 0
+    LUa, LUb = ssl.export_csr(La, ssl.SS_MAT_LU), ssl.export_csr(Lb, ssl.SS_MAT_LU)
+    assert np.array_equal(LUa.indptr, LUb.indptr) and np.array_equal(LUa.indices, LUb.indices)
+    assert np.array_equal(LUa.data, LUb.data)
+    LUo, _ = oilu.ilu0(Aa, guard=1e-8, boost=0.1)
+    rel = np.abs(LUa.data - LUo.data) / np.maximum(np.abs(LUo.data), 1e-300)
+    big = np.abs(LUo.data) > 1e-10 * np.abs(LUo.data).max()
+    assert np.max(rel[big]) <= 1e-11
