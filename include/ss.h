@@ -118,8 +118,12 @@ typedef struct ss_server_s *ss_server;
                                 most as many dependent levels as colours
                                 (about 14 on the Liouvillians here, against
                                 ~10^3 in RCM order), at the price of more
-                                Krylov iterations.  ss_info.colours reports
-                                the count.                                */
+                                Krylov iterations.  On the device-wide path
+                                only the factors take this order: the
+                                Krylov iteration and its SpMV stay in RCM
+                                order, the permutation folded into the
+                                first and last substitution.
+                                ss_info.colours reports the count.        */
 
 typedef struct {
     int32_t prec;       /* SS_FP64 | SS_MIXED                       (SS_FP64)  */
@@ -283,7 +287,10 @@ int ss_prepare(ss_liouv L, int32_t method, const ss_options *opt);
 
 #define SS_MAT_L         0  /* assembled Liouvillian, natural order            */
 #define SS_MAT_A         1  /* transformed matrix (L~ or L - sigma I), natural  */
-#define SS_MAT_A_PERM    2  /* transformed matrix after the ordering: P A P^T  */
+#define SS_MAT_A_PERM    2  /* transformed matrix after the ordering: P A P^T,
+                               the matrix the Krylov iteration multiplies (in
+                               RCM order when SS_ORDER_COLOUR factors run on
+                               the device-wide path)                          */
 #define SS_MAT_LU        3  /* ILU factors in one CSR: strict lower part of the
                                unit-lower L, then U with its diagonal          */
 #define SS_MAT_SYM       4  /* symmetrised pattern of A used by RCM (data = 1)  */
@@ -293,7 +300,11 @@ int ss_prepare(ss_liouv L, int32_t method, const ss_options *opt);
 int ss_export_csr(ss_liouv L, int32_t which, int64_t *nnz, int64_t *indptr,
                   int32_t *indices, double *data);
 
-/* Copy the ordering perm[new] = old (n entries) to a host array. */
+/* Copy the ordering of the ILU factors, perm[new] = old (n entries), to a
+ * host array.  With SS_ORDER_COLOUR on the device-wide path this is the
+ * colour-class order while SS_MAT_A_PERM, the Krylov vectors and the vectors
+ * of the SS_OP_* operators stay in RCM order: the preconditioner operators
+ * apply (LU)^-1 through that permutation. */
 int ss_export_perm(ss_liouv L, int32_t *perm);
 
 #define SS_OP_SPMV_L      0  /* y = L x          (natural order, fp64)         */

@@ -268,11 +268,27 @@ int ss_export_csr(ss_liouv L, int32_t which, int64_t *nnz, int64_t *indptr, int3
     });
 }
 
+// out[q] = a[b[q]]
+__global__ void k_compose(int n, const int *a, const int *b, int *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = a[b[q]];
+}
+
 int ss_export_perm(ss_liouv L, int32_t *perm) {
     return guarded([&]() -> int {
         SS_REQUIRE(L != nullptr && perm != nullptr, SS_E_INVALID_ARG, "null argument");
         SS_REQUIRE(L->prepared, SS_E_STATE, "ss_prepare not called");
-        ss::d2h(perm, L->perm.get(), (size_t)L->n, ss::stream_of(L));
+        hipStream_t s = ss::stream_of(L);
+        const int n = L->n;
+        if (L->split && n > 0) {
+            // the factors' order: RCM position cp[q] of factor row q
+            ss::DevBuf<int> fp((size_t)n);
+            k_compose<<<ss::div_up(n, 256), 256, 0, s>>>(n, L->perm.get(), L->cp.get(), fp.get());
+            SS_HIP(hipGetLastError());
+            ss::d2h(perm, fp.get(), (size_t)n, s);
+        } else {
+            ss::d2h(perm, L->perm.get(), (size_t)n, s);
+        }
         return SS_OK;
     });
 }
@@ -328,6 +344,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<double2> M;
                 M.setup(&L->LU, L->lu_diag.get(), n, s);
+                if (L->split) M.pin = L->cp.get();
                 if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op), L->colours ? L->lorder.get() : nullptr);
                 if (pre) M.apply(xd.get(), yd.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xd.get(), yd.get(), s);
@@ -343,6 +360,7 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y) {
             } else {
                 ss::Precond<float2> M;
                 M.setup(&L->LU32, L->lu_diag.get(), n, s);
+                if (L->split) M.pin = L->cp.get();
                 if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op), L->colours ? L->lorder.get() : nullptr);
                 if (pre) M.apply(xf.get(), yf.get(), s);
                 else if (op == SS_OP_LSOLVE) M.lower(xf.get(), yf.get(), s);
@@ -391,6 +409,7 @@ int ss_time_operator(ss_liouv L, int32_t op, int32_t prec, int32_t reps, double 
             }
             ss::Precond<T> M;
             if (pre) M.setup(LU, L->lu_diag.get(), n, s);
+            if (pre && L->split) M.pin = L->cp.get();
             if (pre && op != SS_OP_PRECOND_SYNCFREE) M.use_levels(L->LU.view(), s, precond_mode(op), L->colours ? L->lorder.get() : nullptr);
             const ss::Csr<T> Av = A->view();
             const int g = ss::spmv_group(Av.n, Av.nnz);

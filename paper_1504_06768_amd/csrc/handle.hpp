@@ -35,6 +35,11 @@ struct ss_liouv_s {
     int diag_added = 0;        // explicit zero diagonals added to Ap
     int colours = 0;           // colour classes of SS_ORDER_COLOUR (else 0)
     ss::DevBuf<int> lorder;    // SS_ORDER_COLOUR: row of each RCM position (rows' order inside a level)
+    // SS_ORDER_COLOUR on the device-wide path: the Krylov iteration runs in
+    // RCM order (perm, Ap) and the factors in the colour-class order; cp[q]
+    // is the RCM position of factor row q (lorder is its inverse)
+    bool split = false;
+    ss::DevBuf<int> cp;
     double t_setup_ms = 0;
     // level schedules of the factors and the gates of the row-group
     // triangular solves, built by ss_prepare for the device-wide path and

@@ -870,9 +870,38 @@ void Precond<T>::borrow_classes(const LevelSched *lo_, const LevelSched *up_) {
     mode = PRE_CLASSES;
 }
 
+// y[q] = x[idx[q]] (gather) or y[idx[q]] = x[q] (scatter); nothing when *skip
+template <typename T, bool SCATTER>
+__global__ void k_permute_vec(int n, const int *idx, const T *x, T *y, const int *skip) {
+    if (skip && *skip) return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    if (SCATTER) y[idx[q]] = x[q];
+    else y[q] = x[idx[q]];
+}
+
 template <typename T>
 void Precond<T>::apply(const T *b, T *out, hipStream_t s, const int *skip) {
     if (n == 0) return;
+    if (pin) {
+        pz.resize((size_t)n);
+        if (mode == PRE_CLASSES) {
+            // the permutation folded into the first and the last substitution
+            const LevelSched &L0 = blo ? *blo : lo, &U0 = bup ? *bup : up;
+            trsv_classes<T>(L0, false, LU->view(), b, y.get(), skip, s, pin, nullptr);
+            trsv_classes<T>(U0, true, LU->view(), y.get(), pz.get(), skip, s, pin, out);
+            return;
+        }
+        pb.resize((size_t)n);
+        k_permute_vec<T, false><<<div_up(n, 256), 256, 0, s>>>(n, pin, b, pb.get(), skip);
+        const int *keep = pin;
+        pin = nullptr;
+        apply(pb.get(), pz.get(), s, skip);
+        pin = keep;
+        k_permute_vec<T, true><<<div_up(n, 256), 256, 0, s>>>(n, pin, pz.get(), out, skip);
+        SS_HIP(hipGetLastError());
+        return;
+    }
     if (mode == PRE_CLASSES) {
         // y takes the lower result (the sentinel is not kept in this mode)
         const LevelSched &L0 = blo ? *blo : lo, &U0 = bup ? *bup : up;
@@ -925,6 +954,18 @@ template <typename T>
 void Precond<T>::lower(const T *b, T *out, hipStream_t s) {
     // out = L^-1 b: run the lower solve into y, then copy (out must not alias y)
     if (n == 0) return;
+    if (pin) {
+        pb.resize((size_t)n);
+        pz.resize((size_t)n);
+        k_permute_vec<T, false><<<div_up(n, 256), 256, 0, s>>>(n, pin, b, pb.get(), nullptr);
+        const int *keep = pin;
+        pin = nullptr;
+        lower(pb.get(), pz.get(), s);
+        pin = keep;
+        k_permute_vec<T, true><<<div_up(n, 256), 256, 0, s>>>(n, pin, pz.get(), out, nullptr);
+        SS_HIP(hipGetLastError());
+        return;
+    }
     const unsigned grid = (unsigned)div_up(n, TRSV_BS);
     k_trsv_lower<T><<<grid, TRSV_BS, 0, s>>>(n, LU->rowptr.get(), LU->col.get(), LU->val.get(), diag, b, y.get(),
                                               nullptr, counter.ctr.get(), counter.take(grid), status.get(),
@@ -937,6 +978,18 @@ void Precond<T>::lower(const T *b, T *out, hipStream_t s) {
 template <typename T>
 void Precond<T>::upper(const T *b, T *out, hipStream_t s) {
     if (n == 0) return;
+    if (pin) {
+        pb.resize((size_t)n);
+        pz.resize((size_t)n);
+        k_permute_vec<T, false><<<div_up(n, 256), 256, 0, s>>>(n, pin, b, pb.get(), nullptr);
+        const int *keep = pin;
+        pin = nullptr;
+        upper(pb.get(), pz.get(), s);
+        pin = keep;
+        k_permute_vec<T, true><<<div_up(n, 256), 256, 0, s>>>(n, pin, pz.get(), out, nullptr);
+        SS_HIP(hipGetLastError());
+        return;
+    }
     SS_HIP(hipMemcpyAsync(y.get(), b, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
     fill_sentinel<T>(n, out, s);
     const unsigned grid = (unsigned)div_up(n, TRSV_BS);

@@ -72,10 +72,13 @@ constexpr int PRE_CLASSES_MAX_LEVELS = 64;
 
 // One triangular solve over the level schedule `ls` with one launch per level
 // (trsv_classes.hip): lower out = L^-1 in, upper out = U^-1 in.  No sentinels
-// are used or restored; nothing runs when *skip != 0 on the device.
+// are used or restored; nothing runs when *skip != 0 on the device.  With
+// pin (a permutation: factor row q is position pin[q] of the caller's
+// vectors) the lower solve reads in[pin[q]] and the upper one also writes
+// outp[pin[q]].
 template <typename T>
 void trsv_classes(const LevelSched &ls, bool upper, const Csr<T> &LU, const T *in, T *out, const int *skip,
-                  hipStream_t s);
+                  hipStream_t s, const int *pin = nullptr, T *outp = nullptr);
 
 // Sync-free triangular solves over all CUs with 16 lanes per row, in level
 // order, polling gated two levels behind the frontier (trsv_groups.hip).
@@ -99,6 +102,11 @@ struct Precond {
     const int *diag = nullptr;
     int n = 0;
     DevBuf<T> y;           // lower-solve result, kept at the sentinel between applies
+    // pin (optional): factor row q is position pin[q] of the vectors apply()
+    // takes and returns (the colour-class factors of a solve run in RCM
+    // order); pb/pz hold the permuted vectors
+    const int *pin = nullptr;
+    DevBuf<T> pb, pz;
     DevBuf<unsigned> status;
     BlockCounter counter;
     // level-scheduled modes (apply() uses them once built)

@@ -53,15 +53,38 @@ __global__ void k_zero_words(unsigned *p, int n) {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// y[q] = x[idx[q]] (gather) or y[idx[q]] = x[q] (scatter)
+template <typename T, bool SCATTER>
+__global__ void k_permute_vec(int n, const int *idx, const T *x, T *y) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    if (SCATTER) y[idx[q]] = x[q];
+    else y[q] = x[idx[q]];
+}
+
 // y = (L U)^-1 x with the row-group solves over the handle's schedules;
-// x, y in precision T, ysol: n of scratch
+// x, y in precision T, ysol: n of scratch; for factors in the colour-class
+// order under an RCM-ordered solve (h->split), xs and ys (n each) hold x and
+// the result in the factors' order
 template <typename T>
-void precond(ss_liouv h, const ss::CsrBuf<T> &LU, const T *x, T *y, T *ysol, unsigned *status, unsigned *ctl,
-             hipStream_t s) {
+void precond(ss_liouv h, const ss::CsrBuf<T> &LU, const T *x, T *y, T *ysol, T *xs, T *ys, unsigned *status,
+             unsigned *ctl, hipStream_t s) {
     const int n = h->n;
+    const T *in = x;
+    T *out = y;
+    if (h->split) {
+        k_permute_vec<T, false><<<ss::div_up(n, 256), 256, 0, s>>>(n, h->cp.get(), x, xs);
+        SS_HIP(hipGetLastError());
+        in = xs;
+        out = ys;
+    }
     ss::fill_sentinel<T>(n, ysol, s);
-    ss::trsv_groups<T>(h->sched_lo, h->gate_lo.get(), false, LU.view(), x, ysol, y, ctl, status, nullptr, s);
-    ss::trsv_groups<T>(h->sched_up, h->gate_up.get(), true, LU.view(), ysol, y, nullptr, ctl, status, nullptr, s);
+    ss::trsv_groups<T>(h->sched_lo, h->gate_lo.get(), false, LU.view(), in, ysol, out, ctl, status, nullptr, s);
+    ss::trsv_groups<T>(h->sched_up, h->gate_up.get(), true, LU.view(), ysol, out, nullptr, ctl, status, nullptr, s);
+    if (h->split) {
+        k_permute_vec<T, true><<<ss::div_up(n, 256), 256, 0, s>>>(n, h->cp.get(), ys, y);
+        SS_HIP(hipGetLastError());
+    }
 }
 
 int run(ss_liouv L, int op, int prec, const double *x, double *y) {
@@ -83,7 +106,8 @@ int run(ss_liouv L, int op, int prec, const double *x, double *y) {
     const size_t nn = (size_t)n;
     // scratch needed: control block, then the operator's vectors
     size_t need = CONTROL_BYTES;
-    if (op == SS_OP_PRECOND) need += align256(nn * (prec == SS_MIXED ? sizeof(float2) : sizeof(double2)));
+    const size_t es = prec == SS_MIXED ? sizeof(float2) : sizeof(double2);
+    if (op == SS_OP_PRECOND) need += (L->split ? 3 : 1) * align256(nn * es);
     if (prec == SS_MIXED) need += 2 * align256(nn * sizeof(float2));
     SS_REQUIRE(need <= NOALLOC_SCRATCH_BYTES, SS_E_INVALID_ARG,
                "ss_apply_noalloc: system too large for the " + std::to_string(NOALLOC_SCRATCH_BYTES >> 20) +
@@ -107,11 +131,16 @@ int run(ss_liouv L, int op, int prec, const double *x, double *y) {
             const ss::Csr<double2> A = L->Ap.view();
             ss::spmv<double2>(A, xd, yd, ss::spmv_group(A.n, A.nnz), s);
         } else {
-            precond<double2>(L, L->LU, xd, yd, reinterpret_cast<double2 *>(vec), status, ctl, s);
+            double2 *v0 = reinterpret_cast<double2 *>(vec);
+            double2 *v1 = reinterpret_cast<double2 *>(vec + align256(nn * sizeof(double2)));
+            double2 *v2 = reinterpret_cast<double2 *>(vec + 2 * align256(nn * sizeof(double2)));
+            precond<double2>(L, L->LU, xd, yd, v0, v1, v2, status, ctl, s);
         }
     } else {
         float2 *ysol = reinterpret_cast<float2 *>(vec);
-        if (op == SS_OP_PRECOND) vec += align256(nn * sizeof(float2));
+        float2 *xs = reinterpret_cast<float2 *>(vec + align256(nn * sizeof(float2)));
+        float2 *ys = reinterpret_cast<float2 *>(vec + 2 * align256(nn * sizeof(float2)));
+        if (op == SS_OP_PRECOND) vec += (L->split ? 3 : 1) * align256(nn * sizeof(float2));
         float2 *xf = reinterpret_cast<float2 *>(vec);
         float2 *yf = reinterpret_cast<float2 *>(vec + align256(nn * sizeof(float2)));
         ss::convert<float2, double2>(n, xd, xf, nullptr, s);
@@ -119,7 +148,7 @@ int run(ss_liouv L, int op, int prec, const double *x, double *y) {
             const ss::Csr<float2> A = L->Ap32.view();
             ss::spmv<float2>(A, xf, yf, ss::spmv_group(A.n, A.nnz), s);
         } else {
-            precond<float2>(L, L->LU32, xf, yf, ysol, status, ctl, s);
+            precond<float2>(L, L->LU32, xf, yf, ysol, xs, ys, status, ctl, s);
         }
         ss::convert<double2, float2>(n, yf, yd, nullptr, s);
     }

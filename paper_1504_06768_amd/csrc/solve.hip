@@ -137,20 +137,39 @@ __global__ void k_rows_by_rcm(int n, const int *rcm_perm, const int *iperm, int 
     if (p < n) lorder[p] = iperm[rcm_perm[p]];
 }
 
+// cp[lorder[p]] = p
+__global__ void k_invert(int n, const int *lorder, int *cp) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) cp[lorder[p]] = p;
+}
+
 // RCM order -> colour-class order (SS_ORDER_COLOUR).  lorder keeps, for
 // each RCM position, the row it became: rows inside a level of the factors'
 // schedules are taken in RCM order, so that the rows running together
-// gather from nearby parts of every class.
-static void recolour(ss_liouv h, hipStream_t s) {
+// gather from nearby parts of every class.  With keep_rcm (the device-wide
+// path) perm and iperm stay the RCM order, which the Krylov iteration and
+// its SpMV keep, and cp maps the factors' rows to it; otherwise the whole
+// solve runs in the colour-class order.
+static void recolour(ss_liouv h, bool keep_rcm, hipStream_t s) {
     DevBuf<int> perm, iperm;
     h->colours = colour_order(h->S, h->perm, h->iperm, perm, iperm, s);
-    h->lorder.resize((size_t)std::max(h->n, 1));
-    if (h->n) {
-        k_rows_by_rcm<<<div_up(h->n, 256), 256, 0, s>>>(h->n, h->perm.get(), iperm.get(), h->lorder.get());
+    const int n = h->n;
+    h->lorder.resize((size_t)std::max(n, 1));
+    if (n) {
+        k_rows_by_rcm<<<div_up(n, 256), 256, 0, s>>>(n, h->perm.get(), iperm.get(), h->lorder.get());
         SS_HIP(hipGetLastError());
     }
-    h->perm = std::move(perm);
-    h->iperm = std::move(iperm);
+    h->split = keep_rcm;
+    if (keep_rcm) {
+        h->cp.resize((size_t)std::max(n, 1));
+        if (n) {
+            k_invert<<<div_up(n, 256), 256, 0, s>>>(n, h->lorder.get(), h->cp.get());
+            SS_HIP(hipGetLastError());
+        }
+    } else {
+        h->perm = std::move(perm);
+        h->iperm = std::move(iperm);
+    }
 }
 
 static void prepare_permute(ss_liouv h, hipStream_t s) {
@@ -164,7 +183,7 @@ static void prepare_permute(ss_liouv h, hipStream_t s) {
 static void prepare_finish(ss_liouv h, int method, const ss_options &o, hipStream_t s, double t0,
                            bool batched = false) {
     const int n = h->n, d = h->d;
-    if (o.ilu == SS_ILU0 && !batched) {
+    if (o.ilu == SS_ILU0 && !batched && !h->split) {
         h->lu_diag.resize((size_t)n);
         if (n) SS_HIP(hipMemcpyAsync(h->lu_diag.get(), h->diag.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
     }
@@ -203,31 +222,45 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     };
     prepare_transform(h, method, o, s);
     phase("transform");
+    // device-wide solves use level schedules of the factors
+    const bool want_sched = !use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31);
     if (o.ordering == SS_ORDER_NATURAL) identity_order(h->n, h->perm, h->iperm, s);
     else rcm_order(h->S, h->perm, h->iperm, s);
     h->colours = 0;
-    if (o.ordering == SS_ORDER_COLOUR) recolour(h, s);
+    h->split = false;
+    if (o.ordering == SS_ORDER_COLOUR) recolour(h, want_sched, s);
     phase("ordering");
     prepare_permute(h, s);
     phase("permute");
-    // device-wide solves use level schedules of the factors; zero fill keeps
-    // A's pattern, so for ILU(0) they are built first and drive the
-    // factorisation too when they are shallow
-    const bool want_sched = !use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31);
+    // the matrix to factorise: Ap, or its colour-class reordering (split)
+    CsrBuf<double2> Ac;
+    DevBuf<int> cdiag;
+    if (h->split) {
+        permute_matrix(h->Ap, h->cp.get(), h->lorder.get(), Ac, s);
+        cdiag.resize((size_t)std::max(h->n, 1));
+        const int missing = find_diagonal(h->n, Ac.rowptr.get(), Ac.col.get(), cdiag.get(), s);
+        SS_REQUIRE(missing == 0, SS_E_ZERO_PIVOT, "colour-class reordering lost a diagonal entry");
+    }
+    const CsrBuf<double2> &F = h->split ? Ac : h->Ap;
+    const int *fdiag = h->split ? cdiag.get() : h->diag.get();
+    // zero fill keeps the pattern, so for ILU(0) the schedules are built
+    // first and drive the factorisation too when they are shallow
     bool sched_built = false;
     if (o.ilu == SS_ILU0 && want_sched) {
-        build_levels(h->Ap.view(), h->diag.get(), h->sched_lo, h->sched_up, s, h->colours ? h->lorder.get() : nullptr);
+        build_levels(F.view(), fdiag, h->sched_lo, h->sched_up, s, h->colours ? h->lorder.get() : nullptr);
         sched_built = true;
         phase("levels");
     }
     if (o.ilu == SS_ILU0 && sched_built && h->sched_lo.nlev <= PRE_CLASSES_MAX_LEVELS) {
-        h->guarded = ilu0_factor_levels(h->Ap, h->diag.get(), h->sched_lo, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+        h->guarded = ilu0_factor_levels(F, fdiag, h->sched_lo, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
     } else if (o.ilu == SS_ILU0) {
-        h->guarded = ilu0_factor(h->Ap, h->diag.get(), PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+        h->guarded = ilu0_factor(F, fdiag, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
     } else {
         h->guarded =
-            ilut_factor(h->Ap, h->diag.get(), o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU, h->lu_diag, s)
-                .guarded;
+            ilut_factor(F, fdiag, o.drop_tol, o.fill, PIVOT_DETECT, PIVOT_BOOST, h->LU, h->lu_diag, s).guarded;
+    }
+    if (o.ilu == SS_ILU0 && h->split) {
+        h->lu_diag = std::move(cdiag);  // (prepare_finish leaves it)
     }
     phase("ilu");
     prepare_finish(h, method, o, s, t0);
@@ -429,6 +462,7 @@ static double condition_estimate(ss_liouv h, hipStream_t s) {
     SS_HIP(hipGetLastError());
     Precond<double2> M;
     M.setup(&h->LU, h->lu_diag.get(), n, s);
+    if (h->split) M.pin = h->cp.get();
     M.use_levels(h->LU.view(), s);
     M.apply(e.get(), y.get(), s);
     norm_inf<double2>(n, y.get(), part.get(), sc.get(), s);
@@ -591,6 +625,7 @@ static int run(ss_liouv h, int method, double tol, const ss_options &o, const Cs
     if (!done_wg) {
         Precond<T> M;
         M.setup(&LUin, h->lu_diag.get(), n, s);
+        if (h->split) M.pin = h->cp.get();
         if (!(o.flags & SS_FLAG_SYNCFREE)) {
             const int mode = (o.flags & SS_FLAG_TRSV_BLOCK)     ? PRE_BLOCK
                              : (o.flags & SS_FLAG_TRSV_LEVELS)  ? PRE_LEVELS
@@ -830,7 +865,8 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
             if (!rcm) identity_order(h->n, h->perm, h->iperm, s);
             else rcm_order(h->S, h->perm, h->iperm, s);
         }
-        if (o.ordering == SS_ORDER_COLOUR) recolour(h, s);
+        h->split = false;
+        if (o.ordering == SS_ORDER_COLOUR) recolour(h, false, s);
         SS_HIP(hipStreamSynchronize(s));
     });
     {

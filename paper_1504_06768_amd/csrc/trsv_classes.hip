@@ -26,7 +26,8 @@ constexpr int CLS_BS = 256;  // threads per workgroup
 // thread's memory latencies overlap.
 template <typename T, bool UPPER, int G, int U>
 __global__ void __launch_bounds__(CLS_BS) k_trsv_level(int lo, int hi, const int4 *slot, const int *col,
-                                                       const T *val, const T *in, T *out, const int *skip) {
+                                                       const T *val, const T *in, T *out, const int *pin, T *outp,
+                                                       const int *skip) {
     if (skip && *skip) return;
     // workgroups go round-robin to the eight XCDs (b -> b % 8); renumbered
     // so that each XCD takes a contiguous eighth of the level, whose rows
@@ -41,7 +42,7 @@ __global__ void __launch_bounds__(CLS_BS) k_trsv_level(int lo, int hi, const int
     if (active) {
         sl = slot[idx];
         if (l == 0) {
-            b = in[sl.x];
+            b = in[(!UPPER && pin) ? pin[sl.x] : sl.x];
             if (UPPER) piv = val[sl.y - 1];
         }
         for (int e0 = sl.y; e0 < sl.z; e0 += G * U) {
@@ -72,16 +73,19 @@ __global__ void __launch_bounds__(CLS_BS) k_trsv_level(int lo, int hi, const int
         T r = csub(b, acc);
         if (UPPER) r = cdiv(r, piv);
         out[sl.x] = r;
+        if (UPPER && pin) outp[pin[sl.x]] = r;
     }
 }
 
 template <typename T, bool UPPER, int G, int U>
-void levels_launch(const LevelSched &ls, const Csr<T> &LU, const T *in, T *out, const int *skip, hipStream_t s) {
+void levels_launch(const LevelSched &ls, const Csr<T> &LU, const T *in, T *out, const int *pin, T *outp,
+                   const int *skip, hipStream_t s) {
     for (int l = 0; l < ls.nlev; ++l) {
         const int lo = ls.hptr[(size_t)l], hi = ls.hptr[(size_t)l + 1];
         if (hi <= lo) continue;
         const unsigned grid = (unsigned)((div_up((int64_t)(hi - lo) * G, CLS_BS) + 7) / 8 * 8);  // a multiple of 8
-        k_trsv_level<T, UPPER, G, U><<<grid, CLS_BS, 0, s>>>(lo, hi, ls.slot.get(), LU.col, LU.val, in, out, skip);
+        k_trsv_level<T, UPPER, G, U><<<grid, CLS_BS, 0, s>>>(lo, hi, ls.slot.get(), LU.col, LU.val, in, out, pin,
+                                                             outp, skip);
     }
 }
 
@@ -89,26 +93,26 @@ void levels_launch(const LevelSched &ls, const Csr<T> &LU, const T *in, T *out, 
 
 template <typename T>
 void trsv_classes(const LevelSched &ls, bool upper, const Csr<T> &LU, const T *in, T *out, const int *skip,
-                  hipStream_t s) {
+                  hipStream_t s, const int *pin, T *outp) {
     SS_REQUIRE((int)ls.hptr.size() == ls.nlev + 1, SS_E_STATE, "level schedule without its host copy");
     if (LU.n == 0) return;
     // mean entries per row of one triangle (the other's are about as many)
     const double mean = std::max(0.0, (double)(LU.nnz - LU.n) / (2.0 * LU.n));
     if (mean <= 12) {
-        if (upper) levels_launch<T, true, 4, 3>(ls, LU, in, out, skip, s);
-        else levels_launch<T, false, 4, 3>(ls, LU, in, out, skip, s);
+        if (upper) levels_launch<T, true, 4, 3>(ls, LU, in, out, pin, outp, skip, s);
+        else levels_launch<T, false, 4, 3>(ls, LU, in, out, pin, outp, skip, s);
     } else if (mean <= 32) {
-        if (upper) levels_launch<T, true, 8, 4>(ls, LU, in, out, skip, s);
-        else levels_launch<T, false, 8, 4>(ls, LU, in, out, skip, s);
+        if (upper) levels_launch<T, true, 8, 4>(ls, LU, in, out, pin, outp, skip, s);
+        else levels_launch<T, false, 8, 4>(ls, LU, in, out, pin, outp, skip, s);
     } else {
-        if (upper) levels_launch<T, true, 32, 2>(ls, LU, in, out, skip, s);
-        else levels_launch<T, false, 32, 2>(ls, LU, in, out, skip, s);
+        if (upper) levels_launch<T, true, 32, 2>(ls, LU, in, out, pin, outp, skip, s);
+        else levels_launch<T, false, 32, 2>(ls, LU, in, out, pin, outp, skip, s);
     }
     SS_HIP(hipGetLastError());
 }
 template void trsv_classes<double2>(const LevelSched &, bool, const Csr<double2> &, const double2 *, double2 *,
-                                    const int *, hipStream_t);
+                                    const int *, hipStream_t, const int *, double2 *);
 template void trsv_classes<float2>(const LevelSched &, bool, const Csr<float2> &, const float2 *, float2 *,
-                                   const int *, hipStream_t);
+                                   const int *, hipStream_t, const int *, float2 *);
 
 }  // namespace ss

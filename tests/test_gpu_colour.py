@@ -152,43 +152,70 @@ def test_colour_in_a_batch(prec, tol):
         assert np.max(np.abs(rho - steady_state_dense(s.H, s.c_ops))) <= tol
 
 
+def _factor_positions(Ao):
+    """cp[q]: the RCM position of row q of the colour-class factors."""
+    base = oord.rcm(Ao)
+    pos = np.empty(Ao.shape[0], dtype=np.int64)
+    pos[base] = np.arange(Ao.shape[0])
+    return pos[oord.colour_order(Ao)]
+
+
 def test_colour_precond_matches_triangular_solves():
-    """(LU)^-1 x by every device-wide triangular solve on the colour-ordered
+    """On the device-wide path the Krylov iteration stays in RCM order and
+    the factors take the colour-class order: (LU)^-1 through the
+    permutation, by every device-wide triangular solve, on the
     Jaynes-Cummings workload, against scipy's triangular solves of the
     exported factors; the sync-free variants agree bit for bit."""
     from scipy.sparse.linalg import spsolve_triangular
     s = qs.config(2)
+    Ao = _transformed(s, "trace_gmres")
+    cp = _factor_positions(Ao)
     L = ssl.build_liouvillian(s.H, s.c_ops)
     ssl.prepare(L, "trace_gmres", ordering="colour")
+    # the Krylov matrix is P A P^T in RCM order, the factors' order is the colour order
+    assert _max_rel(ssl.export_csr(L, ssl.SS_MAT_A_PERM), oord.permute(Ao, oord.rcm(Ao))) <= 1e-14
+    assert np.array_equal(ssl.export_perm(L), oord.colour_order(Ao))
     Lf, Uf = oilu.split(ssl.export_csr(L, ssl.SS_MAT_LU))
     x = np.random.default_rng(7).normal(size=Lf.shape[0]) + 0j
-    ref = spsolve_triangular(Uf, spsolve_triangular(Lf, x, lower=True, unit_diagonal=True), lower=False)
+    ref = np.empty_like(x)
+    ref[cp] = spsolve_triangular(Uf, spsolve_triangular(Lf, x[cp], lower=True, unit_diagonal=True), lower=False)
     outs = {}
     for op in (ssl.SS_OP_PRECOND_SYNCFREE, ssl.SS_OP_PRECOND_LEVELS, ssl.SS_OP_PRECOND_GROUPS,
-               ssl.SS_OP_PRECOND_BLOCK, ssl.SS_OP_PRECOND_CLASSES):
+               ssl.SS_OP_PRECOND_BLOCK, ssl.SS_OP_PRECOND_CLASSES, ssl.SS_OP_PRECOND):
         outs[op] = ssl.apply(L, op, x)
         assert np.max(np.abs(outs[op] - ref)) <= 1e-11 * np.max(np.abs(ref)), op
     for op in (ssl.SS_OP_PRECOND_LEVELS, ssl.SS_OP_PRECOND_GROUPS):
         assert np.array_equal(outs[op], outs[ssl.SS_OP_PRECOND_SYNCFREE]), op
+    # the unit-lower and the upper solve alone, through the permutation
+    yl = ssl.apply(L, ssl.SS_OP_LSOLVE, x)
+    want = np.empty_like(x)
+    want[cp] = spsolve_triangular(Lf, x[cp], lower=True, unit_diagonal=True)
+    assert np.max(np.abs(yl - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+def _max_rel(a, b):
+    a, b = sp.csr_matrix(a), sp.csr_matrix(b)
+    return abs(a - b).max() / max(abs(b).max(), 1e-300)
 
 
 @pytest.mark.parametrize("name", ["jc8", "kerr20", "opto3x5"])
 def test_level_ilu0_equals_sync_free_ilu0(name):
     """The ILU(0) run one launch per level (device-wide path, shallow
-    schedule) gives the same factors, bit for bit, as the sync-free
-    factorisation (the workgroup path's set-up) on the same colour-ordered
-    matrix, and both match the oracle's ILU(0)."""
+    schedule, factors of the colour-class reordering of the RCM-ordered
+    matrix) gives the same factors, bit for bit, as the sync-free
+    factorisation of the colour-ordered matrix (the workgroup path's
+    set-up), and both match the oracle's ILU(0)."""
     s = SMALL[name]()
     La = ssl.build_liouvillian(s.H, s.c_ops)
     ssl.prepare(La, "trace_gmres", ordering="colour", path="device")
     Lb = ssl.build_liouvillian(s.H, s.c_ops)
     ssl.prepare(Lb, "trace_bicgstab", ordering="colour", path="workgroup")
-    Aa, Ab = ssl.export_csr(La, ssl.SS_MAT_A_PERM), ssl.export_csr(Lb, ssl.SS_MAT_A_PERM)
-    assert (Aa != Ab).nnz == 0
+    assert np.array_equal(ssl.export_perm(La), ssl.export_perm(Lb))
+    Ab = ssl.export_csr(Lb, ssl.SS_MAT_A_PERM)
     LUa, LUb = ssl.export_csr(La, ssl.SS_MAT_LU), ssl.export_csr(Lb, ssl.SS_MAT_LU)
     assert np.array_equal(LUa.indptr, LUb.indptr) and np.array_equal(LUa.indices, LUb.indices)
     assert np.array_equal(LUa.data, LUb.data)
-    LUo, _ = oilu.ilu0(Aa, guard=1e-8, boost=0.1)
+    LUo, _ = oilu.ilu0(Ab, guard=1e-8, boost=0.1)
     rel = np.abs(LUa.data - LUo.data) / np.maximum(np.abs(LUo.data), 1e-300)
     big = np.abs(LUo.data) > 1e-10 * np.abs(LUo.data).max()
     assert np.max(rel[big]) <= 1e-11
