@@ -290,9 +290,9 @@ def dominant_kernel(ssl, ch, Hd, Cd, res):
     share = (applies * t_pre) / max(res["fp64"]["median_ms"], 1e-9)
     roof = {"bound": "hbm", "achieved": gbs(bp, t_pre), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": gbs(bp, t_pre) / PEAK_HBM_GBS, "traffic": None,
-            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128, colour-class "
-                      "order): k_trsv_level, one launch per level of each factor (about 14 each); the unit is one "
-                      "application",
+            "kernel": "preconditioner application (ILU(0) lower + upper triangular solve, complex128, factors in "
+                      "colour-class order, input and output in RCM order through the permutation): k_trsv_level, "
+                      "one launch per level of each factor (about 14 each); the unit is one application",
             "bytes_per_launch": bp, "avg_launch_ms": t_pre, "unit_of_launch": "one application (all levels)",
             "applications_per_fp64_solve": applies,
             "share_of_fp64_step": share}
