@@ -26,7 +26,9 @@
 //    graph of a random order is shallow (62 levels on the Kerr chain at
 //    n = 10^6, against ~4000 for the RCM order).  Colours past 63 (dense
 //    rows only) are found by the wavefront together through a bitmap in
-//    LDS; up to 4096 colours are supported.
+//    LDS; up to 4096 colours are supported.  The frontier launches have a
+//    fixed grid and read their frontier's size on the device, so the host
+//    queues them in batches and reads one count per batch.
 //  * bucket_sort puts the vertices in (colour, RCM position) order.
 #include "bucket.hpp"
 #include "rcm.hpp"
@@ -39,6 +41,8 @@ namespace {
 
 constexpr int COL_MAX = 4096;    // colours the ordering supports
 constexpr int COL_BS = 256;
+constexpr int FRONT_GRID = 1024;  // workgroups of a frontier launch (grid-stride over the frontier)
+constexpr int FRONT_BATCH = 16;   // frontier launches queued per host read
 
 __device__ inline int ld_colour(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -56,19 +60,29 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// appends the lanes with `take` set to list[*count ...] (one atomic per wavefront)
-__device__ inline void append(bool take, int v, int *list, int *count) {
+// appends the lanes with `take` set to list[*count ...] (one atomic per
+// wavefront); an append past cap entries is dropped and flagged
+__device__ inline void append(bool take, int v, int *list, int *count, int cap, unsigned *status) {
     const int lane = threadIdx.x & 63;
     const unsigned long long b = __ballot(take);
     int at = 0;
     if (lane == 0 && b) at = atomicAdd(count, __popcll(b));
     at = __shfl(at, 0, 64) + __popcll(b & ((1ull << lane) - 1ull));
-    if (take) list[at] = v;
+    if (take) {
+        if (at < cap) list[at] = v;
+        else atomicOr(status, STATUS_OVERFLOW);
+    }
+}
+
+// largest value over the wavefront
+__device__ inline int wave_max(int x) {
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
 }
 
 // cnt[v] = neighbours visited before v; vertices with none start the frontier
 __global__ void __launch_bounds__(COL_BS) k_colour_init(int n, const int *rowptr, const int *col, int *colour,
-                                                        int *cnt, int *front, int *nfront) {
+                                                        int *cnt, int *front, int *nfront, unsigned *status) {
     const int v = blockIdx.x * COL_BS + threadIdx.x;
     int c = 0;
     if (v < n) {
@@ -80,87 +94,102 @@ __global__ void __launch_bounds__(COL_BS) k_colour_init(int n, const int *rowptr
         cnt[v] = c;
         colour[v] = -1;
     }
-    append(v < n && c == 0, v, front, nfront);
+    append(v < n && c == 0, v, front, nfront, n, status);
 }
 
-// One frontier: every listed vertex has all its earlier neighbours coloured
-// (in earlier launches).  It takes the lowest colour none of them carries,
-// then counts itself off at each later neighbour; a neighbour whose count
-// reaches zero joins the next frontier.  Colours from 64 on (dense rows
-// only) are found by the wavefront together through a bitmap in LDS.
-__global__ void __launch_bounds__(COL_BS) k_colour_front(int m, const int *front, const int *rowptr, const int *col,
-                                                         int *colour, int *cnt, int *next, int *nnext, int *ncol,
+// Frontier k of the walk: every listed vertex has all its earlier
+// neighbours coloured (in earlier launches).  It takes the lowest colour none
+// of them carries, then counts itself off at each later neighbour; a
+// neighbour whose count reaches zero joins the next frontier.  Colours from
+// 64 on (dense rows only) are found by the wavefront together through a
+// bitmap in LDS.  The frontier sizes rotate through three counters: launch
+// k reads counter k mod 3, appends to counter k+1 mod 3 and clears counter
+// k+2 mod 3 (read by no launch before k+2 appends to it); the lists
+// alternate between two buffers.  A launch whose frontier is empty does
+// nothing, so the host may queue more launches than there are frontiers.
+__global__ void __launch_bounds__(COL_BS) k_colour_front(int k, int n, int *list_a, int *list_b, const int *rowptr,
+                                                         const int *col, int *colour, int *cnt, int *ctr,
                                                          unsigned *status) {
     __shared__ unsigned long long bm[COL_BS / 64][COL_MAX / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int t = blockIdx.x * COL_BS + threadIdx.x;
-    const bool active = t < m;
-    int v = 0, e0 = 0, e1 = 0;
-    uint64_t kv = 0;
-    unsigned long long taken = 0;
-    if (active) {
-        v = front[t];
-        kv = priority(v);
-        e0 = rowptr[v];
-        e1 = rowptr[v + 1];
-        for (int e = e0; e < e1; ++e) {
-            const int u = col[e];
-            if (u == v || !visits_before(u, priority(u), v, kv)) continue;
-            const int c = colour[u];
-            if (c < 64) taken |= 1ull << c;
-        }
+    const int m = ctr[k % 3];
+    const int *front = (k & 1) ? list_b : list_a;
+    int *next = (k & 1) ? list_a : list_b;
+    int *nnext = ctr + (k + 1) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctr[(k + 2) % 3] = 0;
+        ctr[3] += m;  // vertices listed so far (one writer per launch, launches in stream order)
     }
-    int mine = -1;
-    if (active && ~taken) mine = __builtin_ctzll(~taken);
-    // colours 0..63 all taken: the wavefront scans each such row into a
-    // bitmap of COL_MAX colours
-    unsigned long long slow = __ballot(active && !~taken);
-    while (slow) {
-        const int L = __ffsll((long long)slow) - 1;
-        slow &= slow - 1;
-        const int vv = __shfl(v, L, 64);
-        const uint64_t kk = priority(vv);
-        const int a = rowptr[vv], b = rowptr[vv + 1];
-        bm[wave][lane] = 0;
-        wave_sync();
-        bool over = false;
-        for (int f = a + lane; f < b; f += 64) {
-            const int u = col[f];
-            if (u == vv || !visits_before(u, priority(u), vv, kk)) continue;
-            const int cc = colour[u];
-            if (cc >= 0 && cc < COL_MAX) atomicOr(&bm[wave][cc >> 6], 1ull << (cc & 63));
-            else over = true;
-        }
-        wave_sync();
-        const unsigned long long w = bm[wave][lane];
-        const unsigned long long open = __ballot(~w != 0);
-        const bool overflow = __any(over) || open == 0;
-        if (lane == L) {
-            if (overflow) {
-                atomicOr(status, STATUS_OVERFLOW);  // more colours than supported: the host rejects
-                mine = COL_MAX;
-            } else {
-                const int word = __ffsll((long long)open) - 1;
-                mine = word * 64 + __builtin_ctzll(~bm[wave][word]);
+    for (int base = blockIdx.x * COL_BS; base < m; base += gridDim.x * COL_BS) {
+        const int t = base + threadIdx.x;
+        const bool active = t < m;
+        int v = 0, e0 = 0, e1 = 0;
+        uint64_t kv = 0;
+        unsigned long long taken = 0;
+        if (active) {
+            v = front[t];
+            kv = priority(v);
+            e0 = rowptr[v];
+            e1 = rowptr[v + 1];
+            for (int e = e0; e < e1; ++e) {
+                const int u = col[e];
+                if (u == v || !visits_before(u, priority(u), v, kv)) continue;
+                const int c = colour[u];
+                if (c < 64) taken |= 1ull << c;
             }
         }
-        wave_sync();
-    }
-    if (active) {
-        colour[v] = mine;
-        atomicMax(ncol, mine + 1);
-    }
-    // count off at the later neighbours, one row entry per lane and step
-    for (int k = 0;; ++k) {
-        const bool more = active && e0 + k < e1;
-        if (!__any(more)) break;
-        bool ready = false;
-        int w = 0;
-        if (more) {
-            w = col[e0 + k];
-            if (w != v && visits_before(v, kv, w, priority(w))) ready = atomicSub(cnt + w, 1) == 1;
+        int mine = -1;
+        if (active && ~taken) mine = __builtin_ctzll(~taken);
+        // colours 0..63 all taken: the wavefront scans each such row into a
+        // bitmap of COL_MAX colours
+        unsigned long long slow = __ballot(active && !~taken);
+        while (slow) {
+            const int L = __ffsll((long long)slow) - 1;
+            slow &= slow - 1;
+            const int vv = __shfl(v, L, 64);
+            const uint64_t kk = priority(vv);
+            const int a = rowptr[vv], b = rowptr[vv + 1];
+            bm[wave][lane] = 0;
+            wave_sync();
+            bool over = false;
+            for (int f = a + lane; f < b; f += 64) {
+                const int u = col[f];
+                if (u == vv || !visits_before(u, priority(u), vv, kk)) continue;
+                const int cc = colour[u];
+                if (cc >= 0 && cc < COL_MAX) atomicOr(&bm[wave][cc >> 6], 1ull << (cc & 63));
+                else over = true;
+            }
+            wave_sync();
+            const unsigned long long w = bm[wave][lane];
+            const unsigned long long open = __ballot(~w != 0);
+            const bool overflow = __any(over) || open == 0;
+            if (lane == L) {
+                if (overflow) {
+                    atomicOr(status, STATUS_OVERFLOW);  // more colours than supported: the host rejects
+                    mine = COL_MAX;
+                } else {
+                    const int word = __ffsll((long long)open) - 1;
+                    mine = word * 64 + __builtin_ctzll(~bm[wave][word]);
+                }
+            }
+            wave_sync();
         }
-        append(ready, w, next, nnext);
+        if (active) colour[v] = mine;
+        // one atomic per wavefront for the colour count
+        const int top = wave_max(mine);
+        if (lane == 0 && top >= 0) atomicMax(ctr + 4, top + 1);
+        // count off at the later neighbours, one row entry per lane and step
+        for (int e = 0;; ++e) {
+            const bool more = active && e0 + e < e1;
+            if (!__any(more)) break;
+            bool ready = false;
+            int w = 0;
+            if (more) {
+                w = col[e0 + e];
+                if (w != v && visits_before(v, kv, w, priority(w))) ready = atomicSub(cnt + w, 1) == 1;
+            }
+            append(ready, w, next, nnext, n, status);
+        }
     }
 }
 
@@ -172,46 +201,54 @@ __global__ void k_gather_int(int n, const int *idx, const int *in, int *out) {
 }  // namespace
 
 int colour_order(const CsrBuf<double2> &S, const DevBuf<int> &base_perm, const DevBuf<int> &base_iperm,
-                 DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s) {
+                 DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s, std::vector<int> *class_ptr) {
     (void)base_iperm;
     const int n = S.n;
     perm.resize((size_t)std::max(n, 1));
     iperm.resize((size_t)std::max(n, 1));
     if (n == 0) return 0;
-    DevBuf<int> colour((size_t)n), cnt((size_t)n), la((size_t)n), lb((size_t)n), ctr(3);
+    DevBuf<int> colour((size_t)n), cnt((size_t)n), la((size_t)n), lb((size_t)n), ctr(5);
     DevBuf<unsigned> status(1);
-    SS_HIP(hipMemsetAsync(ctr.get(), 0, 3 * sizeof(int), s));  // [0] frontier sizes, [1] next, [2] colours
+    // [0..2] frontier sizes (rotating), [3] vertices listed, [4] colours
+    SS_HIP(hipMemsetAsync(ctr.get(), 0, 5 * sizeof(int), s));
     SS_HIP(hipMemsetAsync(status.get(), 0, sizeof(unsigned), s));
     k_colour_init<<<div_up(n, COL_BS), COL_BS, 0, s>>>(n, S.rowptr.get(), S.col.get(), colour.get(), cnt.get(),
-                                                       la.get(), ctr.get());
+                                                       la.get(), ctr.get(), status.get());
     SS_HIP(hipGetLastError());
-    int m = 0, done = 0;
-    d2h(&m, ctr.get(), 1, s);
-    int *front = la.get(), *next = lb.get();
-    // each frontier is one level of the visit's dependency graph
-    while (m > 0) {
-        done += m;
-        SS_REQUIRE(done <= n, SS_E_HIP, "greedy colouring: a vertex was listed twice");
-        k_colour_front<<<div_up(m, COL_BS), COL_BS, 0, s>>>(m, front, S.rowptr.get(), S.col.get(), colour.get(),
-                                                           cnt.get(), next, ctr.get() + 1, ctr.get() + 2,
-                                                           status.get());
-        SS_HIP(hipGetLastError());
-        d2h(&m, ctr.get() + 1, 1, s);
-        SS_HIP(hipMemsetAsync(ctr.get() + 1, 0, sizeof(int), s));
-        std::swap(front, next);
+    // each frontier is one level of the visit's dependency graph; the
+    // launches are queued FRONT_BATCH at a time and the host reads the size
+    // of the next frontier after each batch
+    const int grid = std::min(div_up(n, COL_BS), FRONT_GRID);
+    int k = 0, m = 0;
+    for (;;) {
+        for (int b = 0; b < FRONT_BATCH; ++b, ++k) {
+            k_colour_front<<<grid, COL_BS, 0, s>>>(k, n, la.get(), lb.get(), S.rowptr.get(), S.col.get(),
+                                                   colour.get(), cnt.get(), ctr.get(), status.get());
+            SS_HIP(hipGetLastError());
+        }
+        d2h(&m, ctr.get() + k % 3, 1, s);
+        if (m == 0) break;
+        // every non-empty frontier colours at least one vertex
+        SS_REQUIRE(k <= n, SS_E_HIP, "greedy colouring: the frontier walk did not end");
     }
-    SS_REQUIRE(done == n, SS_E_HIP, "greedy colouring: vertices left uncoloured");
-    int C = 0;
+    int listed = 0, C = 0;
     unsigned st = 0;
-    d2h(&C, ctr.get() + 2, 1, s);
+    d2h(&listed, ctr.get() + 3, 1, s);
+    d2h(&C, ctr.get() + 4, 1, s);
     d2h(&st, status.get(), 1, s);
     SS_REQUIRE(!(st & STATUS_OVERFLOW), SS_E_INVALID_ARG, "colour order: more than 4096 colours");
+    SS_REQUIRE(listed == n, SS_E_HIP, "greedy colouring: vertices left uncoloured or listed twice");
     SS_REQUIRE(C >= 1 && C <= n, SS_E_HIP, "greedy colouring: colour count out of range");
     // colours by RCM position, then the classes in RCM order
     DevBuf<int> cpos((size_t)n);
     k_gather_int<<<div_up(n, 256), 256, 0, s>>>(n, base_perm.get(), colour.get(), cpos.get());
     SS_HIP(hipGetLastError());
-    bucket_sort(n, cpos.get(), C, base_perm.get(), perm.get(), iperm.get(), nullptr, s);
+    DevBuf<int> starts((size_t)C + 1);
+    bucket_sort(n, cpos.get(), C, base_perm.get(), perm.get(), iperm.get(), starts.get(), s);
+    if (class_ptr) {
+        class_ptr->resize((size_t)C + 1);
+        d2h(class_ptr->data(), starts.get(), (size_t)C + 1, s);
+    }
     return C;
 }
 

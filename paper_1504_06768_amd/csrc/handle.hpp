@@ -35,6 +35,7 @@ struct ss_liouv_s {
     int diag_added = 0;        // explicit zero diagonals added to Ap
     int colours = 0;           // colour classes of SS_ORDER_COLOUR (else 0)
     ss::DevBuf<int> lorder;    // SS_ORDER_COLOUR: row of each RCM position (rows' order inside a level)
+    std::vector<int> class_ptr;  // SS_ORDER_COLOUR: first row of each class in the factors' order, then n
     // SS_ORDER_COLOUR on the device-wide path: the Krylov iteration runs in
     // RCM order (perm, Ap) and the factors in the colour-class order; cp[q]
     // is the RCM position of factor row q (lorder is its inverse)

@@ -22,8 +22,12 @@ struct LevelSched {
 // level among the rows it depends on.
 // order (optional, n entries): the rows in the order they take inside a
 // level (default: increasing row index).
+// classes (optional, host, ascending, first 0 and last n): runs of rows with
+// no entry between two rows of one run (the colour-class order of a
+// zero-fill factor); each run's levels then take one launch with no waits,
+// and an entry inside a run is an error.
 void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s,
-                  const int *order = nullptr);
+                  const int *order = nullptr, const std::vector<int> *classes = nullptr);
 
 // The level analysis of many systems in one launch (one workgroup each):
 // job() sets up one system's scratch on its stream, levels_batch runs every

@@ -16,6 +16,8 @@
 // symmetric pattern (stored row entries, a diagonal entry counted twice); a
 // component starts at the unvisited node of lowest degree and highest index;
 // equal-degree neighbours are queued in increasing index.
+#include <climits>
+
 #include "csr_tools.hpp"
 #include "rcm.hpp"
 #include "rowops.hpp"
@@ -23,15 +25,28 @@
 namespace ss {
 
 // --------------------------------------------------- symmetrised pattern
-__global__ void k_union_count(int n, const int *ar, const int *ac, const int *br, const int *bc, int *cnt) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) cnt[r] = union_row<false>(r, ar, ac, br, bc, nullptr, nullptr);
-}
+// One row per group of UNION_G lanes (union by shuffles); a row of A or A^T
+// longer than that is merged by the group's first lane.
+constexpr int UNION_G = 32;
 
-__global__ void k_union_fill(int n, const int *ar, const int *ac, const int *br, const int *bc, const int *orow,
-                             int *ocol, double2 *oval) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) union_row<true>(r, ar, ac, br, bc, ocol + orow[r], oval ? oval + orow[r] : nullptr);
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_union_rows(int n, const int *ar, const int *ac, const int *br,
+                                                    const int *bc, const int *orow, int *ocol, double2 *oval,
+                                                    int *cnt) {
+    const int r = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) / UNION_G);
+    const int t = threadIdx.x & (UNION_G - 1);
+    if (r >= n) return;  // (the whole group)
+    const int as = ar[r], na = ar[r + 1] - as, bs = br[r], nb = br[r + 1] - bs;
+    int *oc = nullptr;
+    double2 *ov = nullptr;
+    if (FILL) {
+        oc = ocol + orow[r];
+        ov = oval ? oval + orow[r] : nullptr;
+    }
+    int len = 0;
+    if (na <= UNION_G && nb <= UNION_G) len = union_row_group<FILL, UNION_G>(as, na, bs, nb, ac, bc, oc, ov);
+    else if (t == 0) len = union_row<FILL>(r, ar, ac, br, bc, oc, ov);
+    if (!FILL && t == 0) cnt[r] = len;
 }
 
 void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_t s) {
@@ -39,9 +54,12 @@ void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_
     transpose(A, At, s, false);
     const int n = A.n;
     DevBuf<int> cnt((size_t)n + 1);
-    k_union_count<<<div_up(n, 256), 256, 0, s>>>(n, A.rowptr.get(), A.col.get(), At.rowptr.get(), At.col.get(),
-                                                 cnt.get());
-    SS_HIP(hipGetLastError());
+    const int grid = div_up((int64_t)n * UNION_G, 256);
+    if (n) {
+        k_union_rows<false><<<grid, 256, 0, s>>>(n, A.rowptr.get(), A.col.get(), At.rowptr.get(), At.col.get(),
+                                                 nullptr, nullptr, nullptr, cnt.get());
+        SS_HIP(hipGetLastError());
+    }
     S.rowptr.resize((size_t)n + 1);
     const int64_t nnz = scan_exclusive(cnt.get(), S.rowptr.get(), n, s, true);
     SS_REQUIRE(nnz < (int64_t(1) << 31), SS_E_INVALID_ARG, "symmetrised pattern too large");
@@ -49,10 +67,11 @@ void symmetrize_pattern(const CsrBuf<double2> &A, CsrBuf<double2> &S, hipStream_
     S.nnz = (int)nnz;
     S.col.resize((size_t)nnz);
     S.val.resize((size_t)nnz);
-    k_union_fill<<<div_up(n, 256), 256, 0, s>>>(n, A.rowptr.get(), A.col.get(), At.rowptr.get(), At.col.get(),
-                                                S.rowptr.get(), S.col.get(), S.val.get());
-    SS_HIP(hipGetLastError());
-    SS_HIP(hipStreamSynchronize(s));
+    if (n) {
+        k_union_rows<true><<<grid, 256, 0, s>>>(n, A.rowptr.get(), A.col.get(), At.rowptr.get(), At.col.get(),
+                                                S.rowptr.get(), S.col.get(), S.val.get(), nullptr);
+        SS_HIP(hipGetLastError());
+    }
 }
 
 // ------------------------------------------------------------------ degree
@@ -476,28 +495,75 @@ __global__ void k_perm_count(int n, const int *perm, const int *rowptr, int *cnt
     if (q < n) cnt[q] = rowptr[perm[q] + 1] - rowptr[perm[q]];
 }
 
-// one wavefront per output row: map columns through iperm, rank-sort
+// PERM_G lanes per output row: each lane maps one column through iperm and
+// finds its place in the sorted row by counting the smaller columns of the
+// row (shuffles within the lane group; a row's columns are distinct).  Rows
+// longer than PERM_G are listed for k_perm_fill_long.
+constexpr int PERM_G = 32;
+constexpr int PERM_LONG_LDS = 8192;  // columns of a long row ranked from LDS
+
 __global__ void __launch_bounds__(256) k_perm_fill(int n, const int *perm, const int *iperm, const int *rowptr,
                                                    const int *col, const double2 *val, const int *orow, int *ocol,
-                                                   double2 *oval) {
-    const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+                                                   double2 *oval, int *longq, int *nlong) {
+    const int lane = threadIdx.x & 63, g = lane & (PERM_G - 1), gb = lane - g;
+    const int q = (blockIdx.x * 256 + threadIdx.x) / PERM_G;
+    int rs = 0, len = 0, c = INT_MAX;
+    double2 v = make_double2(0.0, 0.0);
+    if (q < n) {
+        const int r = perm[q];
+        rs = rowptr[r];
+        len = rowptr[r + 1] - rs;
+        if (g < len) {
+            c = iperm[col[rs + g]];
+            v = val[rs + g];
+        }
+    }
+    int rank = 0;
+    for (int f = 0; f < PERM_G; ++f) rank += (__shfl(c, gb + f, 64) < c);
     if (q >= n) return;
-    const int r = perm[q];
-    const int rs = rowptr[r], re = rowptr[r + 1];
-    const int o = orow[q];
-    for (int e = rs + lane; e < re; e += 64) {
-        const int c = iperm[col[e]];
-        int rank = 0;
-        for (int f = rs; f < re; ++f) rank += (iperm[col[f]] < c);
+    if (len > PERM_G) {
+        if (g == 0) longq[atomicAdd(nlong, 1)] = q;
+        return;
+    }
+    if (g < len) {
+        const int o = orow[q];
         ocol[o + rank] = c;
-        oval[o + rank] = val[e];
+        oval[o + rank] = v;
+    }
+}
+
+// the listed long rows, one workgroup per row at a time
+__global__ void __launch_bounds__(256) k_perm_fill_long(const int *longq, const int *nlong, const int *perm,
+                                                        const int *iperm, const int *rowptr, const int *col,
+                                                        const double2 *val, const int *orow, int *ocol,
+                                                        double2 *oval) {
+    __shared__ int lc[PERM_LONG_LDS];
+    const int m = *nlong;
+    for (int k = blockIdx.x; k < m; k += gridDim.x) {
+        const int q = longq[k], r = perm[q];
+        const int rs = rowptr[r], len = rowptr[r + 1] - rs, o = orow[q];
+        const bool in_lds = len <= PERM_LONG_LDS;
+        __syncthreads();
+        if (in_lds)
+            for (int f = threadIdx.x; f < len; f += 256) lc[f] = iperm[col[rs + f]];
+        __syncthreads();
+        for (int e = threadIdx.x; e < len; e += 256) {
+            const int c = iperm[col[rs + e]];
+            int rank = 0;
+            if (in_lds) {
+                for (int f = 0; f < len; ++f) rank += (lc[f] < c);
+            } else {
+                for (int f = 0; f < len; ++f) rank += (iperm[col[rs + f]] < c);
+            }
+            ocol[o + rank] = c;
+            oval[o + rank] = val[rs + e];
+        }
     }
 }
 
 void permute_matrix(const CsrBuf<double2> &A, const int *perm, const int *iperm, CsrBuf<double2> &B, hipStream_t s) {
     const int n = A.n;
-    DevBuf<int> cnt((size_t)n + 1);
+    DevBuf<int> cnt((size_t)n + 1), longq((size_t)std::max(n, 1)), nlong(1);
     B.alloc(n, A.nnz);
     if (n) {
         k_perm_count<<<div_up(n, 256), 256, 0, s>>>(n, perm, A.rowptr.get(), cnt.get());
@@ -505,11 +571,15 @@ void permute_matrix(const CsrBuf<double2> &A, const int *perm, const int *iperm,
     }
     scan_exclusive(cnt.get(), B.rowptr.get(), n, s, false);
     if (n) {
-        k_perm_fill<<<div_up(n, 4), 256, 0, s>>>(n, perm, iperm, A.rowptr.get(), A.col.get(), A.val.get(),
-                                                 B.rowptr.get(), B.col.get(), B.val.get());
+        SS_HIP(hipMemsetAsync(nlong.get(), 0, sizeof(int), s));
+        k_perm_fill<<<div_up((int64_t)n * PERM_G, 256), 256, 0, s>>>(n, perm, iperm, A.rowptr.get(), A.col.get(),
+                                                                      A.val.get(), B.rowptr.get(), B.col.get(),
+                                                                      B.val.get(), longq.get(), nlong.get());
+        SS_HIP(hipGetLastError());
+        k_perm_fill_long<<<256, 256, 0, s>>>(longq.get(), nlong.get(), perm, iperm, A.rowptr.get(), A.col.get(),
+                                             A.val.get(), B.rowptr.get(), B.col.get(), B.val.get());
         SS_HIP(hipGetLastError());
     }
-    SS_HIP(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------ vector permutes

@@ -30,10 +30,12 @@ void rcm_batch(const RcmJob *jobs, int count, hipStream_t s);
 void identity_order(int n, DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s);
 
 // Colour classes over a base order (colour.hip): the greedy colouring of the
-// symmetric pattern S visited in base order, classes in increasing colour,
-// each in base order.  Returns the number of colours.
+// symmetric pattern S visited in a seeded random order, classes in
+// increasing colour, each in base order.  Returns the number of colours;
+// class_ptr (optional) receives where each class starts in the new order,
+// then n.
 int colour_order(const CsrBuf<double2> &S, const DevBuf<int> &base_perm, const DevBuf<int> &base_iperm,
-                 DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s);
+                 DevBuf<int> &perm, DevBuf<int> &iperm, hipStream_t s, std::vector<int> *class_ptr = nullptr);
 
 // B = P A P^T (rows and columns permuted, rows sorted)
 void permute_matrix(const CsrBuf<double2> &A, const int *perm, const int *iperm, CsrBuf<double2> &B, hipStream_t s);

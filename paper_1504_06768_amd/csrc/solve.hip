@@ -152,7 +152,7 @@ __global__ void k_invert(int n, const int *lorder, int *cp) {
 // solve runs in the colour-class order.
 static void recolour(ss_liouv h, bool keep_rcm, hipStream_t s) {
     DevBuf<int> perm, iperm;
-    h->colours = colour_order(h->S, h->perm, h->iperm, perm, iperm, s);
+    h->colours = colour_order(h->S, h->perm, h->iperm, perm, iperm, s, &h->class_ptr);
     const int n = h->n;
     h->lorder.resize((size_t)std::max(n, 1));
     if (n) {
@@ -247,7 +247,10 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     // first and drive the factorisation too when they are shallow
     bool sched_built = false;
     if (o.ilu == SS_ILU0 && want_sched) {
-        build_levels(F.view(), fdiag, h->sched_lo, h->sched_up, s, h->colours ? h->lorder.get() : nullptr);
+        // (zero fill: the factors keep A's pattern, so no entry joins two
+        // rows of one colour class)
+        build_levels(F.view(), fdiag, h->sched_lo, h->sched_up, s, h->colours ? h->lorder.get() : nullptr,
+                     h->colours ? &h->class_ptr : nullptr);
         sched_built = true;
         phase("levels");
     }

@@ -100,15 +100,74 @@ __global__ void k_mod_fill(int n, int d, int rt, const int *rowptr, const int *c
 }
 
 // ----------------------------------------------------------------- shifted
-__global__ void k_shift_count(int n, const int *rowptr, const int *col, const double2 *val, double sigma, int *cnt) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) cnt[r] = shift_row<false>(r, rowptr, col, val, sigma, nullptr, nullptr);
-}
+// One row per group of SHIFT_G lanes, its entries in chunks of SHIFT_G:
+// the same output as shift_row (diagonal shifted, entries that become or are
+// zero dropped, a diagonal -sigma inserted where the row has none), written
+// coalesced.  The entries' places come from ballots over the group: kept
+// entries before a lane, and the insertion point (the first column past the
+// diagonal when no diagonal entry has been met).
+constexpr int SHIFT_G = 32;
 
-__global__ void k_shift_fill(int n, const int *rowptr, const int *col, const double2 *val, double sigma,
-                             const int *orow, int *ocol, double2 *oval) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) shift_row<true>(r, rowptr, col, val, sigma, ocol + orow[r], oval + orow[r]);
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_shift_rows(int n, const int *rowptr, const int *col, const double2 *val,
+                                                    double sigma, const int *orow, int *ocol, double2 *oval,
+                                                    int *cnt) {
+    const int lane = threadIdx.x & 63, g = lane & (SHIFT_G - 1);
+    const unsigned long long gmask = 0xffffffffull << (lane & 32);
+    const unsigned long long below = gmask & ((1ull << lane) - 1ull);
+    const int r = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) / SHIFT_G);
+    const bool row_ok = r < n;
+    int rs = 0, re = 0, o = 0;
+    if (row_ok) {
+        rs = rowptr[r];
+        re = rowptr[r + 1];
+        if (FILL) o = orow[r];
+    }
+    int at = 0;
+    bool placed = false;
+    for (int base = rs;; base += SHIFT_G) {
+        const bool more = row_ok && base < re;
+        if (!__any(more)) break;
+        const int e = base + g;
+        const bool has = more && e < re;
+        int c = 0;
+        double2 v = mk(0.0, 0.0);
+        if (has) {
+            c = col[e];
+            v = val[e];
+            if (c == r) v.x -= sigma;
+        }
+        const bool keep = has && (v.x != 0.0 || v.y != 0.0);
+        const unsigned long long kp = __ballot(keep) & gmask;
+        const unsigned long long eq = __ballot(has && c == r) & gmask;
+        const unsigned long long gt = __ballot(has && c > r) & gmask;
+        int ins_lane = 64;  // (none)
+        if (!placed && !eq && gt) ins_lane = __ffsll((long long)gt) - 1;
+        const bool ins = ins_lane < 64;
+        if (FILL) {
+            if (keep) {
+                const int p = at + __popcll(kp & below) + ((ins && lane >= ins_lane) ? 1 : 0);
+                ocol[o + p] = c;
+                oval[o + p] = v;
+            }
+            if (ins && lane == ins_lane) {
+                const int p = at + __popcll(kp & below);
+                ocol[o + p] = r;
+                oval[o + p] = mk(-sigma, 0.0);
+            }
+        }
+        at += __popcll(kp) + (ins ? 1 : 0);
+        placed = placed || eq || ins;
+    }
+    if (!row_ok) return;
+    if (!placed) {
+        if (FILL && g == 0) {
+            ocol[o + at] = r;
+            oval[o + at] = mk(-sigma, 0.0);
+        }
+        ++at;
+    }
+    if (!FILL && g == 0) cnt[r] = at;
 }
 
 static void finish_rows(CsrBuf<double2> &A, int n, DevBuf<int> &cnt, hipStream_t s) {
@@ -137,12 +196,18 @@ void make_shifted(const CsrBuf<double2> &L, double sigma, CsrBuf<double2> &A, hi
     const int n = L.n;
     StreamScope scope(s);
     DevBuf<int> cnt((size_t)n + 1);
-    k_shift_count<<<div_up(n, 256), 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma, cnt.get());
-    SS_HIP(hipGetLastError());
+    const int grid = div_up((int64_t)n * SHIFT_G, 256);
+    if (n) {
+        k_shift_rows<false><<<grid, 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma, nullptr,
+                                                 nullptr, nullptr, cnt.get());
+        SS_HIP(hipGetLastError());
+    }
     finish_rows(A, n, cnt, s);
-    k_shift_fill<<<div_up(n, 256), 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma,
-                                                A.rowptr.get(), A.col.get(), A.val.get());
-    SS_HIP(hipGetLastError());
+    if (n) {
+        k_shift_rows<true><<<grid, 256, 0, s>>>(n, L.rowptr.get(), L.col.get(), L.val.get(), sigma, A.rowptr.get(),
+                                                A.col.get(), A.val.get(), nullptr);
+        SS_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace ss

@@ -72,6 +72,32 @@ __global__ void __launch_bounds__(256) k_levels(int n, const int *rowptr, const 
     }
 }
 
+// Levels of one class of rows [lo, hi) whose dependencies all lie in
+// earlier classes (lower) or later ones (upper), whose levels are final:
+// no waits.  An entry inside the class sets STATUS_CLASS_EDGE.
+constexpr unsigned STATUS_CLASS_EDGE = 1u << 8;
+
+template <bool UPPER>
+__global__ void __launch_bounds__(256) k_levels_class(int lo, int hi, const int *rowptr, const int *col,
+                                                      const int *diag, int *lvl, unsigned *status, int *maxlvl) {
+    const int row = lo + blockIdx.x * 256 + threadIdx.x;
+    int m = -1;
+    if (row < hi) {
+        const int e0 = UPPER ? diag[row] + 1 : rowptr[row];
+        const int e1 = UPPER ? rowptr[row + 1] : diag[row];
+        bool inside = false;
+        for (int e = e0; e < e1; ++e) {
+            const int c = col[e];
+            if (UPPER ? c < hi : c >= lo) inside = true;
+            else m = max(m, lvl[c]);
+        }
+        if (inside) atomicOr(status, STATUS_CLASS_EDGE);
+        lvl[row] = m + 1;
+    }
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m >= 0) atomicMax(maxlvl, m + 1);
+}
+
 // Many systems at once, one workgroup each: its threads take the rows in
 // chunks of the workgroup size, in order, so every dependency lies in an
 // earlier chunk (finished) or earlier in the same chunk.
@@ -257,6 +283,7 @@ void LevelBuild::finish(const Csr<double2> &LU, const int *diag, LevelSched &ls,
     d2h(&maxl, misc.get(), 1, s);
     d2h(&st, status.get(), 1, s);
     SS_REQUIRE(!(st & STATUS_SPIN_TIMEOUT), SS_E_TIMEOUT, "level analysis: dependency wait timed out");
+    SS_REQUIRE(!(st & STATUS_CLASS_EDGE), SS_E_HIP, "level analysis: an entry between two rows of one class");
     ls.nlev = n ? maxl + 1 : 0;
     ls.ptr.resize((size_t)ls.nlev + 1);
     ls.slot.resize((size_t)std::max(n, 1));
@@ -304,11 +331,26 @@ template void levels_batch<false>(const LevelJob *, int, hipStream_t);
 template void levels_batch<true>(const LevelJob *, int, hipStream_t);
 
 template <bool UPPER>
-static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s, const int *order) {
+static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hipStream_t s, const int *order,
+                     const std::vector<int> *classes) {
     const int n = LU.n;
     LevelBuild lb;
     LevelJob j = lb.job(LU, diag, s);
-    if (n) {
+    if (n && classes) {
+        const std::vector<int> &cp = *classes;
+        SS_REQUIRE(cp.size() >= 2 && cp.front() == 0 && cp.back() == n, SS_E_INVALID_ARG,
+                   "level analysis: class boundaries do not cover the rows");
+        const int C = (int)cp.size() - 1;
+        for (int k = 0; k < C; ++k) {
+            const int c = UPPER ? C - 1 - k : k;
+            const int lo = cp[(size_t)c], hi = cp[(size_t)c + 1];
+            SS_REQUIRE(lo <= hi, SS_E_INVALID_ARG, "level analysis: class boundaries out of order");
+            if (hi == lo) continue;
+            k_levels_class<UPPER><<<div_up(hi - lo, 256), 256, 0, s>>>(lo, hi, LU.rowptr, LU.col, diag, j.lvl,
+                                                                      j.status, j.maxlvl);
+            SS_HIP(hipGetLastError());
+        }
+    } else if (n) {
         BlockCounter bc;
         bc.init(s);
         const unsigned grid = (unsigned)div_up(n, 256);
@@ -320,9 +362,9 @@ static void one_side(const Csr<double2> &LU, const int *diag, LevelSched &ls, hi
 }
 
 void build_levels(const Csr<double2> &LU, const int *diag, LevelSched &lo, LevelSched &up, hipStream_t s,
-                  const int *order) {
-    one_side<false>(LU, diag, lo, s, order);
-    one_side<true>(LU, diag, up, s, order);
+                  const int *order, const std::vector<int> *classes) {
+    one_side<false>(LU, diag, lo, s, order, classes);
+    one_side<true>(LU, diag, up, s, order, classes);
 }
 
 template <typename T>
