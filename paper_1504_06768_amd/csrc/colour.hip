@@ -41,7 +41,8 @@ namespace {
 
 constexpr int COL_MAX = 4096;    // colours the ordering supports
 constexpr int COL_BS = 256;
-constexpr int FRONT_GRID = 1024;  // workgroups of a frontier launch (grid-stride over the frontier)
+constexpr int FRONT_G = 4;       // lanes per vertex in a frontier launch (1 to 32 measured: 4 best)
+constexpr int FRONT_GRID = 2048;  // workgroups of a frontier launch (grid-stride over the frontier)
 constexpr int FRONT_BATCH = 16;   // frontier launches queued per host read
 
 __device__ inline int ld_colour(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
@@ -100,18 +101,21 @@ __global__ void __launch_bounds__(COL_BS) k_colour_init(int n, const int *rowptr
 // Frontier k of the walk: every listed vertex has all its earlier
 // neighbours coloured (in earlier launches).  It takes the lowest colour none
 // of them carries, then counts itself off at each later neighbour; a
-// neighbour whose count reaches zero joins the next frontier.  Colours from
-// 64 on (dense rows only) are found by the wavefront together through a
-// bitmap in LDS.  The frontier sizes rotate through three counters: launch
-// k reads counter k mod 3, appends to counter k+1 mod 3 and clears counter
-// k+2 mod 3 (read by no launch before k+2 appends to it); the lists
-// alternate between two buffers.  A launch whose frontier is empty does
-// nothing, so the host may queue more launches than there are frontiers.
+// neighbour whose count reaches zero joins the next frontier.  A group of
+// FRONT_G lanes takes one vertex, its row entries dealt out over the lanes,
+// so that several count-off atomics of a row are in flight together (they,
+// not the row walks, bound the launch); colours from 64 on
+// (dense rows only) are found by the wavefront together through a bitmap in
+// LDS.  The frontier sizes rotate through three counters: launch k reads
+// counter k mod 3, appends to counter k+1 mod 3 and clears counter k+2 mod 3
+// (read by no launch before k+2 appends to it); the lists alternate between
+// two buffers.  A launch whose frontier is empty does nothing, so the host
+// may queue more launches than there are frontiers.
 __global__ void __launch_bounds__(COL_BS) k_colour_front(int k, int n, int *list_a, int *list_b, const int *rowptr,
                                                          const int *col, int *colour, int *cnt, int *ctr,
                                                          unsigned *status) {
     __shared__ unsigned long long bm[COL_BS / 64][COL_MAX / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane & (FRONT_G - 1);
     const int m = ctr[k % 3];
     const int *front = (k & 1) ? list_b : list_a;
     int *next = (k & 1) ? list_a : list_b;
@@ -120,29 +124,37 @@ __global__ void __launch_bounds__(COL_BS) k_colour_front(int k, int n, int *list
         ctr[(k + 2) % 3] = 0;
         ctr[3] += m;  // vertices listed so far (one writer per launch, launches in stream order)
     }
-    for (int base = blockIdx.x * COL_BS; base < m; base += gridDim.x * COL_BS) {
-        const int t = base + threadIdx.x;
-        const bool active = t < m;
+    constexpr int ROWS = COL_BS / FRONT_G;  // vertices per workgroup and pass
+    for (int base = blockIdx.x * ROWS; base < m; base += gridDim.x * ROWS) {
+        const int t = base + (int)threadIdx.x / FRONT_G;
+        const bool active = t < m;  // (the whole group)
         int v = 0, e0 = 0, e1 = 0;
         uint64_t kv = 0;
-        unsigned long long taken = 0;
         if (active) {
             v = front[t];
             kv = priority(v);
             e0 = rowptr[v];
             e1 = rowptr[v + 1];
-            for (int e = e0; e < e1; ++e) {
+        }
+        // colours of the earlier neighbours below 64, OR-ed over the group
+        unsigned long long taken = 0;
+        for (int c0 = 0;; c0 += FRONT_G) {
+            const bool more = active && e0 + c0 < e1;
+            if (!__any(more)) break;
+            const int e = e0 + c0 + g;
+            if (more && e < e1) {
                 const int u = col[e];
-                if (u == v || !visits_before(u, priority(u), v, kv)) continue;
-                const int c = colour[u];
-                if (c < 64) taken |= 1ull << c;
+                if (u != v && visits_before(u, priority(u), v, kv)) {
+                    const int c = colour[u];
+                    if (c < 64) taken |= 1ull << c;
+                }
             }
         }
-        int mine = -1;
-        if (active && ~taken) mine = __builtin_ctzll(~taken);
+        for (int o = FRONT_G / 2; o > 0; o >>= 1) taken |= __shfl_xor(taken, o, 64);
+        int mine = (active && ~taken) ? __builtin_ctzll(~taken) : -1;
         // colours 0..63 all taken: the wavefront scans each such row into a
-        // bitmap of COL_MAX colours
-        unsigned long long slow = __ballot(active && !~taken);
+        // bitmap of COL_MAX colours (the group's first lane keeps the result)
+        unsigned long long slow = __ballot(active && g == 0 && !~taken);
         while (slow) {
             const int L = __ffsll((long long)slow) - 1;
             slow &= slow - 1;
@@ -174,18 +186,19 @@ __global__ void __launch_bounds__(COL_BS) k_colour_front(int k, int n, int *list
             }
             wave_sync();
         }
-        if (active) colour[v] = mine;
+        if (active && g == 0) colour[v] = mine;
         // one atomic per wavefront for the colour count
-        const int top = wave_max(mine);
+        const int top = wave_max(g == 0 ? mine : -1);
         if (lane == 0 && top >= 0) atomicMax(ctr + 4, top + 1);
-        // count off at the later neighbours, one row entry per lane and step
-        for (int e = 0;; ++e) {
-            const bool more = active && e0 + e < e1;
+        // count off at the later neighbours, one row entry per lane
+        for (int c0 = 0;; c0 += FRONT_G) {
+            const bool more = active && e0 + c0 < e1;
             if (!__any(more)) break;
+            const int e = e0 + c0 + g;
             bool ready = false;
             int w = 0;
-            if (more) {
-                w = col[e0 + e];
+            if (more && e < e1) {
+                w = col[e];
                 if (w != v && visits_before(v, kv, w, priority(w))) ready = atomicSub(cnt + w, 1) == 1;
             }
             append(ready, w, next, nnext, n, status);
@@ -218,7 +231,7 @@ int colour_order(const CsrBuf<double2> &S, const DevBuf<int> &base_perm, const D
     // each frontier is one level of the visit's dependency graph; the
     // launches are queued FRONT_BATCH at a time and the host reads the size
     // of the next frontier after each batch
-    const int grid = std::min(div_up(n, COL_BS), FRONT_GRID);
+    const int grid = std::min(div_up((int64_t)n * FRONT_G, COL_BS), FRONT_GRID);
     int k = 0, m = 0;
     for (;;) {
         for (int b = 0; b < FRONT_BATCH; ++b, ++k) {

@@ -18,6 +18,8 @@
 // without pivoting, a pivot boosted to a fraction of the row norm keeps the
 // preconditioner bounded, and the Krylov iteration on the exact matrix
 // absorbs the rank-one difference.
+#include <climits>
+
 #include "csr_tools.hpp"
 #include "ilu.hpp"
 #include "syncfree.hpp"
@@ -379,16 +381,26 @@ __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs,
 // up to LG entries (at most LG of them before the pivot, and every row k it
 // eliminates with holding at most LG entries after its pivot) stays in
 // registers, one entry per lane; the U parts of the rows k are fetched eight
-// at a time (one entry per lane each) and matched against the row's columns
-// by shuffles.  Other rows take the general loop.  The steps and their
-// arithmetic are those of ilu0_row, so the factors are the same.
+// at a time (one entry per lane each), each entry finds its column among the
+// row's (kept sorted in LDS) by binary search, and a matched u_kj goes to the
+// lane holding column j through LDS.  Other rows take the general loop.  The
+// steps and their arithmetic are those of ilu0_row, so the factors are the
+// same.
 constexpr int ILU_LEVEL_BS = 256;
 constexpr int ILU_WIDE_LG = 32;
 constexpr int ILU_WIDE_PF = 8;  // U parts fetched per memory round
 
+// orders the LDS accesses of one wavefront (the lane group lies in one)
+__device__ __forceinline__ void ilu_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// scol, su, stag: the group's LG entries of LDS
 template <int LG>
 __device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int lane, double detect,
-                                               double boost) {
+                                               double boost, int *scol, double2 *su, int *stag) {
     const int row = slot.x, rs = slot.y, dg = slot.z, re = slot.w;
     const int nl = dg - rs;  // entries before the pivot: the rows k this row eliminates with
     const bool in = rs + lane < re;
@@ -411,6 +423,10 @@ __device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int 
         return;
     }
     if (lane < nl) ukk0 = gld(J.out + dk0);
+    // the row's columns, sorted, padded past its end
+    scol[lane] = in ? cj : INT_MAX;
+    stag[lane] = -1;
+    ilu_wave_sync();
     for (int p0 = 0; p0 < nl; p0 += ILU_WIDE_PF) {
         int uc[ILU_WIDE_PF];
         double2 uv[ILU_WIDE_PF];
@@ -424,6 +440,19 @@ __device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int 
             if (p < nl && f < ke) {
                 uc[q] = gld(J.col + f);
                 uv[q] = gld(J.out + f);
+            }
+        }
+        // where each fetched u_kj's column sits in the row (-1: not there)
+        int hit[ILU_WIDE_PF];
+#pragma unroll
+        for (int q = 0; q < ILU_WIDE_PF; ++q) {
+            hit[q] = -1;
+            if (uc[q] >= 0) {
+                int pos = 0;
+                for (int st = LG / 2; st > 0; st >>= 1)
+                    if (scol[pos + st - 1] < uc[q]) pos += st;
+                if (scol[pos] < uc[q]) ++pos;
+                if (pos < LG && scol[pos] == uc[q]) hit[q] = pos;
             }
         }
 #pragma unroll
@@ -442,15 +471,13 @@ __device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int 
                 l.x = __shfl(l.x, p, LG);
                 l.y = __shfl(l.y, p, LG);
                 // a_ij -= l u_kj where row k's U part holds column j
-                int sm = -1;
-                for (int t = 0; t < LG; ++t) {
-                    const int c = __shfl(uc[q], t, LG);
-                    if (c >= 0 && c == cj) sm = t;
+                if (hit[q] >= 0) {
+                    su[hit[q]] = uv[q];
+                    stag[hit[q]] = p;
                 }
-                double2 u;
-                u.x = __shfl(uv[q].x, sm < 0 ? 0 : sm, LG);
-                u.y = __shfl(uv[q].y, sm < 0 ? 0 : sm, LG);
-                if (sm >= 0) wv = csub(wv, cmul(l, u));
+                ilu_wave_sync();
+                if (stag[lane] == p) wv = csub(wv, cmul(l, su[lane]));
+                ilu_wave_sync();
             }
         }
     }
@@ -469,10 +496,13 @@ __device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int 
 
 template <int LG>
 __global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu0_level(Ilu0Job J, int lo, int hi, double detect, double boost) {
+    __shared__ int scol[ILU_LEVEL_BS], stag[ILU_LEVEL_BS];
+    __shared__ double2 su[ILU_LEVEL_BS];
     const int t = blockIdx.x * ILU_LEVEL_BS + threadIdx.x;
     const int sl = lo + t / LG, lane = t % LG;
     if (sl >= hi) return;  // (whole groups)
-    ilu0_slot_wide<LG>(J, gld(J.lslot + sl), lane, detect, boost);
+    const int gb = (int)threadIdx.x - lane;
+    ilu0_slot_wide<LG>(J, gld(J.lslot + sl), lane, detect, boost, scol + gb, su + gb, stag + gb);
 }
 
 void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s) {
