@@ -20,29 +20,16 @@ int spmv_group(int n, int nnz) {
 }
 
 // ---------------------------------------------------- block partial sums
-__global__ void __launch_bounds__(256) k_sum_partials(const double2 *partials, int nb, double2 *out) {
-    __shared__ double sx[256], sy[256];
+// One workgroup per group of partials: each thread adds every SUM_BS-th
+// partial in order, then a fixed tree (deterministic).
+__global__ void __launch_bounds__(SUM_BS) k_sum_partials(const double2 *partials, int nb, double2 *out) {
     const int k = blockIdx.x;
-    double x = 0, y = 0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        x += partials[k * nb + b].x;
-        y += partials[k * nb + b].y;
-    }
-    sx[threadIdx.x] = x;
-    sy[threadIdx.x] = y;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            sx[threadIdx.x] += sx[threadIdx.x + off];
-            sy[threadIdx.x] += sy[threadIdx.x + off];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = mk(sx[0], sy[0]);
+    const double2 v = sum_partials_block(partials + (int64_t)k * nb, nb);
+    if (threadIdx.x == 0) out[k] = v;
 }
 
 void sum_partials(const double2 *partials, int nb, int k, double2 *out, hipStream_t s) {
-    k_sum_partials<<<k, 256, 0, s>>>(partials, nb, out);
+    k_sum_partials<<<k, SUM_BS, 0, s>>>(partials, nb, out);
     SS_HIP(hipGetLastError());
 }
 
@@ -153,12 +140,15 @@ void spmv(const Csr<T> &A, const T *x, T *y, int group, hipStream_t s, const int
 }
 
 template <typename T>
-void spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, double2 *partials, int group,
-               hipStream_t s, const int *skip) {
-    const int nb = vec_blocks(A.n);
+int spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, double2 *partials, int group,
+              hipStream_t s, const int *skip) {
     const bool u2y = (u2 == y);
     // the shapes of spmv() for rows of 17..32 entries
     const bool c128 = sizeof(T) == 16;
+    const int g = (group == 16 && !c128) ? 8 : group;
+    // enough workgroups that most rows' loads are in flight at once (each
+    // group takes a few rows in turn), capped for the partial sums
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(A.n, 256 / g), SPMV_DOTS_MAX_BLOCKS));
     switch (group) {
         case 4: k_spmv_dots<T, 4, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
         case 8: k_spmv_dots<T, 8, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
@@ -169,14 +159,15 @@ void spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, doub
         default: k_spmv_dots<T, 32, 1, false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y, u1, u2, u2y, partials, skip); break;
     }
     SS_HIP(hipGetLastError());
+    return nb;
 }
 
 template void spmv<double2>(const Csr<double2> &, const double2 *, double2 *, int, hipStream_t, const int *);
 template void spmv<float2>(const Csr<float2> &, const float2 *, float2 *, int, hipStream_t, const int *);
-template void spmv_dots<double2>(const Csr<double2> &, const double2 *, double2 *, const double2 *, const double2 *,
-                                 double2 *, int, hipStream_t, const int *);
-template void spmv_dots<float2>(const Csr<float2> &, const float2 *, float2 *, const float2 *, const float2 *,
+template int spmv_dots<double2>(const Csr<double2> &, const double2 *, double2 *, const double2 *, const double2 *,
                                 double2 *, int, hipStream_t, const int *);
+template int spmv_dots<float2>(const Csr<float2> &, const float2 *, float2 *, const float2 *, const float2 *,
+                               double2 *, int, hipStream_t, const int *);
 
 template <int G>
 __global__ void __launch_bounds__(256) k_spmv_residual(int n, const int *rowptr, const int *col, const double2 *val,

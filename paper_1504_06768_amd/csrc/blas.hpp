@@ -36,6 +36,32 @@ __device__ inline void block_partials(double2 (&v)[K], double2 *partials) {
     }
 }
 
+// Sum of nb partials by a workgroup of SUM_BS threads: thread t adds
+// partials t, t + SUM_BS, ... in order, then a fixed tree; the result is
+// valid in thread 0.  Every thread of the workgroup must call it.
+constexpr int SUM_BS = 1024;
+__device__ inline double2 sum_partials_block(const double2 *p, int nb) {
+    __shared__ double sx[SUM_BS], sy[SUM_BS];
+    const int t = threadIdx.x;
+    double x = 0, y = 0;
+    for (int b = t; b < nb; b += SUM_BS) {
+        x += p[b].x;
+        y += p[b].y;
+    }
+    __syncthreads();  // (the arrays may still be read by a previous call)
+    sx[t] = x;
+    sy[t] = y;
+    __syncthreads();
+    for (int off = SUM_BS / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            sx[t] += sx[t + off];
+            sy[t] += sy[t + off];
+        }
+        __syncthreads();
+    }
+    return make_double2(sx[0], sy[0]);
+}
+
 // lanes per row for the CSR SpMV, from the mean row length
 int spmv_group(int n, int nnz);
 
@@ -44,10 +70,12 @@ template <typename T>
 void spmv(const Csr<T> &A, const T *x, T *y, int group, hipStream_t s, const int *skip = nullptr);
 
 // y = A x and block partials of conj(u1).y and (if u2 != null) conj(u2).y;
-// u2 == y requests y^H y.  partials: 2 * vec_blocks(A.n) entries.
+// u2 == y requests y^H y.  Returns the number of workgroups nb (at most
+// SPMV_DOTS_MAX_BLOCKS); partials: 2 * nb entries, the second group at nb.
+constexpr int SPMV_DOTS_MAX_BLOCKS = 16384;
 template <typename T>
-void spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, double2 *partials, int group,
-               hipStream_t s, const int *skip);
+int spmv_dots(const Csr<T> &A, const T *x, T *y, const T *u1, const T *u2, double2 *partials, int group,
+              hipStream_t s, const int *skip);
 
 // r = b - A x in fp64 plus block partials of ||r||^2 (partials[0 .. nb))
 void spmv_residual(const Csr<double2> &A, const double2 *b, const double2 *x, double2 *r, double2 *partials,

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_bicg_p(int n, const BicgState *st, cons
 }
 
 // alpha = rho / (r^, v); breakdown when (r^, v) vanishes relative to |r^||v|
-__global__ void k_fin_alpha(BicgState *st, const double2 *scal) {
+__device__ void fin_alpha(BicgState *st, const double2 *scal) {
     if (st->skip) return;
     const double2 rv = scal[0];
     const double vv = scal[1].x;
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_bicg_s(int n, const BicgState *st, cons
     if (threadIdx.x == 0) partials[blockIdx.x] = mk(sh[0] + sh[1] + sh[2] + sh[3], 0.0);
 }
 
-__global__ void k_fin_s(BicgState *st, const double2 *scal) {
+__device__ void fin_s(BicgState *st, const double2 *scal) {
     if (st->skip) return;
     if (scal[0].x <= st->tol2) {
         st->state = 1;
@@ -144,7 +144,7 @@ __global__ void k_fin_s(BicgState *st, const double2 *scal) {
 }
 
 // omega = (t, s) / (t, t) = conj(s^H t) / |t|^2  (scal[0] holds s^H t)
-__global__ void k_fin_omega(BicgState *st, const double2 *scal) {
+__device__ void fin_omega(BicgState *st, const double2 *scal) {
     if (st->skip) return;
     st->dot_ts = cconj(scal[0]);
     st->dot_tt = scal[1].x;
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) k_bicg_x(int n, const BicgState *st, T *x
     }
 }
 
-__global__ void k_fin_x(BicgState *st, const double2 *scal) {
+__device__ void fin_x(BicgState *st, const double2 *scal) {
     const int state = st->state;
     if (state == 1) {
         st->state = 2;
@@ -218,6 +218,24 @@ __global__ void k_fin_x(BicgState *st, const double2 *scal) {
     }
 }
 
+// The k sums of one reduction (one workgroup, fixed order) and the scalar
+// step that uses them, in one launch.
+enum FinStep { FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_X };
+
+template <int STEP>
+__global__ void __launch_bounds__(SUM_BS) k_sum_fin(const double2 *partials, int nb, int k, double2 *scal,
+                                                    BicgState *st) {
+    for (int j = 0; j < k; ++j) {
+        const double2 v = sum_partials_block(partials + (int64_t)j * nb, nb);
+        if (threadIdx.x == 0) scal[j] = v;
+    }
+    if (threadIdx.x != 0) return;
+    if (STEP == FIN_ALPHA) fin_alpha(st, scal);
+    else if (STEP == FIN_S) fin_s(st, scal);
+    else if (STEP == FIN_OMEGA) fin_omega(st, scal);
+    else fin_x(st, scal);
+}
+
 template <typename T>
 void Krylov<T>::init(const Csr<T> &A_, Precond<T> *M_, hipStream_t s_) {
     A = A_;
@@ -228,7 +246,7 @@ void Krylov<T>::init(const Csr<T> &A_, Precond<T> *M_, hipStream_t s_) {
     const size_t nn = (size_t)std::max(n, 1);
     r.resize(nn); rhat.resize(nn); p.resize(nn); v.resize(nn); sv.resize(nn); t.resize(nn);
     phat.resize(nn); shat.resize(nn);
-    partials.resize(4 * (size_t)VEC_MAX_BLOCKS * 24);
+    partials.resize(std::max<size_t>(4 * (size_t)VEC_MAX_BLOCKS * 24, 2 * (size_t)SPMV_DOTS_MAX_BLOCKS));
     scal.resize(128);
     bst.resize(1);
     gst.resize(1);
@@ -256,20 +274,16 @@ KrylovResult Krylov<T>::bicgstab(const T *b, T *x, double rtol, int maxiter, boo
         for (int it = 0; it < BATCH_ITERS; ++it) {
             k_bicg_p<T><<<nb, 256, 0, s>>>(n, st, r.get(), p.get(), v.get());
             M->apply(p.get(), phat.get(), s, skip);
-            spmv_dots<T>(A, phat.get(), v.get(), rhat.get(), v.get(), pp, group, s, skip);
-            sum_partials(pp, nb, 2, sc, s);
-            k_fin_alpha<<<1, 1, 0, s>>>(st, sc);
+            const int nbv = spmv_dots<T>(A, phat.get(), v.get(), rhat.get(), v.get(), pp, group, s, skip);
+            k_sum_fin<FIN_ALPHA><<<1, SUM_BS, 0, s>>>(pp, nbv, 2, sc, st);
             k_bicg_s<T><<<nb, 256, 0, s>>>(n, st, r.get(), v.get(), sv.get(), pp);
-            sum_partials(pp, nb, 1, sc + 2, s);
-            k_fin_s<<<1, 1, 0, s>>>(st, sc + 2);
+            k_sum_fin<FIN_S><<<1, SUM_BS, 0, s>>>(pp, nb, 1, sc + 2, st);
             M->apply(sv.get(), shat.get(), s, skip);
-            spmv_dots<T>(A, shat.get(), t.get(), sv.get(), t.get(), pp, group, s, skip);
-            sum_partials(pp, nb, 2, sc + 4, s);
-            k_fin_omega<<<1, 1, 0, s>>>(st, sc + 4);
+            const int nbt = spmv_dots<T>(A, shat.get(), t.get(), sv.get(), t.get(), pp, group, s, skip);
+            k_sum_fin<FIN_OMEGA><<<1, SUM_BS, 0, s>>>(pp, nbt, 2, sc + 4, st);
             k_bicg_x<T><<<nb, 256, 0, s>>>(n, st, x, phat.get(), shat.get(), r.get(), sv.get(), t.get(),
                                            rhat.get(), pp);
-            sum_partials(pp, nb, 2, sc + 6, s);
-            k_fin_x<<<1, 1, 0, s>>>(st, sc + 6);
+            k_sum_fin<FIN_X><<<1, SUM_BS, 0, s>>>(pp, nb, 2, sc + 6, st);
             SS_HIP(hipGetLastError());
         }
         d2h(&h, st, 1, s);
