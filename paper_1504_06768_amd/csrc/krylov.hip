@@ -14,6 +14,7 @@
 namespace ss {
 
 constexpr int BATCH_ITERS = 4;  // BiCGSTAB iterations enqueued between host checks
+constexpr int GM_BATCH = 4;     // GMRES steps enqueued between host checks
 
 // ------------------------------------------------------------ BiCGSTAB
 template <typename T>
@@ -308,9 +309,12 @@ KrylovResult Krylov<T>::bicgstab(const T *b, T *x, double rtol, int maxiter, boo
 
 // --------------------------------------------------------------- GMRES
 template <typename T>
-__global__ void __launch_bounds__(256) k_multidot(int n, const T *V, int64_t ldv, const T *w, double2 *partials) {
+// (skip set, or gate given and clear: nothing; product self_at is w^H w)
+__global__ void __launch_bounds__(256) k_multidot(int n, const T *V, int64_t ldv, const T *w, int self_at,
+                                                  double2 *partials, const int *skip, const int *gate) {
+    if ((skip && *skip) || (gate && !*gate)) return;
     const int k = blockIdx.y;
-    const T *vk = V + (int64_t)k * ldv;
+    const T *vk = (k == self_at) ? w : V + (int64_t)k * ldv;
     double a = 0, b = 0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const double2 d = cmulc(widen(vk[i]), widen(w[i]));
@@ -332,7 +336,9 @@ __global__ void __launch_bounds__(256) k_multidot(int n, const T *V, int64_t ldv
 // w = sign * sum_k h[k] V_k + (accumulate ? w : 0)
 template <typename T>
 __global__ void __launch_bounds__(256) k_multi_axpy(int n, int nk, const T *V, int64_t ldv, const double2 *h,
-                                                    double sign, bool accumulate, T *w) {
+                                                    double sign, bool accumulate, T *w, const int *skip = nullptr,
+                                                    const int *gate = nullptr) {
+    if ((skip && *skip) || (gate && !*gate)) return;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         double2 acc = accumulate ? widen(w[i]) : mk(0.0, 0.0);
         for (int k = 0; k < nk; ++k) acc = cadd(acc, cscale(cmul(h[k], widen(V[(int64_t)k * ldv + i])), sign));
@@ -341,7 +347,9 @@ __global__ void __launch_bounds__(256) k_multi_axpy(int n, int nk, const T *V, i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scale_into(int n, const T *w, const double2 *den, T *out) {
+__global__ void __launch_bounds__(256) k_scale_into(int n, const T *w, const double2 *den, T *out,
+                                                    const int *skip = nullptr) {
+    if (skip && *skip) return;
     const double inv = 1.0 / den->x;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) out[i] = from_c128<T>(cscale(widen(w[i]), inv));
 }
@@ -357,24 +365,41 @@ __global__ void __launch_bounds__(256) k_add_into(int n, const T *a, T *x) {
 }
 
 // H[:, j] (+)= hcol[0..j]
-__global__ void k_gm_hcol(double2 *H, int ldh, int j, const double2 *hcol, bool accumulate) {
+__global__ void k_gm_hcol(double2 *H, int ldh, int j, const double2 *hcol, bool accumulate, const int *skip,
+                          const int *gate) {
+    if (*skip || (gate && !*gate)) return;
     const int k = threadIdx.x;
     if (k <= j) H[(int64_t)j * ldh + k] = accumulate ? cadd(H[(int64_t)j * ldh + k], hcol[k]) : hcol[k];
 }
 
+// the stopping test's bounds (absolute tolerance, iterations)
+__global__ void k_gm_init(GmresState *st, double tol_abs, int maxiter) {
+    st->tol = tol_abs;
+    st->maxiter = maxiter;
+    st->iters = 0;
+}
 // cycle start: beta = ||r||, g = beta e_1
 __global__ void k_gm_start(GmresState *st, const double2 *norm2, double2 *g, int ldh) {
     const double beta = sqrt(norm2->x);
     st->beta = beta;
     st->res = beta;
     st->j = 0;
+    st->skip = 0;
     for (int k = 0; k < ldh; ++k) g[k] = mk(0.0, 0.0);
     g[0] = mk(beta, 0.0);
 }
 
-// new column j: h_{j+1,j} = ||w||, previous rotations, new rotation, g update
+// second orthogonalisation pass only when the first removed more than
+// 1 - 1/sqrt(2) of w's norm (||w'||^2 < ||w||^2 / 2; Daniel, Gragg, Kaufman
+// and Stewart 1976)
+__global__ void k_gm_need2(GmresState *st, const double2 *wnorm2_after, const double2 *wnorm2_before) {
+    st->pass2 = (!st->skip && wnorm2_after->x < 0.5 * wnorm2_before->x) ? 1 : 0;
+}
+// new column j: h_{j+1,j} = ||w||, previous rotations, new rotation, g
+// update, and the stopping test (which sets skip for the steps queued after)
 __global__ void k_gm_givens(GmresState *st, double2 *H, int ldh, int j, const double2 *wnorm2, double *cs,
                             double2 *sn, double2 *g, double2 *den) {
+    if (st->skip) return;
     double2 *h = H + (int64_t)j * ldh;
     const double hn = sqrt(wnorm2->x);
     st->hnext = hn;
@@ -411,6 +436,8 @@ __global__ void k_gm_givens(GmresState *st, double2 *H, int ldh, int j, const do
     g[j + 1] = cscale(cmulc(sv, gj), -1.0);
     st->res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
     st->j = j + 1;
+    st->iters += 1;
+    if (st->res <= st->tol || hn == 0.0 || st->iters >= st->maxiter) st->skip = 1;
 }
 
 // y = R^-1 g over the first jj columns (back substitution)
@@ -459,9 +486,13 @@ KrylovResult Krylov<T>::gmres(const T *b, T *x, double rtol, int maxiter, int m)
         return res;
     }
     const double tol_abs = rtol * bnorm;
+    k_gm_init<<<1, 1, 0, s>>>(st, tol_abs, maxiter);
+    SS_HIP(hipGetLastError());
+    const int *skip = &st->skip, *pass2 = &st->pass2;
     int total = 0;
     bool first = true;
     double last_res = bnorm;
+    GmresState hs;
     while (true) {
         // r = b - A x into V_0 (x = 0 on the first cycle)
         if (first) {
@@ -474,7 +505,6 @@ KrylovResult Krylov<T>::gmres(const T *b, T *x, double rtol, int maxiter, int m)
         norm2<T>(n, w.get(), pp, sc, s);
         k_gm_start<<<1, 1, 0, s>>>(st, sc, g.get(), ldh);
         SS_HIP(hipGetLastError());
-        GmresState hs;
         d2h(&hs, st, 1, s);
         last_res = hs.beta;
         if (hs.beta <= tol_abs || total >= maxiter) {
@@ -487,33 +517,38 @@ KrylovResult Krylov<T>::gmres(const T *b, T *x, double rtol, int maxiter, int m)
             k_scale_into<T><<<nb, 256, 0, s>>>(n, w.get(), sc + 8, Vp);
             SS_HIP(hipGetLastError());
         }
-        int jj = 0;
+        // Arnoldi steps, queued GM_BATCH at a time: the step that meets the
+        // stopping test sets skip, and the kernels of the steps queued after
+        // it do nothing; the host reads the state once per batch
         bool stop = false;
-        for (int j = 0; j < m; ++j) {
-            T *vj = Vp + (int64_t)j * ldv;
-            M->apply(vj, z.get(), s);
-            spmv<T>(A, z.get(), w.get(), group, s);
-            for (int pass = 0; pass < 2; ++pass) {
-                k_multidot<T><<<dim3(nb, j + 1), 256, 0, s>>>(n, Vp, ldv, w.get(), pp);
+        for (int j0 = 0; j0 < m && !stop; j0 += GM_BATCH) {
+            const int j1 = std::min(m, j0 + GM_BATCH);
+            for (int j = j0; j < j1; ++j) {
+                T *vj = Vp + (int64_t)j * ldv;
+                M->apply(vj, z.get(), s, skip);
+                spmv<T>(A, z.get(), w.get(), group, s, skip);
+                // classical Gram-Schmidt; the first pass also forms w^H w
+                k_multidot<T><<<dim3(nb, j + 2), 256, 0, s>>>(n, Vp, ldv, w.get(), j + 1, pp, skip, nullptr);
+                sum_partials(pp, nb, j + 2, hcol.get(), s);
+                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip);
+                k_gm_hcol<<<1, 256, 0, s>>>(H.get(), ldh, j, hcol.get(), false, skip, nullptr);
+                norm2<T>(n, w.get(), pp, sc, s);
+                k_gm_need2<<<1, 1, 0, s>>>(st, sc, hcol.get() + j + 1);
+                k_multidot<T><<<dim3(nb, j + 1), 256, 0, s>>>(n, Vp, ldv, w.get(), -1, pp, skip, pass2);
                 sum_partials(pp, nb, j + 1, hcol.get(), s);
-                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get());
-                k_gm_hcol<<<1, 256, 0, s>>>(H.get(), ldh, j, hcol.get(), pass == 1);
+                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip, pass2);
+                k_gm_hcol<<<1, 256, 0, s>>>(H.get(), ldh, j, hcol.get(), true, skip, pass2);
+                norm2<T>(n, w.get(), pp, sc, s);
+                k_gm_givens<<<1, 1, 0, s>>>(st, H.get(), ldh, j, sc, cs.get(), sn.get(), g.get(), sc + 9);
+                k_scale_into<T><<<nb, 256, 0, s>>>(n, w.get(), sc + 9, Vp + (int64_t)(j + 1) * ldv, skip);
                 SS_HIP(hipGetLastError());
             }
-            norm2<T>(n, w.get(), pp, sc, s);
-            k_gm_givens<<<1, 1, 0, s>>>(st, H.get(), ldh, j, sc, cs.get(), sn.get(), g.get(), sc + 9);
-            SS_HIP(hipGetLastError());
             d2h(&hs, st, 1, s);
-            ++total;
-            jj = j + 1;
-            last_res = hs.res;
-            if (hs.res <= tol_abs || hs.hnext == 0.0 || total >= maxiter) {
-                stop = true;
-                break;
-            }
-            k_scale_into<T><<<nb, 256, 0, s>>>(n, w.get(), sc + 9, Vp + (int64_t)(j + 1) * ldv);
-            SS_HIP(hipGetLastError());
+            stop = hs.skip != 0;
         }
+        const int jj = hs.j;
+        total = hs.iters;
+        last_res = hs.res;
         // x += M^-1 (V y)
         k_gm_solve<<<1, 1, 0, s>>>(H.get(), ldh, jj, g.get(), yv.get());
         k_multi_axpy<T><<<nb, 256, 0, s>>>(n, jj, Vp, ldv, yv.get(), 1.0, false, u.get());

@@ -26,6 +26,7 @@ struct BicgState {
 struct GmresState {
     double beta, bnorm, tol, res, hnext;
     int j, state, iters, maxiter, skip;
+    int pass2;  // the step's second orthogonalisation pass runs
 };
 
 template <typename T>
