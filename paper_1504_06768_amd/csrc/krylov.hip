@@ -308,42 +308,38 @@ KrylovResult Krylov<T>::bicgstab(const T *b, T *x, double rtol, int maxiter, boo
 }
 
 // --------------------------------------------------------------- GMRES
+// partials of V_k^H w for k = blockIdx.y, w^H w at k = self_at; skip set,
+// or gate given and clear: nothing.  (One workgroup per row slice and k:
+// one workgroup per slice for every k, w read once, measured slower.)
 template <typename T>
-// (skip set, or gate given and clear: nothing; product self_at is w^H w)
 __global__ void __launch_bounds__(256) k_multidot(int n, const T *V, int64_t ldv, const T *w, int self_at,
                                                   double2 *partials, const int *skip, const int *gate) {
     if ((skip && *skip) || (gate && !*gate)) return;
     const int k = blockIdx.y;
     const T *vk = (k == self_at) ? w : V + (int64_t)k * ldv;
-    double a = 0, b = 0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const double2 d = cmulc(widen(vk[i]), widen(w[i]));
-        a += d.x;
-        b += d.y;
-    }
-    __shared__ double sh[2][4];
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_down(a, off, 64);
-        b += __shfl_down(b, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = a; sh[1][threadIdx.x >> 6] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        partials[(int64_t)k * gridDim.x + blockIdx.x] =
-            mk(sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
+    double2 acc[1] = {mk(0.0, 0.0)};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+        acc[0] = cadd(acc[0], cmulc(widen(vk[i]), widen(w[i])));
+    block_partials<1>(acc, partials + (int64_t)k * gridDim.x);
 }
 
 // w = sign * sum_k h[k] V_k + (accumulate ? w : 0)
 template <typename T>
+// (with npart: block partials of the result's ||w||^2 there as well)
 __global__ void __launch_bounds__(256) k_multi_axpy(int n, int nk, const T *V, int64_t ldv, const double2 *h,
                                                     double sign, bool accumulate, T *w, const int *skip = nullptr,
-                                                    const int *gate = nullptr) {
+                                                    const int *gate = nullptr, double2 *npart = nullptr) {
     if ((skip && *skip) || (gate && !*gate)) return;
+    double2 nrm[1] = {mk(0.0, 0.0)};
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         double2 acc = accumulate ? widen(w[i]) : mk(0.0, 0.0);
         for (int k = 0; k < nk; ++k) acc = cadd(acc, cscale(cmul(h[k], widen(V[(int64_t)k * ldv + i])), sign));
-        w[i] = from_c128<T>(acc);
+        const T wi = from_c128<T>(acc);
+        w[i] = wi;
+        const double2 ww = widen(wi);
+        nrm[0].x += ww.x * ww.x + ww.y * ww.y;
     }
+    if (npart) block_partials<1>(nrm, npart);
 }
 
 template <typename T>
@@ -364,12 +360,17 @@ __global__ void __launch_bounds__(256) k_add_into(int n, const T *a, T *x) {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) x[i] = from_c128<T>(cadd(widen(x[i]), widen(a[i])));
 }
 
-// H[:, j] (+)= hcol[0..j]
-__global__ void k_gm_hcol(double2 *H, int ldh, int j, const double2 *hcol, bool accumulate, const int *skip,
-                          const int *gate) {
+// hcol[k] = the sum of partial group k (k < nk), and H[k, j] (+)= hcol[k]
+// for k <= j; one workgroup per group
+__global__ void __launch_bounds__(SUM_BS) k_gm_sum_hcol(const double2 *partials, int nb, double2 *hcol, double2 *H,
+                                                        int ldh, int j, bool accumulate, const int *skip,
+                                                        const int *gate) {
     if (*skip || (gate && !*gate)) return;
-    const int k = threadIdx.x;
-    if (k <= j) H[(int64_t)j * ldh + k] = accumulate ? cadd(H[(int64_t)j * ldh + k], hcol[k]) : hcol[k];
+    const int k = blockIdx.x;
+    const double2 v = sum_partials_block(partials + (int64_t)k * nb, nb);
+    if (threadIdx.x != 0) return;
+    hcol[k] = v;
+    if (k <= j) H[(int64_t)j * ldh + k] = accumulate ? cadd(H[(int64_t)j * ldh + k], v) : v;
 }
 
 // the stopping test's bounds (absolute tolerance, iterations)
@@ -392,13 +393,19 @@ __global__ void k_gm_start(GmresState *st, const double2 *norm2, double2 *g, int
 // second orthogonalisation pass only when the first removed more than
 // 1 - 1/sqrt(2) of w's norm (||w'||^2 < ||w||^2 / 2; Daniel, Gragg, Kaufman
 // and Stewart 1976)
-__global__ void k_gm_need2(GmresState *st, const double2 *wnorm2_after, const double2 *wnorm2_before) {
-    st->pass2 = (!st->skip && wnorm2_after->x < 0.5 * wnorm2_before->x) ? 1 : 0;
+// (the first pass's ||w'||^2 from its partials into wnorm2_after)
+__global__ void __launch_bounds__(SUM_BS) k_gm_need2(GmresState *st, const double2 *npart, int nb,
+                                                     double2 *wnorm2_after, const double2 *wnorm2_before) {
+    if (st->skip) return;
+    const double2 v = sum_partials_block(npart, nb);
+    if (threadIdx.x != 0) return;
+    *wnorm2_after = v;
+    st->pass2 = (v.x < 0.5 * wnorm2_before->x) ? 1 : 0;
 }
 // new column j: h_{j+1,j} = ||w||, previous rotations, new rotation, g
 // update, and the stopping test (which sets skip for the steps queued after)
-__global__ void k_gm_givens(GmresState *st, double2 *H, int ldh, int j, const double2 *wnorm2, double *cs,
-                            double2 *sn, double2 *g, double2 *den) {
+__device__ void gm_givens(GmresState *st, double2 *H, int ldh, int j, const double2 *wnorm2, double *cs,
+                          double2 *sn, double2 *g, double2 *den) {
     if (st->skip) return;
     double2 *h = H + (int64_t)j * ldh;
     const double hn = sqrt(wnorm2->x);
@@ -440,6 +447,19 @@ __global__ void k_gm_givens(GmresState *st, double2 *H, int ldh, int j, const do
     if (st->res <= st->tol || hn == 0.0 || st->iters >= st->maxiter) st->skip = 1;
 }
 
+// ||w||^2 after the second pass (from its partials when it ran, else the
+// first pass's), then the Givens step
+__global__ void __launch_bounds__(SUM_BS) k_gm_givens(GmresState *st, const double2 *npart, int nb,
+                                                      double2 *wnorm2, double2 *H, int ldh, int j, double *cs,
+                                                      double2 *sn, double2 *g, double2 *den) {
+    if (st->skip) return;
+    if (st->pass2) {
+        const double2 v = sum_partials_block(npart, nb);
+        if (threadIdx.x == 0) *wnorm2 = v;
+    }
+    if (threadIdx.x == 0) gm_givens(st, H, ldh, j, wnorm2, cs, sn, g, den);
+}
+
 // y = R^-1 g over the first jj columns (back substitution)
 __global__ void k_gm_solve(const double2 *H, int ldh, int jj, const double2 *g, double2 *y) {
     for (int k = jj - 1; k >= 0; --k) {
@@ -466,7 +486,8 @@ KrylovResult Krylov<T>::gmres(const T *b, T *x, double rtol, int maxiter, int m)
         cs.resize((size_t)m);
         yv.resize((size_t)m);
         hcol.resize((size_t)ldh);
-        if (partials.size() < (size_t)(m + 1) * VEC_MAX_BLOCKS) partials.resize((size_t)(m + 1) * VEC_MAX_BLOCKS);
+        // (m + 1) groups of products, then the norm's partials
+        if (partials.size() < (size_t)(m + 2) * VEC_MAX_BLOCKS) partials.resize((size_t)(m + 2) * VEC_MAX_BLOCKS);
         m_alloc = m;
     }
     const int nb = vec_blocks(n);
@@ -527,19 +548,20 @@ KrylovResult Krylov<T>::gmres(const T *b, T *x, double rtol, int maxiter, int m)
                 T *vj = Vp + (int64_t)j * ldv;
                 M->apply(vj, z.get(), s, skip);
                 spmv<T>(A, z.get(), w.get(), group, s, skip);
-                // classical Gram-Schmidt; the first pass also forms w^H w
+                // classical Gram-Schmidt; the first pass also forms w^H w,
+                // each update also the partials of the new ||w||^2
+                double2 *np = pp + (int64_t)(m + 1) * nb;
                 k_multidot<T><<<dim3(nb, j + 2), 256, 0, s>>>(n, Vp, ldv, w.get(), j + 1, pp, skip, nullptr);
-                sum_partials(pp, nb, j + 2, hcol.get(), s);
-                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip);
-                k_gm_hcol<<<1, 256, 0, s>>>(H.get(), ldh, j, hcol.get(), false, skip, nullptr);
-                norm2<T>(n, w.get(), pp, sc, s);
-                k_gm_need2<<<1, 1, 0, s>>>(st, sc, hcol.get() + j + 1);
+                k_gm_sum_hcol<<<j + 2, SUM_BS, 0, s>>>(pp, nb, hcol.get(), H.get(), ldh, j, false, skip, nullptr);
+                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip, nullptr,
+                                                   np);
+                k_gm_need2<<<1, SUM_BS, 0, s>>>(st, np, nb, sc, hcol.get() + j + 1);
                 k_multidot<T><<<dim3(nb, j + 1), 256, 0, s>>>(n, Vp, ldv, w.get(), -1, pp, skip, pass2);
-                sum_partials(pp, nb, j + 1, hcol.get(), s);
-                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip, pass2);
-                k_gm_hcol<<<1, 256, 0, s>>>(H.get(), ldh, j, hcol.get(), true, skip, pass2);
-                norm2<T>(n, w.get(), pp, sc, s);
-                k_gm_givens<<<1, 1, 0, s>>>(st, H.get(), ldh, j, sc, cs.get(), sn.get(), g.get(), sc + 9);
+                k_gm_sum_hcol<<<j + 1, SUM_BS, 0, s>>>(pp, nb, hcol.get(), H.get(), ldh, j, true, skip, pass2);
+                k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip, pass2,
+                                                   np);
+                k_gm_givens<<<1, SUM_BS, 0, s>>>(st, np, nb, sc, H.get(), ldh, j, cs.get(), sn.get(), g.get(),
+                                                 sc + 9);
                 k_scale_into<T><<<nb, 256, 0, s>>>(n, w.get(), sc + 9, Vp + (int64_t)(j + 1) * ldv, skip);
                 SS_HIP(hipGetLastError());
             }
