@@ -20,16 +20,18 @@ int spmv_group(int n, int nnz) {
 }
 
 // ---------------------------------------------------- block partial sums
-// One workgroup per group of partials: each thread adds every SUM_BS-th
-// partial in order, then a fixed tree (deterministic).
-__global__ void __launch_bounds__(SUM_BS) k_sum_partials(const double2 *partials, int nb, double2 *out) {
+// One workgroup per group of partials (sum_partials_block): 256 threads up to
+// 4096 partials, 1024 above (the fused SpMV's up to 16384).
+template <int BS>
+__global__ void __launch_bounds__(BS) k_sum_partials(const double2 *partials, int nb, double2 *out) {
     const int k = blockIdx.x;
-    const double2 v = sum_partials_block(partials + (int64_t)k * nb, nb);
+    const double2 v = sum_partials_block<BS>(partials + (int64_t)k * nb, nb);
     if (threadIdx.x == 0) out[k] = v;
 }
 
 void sum_partials(const double2 *partials, int nb, int k, double2 *out, hipStream_t s) {
-    k_sum_partials<<<k, SUM_BS, 0, s>>>(partials, nb, out);
+    if (nb <= 4096) k_sum_partials<256><<<k, 256, 0, s>>>(partials, nb, out);
+    else k_sum_partials<SUM_BS><<<k, SUM_BS, 0, s>>>(partials, nb, out);
     SS_HIP(hipGetLastError());
 }
 

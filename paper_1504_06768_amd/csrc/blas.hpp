@@ -36,15 +36,16 @@ __device__ inline void block_partials(double2 (&v)[K], double2 *partials) {
     }
 }
 
-// Sum of nb partials by a workgroup of SUM_BS threads: thread t adds
-// partials t, t + SUM_BS, ... in order, then a fixed tree; the result is
-// valid in thread 0.  Every thread of the workgroup must call it.
+// Sum of nb partials by a workgroup of BS threads: thread t adds partials
+// t, t + BS, ... in order, then a fixed tree; the result is valid in
+// thread 0.  Every thread of the workgroup must call it.
 constexpr int SUM_BS = 1024;
+template <int BS = SUM_BS>
 __device__ inline double2 sum_partials_block(const double2 *p, int nb) {
-    __shared__ double sx[SUM_BS], sy[SUM_BS];
+    __shared__ double sx[BS], sy[BS];
     const int t = threadIdx.x;
     double x = 0, y = 0;
-    for (int b = t; b < nb; b += SUM_BS) {
+    for (int b = t; b < nb; b += BS) {
         x += p[b].x;
         y += p[b].y;
     }
@@ -52,7 +53,7 @@ __device__ inline double2 sum_partials_block(const double2 *p, int nb) {
     sx[t] = x;
     sy[t] = y;
     __syncthreads();
-    for (int off = SUM_BS / 2; off > 0; off >>= 1) {
+    for (int off = BS / 2; off > 0; off >>= 1) {
         if (t < off) {
             sx[t] += sx[t + off];
             sy[t] += sy[t + off];
