@@ -7,6 +7,12 @@ quality is judged by the condition estimate ||(LU)^{-1} e||_inf, e = (1,...,1).
 ilu0  -- ILU with zero fill: L unit lower and U upper keep exactly the
          pattern of A, and (LU)_ij = a_ij on that pattern.  Computed in the
          row-wise (IKJ) elimination order, one row at a time.
+ilu0_fixed_point -- the same zero-fill factors as the fixed point of their
+         defining equations (LU)_ij = a_ij on the pattern, reached by
+         synchronous sweeps (Chow and Patel, "Fine-grained parallel
+         incomplete LU factorization", 2015; not in the paper, which builds
+         its iLU by elimination): every entry is recomputed from the previous
+         sweep's values, so a sweep has no order between entries.
 ilut  -- dual-threshold ILU: during the elimination of row i, multipliers and
          fill entries smaller than drop_tol * ||a_i||_inf are dropped, and at
          most ceil(fill * nnz(a_i)) entries are kept in each of the strict lower
@@ -77,6 +83,61 @@ def ilu0(A, guard: float = 0.0, boost: float | None = None):
             vals[diag[i]] = v
             guarded += int(g)
     return sp.csr_matrix((vals, indices.copy(), indptr.copy()), shape=A.shape), guarded
+
+
+def ilu0_fixed_point(A, sweeps: int, guard: float = 0.0, boost: float | None = None):
+    """ILU(0) factors after `sweeps` synchronous fixed-point sweeps.
+
+    Unknowns: l_ij (j < i) and u_ij (j >= i) on the pattern of A, with
+    l_ii = 1.  The equations (LU)_ij = a_ij give, for every pattern entry,
+        u_ij = a_ij - sum_{k < i} l_ik u_kj                    (j >= i)
+        l_ij = (a_ij - sum_{k < j} l_ik u_kj) / u_jj           (j < i)
+    where the sums run over the k with (i, k) and (k, j) on the pattern.  A
+    sweep evaluates every right-hand side with the previous sweep's values
+    (the products subtracted from a_ij in increasing k, as the elimination
+    does); the pivot guard of ilu0 is applied to each new u_ii.  Start:
+    l_ij = a_ij / a_jj, u_ij = a_ij.  After as many sweeps as the longest
+    chain of dependencies between the unknowns, the values are those of
+    ilu0 (up to rounding).  Returns (LU csr, pivots guarded in the last
+    sweep)."""
+    boost = guard if boost is None else boost
+    A = sp.csr_matrix(A, dtype=np.complex128)
+    A.sort_indices()
+    n = A.shape[0]
+    indptr, indices, a = A.indptr, A.indices, A.data
+    pos = [dict(zip(indices[indptr[i]:indptr[i + 1]].tolist(),
+                    range(indptr[i], indptr[i + 1]))) for i in range(n)]
+    diag = np.array([pos[i].get(i, -1) for i in range(n)])
+    if np.any(diag < 0):
+        raise ValueError("ilu0_fixed_point: structurally zero diagonal")
+    rownorm = [float(np.max(np.abs(a[indptr[i]:indptr[i + 1]]))) for i in range(n)]
+    x = a.copy()
+    for i in range(n):
+        for e in range(indptr[i], diag[i]):
+            x[e] = a[e] / a[diag[indices[e]]]
+    guarded = 0
+    for _ in range(sweeps):
+        new = np.empty_like(x)
+        guarded = 0
+        for i in range(n):
+            for e in range(indptr[i], indptr[i + 1]):
+                j = int(indices[e])
+                v = complex(a[e])
+                for e2 in range(indptr[i], diag[i]):      # k < i, ascending
+                    k = int(indices[e2])
+                    if k >= j:
+                        break
+                    f = pos[k].get(j)                      # u_kj, j > k
+                    if f is not None:
+                        v -= x[e2] * x[f]
+                if j < i:
+                    v = v / x[diag[j]]
+                elif j == i and guard > 0:
+                    v, g = _guard(v, guard * rownorm[i], boost * rownorm[i])
+                    guarded += int(g)
+                new[e] = v
+        x = new
+    return sp.csr_matrix((x, indices.copy(), indptr.copy()), shape=A.shape), guarded
 
 
 def ilut(A, drop_tol: float = 1e-4, fill: float = 10.0, guard: float = 0.0, boost: float | None = None):
