@@ -96,7 +96,10 @@ def ilu0_fixed_point(A, sweeps: int, guard: float = 0.0, boost: float | None = N
     sweep evaluates every right-hand side with the previous sweep's values
     (the products subtracted from a_ij in increasing k, as the elimination
     does); the pivot guard of ilu0 is applied to each new u_ii.  Start:
-    l_ij = a_ij / a_jj, u_ij = a_ij.  After as many sweeps as the longest
+    u_ii = a_ii through the same guard, l_ij = a_ij / u_jj, u_ij = a_ij
+    (a structurally present zero or tiny a_jj, e.g. the shifted zero
+    diagonal of inverse power, would otherwise put huge multipliers into the
+    first sweeps).  After as many sweeps as the longest
     chain of dependencies between the unknowns, the values are those of
     ilu0 (up to rounding).  Returns (LU csr, pivots guarded in the last
     sweep)."""
@@ -112,9 +115,12 @@ def ilu0_fixed_point(A, sweeps: int, guard: float = 0.0, boost: float | None = N
         raise ValueError("ilu0_fixed_point: structurally zero diagonal")
     rownorm = [float(np.max(np.abs(a[indptr[i]:indptr[i + 1]]))) for i in range(n)]
     x = a.copy()
+    if guard > 0:
+        for i in range(n):
+            x[diag[i]] = _guard(complex(a[diag[i]]), guard * rownorm[i], boost * rownorm[i])[0]
     for i in range(n):
         for e in range(indptr[i], diag[i]):
-            x[e] = a[e] / a[diag[indices[e]]]
+            x[e] = a[e] / x[diag[indices[e]]]
     guarded = 0
     for _ in range(sweeps):
         new = np.empty_like(x)

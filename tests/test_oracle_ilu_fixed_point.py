@@ -40,6 +40,16 @@ def test_zero_sweeps_is_the_starting_guess():
             assert LU.data[e] == want
 
 
+def test_starting_guess_takes_the_guarded_pivots():
+    # a_11 = 1e-20 is below 1e-8 * ||a_1||_inf = 2e-8: u_11 starts at 0.1 * 2,
+    # and l_21 = a_21 / u_11
+    A = sp.csr_matrix(np.array([[3.0, 1.0, 0.0], [1.0, 1e-20, 2.0], [0.0, 5.0, 7.0]], dtype=np.complex128))
+    LU, _ = ilu0_fixed_point(A, 0, guard=1e-8, boost=0.1)
+    assert LU[1, 1] == 0.2
+    assert LU[2, 1] == 5.0 / 0.2
+    assert LU[1, 0] == 1.0 / 3.0 and LU[0, 0] == 3.0 and LU[2, 2] == 7.0
+
+
 def test_tridiagonal_chain_terminates():
     # u_ii depends on u_{i-1,i-1}: the last pivot needs about n sweeps
     n = 8
