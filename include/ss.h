@@ -147,6 +147,16 @@ typedef struct {
                            1e-4 in SS_MIXED                                     */
     double weight;      /* trace-row weight w; 0 = mean diagonal of L          */
     int64_t seed;       /* seed of the random start (SS_FLAG_RANDOM_START) (0) */
+    int32_t ilu_sweeps; /* SS_ILU0 on the device-wide path: 0 = the factors by
+                           elimination; s > 0 = the same zero-fill factors as
+                           the fixed point of (LU)_ij = a_ij on the pattern,
+                           after s synchronous sweeps from l_ij = a_ij / a_jj,
+                           u_ij = a_ij (Chow and Patel 2015; exact once s
+                           covers the longest dependency chain, an
+                           approximation of them before).  Not with the
+                           workgroup-resident solve or ss_solve_batch
+                           (SS_E_INVALID_ARG).                        (0)     */
+    int32_t reserved;   /* 0                                                   */
 } ss_options;
 
 #define SS_FLAG_HERMITIZE   1  /* return (rho + rho^+)/2                      */

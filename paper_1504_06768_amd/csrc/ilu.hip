@@ -22,6 +22,7 @@
 
 #include "csr_tools.hpp"
 #include "ilu.hpp"
+#include "ilu_fp.hpp"
 #include "syncfree.hpp"
 
 namespace ss {
@@ -546,6 +547,182 @@ IluResult ilu0_factor_levels(const CsrBuf<double2> &A, const int *diag, const Le
     SS_HIP(hipGetLastError());
     IluResult r;
     d2h(&r.guarded, nguard.get(), 1, s);  // (synchronises before the work array is released)
+    return r;
+}
+
+// ------------------------------------------------ fixed-point ILU(0)
+// The zero-fill factors as the fixed point of (LU)_ij = a_ij on the pattern
+// (Chow and Patel 2015), by synchronous sweeps: every entry is recomputed
+// from the previous sweep's values,
+//   u_ij = a_ij - sum_{k < i} l_ik u_kj,  l_ij = (a_ij - sum_{k < j} l_ik u_kj) / u_jj,
+// the products subtracted in increasing k as the elimination does, and the
+// pivot guard applied to each new u_ii.  Start: u_ii = a_ii through the
+// same guard, then l_ij = a_ij / u_jj and u_ij = a_ij (a tiny a_jj, as in
+// the shifted zero diagonal of inverse power, would otherwise put huge
+// multipliers into the first sweeps).  A sweep has no order between rows:
+// one launch, FP_G lanes
+// per row.  A row of at most FP_G entries keeps them one per lane; the U
+// part of each row k it eliminates with comes FP_G entries at a time, each
+// entry finds its column among the row's (in LDS) by binary search, and a
+// match reaches the lane holding that column through LDS.  Longer rows
+// (a trace row) take one lane per entry, each merging on its own.
+constexpr int FP_G = 32;
+
+// the largest |a_ij| of the row over the lane group (every lane)
+__device__ __forceinline__ double fp_row_norm(const double2 *a, int rs, int re, int lane) {
+    double rn = 0.0;
+    for (int e = rs + lane; e < re; e += FP_G) {
+        const double2 v = a[e];
+        rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
+    }
+    for (int off = FP_G / 2; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, FP_G));
+    return rn;
+}
+
+// the pivot guard of the elimination: below detect * rn, the pivot becomes
+// boost * rn with its phase kept (boost itself if rn is zero)
+__device__ __forceinline__ double2 fp_guard(double2 v, double rn, double detect, double boost, bool *hit) {
+    const double mag = sqrt(v.x * v.x + v.y * v.y);
+    *hit = !(mag >= detect * rn);
+    if (!*hit) return v;
+    const double b = (rn > 0.0) ? boost * rn : 1.0;
+    return (mag > 0.0) ? cscale(v, b / mag) : mk(b, 0.0);
+}
+
+// start, first the pivots: x = a, with u_ii = a_ii through the guard
+__global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu_fp_pivots(int n, const int *rowptr, const int *diag,
+                                                                const double2 *a, double2 *x, double detect,
+                                                                double boost) {
+    const int t = blockIdx.x * ILU_LEVEL_BS + threadIdx.x;
+    const int row = t / FP_G, lane = t % FP_G;
+    if (row >= n) return;
+    const int rs = rowptr[row], re = rowptr[row + 1];
+    const double rn = fp_row_norm(a, rs, re, lane);
+    for (int e = rs + lane; e < re; e += FP_G) x[e] = a[e];
+    if (lane == 0) {
+        bool hit;
+        x[diag[row]] = fp_guard(a[diag[row]], rn, detect, boost, &hit);
+    }
+}
+
+// then the multipliers: l_ij = a_ij / u_jj
+__global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu_fp_start(int n, const int *rowptr, const int *col,
+                                                               const int *diag, const double2 *a, double2 *x) {
+    const int t = blockIdx.x * ILU_LEVEL_BS + threadIdx.x;
+    const int row = t / FP_G, lane = t % FP_G;
+    if (row >= n) return;
+    for (int e = rowptr[row] + lane; e < diag[row]; e += FP_G) x[e] = cdiv(a[e], x[diag[col[e]]]);
+}
+
+// the new value of entry e = (row, j) from v = a_ij minus its products
+__device__ __forceinline__ double2 fp_finish(double2 v, int row, int j, const int *diag, const double2 *old,
+                                             double rn, double detect, double boost, int *nguard) {
+    if (j < row) return cdiv(v, old[diag[j]]);
+    if (j == row) {
+        bool hit;
+        v = fp_guard(v, rn, detect, boost, &hit);
+        if (hit) atomicAdd(nguard, 1);
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu_fp_sweep(int n, const int *rowptr, const int *col,
+                                                               const int *diag, const double2 *a,
+                                                               const double2 *old, double2 *out, double detect,
+                                                               double boost, int *nguard) {
+    __shared__ int scol[ILU_LEVEL_BS], stag[ILU_LEVEL_BS];
+    __shared__ double2 su[ILU_LEVEL_BS];
+    const int t = blockIdx.x * ILU_LEVEL_BS + threadIdx.x;
+    const int row = t / FP_G, lane = t % FP_G;
+    if (row >= n) return;  // (whole groups)
+    const int gb = (int)threadIdx.x - lane;
+    const int rs = rowptr[row], re = rowptr[row + 1], dg = diag[row];
+    const int len = re - rs, nl = dg - rs;
+    const double rn = fp_row_norm(a, rs, re, lane);
+    if (len > FP_G) {
+        // one lane per entry, merging with each row k on its own
+        for (int e = rs + lane; e < re; e += FP_G) {
+            const int j = col[e];
+            double2 v = a[e];
+            for (int e2 = rs; e2 < dg; ++e2) {
+                const int k = col[e2];
+                if (k >= j) break;
+                int lo = diag[k] + 1, hi = rowptr[k + 1] - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int c = col[mid];
+                    if (c == j) {
+                        v = csub(v, cmul(old[e2], old[mid]));
+                        break;
+                    }
+                    if (c < j) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            out[e] = fp_finish(v, row, j, diag, old, rn, detect, boost, nguard);
+        }
+        return;
+    }
+    const bool in = lane < len;
+    const int cj = in ? col[rs + lane] : INT_MAX;
+    double2 v = in ? a[rs + lane] : mk(0.0, 0.0);
+    const double2 lo_v = in ? old[rs + lane] : mk(0.0, 0.0);
+    scol[gb + lane] = cj;
+    stag[gb + lane] = -1;
+    ilu_wave_sync();
+    int tag = 0;
+    for (int p = 0; p < nl; ++p) {
+        const int k = __shfl(cj, p, FP_G);
+        double2 l;
+        l.x = __shfl(lo_v.x, p, FP_G);
+        l.y = __shfl(lo_v.y, p, FP_G);
+        const int ks = diag[k] + 1, ke = rowptr[k + 1];
+        for (int c0 = ks; c0 < ke; c0 += FP_G, ++tag) {
+            const int f = c0 + lane;
+            if (f < ke) {
+                const int uc = col[f];
+                int pos = 0;
+                for (int st = FP_G / 2; st > 0; st >>= 1)
+                    if (scol[gb + pos + st - 1] < uc) pos += st;
+                if (scol[gb + pos] < uc) ++pos;
+                if (pos < FP_G && scol[gb + pos] == uc) {
+                    su[gb + pos] = old[f];
+                    stag[gb + pos] = tag;
+                }
+            }
+            ilu_wave_sync();
+            if (stag[gb + lane] == tag) v = csub(v, cmul(l, su[gb + lane]));
+            ilu_wave_sync();
+        }
+    }
+    if (in) out[rs + lane] = fp_finish(v, row, cj, diag, old, rn, detect, boost, nguard);
+}
+
+IluResult ilu0_fixed_point(const CsrBuf<double2> &A, const int *diag, int sweeps, double detect, double boost,
+                           CsrBuf<double2> &LU, hipStream_t s) {
+    SS_REQUIRE(sweeps >= 1, SS_E_INVALID_ARG, "fixed-point ILU: at least one sweep");
+    const int n = A.n, nnz = A.nnz;
+    LU.alloc(n, nnz);
+    SS_HIP(hipMemcpyAsync(LU.rowptr.get(), A.rowptr.get(), sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) SS_HIP(hipMemcpyAsync(LU.col.get(), A.col.get(), sizeof(int) * nnz, hipMemcpyDeviceToDevice, s));
+    DevBuf<double2> other((size_t)std::max(nnz, 1));
+    DevBuf<int> nguard(1);
+    IluResult r;
+    if (n == 0) return r;
+    // the sweeps alternate between the two buffers and end in LU.val
+    double2 *buf[2] = {LU.val.get(), other.get()};
+    int cur = (sweeps % 2 == 0) ? 0 : 1;
+    const int grid = div_up((int64_t)n * FP_G, ILU_LEVEL_BS);
+    k_ilu_fp_pivots<<<grid, ILU_LEVEL_BS, 0, s>>>(n, A.rowptr.get(), diag, A.val.get(), buf[cur], detect, boost);
+    k_ilu_fp_start<<<grid, ILU_LEVEL_BS, 0, s>>>(n, A.rowptr.get(), A.col.get(), diag, A.val.get(), buf[cur]);
+    SS_HIP(hipGetLastError());
+    for (int k = 0; k < sweeps; ++k) {
+        SS_HIP(hipMemsetAsync(nguard.get(), 0, sizeof(int), s));  // (the last sweep's count)
+        k_ilu_fp_sweep<<<grid, ILU_LEVEL_BS, 0, s>>>(n, A.rowptr.get(), A.col.get(), diag, A.val.get(), buf[cur],
+                                                     buf[1 - cur], detect, boost, nguard.get());
+        SS_HIP(hipGetLastError());
+        cur = 1 - cur;
+    }
+    d2h(&r.guarded, nguard.get(), 1, s);  // (synchronises before the other buffer is released)
     return r;
 }
 

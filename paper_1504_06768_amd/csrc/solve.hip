@@ -29,6 +29,7 @@
 #include "assemble.hpp"
 #include "csr_tools.hpp"
 #include "handle.hpp"
+#include "ilu_fp.hpp"
 #include "rcm.hpp"
 #include "setup_batch.hpp"
 #include "transform.hpp"
@@ -85,6 +86,8 @@ static void check_options(int method, const ss_options &o) {
     SS_REQUIRE(o.ilu == SS_ILU0 || o.ilu == SS_ILUT, SS_E_INVALID_ARG, "unknown ILU kind");
     SS_REQUIRE(o.ordering == SS_ORDER_RCM || o.ordering == SS_ORDER_NATURAL || o.ordering == SS_ORDER_COLOUR,
                SS_E_INVALID_ARG, "unknown ordering");
+    SS_REQUIRE(o.ilu_sweeps >= 0, SS_E_INVALID_ARG, "ilu_sweeps must be >= 0");
+    SS_REQUIRE(o.ilu_sweeps == 0 || o.ilu == SS_ILU0, SS_E_INVALID_ARG, "ilu_sweeps applies to SS_ILU0 only");
 }
 
 static void prepare_transform(ss_liouv h, int method, const ss_options &o, hipStream_t s) {
@@ -224,6 +227,8 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
     phase("transform");
     // device-wide solves use level schedules of the factors
     const bool want_sched = !use_workgroup(h, method, o) && (int64_t)h->n * (int64_t)sizeof(double2) < ((int64_t)1 << 31);
+    SS_REQUIRE(o.ilu_sweeps == 0 || want_sched, SS_E_INVALID_ARG,
+               "ilu_sweeps: fixed-point ILU(0) on the device-wide path only");
     if (o.ordering == SS_ORDER_NATURAL) identity_order(h->n, h->perm, h->iperm, s);
     else rcm_order(h->S, h->perm, h->iperm, s);
     h->colours = 0;
@@ -254,7 +259,9 @@ void prepare(ss_liouv h, int method, const ss_options &o) {
         sched_built = true;
         phase("levels");
     }
-    if (o.ilu == SS_ILU0 && sched_built && h->sched_lo.nlev <= PRE_CLASSES_MAX_LEVELS) {
+    if (o.ilu == SS_ILU0 && o.ilu_sweeps > 0) {
+        h->guarded = ilu0_fixed_point(F, fdiag, o.ilu_sweeps, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
+    } else if (o.ilu == SS_ILU0 && sched_built && h->sched_lo.nlev <= PRE_CLASSES_MAX_LEVELS) {
         h->guarded = ilu0_factor_levels(F, fdiag, h->sched_lo, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
     } else if (o.ilu == SS_ILU0) {
         h->guarded = ilu0_factor(F, fdiag, PIVOT_DETECT, PIVOT_BOOST, h->LU, s).guarded;
@@ -823,6 +830,7 @@ static int run_batch(ss_liouv *hs, int count, int method, const double *tols, co
     };
     // stage 1: transform and symmetrised pattern of every system together
     check_options(method, o);
+    SS_REQUIRE(o.ilu_sweeps == 0, SS_E_INVALID_ARG, "ilu_sweeps: fixed-point ILU(0) on the device-wide path only");
     {
         std::vector<ss_liouv> ok;
         std::vector<int> idx;
@@ -1245,6 +1253,7 @@ static int choose_method(ss_liouv h, const ss_options &o) {
 int solve_ilut_gmres(ss_liouv h, int method, double tol, const ss_options &o, double *rho_out, ss_info *info) {
     ss_options od = o;
     od.ilu = SS_ILUT;
+    od.ilu_sweeps = 0;
     od.flags |= SS_FLAG_DEVICE_WIDE;
     od.flags &= ~SS_FLAG_WORKGROUP;
     const int gm = is_trace(method) ? SS_TRACE_GMRES : SS_INVPOW_GMRES;

@@ -56,7 +56,8 @@ class _Options(ctypes.Structure):
                 ("gmres_m", ctypes.c_int32), ("maxiter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("trace_row", ctypes.c_int32),
                 ("drop_tol", ctypes.c_double), ("fill", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("inner_tol", ctypes.c_double), ("weight", ctypes.c_double), ("seed", ctypes.c_int64)]
+                ("inner_tol", ctypes.c_double), ("weight", ctypes.c_double), ("seed", ctypes.c_int64),
+                ("ilu_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -235,7 +236,7 @@ def _ptr(x) -> int:
 def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, max_outer=20,
             drop_tol=1e-4, fill=10.0, sigma=1e-15, inner_tol=0.0, weight=0.0, hermitize=False,
             no_fallback=False, trace_row=-1, path="auto", trsv="auto", cond_est=False,
-            matrix_free=False, force_breakdown=False, random_start=False, seed=0) -> _Options:
+            matrix_free=False, force_breakdown=False, random_start=False, seed=0, ilu_sweeps=0) -> _Options:
     o = _Options()
     _lib.ss_options_default(ctypes.byref(o))
     o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -258,6 +259,7 @@ def options(prec="fp64", ilu="ilu0", ordering="rcm", gmres_m=20, maxiter=1000, m
     if random_start:
         o.flags |= SS_FLAG_RANDOM_START
     o.seed = int(seed)
+    o.ilu_sweeps = int(ilu_sweeps)
     return o
 
 

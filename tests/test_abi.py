@@ -44,7 +44,7 @@ def test_struct_layouts_match_header():
     """The ctypes mirrors have the sizes the header implies."""
     from paper_1504_06768_amd import ss
     assert ctypes.sizeof(ss._Csr) == 40
-    assert ctypes.sizeof(ss._Options) == 8 * 4 + 5 * 8 + 8
+    assert ctypes.sizeof(ss._Options) == 8 * 4 + 5 * 8 + 8 + 2 * 4
     assert ctypes.sizeof(ss._Info) == 8 * 4 + 3 * 8 + 10 * 8 + 2 * 4
     assert ctypes.sizeof(ss._ServerStats) == 3 * 8 + 2 * 4 + 2 * 8 + 2 * 4
 
