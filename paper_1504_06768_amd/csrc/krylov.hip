@@ -9,6 +9,8 @@
 // into the next step's coefficients, and a skip flag makes every kernel of
 // an already-finished solve return at once, so the host only reads the state
 // every few iterations.
+#include <limits>
+
 #include "krylov.hpp"
 
 namespace ss {
@@ -390,17 +392,22 @@ __global__ void k_gm_start(GmresState *st, const double2 *norm2, double2 *g, int
     g[0] = mk(beta, 0.0);
 }
 
-// second orthogonalisation pass only when the first removed more than
-// 1 - 1/sqrt(2) of w's norm (||w'||^2 < ||w||^2 / 2; Daniel, Gragg, Kaufman
-// and Stewart 1976)
-// (the first pass's ||w'||^2 from its partials into wnorm2_after)
+// second orthogonalisation pass only when the first cancelled w to below
+// sqrt(eps) of its norm (||w'||^2 < eps ||w||^2, eps the unit roundoff of
+// the Krylov vectors): the first pass leaves w' with an error of order
+// eps ||w||, so only then does w' lose more than sqrt(eps) of its
+// orthogonality to the basis.  (The criterion of Daniel, Gragg, Kaufman and
+// Stewart, ||w'||^2 < ||w||^2 / 2, ran the second pass at almost every step
+// on the Liouvillians here with the same iteration counts as never.)
+// The first pass's ||w'||^2 goes from its partials into wnorm2_after.
 __global__ void __launch_bounds__(SUM_BS) k_gm_need2(GmresState *st, const double2 *npart, int nb,
-                                                     double2 *wnorm2_after, const double2 *wnorm2_before) {
+                                                     double2 *wnorm2_after, const double2 *wnorm2_before,
+                                                     double eps) {
     if (st->skip) return;
     const double2 v = sum_partials_block(npart, nb);
     if (threadIdx.x != 0) return;
     *wnorm2_after = v;
-    st->pass2 = (v.x < 0.5 * wnorm2_before->x) ? 1 : 0;
+    st->pass2 = (v.x < eps * wnorm2_before->x) ? 1 : 0;
 }
 // new column j: h_{j+1,j} = ||w||, previous rotations, new rotation, g
 // update, and the stopping test (which sets skip for the steps queued after)
@@ -555,7 +562,8 @@ KrylovResult Krylov<T>::gmres(const T *b, T *x, double rtol, int maxiter, int m)
                 k_gm_sum_hcol<<<j + 2, SUM_BS, 0, s>>>(pp, nb, hcol.get(), H.get(), ldh, j, false, skip, nullptr);
                 k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip, nullptr,
                                                    np);
-                k_gm_need2<<<1, SUM_BS, 0, s>>>(st, np, nb, sc, hcol.get() + j + 1);
+                k_gm_need2<<<1, SUM_BS, 0, s>>>(st, np, nb, sc, hcol.get() + j + 1,
+                                                std::numeric_limits<typename RealOf<T>::type>::epsilon() / 2);
                 k_multidot<T><<<dim3(nb, j + 1), 256, 0, s>>>(n, Vp, ldv, w.get(), -1, pp, skip, pass2);
                 k_gm_sum_hcol<<<j + 1, SUM_BS, 0, s>>>(pp, nb, hcol.get(), H.get(), ldh, j, true, skip, pass2);
                 k_multi_axpy<T><<<nb, 256, 0, s>>>(n, j + 1, Vp, ldv, hcol.get(), -1.0, true, w.get(), skip, pass2,
