@@ -37,7 +37,7 @@ def _factored(L, s, method, ordering):
     """The matrix the device-wide set-up factorises: P A P^T in RCM order, or
     its colour-class reordering (the factors' order on that path)."""
     Ap = ssl.export_csr(L, ssl.SS_MAT_A_PERM)
-    if ordering == "rcm":
+    if ordering in ("rcm", "natural"):
         return Ap
     Lo = liouvillian_sparse(s.H, s.c_ops)
     Ao = otr.modified(Lo, pop=otr.trace_population(Lo))[0] if method.startswith("trace") else otr.shifted(Lo)
@@ -51,10 +51,12 @@ def _factored(L, s, method, ordering):
 @pytest.mark.parametrize("sweeps", [1, 3])
 @pytest.mark.parametrize("name,method,ordering", [("kerr20", "trace_gmres", "rcm"),
                                                   ("jc8", "invpow_gmres", "colour"),
-                                                  ("opto3x5", "trace_gmres", "rcm")])
+                                                  ("opto3x5", "trace_gmres", "rcm"),
+                                                  ("kerr40", "trace_gmres", "natural")])
 def test_factors_after_s_sweeps_match_the_oracle(name, method, ordering, sweeps):
+    # kerr40: the trace row has 40 entries, more than a lane group holds
     s = {"kerr20": lambda: qs.config(1), "jc8": lambda: qs.jaynes_cummings(8, seed=0),
-         "opto3x5": lambda: qs.optomechanics(3, 5, nth=1.0)}[name]()
+         "opto3x5": lambda: qs.optomechanics(3, 5, nth=1.0), "kerr40": lambda: qs.kerr(40)}[name]()
     L = ssl.build_liouvillian(s.H, s.c_ops)
     ssl.prepare(L, method, ordering=ordering, path="device", ilu_sweeps=sweeps)
     F = _factored(L, s, method, ordering)
