@@ -96,11 +96,15 @@ void trsv_classes(const LevelSched &ls, bool upper, const Csr<T> &LU, const T *i
                   hipStream_t s, const int *pin, T *outp) {
     SS_REQUIRE((int)ls.hptr.size() == ls.nlev + 1, SS_E_STATE, "level schedule without its host copy");
     if (LU.n == 0) return;
-    // mean entries per row of one triangle (the other's are about as many)
+    // mean entries per row of one triangle (the other's are about as many).
+    // Kerr chain in the colour-class order (~10 per triangle), per complex128
+    // application: 8 lanes x 3 entries 0.345 ms; 8 x 4 0.346, 8 x 2 0.352,
+    // 8 x 6 0.356, 4 x 4 0.368, 4 x 3 0.372, 4 x 2 0.374, 8 x 1 0.379,
+    // 16 x 2 0.383, 16 x 1 0.402, 2 x 6 0.446 ms
     const double mean = std::max(0.0, (double)(LU.nnz - LU.n) / (2.0 * LU.n));
     if (mean <= 12) {
-        if (upper) levels_launch<T, true, 4, 3>(ls, LU, in, out, pin, outp, skip, s);
-        else levels_launch<T, false, 4, 3>(ls, LU, in, out, pin, outp, skip, s);
+        if (upper) levels_launch<T, true, 8, 3>(ls, LU, in, out, pin, outp, skip, s);
+        else levels_launch<T, false, 8, 3>(ls, LU, in, out, pin, outp, skip, s);
     } else if (mean <= 32) {
         if (upper) levels_launch<T, true, 8, 4>(ls, LU, in, out, pin, outp, skip, s);
         else levels_launch<T, false, 8, 4>(ls, LU, in, out, pin, outp, skip, s);

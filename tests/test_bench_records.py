@@ -12,9 +12,9 @@ _spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(
 bench = importlib.util.module_from_spec(_spec)
 _spec.loader.exec_module(bench)
 
-KERNEL = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<double, 2u>, false, 4, 3>(int, int, ...)"
-KERNEL_UP = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<double, 2u>, true, 4, 3>(int, int, ...)"
-KERNEL_C64 = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<float, 2u>, false, 4, 3>(int, int, ...)"
+KERNEL = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<double, 2u>, false, 8, 3>(int, int, ...)"
+KERNEL_UP = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<double, 2u>, true, 8, 3>(int, int, ...)"
+KERNEL_C64 = "void ss::(anonymous namespace)::k_trsv_level<HIP_vector_type<float, 2u>, false, 8, 3>(int, int, ...)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
