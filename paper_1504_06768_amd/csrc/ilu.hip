@@ -389,6 +389,8 @@ __global__ void __launch_bounds__(ILU_LVL_BS) k_ilu0_levels(const Ilu0Job *jobs,
 // same.
 constexpr int ILU_LEVEL_BS = 256;
 constexpr int ILU_WIDE_LG = 32;
+constexpr int ILU_LONG_BS = 256;     // threads of k_ilu0_long
+constexpr int ILU_LONG_MAX = 2048;   // entries of a row k_ilu0_long holds in LDS
 constexpr int ILU_WIDE_PF = 8;  // U parts fetched per memory round
 
 // orders the LDS accesses of one wavefront (the lane group lies in one)
@@ -495,15 +497,106 @@ __device__ __forceinline__ void ilu0_slot_wide(const Ilu0Job &J, int4 slot, int 
     if (in) gst(J.out + rs + lane, wv);
 }
 
+// Rows longer than LG entries and at most ILU_LONG_MAX (a trace row) are
+// listed in longq for k_ilu0_long when longq is given.
 template <int LG>
-__global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu0_level(Ilu0Job J, int lo, int hi, double detect, double boost) {
+__global__ void __launch_bounds__(ILU_LEVEL_BS) k_ilu0_level(Ilu0Job J, int lo, int hi, double detect, double boost,
+                                                             int *longq, int *nlong) {
     __shared__ int scol[ILU_LEVEL_BS], stag[ILU_LEVEL_BS];
     __shared__ double2 su[ILU_LEVEL_BS];
     const int t = blockIdx.x * ILU_LEVEL_BS + threadIdx.x;
     const int sl = lo + t / LG, lane = t % LG;
     if (sl >= hi) return;  // (whole groups)
     const int gb = (int)threadIdx.x - lane;
-    ilu0_slot_wide<LG>(J, gld(J.lslot + sl), lane, detect, boost, scol + gb, su + gb, stag + gb);
+    const int4 slot = gld(J.lslot + sl);
+    const int len = slot.w - slot.y;
+    if (longq && len > LG && len <= ILU_LONG_MAX) {
+        if (lane == 0) longq[atomicAdd(nlong, 1)] = sl;
+        return;
+    }
+    ilu0_slot_wide<LG>(J, slot, lane, detect, boost, scol + gb, su + gb, stag + gb);
+}
+
+// The listed long rows of one level, one workgroup per row at a time: the
+// row's columns and values in LDS; for each entry k before the pivot, in
+// order, one thread forms l_ik = w_ik / u_kk and the workgroup subtracts
+// l_ik u_kj from the row's entry of column j for every j of row k's U part
+// (found by binary search over the row's columns in LDS).  The steps and
+// their arithmetic are those of ilu0_row_group, so the factors are the same.
+__global__ void __launch_bounds__(ILU_LONG_BS) k_ilu0_long(Ilu0Job J, const int *longq, const int *nlong,
+                                                           double detect, double boost) {
+    __shared__ int scol[ILU_LONG_MAX];
+    __shared__ double2 sw[ILU_LONG_MAX];
+    __shared__ double srn[ILU_LONG_BS / 64];
+    __shared__ int sdk, ske;
+    __shared__ double2 sl;
+    const int m = *nlong;
+    for (int q = blockIdx.x; q < m; q += gridDim.x) {
+        const int4 slot = gld(J.lslot + longq[q]);
+        const int rs = slot.y, dg = slot.z, re = slot.w;
+        const int len = re - rs, nl = dg - rs;
+        __syncthreads();  // (the previous row's LDS reads are done)
+        double rn = 0.0;
+        for (int t = threadIdx.x; t < len; t += ILU_LONG_BS) {
+            scol[t] = gld(J.col + rs + t);
+            const double2 v = gld(J.a + rs + t);
+            sw[t] = v;
+            rn = fmax(rn, sqrt(v.x * v.x + v.y * v.y));
+        }
+        for (int off = 32; off > 0; off >>= 1) rn = fmax(rn, __shfl_xor(rn, off, 64));
+        if ((threadIdx.x & 63) == 0) srn[threadIdx.x >> 6] = rn;
+        __syncthreads();
+        rn = srn[0];
+        for (int w = 1; w < ILU_LONG_BS / 64; ++w) rn = fmax(rn, srn[w]);
+        for (int p = 0; p < nl; ++p) {
+            if (threadIdx.x == 0) {
+                const int k = scol[p];
+                const int dk = gld(J.diag + k);
+                sdk = dk;
+                ske = gld(J.rowptr + k + 1);
+                const double2 l = cdiv(sw[p], gld(J.out + dk));
+                sw[p] = l;
+                sl = l;
+            }
+            __syncthreads();
+            const int dk = sdk, ke = ske;
+            const double2 l = sl;
+            for (int f = dk + 1 + threadIdx.x; f < ke; f += ILU_LONG_BS) {
+                const int c = gld(J.col + f);
+                int lo = p + 1, hi = len - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int cm = scol[mid];
+                    if (cm == c) {
+                        sw[mid] = csub(sw[mid], cmul(l, gld(J.out + f)));
+                        break;
+                    }
+                    if (cm < c) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double2 pv = sw[nl];
+            const double mag = sqrt(pv.x * pv.x + pv.y * pv.y);
+            const double bound = detect * rn;
+            if (!(mag >= bound)) {
+                const double b = (rn > 0.0) ? boost * rn : 1.0;
+                sw[nl] = (mag > 0.0) ? cscale(pv, b / mag) : mk(b, 0.0);
+                atomicAdd(J.nguard, 1);
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < len; t += ILU_LONG_BS) gst(J.out + rs + t, sw[t]);
+    }
+}
+
+// the longest row (one atomic per wavefront)
+__global__ void k_ilu_max_row(int n, const int *rowptr, int *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int len = (r < n) ? rowptr[r + 1] - rowptr[r] : 0;
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, len);
 }
 
 void ilu0_levels_batch(const Ilu0Job *jobs, int count, double detect, double boost, hipStream_t s) {
@@ -538,11 +631,25 @@ IluResult ilu0_factor_levels(const CsrBuf<double2> &A, const int *diag, const Le
     j.nlev = lo.nlev;
     j.lptr = lo.ptr.get();
     j.lslot = lo.slot.get();
+    // rows longer than a lane group (a trace row) go to k_ilu0_long, level by
+    // level after the level's other rows
+    int maxlen = 0;
+    DevBuf<int> mx(1), longq, nlong(1);
+    if (n) {
+        SS_HIP(hipMemsetAsync(mx.get(), 0, sizeof(int), s));
+        k_ilu_max_row<<<div_up(n, 256), 256, 0, s>>>(n, A.rowptr.get(), mx.get());
+        SS_HIP(hipGetLastError());
+        d2h(&maxlen, mx.get(), 1, s);
+    }
+    const bool longrows = maxlen > ILU_WIDE_LG;
+    if (longrows) longq.resize((size_t)std::max(n, 1));
     for (int l = 0; l < lo.nlev; ++l) {
         const int a = lo.hptr[(size_t)l], b = lo.hptr[(size_t)l + 1];
         if (b <= a) continue;
+        if (longrows) SS_HIP(hipMemsetAsync(nlong.get(), 0, sizeof(int), s));
         k_ilu0_level<ILU_WIDE_LG><<<div_up((int64_t)(b - a) * ILU_WIDE_LG, ILU_LEVEL_BS), ILU_LEVEL_BS, 0, s>>>(
-            j, a, b, detect, boost);
+            j, a, b, detect, boost, longrows ? longq.get() : nullptr, nlong.get());
+        if (longrows) k_ilu0_long<<<8, ILU_LONG_BS, 0, s>>>(j, longq.get(), nlong.get(), detect, boost);
     }
     SS_HIP(hipGetLastError());
     IluResult r;
