@@ -84,17 +84,23 @@ __global__ void k_mod_count(int n, int d, int rt, const int *rowptr, const int *
     else cnt[r] = rowptr[r + 1] - rowptr[r];
 }
 
-__global__ void k_mod_fill(int n, int d, int rt, const int *rowptr, const int *col, const double2 *val,
-                           const double2 *w, const int *orow, int *ocol, double2 *oval) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// MOD_G lanes per row: every row but the trace row is copied (coalesced);
+// the trace row is merged with T by the group's first lane
+constexpr int MOD_G = 32;
+
+__global__ void __launch_bounds__(256) k_mod_fill(int n, int d, int rt, const int *rowptr, const int *col,
+                                                  const double2 *val, const double2 *w, const int *orow, int *ocol,
+                                                  double2 *oval) {
+    const int r = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) / MOD_G);
+    const int g = threadIdx.x & (MOD_G - 1);
     if (r >= n) return;
     if (r == rt) {
-        trace_row0<true>(d, rt, rowptr, col, val, *w, ocol + orow[r], oval + orow[r]);
+        if (g == 0) trace_row0<true>(d, rt, rowptr, col, val, *w, ocol + orow[r], oval + orow[r]);
     } else {
-        const int o = orow[r];
-        for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-            ocol[o + e - rowptr[r]] = col[e];
-            oval[o + e - rowptr[r]] = val[e];
+        const int o = orow[r], rs = rowptr[r], re = rowptr[r + 1];
+        for (int e = rs + g; e < re; e += MOD_G) {
+            ocol[o + e - rs] = col[e];
+            oval[o + e - rs] = val[e];
         }
     }
 }
@@ -187,8 +193,8 @@ void make_modified(const CsrBuf<double2> &L, int d, int rt, const double2 *d_w, 
     k_mod_count<<<div_up(n, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(), d_w, cnt.get());
     SS_HIP(hipGetLastError());
     finish_rows(A, n, cnt, s);
-    k_mod_fill<<<div_up(n, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(), d_w,
-                                              A.rowptr.get(), A.col.get(), A.val.get());
+    k_mod_fill<<<div_up((int64_t)n * MOD_G, 256), 256, 0, s>>>(n, d, rt, L.rowptr.get(), L.col.get(), L.val.get(),
+                                                               d_w, A.rowptr.get(), A.col.get(), A.val.get());
     SS_HIP(hipGetLastError());
 }
 
