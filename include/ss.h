@@ -363,10 +363,13 @@ int ss_apply(ss_liouv L, int32_t op, int32_t prec, const double *x, double *y);
  * schedules ss_prepare builds for the device-wide path (n > 4096, a GMRES
  * method or SS_FLAG_DEVICE_WIDE), else SS_E_STATE.  x and y: n complex128
  * (interleaved re, im), DEVICE pointers (else SS_E_INVALID_ARG), not
- * aliased.  Scratch: one library-owned device array of 32 MiB per device,
+ * aliased.  Scratch: one library-owned device array of 64 MiB per device,
  * held until the process ends; a call needs 256 B plus 16 n B (fp64
- * PRECOND) or 24 n B (mixed PRECOND) or 16 n B (mixed SPMV_APERM) and
- * returns SS_E_INVALID_ARG beyond that (n above ~2.09e6 fp64, ~1.39e6 mixed).
+ * PRECOND) or 24 n B (mixed PRECOND) or 16 n B (mixed SPMV_APERM), the
+ * PRECOND vectors three times over (48 n B fp64, 40 n B mixed) when the
+ * factors take the colour-class order on the device-wide path, and returns
+ * SS_E_INVALID_ARG beyond that (n above ~4.19e6 fp64 and ~2.79e6 mixed, or
+ * ~1.39e6 and ~1.67e6 in the colour-class order).
  * Every call on a device shares that array: calls that overlap on one
  * device (other threads, other handles) race.  Synchronous: returns after
  * the result is in y. */

@@ -22,7 +22,7 @@ void set_last_error(const std::string &msg);
 
 namespace {
 
-constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
 constexpr size_t CONTROL_BYTES = 256;  // status word at 0, control words at 64
 constexpr int MAX_DEVICES = 64;
 

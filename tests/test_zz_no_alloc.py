@@ -84,22 +84,26 @@ def test_noalloc_refuses_what_it_cannot_do():
 
 
 def test_noalloc_refuses_sizes_beyond_the_scratch():
-    """Kerr chain 3 x 11 (n = 1 771 561): fp64 needs 16 n B (fits the
-    32 MiB array), mixed needs 24 n B (does not)."""
+    """Kerr chain 3 x 11 (n = 1 771 561) against the 64 MiB array: in the
+    colour-class order the preconditioner needs 48 n B (fp64) or 40 n B
+    (mixed), neither fits; in RCM order 16 n B and 24 n B both fit."""
     import torch
     ch = qs.kerr_chain(3, 11)
     L = ssl.build_liouvillian(ch.H, ch.c_ops)
-    ssl.prepare(L, "invpow_bicgstab", prec="mixed")
     n = L.n
-    assert 16 * n + 256 <= 32 << 20 < 24 * n + 256
+    assert 24 * n + 256 <= 64 << 20 < 40 * n + 256
     xd = torch.zeros(n, dtype=torch.complex128, device="cuda")
     xd[0] = 1.0
     yd = torch.zeros_like(xd)
-    with pytest.raises(ssl.SolverError) as e:
-        ssl.apply_noalloc(L, ssl.SS_OP_PRECOND, xd, yd, prec="mixed")
-    assert e.value.code == ssl.SS_E_INVALID_ARG and "scratch" in str(e.value)
-    ssl.apply_noalloc(L, ssl.SS_OP_PRECOND, xd, yd, prec="fp64")
-    torch.cuda.synchronize()
-    y_ref = ssl.apply(L, ssl.SS_OP_PRECOND_GROUPS, xd.cpu().numpy())
-    assert np.array_equal(yd.cpu().numpy(), y_ref)
+    ssl.prepare(L, "invpow_bicgstab", prec="mixed", ordering="colour", path="device")
+    for prec in ("fp64", "mixed"):
+        with pytest.raises(ssl.SolverError) as e:
+            ssl.apply_noalloc(L, ssl.SS_OP_PRECOND, xd, yd, prec=prec)
+        assert e.value.code == ssl.SS_E_INVALID_ARG and "scratch" in str(e.value)
+    ssl.prepare(L, "invpow_bicgstab", prec="mixed")
+    for prec in ("fp64", "mixed"):
+        ssl.apply_noalloc(L, ssl.SS_OP_PRECOND, xd, yd, prec=prec)
+        torch.cuda.synchronize()
+        y_ref = ssl.apply(L, ssl.SS_OP_PRECOND_GROUPS, xd.cpu().numpy(), prec=prec)
+        assert np.array_equal(yd.cpu().numpy(), y_ref), prec
     L.free()
